@@ -1,0 +1,245 @@
+/*
+ * kryging.h -- C ABI of the MI355X (gfx950) Kryging hot path.
+ *
+ * The library evaluates Gaussian-process likelihoods and kriging predictions
+ * for data on a regular n1 x n2 grid with missing cells, following
+ * Majumder, Guan, Reich & Saibaba, "Kryging: Geostatistical analysis of
+ * large-scale datasets using Krylov subspace methods":
+ *
+ *   model (Sec. 2, eq. obs_mod):  y = A x + eps,  x ~ N(0, sigma^2 Sigma),
+ *                                 eps ~ N(0, tau^2 I), A = identity with the
+ *                                 rows of unobserved cells removed;
+ *   Sigma (Sec. 2):               Matern correlation with range, smoothness
+ *                                 and (rotated) geometric anisotropy; on a
+ *                                 grid it is symmetric BTTB (Sec. 3);
+ *   K  = A Sigma A^T + eta I,     eta = tau^2 / sigma^2, the unit-variance
+ *                                 covariance of the observations.
+ *
+ * Every device step runs in the library's own HIP kernels.  Conventions that
+ * hold for every entry point:
+ *
+ *  - Return value: kry_status, KRY_OK (0) on success.  On failure a message
+ *    is available from kry_last_error() (thread-local, valid until the next
+ *    failing call on that thread).  Inputs are validated before any device
+ *    work; on KRY_EINVAL no output is written.  No C++ exception crosses the
+ *    ABI.
+ *  - Ownership: the caller owns every host array passed in or out and needs
+ *    to keep it alive only for the duration of the call; the library copies
+ *    inputs and writes caller-allocated outputs.  Handles are opaque and owned
+ *    by the library; every destroy function accepts NULL.
+ *  - Grid layout: cell (i, j) is row i (spacing dx1) and column j (spacing
+ *    dx2), row-major cell id i * n2 + j.  "Compact" vectors hold one value
+ *    per observed cell, in increasing cell id.
+ *  - Calls are synchronous: when an entry point taking host buffers returns,
+ *    its outputs are written.  One kry_ctx (and the problems made from it)
+ *    must be used from one host thread at a time.
+ */
+#ifndef KRYGING_H
+#define KRYGING_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KRY_OK = 0,
+    KRY_EINVAL = 1,   /* invalid argument (message says which)              */
+    KRY_ENOMEM = 2,   /* device allocation failed or above the HBM budget   */
+    KRY_EDEVICE = 3,  /* HIP runtime error                                  */
+    KRY_ENOTPSD = 4,  /* circulant embedding not PSD within the size cap    */
+    KRY_ENOCONV = 5,  /* iteration limit reached; outputs still written     */
+    KRY_EBUSY = 6,    /* server queue full                                  */
+    KRY_ENOTIMPL = 7  /* feature not available                              */
+} kry_status;
+
+typedef struct kry_ctx kry_ctx;
+typedef struct kry_problem kry_problem;
+typedef struct kry_server kry_server;
+
+/* Regular grid: n1 rows x n2 columns, 2 <= n1, n2 <= 4096, spacings > 0. */
+typedef struct {
+    int32_t n1, n2;
+    double dx1, dx2;
+} kry_grid;
+
+/* Matern parameters (Sec. 2): marginal variance sigma2 > 0, nugget
+ * variance tau2 >= 0, range > 0 (along the major axis), smoothness nu > 0,
+ * anisotropy ratio >= 1 (1 = isotropic) and angle (radians, counter-clockwise
+ * from the +column axis) of the major axis. */
+typedef struct {
+    double sigma2, tau2, range, nu, aniso_ratio, aniso_angle;
+} kry_matern;
+
+typedef enum { KRY_FP64 = 0, KRY_FP32 = 1 } kry_precision;
+typedef enum { KRY_PROBE_RADEMACHER = 0, KRY_PROBE_COLOURED = 1 } kry_probe_kind;
+typedef enum { KRY_SOLVER_CG = 0, KRY_SOLVER_GENGK = 1 } kry_solver;
+
+/* Options.  precision = KRY_FP32 is the mixed form: transforms and Krylov
+ * vectors in FP32; dot products, Lanczos coefficients, quadrature, CG
+ * scalars and the likelihood in FP64, with FP64 residual refinement in CG. */
+typedef struct {
+    int32_t lanczos_steps;   /* m, Lanczos steps per probe (>= 1)           */
+    int32_t num_probes;      /* N, Rademacher probes (ignored if coloured)  */
+    int32_t probe_kind;      /* kry_probe_kind                              */
+    int32_t colour_period;   /* c for coloured probes (c*c probes)          */
+    uint64_t seed;           /* Philox key for probes and samples           */
+    int32_t reorth;          /* 1 = full reorthogonalisation (FP64 coeffs)  */
+    int32_t precision;       /* kry_precision                               */
+    double cg_rtol;          /* CG stop: ||r|| <= cg_rtol ||b||             */
+    int32_t cg_maxit;        /* CG iteration cap                            */
+    int32_t solver;          /* kry_solver for the quadratic form           */
+    int32_t gk_steps;        /* k for genGK                                 */
+} kry_opts;
+
+typedef struct {
+    double loglik;           /* l at the given sigma2                       */
+    double loglik_profiled;  /* l_p with sigma2 = sigma2_hat                */
+    double sigma2_hat;       /* Q / p                                       */
+    double logdet;           /* estimate of log det K                       */
+    double logdet_se;        /* probe standard error of logdet              */
+    double quad;             /* Q = y^T K^{-1} y                            */
+    int64_t p;               /* number of observed cells                    */
+    int32_t lanczos_steps_used; /* max over probes                          */
+    int32_t cg_iters;        /* CG iterations (or genGK steps)              */
+    double cg_relres;        /* final relative residual                     */
+} kry_loglik_result;
+
+/* ---- status, options ---------------------------------------------------- */
+const char* kry_status_string(kry_status s);
+const char* kry_last_error(void);
+
+/* Defaults: m = 30, N = 10 Rademacher, seed 303, no reorth, FP64,
+ * cg_rtol 1e-8, cg_maxit 20000, CG, gk_steps 100. */
+kry_status kry_opts_default(kry_opts* out);
+
+/* ---- context and problems ----------------------------------------------- */
+/* Binds HIP device `device`; hbm_budget_bytes = 0 means no limit beyond the
+ * device.  Creates the library's stream (default priority). */
+kry_status kry_ctx_create(int32_t device, uint64_t hbm_budget_bytes, kry_ctx** out);
+void kry_ctx_destroy(kry_ctx* ctx);
+
+/* A problem: grid, observation mask (n1*n2 bytes, nonzero = observed; at
+ * least one observed cell) and data y (n1*n2 doubles read only where
+ * observed, must be finite; NULL = zeros).  Uploads the mask in packed form
+ * and y to the device.  The embedding used by the masked product is the
+ * smallest power of two >= max(16, 2 n - 1) per axis. */
+kry_status kry_problem_create(kry_ctx* ctx, const kry_grid* grid, const uint8_t* mask,
+                              const double* y, kry_problem** out);
+/* Replace the data (n1*n2 doubles, read where observed). */
+kry_status kry_problem_set_data(kry_problem* prob, const double* y);
+/* Observed count p and embedding sizes N1, N2 (any pointer may be NULL). */
+kry_status kry_problem_info(const kry_problem* prob, int64_t* p, int32_t* N1, int32_t* N2);
+void kry_problem_destroy(kry_problem* prob);
+
+/* ---- lag grid and spectrum (Sec. 2 Matern; Sec. 3.3 BCCB embedding) ---- */
+/* Lag grid c of the N1 x N2 block-circulant embedding (row-major):
+ * c[l1][l2] = C(h2 dx2, h1 dx1) at the wrapped lag (h1, h2); on a Nyquist
+ * line (l = N/2) the mean over both aliases.  N1, N2 = 0 selects the
+ * problem's own embedding; otherwise powers of two in [16, 8192]. */
+kry_status kry_lag_grid(kry_problem* prob, const kry_matern* theta, int32_t N1, int32_t N2,
+                        double* c_out /* N1*N2 */);
+/* Eigenvalues lam = DFT2(c) on the half spectrum, layout [k2][k1] with
+ * k2 in [0, N2/2], k1 in [0, N1) (so lam_out has (N2/2+1)*N1 doubles), and
+ * minmax = {min lam, max lam}.  Sizes as for kry_lag_grid. */
+kry_status kry_spectrum(kry_problem* prob, const kry_matern* theta, int32_t N1, int32_t N2,
+                        double* lam_out, double* minmax);
+
+/* ---- masked BTTB product (Sec. 3, 3.2: circulant embedding + FFT) ------ */
+/* out = K v for nvec compact vectors (nvec x p, row-major, host). */
+kry_status kry_matvec(kry_problem* prob, const kry_matern* theta, int32_t precision,
+                      int32_t nvec, const double* v, double* out);
+/* Same on device buffers of the precision's element type (double or float),
+ * nvec x p contiguous, enqueued on `hip_stream` (NULL = library stream);
+ * returns after enqueueing.  The library's workspace for this call is owned
+ * by the problem and reused by later calls on the same stream. */
+kry_status kry_matvec_device(kry_problem* prob, const kry_matern* theta, int32_t precision,
+                             int32_t nvec, const void* d_v, void* d_out, void* hip_stream);
+/* Sigma A^T w: compact vectors in, full-grid vectors out (nvec x n1*n2),
+ * no nugget -- the kriging-mean product (eq. act_xhat) and the Sigma
+ * product of Algorithm 1. */
+kry_status kry_cov_apply_full(kry_problem* prob, const kry_matern* theta, int32_t precision,
+                              int32_t nvec, const double* w, double* out);
+
+/* ---- probes and Lanczos quadrature (log det alternative of Sec. 3.3) --- */
+/* The probe vectors used by kry_logdet (nprobe x p, compact); nprobe is
+ * N for Rademacher and c*c for coloured probes (query with out = NULL). */
+kry_status kry_probes(kry_problem* prob, const kry_opts* opts, int32_t* nprobe, double* out);
+/* Lanczos coefficients for every probe: alpha (nprobe x m), beta
+ * (nprobe x m; beta[k][j] couples steps j and j+1, beta[k][m-1] unused) and
+ * the steps each probe ran before an exact breakdown. */
+kry_status kry_lanczos(kry_problem* prob, const kry_matern* theta, const kry_opts* opts,
+                       double* alpha, double* beta, int32_t* steps);
+/* SLQ estimate of log det K: Gauss quadrature of every probe's tridiagonal
+ * (per_probe, nullable, nprobe values) combined as the mean (Rademacher) or
+ * the sum (coloured), with its probe standard error. */
+kry_status kry_logdet(kry_problem* prob, const kry_matern* theta, const kry_opts* opts,
+                      double* logdet, double* se, double* per_probe);
+
+/* Gauss quadrature of given Lanczos tridiagonals on the device (implicit QL
+ * with first eigenvector components): for probe k with steps[k] = s,
+ * T = tridiag(beta[k][0..s-2], alpha[k][0..s-1]) and
+ * gamma[k] = znorm2[k] * sum_i tau_i^2 log theta_i.  alpha, beta: nprobe x m
+ * host arrays; uses the current HIP device. */
+kry_status kry_gauss_quadrature(int32_t nprobe, int32_t m, const double* alpha, const double* beta,
+                                const int32_t* steps, const double* znorm2, double* gamma);
+
+/* ---- solves --------------------------------------------------------------- */
+/* CG solve K x = b for nrhs compact right-hand sides (nrhs x p); iters and
+ * relres per right-hand side (nullable). KRY_ENOCONV if cg_maxit reached. */
+kry_status kry_solve(kry_problem* prob, const kry_matern* theta, const kry_opts* opts,
+                     int32_t nrhs, const double* b, double* x, int32_t* iters, double* relres);
+/* Algorithm 1 (genGK) for k = opts->gk_steps steps on the problem's data with
+ * A the selection and R = tau^2 I: alpha (k+1), beta (k+1) of B_k, z_k (k)
+ * of eq. xhat_est, the full-grid x_k* (n1*n2, nullable) and
+ * J = ||B_k z - beta1 e1||^2 + ||z||^2 / sigma^2 (sigma^2 J approximates Q). */
+kry_status kry_gengk(kry_problem* prob, const kry_matern* theta, const kry_opts* opts,
+                     double* alpha, double* beta, double* z, double* x_full, double* J);
+
+/* ---- likelihood, fit, kriging ------------------------------------------- */
+/* Log-likelihood of the problem's data: logdet by SLQ, Q by CG (or genGK),
+ * l = -1/2 [p log(2 pi sigma2) + logdet + Q / sigma2], sigma2_hat = Q / p,
+ * l_p = -1/2 [p (log 2 pi + log sigma2_hat + 1) + logdet]. */
+kry_status kry_loglik(kry_problem* prob, const kry_matern* theta, const kry_opts* opts,
+                      kry_loglik_result* out);
+/* `count` parameter points on one problem, evaluated together: every
+ * (theta, probe) pair is one vector of a batched product and the CG solves
+ * run as one multi-RHS solve.  Same probes for every theta (common random
+ * numbers). */
+kry_status kry_loglik_batch(kry_problem* prob, const kry_matern* thetas, int32_t count,
+                            const kry_opts* opts, kry_loglik_result* out /* count */);
+/* Maximise l_p over (log range, log eta) -- bit 0 of free_mask frees the
+ * range, bit 1 the nugget ratio -- by Nelder-Mead from `init`, with the same
+ * probes at every point.  est receives the estimate with sigma2 = sigma2_hat
+ * and tau2 = eta * sigma2_hat; at_est the likelihood there. */
+kry_status kry_fit(kry_problem* prob, const kry_matern* init, uint32_t free_mask,
+                   const kry_opts* opts, double xtol, int32_t maxiter,
+                   kry_matern* est, kry_loglik_result* at_est);
+/* Kriging at target cell ids (or every unobserved cell if targets == NULL):
+ * mean_x = c_t^T K^{-1} y; with bootstrap_B == 0 the exact variances
+ * var_x = sigma2 (1 - c_t^T K^{-1} c_t), var_y = var_x + tau2 (multi-RHS
+ * CG); with bootstrap_B > 0 the parametric bootstrap of Sec. 3.5
+ * (eq. bootstrap_uq) with B circulant-embedding fields.  var_x, var_y are
+ * nullable. */
+kry_status kry_krige(kry_problem* prob, const kry_matern* theta, const kry_opts* opts,
+                     const int64_t* targets, int64_t ntargets, double* mean_x, double* var_x,
+                     double* var_y, int32_t bootstrap_B);
+
+/* ---- sampling (Sec. 3.5 fields; Sec. 3.6 embedding caveat) -------------- */
+/* Smallest torus N1 x N2 (powers of two, from the product's embedding,
+ * doubling) whose spectrum satisfies min >= -1e-10 max, up to 8192.
+ * KRY_ENOTPSD if none. */
+kry_status kry_psd_torus(kry_problem* prob, const kry_matern* theta, int32_t* N1, int32_t* N2);
+/* `count` fields x = sigma * (C^{1/2} xi)[corner] on the N1 x N2 torus, xi
+ * from Philox stream s = first_stream + i of domain FIELD, written as count x
+ * n1*n2 doubles.  Negative eigenvalues within the tolerance are set to 0;
+ * minmax (nullable) receives the spectrum's min and max. */
+kry_status kry_sample(kry_problem* prob, const kry_matern* theta, int32_t N1, int32_t N2,
+                      uint64_t seed, int32_t first_stream, int32_t count, double* out,
+                      double* minmax);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KRYGING_H */

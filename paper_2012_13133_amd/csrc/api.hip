@@ -1,0 +1,1657 @@
+// C ABI of the library (include/kryging.h) and the host-side drivers that
+// sequence the device kernels: likelihood (Sec. 3.1, 3.3 alternative, 3.4),
+// generalized Golub-Kahan (Sec. 3.2, Algorithm 1), kriging and the parametric
+// bootstrap (Sec. 3.5), circulant-embedding sampling (Sec. 3.6 caveat) and the
+// profile-likelihood fit (Sec. 3.4).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "krylov.hpp"
+
+using namespace kry;
+
+struct kry_ctx {
+    Ctx c;
+};
+struct kry_problem {
+    Problem P;
+};
+
+static thread_local std::string g_last_error;
+
+template <typename F>
+static kry_status guard(F&& f) {
+    try {
+        f();
+        return KRY_OK;
+    } catch (const Error& e) {
+        g_last_error = e.what();
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return KRY_ENOMEM;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return KRY_EDEVICE;
+    }
+}
+
+namespace kry {
+
+void* dev_alloc(Ctx& c, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    if (c.budget && c.allocated + bytes > c.budget)
+        throw Error(KRY_ENOMEM, "request of " + std::to_string(bytes) + " bytes exceeds the HBM budget (" +
+                                    std::to_string(c.allocated) + " of " + std::to_string(c.budget) + " in use)");
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(KRY_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    c.allocated += bytes;
+    return p;
+}
+
+void dev_free(Ctx& c, void* p, size_t bytes) {
+    if (!p) return;
+    (void)hipFree(p);
+    c.allocated -= std::min<uint64_t>(c.allocated, bytes);
+}
+
+}  // namespace kry
+
+namespace {
+
+// Carves sub-buffers out of one growable device allocation.  Used in two
+// passes: measure (base == nullptr) and then assign.
+struct Arena {
+    char* base = nullptr;
+    size_t off = 0;
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+template <typename F>
+void with_arena(Problem& P, F&& layout) {
+    Arena m;
+    layout(m);
+    P.kws.ensure(*P.ctx, m.off + 256);
+    Arena a;
+    a.base = P.kws.as<char>();
+    layout(a);
+}
+
+void check_theta(const kry_matern* t) {
+    KRY_REQUIRE(t != nullptr, "theta is NULL");
+    const double v[6] = {t->sigma2, t->tau2, t->range, t->nu, t->aniso_ratio, t->aniso_angle};
+    for (double x : v) KRY_REQUIRE(std::isfinite(x), "theta has a non-finite entry");
+    KRY_REQUIRE(t->sigma2 > 0, "sigma2 must be > 0");
+    KRY_REQUIRE(t->tau2 >= 0, "tau2 must be >= 0");
+    KRY_REQUIRE(t->range > 0, "range must be > 0");
+    KRY_REQUIRE(t->nu > 0 && t->nu <= 20, "nu must be in (0, 20]");
+    KRY_REQUIRE(t->aniso_ratio >= 1, "aniso_ratio must be >= 1");
+}
+
+Matern to_matern(const kry_matern* t) {
+    return Matern{t->sigma2, t->tau2, t->range, t->nu, t->aniso_ratio, t->aniso_angle};
+}
+
+void check_opts(const kry_opts* o) {
+    KRY_REQUIRE(o != nullptr, "opts is NULL");
+    KRY_REQUIRE(o->lanczos_steps >= 1 && o->lanczos_steps <= KRY_MAX_LANCZOS, "lanczos_steps must be in [1, 512]");
+    KRY_REQUIRE(o->probe_kind == KRY_PROBE_RADEMACHER || o->probe_kind == KRY_PROBE_COLOURED, "bad probe_kind");
+    if (o->probe_kind == KRY_PROBE_RADEMACHER) KRY_REQUIRE(o->num_probes >= 1 && o->num_probes <= 4096, "num_probes must be in [1, 4096]");
+    else KRY_REQUIRE(o->colour_period >= 1 && o->colour_period <= 64, "colour_period must be in [1, 64]");
+    KRY_REQUIRE(o->precision == KRY_FP64 || o->precision == KRY_FP32, "bad precision");
+    KRY_REQUIRE(o->cg_rtol > 0 && o->cg_rtol < 1, "cg_rtol must be in (0, 1)");
+    KRY_REQUIRE(o->cg_maxit >= 1, "cg_maxit must be >= 1");
+    KRY_REQUIRE(o->solver == KRY_SOLVER_CG || o->solver == KRY_SOLVER_GENGK, "bad solver");
+    KRY_REQUIRE(o->gk_steps >= 1 && o->gk_steps <= 2000, "gk_steps must be in [1, 2000]");
+}
+
+int nprobes_of(const kry_opts* o) {
+    return o->probe_kind == KRY_PROBE_COLOURED ? o->colour_period * o->colour_period : o->num_probes;
+}
+
+int pow2_at_least(int m) {
+    int N = 16;
+    while (N < m) N *= 2;
+    return N;
+}
+
+void bind(Ctx& c) { KRY_HIP(hipSetDevice(c.device)); }
+
+// ---- product operators ----------------------------------------------------------------
+template <typename R>
+MatvecFn<R> masked_op(Problem& P, const void* lam, int64_t lam_tstride, int vpt, const double* d_eta) {
+    Problem* pp = &P;
+    return [pp, lam, lam_tstride, vpt, d_eta](const R* x, R* y, int nvec, hipStream_t st) {
+        Problem& Q = *pp;
+        ConvSpec s;
+        s.N1 = Q.N1;
+        s.N2 = Q.N2;
+        s.nvec = nvec;
+        s.in_mode = IN_COMPACT;
+        s.in = x;
+        s.in_vstride = Q.p;
+        s.rows_in = Q.n1;
+        s.row_len = Q.n2;
+        s.out_mode = OUT_COMPACT;
+        s.out = y;
+        s.out_vstride = Q.p;
+        s.rows_out = Q.n1;
+        s.cols_out = Q.n2;
+        s.vin = x;
+        s.vin_vstride = Q.p;
+        s.eta = d_eta;
+        s.lam = lam;
+        s.lam_tstride = lam_tstride;
+        s.vecs_per_theta = vpt;
+        conv_apply<R>(Q, s, st);
+    };
+}
+
+// Sigma A^T w: compact in, full grid out, no nugget.
+template <typename R>
+void cov_full(Problem& P, const void* lam, const R* w, R* out, int nvec, hipStream_t st) {
+    ConvSpec s;
+    s.N1 = P.N1;
+    s.N2 = P.N2;
+    s.nvec = nvec;
+    s.in_mode = IN_COMPACT;
+    s.in = w;
+    s.in_vstride = P.p;
+    s.rows_in = P.n1;
+    s.row_len = P.n2;
+    s.out_mode = OUT_GRID;
+    s.out = out;
+    s.out_vstride = (int64_t)P.n1 * P.n2;
+    s.rows_out = P.n1;
+    s.cols_out = P.n2;
+    s.scale = 1.0;
+    s.lam = lam;
+    s.lam_tstride = 0;
+    s.vecs_per_theta = nvec;
+    conv_apply<R>(P, s, st);
+}
+
+template <typename R>
+const void* spec_ptr(Spectrum& S);
+template <>
+const void* spec_ptr<double>(Spectrum& S) { return S.s64.ptr; }
+template <>
+const void* spec_ptr<float>(Spectrum& S) { return S.s32.ptr; }
+
+// ---- element kernels used by the drivers --------------------------------------------
+template <typename R>
+__global__ void k_gather(const R* __restrict__ full, const int32_t* __restrict__ cell, int64_t p, int64_t n,
+                         R* __restrict__ out) {
+    const int vec = blockIdx.y;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < p; i += (int64_t)gridDim.x * blockDim.x)
+        out[vec * p + i] = full[vec * n + cell[i]];
+}
+
+// full = 0 off the mask, scale * u on it
+template <typename R>
+__global__ void k_scatter(const R* __restrict__ u, const int32_t* __restrict__ cell, int64_t p, R* __restrict__ full,
+                          double scale) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < p; i += (int64_t)gridDim.x * blockDim.x)
+        full[cell[i]] = (R)(scale * (double)u[i]);
+}
+
+// out[v * p + i] = c( cell_i - target_v ) from the embedding lag grid (row-major N1 x N2)
+__global__ void k_cross_corr(const double* __restrict__ lag, int N1, int N2, const int32_t* __restrict__ cell,
+                             int64_t p, int n2, const int64_t* __restrict__ targets, double* __restrict__ out) {
+    const int v = blockIdx.y;
+    const int64_t t = targets[v];
+    const int tr = (int)(t / n2), tc = (int)(t % n2);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < p; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = cell[i];
+        const int r = c / n2, cc = c - (c / n2) * n2;
+        int l1 = (r - tr) % N1;
+        if (l1 < 0) l1 += N1;
+        int l2 = (cc - tc) % N2;
+        if (l2 < 0) l2 += N2;
+        out[v * p + i] = lag[(int64_t)l1 * N2 + l2];
+    }
+}
+
+// y_b at observed cells: field value plus nugget noise (stream b, domain NOISE)
+__global__ void k_boot_obs(const double* __restrict__ fields, int64_t n, const int32_t* __restrict__ cell, int64_t p,
+                           double tau, uint64_t seed, double* __restrict__ yb) {
+    const int b = blockIdx.y;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < p; i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = cell[i];
+        yb[b * p + i] = fields[b * n + c] + tau * philox_normal((uint32_t)c, (uint32_t)b, DOMAIN_NOISE, seed);
+    }
+}
+
+// accumulate (x_b - xhat_b)^2 and (y_b - xhat_b)^2 at the targets over b in
+// a fixed order (one thread per target)
+__global__ void k_boot_acc(const double* __restrict__ fields, const double* __restrict__ xhat, int64_t n, int B,
+                           const int64_t* __restrict__ targets, int64_t nt, double tau, uint64_t seed,
+                           double* __restrict__ vx, double* __restrict__ vy) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = targets[t];
+        double sx = 0.0, sy = 0.0;
+        for (int b = 0; b < B; ++b) {
+            const double x = fields[b * n + c];
+            const double xh = xhat[b * n + c];
+            const double y = x + tau * philox_normal((uint32_t)c, (uint32_t)b, DOMAIN_TARGET, seed);
+            sx += (x - xh) * (x - xh);
+            sy += (y - xh) * (y - xh);
+        }
+        vx[t] = sx / B;
+        vy[t] = sy / B;
+    }
+}
+
+__global__ void k_pick(const double* __restrict__ full, const int64_t* __restrict__ targets, int64_t nt,
+                       double* __restrict__ out) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x)
+        out[t] = full[targets[t]];
+}
+
+__global__ void k_fill_eta(double* __restrict__ eta, const double* __restrict__ src, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) eta[i] = src[i];
+}
+
+dim3 grid1(int64_t n, int y = 1) {
+    int64_t b = (n + 255) / 256;
+    if (b > 4096) b = 4096;
+    if (b < 1) b = 1;
+    return dim3((unsigned)b, y);
+}
+
+// ---- solves ------------------------------------------------------------------------------
+struct SolveStats {
+    std::vector<int> iters;
+    std::vector<double> relres;
+};
+
+// K X = B for nrhs compact right-hand sides in FP64 (device), with the
+// operator's parameter points given by (spectrum pointers, eta).  FP32 form:
+// restarted FP32 CG inside an FP64 residual refinement loop.
+void solve_device(Problem& P, int precision, const void* lam64, const void* lam32, int64_t lam_tstride, int vpt,
+                  const double* d_eta, int nrhs, const double* B, double* X, double rtol, int maxit, SolveStats& out,
+                  hipStream_t st) {
+    const int64_t p = P.p;
+    const int64_t vn = (int64_t)nrhs * p;
+    out.iters.assign(nrhs, 0);
+    out.relres.assign(nrhs, 0.0);
+    if (precision == KRY_FP64) {
+        CgBuffers<double> cb{};
+        auto lay = [&](Arena& a) {
+            cb.r = a.take<double>(vn);
+            cb.p = a.take<double>(vn);
+            cb.w = a.take<double>(vn);
+            cb.rr = a.take<double>(nrhs);
+            cb.bnorm2 = a.take<double>(nrhs);
+            cb.beta = a.take<double>(nrhs);
+            cb.pw = a.take<double>(nrhs);
+            cb.tmp = a.take<double>(nrhs);
+            cb.partial = a.take<double>((size_t)nrhs * 256);
+            cb.active = a.take<int>(nrhs);
+            cb.iters = a.take<int>(nrhs);
+        };
+        Arena m;
+        lay(m);
+        P.scal.ensure(*P.ctx, m.off + 256);
+        Arena a;
+        a.base = P.scal.as<char>();
+        lay(a);
+        auto A = masked_op<double>(P, lam64, lam_tstride, vpt, d_eta);
+        cg_run<double>(A, p, nrhs, B, X, rtol, maxit, cb, out.iters, out.relres, st);
+        return;
+    }
+    // mixed form
+    CgBuffers<float> cb{};
+    float *b32 = nullptr, *x32 = nullptr;
+    double *r64 = nullptr, *t64 = nullptr, *nrm = nullptr, *part = nullptr;
+    auto lay = [&](Arena& a) {
+        cb.r = a.take<float>(vn);
+        cb.p = a.take<float>(vn);
+        cb.w = a.take<float>(vn);
+        cb.rr = a.take<double>(nrhs);
+        cb.bnorm2 = a.take<double>(nrhs);
+        cb.beta = a.take<double>(nrhs);
+        cb.pw = a.take<double>(nrhs);
+        cb.tmp = a.take<double>(nrhs);
+        cb.partial = a.take<double>((size_t)nrhs * 256);
+        cb.active = a.take<int>(nrhs);
+        cb.iters = a.take<int>(nrhs);
+        b32 = a.take<float>(vn);
+        x32 = a.take<float>(vn);
+        r64 = a.take<double>(vn);
+        t64 = a.take<double>(vn);
+        nrm = a.take<double>(2 * (size_t)nrhs);
+        part = a.take<double>((size_t)nrhs * 256);
+    };
+    Arena m;
+    lay(m);
+    P.scal.ensure(*P.ctx, m.off + 256);
+    Arena a;
+    a.base = P.scal.as<char>();
+    lay(a);
+    auto A32 = masked_op<float>(P, lam32, lam_tstride, vpt, d_eta);
+    auto A64 = masked_op<double>(P, lam64, lam_tstride, vpt, d_eta);
+    KRY_HIP(hipMemsetAsync(X, 0, vn * sizeof(double), st));
+    KRY_HIP(hipMemcpyAsync(r64, B, vn * sizeof(double), hipMemcpyDeviceToDevice, st));
+    dot_batched<double>(B, p, B, p, p, nrhs, part, nrm, st);
+    std::vector<double> bn(nrhs), rn(nrhs);
+    KRY_HIP(hipMemcpyAsync(bn.data(), nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    KRY_HIP(hipStreamSynchronize(st));
+    const double inner = std::max(1e-5, rtol);
+    for (int outer = 0; outer < 12; ++outer) {
+        // residual norms of the FP64 residual
+        dot_batched<double>(r64, p, r64, p, p, nrhs, part, nrm, st);
+        KRY_HIP(hipMemcpyAsync(rn.data(), nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+        KRY_HIP(hipStreamSynchronize(st));
+        bool done = true;
+        for (int v = 0; v < nrhs; ++v) {
+            out.relres[v] = bn[v] > 0 ? std::sqrt(rn[v] / bn[v]) : 0.0;
+            if (out.relres[v] > rtol) done = false;
+        }
+        if (done) break;
+        int budget = maxit;
+        for (int v = 0; v < nrhs; ++v) budget = std::min(budget, maxit - out.iters[v]);
+        if (budget <= 0) break;
+        convert<double, float>(r64, b32, vn, st);
+        std::vector<int> it;
+        std::vector<double> rr;
+        cg_run<float>(A32, p, nrhs, b32, x32, inner, budget, cb, it, rr, st);
+        for (int v = 0; v < nrhs; ++v) out.iters[v] += it[v];
+        add_f32(x32, X, vn, st);
+        A64(X, t64, nrhs, st);
+        KRY_HIP(hipMemcpyAsync(r64, B, vn * sizeof(double), hipMemcpyDeviceToDevice, st));
+        axpby<double>(t64, r64, -1.0, 1.0, p, nrhs, st);
+    }
+}
+
+// ---- likelihood ----------------------------------------------------------------------------
+struct LoglikWork {
+    std::vector<double> gamma;  // per vector
+    std::vector<int> steps;
+};
+
+// SLQ for `count` parameter points sharing the probes (common random numbers).
+// Vectors are ordered theta-major: v = t * nprobe + k.
+template <typename R>
+void slq_device(Problem& P, const kry_opts* o, const void* lam, int64_t lam_tstride, const double* d_eta, int count,
+                LoglikWork& W, std::vector<double>* alpha_out, std::vector<double>* beta_out, hipStream_t st) {
+    const int np = nprobes_of(o);
+    const int nvec = count * np;
+    const int m = o->lanczos_steps;
+    const bool reorth = o->reorth != 0;
+    const int64_t p = P.p;
+    const int nblk = dot_blocks(p);
+    LanczosBuffers<R> B{};
+    R* Z = nullptr;
+    double* gamma = nullptr;
+    auto lay = [&](Arena& a) {
+        Z = a.take<R>((size_t)nvec * p);
+        B.Q = a.take<R>((size_t)(reorth ? m + 1 : 3) * nvec * p);
+        B.W = a.take<R>((size_t)nvec * p);
+        B.alpha = a.take<double>((size_t)m * nvec);
+        B.beta = a.take<double>((size_t)m * nvec);
+        B.znorm2 = a.take<double>(nvec);
+        B.scale = a.take<double>(nvec);
+        B.active = a.take<int>(nvec);
+        B.steps = a.take<int>(nvec);
+        B.partial = a.take<double>((size_t)nvec * (m + 1) * nblk);
+        B.h = a.take<double>((size_t)nvec * (m + 1));
+        gamma = a.take<double>(nvec);
+    };
+    with_arena(P, lay);
+    make_probes<R>(P, np, o->seed, o->probe_kind == KRY_PROBE_COLOURED ? o->colour_period : 0, Z, st);
+    for (int t = 1; t < count; ++t)
+        KRY_HIP(hipMemcpyAsync(Z + (size_t)t * np * p, Z, (size_t)np * p * sizeof(R), hipMemcpyDeviceToDevice, st));
+    auto A = masked_op<R>(P, lam, lam_tstride, np, d_eta);
+    lanczos_run<R>(A, p, nvec, m, reorth, Z, B, st);
+    quadrature(B.alpha, B.beta, B.steps, B.znorm2, nvec, nvec, gamma, st);
+    W.gamma.resize(nvec);
+    W.steps.resize(nvec);
+    KRY_HIP(hipMemcpyAsync(W.gamma.data(), gamma, nvec * sizeof(double), hipMemcpyDeviceToHost, st));
+    KRY_HIP(hipMemcpyAsync(W.steps.data(), B.steps, nvec * sizeof(int), hipMemcpyDeviceToHost, st));
+    if (alpha_out) {
+        alpha_out->resize((size_t)m * nvec);
+        beta_out->resize((size_t)m * nvec);
+        KRY_HIP(hipMemcpyAsync(alpha_out->data(), B.alpha, (size_t)m * nvec * sizeof(double), hipMemcpyDeviceToHost, st));
+        KRY_HIP(hipMemcpyAsync(beta_out->data(), B.beta, (size_t)m * nvec * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    KRY_HIP(hipStreamSynchronize(st));
+}
+
+void combine(const double* vals, int N, bool coloured, double* est, double* se) {
+    double mean = 0;
+    for (int i = 0; i < N; ++i) mean += vals[i];
+    mean /= N;
+    double ss = 0;
+    for (int i = 0; i < N; ++i) ss += (vals[i] - mean) * (vals[i] - mean);
+    const double sd = N > 1 ? std::sqrt(ss / (N - 1)) : 0.0;
+    if (coloured) {
+        *est = mean * N;
+        *se = std::sqrt((double)N) * sd;
+    } else {
+        *est = mean;
+        *se = sd / std::sqrt((double)N);
+    }
+}
+
+void assemble(kry_loglik_result* r, int64_t p, double logdet, double se, double Q, double sigma2) {
+    const double two_pi = 6.283185307179586476925286766559;
+    r->p = p;
+    r->logdet = logdet;
+    r->logdet_se = se;
+    r->quad = Q;
+    r->loglik = -0.5 * ((double)p * std::log(two_pi * sigma2) + logdet + Q / sigma2);
+    r->sigma2_hat = Q / (double)p;
+    r->loglik_profiled = -0.5 * ((double)p * (std::log(two_pi) + std::log(r->sigma2_hat) + 1.0) + logdet);
+}
+
+// genGK quadratic form and x_k* (Algorithm 1 with the one-product reading:
+// s_i = Sigma v_i is carried along, so each step needs one product Sigma A^T u).
+struct GkOut {
+    std::vector<double> alpha, beta, z;
+    double J = 0;
+    double beta1 = 0;
+};
+
+template <typename R>
+void gengk_device(Problem& P, const Matern& th, const kry_opts* o, GkOut& G, double* x_full_host, hipStream_t st) {
+    const int k = o->gk_steps;
+    const bool reorth = o->reorth != 0;
+    const int64_t p = P.p, n = (int64_t)P.n1 * P.n2;
+    const double tau2 = th.tau2 / th.sigma2;  // unit-variance form: sigma^2 = 1, tau^2 = eta
+    const double sig2 = 1.0;
+    KRY_REQUIRE(tau2 > 0, "genGK needs a positive nugget");
+    const double tau = std::sqrt(tau2);
+    Spectrum& S = problem_spectrum(P, th, st);
+    const void* lam = spec_ptr<R>(S);
+    R *U = nullptr, *V = nullptr, *Sv = nullptr, *u = nullptr, *g = nullptr, *t = nullptr, *xi = nullptr, *sx = nullptr;
+    R* b = nullptr;
+    double *dots = nullptr, *part = nullptr, *coef = nullptr;
+    const int nb = dot_blocks(n);
+    auto lay = [&](Arena& a) {
+        U = a.take<R>((size_t)(k + 1) * p);
+        V = a.take<R>((size_t)(k + 1) * n);
+        Sv = a.take<R>((size_t)(k + 1) * n);
+        g = a.take<R>(p);
+        t = a.take<R>(n);
+        xi = a.take<R>(n);
+        sx = a.take<R>(n);
+        b = a.take<R>(p);
+        dots = a.take<double>(4 * (size_t)(k + 2));
+        part = a.take<double>((size_t)nb * (k + 2));
+        coef = a.take<double>((size_t)(k + 2));
+    };
+    with_arena(P, lay);
+    (void)u;
+    const int32_t* cell = P.cell.as<int32_t>();
+    // b = y (compact data in the working precision)
+    if (sizeof(R) == 8) KRY_HIP(hipMemcpyAsync(b, P.y64.ptr, p * sizeof(double), hipMemcpyDeviceToDevice, st));
+    else KRY_HIP(hipMemcpyAsync(b, P.y32.ptr, p * sizeof(float), hipMemcpyDeviceToDevice, st));
+    auto dot = [&](const R* x, const R* y, int64_t len) {
+        double h;
+        dot_batched<R>(x, len, y, len, len, 1, part, dots, st);
+        KRY_HIP(hipMemcpyAsync(&h, dots, sizeof(double), hipMemcpyDeviceToHost, st));
+        KRY_HIP(hipStreamSynchronize(st));
+        return h;
+    };
+    auto scatter = [&](const R* src, R* full, double sc) {
+        KRY_HIP(hipMemsetAsync(full, 0, n * sizeof(R), st));
+        hipLaunchKernelGGL(k_scatter<R>, grid1(p), dim3(256), 0, st, src, cell, p, full, sc);
+        KRY_HIP(hipGetLastError());
+    };
+    auto gather = [&](const R* full, R* out) {
+        hipLaunchKernelGGL(k_gather<R>, grid1(p), dim3(256), 0, st, full, cell, p, n, out);
+        KRY_HIP(hipGetLastError());
+    };
+    // orthogonalise x against the first nq columns of M (Euclidean, scaled by w) : x -= M (M^T x) * w
+    auto reorth_against = [&](const R* Mbase, int64_t len, int nq, R* x, const R* Tbase, R* x2, double w) {
+        // coefficients c_i = T_i . x (T = M for Euclidean, T = Sigma V for the Sigma-inner product)
+        std::vector<double> c(nq);
+        for (int i = 0; i < nq; ++i) c[i] = dot(Tbase + (size_t)i * len, x, len) * w;
+        for (int i = 0; i < nq; ++i) {
+            axpby<R>(Mbase + (size_t)i * len, x, -c[i], 1.0, len, 1, st);
+            if (x2) axpby<R>(Tbase + (size_t)i * len, x2, -c[i], 1.0, len, 1, st);
+        }
+    };
+
+    G.alpha.clear();
+    G.beta.clear();
+    const double beta1 = std::sqrt(dot(b, b, p)) / tau;
+    KRY_REQUIRE(beta1 > 0, "genGK needs nonzero data");
+    G.beta1 = beta1;
+    G.beta.push_back(beta1);
+    // u1 = b / beta1
+    KRY_HIP(hipMemcpyAsync(U, b, p * sizeof(R), hipMemcpyDeviceToDevice, st));
+    axpby<R>(b, U, 0.0, 1.0 / beta1, p, 1, st);
+    // xi = A^T u1 / tau2, Sigma xi = Sigma A^T u1 / tau2
+    scatter(U, xi, 1.0 / tau2);
+    cov_full<R>(P, lam, U, t, 1, st);
+    KRY_HIP(hipMemcpyAsync(sx, t, n * sizeof(R), hipMemcpyDeviceToDevice, st));
+    axpby<R>(t, sx, 0.0, 1.0 / tau2, n, 1, st);
+    double alpha = std::sqrt(dot(xi, sx, n));
+    G.alpha.push_back(alpha);
+    KRY_HIP(hipMemcpyAsync(V, xi, n * sizeof(R), hipMemcpyDeviceToDevice, st));
+    axpby<R>(xi, V, 0.0, 1.0 / alpha, n, 1, st);
+    KRY_HIP(hipMemcpyAsync(Sv, sx, n * sizeof(R), hipMemcpyDeviceToDevice, st));
+    axpby<R>(sx, Sv, 0.0, 1.0 / alpha, n, 1, st);
+    for (int i = 0; i < k; ++i) {
+        R* vi = V + (size_t)i * n;
+        R* si = Sv + (size_t)i * n;
+        R* ui = U + (size_t)i * p;
+        R* un = U + (size_t)(i + 1) * p;
+        // g = A Sigma v_i - alpha_i u_i
+        gather(si, g);
+        axpby<R>(ui, g, -alpha, 1.0, p, 1, st);
+        if (reorth) {
+            for (int pass = 0; pass < 2; ++pass) reorth_against(U, p, i + 1, g, U, nullptr, 1.0 / tau2);
+        }
+        const double beta = std::sqrt(dot(g, g, p)) / tau;
+        G.beta.push_back(beta);
+        KRY_HIP(hipMemcpyAsync(un, g, p * sizeof(R), hipMemcpyDeviceToDevice, st));
+        axpby<R>(g, un, 0.0, 1.0 / beta, p, 1, st);
+        if (i == k - 1) break;  // B_k needs alpha_1..alpha_k, beta_2..beta_{k+1}
+        // xi = A^T u_{i+1} / tau2 - beta v_i ; Sigma xi = Sigma A^T u_{i+1} / tau2 - beta s_i
+        scatter(un, xi, 1.0 / tau2);
+        axpby<R>(vi, xi, -beta, 1.0, n, 1, st);
+        cov_full<R>(P, lam, un, t, 1, st);
+        KRY_HIP(hipMemcpyAsync(sx, si, n * sizeof(R), hipMemcpyDeviceToDevice, st));
+        axpby<R>(t, sx, 1.0 / tau2, -beta, n, 1, st);
+        if (reorth) {
+            for (int pass = 0; pass < 2; ++pass) reorth_against(V, n, i + 1, xi, Sv, sx, 1.0);
+        }
+        alpha = std::sqrt(dot(xi, sx, n));
+        G.alpha.push_back(alpha);
+        R* vn = V + (size_t)(i + 1) * n;
+        R* sn = Sv + (size_t)(i + 1) * n;
+        KRY_HIP(hipMemcpyAsync(vn, xi, n * sizeof(R), hipMemcpyDeviceToDevice, st));
+        axpby<R>(xi, vn, 0.0, 1.0 / alpha, n, 1, st);
+        KRY_HIP(hipMemcpyAsync(sn, sx, n * sizeof(R), hipMemcpyDeviceToDevice, st));
+        axpby<R>(sx, sn, 0.0, 1.0 / alpha, n, 1, st);
+    }
+    // projected Tikhonov problem (eq. xhat_est): (B^T B + I / sigma^2) z = B^T beta1 e1
+    // B^T B is tridiagonal: diag alpha_i^2 + beta_{i+1}^2, off-diag alpha_{i+1} beta_{i+1}
+    std::vector<double> dg(k), od(k > 1 ? k - 1 : 1), rhs(k, 0.0);
+    for (int i = 0; i < k; ++i) dg[i] = G.alpha[i] * G.alpha[i] + G.beta[i + 1] * G.beta[i + 1] + 1.0 / sig2;
+    for (int i = 0; i + 1 < k; ++i) od[i] = G.alpha[i + 1] * G.beta[i + 1];
+    rhs[0] = G.alpha[0] * beta1;
+    // symmetric tridiagonal solve (Thomas algorithm; the matrix is positive definite)
+    std::vector<double> cp(k), dp(k);
+    cp[0] = k > 1 ? od[0] / dg[0] : 0.0;
+    dp[0] = rhs[0] / dg[0];
+    for (int i = 1; i < k; ++i) {
+        const double den = dg[i] - od[i - 1] * cp[i - 1];
+        cp[i] = (i + 1 < k) ? od[i] / den : 0.0;
+        dp[i] = (rhs[i] - od[i - 1] * dp[i - 1]) / den;
+    }
+    G.z.assign(k, 0.0);
+    G.z[k - 1] = dp[k - 1];
+    for (int i = k - 2; i >= 0; --i) G.z[i] = dp[i] - cp[i] * G.z[i + 1];
+    // J = ||B z - beta1 e1||^2 + ||z||^2 / sigma^2
+    double J = 0, zz = 0;
+    for (int i = 0; i <= k; ++i) {
+        double bz = 0;
+        if (i < k) bz += G.alpha[i] * G.z[i];
+        if (i >= 1) bz += G.beta[i] * G.z[i - 1];
+        if (i == 0) bz -= beta1;
+        J += bz * bz;
+    }
+    for (int i = 0; i < k; ++i) zz += G.z[i] * G.z[i];
+    G.J = J + zz / sig2;
+    if (x_full_host) {
+        // x_k* = Sigma V_k z = sum_i z_i s_i
+        KRY_HIP(hipMemsetAsync(t, 0, n * sizeof(R), st));
+        for (int i = 0; i < k; ++i) axpby<R>(Sv + (size_t)i * n, t, G.z[i], 1.0, n, 1, st);
+        std::vector<R> h(n);
+        KRY_HIP(hipMemcpyAsync(h.data(), t, n * sizeof(R), hipMemcpyDeviceToHost, st));
+        KRY_HIP(hipStreamSynchronize(st));
+        for (int64_t i = 0; i < n; ++i) x_full_host[i] = (double)h[i];
+    }
+}
+
+// log-likelihood for `count` parameter points that share nu and anisotropy
+// handling (each with its own spectrum) on one problem.
+void loglik_points(Problem& P, const kry_matern* thetas, int count, const kry_opts* o, kry_loglik_result* out,
+                   hipStream_t st) {
+    Ctx& C = *P.ctx;
+    const int np = nprobes_of(o);
+    const int64_t nspec = (int64_t)(P.N2 / 2 + 1) * P.N1;
+    const bool fp32 = o->precision == KRY_FP32;
+    // spectra for every point
+    P.spec_multi64.ensure(C, (size_t)count * nspec * sizeof(double));
+    if (fp32) P.spec_multi32.ensure(C, (size_t)count * nspec * sizeof(float));
+    std::vector<double> eta(count);
+    for (int t = 0; t < count; ++t) {
+        const Matern th = to_matern(&thetas[t]);
+        eta[t] = th.tau2 / th.sigma2;
+        double lo, hi;
+        double* dst = P.spec_multi64.as<double>() + (size_t)t * nspec;
+        spectrum_device(P, P.N1, P.N2, th, dst, &lo, &hi, st);
+        spectrum_scale(dst, nspec, 1.0 / ((double)P.N1 * P.N2), false, dst,
+                       fp32 ? P.spec_multi32.as<float>() + (size_t)t * nspec : nullptr, st);
+    }
+    // eta and the data for every point live in a small device buffer
+    DevBuf etab;
+    etab.ensure(C, count * sizeof(double) + (size_t)count * P.p * 2 * sizeof(double) + 512);
+    struct Free {
+        Ctx& c;
+        DevBuf& b;
+        ~Free() { b.release(c); }
+    } fr{C, etab};
+    double* d_eta = etab.as<double>();
+    double* Y = reinterpret_cast<double*>(etab.as<char>() + 256);
+    double* X = Y + (size_t)count * P.p;
+    KRY_HIP(hipMemcpyAsync(d_eta, eta.data(), count * sizeof(double), hipMemcpyHostToDevice, st));
+    // log-determinants
+    LoglikWork W;
+    if (fp32) slq_device<float>(P, o, P.spec_multi32.ptr, nspec, d_eta, count, W, nullptr, nullptr, st);
+    else slq_device<double>(P, o, P.spec_multi64.ptr, nspec, d_eta, count, W, nullptr, nullptr, st);
+    // quadratic forms
+    std::vector<double> Q(count, 0.0);
+    std::vector<int> iters(count, 0);
+    std::vector<double> relres(count, 0.0);
+    if (o->solver == KRY_SOLVER_CG) {
+        for (int t = 0; t < count; ++t)
+            KRY_HIP(hipMemcpyAsync(Y + (size_t)t * P.p, P.y64.ptr, P.p * sizeof(double), hipMemcpyDeviceToDevice, st));
+        SolveStats ss;
+        solve_device(P, o->precision, P.spec_multi64.ptr, fp32 ? P.spec_multi32.ptr : nullptr, nspec, 1, d_eta, count,
+                     Y, X, o->cg_rtol, o->cg_maxit, ss, st);
+        // Q_t = y . x_t
+        std::vector<double> h((size_t)count * P.p);
+        double* part = nullptr;
+        P.lagtmp.ensure(C, (size_t)(count * 256 + count + 8) * sizeof(double));
+        part = P.lagtmp.as<double>();
+        dot_batched<double>(Y, P.p, X, P.p, P.p, count, part, part + count * 256, st);
+        KRY_HIP(hipMemcpyAsync(Q.data(), part + count * 256, count * sizeof(double), hipMemcpyDeviceToHost, st));
+        KRY_HIP(hipStreamSynchronize(st));
+        iters = ss.iters;
+        relres = ss.relres;
+    } else {
+        for (int t = 0; t < count; ++t) {
+            GkOut G;
+            const Matern th = to_matern(&thetas[t]);
+            if (fp32) gengk_device<float>(P, th, o, G, nullptr, st);
+            else gengk_device<double>(P, th, o, G, nullptr, st);
+            Q[t] = G.J;  // unit-variance form: sigma^2 = 1 so Q = J
+            iters[t] = o->gk_steps;
+        }
+    }
+    for (int t = 0; t < count; ++t) {
+        double est, se;
+        combine(W.gamma.data() + (size_t)t * np, np, o->probe_kind == KRY_PROBE_COLOURED, &est, &se);
+        kry_loglik_result& r = out[t];
+        std::memset(&r, 0, sizeof(r));
+        assemble(&r, P.p, est, se, Q[t], thetas[t].sigma2);
+        int smax = 0;
+        for (int k = 0; k < np; ++k) smax = std::max(smax, W.steps[(size_t)t * np + k]);
+        r.lanczos_steps_used = smax;
+        r.cg_iters = iters[t];
+        r.cg_relres = relres[t];
+    }
+}
+
+bool any_not_converged(const kry_loglik_result* r, int count, const kry_opts* o) {
+    if (o->solver != KRY_SOLVER_CG) return false;
+    for (int t = 0; t < count; ++t)
+        if (r[t].cg_relres > o->cg_rtol) return true;
+    return false;
+}
+
+}  // namespace
+
+// ===========================================================================
+// ABI (C linkage comes from the declarations in kryging.h)
+// ===========================================================================
+
+const char* kry_status_string(kry_status s) {
+    switch (s) {
+        case KRY_OK: return "ok";
+        case KRY_EINVAL: return "invalid argument";
+        case KRY_ENOMEM: return "out of device memory or above the HBM budget";
+        case KRY_EDEVICE: return "HIP runtime error";
+        case KRY_ENOTPSD: return "circulant embedding not positive semi-definite";
+        case KRY_ENOCONV: return "iteration limit reached";
+        case KRY_EBUSY: return "server queue full";
+        case KRY_ENOTIMPL: return "not implemented";
+    }
+    return "unknown status";
+}
+
+const char* kry_last_error(void) { return g_last_error.c_str(); }
+
+kry_status kry_opts_default(kry_opts* out) {
+    return guard([&] {
+        KRY_REQUIRE(out != nullptr, "out is NULL");
+        kry_opts o;
+        std::memset(&o, 0, sizeof(o));
+        o.lanczos_steps = 30;
+        o.num_probes = 10;
+        o.probe_kind = KRY_PROBE_RADEMACHER;
+        o.colour_period = 4;
+        o.seed = 303;
+        o.reorth = 0;
+        o.precision = KRY_FP64;
+        o.cg_rtol = 1e-8;
+        o.cg_maxit = 20000;
+        o.solver = KRY_SOLVER_CG;
+        o.gk_steps = 100;
+        *out = o;
+    });
+}
+
+kry_status kry_ctx_create(int32_t device, uint64_t hbm_budget_bytes, kry_ctx** out) {
+    return guard([&] {
+        KRY_REQUIRE(out != nullptr, "out is NULL");
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+            (void)hipGetLastError();
+            throw Error(KRY_EDEVICE, "no HIP device available");
+        }
+        KRY_REQUIRE(device >= 0 && device < ndev, "device index out of range");
+        auto* k = new kry_ctx();
+        try {
+            k->c.device = device;
+            k->c.budget = hbm_budget_bytes;
+            KRY_HIP(hipSetDevice(device));
+            KRY_HIP(hipStreamCreateWithFlags(&k->c.stream, hipStreamNonBlocking));
+            // twiddles exp(-2 pi i e / TW_N), computed in long double
+            std::vector<cpx<double>> t64(TW_N);
+            std::vector<cpx<float>> t32(TW_N);
+            const long double pi = 3.141592653589793238462643383279502884L;
+            for (int e = 0; e < TW_N; ++e) {
+                const long double a = -2.0L * pi * (long double)e / (long double)TW_N;
+                t64[e] = {(double)cosl(a), (double)sinl(a)};
+                t32[e] = {(float)cosl(a), (float)sinl(a)};
+            }
+            k->c.tw64 = static_cast<cpx<double>*>(dev_alloc(k->c, TW_N * sizeof(cpx<double>)));
+            k->c.tw32 = static_cast<cpx<float>*>(dev_alloc(k->c, TW_N * sizeof(cpx<float>)));
+            KRY_HIP(hipMemcpy(k->c.tw64, t64.data(), TW_N * sizeof(cpx<double>), hipMemcpyHostToDevice));
+            KRY_HIP(hipMemcpy(k->c.tw32, t32.data(), TW_N * sizeof(cpx<float>), hipMemcpyHostToDevice));
+        } catch (...) {
+            kry_ctx_destroy(k);
+            throw;
+        }
+        *out = k;
+    });
+}
+
+void kry_ctx_destroy(kry_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->c.device);
+    if (ctx->c.stream) (void)hipStreamSynchronize(ctx->c.stream);
+    dev_free(ctx->c, ctx->c.tw64, TW_N * sizeof(cpx<double>));
+    dev_free(ctx->c, ctx->c.tw32, TW_N * sizeof(cpx<float>));
+    if (ctx->c.stream) (void)hipStreamDestroy(ctx->c.stream);
+    delete ctx;
+}
+
+static void upload_data(Problem& P, const double* y) {
+    std::vector<double> yc(P.p, 0.0);
+    if (y) {
+        for (int64_t i = 0; i < P.p; ++i) {
+            const double v = y[P.h_cell[i]];
+            KRY_REQUIRE(std::isfinite(v), "y has a non-finite value at an observed cell");
+            yc[i] = v;
+        }
+    }
+    std::vector<float> yf(yc.begin(), yc.end());
+    KRY_HIP(hipMemcpy(P.y64.ptr, yc.data(), P.p * sizeof(double), hipMemcpyHostToDevice));
+    KRY_HIP(hipMemcpy(P.y32.ptr, yf.data(), P.p * sizeof(float), hipMemcpyHostToDevice));
+}
+
+kry_status kry_problem_create(kry_ctx* ctx, const kry_grid* grid, const uint8_t* mask, const double* y,
+                              kry_problem** out) {
+    return guard([&] {
+        KRY_REQUIRE(ctx && grid && mask && out, "NULL argument");
+        KRY_REQUIRE(grid->n1 >= 2 && grid->n2 >= 2 && grid->n1 <= 4096 && grid->n2 <= 4096,
+                    "grid sides must be in [2, 4096]");
+        KRY_REQUIRE(std::isfinite(grid->dx1) && std::isfinite(grid->dx2) && grid->dx1 > 0 && grid->dx2 > 0,
+                    "grid spacings must be finite and > 0");
+        const int n1 = grid->n1, n2 = grid->n2;
+        const int64_t n = (int64_t)n1 * n2;
+        int64_t p = 0;
+        for (int64_t i = 0; i < n; ++i) p += mask[i] ? 1 : 0;
+        KRY_REQUIRE(p > 0, "mask has no observed cell");
+        if (y)
+            for (int64_t i = 0; i < n; ++i)
+                if (mask[i]) KRY_REQUIRE(std::isfinite(y[i]), "y has a non-finite value at an observed cell");
+        bind(ctx->c);
+        auto* kp = new kry_problem();
+        Problem& P = kp->P;
+        try {
+            P.ctx = &ctx->c;
+            P.n1 = n1;
+            P.n2 = n2;
+            P.dx1 = grid->dx1;
+            P.dx2 = grid->dx2;
+            P.N1 = pow2_at_least(2 * n1 - 1);
+            P.N2 = pow2_at_least(2 * n2 - 1);
+            P.p = p;
+            P.words_per_row = (n2 + 31) / 32;
+            const int64_t nw = (int64_t)n1 * P.words_per_row;
+            std::vector<uint32_t> bits(nw, 0u), base(nw, 0u);
+            P.h_cell.resize(p);
+            P.h_mask.assign(mask, mask + n);
+            std::vector<int32_t> cell(p);
+            int64_t c = 0;
+            for (int i = 0; i < n1; ++i)
+                for (int j = 0; j < n2; ++j)
+                    if (mask[(int64_t)i * n2 + j]) {
+                        bits[(int64_t)i * P.words_per_row + (j >> 5)] |= 1u << (j & 31);
+                        P.h_cell[c] = (int64_t)i * n2 + j;
+                        cell[c] = (int32_t)((int64_t)i * n2 + j);
+                        ++c;
+                    }
+            uint32_t acc = 0;
+            for (int64_t w = 0; w < nw; ++w) {
+                base[w] = acc;
+                acc += (uint32_t)__builtin_popcount(bits[w]);
+            }
+            P.bits.ensure(ctx->c, nw * sizeof(uint32_t));
+            P.base.ensure(ctx->c, nw * sizeof(uint32_t));
+            P.cell.ensure(ctx->c, p * sizeof(int32_t));
+            P.y64.ensure(ctx->c, p * sizeof(double));
+            P.y32.ensure(ctx->c, p * sizeof(float));
+            KRY_HIP(hipMemcpy(P.bits.ptr, bits.data(), nw * sizeof(uint32_t), hipMemcpyHostToDevice));
+            KRY_HIP(hipMemcpy(P.base.ptr, base.data(), nw * sizeof(uint32_t), hipMemcpyHostToDevice));
+            KRY_HIP(hipMemcpy(P.cell.ptr, cell.data(), p * sizeof(int32_t), hipMemcpyHostToDevice));
+            upload_data(P, y);
+        } catch (...) {
+            kry_problem_destroy(kp);
+            throw;
+        }
+        *out = kp;
+    });
+}
+
+kry_status kry_problem_set_data(kry_problem* prob, const double* y) {
+    return guard([&] {
+        KRY_REQUIRE(prob && y, "NULL argument");
+        Problem& P = prob->P;
+        for (int64_t i = 0; i < P.p; ++i)
+            KRY_REQUIRE(std::isfinite(y[P.h_cell[i]]), "y has a non-finite value at an observed cell");
+        bind(*P.ctx);
+        upload_data(P, y);
+    });
+}
+
+kry_status kry_problem_info(const kry_problem* prob, int64_t* p, int32_t* N1, int32_t* N2) {
+    return guard([&] {
+        KRY_REQUIRE(prob != nullptr, "prob is NULL");
+        if (p) *p = prob->P.p;
+        if (N1) *N1 = prob->P.N1;
+        if (N2) *N2 = prob->P.N2;
+    });
+}
+
+void kry_problem_destroy(kry_problem* prob) {
+    if (!prob) return;
+    Problem& P = prob->P;
+    if (P.ctx) {
+        Ctx& c = *P.ctx;
+        (void)hipSetDevice(c.device);
+        (void)hipStreamSynchronize(c.stream);
+        for (DevBuf* b : {&P.bits, &P.base, &P.cell, &P.y64, &P.y32, &P.Y, &P.lagtmp, &P.spectmp, &P.spec_multi64,
+                          &P.spec_multi32, &P.kws, &P.scal, &P.spec.s64, &P.spec.s32})
+            b->release(c);
+    }
+    delete prob;
+}
+
+static void torus_args(Problem& P, int32_t& N1, int32_t& N2) {
+    if (N1 == 0 && N2 == 0) {
+        N1 = P.N1;
+        N2 = P.N2;
+    }
+    KRY_REQUIRE(N1 >= 16 && N2 >= 16 && N1 <= 8192 && N2 <= 8192, "torus sizes must be in [16, 8192]");
+    KRY_REQUIRE((N1 & (N1 - 1)) == 0 && (N2 & (N2 - 1)) == 0, "torus sizes must be powers of two");
+}
+
+kry_status kry_lag_grid(kry_problem* prob, const kry_matern* theta, int32_t N1, int32_t N2, double* c_out) {
+    return guard([&] {
+        KRY_REQUIRE(prob && c_out, "NULL argument");
+        check_theta(theta);
+        Problem& P = prob->P;
+        torus_args(P, N1, N2);
+        bind(*P.ctx);
+        hipStream_t st = P.ctx->stream;
+        P.lagtmp.ensure(*P.ctx, (size_t)N1 * N2 * sizeof(double));
+        lag_grid_device(*P.ctx, N1, N2, P.dx1, P.dx2, to_matern(theta), P.lagtmp.as<double>(), st);
+        KRY_HIP(hipMemcpyAsync(c_out, P.lagtmp.ptr, (size_t)N1 * N2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        KRY_HIP(hipStreamSynchronize(st));
+    });
+}
+
+kry_status kry_spectrum(kry_problem* prob, const kry_matern* theta, int32_t N1, int32_t N2, double* lam_out,
+                        double* minmax) {
+    return guard([&] {
+        KRY_REQUIRE(prob && lam_out, "NULL argument");
+        check_theta(theta);
+        Problem& P = prob->P;
+        torus_args(P, N1, N2);
+        bind(*P.ctx);
+        hipStream_t st = P.ctx->stream;
+        const size_t n = (size_t)(N2 / 2 + 1) * N1;
+        DevBuf tmp;
+        tmp.ensure(*P.ctx, n * sizeof(double));
+        try {
+            double lo, hi;
+            spectrum_device(P, N1, N2, to_matern(theta), tmp.as<double>(), &lo, &hi, st);
+            KRY_HIP(hipMemcpyAsync(lam_out, tmp.ptr, n * sizeof(double), hipMemcpyDeviceToHost, st));
+            KRY_HIP(hipStreamSynchronize(st));
+            if (minmax) {
+                minmax[0] = lo;
+                minmax[1] = hi;
+            }
+        } catch (...) {
+            tmp.release(*P.ctx);
+            throw;
+        }
+        tmp.release(*P.ctx);
+    });
+}
+
+template <typename R>
+static void matvec_dev_impl(Problem& P, const Matern& th, int nvec, const void* in, void* out, hipStream_t st) {
+    Spectrum& S = problem_spectrum(P, th, st);
+    const double eta = th.tau2 / th.sigma2;
+    P.scal.ensure(*P.ctx, 256);
+    KRY_HIP(hipMemcpyAsync(P.scal.ptr, &eta, sizeof(double), hipMemcpyHostToDevice, st));
+    auto A = masked_op<R>(P, spec_ptr<R>(S), 0, nvec, P.scal.as<double>());
+    A(static_cast<const R*>(in), static_cast<R*>(out), nvec, st);
+}
+
+kry_status kry_matvec_device(kry_problem* prob, const kry_matern* theta, int32_t precision, int32_t nvec,
+                             const void* d_v, void* d_out, void* hip_stream) {
+    return guard([&] {
+        KRY_REQUIRE(prob && d_v && d_out, "NULL argument");
+        check_theta(theta);
+        KRY_REQUIRE(nvec >= 1, "nvec must be >= 1");
+        KRY_REQUIRE(precision == KRY_FP64 || precision == KRY_FP32, "bad precision");
+        Problem& P = prob->P;
+        bind(*P.ctx);
+        hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : P.ctx->stream;
+        if (precision == KRY_FP64) matvec_dev_impl<double>(P, to_matern(theta), nvec, d_v, d_out, st);
+        else matvec_dev_impl<float>(P, to_matern(theta), nvec, d_v, d_out, st);
+    });
+}
+
+kry_status kry_matvec(kry_problem* prob, const kry_matern* theta, int32_t precision, int32_t nvec, const double* v,
+                      double* out) {
+    return guard([&] {
+        KRY_REQUIRE(prob && v && out, "NULL argument");
+        check_theta(theta);
+        KRY_REQUIRE(nvec >= 1, "nvec must be >= 1");
+        KRY_REQUIRE(precision == KRY_FP64 || precision == KRY_FP32, "bad precision");
+        Problem& P = prob->P;
+        bind(*P.ctx);
+        hipStream_t st = P.ctx->stream;
+        const size_t n = (size_t)nvec * P.p;
+        DevBuf io;
+        io.ensure(*P.ctx, 2 * n * sizeof(double));
+        struct Free {
+            Ctx& c;
+            DevBuf& b;
+            ~Free() { b.release(c); }
+        } fr{*P.ctx, io};
+        double* d_in = io.as<double>();
+        double* d_out = d_in + n;
+        KRY_HIP(hipMemcpyAsync(d_in, v, n * sizeof(double), hipMemcpyHostToDevice, st));
+        if (precision == KRY_FP64) {
+            matvec_dev_impl<double>(P, to_matern(theta), nvec, d_in, d_out, st);
+        } else {
+            float* f_in = reinterpret_cast<float*>(d_out);  // staging: out region holds the float input first
+            float* f_out = reinterpret_cast<float*>(d_in);
+            convert<double, float>(d_in, f_in, n, st);
+            // f_out overlaps d_in, which is no longer needed once converted
+            matvec_dev_impl<float>(P, to_matern(theta), nvec, f_in, f_out, st);
+            convert<float, double>(f_out, d_out, n, st);
+        }
+        KRY_HIP(hipMemcpyAsync(out, d_out, n * sizeof(double), hipMemcpyDeviceToHost, st));
+        KRY_HIP(hipStreamSynchronize(st));
+    });
+}
+
+kry_status kry_cov_apply_full(kry_problem* prob, const kry_matern* theta, int32_t precision, int32_t nvec,
+                              const double* w, double* out) {
+    return guard([&] {
+        KRY_REQUIRE(prob && w && out, "NULL argument");
+        check_theta(theta);
+        KRY_REQUIRE(nvec >= 1, "nvec must be >= 1");
+        KRY_REQUIRE(precision == KRY_FP64 || precision == KRY_FP32, "bad precision");
+        Problem& P = prob->P;
+        bind(*P.ctx);
+        hipStream_t st = P.ctx->stream;
+        const int64_t n = (int64_t)P.n1 * P.n2;
+        const size_t nin = (size_t)nvec * P.p, nout = (size_t)nvec * n;
+        DevBuf io;
+        io.ensure(*P.ctx, (nin + 2 * nout) * sizeof(double) + 512);
+        struct Free {
+            Ctx& c;
+            DevBuf& b;
+            ~Free() { b.release(c); }
+        } fr{*P.ctx, io};
+        double* d_in = io.as<double>();
+        double* d_out = d_in + nin;
+        Spectrum& S = problem_spectrum(P, to_matern(theta), st);
+        KRY_HIP(hipMemcpyAsync(d_in, w, nin * sizeof(double), hipMemcpyHostToDevice, st));
+        if (precision == KRY_FP64) {
+            cov_full<double>(P, S.s64.ptr, d_in, d_out, nvec, st);
+        } else {
+            float* f_in = reinterpret_cast<float*>(d_out + nout);
+            float* f_out = reinterpret_cast<float*>(d_out);
+            convert<double, float>(d_in, f_in, nin, st);
+            float* tmp = reinterpret_cast<float*>(d_out + nout) + nin;
+            cov_full<float>(P, S.s32.ptr, f_in, tmp, nvec, st);
+            convert<float, double>(tmp, d_out, nout, st);
+            (void)f_out;
+        }
+        KRY_HIP(hipMemcpyAsync(out, d_out, nout * sizeof(double), hipMemcpyDeviceToHost, st));
+        KRY_HIP(hipStreamSynchronize(st));
+    });
+}
+
+kry_status kry_probes(kry_problem* prob, const kry_opts* opts, int32_t* nprobe, double* out) {
+    return guard([&] {
+        KRY_REQUIRE(prob && nprobe, "NULL argument");
+        check_opts(opts);
+        Problem& P = prob->P;
+        const int np = nprobes_of(opts);
+        *nprobe = np;
+        if (!out) return;
+        bind(*P.ctx);
+        hipStream_t st = P.ctx->stream;
+        DevBuf tmp;
+        tmp.ensure(*P.ctx, (size_t)np * P.p * sizeof(double));
+        struct Free {
+            Ctx& c;
+            DevBuf& b;
+            ~Free() { b.release(c); }
+        } fr{*P.ctx, tmp};
+        make_probes<double>(P, np, opts->seed, opts->probe_kind == KRY_PROBE_COLOURED ? opts->colour_period : 0,
+                            tmp.as<double>(), st);
+        KRY_HIP(hipMemcpyAsync(out, tmp.ptr, (size_t)np * P.p * sizeof(double), hipMemcpyDeviceToHost, st));
+        KRY_HIP(hipStreamSynchronize(st));
+    });
+}
+
+static void single_point_spectrum(Problem& P, const Matern& th, const kry_opts* o, const void** lam, double** d_eta,
+                                  hipStream_t st) {
+    Spectrum& S = problem_spectrum(P, th, st);
+    *lam = o->precision == KRY_FP32 ? S.s32.ptr : S.s64.ptr;
+    const double eta = th.tau2 / th.sigma2;
+    P.lagtmp.ensure(*P.ctx, 256);
+    *d_eta = P.lagtmp.as<double>();
+    KRY_HIP(hipMemcpyAsync(*d_eta, &eta, sizeof(double), hipMemcpyHostToDevice, st));
+}
+
+kry_status kry_lanczos(kry_problem* prob, const kry_matern* theta, const kry_opts* opts, double* alpha, double* beta,
+                       int32_t* steps) {
+    return guard([&] {
+        KRY_REQUIRE(prob && alpha && beta && steps, "NULL argument");
+        check_theta(theta);
+        check_opts(opts);
+        Problem& P = prob->P;
+        bind(*P.ctx);
+        hipStream_t st = P.ctx->stream;
+        const void* lam;
+        double* d_eta;
+        // keep eta outside lagtmp (the spectrum path reuses lagtmp): copy to scal
+        single_point_spectrum(P, to_matern(theta), opts, &lam, &d_eta, st);
+        P.scal.ensure(*P.ctx, 256);
+        KRY_HIP(hipMemcpyAsync(P.scal.ptr, d_eta, sizeof(double), hipMemcpyDeviceToDevice, st));
+        LoglikWork W;
+        std::vector<double> a, b;
+        const int np = nprobes_of(opts), m = opts->lanczos_steps;
+        if (opts->precision == KRY_FP32)
+            slq_device<float>(P, opts, lam, 0, P.scal.as<double>(), 1, W, &a, &b, st);
+        else
+            slq_device<double>(P, opts, lam, 0, P.scal.as<double>(), 1, W, &a, &b, st);
+        for (int k = 0; k < np; ++k) {
+            steps[k] = W.steps[k];
+            for (int j = 0; j < m; ++j) {
+                alpha[(size_t)k * m + j] = a[(size_t)j * np + k];
+                beta[(size_t)k * m + j] = b[(size_t)j * np + k];
+            }
+        }
+    });
+}
+
+kry_status kry_logdet(kry_problem* prob, const kry_matern* theta, const kry_opts* opts, double* logdet, double* se,
+                      double* per_probe) {
+    return guard([&] {
+        KRY_REQUIRE(prob && logdet, "NULL argument");
+        check_theta(theta);
+        check_opts(opts);
+        Problem& P = prob->P;
+        bind(*P.ctx);
+        hipStream_t st = P.ctx->stream;
+        const void* lam;
+        double* d_eta;
+        single_point_spectrum(P, to_matern(theta), opts, &lam, &d_eta, st);
+        P.scal.ensure(*P.ctx, 256);
+        KRY_HIP(hipMemcpyAsync(P.scal.ptr, d_eta, sizeof(double), hipMemcpyDeviceToDevice, st));
+        LoglikWork W;
+        if (opts->precision == KRY_FP32)
+            slq_device<float>(P, opts, lam, 0, P.scal.as<double>(), 1, W, nullptr, nullptr, st);
+        else
+            slq_device<double>(P, opts, lam, 0, P.scal.as<double>(), 1, W, nullptr, nullptr, st);
+        const int np = nprobes_of(opts);
+        double est, s;
+        combine(W.gamma.data(), np, opts->probe_kind == KRY_PROBE_COLOURED, &est, &s);
+        *logdet = est;
+        if (se) *se = s;
+        if (per_probe) std::copy(W.gamma.begin(), W.gamma.end(), per_probe);
+    });
+}
+
+kry_status kry_gauss_quadrature(int32_t nprobe, int32_t m, const double* alpha, const double* beta,
+                                const int32_t* steps, const double* znorm2, double* gamma) {
+    return guard([&] {
+        KRY_REQUIRE(alpha && beta && steps && znorm2 && gamma, "NULL argument");
+        KRY_REQUIRE(nprobe >= 1 && m >= 1 && m <= KRY_MAX_LANCZOS, "bad sizes");
+        for (int k = 0; k < nprobe; ++k) KRY_REQUIRE(steps[k] >= 0 && steps[k] <= m, "steps out of range");
+        int dev = 0;
+        KRY_HIP(hipGetDevice(&dev));
+        // device copies in step-major layout
+        std::vector<double> a((size_t)m * nprobe), b((size_t)m * nprobe);
+        for (int k = 0; k < nprobe; ++k)
+            for (int j = 0; j < m; ++j) {
+                a[(size_t)j * nprobe + k] = alpha[(size_t)k * m + j];
+                b[(size_t)j * nprobe + k] = beta[(size_t)k * m + j];
+            }
+        void* d = nullptr;
+        const size_t bytes = (2 * (size_t)m * nprobe + 2 * nprobe) * sizeof(double) + nprobe * sizeof(int);
+        KRY_HIP(hipMalloc(&d, bytes));
+        struct F {
+            void* p;
+            ~F() { (void)hipFree(p); }
+        } f{d};
+        double* da = static_cast<double*>(d);
+        double* db = da + (size_t)m * nprobe;
+        double* dz = db + (size_t)m * nprobe;
+        double* dg = dz + nprobe;
+        int* ds = reinterpret_cast<int*>(dg + nprobe);
+        KRY_HIP(hipMemcpy(da, a.data(), a.size() * sizeof(double), hipMemcpyHostToDevice));
+        KRY_HIP(hipMemcpy(db, b.data(), b.size() * sizeof(double), hipMemcpyHostToDevice));
+        KRY_HIP(hipMemcpy(dz, znorm2, nprobe * sizeof(double), hipMemcpyHostToDevice));
+        KRY_HIP(hipMemcpy(ds, steps, nprobe * sizeof(int), hipMemcpyHostToDevice));
+        quadrature(da, db, ds, dz, nprobe, nprobe, dg, nullptr);
+        KRY_HIP(hipMemcpy(gamma, dg, nprobe * sizeof(double), hipMemcpyDeviceToHost));
+    });
+}
+
+kry_status kry_solve(kry_problem* prob, const kry_matern* theta, const kry_opts* opts, int32_t nrhs, const double* b,
+                     double* x, int32_t* iters, double* relres) {
+    bool noconv = false;
+    kry_status s = guard([&] {
+        KRY_REQUIRE(prob && b && x, "NULL argument");
+        check_theta(theta);
+        check_opts(opts);
+        KRY_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+        Problem& P = prob->P;
+        bind(*P.ctx);
+        hipStream_t st = P.ctx->stream;
+        const Matern th = to_matern(theta);
+        Spectrum& S = problem_spectrum(P, th, st);
+        const double eta = th.tau2 / th.sigma2;
+        const size_t n = (size_t)nrhs * P.p;
+        DevBuf io;
+        io.ensure(*P.ctx, 2 * n * sizeof(double) + 512);
+        struct Free {
+            Ctx& c;
+            DevBuf& b;
+            ~Free() { b.release(c); }
+        } fr{*P.ctx, io};
+        double* d_eta = io.as<double>();
+        double* d_b = reinterpret_cast<double*>(io.as<char>() + 256);
+        double* d_x = d_b + n;
+        KRY_HIP(hipMemcpyAsync(d_eta, &eta, sizeof(double), hipMemcpyHostToDevice, st));
+        KRY_HIP(hipMemcpyAsync(d_b, b, n * sizeof(double), hipMemcpyHostToDevice, st));
+        SolveStats ss;
+        solve_device(P, opts->precision, S.s64.ptr, S.s32.ptr, 0, nrhs, d_eta, nrhs, d_b, d_x, opts->cg_rtol,
+                     opts->cg_maxit, ss, st);
+        KRY_HIP(hipMemcpyAsync(x, d_x, n * sizeof(double), hipMemcpyDeviceToHost, st));
+        KRY_HIP(hipStreamSynchronize(st));
+        for (int v = 0; v < nrhs; ++v) {
+            if (iters) iters[v] = ss.iters[v];
+            if (relres) relres[v] = ss.relres[v];
+            if (ss.relres[v] > opts->cg_rtol) noconv = true;
+        }
+    });
+    if (s == KRY_OK && noconv) {
+        g_last_error = "CG reached cg_maxit before cg_rtol";
+        return KRY_ENOCONV;
+    }
+    return s;
+}
+
+kry_status kry_gengk(kry_problem* prob, const kry_matern* theta, const kry_opts* opts, double* alpha, double* beta,
+                     double* z, double* x_full, double* J) {
+    return guard([&] {
+        KRY_REQUIRE(prob && alpha && beta && z && J, "NULL argument");
+        check_theta(theta);
+        check_opts(opts);
+        Problem& P = prob->P;
+        bind(*P.ctx);
+        hipStream_t st = P.ctx->stream;
+        GkOut G;
+        if (opts->precision == KRY_FP32) gengk_device<float>(P, to_matern(theta), opts, G, x_full, st);
+        else gengk_device<double>(P, to_matern(theta), opts, G, x_full, st);
+        const int k = opts->gk_steps;
+        for (int i = 0; i < k; ++i) {
+            alpha[i] = G.alpha[i];
+            z[i] = G.z[i];
+        }
+        alpha[k] = 0.0;
+        for (int i = 0; i <= k; ++i) beta[i] = G.beta[i];
+        *J = G.J;
+    });
+}
+
+kry_status kry_loglik_batch(kry_problem* prob, const kry_matern* thetas, int32_t count, const kry_opts* opts,
+                            kry_loglik_result* out) {
+    bool noconv = false;
+    kry_status s = guard([&] {
+        KRY_REQUIRE(prob && thetas && out, "NULL argument");
+        KRY_REQUIRE(count >= 1, "count must be >= 1");
+        for (int t = 0; t < count; ++t) check_theta(&thetas[t]);
+        check_opts(opts);
+        Problem& P = prob->P;
+        bind(*P.ctx);
+        hipStream_t st = P.ctx->stream;
+        // points go through in chunks that bound the Krylov workspace
+        const int np = nprobes_of(opts);
+        const size_t per_point = (size_t)np * P.p * (opts->precision == KRY_FP32 ? 4 : 8) *
+                                 (opts->reorth ? opts->lanczos_steps + 3 : 5);
+        int chunk = (int)std::max<size_t>(1, (size_t)16e9 / std::max<size_t>(per_point, 1));
+        chunk = std::min(chunk, (int)count);
+        std::vector<kry_loglik_result> res(count);
+        for (int t0 = 0; t0 < count; t0 += chunk) {
+            const int c = std::min(chunk, (int)count - t0);
+            loglik_points(P, thetas + t0, c, opts, res.data() + t0, st);
+        }
+        std::copy(res.begin(), res.end(), out);
+        noconv = any_not_converged(out, count, opts);
+    });
+    if (s == KRY_OK && noconv) {
+        g_last_error = "CG reached cg_maxit before cg_rtol";
+        return KRY_ENOCONV;
+    }
+    return s;
+}
+
+kry_status kry_loglik(kry_problem* prob, const kry_matern* theta, const kry_opts* opts, kry_loglik_result* out) {
+    return kry_loglik_batch(prob, theta, 1, opts, out);
+}
+
+// ---- sampling -----------------------------------------------------------------------------
+static void sample_fields(Problem& P, const Matern& th, int N1, int N2, uint64_t seed, int first_stream, int count,
+                          double* d_out, double* lo, double* hi, hipStream_t st) {
+    const int64_t nspec = (int64_t)(N2 / 2 + 1) * N1;
+    DevBuf sp;
+    sp.ensure(*P.ctx, nspec * sizeof(double));
+    struct Free {
+        Ctx& c;
+        DevBuf& b;
+        ~Free() { b.release(c); }
+    } fr{*P.ctx, sp};
+    spectrum_device(P, N1, N2, th, sp.as<double>(), lo, hi, st);
+    if (*lo < -1e-10 * *hi)
+        throw Error(KRY_ENOTPSD, "embedding spectrum min/max = " + std::to_string(*lo / *hi) + " on a " +
+                                     std::to_string(N1) + "x" + std::to_string(N2) + " torus");
+    spectrum_scale(sp.as<double>(), nspec, 1.0 / ((double)N1 * N2), true, sp.as<double>(), nullptr, st);
+    ConvSpec s;
+    s.N1 = N1;
+    s.N2 = N2;
+    s.nvec = count;
+    s.in_mode = IN_NOISE;
+    s.in_rstride = N2;
+    s.rows_in = N1;
+    s.row_len = N2;
+    s.seed = seed;
+    s.stream0 = first_stream;
+    s.out_mode = OUT_GRID;
+    s.out = d_out;
+    s.out_vstride = (int64_t)P.n1 * P.n2;
+    s.rows_out = P.n1;
+    s.cols_out = P.n2;
+    s.scale = std::sqrt(th.sigma2);
+    s.lam = sp.ptr;
+    s.lam_tstride = 0;
+    s.vecs_per_theta = count;
+    conv_apply<double>(P, s, st);
+    KRY_HIP(hipStreamSynchronize(st));
+}
+
+static void psd_torus(Problem& P, const Matern& th, int* N1, int* N2, hipStream_t st) {
+    int a = P.N1, b = P.N2;
+    const int64_t cap = 8192;
+    DevBuf sp;
+    struct Free {
+        Ctx& c;
+        DevBuf& b;
+        ~Free() { b.release(c); }
+    } fr{*P.ctx, sp};
+    while (true) {
+        sp.ensure(*P.ctx, (size_t)(b / 2 + 1) * a * sizeof(double));
+        double lo, hi;
+        spectrum_device(P, a, b, th, sp.as<double>(), &lo, &hi, st);
+        if (lo >= -1e-10 * hi) {
+            *N1 = a;
+            *N2 = b;
+            return;
+        }
+        if (2 * a > cap || 2 * b > cap)
+            throw Error(KRY_ENOTPSD, "no PSD embedding up to 8192 per axis (min/max = " + std::to_string(lo / hi) + ")");
+        a *= 2;
+        b *= 2;
+    }
+}
+
+kry_status kry_psd_torus(kry_problem* prob, const kry_matern* theta, int32_t* N1, int32_t* N2) {
+    return guard([&] {
+        KRY_REQUIRE(prob && N1 && N2, "NULL argument");
+        check_theta(theta);
+        Problem& P = prob->P;
+        bind(*P.ctx);
+        int a, b;
+        psd_torus(P, to_matern(theta), &a, &b, P.ctx->stream);
+        *N1 = a;
+        *N2 = b;
+    });
+}
+
+kry_status kry_sample(kry_problem* prob, const kry_matern* theta, int32_t N1, int32_t N2, uint64_t seed,
+                                 int32_t first_stream, int32_t count, double* out, double* minmax) {
+    return guard([&] {
+        KRY_REQUIRE(prob && out, "NULL argument");
+        check_theta(theta);
+        KRY_REQUIRE(count >= 1 && first_stream >= 0, "bad count or stream");
+        Problem& P = prob->P;
+        torus_args(P, N1, N2);
+        KRY_REQUIRE(N1 >= 2 * P.n1 - 1 && N2 >= 2 * P.n2 - 1, "torus smaller than the embedding of the grid");
+        bind(*P.ctx);
+        hipStream_t st = P.ctx->stream;
+        const size_t n = (size_t)P.n1 * P.n2 * count;
+        DevBuf o;
+        o.ensure(*P.ctx, n * sizeof(double));
+        struct Free {
+            Ctx& c;
+            DevBuf& b;
+            ~Free() { b.release(c); }
+        } fr{*P.ctx, o};
+        double lo, hi;
+        sample_fields(P, to_matern(theta), N1, N2, seed, first_stream, count, o.as<double>(), &lo, &hi, st);
+        KRY_HIP(hipMemcpy(out, o.ptr, n * sizeof(double), hipMemcpyDeviceToHost));
+        if (minmax) {
+            minmax[0] = lo;
+            minmax[1] = hi;
+        }
+    });
+}
+
+// ---- kriging --------------------------------------------------------------------------------
+kry_status kry_krige(kry_problem* prob, const kry_matern* theta, const kry_opts* opts,
+                                const int64_t* targets, int64_t ntargets, double* mean_x, double* var_x, double* var_y,
+                                int32_t bootstrap_B) {
+    bool noconv = false;
+    kry_status s = guard([&] {
+        KRY_REQUIRE(prob && mean_x, "NULL argument");
+        check_theta(theta);
+        check_opts(opts);
+        KRY_REQUIRE(bootstrap_B >= 0 && bootstrap_B <= 4096, "bootstrap_B must be in [0, 4096]");
+        Problem& P = prob->P;
+        const int64_t n = (int64_t)P.n1 * P.n2;
+        std::vector<int64_t> tg;
+        if (targets) {
+            KRY_REQUIRE(ntargets >= 1, "ntargets must be >= 1");
+            tg.assign(targets, targets + ntargets);
+            for (int64_t t : tg) KRY_REQUIRE(t >= 0 && t < n, "target cell id out of range");
+        } else {
+            for (int64_t c = 0; c < n; ++c)
+                if (!P.h_mask[c]) tg.push_back(c);
+            KRY_REQUIRE(ntargets == (int64_t)tg.size(), "ntargets must equal the number of unobserved cells");
+        }
+        const int64_t nt = (int64_t)tg.size();
+        if (nt == 0) return;
+        bind(*P.ctx);
+        hipStream_t st = P.ctx->stream;
+        const Matern th = to_matern(theta);
+        const double eta = th.tau2 / th.sigma2;
+        const double tau = std::sqrt(th.tau2);
+        Spectrum& S = problem_spectrum(P, th, st);
+        // device scratch: eta, targets, w, full mean, target values
+        const int64_t p = P.p;
+        DevBuf io;
+        io.ensure(*P.ctx, 512 + nt * sizeof(int64_t) + (size_t)p * 2 * sizeof(double) + (size_t)n * sizeof(double) +
+                              (size_t)nt * 3 * sizeof(double) + 4096);
+        struct Free {
+            Ctx& c;
+            DevBuf& b;
+            ~Free() { b.release(c); }
+        } fr{*P.ctx, io};
+        Arena a;
+        a.base = io.as<char>();
+        double* d_eta = a.take<double>(1);
+        int64_t* d_tg = a.take<int64_t>(nt);
+        double* d_w = a.take<double>(p);
+        double* d_full = a.take<double>(n);
+        double* d_t1 = a.take<double>(nt);
+        double* d_t2 = a.take<double>(nt);
+        KRY_HIP(hipMemcpyAsync(d_eta, &eta, sizeof(double), hipMemcpyHostToDevice, st));
+        KRY_HIP(hipMemcpyAsync(d_tg, tg.data(), nt * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        // mean: w = K^{-1} y, xhat = Sigma A^T w
+        SolveStats ss;
+        solve_device(P, opts->precision, S.s64.ptr, S.s32.ptr, 0, 1, d_eta, 1, P.y64.as<double>(), d_w, opts->cg_rtol,
+                     opts->cg_maxit, ss, st);
+        if (ss.relres[0] > opts->cg_rtol) noconv = true;
+        cov_full<double>(P, S.s64.ptr, d_w, d_full, 1, st);
+        hipLaunchKernelGGL(k_pick, grid1(nt), dim3(256), 0, st, d_full, d_tg, nt, d_t1);
+        KRY_HIP(hipGetLastError());
+        KRY_HIP(hipMemcpyAsync(mean_x, d_t1, nt * sizeof(double), hipMemcpyDeviceToHost, st));
+        KRY_HIP(hipStreamSynchronize(st));
+        if (!var_x && !var_y) return;
+        if (bootstrap_B == 0) {
+            // exact: multi-RHS CG on the cross-correlation columns, in chunks
+            P.lagtmp.ensure(*P.ctx, (size_t)P.N1 * P.N2 * sizeof(double));
+            lag_grid_device(*P.ctx, P.N1, P.N2, P.dx1, P.dx2, th, P.lagtmp.as<double>(), st);
+            const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(256, (int64_t)(2e9 / (8.0 * p * 6))));
+            DevBuf cb;
+            cb.ensure(*P.ctx, (size_t)chunk * p * 2 * sizeof(double) + (size_t)chunk * 257 * sizeof(double) + 1024);
+            struct Free2 {
+                Ctx& c;
+                DevBuf& b;
+                ~Free2() { b.release(c); }
+            } fr2{*P.ctx, cb};
+            double* Cc = cb.as<double>();
+            double* Wc = Cc + (size_t)chunk * p;
+            double* part = Wc + (size_t)chunk * p;
+            double* dots = part + (size_t)chunk * 256;
+            std::vector<double> q(chunk);
+            for (int64_t t0 = 0; t0 < nt; t0 += chunk) {
+                const int c = (int)std::min<int64_t>(chunk, nt - t0);
+                hipLaunchKernelGGL(k_cross_corr, grid1(p, c), dim3(256), 0, st, P.lagtmp.as<double>(), P.N1, P.N2,
+                                   P.cell.as<int32_t>(), p, P.n2, d_tg + t0, Cc);
+                KRY_HIP(hipGetLastError());
+                SolveStats s2;
+                solve_device(P, opts->precision, S.s64.ptr, S.s32.ptr, 0, c, d_eta, c, Cc, Wc, opts->cg_rtol,
+                             opts->cg_maxit, s2, st);
+                for (int v = 0; v < c; ++v)
+                    if (s2.relres[v] > opts->cg_rtol) noconv = true;
+                dot_batched<double>(Cc, p, Wc, p, p, c, part, dots, st);
+                KRY_HIP(hipMemcpyAsync(q.data(), dots, c * sizeof(double), hipMemcpyDeviceToHost, st));
+                KRY_HIP(hipStreamSynchronize(st));
+                for (int v = 0; v < c; ++v) {
+                    const double vx = th.sigma2 * (1.0 - q[v]);
+                    if (var_x) var_x[t0 + v] = vx;
+                    if (var_y) var_y[t0 + v] = vx + th.tau2;
+                }
+            }
+            return;
+        }
+        // parametric bootstrap (eq. bootstrap_uq)
+        int N1s, N2s;
+        psd_torus(P, th, &N1s, &N2s, st);
+        const int B = bootstrap_B;
+        DevBuf bb;
+        bb.ensure(*P.ctx, (size_t)B * n * 2 * sizeof(double) + (size_t)B * p * 2 * sizeof(double) + 1024);
+        struct Free3 {
+            Ctx& c;
+            DevBuf& b;
+            ~Free3() { b.release(c); }
+        } fr3{*P.ctx, bb};
+        double* F = bb.as<double>();
+        double* XH = F + (size_t)B * n;
+        double* YB = XH + (size_t)B * n;
+        double* WB = YB + (size_t)B * p;
+        double lo, hi;
+        sample_fields(P, th, N1s, N2s, opts->seed, 0, B, F, &lo, &hi, st);
+        hipLaunchKernelGGL(k_boot_obs, grid1(p, B), dim3(256), 0, st, F, n, P.cell.as<int32_t>(), p, tau, opts->seed, YB);
+        KRY_HIP(hipGetLastError());
+        SolveStats s3;
+        solve_device(P, opts->precision, S.s64.ptr, S.s32.ptr, 0, B, d_eta, B, YB, WB, opts->cg_rtol, opts->cg_maxit, s3,
+                     st);
+        for (int v = 0; v < B; ++v)
+            if (s3.relres[v] > opts->cg_rtol) noconv = true;
+        cov_full<double>(P, S.s64.ptr, WB, XH, B, st);
+        hipLaunchKernelGGL(k_boot_acc, grid1(nt), dim3(256), 0, st, F, XH, n, B, d_tg, nt, tau, opts->seed, d_t1, d_t2);
+        KRY_HIP(hipGetLastError());
+        if (var_x) KRY_HIP(hipMemcpyAsync(var_x, d_t1, nt * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (var_y) KRY_HIP(hipMemcpyAsync(var_y, d_t2, nt * sizeof(double), hipMemcpyDeviceToHost, st));
+        KRY_HIP(hipStreamSynchronize(st));
+    });
+    if (s == KRY_OK && noconv) {
+        g_last_error = "CG reached cg_maxit before cg_rtol";
+        return KRY_ENOCONV;
+    }
+    return s;
+}
+
+// ---- fit ----------------------------------------------------------------------------------------
+kry_status kry_fit(kry_problem* prob, const kry_matern* init, uint32_t free_mask, const kry_opts* opts,
+                              double xtol, int32_t maxiter, kry_matern* est, kry_loglik_result* at_est) {
+    return guard([&] {
+        KRY_REQUIRE(prob && init && est, "NULL argument");
+        check_theta(init);
+        check_opts(opts);
+        KRY_REQUIRE((free_mask & 3u) != 0, "free_mask must free the range and/or the nugget ratio");
+        KRY_REQUIRE(xtol > 0 && maxiter >= 1, "bad xtol or maxiter");
+        KRY_REQUIRE(init->tau2 > 0, "the nugget ratio needs tau2 > 0 to be fitted on the log scale");
+        Problem& P = prob->P;
+        bind(*P.ctx);
+        hipStream_t st = P.ctx->stream;
+        // free coordinates: log range, log eta
+        std::vector<int> which;
+        if (free_mask & 1u) which.push_back(0);
+        if (free_mask & 2u) which.push_back(1);
+        const int d = (int)which.size();
+        const double x0[2] = {std::log(init->range), std::log(init->tau2 / init->sigma2)};
+        auto point = [&](const std::vector<double>& x) {
+            double lr = x0[0], le = x0[1];
+            for (int i = 0; i < d; ++i) (which[i] == 0 ? lr : le) = x[i];
+            kry_matern t = *init;
+            t.range = std::exp(lr);
+            t.sigma2 = 1.0;
+            t.tau2 = std::exp(le);
+            return t;
+        };
+        auto f = [&](const std::vector<double>& x) {
+            kry_matern t = point(x);
+            kry_loglik_result r;
+            loglik_points(P, &t, 1, opts, &r, st);
+            return -r.loglik_profiled;
+        };
+        // Nelder-Mead (reflection 1, expansion 2, contraction 1/2, shrink 1/2)
+        std::vector<std::vector<double>> sx(d + 1, std::vector<double>(d));
+        for (int i = 0; i < d; ++i) sx[0][i] = x0[which[i]];
+        for (int k = 1; k <= d; ++k) {
+            sx[k] = sx[0];
+            sx[k][k - 1] += 0.3;
+        }
+        std::vector<double> fx(d + 1);
+        for (int k = 0; k <= d; ++k) fx[k] = f(sx[k]);
+        for (int it = 0; it < maxiter; ++it) {
+            std::vector<int> ord(d + 1);
+            std::iota(ord.begin(), ord.end(), 0);
+            std::sort(ord.begin(), ord.end(), [&](int a, int b) { return fx[a] < fx[b]; });
+            std::vector<std::vector<double>> s2(d + 1);
+            std::vector<double> f2(d + 1);
+            for (int k = 0; k <= d; ++k) {
+                s2[k] = sx[ord[k]];
+                f2[k] = fx[ord[k]];
+            }
+            sx = s2;
+            fx = f2;
+            double size = 0;
+            for (int k = 1; k <= d; ++k)
+                for (int i = 0; i < d; ++i) size = std::max(size, std::fabs(sx[k][i] - sx[0][i]));
+            if (size < xtol) break;
+            std::vector<double> c(d, 0.0);
+            for (int k = 0; k < d; ++k)
+                for (int i = 0; i < d; ++i) c[i] += sx[k][i] / d;
+            auto lerp = [&](double t) {
+                std::vector<double> r(d);
+                for (int i = 0; i < d; ++i) r[i] = c[i] + t * (sx[d][i] - c[i]);
+                return r;
+            };
+            std::vector<double> xr = lerp(-1.0);
+            const double fr = f(xr);
+            if (fr < fx[0]) {
+                std::vector<double> xe = lerp(-2.0);
+                const double fe = f(xe);
+                if (fe < fr) {
+                    sx[d] = xe;
+                    fx[d] = fe;
+                } else {
+                    sx[d] = xr;
+                    fx[d] = fr;
+                }
+            } else if (fr < fx[d - 1]) {
+                sx[d] = xr;
+                fx[d] = fr;
+            } else {
+                const bool outside = fr < fx[d];
+                std::vector<double> xc = lerp(outside ? -0.5 : 0.5);
+                const double fc = f(xc);
+                if (fc < (outside ? fr : fx[d])) {
+                    sx[d] = xc;
+                    fx[d] = fc;
+                } else {
+                    for (int k = 1; k <= d; ++k) {
+                        for (int i = 0; i < d; ++i) sx[k][i] = sx[0][i] + 0.5 * (sx[k][i] - sx[0][i]);
+                        fx[k] = f(sx[k]);
+                    }
+                }
+            }
+        }
+        int best = 0;
+        for (int k = 1; k <= d; ++k)
+            if (fx[k] < fx[best]) best = k;
+        kry_matern t = point(sx[best]);
+        kry_loglik_result r;
+        loglik_points(P, &t, 1, opts, &r, st);
+        t.sigma2 = r.sigma2_hat;
+        t.tau2 = std::exp(std::log(point(sx[best]).tau2)) * r.sigma2_hat;
+        *est = t;
+        if (at_est) {
+            kry_matern t2 = t;
+            loglik_points(P, &t2, 1, opts, at_est, st);
+        }
+    });
+}
+

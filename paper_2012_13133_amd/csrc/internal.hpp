@@ -1,0 +1,155 @@
+// Host-side structures shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/kryging.h"
+#include "common.hpp"
+
+namespace kry {
+
+// Error carried from the drivers to the ABI boundary, where it becomes a
+// kry_status and a thread-local message.
+struct Error : std::runtime_error {
+    kry_status status;
+    Error(kry_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define KRY_HIP(call)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            throw ::kry::Error(KRY_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define KRY_REQUIRE(cond, msg)                                        \
+    do {                                                              \
+        if (!(cond)) throw ::kry::Error(KRY_EINVAL, std::string(msg)); \
+    } while (0)
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint64_t budget = 0;     // 0 = unlimited
+    uint64_t allocated = 0;  // bytes currently held through dev_alloc
+    cpx<double>* tw64 = nullptr;
+    cpx<float>* tw32 = nullptr;
+};
+
+void* dev_alloc(Ctx& c, size_t bytes);
+void dev_free(Ctx& c, void* p, size_t bytes);
+
+// A device buffer that only grows; freed with its owner.
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    void ensure(Ctx& c, size_t need) {
+        if (need <= bytes) return;
+        if (ptr) dev_free(c, ptr, bytes);
+        ptr = nullptr;
+        bytes = 0;
+        ptr = dev_alloc(c, need);
+        bytes = need;
+    }
+    void release(Ctx& c) {
+        if (ptr) dev_free(c, ptr, bytes);
+        ptr = nullptr;
+        bytes = 0;
+    }
+    template <typename T>
+    T* as() const { return reinterpret_cast<T*>(ptr); }
+};
+
+struct Matern {
+    double sigma2, tau2, range, nu, ratio, angle;
+};
+
+// Spectrum of one parameter point on the problem's embedding, scaled by
+// 1 / (N1 N2) for the product, in both precisions; layout [k2][k1].
+struct Spectrum {
+    Matern theta{};
+    bool valid = false;
+    double lam_min = 0, lam_max = 0;
+    DevBuf s64, s32;
+};
+
+struct Problem {
+    Ctx* ctx = nullptr;
+    int n1 = 0, n2 = 0;
+    double dx1 = 0, dx2 = 0;
+    int N1 = 0, N2 = 0;          // embedding of the masked product
+    int64_t p = 0;
+    int words_per_row = 0;
+    DevBuf bits, base;           // packed mask
+    DevBuf cell;                 // compact index -> cell id (int32)
+    DevBuf y64, y32;             // compact data
+    std::vector<int64_t> h_cell; // compact index -> cell id (host)
+    std::vector<uint8_t> h_mask;
+    Spectrum spec;               // cache of the last parameter point
+    DevBuf Y;                    // transform workspace
+    DevBuf lagtmp, spectmp, spec_multi64, spec_multi32;
+    DevBuf kws;                  // Krylov workspace
+    DevBuf scal;                 // device scalars
+    MaskView mask_view() const {
+        return MaskView{bits.as<uint32_t>(), base.as<uint32_t>(), words_per_row};
+    }
+};
+
+// ---- transforms (conv.hip) -------------------------------------------------
+enum InMode { IN_COMPACT = 0, IN_DENSE = 1, IN_NOISE = 2 };
+enum OutMode { OUT_COMPACT = 0, OUT_GRID = 1 };
+
+// One batched circulant-embedding product on an N1 x N2 torus:
+//   rows_in x row_len input block (rows from the top-left corner) ->
+//   FFT2 -> multiply by lam (per parameter point) -> inverse FFT2 ->
+//   rows_out x cols_out output block.
+struct ConvSpec {
+    int N1 = 0, N2 = 0;
+    int nvec = 0;
+    int in_mode = IN_COMPACT;
+    const void* in = nullptr;   // compact (element type R) or dense rows (double)
+    int64_t in_vstride = 0;
+    int in_rstride = 0;         // dense / noise: row stride of the input
+    int rows_in = 0, row_len = 0;
+    uint64_t seed = 0;
+    int stream0 = 0;
+    int out_mode = OUT_COMPACT;
+    void* out = nullptr;        // element type R
+    int64_t out_vstride = 0;
+    int rows_out = 0, cols_out = 0;
+    const void* vin = nullptr;  // nugget term source (compact, element type R)
+    int64_t vin_vstride = 0;
+    const double* eta = nullptr;  // per parameter point (device)
+    double scale = 1.0;
+    const void* lam = nullptr;  // [theta][k2][k1], element type R, scaled
+    int64_t lam_tstride = 0;
+    int vecs_per_theta = 1;
+};
+
+template <typename R>
+void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st);
+
+// Lag grid (N1 x N2 doubles) of the embedding on device.
+void lag_grid_device(Ctx& c, int N1, int N2, double dx1, double dx2, const Matern& th, double* d_c,
+                     hipStream_t st);
+// Unscaled FP64 half spectrum [k2][k1] of the torus; returns min and max.
+void spectrum_device(Problem& P, int N1, int N2, const Matern& th, double* d_lam, double* lam_min,
+                     double* lam_max, hipStream_t st);
+// Scale a half spectrum by s into FP64 and FP32 copies; optional sqrt of
+// max(lam, 0) first (sampling).
+void spectrum_scale(const double* lam, int64_t n, double s, bool sqrt_clip, double* out64,
+                    float* out32, hipStream_t st);
+// Cached, scaled spectrum of theta on the problem's embedding.
+Spectrum& problem_spectrum(Problem& P, const Matern& th, hipStream_t st);
+
+// ---- Krylov building blocks (krylov.hip) --------------------------------------
+int dot_blocks(int64_t n);
+template <typename R>
+void dot_batched(const R* a, int64_t sa, const R* b, int64_t sb, int64_t n, int nvec, double* partial,
+                 double* out, hipStream_t st);
+
+}  // namespace kry

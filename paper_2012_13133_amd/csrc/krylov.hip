@@ -1,0 +1,515 @@
+// Batched Krylov building blocks: deterministic dot products, the Lanczos
+// recurrence, Gauss quadrature of the Lanczos tridiagonals and conjugate
+// gradients, all with scalars kept on the device so the host loop never waits
+// on the GPU inside an iteration.
+//
+// Reductions are fixed-order trees: block b of vector v always sums the same
+// elements in the same order, and the per-block partials are summed by one
+// block in a fixed order.  The result for a vector therefore does not depend
+// on which other vectors share the launch.  Accumulation is FP64 for both
+// element types.
+#include <cmath>
+
+#include "internal.hpp"
+#include "krylov.hpp"
+
+namespace kry {
+
+constexpr int RB = 256;  // threads per reduction block
+
+int dot_blocks(int64_t n) {
+    int64_t b = (n + 8 * RB - 1) / (8 * RB);
+    if (b < 1) b = 1;
+    if (b > 256) b = 256;
+    return (int)b;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = RB / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// partial[v * nblk + b] = sum over block b's elements of a_v . b_v
+template <typename R>
+__global__ void __launch_bounds__(RB) k_dot_partial(const R* __restrict__ a, int64_t sa, const R* __restrict__ b,
+                                                    int64_t sb, int64_t n, double* __restrict__ partial) {
+    __shared__ double sh[RB];
+    const int nblk = gridDim.x, vec = blockIdx.y;
+    const R* av = a + vec * sa;
+    const R* bv = b + vec * sb;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)nblk * RB)
+        acc += (double)av[i] * (double)bv[i];
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[vec * nblk + blockIdx.x] = acc;
+}
+
+// out[v * ostride] = sum_b partial[v * nblk + b]
+__global__ void __launch_bounds__(RB) k_reduce(const double* __restrict__ partial, int nblk,
+                                               double* __restrict__ out, int64_t ostride) {
+    __shared__ double sh[RB];
+    const int vec = blockIdx.x;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += RB) acc += partial[vec * nblk + i];
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[vec * ostride] = acc;
+}
+
+template <typename R>
+void dot_batched(const R* a, int64_t sa, const R* b, int64_t sb, int64_t n, int nvec, double* partial,
+                 double* out, hipStream_t st) {
+    const int nblk = dot_blocks(n);
+    hipLaunchKernelGGL(k_dot_partial<R>, dim3(nblk, nvec), dim3(RB), 0, st, a, sa, b, sb, n, partial);
+    KRY_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce, dim3(nvec), dim3(RB), 0, st, partial, nblk, out, (int64_t)1);
+    KRY_HIP(hipGetLastError());
+}
+template void dot_batched<double>(const double*, int64_t, const double*, int64_t, int64_t, int, double*, double*,
+                                  hipStream_t);
+template void dot_batched<float>(const float*, int64_t, const float*, int64_t, int64_t, int, double*, double*,
+                                 hipStream_t);
+
+// ---- element-wise helpers -----------------------------------------------------
+template <typename R>
+__global__ void k_scale_vec(const R* __restrict__ x, const double* __restrict__ s, R* __restrict__ y, int64_t n) {
+    const int vec = blockIdx.y;
+    const R f = (R)s[vec];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[vec * n + i] = x[vec * n + i] * f;
+}
+
+template <typename A, typename B>
+__global__ void k_convert(const A* __restrict__ x, B* __restrict__ y, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (B)x[i];
+}
+
+static dim3 vec_grid(int64_t n, int nvec) {
+    int64_t b = (n + 255) / 256;
+    if (b > 1024) b = 1024;
+    return dim3((unsigned)b, nvec);
+}
+
+template <typename A, typename B>
+void convert(const A* x, B* y, int64_t n, hipStream_t st) {
+    int64_t b = (n + 255) / 256;
+    if (b > 16384) b = 16384;
+    hipLaunchKernelGGL((k_convert<A, B>), dim3((unsigned)b), dim3(256), 0, st, x, y, n);
+    KRY_HIP(hipGetLastError());
+}
+template void convert<double, float>(const double*, float*, int64_t, hipStream_t);
+template void convert<float, double>(const float*, double*, int64_t, hipStream_t);
+template void convert<double, double>(const double*, double*, int64_t, hipStream_t);
+
+// ---- probes -----------------------------------------------------------------
+// Rademacher sign of (compact index, probe); coloured probes keep the sign
+// only on cells of colour k = (row mod c) + c (col mod c).
+template <typename R>
+__global__ void k_probes(const int32_t* __restrict__ cell, int64_t p, int n2, int nprobe, uint64_t seed,
+                         int period, R* __restrict__ out) {
+    const int k = blockIdx.y;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < p; i += (int64_t)gridDim.x * blockDim.x) {
+        double v = rademacher((uint32_t)i, (uint32_t)k, seed);
+        if (period > 0) {
+            const int c = cell[i];
+            const int row = c / n2, col = c - (c / n2) * n2;
+            const int colour = (row % period) + period * (col % period);
+            if (colour != k) v = 0.0;
+        }
+        out[k * p + i] = (R)v;
+    }
+}
+
+template <typename R>
+void make_probes(const Problem& P, int nprobe, uint64_t seed, int period, R* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_probes<R>, vec_grid(P.p, nprobe), dim3(256), 0, st, P.cell.as<int32_t>(), P.p, P.n2, nprobe,
+                       seed, period, out);
+    KRY_HIP(hipGetLastError());
+}
+template void make_probes<double>(const Problem&, int, uint64_t, int, double*, hipStream_t);
+template void make_probes<float>(const Problem&, int, uint64_t, int, float*, hipStream_t);
+
+// ---- Lanczos ----------------------------------------------------------------------
+// start: znorm2 known -> scale = 1/||z|| (0 for an all-zero probe)
+__global__ void k_lanczos_init(const double* __restrict__ znorm2, double* __restrict__ scale,
+                               int* __restrict__ active, int* __restrict__ steps, int nvec) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nvec) return;
+    const double z2 = znorm2[v];
+    active[v] = z2 > 0.0;
+    steps[v] = 0;
+    scale[v] = z2 > 0.0 ? 1.0 / sqrt(z2) : 0.0;
+}
+
+// r = w - alpha_j q_j - beta_{j-1} q_{j-1} (in place in w); partial ||r||^2 if requested
+template <typename R>
+__global__ void __launch_bounds__(RB) k_lanczos_update(R* __restrict__ w, const R* __restrict__ q,
+                                                       const R* __restrict__ qprev, const double* __restrict__ alpha,
+                                                       const double* __restrict__ beta_prev, int64_t n,
+                                                       double* __restrict__ partial) {
+    __shared__ double sh[RB];
+    const int nblk = gridDim.x, vec = blockIdx.y;
+    const R a = (R)alpha[vec];
+    const R b = beta_prev ? (R)beta_prev[vec] : (R)0;
+    R* wv = w + vec * n;
+    const R* qv = q + vec * n;
+    const R* pv = qprev ? qprev + vec * n : nullptr;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)nblk * RB) {
+        R r = wv[i] - a * qv[i];
+        if (pv) r -= b * pv[i];
+        wv[i] = r;
+        acc += (double)r * (double)r;
+    }
+    if (partial) {
+        acc = block_sum(acc, sh);
+        if (threadIdx.x == 0) partial[vec * nblk + blockIdx.x] = acc;
+    }
+}
+
+// beta_j = ||r||, breakdown test against the oracle's rule
+// (beta <= tol * max(|alpha_j|, beta_{j-1})), step counts and 1/beta.
+__global__ void __launch_bounds__(RB) k_lanczos_beta(const double* __restrict__ partial, int nblk, int j,
+                                                     const double* __restrict__ alpha_j,
+                                                     const double* __restrict__ beta_prev, double* __restrict__ beta_j,
+                                                     double* __restrict__ scale, int* __restrict__ active,
+                                                     int* __restrict__ steps, double tol) {
+    __shared__ double sh[RB];
+    const int vec = blockIdx.x;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += RB) acc += partial[vec * nblk + i];
+    acc = block_sum(acc, sh);
+    if (threadIdx.x != 0) return;
+    const double b = sqrt(acc);
+    if (!active[vec]) {
+        beta_j[vec] = 0.0;
+        scale[vec] = 0.0;
+        return;
+    }
+    steps[vec] = j + 1;
+    const double bp = beta_prev ? beta_prev[vec] : 0.0;
+    const double ref = fmax(fmax(fabs(alpha_j[vec]), bp), 1e-300);
+    if (b <= tol * ref) {
+        active[vec] = 0;
+        beta_j[vec] = 0.0;
+        scale[vec] = 0.0;
+    } else {
+        beta_j[vec] = b;
+        scale[vec] = 1.0 / b;
+    }
+}
+
+// Classical Gram-Schmidt against stored basis vectors: h[v][i] = q_i . r
+template <typename R>
+__global__ void __launch_bounds__(RB) k_multidot_partial(const R* __restrict__ Q, int64_t qslot, const R* __restrict__ r,
+                                                         int nq, int64_t n, double* __restrict__ partial) {
+    __shared__ double sh[RB];
+    const int nblk = gridDim.x, vec = blockIdx.y;
+    const R* rv = r + vec * n;
+    for (int q = 0; q < nq; ++q) {
+        const R* qv = Q + q * qslot + vec * n;
+        double acc = 0.0;
+        for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)nblk * RB)
+            acc += (double)qv[i] * (double)rv[i];
+        acc = block_sum(acc, sh);
+        if (threadIdx.x == 0) partial[((int64_t)vec * nq + q) * nblk + blockIdx.x] = acc;
+    }
+}
+
+// r -= sum_i h_i q_i
+template <typename R>
+__global__ void k_multi_axpy(const R* __restrict__ Q, int64_t qslot, const double* __restrict__ h, int nq,
+                             R* __restrict__ r, int64_t n) {
+    const int vec = blockIdx.y;
+    const double* hv = h + (int64_t)vec * nq;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double acc = (double)r[vec * n + i];
+        for (int q = 0; q < nq; ++q) acc -= hv[q] * (double)Q[q * qslot + vec * n + i];
+        r[vec * n + i] = (R)acc;
+    }
+}
+
+template <typename R>
+void lanczos_run(const MatvecFn<R>& A, int64_t n, int nvec, int m, bool reorth, const R* Z, LanczosBuffers<R>& B,
+                 hipStream_t st) {
+    const int nblk = dot_blocks(n);
+    const double tol = sizeof(R) == 8 ? 1e-12 : 1e-6;
+    const int64_t slot = (int64_t)nvec * n;
+    const int nslots = reorth ? m + 1 : 3;
+    auto Qs = [&](int j) { return B.Q + (int64_t)(reorth ? j : j % 3) * slot; };
+
+    dot_batched<R>(Z, n, Z, n, n, nvec, B.partial, B.znorm2, st);
+    hipLaunchKernelGGL(k_lanczos_init, dim3((nvec + 63) / 64), dim3(64), 0, st, B.znorm2, B.scale, B.active, B.steps,
+                       nvec);
+    KRY_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_scale_vec<R>, vec_grid(n, nvec), dim3(256), 0, st, Z, B.scale, Qs(0), n);
+    KRY_HIP(hipGetLastError());
+    (void)nslots;
+    for (int j = 0; j < m; ++j) {
+        R* q = Qs(j);
+        const R* qp = j > 0 ? Qs(j - 1) : nullptr;
+        double* aj = B.alpha + (int64_t)j * nvec;
+        double* bj = B.beta + (int64_t)j * nvec;
+        const double* bprev = j > 0 ? B.beta + (int64_t)(j - 1) * nvec : nullptr;
+        A(q, B.W, nvec, st);
+        dot_batched<R>(q, n, B.W, n, n, nvec, B.partial, aj, st);
+        if (!reorth) {
+            hipLaunchKernelGGL(k_lanczos_update<R>, dim3(nblk, nvec), dim3(RB), 0, st, B.W, q, qp, aj, bprev, n,
+                               B.partial);
+            KRY_HIP(hipGetLastError());
+        } else {
+            hipLaunchKernelGGL(k_lanczos_update<R>, dim3(nblk, nvec), dim3(RB), 0, st, B.W, q, qp, aj, bprev, n,
+                               (double*)nullptr);
+            KRY_HIP(hipGetLastError());
+            for (int pass = 0; pass < 2; ++pass) {
+                hipLaunchKernelGGL(k_multidot_partial<R>, dim3(nblk, nvec), dim3(RB), 0, st, B.Q, slot, B.W, j + 1, n,
+                                   B.partial);
+                KRY_HIP(hipGetLastError());
+                hipLaunchKernelGGL(k_reduce, dim3(nvec * (j + 1)), dim3(RB), 0, st, B.partial, nblk, B.h, (int64_t)1);
+                KRY_HIP(hipGetLastError());
+                hipLaunchKernelGGL(k_multi_axpy<R>, vec_grid(n, nvec), dim3(256), 0, st, B.Q, slot, B.h, j + 1, B.W, n);
+                KRY_HIP(hipGetLastError());
+            }
+            hipLaunchKernelGGL(k_dot_partial<R>, dim3(nblk, nvec), dim3(RB), 0, st, B.W, n, B.W, n, n, B.partial);
+            KRY_HIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_lanczos_beta, dim3(nvec), dim3(RB), 0, st, B.partial, nblk, j, aj, bprev, bj, B.scale,
+                           B.active, B.steps, tol);
+        KRY_HIP(hipGetLastError());
+        if (j + 1 < m) {
+            hipLaunchKernelGGL(k_scale_vec<R>, vec_grid(n, nvec), dim3(256), 0, st, B.W, B.scale, Qs(j + 1), n);
+            KRY_HIP(hipGetLastError());
+        }
+    }
+}
+template void lanczos_run<double>(const MatvecFn<double>&, int64_t, int, int, bool, const double*,
+                                  LanczosBuffers<double>&, hipStream_t);
+template void lanczos_run<float>(const MatvecFn<float>&, int64_t, int, int, bool, const float*,
+                                 LanczosBuffers<float>&, hipStream_t);
+
+// ---- Gauss quadrature ---------------------------------------------------------------
+// For each probe: eigen-decomposition of its Lanczos tridiagonal T (steps
+// s <= m) by the implicit QL iteration with Wilkinson shifts (Bowdler,
+// Martin, Reinsch & Wilkinson, 1968), tracking only the first component of
+// every eigenvector (Golub & Welsch, 1969); then
+//   gamma = ||z||^2 sum_i tau_i^2 log theta_i.
+__global__ void k_quadrature(const double* __restrict__ alpha, const double* __restrict__ beta,
+                             const int* __restrict__ steps, const double* __restrict__ znorm2, int nvec,
+                             int64_t coef_stride /* distance between steps j and j+1 */, double* __restrict__ gamma) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nvec) return;
+    const int n = steps[v];
+    if (n <= 0) {
+        gamma[v] = 0.0;
+        return;
+    }
+    double d[KRY_MAX_LANCZOS], e[KRY_MAX_LANCZOS], z[KRY_MAX_LANCZOS];
+    for (int i = 0; i < n; ++i) {
+        d[i] = alpha[i * coef_stride + v];
+        e[i] = (i + 1 < n) ? beta[i * coef_stride + v] : 0.0;
+        z[i] = (i == 0) ? 1.0 : 0.0;
+    }
+    const double eps = 2.220446049250313e-16;
+    for (int l = 0; l < n; ++l) {
+        for (int iter = 0; iter < 100; ++iter) {
+            int mm = l;
+            for (; mm < n - 1; ++mm) {
+                const double dd = fabs(d[mm]) + fabs(d[mm + 1]);
+                if (fabs(e[mm]) <= eps * dd) break;
+            }
+            if (mm == l) break;
+            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            double r = hypot(g, 1.0);
+            g = d[mm] - d[l] + e[l] / (g + copysign(r, g));
+            double s = 1.0, c = 1.0, p = 0.0;
+            bool early = false;
+            for (int i = mm - 1; i >= l; --i) {
+                const double f = s * e[i];
+                const double b = c * e[i];
+                r = hypot(f, g);
+                e[i + 1] = r;
+                if (r == 0.0) {
+                    d[i + 1] -= p;
+                    e[mm] = 0.0;
+                    early = true;
+                    break;
+                }
+                s = f / r;
+                c = g / r;
+                g = d[i + 1] - p;
+                r = (d[i] - g) * s + 2.0 * c * b;
+                p = s * r;
+                d[i + 1] = g + p;
+                g = c * r - b;
+                const double zf = z[i + 1];
+                z[i + 1] = s * z[i] + c * zf;
+                z[i] = c * z[i] - s * zf;
+            }
+            if (early) continue;
+            d[l] -= p;
+            e[l] = g;
+            e[mm] = 0.0;
+        }
+    }
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) acc += z[i] * z[i] * log(d[i]);
+    gamma[v] = znorm2[v] * acc;
+}
+
+void quadrature(const double* alpha, const double* beta, const int* steps, const double* znorm2, int nvec,
+                int64_t coef_stride, double* gamma, hipStream_t st) {
+    hipLaunchKernelGGL(k_quadrature, dim3((nvec + 63) / 64), dim3(64), 0, st, alpha, beta, steps, znorm2, nvec,
+                       coef_stride, gamma);
+    KRY_HIP(hipGetLastError());
+}
+
+// ---- conjugate gradients ---------------------------------------------------------------
+__global__ void k_cg_init(const double* __restrict__ rr, double* __restrict__ bnorm2, double* __restrict__ rr_state,
+                          int* __restrict__ active, int* __restrict__ iters, int nvec) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nvec) return;
+    bnorm2[v] = rr[v];
+    rr_state[v] = rr[v];
+    active[v] = rr[v] > 0.0;
+    iters[v] = 0;
+}
+
+// a = rr / (p . w); x += a p; r -= a w; partial r . r
+template <typename R>
+__global__ void __launch_bounds__(RB) k_cg_xr(R* __restrict__ x, R* __restrict__ r, const R* __restrict__ p,
+                                              const R* __restrict__ w, const double* __restrict__ rr,
+                                              const double* __restrict__ pw, const int* __restrict__ active, int64_t n,
+                                              double* __restrict__ partial) {
+    __shared__ double sh[RB];
+    const int nblk = gridDim.x, vec = blockIdx.y;
+    const bool on = active[vec] != 0;
+    const double a = on ? rr[vec] / pw[vec] : 0.0;
+    const R ar = (R)a;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)nblk * RB) {
+        const int64_t k = vec * n + i;
+        R ri = r[k];
+        if (on) {
+            x[k] += ar * p[k];
+            ri -= ar * w[k];
+            r[k] = ri;
+        }
+        acc += (double)ri * (double)ri;
+    }
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[vec * nblk + blockIdx.x] = acc;
+}
+
+__global__ void __launch_bounds__(RB) k_cg_finish(const double* __restrict__ partial, int nblk,
+                                                  double* __restrict__ rr, const double* __restrict__ bnorm2,
+                                                  double* __restrict__ beta, int* __restrict__ active,
+                                                  int* __restrict__ iters, double rtol) {
+    __shared__ double sh[RB];
+    const int vec = blockIdx.x;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += RB) acc += partial[vec * nblk + i];
+    acc = block_sum(acc, sh);
+    if (threadIdx.x != 0) return;
+    if (!active[vec]) {
+        beta[vec] = 0.0;
+        return;
+    }
+    beta[vec] = acc / rr[vec];
+    rr[vec] = acc;
+    iters[vec] += 1;
+    if (!(sqrt(acc) > rtol * sqrt(bnorm2[vec]))) active[vec] = 0;
+}
+
+template <typename R>
+__global__ void k_cg_p(R* __restrict__ p, const R* __restrict__ r, const double* __restrict__ beta,
+                       const int* __restrict__ active, int64_t n) {
+    const int vec = blockIdx.y;
+    if (!active[vec]) return;
+    const R b = (R)beta[vec];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[vec * n + i] = r[vec * n + i] + b * p[vec * n + i];
+}
+
+template <typename R>
+void cg_run(const MatvecFn<R>& A, int64_t n, int nvec, const R* b, R* x, double rtol, int maxit, CgBuffers<R>& B,
+            std::vector<int>& iters, std::vector<double>& relres, hipStream_t st) {
+    const int nblk = dot_blocks(n);
+    const size_t vbytes = (size_t)nvec * n * sizeof(R);
+    KRY_HIP(hipMemsetAsync(x, 0, vbytes, st));
+    KRY_HIP(hipMemcpyAsync(B.r, b, vbytes, hipMemcpyDeviceToDevice, st));
+    KRY_HIP(hipMemcpyAsync(B.p, b, vbytes, hipMemcpyDeviceToDevice, st));
+    dot_batched<R>(b, n, b, n, n, nvec, B.partial, B.tmp, st);
+    hipLaunchKernelGGL(k_cg_init, dim3((nvec + 63) / 64), dim3(64), 0, st, B.tmp, B.bnorm2, B.rr, B.active, B.iters,
+                       nvec);
+    KRY_HIP(hipGetLastError());
+    std::vector<int> act(nvec);
+    const int check = 16;
+    for (int it = 0; it < maxit; ++it) {
+        A(B.p, B.w, nvec, st);
+        dot_batched<R>(B.p, n, B.w, n, n, nvec, B.partial, B.pw, st);
+        hipLaunchKernelGGL(k_cg_xr<R>, dim3(nblk, nvec), dim3(RB), 0, st, x, B.r, B.p, B.w, B.rr, B.pw, B.active, n,
+                           B.partial);
+        KRY_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_cg_finish, dim3(nvec), dim3(RB), 0, st, B.partial, nblk, B.rr, B.bnorm2, B.beta, B.active,
+                           B.iters, rtol);
+        KRY_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_cg_p<R>, vec_grid(n, nvec), dim3(256), 0, st, B.p, B.r, B.beta, B.active, n);
+        KRY_HIP(hipGetLastError());
+        if ((it + 1) % check == 0 || it + 1 == maxit) {
+            KRY_HIP(hipMemcpyAsync(act.data(), B.active, nvec * sizeof(int), hipMemcpyDeviceToHost, st));
+            KRY_HIP(hipStreamSynchronize(st));
+            bool any = false;
+            for (int v = 0; v < nvec; ++v) any = any || act[v];
+            if (!any) break;
+        }
+    }
+    std::vector<double> rr(nvec), bn(nvec);
+    iters.resize(nvec);
+    relres.resize(nvec);
+    KRY_HIP(hipMemcpyAsync(iters.data(), B.iters, nvec * sizeof(int), hipMemcpyDeviceToHost, st));
+    KRY_HIP(hipMemcpyAsync(rr.data(), B.rr, nvec * sizeof(double), hipMemcpyDeviceToHost, st));
+    KRY_HIP(hipMemcpyAsync(bn.data(), B.bnorm2, nvec * sizeof(double), hipMemcpyDeviceToHost, st));
+    KRY_HIP(hipStreamSynchronize(st));
+    for (int v = 0; v < nvec; ++v) relres[v] = bn[v] > 0 ? std::sqrt(rr[v] / bn[v]) : 0.0;
+}
+template void cg_run<double>(const MatvecFn<double>&, int64_t, int, const double*, double*, double, int,
+                             CgBuffers<double>&, std::vector<int>&, std::vector<double>&, hipStream_t);
+template void cg_run<float>(const MatvecFn<float>&, int64_t, int, const float*, float*, double, int, CgBuffers<float>&,
+                            std::vector<int>&, std::vector<double>&, hipStream_t);
+
+// y = a x + b y  (FP64 coefficients per vector)
+template <typename R>
+__global__ void k_axpby(const R* __restrict__ x, R* __restrict__ y, double a, double b, int64_t n) {
+    const int vec = blockIdx.y;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[vec * n + i] = (R)(a * (double)x[vec * n + i] + b * (double)y[vec * n + i]);
+}
+
+template <typename R>
+void axpby(const R* x, R* y, double a, double b, int64_t n, int nvec, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpby<R>, vec_grid(n, nvec), dim3(256), 0, st, x, y, a, b, n);
+    KRY_HIP(hipGetLastError());
+}
+template void axpby<double>(const double*, double*, double, double, int64_t, int, hipStream_t);
+template void axpby<float>(const float*, float*, double, double, int64_t, int, hipStream_t);
+
+// x64 += (double) d32
+__global__ void k_add_f32(const float* __restrict__ d, double* __restrict__ x, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] += (double)d[i];
+}
+void add_f32(const float* d, double* x, int64_t n, hipStream_t st) {
+    int64_t b = (n + 255) / 256;
+    if (b > 16384) b = 16384;
+    hipLaunchKernelGGL(k_add_f32, dim3((unsigned)b), dim3(256), 0, st, d, x, n);
+    KRY_HIP(hipGetLastError());
+}
+
+}  // namespace kry

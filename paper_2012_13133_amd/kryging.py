@@ -1,0 +1,368 @@
+"""ctypes binding of libkryging.so (C ABI in include/kryging.h).
+
+Argument marshalling only: every function here converts numpy arrays to
+pointers, calls the C entry point of the same name and turns a non-zero
+status into ``KryError``.  There is no fallback: if the HIP library is not
+built, importing this module raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkryging.so")
+
+KRY_OK, KRY_EINVAL, KRY_ENOMEM, KRY_EDEVICE, KRY_ENOTPSD, KRY_ENOCONV, KRY_EBUSY, KRY_ENOTIMPL = range(8)
+KRY_FP64, KRY_FP32 = 0, 1
+KRY_PROBE_RADEMACHER, KRY_PROBE_COLOURED = 0, 1
+KRY_SOLVER_CG, KRY_SOLVER_GENGK = 0, 1
+
+
+class KryError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s (status %d): %s" % (_STATUS_NAMES.get(status, "?"), status, message))
+        self.status = status
+
+
+_STATUS_NAMES = {0: "KRY_OK", 1: "KRY_EINVAL", 2: "KRY_ENOMEM", 3: "KRY_EDEVICE", 4: "KRY_ENOTPSD",
+                 5: "KRY_ENOCONV", 6: "KRY_EBUSY", 7: "KRY_ENOTIMPL"}
+
+
+class kry_grid(C.Structure):
+    _fields_ = [("n1", C.c_int32), ("n2", C.c_int32), ("dx1", C.c_double), ("dx2", C.c_double)]
+
+
+class kry_matern(C.Structure):
+    _fields_ = [("sigma2", C.c_double), ("tau2", C.c_double), ("range", C.c_double), ("nu", C.c_double),
+                ("aniso_ratio", C.c_double), ("aniso_angle", C.c_double)]
+
+
+class kry_opts(C.Structure):
+    _fields_ = [("lanczos_steps", C.c_int32), ("num_probes", C.c_int32), ("probe_kind", C.c_int32),
+                ("colour_period", C.c_int32), ("seed", C.c_uint64), ("reorth", C.c_int32),
+                ("precision", C.c_int32), ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32),
+                ("solver", C.c_int32), ("gk_steps", C.c_int32)]
+
+
+class kry_loglik_result(C.Structure):
+    _fields_ = [("loglik", C.c_double), ("loglik_profiled", C.c_double), ("sigma2_hat", C.c_double),
+                ("logdet", C.c_double), ("logdet_se", C.c_double), ("quad", C.c_double), ("p", C.c_int64),
+                ("lanczos_steps_used", C.c_int32), ("cg_iters", C.c_int32), ("cg_relres", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = C.c_void_p
+_DP = C.POINTER(C.c_double)
+_I32P = C.POINTER(C.c_int32)
+_SIGS = {
+    "kry_status_string": (C.c_char_p, [C.c_int]),
+    "kry_last_error": (C.c_char_p, []),
+    "kry_opts_default": (C.c_int, [C.POINTER(kry_opts)]),
+    "kry_ctx_create": (C.c_int, [C.c_int32, C.c_uint64, C.POINTER(_P)]),
+    "kry_ctx_destroy": (None, [_P]),
+    "kry_problem_create": (C.c_int, [_P, C.POINTER(kry_grid), C.POINTER(C.c_uint8), _DP, C.POINTER(_P)]),
+    "kry_problem_set_data": (C.c_int, [_P, _DP]),
+    "kry_problem_info": (C.c_int, [_P, C.POINTER(C.c_int64), _I32P, _I32P]),
+    "kry_problem_destroy": (None, [_P]),
+    "kry_lag_grid": (C.c_int, [_P, C.POINTER(kry_matern), C.c_int32, C.c_int32, _DP]),
+    "kry_spectrum": (C.c_int, [_P, C.POINTER(kry_matern), C.c_int32, C.c_int32, _DP, _DP]),
+    "kry_matvec": (C.c_int, [_P, C.POINTER(kry_matern), C.c_int32, C.c_int32, _DP, _DP]),
+    "kry_matvec_device": (C.c_int, [_P, C.POINTER(kry_matern), C.c_int32, C.c_int32, _P, _P, _P]),
+    "kry_cov_apply_full": (C.c_int, [_P, C.POINTER(kry_matern), C.c_int32, C.c_int32, _DP, _DP]),
+    "kry_probes": (C.c_int, [_P, C.POINTER(kry_opts), _I32P, _DP]),
+    "kry_lanczos": (C.c_int, [_P, C.POINTER(kry_matern), C.POINTER(kry_opts), _DP, _DP, _I32P]),
+    "kry_logdet": (C.c_int, [_P, C.POINTER(kry_matern), C.POINTER(kry_opts), _DP, _DP, _DP]),
+    "kry_gauss_quadrature": (C.c_int, [C.c_int32, C.c_int32, _DP, _DP, _I32P, _DP, _DP]),
+    "kry_solve": (C.c_int, [_P, C.POINTER(kry_matern), C.POINTER(kry_opts), C.c_int32, _DP, _DP, _I32P, _DP]),
+    "kry_gengk": (C.c_int, [_P, C.POINTER(kry_matern), C.POINTER(kry_opts), _DP, _DP, _DP, _DP, _DP]),
+    "kry_loglik": (C.c_int, [_P, C.POINTER(kry_matern), C.POINTER(kry_opts), C.POINTER(kry_loglik_result)]),
+    "kry_loglik_batch": (C.c_int, [_P, C.POINTER(kry_matern), C.c_int32, C.POINTER(kry_opts),
+                                   C.POINTER(kry_loglik_result)]),
+    "kry_fit": (C.c_int, [_P, C.POINTER(kry_matern), C.c_uint32, C.POINTER(kry_opts), C.c_double, C.c_int32,
+                          C.POINTER(kry_matern), C.POINTER(kry_loglik_result)]),
+    "kry_krige": (C.c_int, [_P, C.POINTER(kry_matern), C.POINTER(kry_opts), C.POINTER(C.c_int64), C.c_int64,
+                            _DP, _DP, _DP, C.c_int32]),
+    "kry_psd_torus": (C.c_int, [_P, C.POINTER(kry_matern), _I32P, _I32P]),
+    "kry_sample": (C.c_int, [_P, C.POINTER(kry_matern), C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_int32,
+                             _DP, _DP]),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libkryging.so is not built (%s); run `python -c \"import __graft_entry__ as g; "
+                          "g.build()\"` first" % LIB_PATH)
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(status):
+    if status != KRY_OK:
+        raise KryError(status, lib.kry_last_error().decode(errors="replace"))
+
+
+def _dp(a):
+    return a.ctypes.data_as(_DP) if a is not None else None
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def theta(sigma2=1.0, tau2=0.1, range=0.1, nu=0.5, aniso_ratio=1.0, aniso_angle=0.0):
+    return kry_matern(sigma2, tau2, range, nu, aniso_ratio, aniso_angle)
+
+
+def theta_from_dict(d):
+    return kry_matern(d.get("sigma2", 1.0), d.get("tau2", 0.1), d["range"], d["nu"],
+                      d.get("aniso_ratio", 1.0), d.get("aniso_angle", 0.0))
+
+
+# ---- functions with the ABI's names ---------------------------------------------------
+def kry_status_string(s):
+    return lib.kry_status_string(s).decode()
+
+
+def kry_opts_default(**overrides):
+    o = kry_opts()
+    _check(lib.kry_opts_default(C.byref(o)))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def kry_ctx_create(device=0, hbm_budget_bytes=0):
+    h = _P()
+    _check(lib.kry_ctx_create(device, hbm_budget_bytes, C.byref(h)))
+    return h
+
+
+def kry_ctx_destroy(ctx):
+    lib.kry_ctx_destroy(ctx)
+
+
+def kry_problem_create(ctx, n1, n2, mask, y=None, dx1=None, dx2=None):
+    g = kry_grid(n1, n2, 1.0 / n1 if dx1 is None else dx1, 1.0 / n2 if dx2 is None else dx2)
+    m = np.ascontiguousarray(np.asarray(mask).reshape(n1 * n2) != 0, dtype=np.uint8)
+    yy = None if y is None else _f64(np.asarray(y).reshape(n1 * n2))
+    h = _P()
+    _check(lib.kry_problem_create(ctx, C.byref(g), m.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(yy), C.byref(h)))
+    return h
+
+
+def kry_problem_set_data(prob, y):
+    yy = _f64(np.asarray(y).ravel())
+    _check(lib.kry_problem_set_data(prob, _dp(yy)))
+
+
+def kry_problem_info(prob):
+    p = C.c_int64()
+    a = C.c_int32()
+    b = C.c_int32()
+    _check(lib.kry_problem_info(prob, C.byref(p), C.byref(a), C.byref(b)))
+    return p.value, a.value, b.value
+
+
+def kry_problem_destroy(prob):
+    lib.kry_problem_destroy(prob)
+
+
+def kry_lag_grid(prob, th, N1=0, N2=0):
+    if N1 == 0:
+        _, N1, N2 = kry_problem_info(prob)
+    out = np.empty((N1, N2))
+    _check(lib.kry_lag_grid(prob, C.byref(th), N1, N2, _dp(out)))
+    return out
+
+
+def kry_spectrum(prob, th, N1=0, N2=0):
+    if N1 == 0:
+        _, N1, N2 = kry_problem_info(prob)
+    out = np.empty((N2 // 2 + 1, N1))
+    mm = np.empty(2)
+    _check(lib.kry_spectrum(prob, C.byref(th), N1, N2, _dp(out), _dp(mm)))
+    return out, mm
+
+
+def kry_matvec(prob, th, v, precision=KRY_FP64):
+    v = _f64(np.atleast_2d(v))
+    out = np.empty_like(v)
+    _check(lib.kry_matvec(prob, C.byref(th), precision, v.shape[0], _dp(v), _dp(out)))
+    return out
+
+
+def kry_matvec_device(prob, th, precision, nvec, d_v, d_out, stream=None):
+    """d_v, d_out: device pointers (int), e.g. torch tensors' data_ptr()."""
+    _check(lib.kry_matvec_device(prob, C.byref(th), precision, nvec, C.c_void_p(d_v), C.c_void_p(d_out),
+                                 C.c_void_p(stream) if stream else None))
+
+
+def kry_cov_apply_full(prob, th, w, n, precision=KRY_FP64):
+    w = _f64(np.atleast_2d(w))
+    out = np.empty((w.shape[0], n))
+    _check(lib.kry_cov_apply_full(prob, C.byref(th), precision, w.shape[0], _dp(w), _dp(out)))
+    return out
+
+
+def kry_probes(prob, opts):
+    n = C.c_int32()
+    _check(lib.kry_probes(prob, C.byref(opts), C.byref(n), None))
+    p, _, _ = kry_problem_info(prob)
+    out = np.empty((n.value, p))
+    _check(lib.kry_probes(prob, C.byref(opts), C.byref(n), _dp(out)))
+    return out
+
+
+def kry_lanczos(prob, th, opts):
+    n = C.c_int32()
+    _check(lib.kry_probes(prob, C.byref(opts), C.byref(n), None))
+    m = opts.lanczos_steps
+    a = np.empty((n.value, m))
+    b = np.empty((n.value, m))
+    s = np.empty(n.value, dtype=np.int32)
+    _check(lib.kry_lanczos(prob, C.byref(th), C.byref(opts), _dp(a), _dp(b), s.ctypes.data_as(_I32P)))
+    return a, b, s
+
+
+def kry_logdet(prob, th, opts):
+    n = C.c_int32()
+    _check(lib.kry_probes(prob, C.byref(opts), C.byref(n), None))
+    ld = C.c_double()
+    se = C.c_double()
+    per = np.empty(n.value)
+    _check(lib.kry_logdet(prob, C.byref(th), C.byref(opts), C.byref(ld), C.byref(se), _dp(per)))
+    return ld.value, se.value, per
+
+
+def kry_gauss_quadrature(alpha, beta, steps, znorm2):
+    alpha = _f64(alpha)
+    beta = _f64(beta)
+    steps = np.ascontiguousarray(steps, dtype=np.int32)
+    znorm2 = _f64(znorm2)
+    n, m = alpha.shape
+    out = np.empty(n)
+    _check(lib.kry_gauss_quadrature(n, m, _dp(alpha), _dp(beta), steps.ctypes.data_as(_I32P), _dp(znorm2),
+                                    _dp(out)))
+    return out
+
+
+def kry_solve(prob, th, opts, b, allow_noconv=False):
+    b = _f64(np.atleast_2d(b))
+    x = np.empty_like(b)
+    it = np.empty(b.shape[0], dtype=np.int32)
+    rr = np.empty(b.shape[0])
+    s = lib.kry_solve(prob, C.byref(th), C.byref(opts), b.shape[0], _dp(b), _dp(x), it.ctypes.data_as(_I32P), _dp(rr))
+    if not (allow_noconv and s == KRY_ENOCONV):
+        _check(s)
+    return x, it, rr
+
+
+def kry_gengk(prob, th, opts, n=None):
+    k = opts.gk_steps
+    a = np.empty(k + 1)
+    b = np.empty(k + 1)
+    z = np.empty(k)
+    x = None if n is None else np.empty(n)
+    J = C.c_double()
+    _check(lib.kry_gengk(prob, C.byref(th), C.byref(opts), _dp(a), _dp(b), _dp(z), _dp(x), C.byref(J)))
+    return a, b, z, x, J.value
+
+
+def kry_loglik(prob, th, opts, allow_noconv=False):
+    r = kry_loglik_result()
+    s = lib.kry_loglik(prob, C.byref(th), C.byref(opts), C.byref(r))
+    if not (allow_noconv and s == KRY_ENOCONV):
+        _check(s)
+    return r.as_dict()
+
+
+def kry_loglik_batch(prob, thetas, opts, allow_noconv=False):
+    arr = (kry_matern * len(thetas))(*thetas)
+    res = (kry_loglik_result * len(thetas))()
+    s = lib.kry_loglik_batch(prob, arr, len(thetas), C.byref(opts), res)
+    if not (allow_noconv and s == KRY_ENOCONV):
+        _check(s)
+    return [r.as_dict() for r in res]
+
+
+def kry_fit(prob, init, free_mask, opts, xtol=1e-3, maxiter=200):
+    est = kry_matern()
+    r = kry_loglik_result()
+    _check(lib.kry_fit(prob, C.byref(init), free_mask, C.byref(opts), xtol, maxiter, C.byref(est), C.byref(r)))
+    return est, r.as_dict()
+
+
+def kry_krige(prob, th, opts, targets=None, ntargets=None, want_var=True, bootstrap_B=0):
+    if targets is None:
+        tg = None
+        nt = ntargets
+    else:
+        tg = np.ascontiguousarray(targets, dtype=np.int64)
+        nt = tg.size
+    mean = np.empty(nt)
+    vx = np.empty(nt) if want_var else None
+    vy = np.empty(nt) if want_var else None
+    _check(lib.kry_krige(prob, C.byref(th), C.byref(opts),
+                         tg.ctypes.data_as(C.POINTER(C.c_int64)) if tg is not None else None, nt,
+                         _dp(mean), _dp(vx), _dp(vy), bootstrap_B))
+    return mean, vx, vy
+
+
+def kry_psd_torus(prob, th):
+    a = C.c_int32()
+    b = C.c_int32()
+    _check(lib.kry_psd_torus(prob, C.byref(th), C.byref(a), C.byref(b)))
+    return a.value, b.value
+
+
+def kry_sample(prob, th, N1, N2, seed, first_stream, count, n1, n2):
+    """count fields on the n1 x n2 grid of `prob` (n1, n2 as given to
+    kry_problem_create); returns (fields (count, n1, n2), minmax)."""
+    out = np.empty((count, n1, n2))
+    mm = np.empty(2)
+    _check(lib.kry_sample(prob, C.byref(th), N1, N2, seed, first_stream, count, _dp(out), _dp(mm)))
+    return out, mm
+
+
+class Problem:
+    """Owns a context and a problem handle (closes both)."""
+
+    def __init__(self, n1, n2, mask, y=None, device=0, dx1=None, dx2=None, hbm_budget_bytes=0):
+        self.n1, self.n2 = n1, n2
+        self.ctx = kry_ctx_create(device, hbm_budget_bytes)
+        try:
+            self.h = kry_problem_create(self.ctx, n1, n2, mask, y, dx1, dx2)
+        except Exception:
+            kry_ctx_destroy(self.ctx)
+            raise
+        self.p, self.N1, self.N2 = kry_problem_info(self.h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            kry_problem_destroy(self.h)
+            self.h = None
+        if getattr(self, "ctx", None):
+            kry_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,107 @@
+"""GPU parity: lag grid, spectrum and masked BTTB product against the oracle."""
+import numpy as np
+import pytest
+
+from oracle import direct
+from oracle.geometry import embedding_lags
+from paper_2012_13133_amd import synth
+from tests.gpu_util import rows_rel
+from tests.oracle_cases import grid, theta
+
+pytestmark = pytest.mark.gpu
+
+K = pytest.importorskip("paper_2012_13133_amd.kryging")
+
+THETAS = [
+    theta(0.1, 0.5, tau2=0.1),
+    theta(0.05, 1.5, tau2=0.2),
+    theta(0.2, 2.5, tau2=0.05),
+    theta(0.08, 1.0, tau2=0.1, ratio=2.0, angle=np.pi / 6),
+    theta(0.15, 0.7, tau2=0.3, ratio=1.5, angle=2.0),
+]
+
+
+@pytest.mark.parametrize("th", THETAS)
+@pytest.mark.parametrize("tor", [(16, 32), (64, 64), (128, 16)])
+def test_lag_grid(th, tor):
+    n1, n2 = 9, 7
+    with K.Problem(n1, n2, np.ones((n1, n2))) as P:
+        got = K.kry_lag_grid(P.h, K.theta_from_dict(th), *tor)
+    ref = embedding_lags(tor[0], tor[1], 1.0 / n1, 1.0 / n2, th)
+    assert np.all(np.abs(got - ref) <= 1e-13 * np.abs(ref) + 1e-15)
+
+
+@pytest.mark.parametrize("th", THETAS)
+@pytest.mark.parametrize("tor", [(16, 16), (64, 32), (256, 512)])
+def test_spectrum(th, tor):
+    n1, n2 = 8, 8
+    with K.Problem(n1, n2, np.ones((n1, n2))) as P:
+        lam, mm = K.kry_spectrum(P.h, K.theta_from_dict(th), *tor)
+    c = embedding_lags(tor[0], tor[1], 1.0 / n1, 1.0 / n2, th)
+    ref = np.real(np.fft.fft2(c))[:, : tor[1] // 2 + 1].T
+    scale = np.abs(ref).max()
+    assert np.abs(lam - ref).max() <= 1e-12 * scale
+    assert abs(mm[0] - ref.min()) <= 1e-12 * scale and abs(mm[1] - ref.max()) <= 1e-12 * scale
+
+
+SHAPES = [(2, 2), (3, 5), (7, 9), (16, 16), (32, 32), (33, 47), (64, 50), (100, 3)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("ti", range(len(THETAS)))
+def test_masked_product_fp64_and_fp32(shape, ti):
+    th = THETAS[ti]
+    n1, n2 = shape
+    g = grid(n1, n2)
+    mask = synth.uniform_mask(n1, n2, 0.3 if n1 * n2 > 4 else 0.25, seed=11 + ti)
+    p = int(mask.sum())
+    v = synth.random_vectors(p, 3, seed=5)
+    ref = direct.masked_matvec(g, mask, th, v.T).T
+    with K.Problem(n1, n2, mask) as P:
+        t = K.theta_from_dict(th)
+        got64 = K.kry_matvec(P.h, t, v, K.KRY_FP64)
+        got32 = K.kry_matvec(P.h, t, v, K.KRY_FP32)
+    assert rows_rel(got64, ref) <= 1e-12
+    assert rows_rel(got32, ref) <= 1e-5
+
+
+def test_all_missing_but_one_and_fully_observed():
+    n1, n2 = 12, 10
+    th = THETAS[1]
+    g = grid(n1, n2)
+    for mask in (np.eye(1, n1 * n2, 37).reshape(n1, n2), np.ones((n1, n2))):
+        p = int(mask.sum())
+        v = synth.random_vectors(p, 2, seed=3)
+        ref = direct.masked_matvec(g, mask, th, v.T).T
+        with K.Problem(n1, n2, mask) as P:
+            got = K.kry_matvec(P.h, K.theta_from_dict(th), v, K.KRY_FP64)
+        assert rows_rel(got, ref) <= 1e-12
+
+
+def test_full_grid_product():
+    n1, n2 = 20, 13
+    th = THETAS[3]
+    g = grid(n1, n2)
+    mask = synth.uniform_mask(n1, n2, 0.4, seed=2)
+    w = synth.random_vectors(int(mask.sum()), 2, seed=9)
+    X = np.zeros((2, n1 * n2))
+    X[:, mask.ravel().astype(bool)] = w
+    ref = np.stack([direct.full_matvec(g, th, x) for x in X])
+    with K.Problem(n1, n2, mask) as P:
+        got = K.kry_cov_apply_full(P.h, K.theta_from_dict(th), w, n1 * n2, K.KRY_FP64)
+        got32 = K.kry_cov_apply_full(P.h, K.theta_from_dict(th), w, n1 * n2, K.KRY_FP32)
+    assert rows_rel(got, ref) <= 1e-12
+    assert rows_rel(got32, ref) <= 1e-5
+
+
+def test_probes_bit_exact():
+    from oracle import philox
+    from oracle.geometry import observed_cells
+    n1, n2 = 30, 41
+    mask = synth.uniform_mask(n1, n2, 0.3, seed=4)
+    r, c = observed_cells(mask)
+    with K.Problem(n1, n2, mask) as P:
+        z = K.kry_probes(P.h, K.kry_opts_default(num_probes=7, seed=12345))
+        zc = K.kry_probes(P.h, K.kry_opts_default(probe_kind=K.KRY_PROBE_COLOURED, colour_period=3, seed=99))
+    np.testing.assert_array_equal(z, philox.probe_matrix(r, c, 7, 12345).T)
+    np.testing.assert_array_equal(zc, philox.probe_matrix(r, c, 0, 99, colour_period=3).T)
