@@ -1,0 +1,238 @@
+"""Benchmark of the Kryging hot path on one MI355X.
+
+Workload (the metric shape): a 1024 x 1024 grid on the unit square with 30 %
+of the cells missing uniformly at random (p = 734,003 observed cells),
+Matern nu = 1.5, range 0.05, nugget ratio 0.2, data drawn by circulant
+embedding on a PSD torus plus nugget noise (synthetic, seeded).
+
+One step = one pass of the whole hot path over one batch of parameter
+points: lag grid and spectrum for every point, Rademacher probes, batched
+Lanczos (20 probes x 50 steps per point), Gauss quadrature, multi-RHS CG for
+the quadratic forms and the likelihood assembly (kry_loglik_batch, FP32
+transforms with FP64 scalars).  `value` is the masked products per second
+inside the timed steps (Lanczos products + CG iterations; the FP64
+refinement products are not counted).  The JSON line also carries the
+isolated batched product rate, likelihood evaluations per second of the
+batched FP32 form and of the plain FP64 single-point form, their accuracy
+against FP64 with the same probes, the roofline of the dominant kernel and
+the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "masked BTTB matvecs/s + profile-loglik evals/s at 1024² grid; serve p50/p99"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--points", type=int, default=16, help="parameter points per step")
+    ap.add_argument("--probes", type=int, default=20)
+    ap.add_argument("--lanczos", type=int, default=50)
+    ap.add_argument("--cg-rtol", type=float, default=1e-6)
+    ap.add_argument("--mv-batch", type=int, default=32)
+    ap.add_argument("--mv-reps", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--matvec-only", action="store_true", help="only the isolated batched product (profiling)")
+    return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2012_13133_amd import kryging as K, synth
+
+    n = args.n
+    nu, rho, eta = 1.5, 0.05, 0.2
+    mask = synth.uniform_mask(n, n, 0.3, seed=101)
+    th0 = K.theta(sigma2=1.0, tau2=eta, range=rho, nu=nu)
+    P = K.Problem(n, n, mask)
+    log("problem: %dx%d p=%d embedding %dx%d" % (n, n, P.p, P.N1, P.N2))
+    # data: circulant-embedding field + nugget noise (setup, untimed)
+    N = K.kry_psd_torus(P.h, th0)
+    x, _ = K.kry_sample(P.h, th0, N[0], N[1], 202, 0, 1, n, n)
+    rng = np.random.default_rng(303)
+    y = x[0] + np.sqrt(eta) * rng.standard_normal((n, n))
+    K.kry_problem_set_data(P.h, y)
+    log("data sampled on a %dx%d torus" % N)
+
+    # ---- isolated batched masked product (FP32 and FP64) with stage timing ----
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()  # default priority; the library launches on it
+    torch.cuda.set_stream(stream)
+    sp = stream.cuda_stream
+    mv = {}
+    for prec, dt in ((K.KRY_FP32, torch.float32), (K.KRY_FP64, torch.float64)):
+        B = args.mv_batch
+        vin = torch.randn(B, P.p, device=dev, dtype=dt)
+        vout = torch.empty_like(vin)
+        for _ in range(3):
+            K.kry_matvec_device(P.h, th0, prec, B, vin.data_ptr(), vout.data_ptr(), sp)
+        torch.cuda.synchronize()
+        K.kry_profile_begin(P.ctx)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.mv_reps):
+            K.kry_matvec_device(P.h, th0, prec, B, vin.data_ptr(), vout.data_ptr(), sp)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_total = e0.elapsed_time(e1)
+        st_ms, st_n, st_vec = K.kry_profile_end(P.ctx)
+        rate = B * args.mv_reps / (ms_total / 1e3)
+        mv[prec] = dict(batch=B, matvecs_per_s=rate, ms_per_launch=ms_total / args.mv_reps,
+                        stage_ms=[float(v / max(c, 1)) for v, c in zip(st_ms, st_n)])
+        log("matvec %s B=%d: %.0f matvecs/s, stages A/B/C ms %s" %
+            ("fp32" if prec == K.KRY_FP32 else "fp64", B, rate, mv[prec]["stage_ms"]))
+        del vin, vout
+    torch.cuda.empty_cache()
+
+    if args.matvec_only:
+        print(json.dumps({"matvec_batched": {"fp32": mv[K.KRY_FP32], "fp64": mv[K.KRY_FP64]}}))
+        P.close()
+        return
+
+    # ---- algorithmic bytes of the dominant kernel (stage B, FP32) ----
+    p = P.p
+    M = P.N2 // 2
+    cs = 8  # complex FP32
+    Bv = args.mv_batch
+    inter = n * (M + 1) * cs                   # one vector's half-spectrum intermediate (n1 rows)
+    lam_bytes = (M + 1) * P.N1 * 4             # FP32 spectrum, read once per launch
+    stage_b_bytes = Bv * 2 * inter + lam_bytes
+    stage_ms = mv[K.KRY_FP32]["stage_ms"]
+    dom = int(np.argmax(stage_ms))
+    words = n * ((n + 31) // 32) * 8           # mask words + word offsets
+    stage_bytes = [Bv * (4 * p + inter) + words, stage_b_bytes, Bv * (inter + 4 * p + 4 * p) + words]
+    achieved = stage_bytes[dom] / (stage_ms[dom] / 1e3) / 1e9
+    mv_bytes = sum(stage_bytes)
+    mv_achieved = mv_bytes / (sum(stage_ms) / 1e3) / 1e9
+
+    # ---- timed steps: batched FP32-mixed likelihood over a point batch ----
+    side = int(round(np.sqrt(args.points)))
+    rhos = rho * np.geomspace(0.7, 1.4, side)
+    etas = eta * np.geomspace(0.7, 1.4, max(args.points // side, 1))
+    thetas = [K.theta(sigma2=1.0, tau2=float(e), range=float(r), nu=nu) for r in rhos for e in etas]
+    opts32 = K.kry_opts_default(lanczos_steps=args.lanczos, num_probes=args.probes, seed=303,
+                                precision=K.KRY_FP32, cg_rtol=args.cg_rtol, cg_maxit=20000)
+    for w in range(args.warmup):
+        K.kry_loglik_batch(P.h, thetas, opts32)
+        log("warmup %d done" % w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = None
+    for s in range(args.steps):
+        results = K.kry_loglik_batch(P.h, thetas, opts32)
+        log("step %d done" % s)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    per_step = sum(args.probes * r["lanczos_steps_used"] + r["cg_iters"] for r in results)
+    matvecs_per_s = per_step * args.steps / dt
+    evals_per_s = len(thetas) * args.steps / dt
+
+    # ---- plain FP64 single-point form, same probes, and accuracy ----
+    plain = None
+    if not args.no_plain:
+        opts64 = K.kry_opts_default(lanczos_steps=args.lanczos, num_probes=args.probes, seed=303,
+                                    precision=K.KRY_FP64, cg_rtol=1e-8, cg_maxit=20000)
+        t1 = time.perf_counter()
+        r64 = K.kry_loglik(P.h, thetas[0], opts64)
+        torch.cuda.synchronize()
+        d64 = time.perf_counter() - t1
+        rel = abs(results[0]["loglik"] - r64["loglik"]) / abs(r64["loglik"])
+        plain = dict(evals_per_s=1.0 / d64, seconds=d64, loglik=r64["loglik"], cg_iters=r64["cg_iters"],
+                     fp32_batched_rel_err_vs_fp64=rel)
+        log("plain fp64: %.2f s, fp32-batched rel err %.2e" % (d64, rel))
+
+    # ---- CPU oracle on a bounded sample ----
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(n, mask, dict(range=rho, nu=nu, sigma2=1.0, tau2=eta), P.p)
+
+    out = {
+        "metric": METRIC,
+        "value": matvecs_per_s,
+        "unit": "matvecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "1024x1024 grid, 30%% uniform missing (p=%d), Matern nu=1.5 range=0.05 nugget ratio 0.2; "
+                        "one step = kry_loglik_batch over %d (range, nugget) points, %d probes x %d Lanczos steps, "
+                        "CG to %g, FP32 transforms + FP64 scalars" % (P.p, len(thetas), args.probes, args.lanczos,
+                                                                      args.cg_rtol),
+            "global_batch": len(thetas) * args.probes,
+            "embedding": [P.N1, P.N2],
+        },
+        "loglik_evals_per_s": evals_per_s,
+        "matvec_batched": {"fp32": mv[K.KRY_FP32], "fp64": mv[K.KRY_FP64],
+                           "bytes_per_launch_fp32": mv_bytes, "achieved_GBs_fp32": mv_achieved},
+        "plain_fp64": plain,
+        "batched_vs_plain_evals": (evals_per_s / plain["evals_per_s"]) if plain else None,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": ["stage A (row transform)", "stage B (column transform x spectrum)",
+                                "stage C (inverse row transform, gather)"][dom],
+                     "bytes_per_launch": stage_bytes[dom], "launch_ms": stage_ms[dom], "batch": Bv},
+        "cpu_baseline": cpu,
+        "results_first_point": results[0],
+    }
+    print(json.dumps(out))
+    P.close()
+
+
+def cpu_baseline(n, mask, th, p, budget_s=15.0):
+    """The oracle's direct O(p^2) masked product on a bounded sample of output
+    rows of the same workload, scaled to full products per second."""
+    import numpy as np
+
+    from oracle import direct
+    from oracle.geometry import lag_table
+
+    g = (n, n, 1.0 / n, 1.0 / n)
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(p)
+    t0 = time.perf_counter()
+    T = lag_table(n, n, 1.0 / n, 1.0 / n, th)
+    t_table = time.perf_counter() - t0
+    rows = 0
+    t1 = time.perf_counter()
+    while time.perf_counter() - t1 < budget_s:
+        direct.masked_matvec(g, mask, th, v, rows=np.arange(rows, rows + 25), table=T)
+        rows += 25
+    dt = time.perf_counter() - t1
+    rate = rows / dt / p
+    return {"value": rate, "unit": "matvecs/s", "cores": 1, "kind": "oracle",
+            "sample": "direct O(p^2) masked product, %d of %d output rows (%.1f s) plus the lag table (%.1f s, "
+                      "not counted) at 1024x1024, 30%% missing" % (rows, p, dt, t_table)}
+
+
+if __name__ == "__main__":
+    main()

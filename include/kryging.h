@@ -114,6 +114,17 @@ const char* kry_last_error(void);
  * cg_rtol 1e-8, cg_maxit 20000, CG, gk_steps 100. */
 kry_status kry_opts_default(kry_opts* out);
 
+/* ---- stage timing ----------------------------------------------------------- */
+/* Start recording HIP events around the three stage kernels of every masked
+ * product launched through this context (on the stream each is launched
+ * on).  Adds two event records per stage launch. */
+kry_status kry_profile_begin(kry_ctx* ctx);
+/* Stop recording; synchronise the device and return, for stages A (row
+ * transform), B (column transform and spectrum multiply) and C (inverse row
+ * transform and gather): total milliseconds ms[3], launch counts
+ * launches[3], and the number of vectors the recorded products processed. */
+kry_status kry_profile_end(kry_ctx* ctx, double* ms, int64_t* launches, int64_t* vectors);
+
 /* ---- context and problems ----------------------------------------------- */
 /* Binds HIP device `device`; hbm_budget_bytes = 0 means no limit beyond the
  * device.  Creates the library's stream (default priority). */

@@ -58,3 +58,17 @@ def circulant_field(grid, theta, N1, N2, seed, stream=0, clip_tol=1e-10):
 def circulant_sqrt_apply(lam, xi):
     """C^{1/2} xi on the torus for a non-negative spectrum lam (N1 x N2)."""
     return np.real(np.fft.ifft2(np.sqrt(lam) * np.fft.fft2(xi)))
+
+
+def psd_torus(grid, theta, N1, N2, cap=8192, tol=1e-10):
+    """Reading of the Sec. 3.6 caveat: starting from (N1, N2), double both
+    torus sides until the embedding spectrum has min >= -tol * max; None if
+    the cap is passed first."""
+    while True:
+        lam = torus_spectrum(grid, theta, N1, N2)
+        if lam.min() >= -tol * lam.max():
+            return N1, N2
+        if 2 * N1 > cap or 2 * N2 > cap:
+            return None
+        N1 *= 2
+        N2 *= 2

@@ -304,6 +304,7 @@ void solve_device(Problem& P, int precision, const void* lam64, const void* lam3
             cb.partial = a.take<double>((size_t)nrhs * 256);
             cb.active = a.take<int>(nrhs);
             cb.iters = a.take<int>(nrhs);
+            cb.limit = a.take<int>(nrhs);
         };
         Arena m;
         lay(m);
@@ -331,6 +332,7 @@ void solve_device(Problem& P, int precision, const void* lam64, const void* lam3
         cb.partial = a.take<double>((size_t)nrhs * 256);
         cb.active = a.take<int>(nrhs);
         cb.iters = a.take<int>(nrhs);
+        cb.limit = a.take<int>(nrhs);
         b32 = a.take<float>(vn);
         x32 = a.take<float>(vn);
         r64 = a.take<double>(vn);
@@ -364,13 +366,21 @@ void solve_device(Problem& P, int precision, const void* lam64, const void* lam3
             if (out.relres[v] > rtol) done = false;
         }
         if (done) break;
-        int budget = maxit;
-        for (int v = 0; v < nrhs; ++v) budget = std::min(budget, maxit - out.iters[v]);
-        if (budget <= 0) break;
+        // right-hand sides already at tolerance get a zero inner system, so
+        // each solution is the same whatever else shares the launch
         convert<double, float>(r64, b32, vn, st);
+        std::vector<int> lim(nrhs);
+        bool any = false;
+        for (int v = 0; v < nrhs; ++v) {
+            const bool conv = out.relres[v] <= rtol;
+            lim[v] = conv ? 0 : maxit - out.iters[v];
+            if (conv) KRY_HIP(hipMemsetAsync(b32 + (size_t)v * p, 0, p * sizeof(float), st));
+            any = any || lim[v] > 0;
+        }
+        if (!any) break;
         std::vector<int> it;
         std::vector<double> rr;
-        cg_run<float>(A32, p, nrhs, b32, x32, inner, budget, cb, it, rr, st);
+        cg_run<float>(A32, p, nrhs, b32, x32, inner, maxit, cb, it, rr, st, &lim);
         for (int v = 0; v < nrhs; ++v) out.iters[v] += it[v];
         add_f32(x32, X, vn, st);
         A64(X, t64, nrhs, st);
@@ -789,10 +799,47 @@ kry_status kry_ctx_create(int32_t device, uint64_t hbm_budget_bytes, kry_ctx** o
     });
 }
 
+kry_status kry_profile_begin(kry_ctx* ctx) {
+    return guard([&] {
+        KRY_REQUIRE(ctx != nullptr, "ctx is NULL");
+        bind(ctx->c);
+        ctx->c.prof.on = true;
+        ctx->c.prof.recs.clear();
+        ctx->c.prof.next = 0;
+    });
+}
+
+kry_status kry_profile_end(kry_ctx* ctx, double* ms, int64_t* launches, int64_t* vectors) {
+    return guard([&] {
+        KRY_REQUIRE(ctx && ms && launches && vectors, "NULL argument");
+        bind(ctx->c);
+        StageProfile& pr = ctx->c.prof;
+        KRY_HIP(hipDeviceSynchronize());
+        for (int i = 0; i < 3; ++i) {
+            ms[i] = 0.0;
+            launches[i] = 0;
+        }
+        *vectors = 0;
+        for (const auto& r : pr.recs) {
+            for (int i = 0; i < 3; ++i) {
+                float t = 0.f;
+                KRY_HIP(hipEventElapsedTime(&t, pr.pool[r[i]], pr.pool[r[i + 1]]));
+                ms[i] += t;
+                launches[i] += 1;
+            }
+            *vectors += r[4];
+        }
+        pr.on = false;
+        pr.recs.clear();
+        pr.next = 0;
+    });
+}
+
 void kry_ctx_destroy(kry_ctx* ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->c.device);
     if (ctx->c.stream) (void)hipStreamSynchronize(ctx->c.stream);
+    for (hipEvent_t e : ctx->c.prof.pool) (void)hipEventDestroy(e);
     dev_free(ctx->c, ctx->c.tw64, TW_N * sizeof(cpx<double>));
     dev_free(ctx->c, ctx->c.tw32, TW_N * sizeof(cpx<float>));
     if (ctx->c.stream) (void)hipStreamDestroy(ctx->c.stream);

@@ -469,9 +469,24 @@ void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st) {
     P.Y.ensure(*P.ctx, (size_t)Yvs * s.nvec * sizeof(cpx<R>));
     cpx<R>* Y = P.Y.as<cpx<R>>();
 
+    StageProfile& pr = P.ctx->prof;
+    std::array<int, 5> rec{};
+    auto mark = [&](int slot) {
+        if (!pr.on) return;
+        if (pr.next == pr.pool.size()) {
+            hipEvent_t e;
+            KRY_HIP(hipEventCreate(&e));
+            pr.pool.push_back(e);
+        }
+        rec[slot] = (int)pr.next;
+        KRY_HIP(hipEventRecord(pr.pool[pr.next++], st));
+    };
+    mark(0);
     run_stage_a<R>(P, s, Y, ldY, Yvs, st);
+    mark(1);
     run_stage_b<R>(P, s.N1, M, s.nvec, Y, ldY, Yvs, s.rows_in, s.rows_out, s.lam, s.lam_tstride,
                    s.vecs_per_theta, nullptr, st);
+    mark(2);
 
     StageCArgs c;
     c.Y = Y;
@@ -498,6 +513,11 @@ void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st) {
     } else {
         if (s.out_mode == OUT_COMPACT) launch_c<R, 16, OUT_COMPACT>(c, grid, ta.threads, ta.lds, tw, st);
         else launch_c<R, 16, OUT_GRID>(c, grid, ta.threads, ta.lds, tw, st);
+    }
+    mark(3);
+    if (pr.on) {
+        rec[4] = s.nvec;
+        pr.recs.push_back(rec);
     }
 }
 

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <stdexcept>
 #include <string>
@@ -31,9 +32,19 @@ struct Error : std::runtime_error {
         if (!(cond)) throw ::kry::Error(KRY_EINVAL, std::string(msg)); \
     } while (0)
 
+// Per-stage timing of the masked product: events recorded around each
+// stage launch while profiling is on, summed when read back.
+struct StageProfile {
+    bool on = false;
+    std::vector<hipEvent_t> pool;          // reusable events
+    std::vector<std::array<int, 5>> recs;  // event indices: A0, B0, C0, C1 per product, + nvec
+    size_t next = 0;
+};
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    StageProfile prof;
     uint64_t budget = 0;     // 0 = unlimited
     uint64_t allocated = 0;  // bytes currently held through dev_alloc
     cpx<double>* tw64 = nullptr;

@@ -8,6 +8,7 @@
 // block in a fixed order.  The result for a vector therefore does not depend
 // on which other vectors share the launch.  Accumulation is FP64 for both
 // element types.
+#include <algorithm>
 #include <cmath>
 
 #include "internal.hpp"
@@ -372,12 +373,12 @@ void quadrature(const double* alpha, const double* beta, const int* steps, const
 
 // ---- conjugate gradients ---------------------------------------------------------------
 __global__ void k_cg_init(const double* __restrict__ rr, double* __restrict__ bnorm2, double* __restrict__ rr_state,
-                          int* __restrict__ active, int* __restrict__ iters, int nvec) {
+                          int* __restrict__ active, int* __restrict__ iters, const int* __restrict__ limit, int nvec) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nvec) return;
     bnorm2[v] = rr[v];
     rr_state[v] = rr[v];
-    active[v] = rr[v] > 0.0;
+    active[v] = rr[v] > 0.0 && limit[v] > 0;
     iters[v] = 0;
 }
 
@@ -410,7 +411,7 @@ __global__ void __launch_bounds__(RB) k_cg_xr(R* __restrict__ x, R* __restrict__
 __global__ void __launch_bounds__(RB) k_cg_finish(const double* __restrict__ partial, int nblk,
                                                   double* __restrict__ rr, const double* __restrict__ bnorm2,
                                                   double* __restrict__ beta, int* __restrict__ active,
-                                                  int* __restrict__ iters, double rtol) {
+                                                  int* __restrict__ iters, const int* __restrict__ limit, double rtol) {
     __shared__ double sh[RB];
     const int vec = blockIdx.x;
     double acc = 0.0;
@@ -424,7 +425,7 @@ __global__ void __launch_bounds__(RB) k_cg_finish(const double* __restrict__ par
     beta[vec] = acc / rr[vec];
     rr[vec] = acc;
     iters[vec] += 1;
-    if (!(sqrt(acc) > rtol * sqrt(bnorm2[vec]))) active[vec] = 0;
+    if (!(sqrt(acc) > rtol * sqrt(bnorm2[vec])) || iters[vec] >= limit[vec]) active[vec] = 0;
 }
 
 template <typename R>
@@ -439,30 +440,37 @@ __global__ void k_cg_p(R* __restrict__ p, const R* __restrict__ r, const double*
 
 template <typename R>
 void cg_run(const MatvecFn<R>& A, int64_t n, int nvec, const R* b, R* x, double rtol, int maxit, CgBuffers<R>& B,
-            std::vector<int>& iters, std::vector<double>& relres, hipStream_t st) {
+            std::vector<int>& iters, std::vector<double>& relres, hipStream_t st, const std::vector<int>* limits) {
     const int nblk = dot_blocks(n);
+    std::vector<int> lim(nvec, maxit);
+    if (limits) {
+        for (int v = 0; v < nvec; ++v) lim[v] = std::min(maxit, (*limits)[v]);
+    }
+    int loop_max = 0;
+    for (int v = 0; v < nvec; ++v) loop_max = std::max(loop_max, lim[v]);
+    KRY_HIP(hipMemcpyAsync(B.limit, lim.data(), nvec * sizeof(int), hipMemcpyHostToDevice, st));
     const size_t vbytes = (size_t)nvec * n * sizeof(R);
     KRY_HIP(hipMemsetAsync(x, 0, vbytes, st));
     KRY_HIP(hipMemcpyAsync(B.r, b, vbytes, hipMemcpyDeviceToDevice, st));
     KRY_HIP(hipMemcpyAsync(B.p, b, vbytes, hipMemcpyDeviceToDevice, st));
     dot_batched<R>(b, n, b, n, n, nvec, B.partial, B.tmp, st);
     hipLaunchKernelGGL(k_cg_init, dim3((nvec + 63) / 64), dim3(64), 0, st, B.tmp, B.bnorm2, B.rr, B.active, B.iters,
-                       nvec);
+                       B.limit, nvec);
     KRY_HIP(hipGetLastError());
     std::vector<int> act(nvec);
     const int check = 16;
-    for (int it = 0; it < maxit; ++it) {
+    for (int it = 0; it < loop_max; ++it) {
         A(B.p, B.w, nvec, st);
         dot_batched<R>(B.p, n, B.w, n, n, nvec, B.partial, B.pw, st);
         hipLaunchKernelGGL(k_cg_xr<R>, dim3(nblk, nvec), dim3(RB), 0, st, x, B.r, B.p, B.w, B.rr, B.pw, B.active, n,
                            B.partial);
         KRY_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_cg_finish, dim3(nvec), dim3(RB), 0, st, B.partial, nblk, B.rr, B.bnorm2, B.beta, B.active,
-                           B.iters, rtol);
+                           B.iters, B.limit, rtol);
         KRY_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_cg_p<R>, vec_grid(n, nvec), dim3(256), 0, st, B.p, B.r, B.beta, B.active, n);
         KRY_HIP(hipGetLastError());
-        if ((it + 1) % check == 0 || it + 1 == maxit) {
+        if ((it + 1) % check == 0 || it + 1 == loop_max) {
             KRY_HIP(hipMemcpyAsync(act.data(), B.active, nvec * sizeof(int), hipMemcpyDeviceToHost, st));
             KRY_HIP(hipStreamSynchronize(st));
             bool any = false;
@@ -480,9 +488,10 @@ void cg_run(const MatvecFn<R>& A, int64_t n, int nvec, const R* b, R* x, double 
     for (int v = 0; v < nvec; ++v) relres[v] = bn[v] > 0 ? std::sqrt(rr[v] / bn[v]) : 0.0;
 }
 template void cg_run<double>(const MatvecFn<double>&, int64_t, int, const double*, double*, double, int,
-                             CgBuffers<double>&, std::vector<int>&, std::vector<double>&, hipStream_t);
+                             CgBuffers<double>&, std::vector<int>&, std::vector<double>&, hipStream_t,
+                             const std::vector<int>*);
 template void cg_run<float>(const MatvecFn<float>&, int64_t, int, const float*, float*, double, int, CgBuffers<float>&,
-                            std::vector<int>&, std::vector<double>&, hipStream_t);
+                            std::vector<int>&, std::vector<double>&, hipStream_t, const std::vector<int>*);
 
 // y = a x + b y  (FP64 coefficients per vector)
 template <typename R>

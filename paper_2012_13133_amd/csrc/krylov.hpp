@@ -34,6 +34,7 @@ struct CgBuffers {
     R *r, *p, *w;
     double *rr, *bnorm2, *beta, *pw, *tmp, *partial;
     int *active, *iters;
+    int* limit;  // per-vector iteration cap (device, nvec)
 };
 
 template <typename R>
@@ -41,9 +42,12 @@ void lanczos_run(const MatvecFn<R>& A, int64_t n, int nvec, int m, bool reorth, 
                  hipStream_t st);
 void quadrature(const double* alpha, const double* beta, const int* steps, const double* znorm2, int nvec,
                 int64_t coef_stride, double* gamma, hipStream_t st);
+// CG on nvec systems; vector v stops at ||r|| <= rtol ||b|| or after
+// limits[v] iterations (limits == nullptr: maxit for all).
 template <typename R>
 void cg_run(const MatvecFn<R>& A, int64_t n, int nvec, const R* b, R* x, double rtol, int maxit, CgBuffers<R>& B,
-            std::vector<int>& iters, std::vector<double>& relres, hipStream_t st);
+            std::vector<int>& iters, std::vector<double>& relres, hipStream_t st,
+            const std::vector<int>* limits = nullptr);
 template <typename R>
 void make_probes(const Problem& P, int nprobe, uint64_t seed, int period, R* out, hipStream_t st);
 template <typename A, typename B>

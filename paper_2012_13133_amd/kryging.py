@@ -63,6 +63,8 @@ _SIGS = {
     "kry_opts_default": (C.c_int, [C.POINTER(kry_opts)]),
     "kry_ctx_create": (C.c_int, [C.c_int32, C.c_uint64, C.POINTER(_P)]),
     "kry_ctx_destroy": (None, [_P]),
+    "kry_profile_begin": (C.c_int, [_P]),
+    "kry_profile_end": (C.c_int, [_P, _DP, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "kry_problem_create": (C.c_int, [_P, C.POINTER(kry_grid), C.POINTER(C.c_uint8), _DP, C.POINTER(_P)]),
     "kry_problem_set_data": (C.c_int, [_P, _DP]),
     "kry_problem_info": (C.c_int, [_P, C.POINTER(C.c_int64), _I32P, _I32P]),
@@ -149,6 +151,18 @@ def kry_ctx_create(device=0, hbm_budget_bytes=0):
 
 def kry_ctx_destroy(ctx):
     lib.kry_ctx_destroy(ctx)
+
+
+def kry_profile_begin(ctx):
+    _check(lib.kry_profile_begin(ctx))
+
+
+def kry_profile_end(ctx):
+    ms = np.zeros(3)
+    n = np.zeros(3, dtype=np.int64)
+    v = C.c_int64()
+    _check(lib.kry_profile_end(ctx, _dp(ms), n.ctypes.data_as(C.POINTER(C.c_int64)), C.byref(v)))
+    return ms, n, v.value
 
 
 def kry_problem_create(ctx, n1, n2, mask, y=None, dx1=None, dx2=None):

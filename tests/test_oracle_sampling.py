@@ -81,3 +81,14 @@ def test_profile_fit_is_stationary_and_beats_neighbours():
     assert abs(gr) < 1e-2 and abs(ge) < 1e-2
     for dr, de in [(0.1, 0), (-0.1, 0), (0, 0.1), (0, -0.1)]:
         assert f(lr + dr, le + de) < best
+
+
+def test_psd_torus_doubles_until_psd():
+    g = grid(16, 16)
+    th = theta(0.5, 2.5)
+    N = sampler.psd_torus(g, th, 32, 32, cap=1024)
+    assert N is not None and N[0] > 32
+    lam = sampler.torus_spectrum(g, th, *N)
+    assert lam.min() >= -1e-10 * lam.max()
+    half = sampler.torus_spectrum(g, th, N[0] // 2, N[1] // 2)
+    assert half.min() < -1e-10 * half.max()
