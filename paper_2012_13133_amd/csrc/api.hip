@@ -840,6 +840,10 @@ void kry_ctx_destroy(kry_ctx* ctx) {
     (void)hipSetDevice(ctx->c.device);
     if (ctx->c.stream) (void)hipStreamSynchronize(ctx->c.stream);
     for (hipEvent_t e : ctx->c.prof.pool) (void)hipEventDestroy(e);
+    for (int i = 0; i < 14; ++i) {
+        if (ctx->c.plan64[i]) (void)hipFree(ctx->c.plan64[i]);
+        if (ctx->c.plan32[i]) (void)hipFree(ctx->c.plan32[i]);
+    }
     dev_free(ctx->c, ctx->c.tw64, TW_N * sizeof(cpx<double>));
     dev_free(ctx->c, ctx->c.tw32, TW_N * sizeof(cpx<float>));
     if (ctx->c.stream) (void)hipStreamDestroy(ctx->c.stream);

@@ -17,11 +17,12 @@
 //                    multiply by lam, inverse FFT, keep the output rows
 //  stage C  rows:    read RT-row tiles, merge the split, inverse FFT of length
 //                    N2/2, gather observed cells (+ eta v) or write the grid
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 #include <unordered_map>
 
-#include "fft.hpp"
+#include "fftk.hpp"
 #include "internal.hpp"
 
 namespace kry {
@@ -103,7 +104,7 @@ __global__ void k_lag_grid(double* __restrict__ c, int N1, int N2, MaternDev m) 
 }
 
 // ---------------------------------------------------------------------------
-// Stage kernels
+// Stage kernels (compile-time plans, register hand-off; see fftk.hpp)
 // ---------------------------------------------------------------------------
 struct StageAArgs {
     const void* in;
@@ -111,66 +112,87 @@ struct StageAArgs {
     int in_rstride;
     MaskView mask;
     int rows_in, row_len;
-    int log2M;
     int RT, log2RT;
     void* Y;
     int ldY;
     int64_t Y_vstride;
     uint64_t seed;
     int stream0;
+    int vec0;
 };
 
-template <typename R, int VPT, int IN>
-__global__ void __launch_bounds__(1024) k_stage_a(StageAArgs a, const cpx<R>* __restrict__ tw) {
-    extern __shared__ unsigned char smem_raw[];
-    cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
-    R* ldsr = reinterpret_cast<R*>(smem_raw);
-    const int M = 1 << a.log2M;
-    const int S = M + 1;  // LDS row stride (complex elements)
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int row0 = blockIdx.x * a.RT;
-    const int vec = blockIdx.y;
-
-    for (int i = tid; i < a.RT * S; i += nt) lds[i] = cpx<R>{(R)0, (R)0};
-    __syncthreads();
-    const int total = a.RT * a.row_len;
-    for (int idx = tid; idx < total; idx += nt) {
-        const int rr = idx / a.row_len;
-        const int j = idx - rr * a.row_len;
-        const int row = row0 + rr;
-        if (row >= a.rows_in) continue;
-        R val;
-        if constexpr (IN == IN_COMPACT) {
-            int64_t c;
-            if (!mask_lookup(a.mask, row, j, c)) continue;
-            val = reinterpret_cast<const R*>(a.in)[vec * a.in_vstride + c];
-        } else if constexpr (IN == IN_DENSE) {
-            val = (R) reinterpret_cast<const double*>(a.in)[vec * a.in_vstride + (int64_t)row * a.in_rstride + j];
-        } else {
-            val = (R)philox_normal((uint32_t)(row * a.in_rstride + j), (uint32_t)(a.stream0 + vec),
-                                   DOMAIN_FIELD, a.seed);
-        }
-        ldsr[2 * rr * S + j] = val;
-    }
-    __syncthreads();
-    fft_lds<R, false, VPT>(lds, a.log2M, S, tid, nt, tw);
-
-    cpx<R>* Y = reinterpret_cast<cpx<R>*>(a.Y) + vec * a.Y_vstride;
-    const int nout = a.RT * (M + 1);
-    for (int o = tid; o < nout; o += nt) {
-        const int rr = o & (a.RT - 1);
-        const int k = o >> a.log2RT;
-        const cpx<R> zk = lds[rr * S + (k & (M - 1))];
-        const cpx<R> zc = cconj(lds[rr * S + ((M - k) & (M - 1))]);
-        const cpx<R> w = twiddle<R, false>(tw, k, a.log2M + 1);
-        const cpx<R> s = cadd(zk, zc);
-        const cpx<R> wd = cmul(w, csub(zk, zc));
-        // X[k] = (s - i w d) / 2
-        Y[(int64_t)k * a.ldY + row0 + rr] = cpx<R>{(R)0.5 * (s.x + wd.y), (R)0.5 * (s.y - wd.x)};
+// Value of input column c of a row (0 beyond the data or off the mask).
+template <typename R, int IN>
+__device__ __forceinline__ void load_pair(const StageAArgs& a, int vec, int row, int c0, cpx<R>& out) {
+    out = cpx<R>{(R)0, (R)0};
+    if (c0 >= a.row_len) return;
+    if constexpr (IN == IN_COMPACT) {
+        const int w = row * a.mask.words_per_row + (c0 >> 5);
+        const uint32_t word = a.mask.bits[w];
+        const uint32_t b0 = 1u << (c0 & 31);
+        const uint32_t pair = word & (b0 | (b0 << 1));
+        if (!pair) return;
+        const R* vin = reinterpret_cast<const R*>(a.in) + vec * a.in_vstride;
+        int64_t ci = (int64_t)a.mask.base[w] + __popc(word & (b0 - 1u));
+        if (word & b0) out.x = vin[ci++];
+        if (word & (b0 << 1)) out.y = vin[ci];
+    } else if constexpr (IN == IN_DENSE) {
+        const double* src = reinterpret_cast<const double*>(a.in) + vec * a.in_vstride + (int64_t)row * a.in_rstride;
+        out.x = (R)src[c0];
+        if (c0 + 1 < a.row_len) out.y = (R)src[c0 + 1];
+    } else {
+        const uint32_t idx = (uint32_t)(row * a.in_rstride + c0);
+        const uint32_t stream = (uint32_t)(a.stream0 + a.vec0 + vec);
+        out.x = (R)philox_normal(idx, stream, DOMAIN_FIELD, a.seed);
+        if (c0 + 1 < a.row_len) out.y = (R)philox_normal(idx + 1u, stream, DOMAIN_FIELD, a.seed);
     }
 }
 
-enum { B_CONV = 0, B_SPEC = 1 };
+// Stage A: per row, z[m] = x[2m] + i x[2m+1] -> FFT of length M -> split into
+// the real transform X[k], k = 0..M, written as Y[k][row] in RT-row runs.
+template <typename R, int LOG2M, int IN>
+__global__ void __launch_bounds__(1024) k_row_fwd(StageAArgs a, const cpx<R>* __restrict__ twp,
+                                                  const cpx<R>* __restrict__ twb) {
+    using S = Sched<LOG2M>;
+    constexpr int M = S::L, T = M / 8, PM = padded(M) + 1;
+    constexpr bool LOW = (IN == IN_COMPACT);  // row_len <= M: z[m] = 0 for m >= M/2
+    extern __shared__ unsigned char smem_raw[];
+    cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int rr = tid / T, t = tid % T;
+    const int row0 = blockIdx.x * a.RT;
+    const int row = row0 + rr;
+    const int vec = blockIdx.y;
+    cpx<R>* buf = lds + rr * PM;
+    cpx<R> v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        v[r] = cpx<R>{(R)0, (R)0};
+        if (LOW && r >= 4) continue;
+        if (row < a.rows_in) load_pair<R, IN>(a, vec, row, 2 * (t + r * T), v[r]);
+    }
+    pass_compute<R, LOG2M, false, 0, LOW>(v, t, twp);
+    pass_write<R, LOG2M, false, 0>(v, buf, t);
+    __syncthreads();
+    LdsPasses<R, LOG2M, false, 1, S::npass>::run(v, buf, t, twp);
+
+    cpx<R>* Y = reinterpret_cast<cpx<R>*>(a.Y) + vec * a.Y_vstride;
+    const int nout = a.RT * (M + 1);
+    for (int o = tid; o < nout; o += blockDim.x) {
+        const int r2 = o & (a.RT - 1);
+        const int k = o >> a.log2RT;
+        const cpx<R>* bp = lds + r2 * PM;
+        const cpx<R> zk = bp[pad8(k & (M - 1))];
+        const cpx<R> zc = cconj(bp[pad8((M - k) & (M - 1))]);
+        const cpx<R> w = twiddle<R, false>(twb, k, LOG2M + 1);
+        const cpx<R> s = cadd(zk, zc);
+        const cpx<R> wd = cmul(w, csub(zk, zc));
+        // X[k] = (s - i w d) / 2
+        Y[(int64_t)k * a.ldY + row0 + r2] = cpx<R>{(R)0.5 * (s.x + wd.y), (R)0.5 * (s.y - wd.x)};
+    }
+}
+
+enum { B_LOW = 0, B_FULL = 1, B_SPEC = 2 };
 
 struct StageBArgs {
     void* Y;
@@ -178,55 +200,70 @@ struct StageBArgs {
     int64_t Y_vstride;
     int ncols;
     int rows_in, rows_out;
-    int log2N1;
     int CB;
     const void* lam;
     int64_t lam_tstride;
     int vecs_per_theta;
+    int vec0;
     double* spec_out;
 };
 
-template <typename R, int VPT, int MODE>
-__global__ void __launch_bounds__(1024) k_stage_b(StageBArgs a, const cpx<R>* __restrict__ tw) {
+// Stage B: per column of the half spectrum, forward FFT of length L (rows
+// beyond rows_in are zero), multiply by lam in registers, inverse FFT, keep
+// rows_out rows.  B_SPEC: forward only, real part to spec_out.
+template <typename R, int LOG2L, int MODE>
+__global__ void __launch_bounds__(1024) k_col(StageBArgs a, const cpx<R>* __restrict__ twp) {
+    using S = Sched<LOG2L>;
+    constexpr int L = S::L, T = L / 8, PL = padded(L);
+    constexpr bool LOW = (MODE == B_LOW);
+    constexpr int LRF = S::lr(false, S::npass - 1);  // last forward radix = first inverse radix
     extern __shared__ unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
-    const int N1 = 1 << a.log2N1;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int col0 = blockIdx.x * a.CB;
+    const int tid = threadIdx.x;
+    const int cl = tid / T, t = tid % T;
+    const int col = blockIdx.x * a.CB + cl;
+    const bool valid = col < a.ncols;
     const int vec = blockIdx.y;
-    cpx<R>* Y = reinterpret_cast<cpx<R>*>(a.Y) + vec * a.Y_vstride;
-    const int n = a.CB * N1;
-
-    for (int i = tid; i < n; i += nt) {
-        const int c = i >> a.log2N1, r = i & (N1 - 1);
-        const int col = col0 + c;
-        cpx<R> v{(R)0, (R)0};
-        if (col < a.ncols && r < a.rows_in) v = Y[(int64_t)col * a.ldY + r];
-        lds[i] = v;
+    cpx<R>* buf = lds + cl * PL;
+    cpx<R>* Y = reinterpret_cast<cpx<R>*>(a.Y) + vec * a.Y_vstride + (int64_t)(valid ? col : 0) * a.ldY;
+    cpx<R> v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int idx = t + r * T;
+        v[r] = cpx<R>{(R)0, (R)0};
+        if (LOW && r >= 4) continue;
+        if (valid && idx < a.rows_in) v[r] = Y[idx];
     }
+    pass_compute<R, LOG2L, false, 0, LOW>(v, t, twp);
+    pass_write<R, LOG2L, false, 0>(v, buf, t);
     __syncthreads();
-    fft_lds<R, false, VPT>(lds, a.log2N1, N1, tid, nt, tw);
+    LdsPasses<R, LOG2L, false, 1, S::npass - 1>::run(v, buf, t, twp);
+    pass_read<R, LOG2L, false, S::npass - 1>(v, buf, t);
+    pass_compute<R, LOG2L, false, S::npass - 1>(v, t, twp);
     if constexpr (MODE == B_SPEC) {
-        for (int i = tid; i < n; i += nt) {
-            const int c = i >> a.log2N1, r = i & (N1 - 1);
-            const int col = col0 + c;
-            if (col < a.ncols) a.spec_out[(int64_t)col * N1 + r] = (double)lds[i].x;
+        if (valid) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) a.spec_out[(int64_t)col * L + edge_pos<LOG2L, LRF>(t, k)] = (double)v[k].x;
         }
         return;
     } else {
-        const R* lam = reinterpret_cast<const R*>(a.lam) + (int64_t)(vec / a.vecs_per_theta) * a.lam_tstride;
-        for (int i = tid; i < n; i += nt) {
-            const int c = i >> a.log2N1, r = i & (N1 - 1);
-            const int col = col0 + c;
-            const R l = (col < a.ncols) ? lam[(int64_t)col * N1 + r] : (R)0;
-            lds[i] = cscale(lds[i], l);
-        }
+        const R* lam = reinterpret_cast<const R*>(a.lam) +
+                       (int64_t)((a.vec0 + vec) / a.vecs_per_theta) * a.lam_tstride + (int64_t)(valid ? col : 0) * L;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = cscale(v[k], lam[edge_pos<LOG2L, LRF>(t, k)]);
         __syncthreads();
-        fft_lds<R, true, VPT>(lds, a.log2N1, N1, tid, nt, tw);
-        for (int i = tid; i < n; i += nt) {
-            const int c = i >> a.log2N1, r = i & (N1 - 1);
-            const int col = col0 + c;
-            if (col < a.ncols && r < a.rows_out) Y[(int64_t)col * a.ldY + r] = lds[i];
+        pass_compute<R, LOG2L, true, 0>(v, t, twp);
+        pass_write<R, LOG2L, true, 0>(v, buf, t);
+        __syncthreads();
+        LdsPasses<R, LOG2L, true, 1, S::npass - 1>::run(v, buf, t, twp);
+        pass_read<R, LOG2L, true, S::npass - 1>(v, buf, t);
+        pass_compute<R, LOG2L, true, S::npass - 1>(v, t, twp);
+        if (valid) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int idx = t + k * T;
+                if (idx < a.rows_out) Y[idx] = v[k];
+            }
         }
     }
 }
@@ -236,77 +273,93 @@ struct StageCArgs {
     int ldY;
     int64_t Y_vstride;
     int rows_out, cols_out;
-    int log2M;
     int RT, log2RT;
     MaskView mask;
     const void* vin;
     int64_t vin_vstride;
     const double* eta;
     int vecs_per_theta;
+    int vec0;
     void* out;
     int64_t out_vstride;
     double scale;
 };
 
-template <typename R, int VPT, int OUT>
-__global__ void __launch_bounds__(1024) k_stage_c(StageCArgs a, const cpx<R>* __restrict__ tw) {
+// Stage C: read RT-row runs of X[k], k = 0..M, merge the even/odd split into
+// Z[k] = (X[k] + X*[M-k]) + i W^{-k} (X[k] - X*[M-k]), inverse FFT of length M,
+// then x[2m], x[2m+1] = Re, Im z[m] go to the observed cells (+ eta v) or the
+// grid.
+template <typename R, int LOG2M, int OUT>
+__global__ void __launch_bounds__(1024) k_row_inv(StageCArgs a, const cpx<R>* __restrict__ twp,
+                                                  const cpx<R>* __restrict__ twb) {
+    using S = Sched<LOG2M>;
+    constexpr int M = S::L, T = M / 8, PM = padded(M) + 1;
+    constexpr int LRL = S::lr(true, S::npass - 1);
     extern __shared__ unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
-    const R* ldsr = reinterpret_cast<const R*>(smem_raw);
-    const int M = 1 << a.log2M;
-    const int S = M + 1;
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x;
     const int row0 = blockIdx.x * a.RT;
     const int vec = blockIdx.y;
     const cpx<R>* Y = reinterpret_cast<const cpx<R>*>(a.Y) + vec * a.Y_vstride;
-
     const int nin = a.RT * (M + 1);
-    for (int o = tid; o < nin; o += nt) {
-        const int rr = o & (a.RT - 1);
+    for (int o = tid; o < nin; o += blockDim.x) {
+        const int r2 = o & (a.RT - 1);
         const int k = o >> a.log2RT;
-        const int row = row0 + rr;
-        lds[rr * S + k] = (row < a.rows_out) ? Y[(int64_t)k * a.ldY + row] : cpx<R>{(R)0, (R)0};
+        const int row = row0 + r2;
+        lds[r2 * PM + pad8(k)] = (row < a.rows_out) ? Y[(int64_t)k * a.ldY + row] : cpx<R>{(R)0, (R)0};
     }
     __syncthreads();
-    // merge the even/odd split: Z[k] = (X[k] + X*[M-k]) + i W^{-k} (X[k] - X*[M-k]),
-    // done for k and M - k together so the update is in place.
-    const int half = M / 2;
-    const int npair = a.RT * (half + 1);
-    for (int o = tid; o < npair; o += nt) {
-        const int rr = o & (a.RT - 1);
+    const int npair = a.RT * (M / 2 + 1);
+    for (int o = tid; o < npair; o += blockDim.x) {
+        const int r2 = o & (a.RT - 1);
         const int k = o >> a.log2RT;
-        cpx<R>* rowp = lds + rr * S;
-        const cpx<R> xk = rowp[k];
-        const cpx<R> xm = rowp[M - k];
+        cpx<R>* bp = lds + r2 * PM;
+        const cpx<R> xk = bp[pad8(k)];
+        const cpx<R> xm = bp[pad8(M - k)];
         {
             const cpx<R> s = cadd(xk, cconj(xm));
-            const cpx<R> d = cmul(twiddle<R, true>(tw, k, a.log2M + 1), csub(xk, cconj(xm)));
-            rowp[k] = cpx<R>{s.x - d.y, s.y + d.x};
+            const cpx<R> d = cmul(twiddle<R, true>(twb, k, LOG2M + 1), csub(xk, cconj(xm)));
+            bp[pad8(k)] = cpx<R>{s.x - d.y, s.y + d.x};
         }
         if (k > 0 && k < M - k) {
             const cpx<R> s = cadd(xm, cconj(xk));
-            const cpx<R> d = cmul(twiddle<R, true>(tw, M - k, a.log2M + 1), csub(xm, cconj(xk)));
-            rowp[M - k] = cpx<R>{s.x - d.y, s.y + d.x};
+            const cpx<R> d = cmul(twiddle<R, true>(twb, M - k, LOG2M + 1), csub(xm, cconj(xk)));
+            bp[pad8(M - k)] = cpx<R>{s.x - d.y, s.y + d.x};
         }
     }
     __syncthreads();
-    fft_lds<R, true, VPT>(lds, a.log2M, S, tid, nt, tw);
-
-    const int total = a.RT * a.cols_out;
-    const int theta = vec / a.vecs_per_theta;
-    for (int idx = tid; idx < total; idx += nt) {
-        const int rr = idx / a.cols_out;
-        const int j = idx - rr * a.cols_out;
-        const int row = row0 + rr;
-        if (row >= a.rows_out) continue;
-        const R x = ldsr[2 * rr * S + j];
+    const int rr = tid / T, t = tid % T;
+    const int row = row0 + rr;
+    cpx<R>* buf = lds + rr * PM;
+    cpx<R> v[8];
+    LdsPasses<R, LOG2M, true, 0, S::npass - 1>::run(v, buf, t, twp);
+    pass_read<R, LOG2M, true, S::npass - 1>(v, buf, t);
+    pass_compute<R, LOG2M, true, S::npass - 1>(v, t, twp);
+    if (row >= a.rows_out) return;
+    const int theta = (a.vec0 + vec) / a.vecs_per_theta;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int m = edge_pos<LOG2M, LRL>(t, k);
+        const int c0 = 2 * m;
+        if (c0 >= a.cols_out) continue;
         if constexpr (OUT == OUT_COMPACT) {
-            int64_t c;
-            if (!mask_lookup(a.mask, row, j, c)) continue;
-            const R vi = reinterpret_cast<const R*>(a.vin)[vec * a.vin_vstride + c];
-            reinterpret_cast<R*>(a.out)[vec * a.out_vstride + c] = x + (R)a.eta[theta] * vi;
+            const int w = row * a.mask.words_per_row + (c0 >> 5);
+            const uint32_t word = a.mask.bits[w];
+            const uint32_t b0 = 1u << (c0 & 31);
+            if (!(word & (b0 | (b0 << 1)))) continue;
+            int64_t ci = (int64_t)a.mask.base[w] + __popc(word & (b0 - 1u));
+            const R e = (R)a.eta[theta];
+            const R* vi = reinterpret_cast<const R*>(a.vin) + vec * a.vin_vstride;
+            R* o = reinterpret_cast<R*>(a.out) + vec * a.out_vstride;
+            if (word & b0) {
+                o[ci] = v[k].x + e * vi[ci];
+                ++ci;
+            }
+            if (word & (b0 << 1)) o[ci] = v[k].y + e * vi[ci];
         } else {
-            reinterpret_cast<R*>(a.out)[vec * a.out_vstride + (int64_t)row * a.cols_out + j] = (R)a.scale * x;
+            R* o = reinterpret_cast<R*>(a.out) + vec * a.out_vstride + (int64_t)row * a.cols_out;
+            o[c0] = (R)a.scale * v[k].x;
+            if (c0 + 1 < a.cols_out) o[c0 + 1] = (R)a.scale * v[k].y;
         }
     }
 }
@@ -318,36 +371,6 @@ static int ilog2(int v) {
     int l = 0;
     while ((1 << l) < v) ++l;
     return l;
-}
-
-struct RowTiling {
-    int RT, VPT, threads;
-    size_t lds;
-};
-
-// Rows per tile: transposed writes in runs of RT * sizeof(cpx) = 64 bytes
-// where LDS allows, at most 1024 threads per workgroup.
-template <typename R>
-static RowTiling row_tiling(int M) {
-    const int cs = (int)sizeof(cpx<R>);
-    int RT = 64 / cs;
-    while (RT > 1 && (size_t)RT * (M + 1) * cs > 131072) RT /= 2;
-    int VPT = 8;
-    while (RT * M / VPT > 1024) VPT *= 2;
-    while (RT * M / VPT < 256 && RT < 64) RT *= 2;
-    RowTiling t;
-    t.RT = RT;
-    t.VPT = VPT;
-    t.threads = RT * M / VPT;
-    t.lds = (size_t)RT * (M + 1) * cs;
-    return t;
-}
-
-template <typename R>
-static int col_batch(int N1) {
-    // 256 threads (VPT = 8) per workgroup where the column is short
-    int CB = 2048 / N1;
-    return CB < 1 ? 1 : CB;
 }
 
 // Raise a kernel's dynamic LDS limit once per kernel (and size).
@@ -370,42 +393,119 @@ const cpx<double>* twiddles<double>(Ctx& c) { return c.tw64; }
 template <>
 const cpx<float>* twiddles<float>(Ctx& c) { return c.tw32; }
 
-template <typename R, int VPT, int IN>
-static void launch_a(const StageAArgs& a, dim3 grid, int threads, size_t lds, const cpx<R>* tw, hipStream_t st) {
-    auto k = k_stage_a<R, VPT, IN>;
-    set_lds(k, lds);
-    hipLaunchKernelGGL(k, grid, dim3(threads), lds, st, a, tw);
-    KRY_HIP(hipGetLastError());
-}
-
-template <typename R, int VPT, int OUT>
-static void launch_c(const StageCArgs& a, dim3 grid, int threads, size_t lds, const cpx<R>* tw, hipStream_t st) {
-    auto k = k_stage_c<R, VPT, OUT>;
-    set_lds(k, lds);
-    hipLaunchKernelGGL(k, grid, dim3(threads), lds, st, a, tw);
-    KRY_HIP(hipGetLastError());
-}
-
-template <typename R, int MODE>
-static void launch_b(const StageBArgs& a, dim3 grid, int threads, size_t lds, const cpx<R>* tw, hipStream_t st) {
-    auto k = k_stage_b<R, 8, MODE>;
-    set_lds(k, lds);
-    hipLaunchKernelGGL(k, grid, dim3(threads), lds, st, a, tw);
-    KRY_HIP(hipGetLastError());
+// Per-length pass twiddle tables (fftk.hpp layout), built on first use.
+template <int LOG2L>
+static void fill_plan(std::vector<std::array<long double, 2>>& out) {
+    using S = Sched<LOG2L>;
+    out.assign(S::tw_total > 0 ? S::tw_total : 1, {1.0L, 0.0L});
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int inv = 0; inv < 2; ++inv)
+        for (int p = 1; p < S::npass; ++p) {
+            const int R = 1 << S::lr(inv, p), NS = 1 << S::lns(inv, p);
+            const int off = S::tw_off(inv, p);
+            for (int jn = 0; jn < NS; ++jn)
+                for (int r = 0; r < R; ++r) {
+                    const long double ang = (inv ? 2.0L : -2.0L) * pi * (long double)(r * jn) / (long double)(NS * R);
+                    out[off + jn * R + r] = {cosl(ang), sinl(ang)};
+                }
+        }
 }
 
 template <typename R>
-static void run_stage_a(Problem& P, const ConvSpec& s, cpx<R>* Y, int ldY, int64_t Yvs, hipStream_t st) {
+static const cpx<R>* plan_table(Ctx& c, int log2L) {
+    static std::mutex mu;
+    std::lock_guard<std::mutex> g(mu);
+    void*& slot = (sizeof(R) == 8 ? c.plan64 : c.plan32)[log2L];
+    if (slot) return static_cast<const cpx<R>*>(slot);
+    std::vector<std::array<long double, 2>> tab;
+    switch (log2L) {
+        case 3: fill_plan<3>(tab); break;
+        case 4: fill_plan<4>(tab); break;
+        case 5: fill_plan<5>(tab); break;
+        case 6: fill_plan<6>(tab); break;
+        case 7: fill_plan<7>(tab); break;
+        case 8: fill_plan<8>(tab); break;
+        case 9: fill_plan<9>(tab); break;
+        case 10: fill_plan<10>(tab); break;
+        case 11: fill_plan<11>(tab); break;
+        case 12: fill_plan<12>(tab); break;
+        case 13: fill_plan<13>(tab); break;
+        default: throw Error(KRY_EINVAL, "transform length out of range");
+    }
+    std::vector<cpx<R>> h(tab.size());
+    for (size_t i = 0; i < tab.size(); ++i) h[i] = cpx<R>{(R)tab[i][0], (R)tab[i][1]};
+    slot = dev_alloc(c, h.size() * sizeof(cpx<R>));
+    KRY_HIP(hipMemcpy(slot, h.data(), h.size() * sizeof(cpx<R>), hipMemcpyHostToDevice));
+    return static_cast<const cpx<R>*>(slot);
+}
+
+struct RowTiling {
+    int RT, T, threads;
+    size_t lds;
+};
+
+// Rows per tile: transposed runs of RT * sizeof(cpx) = 64 bytes where the
+// workgroup (<= 1024 threads) and LDS allow; more rows for short rows.
+template <typename R>
+static RowTiling row_tiling(int M) {
+    const size_t cs = sizeof(cpx<R>);
+    const int T = M / 8;
+    const size_t PM = (size_t)M + M / 8 + 1;
+    int RT = (int)(64 / cs);
+    while (RT > 1 && RT * T > 1024) RT /= 2;
+    while (RT > 1 && RT * PM * cs > 150 * 1024) RT /= 2;
+    while (RT * T < 256 && RT < 64 && (size_t)(2 * RT) * PM * cs <= 64 * 1024) RT *= 2;
+    RowTiling t;
+    t.RT = RT;
+    t.T = T;
+    t.threads = RT * T;
+    t.lds = RT * PM * cs;
+    return t;
+}
+
+template <typename R, int LG, int IN>
+static void launch_row_fwd(const StageAArgs& a, dim3 grid, const RowTiling& t, Ctx& c, hipStream_t st) {
+    auto k = k_row_fwd<R, LG, IN>;
+    set_lds(k, t.lds);
+    hipLaunchKernelGGL(k, grid, dim3(t.threads), t.lds, st, a, plan_table<R>(c, LG), twiddles<R>(c));
+    KRY_HIP(hipGetLastError());
+}
+
+template <typename R, int LG, int OUT>
+static void launch_row_inv(const StageCArgs& a, dim3 grid, const RowTiling& t, Ctx& c, hipStream_t st) {
+    auto k = k_row_inv<R, LG, OUT>;
+    set_lds(k, t.lds);
+    hipLaunchKernelGGL(k, grid, dim3(t.threads), t.lds, st, a, plan_table<R>(c, LG), twiddles<R>(c));
+    KRY_HIP(hipGetLastError());
+}
+
+template <typename R, int LG, int MODE>
+static void launch_col(const StageBArgs& b, int nvec, Ctx& c, hipStream_t st) {
+    constexpr int L = 1 << LG, T = L / 8;
+    const size_t lds = (size_t)b.CB * padded(L) * sizeof(cpx<R>);
+    dim3 grid((b.ncols + b.CB - 1) / b.CB, nvec);
+    auto k = k_col<R, LG, MODE>;
+    set_lds(k, lds);
+    hipLaunchKernelGGL(k, grid, dim3(b.CB * T), lds, st, b, plan_table<R>(c, LG));
+    KRY_HIP(hipGetLastError());
+}
+
+#define KRY_SIZES(X) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
+
+template <typename R>
+static void run_stage_a(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R>* Y, int ldY, int64_t Yvs,
+                        hipStream_t st) {
     const int M = s.N2 / 2;
     const RowTiling t = row_tiling<R>(M);
     StageAArgs a;
-    a.in = s.in;
+    a.in = s.in_mode == IN_COMPACT ? (const void*)((const R*)s.in + vec0 * s.in_vstride)
+                                   : (const void*)((const double*)s.in + vec0 * s.in_vstride);
+    if (s.in_mode == IN_NOISE) a.in = nullptr;
     a.in_vstride = s.in_vstride;
     a.in_rstride = s.in_rstride;
     a.mask = P.mask_view();
     a.rows_in = s.rows_in;
     a.row_len = s.row_len;
-    a.log2M = ilog2(M);
     a.RT = t.RT;
     a.log2RT = ilog2(t.RT);
     a.Y = Y;
@@ -413,26 +513,28 @@ static void run_stage_a(Problem& P, const ConvSpec& s, cpx<R>* Y, int ldY, int64
     a.Y_vstride = Yvs;
     a.seed = s.seed;
     a.stream0 = s.stream0;
-    dim3 grid((s.rows_in + t.RT - 1) / t.RT, s.nvec);
-    const cpx<R>* tw = twiddles<R>(*P.ctx);
-#define KRY_A(V, I) launch_a<R, V, I>(a, grid, t.threads, t.lds, tw, st)
-    if (t.VPT == 8) {
-        if (s.in_mode == IN_COMPACT) KRY_A(8, IN_COMPACT);
-        else if (s.in_mode == IN_DENSE) KRY_A(8, IN_DENSE);
-        else KRY_A(8, IN_NOISE);
-    } else {
-        if (s.in_mode == IN_COMPACT) KRY_A(16, IN_COMPACT);
-        else if (s.in_mode == IN_DENSE) KRY_A(16, IN_DENSE);
-        else KRY_A(16, IN_NOISE);
+    a.vec0 = vec0;
+    dim3 grid((s.rows_in + t.RT - 1) / t.RT, nvec);
+    const int lg = ilog2(M);
+    Ctx& c = *P.ctx;
+#define KRY_A(LG)                                                                             \
+    case LG:                                                                                  \
+        if (s.in_mode == IN_COMPACT) launch_row_fwd<R, LG, IN_COMPACT>(a, grid, t, c, st);    \
+        else if (s.in_mode == IN_DENSE) launch_row_fwd<R, LG, IN_DENSE>(a, grid, t, c, st);   \
+        else launch_row_fwd<R, LG, IN_NOISE>(a, grid, t, c, st);                              \
+        break;
+    switch (lg) {
+        KRY_SIZES(KRY_A)
+        default: throw Error(KRY_EINVAL, "row transform length out of range");
     }
 #undef KRY_A
 }
 
 template <typename R>
-static void run_stage_b(Problem& P, int N1, int M, int nvec, cpx<R>* Y, int ldY, int64_t Yvs, int rows_in,
+static void run_stage_b(Problem& P, int N1, int M, int vec0, int nvec, cpx<R>* Y, int ldY, int64_t Yvs, int rows_in,
                         int rows_out, const void* lam, int64_t lam_tstride, int vpt, double* spec_out,
                         hipStream_t st) {
-    const int CB = col_batch<R>(N1);
+    const int T = N1 / 8;
     StageBArgs b;
     b.Y = Y;
     b.ldY = ldY;
@@ -440,18 +542,63 @@ static void run_stage_b(Problem& P, int N1, int M, int nvec, cpx<R>* Y, int ldY,
     b.ncols = M + 1;
     b.rows_in = rows_in;
     b.rows_out = rows_out;
-    b.log2N1 = ilog2(N1);
-    b.CB = CB;
+    b.CB = T >= 256 ? 1 : 256 / T;
     b.lam = lam;
     b.lam_tstride = lam_tstride;
     b.vecs_per_theta = vpt;
+    b.vec0 = vec0;
     b.spec_out = spec_out;
-    const int threads = CB * N1 / 8;
-    const size_t lds = (size_t)CB * N1 * sizeof(cpx<R>);
-    dim3 grid((M + 1 + CB - 1) / CB, nvec);
-    const cpx<R>* tw = twiddles<R>(*P.ctx);
-    if (spec_out) launch_b<R, B_SPEC>(b, grid, threads, lds, tw, st);
-    else launch_b<R, B_CONV>(b, grid, threads, lds, tw, st);
+    const int mode = spec_out ? B_SPEC : (2 * rows_in <= N1 ? B_LOW : B_FULL);
+    const int lg = ilog2(N1);
+    Ctx& c = *P.ctx;
+#define KRY_B(LG)                                                                          \
+    case LG + 1:                                                                           \
+        if (mode == B_LOW) launch_col<R, LG + 1, B_LOW>(b, nvec, c, st);                   \
+        else if (mode == B_FULL) launch_col<R, LG + 1, B_FULL>(b, nvec, c, st);            \
+        else launch_col<R, LG + 1, B_SPEC>(b, nvec, c, st);                                \
+        break;
+    switch (lg) {
+        KRY_SIZES(KRY_B)
+        default: throw Error(KRY_EINVAL, "column transform length out of range");
+    }
+#undef KRY_B
+}
+
+template <typename R>
+static void run_stage_c(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R>* Y, int ldY, int64_t Yvs,
+                        hipStream_t st) {
+    const int M = s.N2 / 2;
+    const RowTiling t = row_tiling<R>(M);
+    StageCArgs c;
+    c.Y = Y;
+    c.ldY = ldY;
+    c.Y_vstride = Yvs;
+    c.rows_out = s.rows_out;
+    c.cols_out = s.cols_out;
+    c.RT = t.RT;
+    c.log2RT = ilog2(t.RT);
+    c.mask = P.mask_view();
+    c.vin = s.vin ? (const void*)((const R*)s.vin + vec0 * s.vin_vstride) : nullptr;
+    c.vin_vstride = s.vin_vstride;
+    c.eta = s.eta;
+    c.vecs_per_theta = s.vecs_per_theta;
+    c.vec0 = vec0;
+    c.out = (void*)((R*)s.out + vec0 * s.out_vstride);
+    c.out_vstride = s.out_vstride;
+    c.scale = s.scale;
+    dim3 grid((s.rows_out + t.RT - 1) / t.RT, nvec);
+    const int lg = ilog2(M);
+    Ctx& cx = *P.ctx;
+#define KRY_C(LG)                                                                             \
+    case LG:                                                                                  \
+        if (s.out_mode == OUT_COMPACT) launch_row_inv<R, LG, OUT_COMPACT>(c, grid, t, cx, st);\
+        else launch_row_inv<R, LG, OUT_GRID>(c, grid, t, cx, st);                             \
+        break;
+    switch (lg) {
+        KRY_SIZES(KRY_C)
+        default: throw Error(KRY_EINVAL, "row transform length out of range");
+    }
+#undef KRY_C
 }
 
 template <typename R>
@@ -460,64 +607,45 @@ void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st) {
     KRY_REQUIRE((s.N1 & (s.N1 - 1)) == 0 && (s.N2 & (s.N2 - 1)) == 0, "torus sizes must be powers of two");
     KRY_REQUIRE(s.rows_in <= s.N1 && s.row_len <= s.N2 && s.rows_out <= s.N1 && s.cols_out <= s.N2,
                 "block larger than the torus");
+    KRY_REQUIRE(s.in_mode != IN_COMPACT || 2 * s.row_len <= s.N2, "compact input wider than half the torus");
     if (s.nvec <= 0) return;
     const int M = s.N2 / 2;
     const RowTiling ta = row_tiling<R>(M);
     const int rows_max = s.rows_in > s.rows_out ? s.rows_in : s.rows_out;
     const int ldY = ((rows_max + ta.RT - 1) / ta.RT) * ta.RT;
     const int64_t Yvs = (int64_t)(M + 1) * ldY;
-    P.Y.ensure(*P.ctx, (size_t)Yvs * s.nvec * sizeof(cpx<R>));
+    // vectors go through in chunks that keep the intermediate near 4 GB
+    const int64_t per_vec = Yvs * (int64_t)sizeof(cpx<R>);
+    int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(s.nvec, (int64_t)(4LL << 30) / per_vec));
+    chunk = std::min(chunk, 65535);
+    P.Y.ensure(*P.ctx, (size_t)Yvs * chunk * sizeof(cpx<R>));
     cpx<R>* Y = P.Y.as<cpx<R>>();
-
     StageProfile& pr = P.ctx->prof;
-    std::array<int, 5> rec{};
-    auto mark = [&](int slot) {
-        if (!pr.on) return;
-        if (pr.next == pr.pool.size()) {
-            hipEvent_t e;
-            KRY_HIP(hipEventCreate(&e));
-            pr.pool.push_back(e);
+    for (int v0 = 0; v0 < s.nvec; v0 += chunk) {
+        const int nv = std::min(chunk, s.nvec - v0);
+        std::array<int, 5> rec{};
+        auto mark = [&](int slot) {
+            if (!pr.on) return;
+            if (pr.next == pr.pool.size()) {
+                hipEvent_t e;
+                KRY_HIP(hipEventCreate(&e));
+                pr.pool.push_back(e);
+            }
+            rec[slot] = (int)pr.next;
+            KRY_HIP(hipEventRecord(pr.pool[pr.next++], st));
+        };
+        mark(0);
+        run_stage_a<R>(P, s, v0, nv, Y, ldY, Yvs, st);
+        mark(1);
+        run_stage_b<R>(P, s.N1, M, v0, nv, Y, ldY, Yvs, s.rows_in, s.rows_out, s.lam, s.lam_tstride,
+                       s.vecs_per_theta, nullptr, st);
+        mark(2);
+        run_stage_c<R>(P, s, v0, nv, Y, ldY, Yvs, st);
+        mark(3);
+        if (pr.on) {
+            rec[4] = nv;
+            pr.recs.push_back(rec);
         }
-        rec[slot] = (int)pr.next;
-        KRY_HIP(hipEventRecord(pr.pool[pr.next++], st));
-    };
-    mark(0);
-    run_stage_a<R>(P, s, Y, ldY, Yvs, st);
-    mark(1);
-    run_stage_b<R>(P, s.N1, M, s.nvec, Y, ldY, Yvs, s.rows_in, s.rows_out, s.lam, s.lam_tstride,
-                   s.vecs_per_theta, nullptr, st);
-    mark(2);
-
-    StageCArgs c;
-    c.Y = Y;
-    c.ldY = ldY;
-    c.Y_vstride = Yvs;
-    c.rows_out = s.rows_out;
-    c.cols_out = s.cols_out;
-    c.log2M = ilog2(M);
-    c.RT = ta.RT;
-    c.log2RT = ilog2(ta.RT);
-    c.mask = P.mask_view();
-    c.vin = s.vin;
-    c.vin_vstride = s.vin_vstride;
-    c.eta = s.eta;
-    c.vecs_per_theta = s.vecs_per_theta;
-    c.out = s.out;
-    c.out_vstride = s.out_vstride;
-    c.scale = s.scale;
-    dim3 grid((s.rows_out + ta.RT - 1) / ta.RT, s.nvec);
-    const cpx<R>* tw = twiddles<R>(*P.ctx);
-    if (ta.VPT == 8) {
-        if (s.out_mode == OUT_COMPACT) launch_c<R, 8, OUT_COMPACT>(c, grid, ta.threads, ta.lds, tw, st);
-        else launch_c<R, 8, OUT_GRID>(c, grid, ta.threads, ta.lds, tw, st);
-    } else {
-        if (s.out_mode == OUT_COMPACT) launch_c<R, 16, OUT_COMPACT>(c, grid, ta.threads, ta.lds, tw, st);
-        else launch_c<R, 16, OUT_GRID>(c, grid, ta.threads, ta.lds, tw, st);
-    }
-    mark(3);
-    if (pr.on) {
-        rec[4] = s.nvec;
-        pr.recs.push_back(rec);
     }
 }
 
@@ -603,8 +731,8 @@ void spectrum_device(Problem& P, int N1, int N2, const Matern& th, double* d_lam
     s.in_rstride = N2;
     s.rows_in = N1;
     s.row_len = N2;
-    run_stage_a<double>(P, s, Y, ldY, Yvs, st);
-    run_stage_b<double>(P, N1, M, 1, Y, ldY, Yvs, N1, N1, nullptr, 0, 1, d_lam, st);
+    run_stage_a<double>(P, s, 0, 1, Y, ldY, Yvs, st);
+    run_stage_b<double>(P, N1, M, 0, 1, Y, ldY, Yvs, N1, N1, nullptr, 0, 1, d_lam, st);
     // min / max
     double* part = reinterpret_cast<double*>(reinterpret_cast<char*>(P.spectmp.ptr) + (size_t)Yvs * sizeof(cpx<double>));
     const int64_t n = (int64_t)(M + 1) * N1;

@@ -1,0 +1,163 @@
+// Register-resident power-of-two FFT passes with compile-time plans.
+//
+// A transform of length L = 2^LOG2L is done by T = L/8 threads, each holding
+// 8 values between passes.  The forward plan uses radix-8 passes first and
+// one radix-4 or radix-2 pass last; the inverse plan is the forward plan
+// reversed.  Pass p of radix R and span Ns (product of the earlier radices)
+// is the Stockham autosort step
+//   inputs   x[j + r L/R]                      r = 0..R-1
+//   twiddle  x_r *= W_{Ns R}^{r (j mod Ns)}     (table, conjugate for inverse)
+//   outputs  y[(j div Ns) Ns R + (j mod Ns) + r Ns]
+// for butterflies j = t + b T, b = 0..8/R-1.  Twiddles come from a per-length
+// table holding, for every pass with Ns > 1, the R entries of each j mod Ns
+// contiguously, so a butterfly reads one small block.
+//
+// Because the last forward pass (radix R, Ns = L/R) leaves thread t holding
+// positions j + r L/R and the first inverse pass (radix R, Ns = 1) reads the
+// same positions, a pointwise multiply between them needs no exchange.
+//
+// Values exchanged through LDS use the padded index i + i/8, which spreads
+// the stride-8 accesses of the radix-8 passes over the banks.
+#pragma once
+#include "fft.hpp"
+
+namespace kry {
+
+__device__ __forceinline__ int pad8(int i) { return i + (i >> 3); }
+constexpr int padded(int L) { return L + L / 8; }
+
+template <int LOG2L>
+struct Sched {
+    static constexpr int L = 1 << LOG2L;
+    static constexpr int n8 = LOG2L / 3;
+    static constexpr int rem = LOG2L % 3;
+    static constexpr int npass = n8 + (rem ? 1 : 0);
+    static constexpr int lr(bool inv, int p) {
+        const int q = inv ? npass - 1 - p : p;
+        return q < n8 ? 3 : rem;
+    }
+    static constexpr int lns(bool inv, int p) {
+        int s = 0;
+        for (int i = 0; i < p; ++i) s += lr(inv, i);
+        return s;
+    }
+    static constexpr int tw_size(bool inv, int p) { return p == 0 ? 0 : (1 << lns(inv, p)) << lr(inv, p); }
+    static constexpr int dir_total(bool inv) {
+        int o = 0;
+        for (int i = 0; i < npass; ++i) o += tw_size(inv, i);
+        return o;
+    }
+    static constexpr int tw_off(bool inv, int p) {
+        int o = inv ? dir_total(false) : 0;
+        for (int i = 0; i < p; ++i) o += tw_size(inv, i);
+        return o;
+    }
+    static constexpr int tw_total = dir_total(false) + dir_total(true);
+};
+
+// DFT-8 whose inputs 4..7 are zero (the zero-padded half of a transform).
+template <typename R, bool INV>
+__device__ __forceinline__ void dft8_low(cpx<R>* v) {
+    const cpx<R> x0 = v[0], x1 = v[1], x2 = v[2], x3 = v[3];
+    const cpx<R> e0 = cadd(x0, x2), e2 = csub(x0, x2);
+    const cpx<R> e1 = cadd(x0, rot90<R, INV>(x2)), e3 = csub(x0, rot90<R, INV>(x2));
+    cpx<R> o0 = cadd(x1, x3), o2 = csub(x1, x3);
+    cpx<R> o1 = cadd(x1, rot90<R, INV>(x3)), o3 = csub(x1, rot90<R, INV>(x3));
+    const R h = (R)0.70710678118654752440084436210484903928;
+    const cpx<R> w1 = INV ? cpx<R>{h, h} : cpx<R>{h, -h};
+    const cpx<R> w3 = INV ? cpx<R>{-h, h} : cpx<R>{-h, -h};
+    o1 = cmul(o1, w1);
+    o2 = rot90<R, INV>(o2);
+    o3 = cmul(o3, w3);
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1);
+    v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2);
+    v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3);
+    v[7] = csub(e3, o3);
+}
+
+// Twiddle and butterfly of pass P on the 8 register values of thread t.
+template <typename R, int LOG2L, bool INV, int P, bool LOWHALF = false>
+__device__ __forceinline__ void pass_compute(cpx<R>* v, int t, const cpx<R>* __restrict__ tw) {
+    using S = Sched<LOG2L>;
+    constexpr int LR = S::lr(INV, P);
+    constexpr int RADIX = 1 << LR;
+    constexpr int NS = 1 << S::lns(INV, P);
+    constexpr int T = S::L / 8;
+    constexpr int BPT = 8 / RADIX;
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+        if constexpr (P > 0) {
+            const int j = t + b * T;
+            const int jn = j & (NS - 1);
+            const cpx<R>* w = tw + S::tw_off(INV, P) + jn * RADIX;
+#pragma unroll
+            for (int r = 1; r < RADIX; ++r) v[b * RADIX + r] = cmul(v[b * RADIX + r], w[r]);
+        }
+        if constexpr (LOWHALF && RADIX == 8) dft8_low<R, INV>(v);
+        else dft<R, RADIX, INV>(v + b * RADIX);
+    }
+}
+
+// Inputs of pass P from LDS (transform base `buf`).
+template <typename R, int LOG2L, bool INV, int P>
+__device__ __forceinline__ void pass_read(cpx<R>* v, const cpx<R>* buf, int t) {
+    using S = Sched<LOG2L>;
+    constexpr int RADIX = 1 << S::lr(INV, P);
+    constexpr int T = S::L / 8;
+    constexpr int Q = S::L / RADIX;
+#pragma unroll
+    for (int b = 0; b < 8 / RADIX; ++b) {
+        const int j = t + b * T;
+#pragma unroll
+        for (int r = 0; r < RADIX; ++r) v[b * RADIX + r] = buf[pad8(j + r * Q)];
+    }
+}
+
+// Outputs of pass P to their autosorted LDS positions.
+template <typename R, int LOG2L, bool INV, int P>
+__device__ __forceinline__ void pass_write(const cpx<R>* v, cpx<R>* buf, int t) {
+    using S = Sched<LOG2L>;
+    constexpr int LR = S::lr(INV, P);
+    constexpr int RADIX = 1 << LR;
+    constexpr int LNS = S::lns(INV, P);
+    constexpr int NS = 1 << LNS;
+    constexpr int T = S::L / 8;
+#pragma unroll
+    for (int b = 0; b < 8 / RADIX; ++b) {
+        const int j = t + b * T;
+        const int dst = ((j >> LNS) << (LNS + LR)) + (j & (NS - 1));
+#pragma unroll
+        for (int r = 0; r < RADIX; ++r) buf[pad8(dst + r * NS)] = v[b * RADIX + r];
+    }
+}
+
+// Natural-order position of register value k after the last pass (or before
+// the first pass) of a plan whose boundary radix is 2^LR.
+template <int LOG2L, int LR>
+__device__ __forceinline__ int edge_pos(int t, int k) {
+    constexpr int RADIX = 1 << LR;
+    constexpr int T = (1 << LOG2L) / 8;
+    constexpr int Q = (1 << LOG2L) / RADIX;
+    return t + (k / RADIX) * T + (k % RADIX) * Q;
+}
+
+// Passes PB..PE-1 entirely through LDS (read, sync, compute, write, sync).
+template <typename R, int LOG2L, bool INV, int P, int PE>
+struct LdsPasses {
+    __device__ __forceinline__ static void run(cpx<R>* v, cpx<R>* buf, int t, const cpx<R>* __restrict__ tw) {
+        if constexpr (P < PE) {
+            pass_read<R, LOG2L, INV, P>(v, buf, t);
+            __syncthreads();
+            pass_compute<R, LOG2L, INV, P>(v, t, tw);
+            pass_write<R, LOG2L, INV, P>(v, buf, t);
+            __syncthreads();
+            LdsPasses<R, LOG2L, INV, P + 1, PE>::run(v, buf, t, tw);
+        }
+    }
+};
+
+}  // namespace kry

@@ -49,6 +49,8 @@ struct Ctx {
     uint64_t allocated = 0;  // bytes currently held through dev_alloc
     cpx<double>* tw64 = nullptr;
     cpx<float>* tw32 = nullptr;
+    void* plan64[14] = {};  // per-length pass twiddle tables (index log2 length)
+    void* plan32[14] = {};
 };
 
 void* dev_alloc(Ctx& c, size_t bytes);
