@@ -250,6 +250,50 @@ kry_status kry_sample(kry_problem* prob, const kry_matern* theta, int32_t N1, in
                       uint64_t seed, int32_t first_stream, int32_t count, double* out,
                       double* minmax);
 
+/* ---- serving ----------------------------------------------------------------
+ * A server runs likelihood and kriging requests on device-resident problems
+ * with continuous batching: `slots` worker streams take requests as they
+ * arrive, admitting one when a slot is free and the estimated device
+ * footprint of all requests in flight stays within hbm_budget_bytes (0 = no
+ * limit); queued likelihood requests on the same problem with identical
+ * options are evaluated together (up to max_batch).  A request's result is
+ * the same alone and in any mix.  Problems must outlive their requests and
+ * must not be modified (kry_problem_set_data) while requests on them are
+ * pending; stage timing (kry_profile_begin) must be off while a server runs. */
+typedef enum { KRY_REQ_LOGLIK = 0, KRY_REQ_KRIGE = 1 } kry_request_kind;
+typedef struct {
+    int32_t kind;            /* kry_request_kind                                   */
+    kry_problem* prob;
+    kry_matern theta;
+    kry_opts opts;
+    const int64_t* targets;  /* KRIGE: target cell ids (copied at submit)          */
+    int64_t ntargets;
+    int32_t variances;       /* KRIGE: 1 = also exact var_x / var_y                */
+    double* mean_x;          /* KRIGE outputs, ntargets each, caller-owned and     */
+    double* var_x;           /* kept alive until the request is done               */
+    double* var_y;
+} kry_request;
+typedef struct {
+    int32_t status;          /* kry_status of the request (KRY_ENOCONV: outputs   */
+                             /* written, CG stopped at cg_maxit)                   */
+    int32_t batch;           /* requests evaluated together with this one         */
+    kry_loglik_result loglik;
+    double t_submit, t_start, t_end;  /* seconds since the server was created  */
+} kry_response;
+/* slots in [1, 16]; max_queue bounds pending (not yet started) requests. */
+kry_status kry_server_create(kry_ctx* ctx, int32_t slots, uint64_t hbm_budget_bytes, int32_t max_batch,
+                             int32_t max_queue, kry_server** out);
+/* Non-blocking: KRY_EBUSY when the queue is full, KRY_ENOMEM when the
+ * request alone exceeds the budget, KRY_EINVAL for invalid requests. */
+kry_status kry_server_submit(kry_server* srv, const kry_request* req, uint64_t* ticket);
+/* done = 1 and *out filled once the request has finished (the ticket is then
+ * released); done = 0 otherwise. */
+kry_status kry_server_poll(kry_server* srv, uint64_t ticket, kry_response* out, int32_t* done);
+/* Block until the request has finished. */
+kry_status kry_server_wait(kry_server* srv, uint64_t ticket, kry_response* out);
+/* Finishes every queued request, then stops the workers. */
+void kry_server_destroy(kry_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libkryging.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["conv.hip", "krylov.hip", "api.hip"]
+SOURCES = ["conv.hip", "krylov.hip", "api.hip", "server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -20,6 +20,8 @@ FLAGS = [
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
+    # no implicit contraction: results must not depend on batch composition
+    "-ffp-contract=off",
     "-I" + os.path.join(HERE, "..", "include"),
 ]
 

@@ -15,13 +15,6 @@
 
 using namespace kry;
 
-struct kry_ctx {
-    Ctx c;
-};
-struct kry_problem {
-    Problem P;
-};
-
 static thread_local std::string g_last_error;
 
 template <typename F>
@@ -45,21 +38,28 @@ namespace kry {
 
 void* dev_alloc(Ctx& c, size_t bytes) {
     if (bytes == 0) bytes = 256;
-    if (c.budget && c.allocated + bytes > c.budget)
-        throw Error(KRY_ENOMEM, "request of " + std::to_string(bytes) + " bytes exceeds the HBM budget (" +
-                                    std::to_string(c.allocated) + " of " + std::to_string(c.budget) + " in use)");
+    {
+        std::lock_guard<std::mutex> g(c.alloc_mu);
+        if (c.budget && c.allocated + bytes > c.budget)
+            throw Error(KRY_ENOMEM, "request of " + std::to_string(bytes) + " bytes exceeds the HBM budget (" +
+                                        std::to_string(c.allocated) + " of " + std::to_string(c.budget) +
+                                        " in use)");
+        c.allocated += bytes;
+    }
     void* p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
+        std::lock_guard<std::mutex> g(c.alloc_mu);
+        c.allocated -= bytes;
         throw Error(KRY_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
     }
-    c.allocated += bytes;
     return p;
 }
 
 void dev_free(Ctx& c, void* p, size_t bytes) {
     if (!p) return;
     (void)hipFree(p);
+    std::lock_guard<std::mutex> g(c.alloc_mu);
     c.allocated -= std::min<uint64_t>(c.allocated, bytes);
 }
 
@@ -91,6 +91,9 @@ void with_arena(Problem& P, F&& layout) {
     layout(a);
 }
 
+}  // namespace
+
+namespace kry {
 void check_theta(const kry_matern* t) {
     KRY_REQUIRE(t != nullptr, "theta is NULL");
     const double v[6] = {t->sigma2, t->tau2, t->range, t->nu, t->aniso_ratio, t->aniso_angle};
@@ -100,10 +103,6 @@ void check_theta(const kry_matern* t) {
     KRY_REQUIRE(t->range > 0, "range must be > 0");
     KRY_REQUIRE(t->nu > 0 && t->nu <= 20, "nu must be in (0, 20]");
     KRY_REQUIRE(t->aniso_ratio >= 1, "aniso_ratio must be >= 1");
-}
-
-Matern to_matern(const kry_matern* t) {
-    return Matern{t->sigma2, t->tau2, t->range, t->nu, t->aniso_ratio, t->aniso_angle};
 }
 
 void check_opts(const kry_opts* o) {
@@ -121,6 +120,13 @@ void check_opts(const kry_opts* o) {
 
 int nprobes_of(const kry_opts* o) {
     return o->probe_kind == KRY_PROBE_COLOURED ? o->colour_period * o->colour_period : o->num_probes;
+}
+}  // namespace kry
+
+namespace {
+
+Matern to_matern(const kry_matern* t) {
+    return Matern{t->sigma2, t->tau2, t->range, t->nu, t->aniso_ratio, t->aniso_angle};
 }
 
 int pow2_at_least(int m) {
@@ -633,6 +639,16 @@ void gengk_device(Problem& P, const Matern& th, const kry_opts* o, GkOut& G, dou
     }
 }
 
+bool any_not_converged(const kry_loglik_result* r, int count, const kry_opts* o) {
+    if (o->solver != KRY_SOLVER_CG) return false;
+    for (int t = 0; t < count; ++t)
+        if (r[t].cg_relres > o->cg_rtol) return true;
+    return false;
+}
+
+}  // namespace
+
+namespace kry {
 // log-likelihood for `count` parameter points that share nu and anisotropy
 // handling (each with its own spectrum) on one problem.
 void loglik_points(Problem& P, const kry_matern* thetas, int count, const kry_opts* o, kry_loglik_result* out,
@@ -655,13 +671,8 @@ void loglik_points(Problem& P, const kry_matern* thetas, int count, const kry_op
                        fp32 ? P.spec_multi32.as<float>() + (size_t)t * nspec : nullptr, st);
     }
     // eta and the data for every point live in a small device buffer
-    DevBuf etab;
+    DevBuf& etab = P.tmp1;
     etab.ensure(C, count * sizeof(double) + (size_t)count * P.p * 2 * sizeof(double) + 512);
-    struct Free {
-        Ctx& c;
-        DevBuf& b;
-        ~Free() { b.release(c); }
-    } fr{C, etab};
     double* d_eta = etab.as<double>();
     double* Y = reinterpret_cast<double*>(etab.as<char>() + 256);
     double* X = Y + (size_t)count * P.p;
@@ -713,15 +724,7 @@ void loglik_points(Problem& P, const kry_matern* thetas, int count, const kry_op
         r.cg_relres = relres[t];
     }
 }
-
-bool any_not_converged(const kry_loglik_result* r, int count, const kry_opts* o) {
-    if (o->solver != KRY_SOLVER_CG) return false;
-    for (int t = 0; t < count; ++t)
-        if (r[t].cg_relres > o->cg_rtol) return true;
-    return false;
-}
-
-}  // namespace
+}  // namespace kry
 
 // ===========================================================================
 // ABI (C linkage comes from the declarations in kryging.h)
@@ -854,7 +857,7 @@ static void upload_data(Problem& P, const double* y) {
     std::vector<double> yc(P.p, 0.0);
     if (y) {
         for (int64_t i = 0; i < P.p; ++i) {
-            const double v = y[P.h_cell[i]];
+            const double v = y[(*P.h_cell)[i]];
             KRY_REQUIRE(std::isfinite(v), "y has a non-finite value at an observed cell");
             yc[i] = v;
         }
@@ -895,18 +898,23 @@ kry_status kry_problem_create(kry_ctx* ctx, const kry_grid* grid, const uint8_t*
             P.words_per_row = (n2 + 31) / 32;
             const int64_t nw = (int64_t)n1 * P.words_per_row;
             std::vector<uint32_t> bits(nw, 0u), base(nw, 0u);
-            P.h_cell.resize(p);
-            P.h_mask.assign(mask, mask + n);
+            auto hc = std::make_shared<std::vector<int64_t>>(p);
+            auto hm = std::make_shared<std::vector<uint8_t>>(n);
             std::vector<int32_t> cell(p);
             int64_t c = 0;
             for (int i = 0; i < n1; ++i)
-                for (int j = 0; j < n2; ++j)
-                    if (mask[(int64_t)i * n2 + j]) {
+                for (int j = 0; j < n2; ++j) {
+                    const int64_t id = (int64_t)i * n2 + j;
+                    (*hm)[id] = mask[id] ? 1 : 0;
+                    if (mask[id]) {
                         bits[(int64_t)i * P.words_per_row + (j >> 5)] |= 1u << (j & 31);
-                        P.h_cell[c] = (int64_t)i * n2 + j;
-                        cell[c] = (int32_t)((int64_t)i * n2 + j);
+                        (*hc)[c] = id;
+                        cell[c] = (int32_t)id;
                         ++c;
                     }
+                }
+            P.h_cell = hc;
+            P.h_mask = hm;
             uint32_t acc = 0;
             for (int64_t w = 0; w < nw; ++w) {
                 base[w] = acc;
@@ -934,7 +942,7 @@ kry_status kry_problem_set_data(kry_problem* prob, const double* y) {
         KRY_REQUIRE(prob && y, "NULL argument");
         Problem& P = prob->P;
         for (int64_t i = 0; i < P.p; ++i)
-            KRY_REQUIRE(std::isfinite(y[P.h_cell[i]]), "y has a non-finite value at an observed cell");
+            KRY_REQUIRE(std::isfinite(y[(*P.h_cell)[i]]), "y has a non-finite value at an observed cell");
         bind(*P.ctx);
         upload_data(P, y);
     });
@@ -956,9 +964,9 @@ void kry_problem_destroy(kry_problem* prob) {
         Ctx& c = *P.ctx;
         (void)hipSetDevice(c.device);
         (void)hipStreamSynchronize(c.stream);
-        for (DevBuf* b : {&P.bits, &P.base, &P.cell, &P.y64, &P.y32, &P.Y, &P.lagtmp, &P.spectmp, &P.spec_multi64,
-                          &P.spec_multi32, &P.kws, &P.scal, &P.spec.s64, &P.spec.s32})
+        for (DevBuf* b : {&P.bits, &P.base, &P.cell, &P.y64, &P.y32})
             b->release(c);
+        P.release_work();
     }
     delete prob;
 }
@@ -1354,13 +1362,8 @@ kry_status kry_loglik(kry_problem* prob, const kry_matern* theta, const kry_opts
 static void sample_fields(Problem& P, const Matern& th, int N1, int N2, uint64_t seed, int first_stream, int count,
                           double* d_out, double* lo, double* hi, hipStream_t st) {
     const int64_t nspec = (int64_t)(N2 / 2 + 1) * N1;
-    DevBuf sp;
+    DevBuf& sp = P.tmp4;
     sp.ensure(*P.ctx, nspec * sizeof(double));
-    struct Free {
-        Ctx& c;
-        DevBuf& b;
-        ~Free() { b.release(c); }
-    } fr{*P.ctx, sp};
     spectrum_device(P, N1, N2, th, sp.as<double>(), lo, hi, st);
     if (*lo < -1e-10 * *hi)
         throw Error(KRY_ENOTPSD, "embedding spectrum min/max = " + std::to_string(*lo / *hi) + " on a " +
@@ -1392,12 +1395,7 @@ static void sample_fields(Problem& P, const Matern& th, int N1, int N2, uint64_t
 static void psd_torus(Problem& P, const Matern& th, int* N1, int* N2, hipStream_t st) {
     int a = P.N1, b = P.N2;
     const int64_t cap = 8192;
-    DevBuf sp;
-    struct Free {
-        Ctx& c;
-        DevBuf& b;
-        ~Free() { b.release(c); }
-    } fr{*P.ctx, sp};
+    DevBuf& sp = P.tmp4;
     while (true) {
         sp.ensure(*P.ctx, (size_t)(b / 2 + 1) * a * sizeof(double));
         double lo, hi;
@@ -1457,9 +1455,105 @@ kry_status kry_sample(kry_problem* prob, const kry_matern* theta, int32_t N1, in
 }
 
 // ---- kriging --------------------------------------------------------------------------------
+void kry::krige_impl(Problem& P, const kry_matern* theta, const kry_opts* opts, const std::vector<int64_t>& tg,
+                     double* mean_x, double* var_x, double* var_y, int32_t bootstrap_B, bool* noconv,
+                     hipStream_t st) {
+    const int64_t n = (int64_t)P.n1 * P.n2;
+    const int64_t nt = (int64_t)tg.size();
+    if (nt == 0) return;
+    const Matern th = to_matern(theta);
+    const double eta = th.tau2 / th.sigma2;
+    const double tau = std::sqrt(th.tau2);
+    Spectrum& S = problem_spectrum(P, th, st);
+    // device scratch: eta, targets, w, full mean, target values
+    const int64_t p = P.p;
+    DevBuf& io = P.tmp1;
+    io.ensure(*P.ctx, 512 + nt * sizeof(int64_t) + (size_t)p * 2 * sizeof(double) + (size_t)n * sizeof(double) +
+                          (size_t)nt * 3 * sizeof(double) + 4096);
+    Arena a;
+    a.base = io.as<char>();
+    double* d_eta = a.take<double>(1);
+    int64_t* d_tg = a.take<int64_t>(nt);
+    double* d_w = a.take<double>(p);
+    double* d_full = a.take<double>(n);
+    double* d_t1 = a.take<double>(nt);
+    double* d_t2 = a.take<double>(nt);
+    KRY_HIP(hipMemcpyAsync(d_eta, &eta, sizeof(double), hipMemcpyHostToDevice, st));
+    KRY_HIP(hipMemcpyAsync(d_tg, tg.data(), nt * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    // mean: w = K^{-1} y, xhat = Sigma A^T w
+    SolveStats ss;
+    solve_device(P, opts->precision, S.s64.ptr, S.s32.ptr, 0, 1, d_eta, 1, P.y64.as<double>(), d_w, opts->cg_rtol,
+                 opts->cg_maxit, ss, st);
+    if (ss.relres[0] > opts->cg_rtol) *noconv = true;
+    cov_full<double>(P, S.s64.ptr, d_w, d_full, 1, st);
+    hipLaunchKernelGGL(k_pick, grid1(nt), dim3(256), 0, st, d_full, d_tg, nt, d_t1);
+    KRY_HIP(hipGetLastError());
+    KRY_HIP(hipMemcpyAsync(mean_x, d_t1, nt * sizeof(double), hipMemcpyDeviceToHost, st));
+    KRY_HIP(hipStreamSynchronize(st));
+    if (!var_x && !var_y) return;
+    if (bootstrap_B == 0) {
+        // exact: multi-RHS CG on the cross-correlation columns, in chunks
+        P.lagtmp.ensure(*P.ctx, (size_t)P.N1 * P.N2 * sizeof(double));
+        lag_grid_device(*P.ctx, P.N1, P.N2, P.dx1, P.dx2, th, P.lagtmp.as<double>(), st);
+        const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(256, (int64_t)(2e9 / (8.0 * p * 6))));
+        DevBuf& cb = P.tmp2;
+        cb.ensure(*P.ctx, (size_t)chunk * p * 2 * sizeof(double) + (size_t)chunk * 257 * sizeof(double) + 1024);
+        double* Cc = cb.as<double>();
+        double* Wc = Cc + (size_t)chunk * p;
+        double* part = Wc + (size_t)chunk * p;
+        double* dots = part + (size_t)chunk * 256;
+        std::vector<double> q(chunk);
+        for (int64_t t0 = 0; t0 < nt; t0 += chunk) {
+            const int c = (int)std::min<int64_t>(chunk, nt - t0);
+            hipLaunchKernelGGL(k_cross_corr, grid1(p, c), dim3(256), 0, st, P.lagtmp.as<double>(), P.N1, P.N2,
+                               P.cell.as<int32_t>(), p, P.n2, d_tg + t0, Cc);
+            KRY_HIP(hipGetLastError());
+            SolveStats s2;
+            solve_device(P, opts->precision, S.s64.ptr, S.s32.ptr, 0, c, d_eta, c, Cc, Wc, opts->cg_rtol,
+                         opts->cg_maxit, s2, st);
+            for (int v = 0; v < c; ++v)
+                if (s2.relres[v] > opts->cg_rtol) *noconv = true;
+            dot_batched<double>(Cc, p, Wc, p, p, c, part, dots, st);
+            KRY_HIP(hipMemcpyAsync(q.data(), dots, c * sizeof(double), hipMemcpyDeviceToHost, st));
+            KRY_HIP(hipStreamSynchronize(st));
+            for (int v = 0; v < c; ++v) {
+                const double vx = th.sigma2 * (1.0 - q[v]);
+                if (var_x) var_x[t0 + v] = vx;
+                if (var_y) var_y[t0 + v] = vx + th.tau2;
+            }
+        }
+        return;
+    }
+    // parametric bootstrap (eq. bootstrap_uq)
+    int N1s, N2s;
+    psd_torus(P, th, &N1s, &N2s, st);
+    const int B = bootstrap_B;
+    DevBuf& bb = P.tmp3;
+    bb.ensure(*P.ctx, (size_t)B * n * 2 * sizeof(double) + (size_t)B * p * 2 * sizeof(double) + 1024);
+    double* F = bb.as<double>();
+    double* XH = F + (size_t)B * n;
+    double* YB = XH + (size_t)B * n;
+    double* WB = YB + (size_t)B * p;
+    double lo, hi;
+    sample_fields(P, th, N1s, N2s, opts->seed, 0, B, F, &lo, &hi, st);
+    hipLaunchKernelGGL(k_boot_obs, grid1(p, B), dim3(256), 0, st, F, n, P.cell.as<int32_t>(), p, tau, opts->seed, YB);
+    KRY_HIP(hipGetLastError());
+    SolveStats s3;
+    solve_device(P, opts->precision, S.s64.ptr, S.s32.ptr, 0, B, d_eta, B, YB, WB, opts->cg_rtol, opts->cg_maxit, s3,
+                 st);
+    for (int v = 0; v < B; ++v)
+        if (s3.relres[v] > opts->cg_rtol) *noconv = true;
+    cov_full<double>(P, S.s64.ptr, WB, XH, B, st);
+    hipLaunchKernelGGL(k_boot_acc, grid1(nt), dim3(256), 0, st, F, XH, n, B, d_tg, nt, tau, opts->seed, d_t1, d_t2);
+    KRY_HIP(hipGetLastError());
+    if (var_x) KRY_HIP(hipMemcpyAsync(var_x, d_t1, nt * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (var_y) KRY_HIP(hipMemcpyAsync(var_y, d_t2, nt * sizeof(double), hipMemcpyDeviceToHost, st));
+    KRY_HIP(hipStreamSynchronize(st));
+}
+
 kry_status kry_krige(kry_problem* prob, const kry_matern* theta, const kry_opts* opts,
-                                const int64_t* targets, int64_t ntargets, double* mean_x, double* var_x, double* var_y,
-                                int32_t bootstrap_B) {
+                     const int64_t* targets, int64_t ntargets, double* mean_x, double* var_x, double* var_y,
+                     int32_t bootstrap_B) {
     bool noconv = false;
     kry_status s = guard([&] {
         KRY_REQUIRE(prob && mean_x, "NULL argument");
@@ -1475,116 +1569,11 @@ kry_status kry_krige(kry_problem* prob, const kry_matern* theta, const kry_opts*
             for (int64_t t : tg) KRY_REQUIRE(t >= 0 && t < n, "target cell id out of range");
         } else {
             for (int64_t c = 0; c < n; ++c)
-                if (!P.h_mask[c]) tg.push_back(c);
+                if (!(*P.h_mask)[c]) tg.push_back(c);
             KRY_REQUIRE(ntargets == (int64_t)tg.size(), "ntargets must equal the number of unobserved cells");
         }
-        const int64_t nt = (int64_t)tg.size();
-        if (nt == 0) return;
         bind(*P.ctx);
-        hipStream_t st = P.ctx->stream;
-        const Matern th = to_matern(theta);
-        const double eta = th.tau2 / th.sigma2;
-        const double tau = std::sqrt(th.tau2);
-        Spectrum& S = problem_spectrum(P, th, st);
-        // device scratch: eta, targets, w, full mean, target values
-        const int64_t p = P.p;
-        DevBuf io;
-        io.ensure(*P.ctx, 512 + nt * sizeof(int64_t) + (size_t)p * 2 * sizeof(double) + (size_t)n * sizeof(double) +
-                              (size_t)nt * 3 * sizeof(double) + 4096);
-        struct Free {
-            Ctx& c;
-            DevBuf& b;
-            ~Free() { b.release(c); }
-        } fr{*P.ctx, io};
-        Arena a;
-        a.base = io.as<char>();
-        double* d_eta = a.take<double>(1);
-        int64_t* d_tg = a.take<int64_t>(nt);
-        double* d_w = a.take<double>(p);
-        double* d_full = a.take<double>(n);
-        double* d_t1 = a.take<double>(nt);
-        double* d_t2 = a.take<double>(nt);
-        KRY_HIP(hipMemcpyAsync(d_eta, &eta, sizeof(double), hipMemcpyHostToDevice, st));
-        KRY_HIP(hipMemcpyAsync(d_tg, tg.data(), nt * sizeof(int64_t), hipMemcpyHostToDevice, st));
-        // mean: w = K^{-1} y, xhat = Sigma A^T w
-        SolveStats ss;
-        solve_device(P, opts->precision, S.s64.ptr, S.s32.ptr, 0, 1, d_eta, 1, P.y64.as<double>(), d_w, opts->cg_rtol,
-                     opts->cg_maxit, ss, st);
-        if (ss.relres[0] > opts->cg_rtol) noconv = true;
-        cov_full<double>(P, S.s64.ptr, d_w, d_full, 1, st);
-        hipLaunchKernelGGL(k_pick, grid1(nt), dim3(256), 0, st, d_full, d_tg, nt, d_t1);
-        KRY_HIP(hipGetLastError());
-        KRY_HIP(hipMemcpyAsync(mean_x, d_t1, nt * sizeof(double), hipMemcpyDeviceToHost, st));
-        KRY_HIP(hipStreamSynchronize(st));
-        if (!var_x && !var_y) return;
-        if (bootstrap_B == 0) {
-            // exact: multi-RHS CG on the cross-correlation columns, in chunks
-            P.lagtmp.ensure(*P.ctx, (size_t)P.N1 * P.N2 * sizeof(double));
-            lag_grid_device(*P.ctx, P.N1, P.N2, P.dx1, P.dx2, th, P.lagtmp.as<double>(), st);
-            const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(256, (int64_t)(2e9 / (8.0 * p * 6))));
-            DevBuf cb;
-            cb.ensure(*P.ctx, (size_t)chunk * p * 2 * sizeof(double) + (size_t)chunk * 257 * sizeof(double) + 1024);
-            struct Free2 {
-                Ctx& c;
-                DevBuf& b;
-                ~Free2() { b.release(c); }
-            } fr2{*P.ctx, cb};
-            double* Cc = cb.as<double>();
-            double* Wc = Cc + (size_t)chunk * p;
-            double* part = Wc + (size_t)chunk * p;
-            double* dots = part + (size_t)chunk * 256;
-            std::vector<double> q(chunk);
-            for (int64_t t0 = 0; t0 < nt; t0 += chunk) {
-                const int c = (int)std::min<int64_t>(chunk, nt - t0);
-                hipLaunchKernelGGL(k_cross_corr, grid1(p, c), dim3(256), 0, st, P.lagtmp.as<double>(), P.N1, P.N2,
-                                   P.cell.as<int32_t>(), p, P.n2, d_tg + t0, Cc);
-                KRY_HIP(hipGetLastError());
-                SolveStats s2;
-                solve_device(P, opts->precision, S.s64.ptr, S.s32.ptr, 0, c, d_eta, c, Cc, Wc, opts->cg_rtol,
-                             opts->cg_maxit, s2, st);
-                for (int v = 0; v < c; ++v)
-                    if (s2.relres[v] > opts->cg_rtol) noconv = true;
-                dot_batched<double>(Cc, p, Wc, p, p, c, part, dots, st);
-                KRY_HIP(hipMemcpyAsync(q.data(), dots, c * sizeof(double), hipMemcpyDeviceToHost, st));
-                KRY_HIP(hipStreamSynchronize(st));
-                for (int v = 0; v < c; ++v) {
-                    const double vx = th.sigma2 * (1.0 - q[v]);
-                    if (var_x) var_x[t0 + v] = vx;
-                    if (var_y) var_y[t0 + v] = vx + th.tau2;
-                }
-            }
-            return;
-        }
-        // parametric bootstrap (eq. bootstrap_uq)
-        int N1s, N2s;
-        psd_torus(P, th, &N1s, &N2s, st);
-        const int B = bootstrap_B;
-        DevBuf bb;
-        bb.ensure(*P.ctx, (size_t)B * n * 2 * sizeof(double) + (size_t)B * p * 2 * sizeof(double) + 1024);
-        struct Free3 {
-            Ctx& c;
-            DevBuf& b;
-            ~Free3() { b.release(c); }
-        } fr3{*P.ctx, bb};
-        double* F = bb.as<double>();
-        double* XH = F + (size_t)B * n;
-        double* YB = XH + (size_t)B * n;
-        double* WB = YB + (size_t)B * p;
-        double lo, hi;
-        sample_fields(P, th, N1s, N2s, opts->seed, 0, B, F, &lo, &hi, st);
-        hipLaunchKernelGGL(k_boot_obs, grid1(p, B), dim3(256), 0, st, F, n, P.cell.as<int32_t>(), p, tau, opts->seed, YB);
-        KRY_HIP(hipGetLastError());
-        SolveStats s3;
-        solve_device(P, opts->precision, S.s64.ptr, S.s32.ptr, 0, B, d_eta, B, YB, WB, opts->cg_rtol, opts->cg_maxit, s3,
-                     st);
-        for (int v = 0; v < B; ++v)
-            if (s3.relres[v] > opts->cg_rtol) noconv = true;
-        cov_full<double>(P, S.s64.ptr, WB, XH, B, st);
-        hipLaunchKernelGGL(k_boot_acc, grid1(nt), dim3(256), 0, st, F, XH, n, B, d_tg, nt, tau, opts->seed, d_t1, d_t2);
-        KRY_HIP(hipGetLastError());
-        if (var_x) KRY_HIP(hipMemcpyAsync(var_x, d_t1, nt * sizeof(double), hipMemcpyDeviceToHost, st));
-        if (var_y) KRY_HIP(hipMemcpyAsync(var_y, d_t2, nt * sizeof(double), hipMemcpyDeviceToHost, st));
-        KRY_HIP(hipStreamSynchronize(st));
+        krige_impl(P, theta, opts, tg, mean_x, var_x, var_y, bootstrap_B, &noconv, P.ctx->stream);
     });
     if (s == KRY_OK && noconv) {
         g_last_error = "CG reached cg_maxit before cg_rtol";

@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(1024) k_row_fwd(StageAArgs a, const cpx<R>* __
     pass_compute<R, LOG2M, false, 0, LOW>(v, t, twp);
     pass_write<R, LOG2M, false, 0>(v, buf, t);
     __syncthreads();
-    LdsPasses<R, LOG2M, false, 1, S::npass>::run(v, buf, t, twp);
+    LdsPasses<R, LOG2M, false, 1, S::npass>::run(v, buf, 0, t, twp);
 
     cpx<R>* Y = reinterpret_cast<cpx<R>*>(a.Y) + vec * a.Y_vstride;
     const int nout = a.RT * (M + 1);
@@ -198,6 +198,7 @@ struct StageBArgs {
     void* Y;
     int ldY;
     int64_t Y_vstride;
+    int nvec;
     int ncols;
     int rows_in, rows_out;
     int CB;
@@ -210,8 +211,10 @@ struct StageBArgs {
 
 // Stage B: per column of the half spectrum, forward FFT of length L (rows
 // beyond rows_in are zero), multiply by lam in registers, inverse FFT, keep
-// rows_out rows.  B_SPEC: forward only, real part to spec_out.
-template <typename R, int LOG2L, int MODE>
+// rows_out rows.  Each thread carries the same column of V consecutive
+// vectors, sharing twiddle and spectrum loads.  B_SPEC: forward only, real
+// part to spec_out.
+template <typename R, int LOG2L, int MODE, int V>
 __global__ void __launch_bounds__(1024) k_col(StageBArgs a, const cpx<R>* __restrict__ twp) {
     using S = Sched<LOG2L>;
     constexpr int L = S::L, T = L / 8, PL = padded(L);
@@ -223,23 +226,30 @@ __global__ void __launch_bounds__(1024) k_col(StageBArgs a, const cpx<R>* __rest
     const int cl = tid / T, t = tid % T;
     const int col = blockIdx.x * a.CB + cl;
     const bool valid = col < a.ncols;
-    const int vec = blockIdx.y;
-    cpx<R>* buf = lds + cl * PL;
-    cpx<R>* Y = reinterpret_cast<cpx<R>*>(a.Y) + vec * a.Y_vstride + (int64_t)(valid ? col : 0) * a.ldY;
-    cpx<R> v[8];
+    const int vbase = blockIdx.y * V;  // first vector of this workgroup (within the launch)
+    cpx<R>* buf = lds + cl * V * PL;
+    cpx<R>* Ycol = reinterpret_cast<cpx<R>*>(a.Y) + (int64_t)(valid ? col : 0) * a.ldY;
+    cpx<R> v[V * 8];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const int idx = t + r * T;
-        v[r] = cpx<R>{(R)0, (R)0};
-        if (LOW && r >= 4) continue;
-        if (valid && idx < a.rows_in) v[r] = Y[idx];
+    for (int u = 0; u < V; ++u) {
+        const bool vu = valid && (vbase + u < a.nvec);
+        const cpx<R>* Yv = Ycol + (vbase + u) * a.Y_vstride;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int idx = t + r * T;
+            v[u * 8 + r] = cpx<R>{(R)0, (R)0};
+            if (LOW && r >= 4) continue;
+            if (vu && idx < a.rows_in) v[u * 8 + r] = Yv[idx];
+        }
     }
-    pass_compute<R, LOG2L, false, 0, LOW>(v, t, twp);
-    pass_write<R, LOG2L, false, 0>(v, buf, t);
+    pass_compute<R, LOG2L, false, 0, LOW, V>(v, t, twp);
+#pragma unroll
+    for (int u = 0; u < V; ++u) pass_write<R, LOG2L, false, 0>(v + u * 8, buf + u * PL, t);
     __syncthreads();
-    LdsPasses<R, LOG2L, false, 1, S::npass - 1>::run(v, buf, t, twp);
-    pass_read<R, LOG2L, false, S::npass - 1>(v, buf, t);
-    pass_compute<R, LOG2L, false, S::npass - 1>(v, t, twp);
+    LdsPasses<R, LOG2L, false, 1, S::npass - 1, V>::run(v, buf, PL, t, twp);
+#pragma unroll
+    for (int u = 0; u < V; ++u) pass_read<R, LOG2L, false, S::npass - 1>(v + u * 8, buf + u * PL, t);
+    pass_compute<R, LOG2L, false, S::npass - 1, false, V>(v, t, twp);
     if constexpr (MODE == B_SPEC) {
         if (valid) {
 #pragma unroll
@@ -247,22 +257,33 @@ __global__ void __launch_bounds__(1024) k_col(StageBArgs a, const cpx<R>* __rest
         }
         return;
     } else {
-        const R* lam = reinterpret_cast<const R*>(a.lam) +
-                       (int64_t)((a.vec0 + vec) / a.vecs_per_theta) * a.lam_tstride + (int64_t)(valid ? col : 0) * L;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = cscale(v[k], lam[edge_pos<LOG2L, LRF>(t, k)]);
+        for (int u = 0; u < V; ++u) {
+            // an unused slot (vbase + u >= nvec) reads the last vector's spectrum, never past the end
+            const int vu = min(vbase + u, a.nvec - 1);
+            const R* lam = reinterpret_cast<const R*>(a.lam) +
+                           (int64_t)((a.vec0 + vu) / a.vecs_per_theta) * a.lam_tstride +
+                           (int64_t)(valid ? col : 0) * L;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[u * 8 + k] = cscale(v[u * 8 + k], lam[edge_pos<LOG2L, LRF>(t, k)]);
+        }
         __syncthreads();
-        pass_compute<R, LOG2L, true, 0>(v, t, twp);
-        pass_write<R, LOG2L, true, 0>(v, buf, t);
+        pass_compute<R, LOG2L, true, 0, false, V>(v, t, twp);
+#pragma unroll
+        for (int u = 0; u < V; ++u) pass_write<R, LOG2L, true, 0>(v + u * 8, buf + u * PL, t);
         __syncthreads();
-        LdsPasses<R, LOG2L, true, 1, S::npass - 1>::run(v, buf, t, twp);
-        pass_read<R, LOG2L, true, S::npass - 1>(v, buf, t);
-        pass_compute<R, LOG2L, true, S::npass - 1>(v, t, twp);
-        if (valid) {
+        LdsPasses<R, LOG2L, true, 1, S::npass - 1, V>::run(v, buf, PL, t, twp);
+#pragma unroll
+        for (int u = 0; u < V; ++u) pass_read<R, LOG2L, true, S::npass - 1>(v + u * 8, buf + u * PL, t);
+        pass_compute<R, LOG2L, true, S::npass - 1, false, V>(v, t, twp);
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            if (!(valid && vbase + u < a.nvec)) continue;
+            cpx<R>* Yv = Ycol + (vbase + u) * a.Y_vstride;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const int idx = t + k * T;
-                if (idx < a.rows_out) Y[idx] = v[k];
+                if (idx < a.rows_out) Yv[idx] = v[u * 8 + k];
             }
         }
     }
@@ -332,7 +353,7 @@ __global__ void __launch_bounds__(1024) k_row_inv(StageCArgs a, const cpx<R>* __
     const int row = row0 + rr;
     cpx<R>* buf = lds + rr * PM;
     cpx<R> v[8];
-    LdsPasses<R, LOG2M, true, 0, S::npass - 1>::run(v, buf, t, twp);
+    LdsPasses<R, LOG2M, true, 0, S::npass - 1>::run(v, buf, 0, t, twp);
     pass_read<R, LOG2M, true, S::npass - 1>(v, buf, t);
     pass_compute<R, LOG2M, true, S::npass - 1>(v, t, twp);
     if (row >= a.rows_out) return;
@@ -482,11 +503,15 @@ static void launch_row_inv(const StageCArgs& a, dim3 grid, const RowTiling& t, C
 template <typename R, int LG, int MODE>
 static void launch_col(const StageBArgs& b, int nvec, Ctx& c, hipStream_t st) {
     constexpr int L = 1 << LG, T = L / 8;
-    const size_t lds = (size_t)b.CB * padded(L) * sizeof(cpx<R>);
-    dim3 grid((b.ncols + b.CB - 1) / b.CB, nvec);
-    auto k = k_col<R, LG, MODE>;
+    // two vectors per workgroup in FP32 (shared twiddles and spectrum), one in FP64
+    constexpr int V = (sizeof(R) == 4 && MODE != B_SPEC) ? 2 : 1;
+    const size_t lds = (size_t)b.CB * V * padded(L) * sizeof(cpx<R>);
+    dim3 grid((b.ncols + b.CB - 1) / b.CB, (nvec + V - 1) / V);
+    auto k = k_col<R, LG, MODE, V>;
     set_lds(k, lds);
-    hipLaunchKernelGGL(k, grid, dim3(b.CB * T), lds, st, b, plan_table<R>(c, LG));
+    StageBArgs bb = b;
+    bb.nvec = nvec;
+    hipLaunchKernelGGL(k, grid, dim3(b.CB * T), lds, st, bb, plan_table<R>(c, LG));
     KRY_HIP(hipGetLastError());
 }
 

@@ -79,8 +79,9 @@ __device__ __forceinline__ void dft8_low(cpx<R>* v) {
     v[7] = csub(e3, o3);
 }
 
-// Twiddle and butterfly of pass P on the 8 register values of thread t.
-template <typename R, int LOG2L, bool INV, int P, bool LOWHALF = false>
+// Twiddle and butterfly of pass P on V independent sets of 8 register values
+// (v[u * 8 + k]); the twiddles are loaded once and applied to every set.
+template <typename R, int LOG2L, bool INV, int P, bool LOWHALF = false, int V = 1>
 __device__ __forceinline__ void pass_compute(cpx<R>* v, int t, const cpx<R>* __restrict__ tw) {
     using S = Sched<LOG2L>;
     constexpr int LR = S::lr(INV, P);
@@ -93,14 +94,27 @@ __device__ __forceinline__ void pass_compute(cpx<R>* v, int t, const cpx<R>* __r
         if constexpr (P > 0) {
             const int j = t + b * T;
             const int jn = j & (NS - 1);
-            const cpx<R>* w = tw + S::tw_off(INV, P) + jn * RADIX;
+            const cpx<R>* wp = tw + S::tw_off(INV, P) + jn * RADIX;
+            cpx<R> w[RADIX];
 #pragma unroll
-            for (int r = 1; r < RADIX; ++r) v[b * RADIX + r] = cmul(v[b * RADIX + r], w[r]);
+            for (int r = 1; r < RADIX; ++r) w[r] = wp[r];
+#pragma unroll
+            for (int u = 0; u < V; ++u)
+#pragma unroll
+                for (int r = 1; r < RADIX; ++r) v[u * 8 + b * RADIX + r] = cmul(v[u * 8 + b * RADIX + r], w[r]);
         }
-        if constexpr (LOWHALF && RADIX == 8) dft8_low<R, INV>(v);
-        else dft<R, RADIX, INV>(v + b * RADIX);
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            if constexpr (LOWHALF && RADIX == 8) dft8_low<R, INV>(v + u * 8);
+            else dft<R, RADIX, INV>(v + u * 8 + b * RADIX);
+        }
     }
 }
+
+// Padded LDS offset of element base + d when base + d stays in the same
+// 8-aligned structure: the caller guarantees (base mod 8) + (d mod 8) < 8 or
+// d a multiple of 8, so pad8(base + d) = pad8(base) + d + d/8.
+constexpr int pad_off(int d) { return d + d / 8; }
 
 // Inputs of pass P from LDS (transform base `buf`).
 template <typename R, int LOG2L, bool INV, int P>
@@ -112,8 +126,14 @@ __device__ __forceinline__ void pass_read(cpx<R>* v, const cpx<R>* buf, int t) {
 #pragma unroll
     for (int b = 0; b < 8 / RADIX; ++b) {
         const int j = t + b * T;
+        if constexpr (Q % 8 == 0) {
+            const cpx<R>* p = buf + pad8(j);
 #pragma unroll
-        for (int r = 0; r < RADIX; ++r) v[b * RADIX + r] = buf[pad8(j + r * Q)];
+            for (int r = 0; r < RADIX; ++r) v[b * RADIX + r] = p[pad_off(r * Q)];
+        } else {
+#pragma unroll
+            for (int r = 0; r < RADIX; ++r) v[b * RADIX + r] = buf[pad8(j + r * Q)];
+        }
     }
 }
 
@@ -126,12 +146,20 @@ __device__ __forceinline__ void pass_write(const cpx<R>* v, cpx<R>* buf, int t) 
     constexpr int LNS = S::lns(INV, P);
     constexpr int NS = 1 << LNS;
     constexpr int T = S::L / 8;
+    // dst mod 8 = j mod NS when NS divides 8 and NS * RADIX is a multiple of 8
+    constexpr bool FAST = (NS % 8 == 0) || (8 % NS == 0 && (NS * RADIX) % 8 == 0);
 #pragma unroll
     for (int b = 0; b < 8 / RADIX; ++b) {
         const int j = t + b * T;
         const int dst = ((j >> LNS) << (LNS + LR)) + (j & (NS - 1));
+        if constexpr (FAST) {
+            cpx<R>* p = buf + pad8(dst);
 #pragma unroll
-        for (int r = 0; r < RADIX; ++r) buf[pad8(dst + r * NS)] = v[b * RADIX + r];
+            for (int r = 0; r < RADIX; ++r) p[pad_off(r * NS)] = v[b * RADIX + r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < RADIX; ++r) buf[pad8(dst + r * NS)] = v[b * RADIX + r];
+        }
     }
 }
 
@@ -145,17 +173,21 @@ __device__ __forceinline__ int edge_pos(int t, int k) {
     return t + (k / RADIX) * T + (k % RADIX) * Q;
 }
 
-// Passes PB..PE-1 entirely through LDS (read, sync, compute, write, sync).
-template <typename R, int LOG2L, bool INV, int P, int PE>
+// Passes P..PE-1 entirely through LDS (read, sync, compute, write, sync) for V
+// transforms at buf + u * stride.
+template <typename R, int LOG2L, bool INV, int P, int PE, int V = 1>
 struct LdsPasses {
-    __device__ __forceinline__ static void run(cpx<R>* v, cpx<R>* buf, int t, const cpx<R>* __restrict__ tw) {
+    __device__ __forceinline__ static void run(cpx<R>* v, cpx<R>* buf, int stride, int t,
+                                               const cpx<R>* __restrict__ tw) {
         if constexpr (P < PE) {
-            pass_read<R, LOG2L, INV, P>(v, buf, t);
+#pragma unroll
+            for (int u = 0; u < V; ++u) pass_read<R, LOG2L, INV, P>(v + u * 8, buf + u * stride, t);
             __syncthreads();
-            pass_compute<R, LOG2L, INV, P>(v, t, tw);
-            pass_write<R, LOG2L, INV, P>(v, buf, t);
+            pass_compute<R, LOG2L, INV, P, false, V>(v, t, tw);
+#pragma unroll
+            for (int u = 0; u < V; ++u) pass_write<R, LOG2L, INV, P>(v + u * 8, buf + u * stride, t);
             __syncthreads();
-            LdsPasses<R, LOG2L, INV, P + 1, PE>::run(v, buf, t, tw);
+            LdsPasses<R, LOG2L, INV, P + 1, PE, V>::run(v, buf, stride, t, tw);
         }
     }
 };

@@ -4,6 +4,8 @@
 
 #include <array>
 #include <cstdint>
+#include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -51,6 +53,7 @@ struct Ctx {
     cpx<float>* tw32 = nullptr;
     void* plan64[14] = {};  // per-length pass twiddle tables (index log2 length)
     void* plan32[14] = {};
+    std::mutex alloc_mu;     // guards `allocated` (server slots allocate concurrently)
 };
 
 void* dev_alloc(Ctx& c, size_t bytes);
@@ -90,6 +93,10 @@ struct Spectrum {
     DevBuf s64, s32;
 };
 
+// A problem: grid, packed mask, compact data (immutable after creation and
+// shared with views) plus a mutable workspace.  A view shares the immutable
+// part and owns a fresh workspace, so requests on one problem can run
+// concurrently on different streams.
 struct Problem {
     Ctx* ctx = nullptr;
     int n1 = 0, n2 = 0;
@@ -100,15 +107,45 @@ struct Problem {
     DevBuf bits, base;           // packed mask
     DevBuf cell;                 // compact index -> cell id (int32)
     DevBuf y64, y32;             // compact data
-    std::vector<int64_t> h_cell; // compact index -> cell id (host)
-    std::vector<uint8_t> h_mask;
+    std::shared_ptr<const std::vector<int64_t>> h_cell;  // compact index -> cell id (host)
+    std::shared_ptr<const std::vector<uint8_t>> h_mask;
+    bool is_view = false;
+    // workspace (per problem or per view)
     Spectrum spec;               // cache of the last parameter point
     DevBuf Y;                    // transform workspace
     DevBuf lagtmp, spectmp, spec_multi64, spec_multi32;
     DevBuf kws;                  // Krylov workspace
     DevBuf scal;                 // device scalars
+    DevBuf tmp1, tmp2, tmp3, tmp4;  // per-call scratch of the drivers
     MaskView mask_view() const {
         return MaskView{bits.as<uint32_t>(), base.as<uint32_t>(), words_per_row};
+    }
+    Problem view() const {
+        Problem v;
+        v.ctx = ctx;
+        v.n1 = n1;
+        v.n2 = n2;
+        v.dx1 = dx1;
+        v.dx2 = dx2;
+        v.N1 = N1;
+        v.N2 = N2;
+        v.p = p;
+        v.words_per_row = words_per_row;
+        v.bits = bits;
+        v.base = base;
+        v.cell = cell;
+        v.y64 = y64;
+        v.y32 = y32;
+        v.h_cell = h_cell;
+        v.h_mask = h_mask;
+        v.is_view = true;
+        return v;
+    }
+    void release_work() {
+        for (DevBuf* b : {&Y, &lagtmp, &spectmp, &spec_multi64, &spec_multi32, &kws, &scal, &tmp1, &tmp2, &tmp3,
+                          &tmp4, &spec.s64, &spec.s32})
+            b->release(*ctx);
+        spec.valid = false;
     }
 };
 
@@ -159,6 +196,16 @@ void spectrum_scale(const double* lam, int64_t n, double s, bool sqrt_clip, doub
 // Cached, scaled spectrum of theta on the problem's embedding.
 Spectrum& problem_spectrum(Problem& P, const Matern& th, hipStream_t st);
 
+// ---- drivers (api.hip), used by the ABI and by the server ----------------------
+void loglik_points(Problem& P, const kry_matern* thetas, int count, const kry_opts* o, kry_loglik_result* out,
+                   hipStream_t st);
+// Kriging; sets *noconv when a CG solve stopped at cg_maxit.
+void krige_impl(Problem& P, const kry_matern* theta, const kry_opts* opts, const std::vector<int64_t>& targets,
+                double* mean_x, double* var_x, double* var_y, int bootstrap_B, bool* noconv, hipStream_t st);
+void check_theta(const kry_matern* t);
+void check_opts(const kry_opts* o);
+int nprobes_of(const kry_opts* o);
+
 // ---- Krylov building blocks (krylov.hip) --------------------------------------
 int dot_blocks(int64_t n);
 template <typename R>
@@ -166,3 +213,11 @@ void dot_batched(const R* a, int64_t sa, const R* b, int64_t sb, int64_t n, int 
                  double* out, hipStream_t st);
 
 }  // namespace kry
+
+// Opaque handles of the C ABI.
+struct kry_ctx {
+    kry::Ctx c;
+};
+struct kry_problem {
+    kry::Problem P;
+};

@@ -1,0 +1,318 @@
+// Request server: continuous batching of likelihood and kriging requests on
+// device-resident problems.
+//
+// `slots` worker threads each own a HIP stream (default priority) and a
+// workspace; a request is admitted when a slot is free and the estimated
+// device footprint of everything in flight stays within the HBM budget, so
+// requests that arrive while others run start as soon as a slot and memory
+// free up, and their kernels overlap on the device.  A worker that takes a
+// likelihood request also takes every queued likelihood request on the same
+// problem with identical options (up to max_batch) and runs them as one
+// batched evaluation (every (point, probe) vector in the same products).
+// Reductions are fixed-order per vector, so a request's result is the same
+// whether it runs alone or batched with others.
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <thread>
+#include <unordered_map>
+
+#include "internal.hpp"
+
+using namespace kry;
+
+namespace {
+
+struct Pending {
+    uint64_t ticket;
+    kry_request req;
+    std::vector<int64_t> targets;
+    uint64_t footprint;
+    double t_submit;
+};
+
+// Workspace of one slot, moved into a problem view for the duration of a
+// request.
+struct SlotWork {
+    DevBuf Y, lagtmp, spectmp, spec_multi64, spec_multi32, kws, scal, tmp1, tmp2, tmp3, tmp4;
+    Spectrum spec;
+    const Problem* last = nullptr;
+};
+
+void swap_work(Problem& v, SlotWork& w) {
+    std::swap(v.Y, w.Y);
+    std::swap(v.lagtmp, w.lagtmp);
+    std::swap(v.spectmp, w.spectmp);
+    std::swap(v.spec_multi64, w.spec_multi64);
+    std::swap(v.spec_multi32, w.spec_multi32);
+    std::swap(v.kws, w.kws);
+    std::swap(v.scal, w.scal);
+    std::swap(v.tmp1, w.tmp1);
+    std::swap(v.tmp2, w.tmp2);
+    std::swap(v.tmp3, w.tmp3);
+    std::swap(v.tmp4, w.tmp4);
+    std::swap(v.spec.s64, w.spec.s64);
+    std::swap(v.spec.s32, w.spec.s32);
+    std::swap(v.spec.theta, w.spec.theta);
+    std::swap(v.spec.valid, w.spec.valid);
+    std::swap(v.spec.lam_min, w.spec.lam_min);
+    std::swap(v.spec.lam_max, w.spec.lam_max);
+}
+
+// Rough device footprint of a request (bytes): Krylov vectors, transform
+// intermediate, spectra and solver vectors.
+uint64_t footprint(const Problem& P, const kry_request& r, int count) {
+    const uint64_t p = P.p, n = (uint64_t)P.n1 * P.n2;
+    const uint64_t M = P.N2 / 2, nspec = (M + 1) * P.N1;
+    const uint64_t el = r.opts.precision == KRY_FP32 ? 4 : 8;
+    const uint64_t inter = (M + 1) * (uint64_t)P.n1 * 2 * el;
+    if (r.kind == KRY_REQ_LOGLIK) {
+        const uint64_t np = nprobes_of(&r.opts);
+        const uint64_t slots = r.opts.reorth ? r.opts.lanczos_steps + 3 : 5;
+        const uint64_t vecs = count * np;
+        return vecs * p * el * slots + std::min<uint64_t>(vecs, 64) * inter + count * nspec * 12 +
+               count * p * 8 * 6 + P.N1 * (uint64_t)P.N2 * 8;
+    }
+    return inter + nspec * 12 + p * 8 * 8 + n * 8 * 2 + P.N1 * (uint64_t)P.N2 * 8 +
+           (r.variances ? std::min<uint64_t>(r.ntargets, 256) * p * 8 * 8 : 0);
+}
+
+}  // namespace
+
+struct kry_server {
+    Ctx* ctx = nullptr;
+    int slots = 1, max_batch = 1, max_queue = 1;
+    uint64_t budget = 0;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Pending> queue;
+    std::unordered_map<uint64_t, kry_response> done;
+    std::unordered_map<uint64_t, bool> known;
+    uint64_t next_ticket = 1;
+    uint64_t inflight = 0;
+    bool stop = false;
+    std::vector<std::thread> workers;
+    std::vector<hipStream_t> streams;
+    std::vector<SlotWork> work;
+    std::chrono::steady_clock::time_point t0;
+
+    double now() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+
+    static bool same_opts(const kry_opts& a, const kry_opts& b) {
+        return a.lanczos_steps == b.lanczos_steps && a.num_probes == b.num_probes && a.probe_kind == b.probe_kind &&
+               a.colour_period == b.colour_period && a.seed == b.seed && a.reorth == b.reorth &&
+               a.precision == b.precision && a.cg_rtol == b.cg_rtol && a.cg_maxit == b.cg_maxit &&
+               a.solver == b.solver && a.gk_steps == b.gk_steps;
+    }
+
+    void run_slot(int slot) {
+        (void)hipSetDevice(ctx->device);
+        hipStream_t st = streams[slot];
+        SlotWork& w = work[slot];
+        while (true) {
+            std::vector<Pending> batch;
+            uint64_t fp = 0;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_work.wait(lk, [&] {
+                    return stop || (!queue.empty() && (inflight + queue.front().footprint <= budget || inflight == 0));
+                });
+                if (queue.empty()) {
+                    if (stop) return;
+                    continue;
+                }
+                batch.push_back(std::move(queue.front()));
+                queue.pop_front();
+                fp = batch[0].footprint;
+                const kry_request& h = batch[0].req;
+                if (h.kind == KRY_REQ_LOGLIK) {
+                    for (auto it = queue.begin(); it != queue.end() && (int)batch.size() < max_batch;) {
+                        const kry_request& r = it->req;
+                        if (r.kind == KRY_REQ_LOGLIK && r.prob == h.prob && same_opts(r.opts, h.opts) &&
+                            inflight + fp + it->footprint <= budget) {
+                            fp += it->footprint;
+                            batch.push_back(std::move(*it));
+                            it = queue.erase(it);
+                        } else {
+                            ++it;
+                        }
+                    }
+                }
+                inflight += fp;
+            }
+            const double t_start = now();
+            std::vector<kry_response> resp(batch.size());
+            execute(batch, resp, w, st);
+            const double t_end = now();
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                inflight -= fp;
+                for (size_t i = 0; i < batch.size(); ++i) {
+                    resp[i].t_submit = batch[i].t_submit;
+                    resp[i].t_start = t_start;
+                    resp[i].t_end = t_end;
+                    resp[i].batch = (int32_t)batch.size();
+                    done[batch[i].ticket] = resp[i];
+                }
+            }
+            cv_done.notify_all();
+            cv_work.notify_all();
+        }
+    }
+
+    void execute(std::vector<Pending>& batch, std::vector<kry_response>& resp, SlotWork& w, hipStream_t st) {
+        const Problem& base = batch[0].req.prob->P;
+        Problem v = base.view();
+        w.spec.valid = false;  // the cached spectrum may belong to another problem
+        w.last = &base;
+        swap_work(v, w);
+        const kry_request& h = batch[0].req;
+        kry_status status = KRY_OK;
+        std::string msg;
+        try {
+            if (h.kind == KRY_REQ_LOGLIK) {
+                std::vector<kry_matern> th(batch.size());
+                std::vector<kry_loglik_result> res(batch.size());
+                for (size_t i = 0; i < batch.size(); ++i) th[i] = batch[i].req.theta;
+                loglik_points(v, th.data(), (int)th.size(), &h.opts, res.data(), st);
+                for (size_t i = 0; i < batch.size(); ++i) {
+                    resp[i].loglik = res[i];
+                    resp[i].status = (h.opts.solver == KRY_SOLVER_CG && res[i].cg_relres > h.opts.cg_rtol)
+                                         ? KRY_ENOCONV
+                                         : KRY_OK;
+                }
+            } else {
+                bool noconv = false;
+                krige_impl(v, &h.theta, &h.opts, batch[0].targets, h.mean_x, h.variances ? h.var_x : nullptr,
+                           h.variances ? h.var_y : nullptr, 0, &noconv, st);
+                resp[0].status = noconv ? KRY_ENOCONV : KRY_OK;
+            }
+        } catch (const Error& e) {
+            status = e.status;
+            msg = e.what();
+        } catch (const std::exception& e) {
+            status = KRY_EDEVICE;
+            msg = e.what();
+        }
+        (void)hipStreamSynchronize(st);
+        swap_work(v, w);
+        if (status != KRY_OK)
+            for (auto& r : resp) r.status = status;
+    }
+};
+
+kry_status kry_server_create(kry_ctx* kctx, int32_t slots, uint64_t hbm_budget_bytes, int32_t max_batch,
+                             int32_t max_queue, kry_server** out) {
+    try {
+        if (!kctx || !out || slots < 1 || slots > 16 || max_batch < 1 || max_queue < 1) return KRY_EINVAL;
+        Ctx& c = kctx->c;
+        auto* s = new kry_server();
+        s->ctx = &c;
+        s->slots = slots;
+        s->max_batch = max_batch;
+        s->max_queue = max_queue;
+        s->budget = hbm_budget_bytes ? hbm_budget_bytes : ~0ull;
+        s->t0 = std::chrono::steady_clock::now();
+        if (hipSetDevice(c.device) != hipSuccess) {
+            delete s;
+            return KRY_EDEVICE;
+        }
+        s->streams.resize(slots, nullptr);
+        s->work.resize(slots);
+        for (int i = 0; i < slots; ++i) {
+            if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess) {
+                for (int j = 0; j < i; ++j) (void)hipStreamDestroy(s->streams[j]);
+                delete s;
+                return KRY_EDEVICE;
+            }
+        }
+        for (int i = 0; i < slots; ++i) s->workers.emplace_back([s, i] { s->run_slot(i); });
+        *out = s;
+        return KRY_OK;
+    } catch (...) {
+        return KRY_EDEVICE;
+    }
+}
+
+kry_status kry_server_submit(kry_server* s, const kry_request* req, uint64_t* ticket) {
+    if (!s || !req || !ticket || !req->prob) return KRY_EINVAL;
+    try {
+        check_theta(&req->theta);
+        check_opts(&req->opts);
+        if (req->kind != KRY_REQ_LOGLIK && req->kind != KRY_REQ_KRIGE) return KRY_EINVAL;
+        Pending pd;
+        pd.req = *req;
+        const Problem& P = req->prob->P;
+        if (req->kind == KRY_REQ_KRIGE) {
+            if (!req->targets || req->ntargets < 1 || !req->mean_x) return KRY_EINVAL;
+            const int64_t n = (int64_t)P.n1 * P.n2;
+            pd.targets.assign(req->targets, req->targets + req->ntargets);
+            for (int64_t t : pd.targets)
+                if (t < 0 || t >= n) return KRY_EINVAL;
+        }
+        pd.footprint = footprint(P, *req, 1);
+        if (pd.footprint > s->budget) return KRY_ENOMEM;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            if ((int)s->queue.size() >= s->max_queue) return KRY_EBUSY;
+            pd.ticket = s->next_ticket++;
+            pd.t_submit = s->now();
+            s->known[pd.ticket] = true;
+            *ticket = pd.ticket;
+            s->queue.push_back(std::move(pd));
+        }
+        s->cv_work.notify_one();
+        return KRY_OK;
+    } catch (const Error& e) {
+        return e.status;
+    } catch (...) {
+        return KRY_EDEVICE;
+    }
+}
+
+kry_status kry_server_poll(kry_server* s, uint64_t ticket, kry_response* out, int32_t* is_done) {
+    if (!s || !out || !is_done) return KRY_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!s->known.count(ticket)) return KRY_EINVAL;
+    auto it = s->done.find(ticket);
+    if (it == s->done.end()) {
+        *is_done = 0;
+        return KRY_OK;
+    }
+    *out = it->second;
+    *is_done = 1;
+    s->done.erase(it);
+    s->known.erase(ticket);
+    return KRY_OK;
+}
+
+kry_status kry_server_wait(kry_server* s, uint64_t ticket, kry_response* out) {
+    if (!s || !out) return KRY_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (!s->known.count(ticket)) return KRY_EINVAL;
+    s->cv_done.wait(lk, [&] { return s->done.count(ticket) > 0; });
+    *out = s->done[ticket];
+    s->done.erase(ticket);
+    s->known.erase(ticket);
+    return KRY_OK;
+}
+
+void kry_server_destroy(kry_server* s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    for (auto& t : s->workers) t.join();
+    (void)hipSetDevice(s->ctx->device);
+    for (auto& w : s->work)
+        for (DevBuf* b : {&w.Y, &w.lagtmp, &w.spectmp, &w.spec_multi64, &w.spec_multi32, &w.kws, &w.scal, &w.tmp1,
+                          &w.tmp2, &w.tmp3, &w.tmp4, &w.spec.s64, &w.spec.s32})
+            b->release(*s->ctx);
+    for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+    delete s;
+}

@@ -54,6 +54,20 @@ class kry_loglik_result(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class kry_request(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("prob", C.c_void_p), ("theta", kry_matern), ("opts", kry_opts),
+                ("targets", C.POINTER(C.c_int64)), ("ntargets", C.c_int64), ("variances", C.c_int32),
+                ("mean_x", C.POINTER(C.c_double)), ("var_x", C.POINTER(C.c_double)),
+                ("var_y", C.POINTER(C.c_double))]
+
+
+class kry_response(C.Structure):
+    _fields_ = [("status", C.c_int32), ("batch", C.c_int32), ("loglik", kry_loglik_result),
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_end", C.c_double)]
+
+
+KRY_REQ_LOGLIK, KRY_REQ_KRIGE = 0, 1
+
 _P = C.c_void_p
 _DP = C.POINTER(C.c_double)
 _I32P = C.POINTER(C.c_int32)
@@ -90,6 +104,11 @@ _SIGS = {
     "kry_psd_torus": (C.c_int, [_P, C.POINTER(kry_matern), _I32P, _I32P]),
     "kry_sample": (C.c_int, [_P, C.POINTER(kry_matern), C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_int32,
                              _DP, _DP]),
+    "kry_server_create": (C.c_int, [_P, C.c_int32, C.c_uint64, C.c_int32, C.c_int32, C.POINTER(_P)]),
+    "kry_server_submit": (C.c_int, [_P, C.POINTER(kry_request), C.POINTER(C.c_uint64)]),
+    "kry_server_poll": (C.c_int, [_P, C.c_uint64, C.POINTER(kry_response), C.POINTER(C.c_int32)]),
+    "kry_server_wait": (C.c_int, [_P, C.c_uint64, C.POINTER(kry_response)]),
+    "kry_server_destroy": (None, [_P]),
 }
 
 
@@ -346,6 +365,62 @@ def kry_sample(prob, th, N1, N2, seed, first_stream, count, n1, n2):
     mm = np.empty(2)
     _check(lib.kry_sample(prob, C.byref(th), N1, N2, seed, first_stream, count, _dp(out), _dp(mm)))
     return out, mm
+
+
+def kry_server_create(ctx, slots=4, hbm_budget_bytes=0, max_batch=16, max_queue=4096):
+    h = _P()
+    _check(lib.kry_server_create(ctx, slots, hbm_budget_bytes, max_batch, max_queue, C.byref(h)))
+    return h
+
+
+class PendingRequest:
+    """Keeps a submitted request's structure and output arrays alive."""
+
+    def __init__(self, ticket, req, outputs):
+        self.ticket, self.req, self.outputs = ticket, req, outputs
+
+
+def kry_server_submit(srv, kind, prob, th, opts, targets=None, variances=False):
+    """Submit a request; returns a PendingRequest (its outputs are filled when done)."""
+    req = kry_request()
+    req.kind = kind
+    req.prob = prob
+    req.theta = th
+    req.opts = opts
+    outputs = {}
+    if kind == KRY_REQ_KRIGE:
+        tg = np.ascontiguousarray(targets, dtype=np.int64)
+        outputs["targets"] = tg
+        outputs["mean_x"] = np.empty(tg.size)
+        req.targets = tg.ctypes.data_as(C.POINTER(C.c_int64))
+        req.ntargets = tg.size
+        req.mean_x = _dp(outputs["mean_x"])
+        if variances:
+            req.variances = 1
+            outputs["var_x"] = np.empty(tg.size)
+            outputs["var_y"] = np.empty(tg.size)
+            req.var_x = _dp(outputs["var_x"])
+            req.var_y = _dp(outputs["var_y"])
+    t = C.c_uint64()
+    _check(lib.kry_server_submit(srv, C.byref(req), C.byref(t)))
+    return PendingRequest(t.value, req, outputs)
+
+
+def kry_server_poll(srv, pending):
+    r = kry_response()
+    d = C.c_int32()
+    _check(lib.kry_server_poll(srv, pending.ticket, C.byref(r), C.byref(d)))
+    return r if d.value else None
+
+
+def kry_server_wait(srv, pending):
+    r = kry_response()
+    _check(lib.kry_server_wait(srv, pending.ticket, C.byref(r)))
+    return r
+
+
+def kry_server_destroy(srv):
+    lib.kry_server_destroy(srv)
 
 
 class Problem:

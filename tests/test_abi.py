@@ -1,0 +1,71 @@
+"""CPU checks of the C ABI: the library loads and exports every function that
+include/kryging.h declares; host-side validation and error paths that need no
+GPU (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kryging.h")
+
+
+def _lib_path():
+    from paper_2012_13133_amd import build as b
+    if not os.path.exists(b.OUT):
+        b.build()
+    return b.OUT
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(kry_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("kry_matvec", "kry_matvec_device", "kry_loglik", "kry_loglik_batch", "kry_krige", "kry_fit",
+                 "kry_lanczos", "kry_logdet", "kry_gauss_quadrature", "kry_solve", "kry_gengk", "kry_lag_grid",
+                 "kry_spectrum", "kry_sample", "kry_psd_torus", "kry_probes", "kry_server_create",
+                 "kry_server_submit", "kry_server_poll", "kry_server_wait", "kry_server_destroy"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(_lib_path())
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_host_side_paths_without_gpu():
+    _lib_path()
+    from paper_2012_13133_amd import kryging as K
+    o = K.kry_opts_default()
+    assert (o.lanczos_steps, o.num_probes, o.seed, o.precision, o.cg_rtol) == (30, 10, 303, 0, 1e-8)
+    assert K.kry_status_string(K.KRY_ENOTPSD).startswith("circulant")
+    # problem creation with a NULL context is rejected before any device work
+    g = K.kry_grid(8, 8, 0.125, 0.125)
+    h = ctypes.c_void_p()
+    m = (ctypes.c_uint8 * 64)(*([1] * 64))
+    st = K.lib.kry_problem_create(None, ctypes.byref(g), m, None, ctypes.byref(h))
+    assert st == K.KRY_EINVAL
+    # gauss quadrature validates its sizes before touching the device
+    one = (ctypes.c_double * 1)(1.0)
+    steps = (ctypes.c_int32 * 1)(5)
+    st = K.lib.kry_gauss_quadrature(1, 2, one, one, steps, one, one)
+    assert st == K.KRY_EINVAL
+    assert b"steps" in K.lib.kry_last_error()
+    # server creation rejects bad arguments
+    assert K.lib.kry_server_create(None, 2, 0, 4, 16, ctypes.byref(h)) == K.KRY_EINVAL
+
+
+@pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="a GPU is present")
+def test_context_without_device_reports_edevice():
+    _lib_path()
+    from paper_2012_13133_amd import kryging as K
+    with pytest.raises(K.KryError) as e:
+        K.kry_ctx_create()
+    assert e.value.status == K.KRY_EDEVICE

@@ -1,0 +1,127 @@
+"""GPU: the request server (continuous batching) gives every request the same
+result as running it alone, and reports timing."""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import sampler
+from paper_2012_13133_amd import synth
+from tests.oracle_cases import grid, theta
+
+pytestmark = pytest.mark.gpu
+
+K = pytest.importorskip("paper_2012_13133_amd.kryging")
+
+SHAPES = [(40, 36, 0.3, "uniform"), (64, 64, 0.2, "blob"), (24, 50, 0.5, "uniform")]
+
+
+def _problems(ctx):
+    probs, masks = [], []
+    for i, (n1, n2, frac, kind) in enumerate(SHAPES):
+        if kind == "uniform":
+            mask = synth.uniform_mask(n1, n2, frac, seed=10 + i)
+        else:
+            mask = synth.blob_mask(n1, n2, frac, seed=10 + i, rmin=3, rmax=10)
+        _, y = sampler.cholesky_field(grid(n1, n2), theta(0.1, 1.5, tau2=0.2), seed=20 + i)
+        probs.append(K.kry_problem_create(ctx, n1, n2, mask, y))
+        masks.append(mask)
+    return probs, masks
+
+
+def _requests(masks, count, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(count):
+        pi = int(rng.integers(len(masks)))
+        th = K.theta(sigma2=float(rng.uniform(0.5, 2)), tau2=float(rng.uniform(0.05, 0.5)),
+                     range=float(np.exp(rng.uniform(np.log(0.03), np.log(0.2)))),
+                     nu=float(rng.choice([0.5, 1.5, 2.5])))
+        prec = int(rng.integers(2))
+        if rng.uniform() < 0.7:
+            # a few option sets so that batching has something to merge
+            opts = K.kry_opts_default(lanczos_steps=20, num_probes=6, precision=prec, cg_rtol=1e-8)
+            reqs.append(("loglik", pi, th, opts, None))
+        else:
+            miss = np.flatnonzero(masks[pi].ravel() == 0)
+            tg = rng.choice(miss, size=min(12, miss.size), replace=False)
+            opts = K.kry_opts_default(precision=prec, cg_rtol=1e-9)
+            reqs.append(("krige", pi, th, opts, tg))
+    return reqs
+
+
+def test_server_same_alone_and_in_mix():
+    ctx = K.kry_ctx_create()
+    probs, masks = _problems(ctx)
+    try:
+        reqs = _requests(masks, 48, seed=1)
+        alone = []
+        for kind, pi, th, opts, tg in reqs:
+            if kind == "loglik":
+                alone.append(K.kry_loglik(probs[pi], th, opts))
+            else:
+                alone.append(K.kry_krige(probs[pi], th, opts, tg))
+        srv = K.kry_server_create(ctx, slots=3, max_batch=8)
+        try:
+            pend = []
+            for i, (kind, pi, th, opts, tg) in enumerate(reqs):
+                if kind == "loglik":
+                    pend.append(K.kry_server_submit(srv, K.KRY_REQ_LOGLIK, probs[pi], th, opts))
+                else:
+                    pend.append(K.kry_server_submit(srv, K.KRY_REQ_KRIGE, probs[pi], th, opts, tg, variances=True))
+                if i % 7 == 6:
+                    time.sleep(0.002)  # staggered arrivals
+            resp = [K.kry_server_wait(srv, p) for p in pend]
+        finally:
+            K.kry_server_destroy(srv)
+        batches = 0
+        for (kind, pi, th, opts, tg), a, p, r in zip(reqs, alone, pend, resp):
+            assert r.status == K.KRY_OK
+            assert r.t_submit <= r.t_start <= r.t_end
+            batches = max(batches, r.batch)
+            if kind == "loglik":
+                got = r.loglik.as_dict()
+                for key in ("loglik", "loglik_profiled", "logdet", "logdet_se", "quad", "cg_iters"):
+                    assert got[key] == a[key], (key, got[key], a[key])
+            else:
+                np.testing.assert_array_equal(p.outputs["mean_x"], a[0])
+                np.testing.assert_array_equal(p.outputs["var_x"], a[1])
+                np.testing.assert_array_equal(p.outputs["var_y"], a[2])
+        assert batches > 1, "no request was batched with another"
+        # requests ran concurrently on different slots
+        spans = sorted((r.t_start, r.t_end) for r in resp)
+        assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
+    finally:
+        for h in probs:
+            K.kry_problem_destroy(h)
+        K.kry_ctx_destroy(ctx)
+
+
+def test_server_admission_by_footprint():
+    ctx = K.kry_ctx_create()
+    probs, masks = _problems(ctx)
+    try:
+        opts = K.kry_opts_default(lanczos_steps=10, num_probes=4)
+        th = K.theta(range=0.1, nu=0.5, tau2=0.2)
+        # a budget far below one request's footprint is refused at submit
+        srv = K.kry_server_create(ctx, slots=2, hbm_budget_bytes=1 << 10)
+        try:
+            with pytest.raises(K.KryError) as e:
+                K.kry_server_submit(srv, K.KRY_REQ_LOGLIK, probs[1], th, opts)
+            assert e.value.status == K.KRY_ENOMEM
+        finally:
+            K.kry_server_destroy(srv)
+        # a budget that fits one request at a time still completes every request
+        srv = K.kry_server_create(ctx, slots=3, hbm_budget_bytes=300 << 20, max_batch=1)
+        try:
+            pend = [K.kry_server_submit(srv, K.KRY_REQ_LOGLIK, probs[i % 3], th, opts) for i in range(6)]
+            resp = [K.kry_server_wait(srv, p) for p in pend]
+            assert all(r.status == K.KRY_OK for r in resp)
+            ref = [K.kry_loglik(probs[i % 3], th, opts)["loglik"] for i in range(6)]
+            assert [r.loglik.loglik for r in resp] == ref
+        finally:
+            K.kry_server_destroy(srv)
+    finally:
+        for h in probs:
+            K.kry_problem_destroy(h)
+        K.kry_ctx_destroy(ctx)
