@@ -45,6 +45,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--matvec-only", action="store_true", help="only the isolated batched product (profiling)")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-sides", type=str, default="128,512",
+                    help="grid sides log-uniform in [lo,hi] for the served stream (the full served workload uses 128,2048)")
+    ap.add_argument("--serve-slots", type=int, default=4)
     return ap.parse_args()
 
 
@@ -165,10 +170,19 @@ def main():
                      fp32_batched_rel_err_vs_fp64=rel)
         log("plain fp64: %.2f s, fp32-batched rel err %.2e" % (d64, rel))
 
+    # ---- served form: Poisson stream of likelihood / kriging requests ----
+    p_obs, emb = P.p, [P.N1, P.N2]
+    serve = None
+    if not args.no_serve:
+        P.close()
+        P = None
+        torch.cuda.empty_cache()
+        serve = serve_bench(args, K, synth, np)
+
     # ---- CPU oracle on a bounded sample ----
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(n, mask, dict(range=rho, nu=nu, sigma2=1.0, tau2=eta), P.p)
+        cpu = cpu_baseline(n, mask, dict(range=rho, nu=nu, sigma2=1.0, tau2=eta), p_obs)
 
     out = {
         "metric": METRIC,
@@ -186,10 +200,10 @@ def main():
         "config": {
             "workload": "1024x1024 grid, 30%% uniform missing (p=%d), Matern nu=1.5 range=0.05 nugget ratio 0.2; "
                         "one step = kry_loglik_batch over %d (range, nugget) points, %d probes x %d Lanczos steps, "
-                        "CG to %g, FP32 transforms + FP64 scalars" % (P.p, len(thetas), args.probes, args.lanczos,
+                        "CG to %g, FP32 transforms + FP64 scalars" % (p_obs, len(thetas), args.probes, args.lanczos,
                                                                       args.cg_rtol),
             "global_batch": len(thetas) * args.probes,
-            "embedding": [P.N1, P.N2],
+            "embedding": emb,
         },
         "loglik_evals_per_s": evals_per_s,
         "matvec_batched": {"fp32": mv[K.KRY_FP32], "fp64": mv[K.KRY_FP64],
@@ -204,8 +218,105 @@ def main():
         "cpu_baseline": cpu,
         "results_first_point": results[0],
     }
+    out["serve"] = serve
     print(json.dumps(out))
-    P.close()
+    if P is not None:
+        P.close()
+
+
+def serve_bench(args, K, synth, np):
+    """Served form: a Poisson stream of requests (70 % likelihood, 30 % kriging
+    at 16 held-out cells with exact variances) on grids with sides log-uniform
+    in the given range, 10-50 % missing (uniform or blob masks), nu in
+    {0.5, 1.5, 2.5}.  Problems are created once and stay device-resident.
+    Reports p50/p99 latency (submit to completion) and throughput at 80 % of
+    the measured saturation rate, and the same requests run sequentially in
+    the plain FP64 single-request form on the same GPU."""
+    lo, hi = (int(x) for x in args.serve_sides.split(","))
+    rng = np.random.default_rng(505)
+    ctx = K.kry_ctx_create()
+    nprob = 8
+    sides = synth.log_uniform_sides(nprob, lo, hi, seed=506)
+    probs, masks = [], []
+    for i, n in enumerate(sides):
+        frac = float(rng.uniform(0.1, 0.5))
+        if rng.uniform() < 0.5:
+            mask = synth.uniform_mask(int(n), int(n), frac, seed=600 + i)
+        else:
+            mask = synth.blob_mask(int(n), int(n), frac, seed=600 + i, rmin=max(2.0, n / 100), rmax=max(4.0, n / 12))
+        th = K.theta(sigma2=1.0, tau2=0.2, range=0.05, nu=1.5)
+        h = K.kry_problem_create(ctx, int(n), int(n), mask)
+        Nt = K.kry_psd_torus(h, th)
+        x, _ = K.kry_sample(h, th, Nt[0], Nt[1], 700 + i, 0, 1, int(n), int(n))
+        K.kry_problem_set_data(h, x[0] + np.sqrt(0.2) * rng.standard_normal((int(n), int(n))))
+        probs.append(h)
+        masks.append(mask)
+    reqs = []
+    for _ in range(args.serve_requests):
+        pi = int(rng.integers(nprob))
+        th = K.theta(sigma2=1.0, tau2=float(np.exp(rng.uniform(np.log(0.05), np.log(0.5)))),
+                     range=float(np.exp(rng.uniform(np.log(0.02), np.log(0.2)))), nu=float(rng.choice([0.5, 1.5, 2.5])))
+        if rng.uniform() < 0.7:
+            reqs.append(("loglik", pi, th, None))
+        else:
+            miss = np.flatnonzero(masks[pi].ravel() == 0)
+            reqs.append(("krige", pi, th, rng.choice(miss, size=16, replace=False)))
+    o32 = K.kry_opts_default(lanczos_steps=30, num_probes=10, precision=K.KRY_FP32, cg_rtol=1e-6)
+    o64 = K.kry_opts_default(lanczos_steps=30, num_probes=10, precision=K.KRY_FP64, cg_rtol=1e-8)
+
+    def submit(srv, r, opts):
+        kind, pi, th, tg = r
+        if kind == "loglik":
+            return K.kry_server_submit(srv, K.KRY_REQ_LOGLIK, probs[pi], th, opts)
+        return K.kry_server_submit(srv, K.KRY_REQ_KRIGE, probs[pi], th, opts, tg, variances=True)
+
+    srv = K.kry_server_create(ctx, slots=args.serve_slots, max_batch=16)
+    try:
+        # saturation: everything submitted at once
+        t0 = time.perf_counter()
+        pend = [submit(srv, r, o32) for r in reqs]
+        for p_ in pend:
+            K.kry_server_wait(srv, p_)
+        sat = len(reqs) / (time.perf_counter() - t0)
+        log("serve: saturation %.1f requests/s" % sat)
+        # Poisson arrivals at 80 % of saturation
+        rate = 0.8 * sat
+        gaps = rng.exponential(1.0 / rate, size=len(reqs))
+        t0 = time.perf_counter()
+        pend = []
+        tnext = t0
+        for r, gap in zip(reqs, gaps):
+            tnext += gap
+            while time.perf_counter() < tnext:
+                time.sleep(min(0.0005, max(0.0, tnext - time.perf_counter())))
+            pend.append(submit(srv, r, o32))
+        resp = [K.kry_server_wait(srv, p_) for p_ in pend]
+        wall = time.perf_counter() - t0
+    finally:
+        K.kry_server_destroy(srv)
+    lat = np.array([r.t_end - r.t_submit for r in resp]) * 1e3
+    n_ll = sum(1 for r in reqs if r[0] == "loglik")
+    # sequential plain FP64 form of the same requests
+    t1 = time.perf_counter()
+    for kind, pi, th, tg in reqs:
+        if kind == "loglik":
+            K.kry_loglik(probs[pi], th, o64, allow_noconv=True)
+        else:
+            K.kry_krige(probs[pi], th, o64, tg)
+    seq = time.perf_counter() - t1
+    for h in probs:
+        K.kry_problem_destroy(h)
+    K.kry_ctx_destroy(ctx)
+    out = {"requests": len(reqs), "loglik_fraction": n_ll / len(reqs), "sides": [lo, hi], "slots": args.serve_slots,
+           "saturation_req_per_s": sat, "arrival_rate_per_s": rate, "p50_ms": float(np.percentile(lat, 50)),
+           "p99_ms": float(np.percentile(lat, 99)), "req_per_s": len(reqs) / wall, "loglik_evals_per_s": n_ll / wall,
+           "max_batch_seen": int(max(r.batch for r in resp)),
+           "plain_fp64_sequential_req_per_s": len(reqs) / seq,
+           "plain_fp64_sequential_loglik_evals_per_s": n_ll / seq,
+           "served_vs_plain": (len(reqs) / wall) / (len(reqs) / seq)}
+    log("serve: p50 %.1f ms p99 %.1f ms, %.1f req/s vs plain fp64 sequential %.1f req/s" %
+        (out["p50_ms"], out["p99_ms"], out["req_per_s"], out["plain_fp64_sequential_req_per_s"]))
+    return out
 
 
 def cpu_baseline(n, mask, th, p, budget_s=15.0):

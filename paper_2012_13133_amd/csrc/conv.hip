@@ -176,20 +176,25 @@ __global__ void __launch_bounds__(1024) k_row_fwd(StageAArgs a, const cpx<R>* __
     __syncthreads();
     LdsPasses<R, LOG2M, false, 1, S::npass>::run(v, buf, 0, t, twp);
 
+    // split Z into the real transform X[k] = (s - i w d) / 2, k = 0..M:
+    // 8 outputs per thread for k < M plus the Nyquist column k = M
     cpx<R>* Y = reinterpret_cast<cpx<R>*>(a.Y) + vec * a.Y_vstride;
-    const int nout = a.RT * (M + 1);
-    for (int o = tid; o < nout; o += blockDim.x) {
-        const int r2 = o & (a.RT - 1);
-        const int k = o >> a.log2RT;
+    const int nt = blockDim.x;
+    auto split = [&](int r2, int k) {
         const cpx<R>* bp = lds + r2 * PM;
         const cpx<R> zk = bp[pad8(k & (M - 1))];
         const cpx<R> zc = cconj(bp[pad8((M - k) & (M - 1))]);
         const cpx<R> w = twiddle<R, false>(twb, k, LOG2M + 1);
         const cpx<R> s = cadd(zk, zc);
         const cpx<R> wd = cmul(w, csub(zk, zc));
-        // X[k] = (s - i w d) / 2
         Y[(int64_t)k * a.ldY + row0 + r2] = cpx<R>{(R)0.5 * (s.x + wd.y), (R)0.5 * (s.y - wd.x)};
+    };
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int o = tid + i * nt;
+        split(o & (a.RT - 1), o >> a.log2RT);
     }
+    if (tid < a.RT) split(tid, M);
 }
 
 enum { B_LOW = 0, B_FULL = 1, B_SPEC = 2 };
@@ -230,6 +235,21 @@ __global__ void __launch_bounds__(1024) k_col(StageBArgs a, const cpx<R>* __rest
     cpx<R>* buf = lds + cl * V * PL;
     cpx<R>* Ycol = reinterpret_cast<cpx<R>*>(a.Y) + (int64_t)(valid ? col : 0) * a.ldY;
     cpx<R> v[V * 8];
+    // spectrum values for this column, fetched up front so their latency
+    // overlaps the forward transform (an unused slot, vbase + u >= nvec,
+    // reads the last vector's spectrum, never past the end)
+    R lamv[MODE == B_SPEC ? 1 : V * 8];
+    if constexpr (MODE != B_SPEC) {
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            const int vl = min(vbase + u, a.nvec - 1);
+            const R* lam = reinterpret_cast<const R*>(a.lam) +
+                           (int64_t)((a.vec0 + vl) / a.vecs_per_theta) * a.lam_tstride +
+                           (int64_t)(valid ? col : 0) * L;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) lamv[u * 8 + k] = lam[edge_pos<LOG2L, LRF>(t, k)];
+        }
+    }
 #pragma unroll
     for (int u = 0; u < V; ++u) {
         const bool vu = valid && (vbase + u < a.nvec);
@@ -258,15 +278,7 @@ __global__ void __launch_bounds__(1024) k_col(StageBArgs a, const cpx<R>* __rest
         return;
     } else {
 #pragma unroll
-        for (int u = 0; u < V; ++u) {
-            // an unused slot (vbase + u >= nvec) reads the last vector's spectrum, never past the end
-            const int vu = min(vbase + u, a.nvec - 1);
-            const R* lam = reinterpret_cast<const R*>(a.lam) +
-                           (int64_t)((a.vec0 + vu) / a.vecs_per_theta) * a.lam_tstride +
-                           (int64_t)(valid ? col : 0) * L;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) v[u * 8 + k] = cscale(v[u * 8 + k], lam[edge_pos<LOG2L, LRF>(t, k)]);
-        }
+        for (int k = 0; k < V * 8; ++k) v[k] = cscale(v[k], lamv[k]);
         __syncthreads();
         pass_compute<R, LOG2L, true, 0, false, V>(v, t, twp);
 #pragma unroll
@@ -322,12 +334,60 @@ __global__ void __launch_bounds__(1024) k_row_inv(StageCArgs a, const cpx<R>* __
     const int row0 = blockIdx.x * a.RT;
     const int vec = blockIdx.y;
     const cpx<R>* Y = reinterpret_cast<const cpx<R>*>(a.Y) + vec * a.Y_vstride;
-    const int nin = a.RT * (M + 1);
-    for (int o = tid; o < nin; o += blockDim.x) {
-        const int r2 = o & (a.RT - 1);
-        const int k = o >> a.log2RT;
-        const int row = row0 + r2;
-        lds[r2 * PM + pad8(k)] = (row < a.rows_out) ? Y[(int64_t)k * a.ldY + row] : cpx<R>{(R)0, (R)0};
+    const int rr = tid / T, t = tid % T;
+    const int row = row0 + rr;
+    // Output cells of this thread (columns 2m, 2m+1 for its 8 values m) do
+    // not depend on the transform: look up their compact indices now (and,
+    // in FP64 where registers allow, the nugget-term inputs), so the loads
+    // overlap the transform.
+    constexpr bool PRE_V = (OUT == OUT_COMPACT) && sizeof(R) == 8;
+    int32_t oci[8];
+    uint32_t obits = 0u;  // 2 bits per value: columns 2m and 2m+1 observed
+    R vx[PRE_V ? 8 : 1], vy[PRE_V ? 8 : 1];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        oci[k] = 0;
+        if constexpr (OUT == OUT_COMPACT) {
+            const int c0 = 2 * edge_pos<LOG2M, LRL>(t, k);
+            if (row < a.rows_out && c0 < a.cols_out) {
+                const int w = row * a.mask.words_per_row + (c0 >> 5);
+                const uint32_t word = a.mask.bits[w];
+                const uint32_t b0 = 1u << (c0 & 31);
+                obits |= ((word & b0 ? 1u : 0u) | (word & (b0 << 1) ? 2u : 0u)) << (2 * k);
+                oci[k] = (int32_t)(a.mask.base[w] + __popc(word & (b0 - 1u)));
+            }
+        }
+    }
+    if constexpr (PRE_V) {
+        const R* vi = reinterpret_cast<const R*>(a.vin) + vec * a.vin_vstride;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t b = (obits >> (2 * k)) & 3u;
+            vx[k] = (b & 1u) ? vi[oci[k]] : (R)0;
+            vy[k] = (b & 2u) ? vi[oci[k] + (b & 1u)] : (R)0;
+        }
+    }
+    // the tile holds RT x (M + 1) values: exactly 8 per thread for k < M (all
+    // loads issued before any is used) plus the Nyquist column k = M
+    {
+        const int nt = blockDim.x;  // = RT * M / 8
+        cpx<R> t8[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int o = tid + i * nt;
+            const int r2 = o & (a.RT - 1);
+            const int k = o >> a.log2RT;
+            const int row = row0 + r2;
+            t8[i] = (row < a.rows_out) ? Y[(int64_t)k * a.ldY + row] : cpx<R>{(R)0, (R)0};
+        }
+        cpx<R> ny{(R)0, (R)0};
+        if (tid < a.RT && row0 + tid < a.rows_out) ny = Y[(int64_t)M * a.ldY + row0 + tid];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int o = tid + i * nt;
+            lds[(o & (a.RT - 1)) * PM + pad8(o >> a.log2RT)] = t8[i];
+        }
+        if (tid < a.RT) lds[tid * PM + pad8(M)] = ny;
     }
     __syncthreads();
     const int npair = a.RT * (M / 2 + 1);
@@ -349,8 +409,6 @@ __global__ void __launch_bounds__(1024) k_row_inv(StageCArgs a, const cpx<R>* __
         }
     }
     __syncthreads();
-    const int rr = tid / T, t = tid % T;
-    const int row = row0 + rr;
     cpx<R>* buf = lds + rr * PM;
     cpx<R> v[8];
     LdsPasses<R, LOG2M, true, 0, S::npass - 1>::run(v, buf, 0, t, twp);
@@ -364,19 +422,17 @@ __global__ void __launch_bounds__(1024) k_row_inv(StageCArgs a, const cpx<R>* __
         const int c0 = 2 * m;
         if (c0 >= a.cols_out) continue;
         if constexpr (OUT == OUT_COMPACT) {
-            const int w = row * a.mask.words_per_row + (c0 >> 5);
-            const uint32_t word = a.mask.bits[w];
-            const uint32_t b0 = 1u << (c0 & 31);
-            if (!(word & (b0 | (b0 << 1)))) continue;
-            int64_t ci = (int64_t)a.mask.base[w] + __popc(word & (b0 - 1u));
+            const uint32_t b = (obits >> (2 * k)) & 3u;
+            if (!b) continue;
+            int64_t ci = oci[k];
             const R e = (R)a.eta[theta];
             const R* vi = reinterpret_cast<const R*>(a.vin) + vec * a.vin_vstride;
             R* o = reinterpret_cast<R*>(a.out) + vec * a.out_vstride;
-            if (word & b0) {
-                o[ci] = v[k].x + e * vi[ci];
+            if (b & 1u) {
+                o[ci] = v[k].x + e * (PRE_V ? vx[PRE_V ? k : 0] : vi[ci]);
                 ++ci;
             }
-            if (word & (b0 << 1)) o[ci] = v[k].y + e * vi[ci];
+            if (b & 2u) o[ci] = v[k].y + e * (PRE_V ? vy[PRE_V ? k : 0] : vi[ci]);
         } else {
             R* o = reinterpret_cast<R*>(a.out) + vec * a.out_vstride + (int64_t)row * a.cols_out;
             o[c0] = (R)a.scale * v[k].x;
