@@ -36,10 +36,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=1024)
-    ap.add_argument("--points", type=int, default=16, help="parameter points per step")
+    ap.add_argument("--points", type=int, default=100, help="parameter points per step (a square grid)")
     ap.add_argument("--probes", type=int, default=20)
     ap.add_argument("--lanczos", type=int, default=50)
-    ap.add_argument("--cg-rtol", type=float, default=1e-6)
+    ap.add_argument("--cg-rtol", type=float, default=1e-8)
+    ap.add_argument("--cg-maxit", type=int, default=100000)
+    ap.add_argument("--reorth", type=int, default=1, help="full reorthogonalisation in Lanczos (FP64 coefficients)")
     ap.add_argument("--mv-batch", type=int, default=32)
     ap.add_argument("--mv-reps", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
@@ -134,13 +136,14 @@ def main():
     mv_bytes = sum(stage_bytes)
     mv_achieved = mv_bytes / (sum(stage_ms) / 1e3) / 1e9
 
-    # ---- timed steps: batched FP32-mixed likelihood over a point batch ----
+    # ---- timed steps: batched likelihood over the (range, nugget) grid ----
     side = int(round(np.sqrt(args.points)))
-    rhos = rho * np.geomspace(0.7, 1.4, side)
-    etas = eta * np.geomspace(0.7, 1.4, max(args.points // side, 1))
+    rhos = np.geomspace(0.01, 0.2, side)
+    etas = np.geomspace(0.01, 1.0, side)
     thetas = [K.theta(sigma2=1.0, tau2=float(e), range=float(r), nu=nu) for r in rhos for e in etas]
     opts32 = K.kry_opts_default(lanczos_steps=args.lanczos, num_probes=args.probes, seed=303,
-                                precision=K.KRY_FP32, cg_rtol=args.cg_rtol, cg_maxit=20000)
+                                precision=K.KRY_FP32, cg_rtol=args.cg_rtol, cg_maxit=args.cg_maxit, shift_share=1,
+                                reorth=args.reorth)
     for w in range(args.warmup):
         K.kry_loglik_batch(P.h, thetas, opts32)
         log("warmup %d done" % w)
@@ -152,23 +155,41 @@ def main():
         log("step %d done" % s)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    per_step = sum(args.probes * r["lanczos_steps_used"] + r["cg_iters"] for r in results)
+    # products actually applied per step: per range group, probes x Lanczos
+    # steps and the multi-shift CG's base iterations (its slowest nugget)
+    groups = [results[i * side:(i + 1) * side] for i in range(side)]
+    per_step = sum(args.probes * max(r["lanczos_steps_used"] for r in g_) + max(r["cg_iters"] for r in g_)
+                   for g_ in groups)
     matvecs_per_s = per_step * args.steps / dt
     evals_per_s = len(thetas) * args.steps / dt
+    log("batched: %.2f s per step, %.1f evals/s, cg iters per range %s" %
+        (dt / args.steps, evals_per_s, [max(r["cg_iters"] for r in g_) for g_ in groups]))
 
-    # ---- plain FP64 single-point form, same probes, and accuracy ----
+    # ---- plain FP64 single-point form on a stratified sample of the grid ----
     plain = None
     if not args.no_plain:
         opts64 = K.kry_opts_default(lanczos_steps=args.lanczos, num_probes=args.probes, seed=303,
-                                    precision=K.KRY_FP64, cg_rtol=1e-8, cg_maxit=20000)
-        t1 = time.perf_counter()
-        r64 = K.kry_loglik(P.h, thetas[0], opts64)
-        torch.cuda.synchronize()
-        d64 = time.perf_counter() - t1
-        rel = abs(results[0]["loglik"] - r64["loglik"]) / abs(r64["loglik"])
-        plain = dict(evals_per_s=1.0 / d64, seconds=d64, loglik=r64["loglik"], cg_iters=r64["cg_iters"],
-                     fp32_batched_rel_err_vs_fp64=rel)
-        log("plain fp64: %.2f s, fp32-batched rel err %.2e" % (d64, rel))
+                                    precision=K.KRY_FP64, cg_rtol=args.cg_rtol, cg_maxit=args.cg_maxit,
+                                    reorth=args.reorth)
+        stride = max(1, side // 2)
+        sample = [i * side + j for i in range(side) for j in range(side) if (i + j) % stride == 0]
+        errs, errs_p, secs, its = [], [], [], []
+        for k in sample:
+            t1 = time.perf_counter()
+            r64 = K.kry_loglik(P.h, thetas[k], opts64, allow_noconv=True)
+            torch.cuda.synchronize()
+            secs.append(time.perf_counter() - t1)
+            its.append(r64["cg_iters"])
+            errs.append(abs(results[k]["loglik"] - r64["loglik"]) / abs(r64["loglik"]))
+            errs_p.append(abs(results[k]["loglik_profiled"] - r64["loglik_profiled"]) / abs(r64["loglik_profiled"]))
+            log("plain fp64 point %d: %.2f s, %d CG iterations, rel err %.2e" % (k, secs[-1], its[-1], errs[-1]))
+        plain = dict(evals_per_s=len(sample) / sum(secs), sample_points=len(sample),
+                     sample="grid points (i, j) with (i + j) mod %d == 0: every range and every nugget equally often"
+                            % stride,
+                     seconds=sum(secs), cg_iters=its,
+                     batched_rel_err_vs_fp64_max=max(errs), batched_rel_err_vs_fp64_profiled_max=max(errs_p))
+        log("plain fp64: %.2f evals/s over %d sampled points; batched max rel err %.2e (profiled %.2e)" %
+            (plain["evals_per_s"], len(sample), max(errs), max(errs_p)))
 
     # ---- served form: Poisson stream of likelihood / kriging requests ----
     p_obs, emb = P.p, [P.N1, P.N2]
@@ -198,10 +219,11 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "1024x1024 grid, 30%% uniform missing (p=%d), Matern nu=1.5 range=0.05 nugget ratio 0.2; "
-                        "one step = kry_loglik_batch over %d (range, nugget) points, %d probes x %d Lanczos steps, "
-                        "CG to %g, FP32 transforms + FP64 scalars" % (p_obs, len(thetas), args.probes, args.lanczos,
-                                                                      args.cg_rtol),
+            "workload": "1024x1024 grid, 30%% uniform missing (p=%d), Matern nu=1.5, data at range 0.05 nugget "
+                        "ratio 0.2; one step = kry_loglik_batch over the %dx%d grid of range in [0.01, 0.2] x nugget "
+                        "ratio in [0.01, 1] (log-spaced), %d probes x %d Lanczos steps, CG to %g; FP32 transforms "
+                        "in Lanczos, FP64 multi-shift CG, FP64 scalars" % (p_obs, side, side, args.probes,
+                                                                          args.lanczos, args.cg_rtol),
             "global_batch": len(thetas) * args.probes,
             "embedding": emb,
         },
@@ -210,6 +232,8 @@ def main():
                            "bytes_per_launch_fp32": mv_bytes, "achieved_GBs_fp32": mv_achieved},
         "plain_fp64": plain,
         "batched_vs_plain_evals": (evals_per_s / plain["evals_per_s"]) if plain else None,
+        "batched_cg_iters_per_range": [max(r["cg_iters"] for r in g_) for g_ in groups],
+        "products_per_step": per_step,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": ["stage A (row transform)", "stage B (column transform x spectrum)",

@@ -91,6 +91,8 @@ typedef struct {
     int32_t cg_maxit;        /* CG iteration cap                            */
     int32_t solver;          /* kry_solver for the quadratic form           */
     int32_t gk_steps;        /* k for genGK                                 */
+    int32_t shift_share;     /* 1 = points of one call that differ only in
+                                the nugget ratio share Krylov spaces (below) */
 } kry_opts;
 
 typedef struct {
@@ -111,7 +113,7 @@ const char* kry_status_string(kry_status s);
 const char* kry_last_error(void);
 
 /* Defaults: m = 30, N = 10 Rademacher, seed 303, no reorth, FP64,
- * cg_rtol 1e-8, cg_maxit 20000, CG, gk_steps 100. */
+ * cg_rtol 1e-8, cg_maxit 20000, CG, gk_steps 100, no shift sharing. */
 kry_status kry_opts_default(kry_opts* out);
 
 /* ---- stage timing ----------------------------------------------------------- */
@@ -217,7 +219,22 @@ kry_status kry_loglik(kry_problem* prob, const kry_matern* theta, const kry_opts
 /* `count` parameter points on one problem, evaluated together: every
  * (theta, probe) pair is one vector of a batched product and the CG solves
  * run as one multi-RHS solve.  Same probes for every theta (common random
- * numbers). */
+ * numbers).
+ *
+ * With opts->shift_share = 1, points with equal range, smoothness and
+ * anisotropy form a group whose covariances K = Sigma_oo + eta I differ only
+ * by a multiple of I.  A Krylov space does not change under such a shift, so
+ * each group runs one Lanczos recurrence per probe on the nugget-free
+ * Sigma_oo (in opts->precision) and every point takes the Gauss quadrature
+ * of log(x + eta) on the shifted tridiagonal T + eta I; the quadratic forms
+ * of the group come from one multi-shift CG recurrence on Sigma_oo in FP64
+ * (vectors and products), which reaches cg_rtol for every nugget without
+ * residual refinement.  Each point's result depends only on its own
+ * parameters, not on which other points share the call.  Lanczos breakdown
+ * is tested on Sigma_oo, so lanczos_steps_used can differ from the unshared
+ * form.  Q is accumulated from the multi-shift recurrence's scalars (the
+ * shifted solutions are never formed) and cg_relres is the recursive
+ * residual |zeta| ||r|| / ||y||. */
 kry_status kry_loglik_batch(kry_problem* prob, const kry_matern* thetas, int32_t count,
                             const kry_opts* opts, kry_loglik_result* out /* count */);
 /* Maximise l_p over (log range, log eta) -- bit 0 of free_mask frees the

@@ -116,6 +116,7 @@ void check_opts(const kry_opts* o) {
     KRY_REQUIRE(o->cg_maxit >= 1, "cg_maxit must be >= 1");
     KRY_REQUIRE(o->solver == KRY_SOLVER_CG || o->solver == KRY_SOLVER_GENGK, "bad solver");
     KRY_REQUIRE(o->gk_steps >= 1 && o->gk_steps <= 2000, "gk_steps must be in [1, 2000]");
+    KRY_REQUIRE(o->shift_share == 0 || o->shift_share == 1, "shift_share must be 0 or 1");
 }
 
 int nprobes_of(const kry_opts* o) {
@@ -401,11 +402,21 @@ struct LoglikWork {
     std::vector<int> steps;
 };
 
+// Quadrature outputs that read shifted copies of the recurrences' tridiagonals:
+// output v uses recurrence src[v] with T + shift[v] I (device arrays).
+struct ShiftQuad {
+    int nout = 0;
+    const int* src = nullptr;
+    const double* shift = nullptr;
+};
+
 // SLQ for `count` parameter points sharing the probes (common random numbers).
-// Vectors are ordered theta-major: v = t * nprobe + k.
+// Vectors are ordered theta-major: v = t * nprobe + k.  With sq, W.gamma holds
+// sq->nout shifted quadratures instead of one per recurrence.
 template <typename R>
 void slq_device(Problem& P, const kry_opts* o, const void* lam, int64_t lam_tstride, const double* d_eta, int count,
-                LoglikWork& W, std::vector<double>* alpha_out, std::vector<double>* beta_out, hipStream_t st) {
+                LoglikWork& W, std::vector<double>* alpha_out, std::vector<double>* beta_out, hipStream_t st,
+                const ShiftQuad* sq = nullptr) {
     const int np = nprobes_of(o);
     const int nvec = count * np;
     const int m = o->lanczos_steps;
@@ -427,7 +438,7 @@ void slq_device(Problem& P, const kry_opts* o, const void* lam, int64_t lam_tstr
         B.steps = a.take<int>(nvec);
         B.partial = a.take<double>((size_t)nvec * (m + 1) * nblk);
         B.h = a.take<double>((size_t)nvec * (m + 1));
-        gamma = a.take<double>(nvec);
+        gamma = a.take<double>(sq ? std::max(nvec, sq->nout) : nvec);
     };
     with_arena(P, lay);
     make_probes<R>(P, np, o->seed, o->probe_kind == KRY_PROBE_COLOURED ? o->colour_period : 0, Z, st);
@@ -435,10 +446,12 @@ void slq_device(Problem& P, const kry_opts* o, const void* lam, int64_t lam_tstr
         KRY_HIP(hipMemcpyAsync(Z + (size_t)t * np * p, Z, (size_t)np * p * sizeof(R), hipMemcpyDeviceToDevice, st));
     auto A = masked_op<R>(P, lam, lam_tstride, np, d_eta);
     lanczos_run<R>(A, p, nvec, m, reorth, Z, B, st);
-    quadrature(B.alpha, B.beta, B.steps, B.znorm2, nvec, nvec, gamma, st);
-    W.gamma.resize(nvec);
+    const int nout = sq ? sq->nout : nvec;
+    if (sq) quadrature(B.alpha, B.beta, B.steps, B.znorm2, nout, nvec, gamma, st, sq->src, sq->shift);
+    else quadrature(B.alpha, B.beta, B.steps, B.znorm2, nvec, nvec, gamma, st);
+    W.gamma.resize(nout);
     W.steps.resize(nvec);
-    KRY_HIP(hipMemcpyAsync(W.gamma.data(), gamma, nvec * sizeof(double), hipMemcpyDeviceToHost, st));
+    KRY_HIP(hipMemcpyAsync(W.gamma.data(), gamma, nout * sizeof(double), hipMemcpyDeviceToHost, st));
     KRY_HIP(hipMemcpyAsync(W.steps.data(), B.steps, nvec * sizeof(int), hipMemcpyDeviceToHost, st));
     if (alpha_out) {
         alpha_out->resize((size_t)m * nvec);
@@ -639,6 +652,121 @@ void gengk_device(Problem& P, const Matern& th, const kry_opts* o, GkOut& G, dou
     }
 }
 
+// Points with equal range, smoothness and anisotropy: their covariances
+// differ only in the nugget ratio.  Returns the group of every point and the
+// first point of every group.
+std::vector<int> shift_groups(const kry_matern* th, int count, std::vector<int>& rep) {
+    std::vector<int> grp(count);
+    rep.clear();
+    for (int t = 0; t < count; ++t) {
+        int g = 0;
+        for (; g < (int)rep.size(); ++g) {
+            const kry_matern& a = th[rep[g]];
+            if (a.range == th[t].range && a.nu == th[t].nu && a.aniso_ratio == th[t].aniso_ratio &&
+                a.aniso_angle == th[t].aniso_angle)
+                break;
+        }
+        if (g == (int)rep.size()) rep.push_back(t);
+        grp[t] = g;
+    }
+    return grp;
+}
+
+// Likelihood of `count` points where every group of nugget-only variants
+// shares its Krylov spaces: Lanczos on the nugget-free Sigma_oo per probe and
+// group, quadrature of T + eta I per point; multi-shift CG on Sigma_oo with
+// shifts eta for the quadratic forms.
+void loglik_points_shared(Problem& P, const kry_matern* thetas, int count, const kry_opts* o,
+                          kry_loglik_result* out, hipStream_t st) {
+    Ctx& C = *P.ctx;
+    const int np = nprobes_of(o);
+    const int64_t nspec = (int64_t)(P.N2 / 2 + 1) * P.N1;
+    const bool fp32 = o->precision == KRY_FP32;
+    const int64_t p = P.p;
+    std::vector<int> rep;
+    const std::vector<int> grp = shift_groups(thetas, count, rep);
+    const int G = (int)rep.size();
+    P.spec_multi64.ensure(C, (size_t)G * nspec * sizeof(double));
+    if (fp32) P.spec_multi32.ensure(C, (size_t)G * nspec * sizeof(float));
+    for (int g = 0; g < G; ++g) {
+        const Matern th = to_matern(&thetas[rep[g]]);
+        double lo, hi;
+        double* dst = P.spec_multi64.as<double>() + (size_t)g * nspec;
+        spectrum_device(P, P.N1, P.N2, th, dst, &lo, &hi, st);
+        spectrum_scale(dst, nspec, 1.0 / ((double)P.N1 * P.N2), false, dst,
+                       fp32 ? P.spec_multi32.as<float>() + (size_t)g * nspec : nullptr, st);
+    }
+    // zero nugget per group, and per (point, probe) output its recurrence and shift
+    const int nout = count * np;
+    std::vector<double> eta(count), shift(nout), zeros(G, 0.0);
+    std::vector<int> src(nout);
+    for (int t = 0; t < count; ++t) {
+        eta[t] = thetas[t].tau2 / thetas[t].sigma2;
+        for (int k = 0; k < np; ++k) {
+            src[(size_t)t * np + k] = grp[t] * np + k;
+            shift[(size_t)t * np + k] = eta[t];
+        }
+    }
+    DevBuf& sb = P.tmp3;
+    const size_t zoff = 0, soff = ((size_t)G * 8 + 255) & ~size_t(255);
+    const size_t ioff = soff + (((size_t)nout * 8 + 255) & ~size_t(255));
+    sb.ensure(C, ioff + (size_t)nout * 4 + 256);
+    double* d_zero = reinterpret_cast<double*>(sb.as<char>() + zoff);
+    double* d_shift = reinterpret_cast<double*>(sb.as<char>() + soff);
+    int* d_src = reinterpret_cast<int*>(sb.as<char>() + ioff);
+    KRY_HIP(hipMemcpyAsync(d_zero, zeros.data(), G * sizeof(double), hipMemcpyHostToDevice, st));
+    KRY_HIP(hipMemcpyAsync(d_shift, shift.data(), nout * sizeof(double), hipMemcpyHostToDevice, st));
+    KRY_HIP(hipMemcpyAsync(d_src, src.data(), nout * sizeof(int), hipMemcpyHostToDevice, st));
+    ShiftQuad sq{nout, d_src, d_shift};
+    LoglikWork W;
+    if (fp32) slq_device<float>(P, o, P.spec_multi32.ptr, nspec, d_zero, G, W, nullptr, nullptr, st, &sq);
+    else slq_device<double>(P, o, P.spec_multi64.ptr, nspec, d_zero, G, W, nullptr, nullptr, st, &sq);
+    std::vector<double> Q(count, 0.0), relres(count, 0.0);
+    std::vector<int> iters(count, 0);
+    if (o->solver == KRY_SOLVER_CG) {
+        const int nblk = dot_blocks(p);
+        MsCgBuffers B{};
+        auto lay = [&](Arena& a) {
+            B.r = a.take<double>((size_t)G * p);
+            B.p = a.take<double>((size_t)G * p);
+            B.w = a.take<double>((size_t)G * p);
+            for (double** d : {&B.rr, &B.pw, &B.alpha, &B.alpha_old, &B.beta, &B.beta_old, &B.bnorm2})
+                *d = a.take<double>(G);
+            B.rc = a.take<double>(2 * (size_t)G);
+            for (double** d : {&B.zeta, &B.zeta_old, &B.zeta_new, &B.alpha_s, &B.sigma, &B.d, &B.Q, &B.relres})
+                *d = a.take<double>(count);
+            for (int** d : {&B.active, &B.iters, &B.limit, &B.pos, &B.list}) *d = a.take<int>(count);
+            B.partial = a.take<double>(2 * (size_t)G * nblk);
+        };
+        with_arena(P, lay);
+        auto A = masked_op<double>(P, P.spec_multi64.ptr, nspec, 1, d_zero);
+        double* lam64 = P.spec_multi64.as<double>();
+        auto swp = [&](int a, int b) { swap_vectors<double>(lam64, nspec, a, b, nspec, st); };
+        mscg_run(A, swp, p, G, grp, eta, P.y64.as<double>(), o->cg_rtol, o->cg_maxit, B, iters, relres, Q, st);
+    } else {
+        for (int t = 0; t < count; ++t) {
+            GkOut Gk;
+            const Matern th = to_matern(&thetas[t]);
+            if (fp32) gengk_device<float>(P, th, o, Gk, nullptr, st);
+            else gengk_device<double>(P, th, o, Gk, nullptr, st);
+            Q[t] = Gk.J;
+            iters[t] = o->gk_steps;
+        }
+    }
+    for (int t = 0; t < count; ++t) {
+        double est, se;
+        combine(W.gamma.data() + (size_t)t * np, np, o->probe_kind == KRY_PROBE_COLOURED, &est, &se);
+        kry_loglik_result& r = out[t];
+        std::memset(&r, 0, sizeof(r));
+        assemble(&r, p, est, se, Q[t], thetas[t].sigma2);
+        int smax = 0;
+        for (int k = 0; k < np; ++k) smax = std::max(smax, W.steps[(size_t)grp[t] * np + k]);
+        r.lanczos_steps_used = smax;
+        r.cg_iters = iters[t];
+        r.cg_relres = relres[t];
+    }
+}
+
 bool any_not_converged(const kry_loglik_result* r, int count, const kry_opts* o) {
     if (o->solver != KRY_SOLVER_CG) return false;
     for (int t = 0; t < count; ++t)
@@ -653,6 +781,10 @@ namespace kry {
 // handling (each with its own spectrum) on one problem.
 void loglik_points(Problem& P, const kry_matern* thetas, int count, const kry_opts* o, kry_loglik_result* out,
                    hipStream_t st) {
+    if (o->shift_share) {
+        loglik_points_shared(P, thetas, count, o, out, st);
+        return;
+    }
     Ctx& C = *P.ctx;
     const int np = nprobes_of(o);
     const int64_t nspec = (int64_t)(P.N2 / 2 + 1) * P.N1;
@@ -762,6 +894,7 @@ kry_status kry_opts_default(kry_opts* out) {
         o.cg_maxit = 20000;
         o.solver = KRY_SOLVER_CG;
         o.gk_steps = 100;
+        o.shift_share = 0;
         *out = o;
     });
 }
@@ -1337,12 +1470,51 @@ kry_status kry_loglik_batch(kry_problem* prob, const kry_matern* thetas, int32_t
         const int np = nprobes_of(opts);
         const size_t per_point = (size_t)np * P.p * (opts->precision == KRY_FP32 ? 4 : 8) *
                                  (opts->reorth ? opts->lanczos_steps + 3 : 5);
-        int chunk = (int)std::max<size_t>(1, (size_t)16e9 / std::max<size_t>(per_point, 1));
-        chunk = std::min(chunk, (int)count);
+        // workspace per chunk: 48 GB, or half the context's budget when one is set
+        size_t cap = (size_t)48e9;
+        if (P.ctx->budget > 0) cap = std::min<size_t>(cap, P.ctx->budget / 2);
         std::vector<kry_loglik_result> res(count);
-        for (int t0 = 0; t0 < count; t0 += chunk) {
-            const int c = std::min(chunk, (int)count - t0);
-            loglik_points(P, thetas + t0, c, opts, res.data() + t0, st);
+        if (opts->shift_share) {
+            // whole groups per chunk: one Lanczos block and 3 CG base vectors
+            // per group, 2 FP64 vectors per point; results do not depend on
+            // the chunking
+            std::vector<int> rep;
+            const std::vector<int> grp = shift_groups(thetas, count, rep);
+            const size_t per_group = per_point + 3 * (size_t)P.p * 8, per_shift = 2 * (size_t)P.p * 8;
+            std::vector<std::vector<int>> members(rep.size());
+            for (int t = 0; t < count; ++t) members[grp[t]].push_back(t);
+            std::vector<int> idx;
+            size_t mem = 0;
+            auto flush = [&]() {
+                if (idx.empty()) return;
+                std::vector<kry_matern> th(idx.size());
+                std::vector<kry_loglik_result> r(idx.size());
+                for (size_t i = 0; i < idx.size(); ++i) th[i] = thetas[idx[i]];
+                loglik_points(P, th.data(), (int)idx.size(), opts, r.data(), st);
+                for (size_t i = 0; i < idx.size(); ++i) res[idx[i]] = r[i];
+                idx.clear();
+                mem = 0;
+            };
+            for (const auto& mb : members) {
+                if (mem > 0 && mem + per_group + mb.size() * per_shift > cap) flush();
+                mem += per_group;
+                for (int t : mb) {
+                    if (mem + per_shift > cap && mem > per_group) {
+                        flush();
+                        mem = per_group;
+                    }
+                    idx.push_back(t);
+                    mem += per_shift;
+                }
+            }
+            flush();
+        } else {
+            int chunk = (int)std::max<size_t>(1, cap / std::max<size_t>(per_point, 1));
+            chunk = std::min(chunk, (int)count);
+            for (int t0 = 0; t0 < count; t0 += chunk) {
+                const int c = std::min(chunk, (int)count - t0);
+                loglik_points(P, thetas + t0, c, opts, res.data() + t0, st);
+            }
         }
         std::copy(res.begin(), res.end(), out);
         noconv = any_not_converged(out, count, opts);

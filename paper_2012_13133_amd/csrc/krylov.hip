@@ -301,20 +301,26 @@ template void lanczos_run<float>(const MatvecFn<float>&, int64_t, int, int, bool
 // Martin, Reinsch & Wilkinson, 1968), tracking only the first component of
 // every eigenvector (Golub & Welsch, 1969); then
 //   gamma = ||z||^2 sum_i tau_i^2 log theta_i.
+// Output v reads the tridiagonal of recurrence src[v] (v itself when src is
+// NULL) shifted by shift[v] (none when NULL): T + shift I has the same
+// eigenvectors and eigenvalues moved by the shift.
 __global__ void k_quadrature(const double* __restrict__ alpha, const double* __restrict__ beta,
                              const int* __restrict__ steps, const double* __restrict__ znorm2, int nvec,
-                             int64_t coef_stride /* distance between steps j and j+1 */, double* __restrict__ gamma) {
+                             int64_t coef_stride /* distance between steps j and j+1 */, double* __restrict__ gamma,
+                             const int* __restrict__ src, const double* __restrict__ shift) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nvec) return;
-    const int n = steps[v];
+    const int u = src ? src[v] : v;
+    const double sh = shift ? shift[v] : 0.0;
+    const int n = steps[u];
     if (n <= 0) {
         gamma[v] = 0.0;
         return;
     }
     double d[KRY_MAX_LANCZOS], e[KRY_MAX_LANCZOS], z[KRY_MAX_LANCZOS];
     for (int i = 0; i < n; ++i) {
-        d[i] = alpha[i * coef_stride + v];
-        e[i] = (i + 1 < n) ? beta[i * coef_stride + v] : 0.0;
+        d[i] = alpha[i * coef_stride + u] + sh;
+        e[i] = (i + 1 < n) ? beta[i * coef_stride + u] : 0.0;
         z[i] = (i == 0) ? 1.0 : 0.0;
     }
     const double eps = 2.220446049250313e-16;
@@ -361,13 +367,13 @@ __global__ void k_quadrature(const double* __restrict__ alpha, const double* __r
     }
     double acc = 0.0;
     for (int i = 0; i < n; ++i) acc += z[i] * z[i] * log(d[i]);
-    gamma[v] = znorm2[v] * acc;
+    gamma[v] = znorm2[u] * acc;
 }
 
 void quadrature(const double* alpha, const double* beta, const int* steps, const double* znorm2, int nvec,
-                int64_t coef_stride, double* gamma, hipStream_t st) {
+                int64_t coef_stride, double* gamma, hipStream_t st, const int* src, const double* shift) {
     hipLaunchKernelGGL(k_quadrature, dim3((nvec + 63) / 64), dim3(64), 0, st, alpha, beta, steps, znorm2, nvec,
-                       coef_stride, gamma);
+                       coef_stride, gamma, src, shift);
     KRY_HIP(hipGetLastError());
 }
 
@@ -492,6 +498,273 @@ template void cg_run<double>(const MatvecFn<double>&, int64_t, int, const double
                              const std::vector<int>*);
 template void cg_run<float>(const MatvecFn<float>&, int64_t, int, const float*, float*, double, int, CgBuffers<float>&,
                             std::vector<int>&, std::vector<double>&, hipStream_t, const std::vector<int>*);
+
+// ---- multi-shift conjugate gradients ---------------------------------------------------
+// One CG recurrence per group on its base operator A; the shifted system
+// (A + sigma I) x = b has, in the same Krylov space, the residual zeta r of the
+// base residual r (Jegerlehner, hep-lat/9612014).  With the base's alpha_k,
+// beta_k (alpha_{-1} = 1, beta_{-1} = 0, zeta_0 = zeta_{-1} = 1):
+//   zeta_{k+1} = zeta_k zeta_{k-1} alpha_{k-1} /
+//                (alpha_k beta_{k-1} (zeta_{k-1} - zeta_k) + zeta_{k-1} alpha_{k-1} (1 + sigma alpha_k))
+//   alpha^s_k = alpha_k zeta_{k+1} / zeta_k,    beta^s_k = beta_k (zeta_{k+1} / zeta_k)^2
+//   x^s += alpha^s_k p^s,                       p^s = zeta_{k+1} r_{k+1} + beta^s_k p^s.
+// Only Q^s = b . x^s is wanted, so the shifted vectors are never formed:
+// with c_k = b . r_k and d^s = b . p^s,
+//   Q^s += alpha^s_k d^s,                       d^s = zeta_{k+1} c_{k+1} + beta^s_k d^s,
+// which leaves one base CG (vectors r, p, w) per group and scalars per shift.
+// A shift stops once |zeta_{k+1}| ||r_{k+1}|| <= rtol ||b|| (or at its
+// iteration cap); its values never depend on the other shifts or groups.
+
+__global__ void k_ms_init(const double* __restrict__ bb, int G, int S, double* __restrict__ rr,
+                          double* __restrict__ bnorm2, double* __restrict__ alpha_old, double* __restrict__ beta_old,
+                          double* __restrict__ zeta, double* __restrict__ zeta_old, double* __restrict__ d,
+                          double* __restrict__ Q, double* __restrict__ relres, int* __restrict__ active,
+                          int* __restrict__ iters, const int* __restrict__ limit) {
+    const double b2 = bb[0];
+    for (int q = threadIdx.x; q < G; q += blockDim.x) {
+        rr[q] = b2;
+        bnorm2[q] = b2;
+        alpha_old[q] = 1.0;
+        beta_old[q] = 0.0;
+    }
+    for (int s = threadIdx.x; s < S; s += blockDim.x) {
+        zeta[s] = 1.0;
+        zeta_old[s] = 1.0;
+        d[s] = b2;
+        Q[s] = 0.0;
+        relres[s] = b2 > 0.0 ? 1.0 : 0.0;
+        active[s] = b2 > 0.0 && limit[s] > 0;
+        iters[s] = 0;
+    }
+}
+
+// base alpha per active position, then zeta_{k+1} and alpha^s of the listed shifts
+__global__ void k_ms_alpha(int Gact, const double* __restrict__ rr, const double* __restrict__ pw,
+                           double* __restrict__ alpha, const double* __restrict__ alpha_old,
+                           const double* __restrict__ beta_old, const int* __restrict__ list, int nlist,
+                           const int* __restrict__ pos, const double* __restrict__ sigma,
+                           const double* __restrict__ zeta, const double* __restrict__ zeta_old,
+                           double* __restrict__ zeta_new, double* __restrict__ alpha_s, int* __restrict__ active) {
+    for (int q = threadIdx.x; q < Gact; q += blockDim.x) alpha[q] = pw[q] > 0.0 ? rr[q] / pw[q] : 0.0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < nlist; i += blockDim.x) {
+        const int s = list[i];
+        if (!active[s]) continue;
+        const int q = pos[s];
+        const double z = zeta[s];
+        if (!(pw[q] > 0.0) || !(fabs(z) > 0.0)) {  // breakdown of the base, or a vanished shifted residual
+            active[s] = 0;
+            continue;
+        }
+        const double a = alpha[q], ao = alpha_old[q], bo = beta_old[q], zo = zeta_old[s];
+        const double den = a * bo * (zo - z) + zo * ao * (1.0 + sigma[s] * a);
+        const double zn = z * zo * ao / den;
+        zeta_new[s] = zn;
+        alpha_s[s] = a * zn / z;
+    }
+}
+
+// r_q -= alpha_q w_q; partials of r_q . r_q (rows 0..Gact-1) and b . r_q
+// (rows Gact..2 Gact-1)
+__global__ void __launch_bounds__(RB) k_ms_r(double* __restrict__ r, const double* __restrict__ w,
+                                             const double* __restrict__ b, const double* __restrict__ alpha,
+                                             int Gact, int64_t n, double* __restrict__ partial) {
+    __shared__ double sh[RB];
+    const int nblk = gridDim.x, q = blockIdx.y;
+    const double a = alpha[q];
+    double acc = 0.0, accb = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)nblk * RB) {
+        const int64_t k = q * n + i;
+        const double ri = r[k] - a * w[k];
+        r[k] = ri;
+        acc += ri * ri;
+        accb += b[i] * ri;
+    }
+    acc = block_sum(acc, sh);
+    accb = block_sum(accb, sh);
+    if (threadIdx.x == 0) {
+        partial[q * nblk + blockIdx.x] = acc;
+        partial[(Gact + q) * nblk + blockIdx.x] = accb;
+    }
+}
+
+// base beta and roll of the position scalars; Q^s and d^s, beta^s, the
+// stopping test and the zeta roll of the listed shifts.  rc holds ||r_{k+1}||^2
+// (rows 0..Gact-1) and b . r_{k+1} (rows Gact..).
+__global__ void k_ms_beta(int Gact, double* __restrict__ rr, const double* __restrict__ rc,
+                          double* __restrict__ beta, const double* __restrict__ alpha, double* __restrict__ alpha_old,
+                          double* __restrict__ beta_old, const double* __restrict__ bnorm2,
+                          const int* __restrict__ list, int nlist, const int* __restrict__ pos,
+                          double* __restrict__ zeta, double* __restrict__ zeta_old,
+                          const double* __restrict__ zeta_new, const double* __restrict__ alpha_s,
+                          double* __restrict__ d, double* __restrict__ Q, double* __restrict__ relres,
+                          int* __restrict__ active, int* __restrict__ iters, const int* __restrict__ limit,
+                          double rtol) {
+    for (int i = threadIdx.x; i < nlist; i += blockDim.x) {
+        const int s = list[i];
+        if (!active[s]) continue;
+        const int q = pos[s];
+        const double rn = rc[q];
+        const double b = rr[q] > 0.0 ? rn / rr[q] : 0.0;
+        const double z = zeta[s], zn = zeta_new[s];
+        const double ratio = zn / z;
+        const double bs = b * ratio * ratio;
+        Q[s] += alpha_s[s] * d[s];
+        d[s] = zn * rc[Gact + q] + bs * d[s];
+        const int it = iters[s] + 1;
+        iters[s] = it;
+        const double res = fabs(zn) * sqrt(rn);
+        const double bn = sqrt(bnorm2[q]);
+        relres[s] = res / bn;
+        if (!(res > rtol * bn) || it >= limit[s]) active[s] = 0;
+        zeta_old[s] = z;
+        zeta[s] = zn;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < Gact; q += blockDim.x) {
+        const double b = rr[q] > 0.0 ? rc[q] / rr[q] : 0.0;
+        beta[q] = b;
+        alpha_old[q] = alpha[q];
+        beta_old[q] = b;
+        rr[q] = rc[q];
+    }
+}
+
+// p_q = r_q + beta_q p_q
+__global__ void k_ms_p(double* __restrict__ p, const double* __restrict__ r, const double* __restrict__ beta,
+                       int64_t n) {
+    const int q = blockIdx.y;
+    const double b = beta[q];
+    double* pq = p + q * n;
+    const double* rq = r + q * n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        pq[i] = rq[i] + b * pq[i];
+}
+
+template <typename T>
+__global__ void k_swap_vec(T* __restrict__ base, int64_t stride, int a, int b, int64_t n) {
+    T* pa = base + a * stride;
+    T* pb = base + b * stride;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const T t = pa[i];
+        pa[i] = pb[i];
+        pb[i] = t;
+    }
+}
+
+template <typename T>
+void swap_vectors(T* base, int64_t stride, int a, int b, int64_t n, hipStream_t st) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_swap_vec<T>, dim3((unsigned)blocks), dim3(256), 0, st, base, stride, a, b, n);
+    KRY_HIP(hipGetLastError());
+}
+template void swap_vectors<double>(double*, int64_t, int, int, int64_t, hipStream_t);
+template void swap_vectors<float>(float*, int64_t, int, int, int64_t, hipStream_t);
+
+__global__ void k_ms_swap_scalars(double* rr, double* bnorm2, double* alpha_old, double* beta_old, int a, int b) {
+    if (threadIdx.x != 0) return;
+    double* arr[4] = {rr, bnorm2, alpha_old, beta_old};
+    for (double* v : arr) {
+        const double t = v[a];
+        v[a] = v[b];
+        v[b] = t;
+    }
+}
+
+void mscg_run(const MatvecFn<double>& A, const std::function<void(int, int)>& swap, int64_t n, int G,
+              const std::vector<int>& group_of_shift, const std::vector<double>& sigma, const double* b, double rtol,
+              int maxit, MsCgBuffers& B, std::vector<int>& iters, std::vector<double>& relres,
+              std::vector<double>& Q, hipStream_t st) {
+    const int S = (int)group_of_shift.size();
+    const int nblk = dot_blocks(n);
+    const size_t vb = (size_t)n * sizeof(double);
+    for (int q = 0; q < G; ++q) {
+        KRY_HIP(hipMemcpyAsync(B.r + (size_t)q * n, b, vb, hipMemcpyDeviceToDevice, st));
+        KRY_HIP(hipMemcpyAsync(B.p + (size_t)q * n, b, vb, hipMemcpyDeviceToDevice, st));
+    }
+    // host state: group -> position, position -> group, active shift list
+    std::vector<int> pos_of(G), grp_at(G), pos(S), list(S), lim(S, maxit), act(S);
+    for (int g = 0; g < G; ++g) pos_of[g] = grp_at[g] = g;
+    for (int s = 0; s < S; ++s) {
+        pos[s] = group_of_shift[s];
+        list[s] = s;
+    }
+    KRY_HIP(hipMemcpyAsync(B.pos, pos.data(), S * sizeof(int), hipMemcpyHostToDevice, st));
+    KRY_HIP(hipMemcpyAsync(B.list, list.data(), S * sizeof(int), hipMemcpyHostToDevice, st));
+    KRY_HIP(hipMemcpyAsync(B.limit, lim.data(), S * sizeof(int), hipMemcpyHostToDevice, st));
+    KRY_HIP(hipMemcpyAsync(B.sigma, sigma.data(), S * sizeof(double), hipMemcpyHostToDevice, st));
+    dot_batched<double>(b, 0, b, 0, n, 1, B.partial, B.rc, st);
+    hipLaunchKernelGGL(k_ms_init, dim3(1), dim3(256), 0, st, B.rc, G, S, B.rr, B.bnorm2, B.alpha_old, B.beta_old,
+                       B.zeta, B.zeta_old, B.d, B.Q, B.relres, B.active, B.iters, B.limit);
+    KRY_HIP(hipGetLastError());
+    int Gact = G, nlist = S;
+    int64_t ublocks = (n + 255) / 256;
+    if (ublocks > 1024) ublocks = 1024;
+    const int check = 16;
+    for (int it = 0; it < maxit && Gact > 0; ++it) {
+        A(B.p, B.w, Gact, st);
+        dot_batched<double>(B.p, n, B.w, n, n, Gact, B.partial, B.pw, st);
+        hipLaunchKernelGGL(k_ms_alpha, dim3(1), dim3(256), 0, st, Gact, B.rr, B.pw, B.alpha, B.alpha_old, B.beta_old,
+                           B.list, nlist, B.pos, B.sigma, B.zeta, B.zeta_old, B.zeta_new, B.alpha_s, B.active);
+        KRY_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_ms_r, dim3(nblk, Gact), dim3(RB), 0, st, B.r, B.w, b, B.alpha, Gact, n, B.partial);
+        KRY_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_reduce, dim3(2 * Gact), dim3(RB), 0, st, B.partial, nblk, B.rc, (int64_t)1);
+        KRY_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_ms_beta, dim3(1), dim3(256), 0, st, Gact, B.rr, B.rc, B.beta, B.alpha, B.alpha_old,
+                           B.beta_old, B.bnorm2, B.list, nlist, B.pos, B.zeta, B.zeta_old, B.zeta_new, B.alpha_s, B.d,
+                           B.Q, B.relres, B.active, B.iters, B.limit, rtol);
+        KRY_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_ms_p, dim3((unsigned)ublocks, Gact), dim3(256), 0, st, B.p, B.r, B.beta, n);
+        KRY_HIP(hipGetLastError());
+        if ((it + 1) % check != 0 && it + 1 != maxit) continue;
+        KRY_HIP(hipMemcpyAsync(act.data(), B.active, S * sizeof(int), hipMemcpyDeviceToHost, st));
+        KRY_HIP(hipStreamSynchronize(st));
+        std::vector<char> alive(G, 0);
+        nlist = 0;
+        for (int s = 0; s < S; ++s)
+            if (act[s]) {
+                list[nlist++] = s;
+                alive[group_of_shift[s]] = 1;
+            }
+        // move groups with no running shift behind the active positions
+        bool moved = false;
+        int q = 0;
+        while (q < Gact) {
+            if (alive[grp_at[q]]) {
+                ++q;
+                continue;
+            }
+            const int last = Gact - 1;
+            if (last != q) {
+                swap_vectors<double>(B.r, n, q, last, n, st);
+                swap_vectors<double>(B.p, n, q, last, n, st);
+                hipLaunchKernelGGL(k_ms_swap_scalars, dim3(1), dim3(64), 0, st, B.rr, B.bnorm2, B.alpha_old,
+                                   B.beta_old, q, last);
+                KRY_HIP(hipGetLastError());
+                swap(q, last);
+                std::swap(grp_at[q], grp_at[last]);
+                pos_of[grp_at[q]] = q;
+                pos_of[grp_at[last]] = last;
+                moved = true;
+            }
+            --Gact;
+        }
+        if (moved) {
+            for (int s = 0; s < S; ++s) pos[s] = pos_of[group_of_shift[s]];
+            KRY_HIP(hipMemcpyAsync(B.pos, pos.data(), S * sizeof(int), hipMemcpyHostToDevice, st));
+        }
+        if (nlist > 0) KRY_HIP(hipMemcpyAsync(B.list, list.data(), nlist * sizeof(int), hipMemcpyHostToDevice, st));
+    }
+    iters.resize(S);
+    relres.resize(S);
+    Q.resize(S);
+    KRY_HIP(hipMemcpyAsync(iters.data(), B.iters, S * sizeof(int), hipMemcpyDeviceToHost, st));
+    KRY_HIP(hipMemcpyAsync(relres.data(), B.relres, S * sizeof(double), hipMemcpyDeviceToHost, st));
+    KRY_HIP(hipMemcpyAsync(Q.data(), B.Q, S * sizeof(double), hipMemcpyDeviceToHost, st));
+    KRY_HIP(hipStreamSynchronize(st));
+}
 
 // y = a x + b y  (FP64 coefficients per vector)
 template <typename R>

@@ -37,11 +37,36 @@ struct CgBuffers {
     int* limit;  // per-vector iteration cap (device, nvec)
 };
 
+// Multi-shift CG: Q_s = b^T (A_g + sigma_s I)^{-1} b for shifts s, each tied
+// to a group g whose base operator A_g supplies the shared Krylov space; the
+// shifted solutions themselves are not formed.  Group state lives at packed
+// positions 0..G-1; a group whose shifts have all stopped is moved behind the
+// active ones so products run on active groups only.  All FP64.
+struct MsCgBuffers {
+    double *r, *p, *w;      // G x n, by position
+    double *rr, *rc, *pw, *alpha, *alpha_old, *beta, *beta_old, *bnorm2;  // G (rc: 2 G), by position
+    double *zeta, *zeta_old, *zeta_new, *alpha_s, *sigma, *d, *Q, *relres; // S
+    int *active, *iters, *limit, *pos, *list;                             // S
+    double* partial;        // 2 G x nblk
+};
+// A(x, y, k, st) applies the base operators of positions 0..k-1;
+// swap(a, b) exchanges whatever the caller keeps per position (spectra).
+void mscg_run(const MatvecFn<double>& A, const std::function<void(int, int)>& swap, int64_t n, int G,
+              const std::vector<int>& group_of_shift, const std::vector<double>& sigma, const double* b, double rtol,
+              int maxit, MsCgBuffers& B, std::vector<int>& iters, std::vector<double>& relres,
+              std::vector<double>& Q, hipStream_t st);
+// Exchange vectors a and b (each n elements) of base + k * stride.
+template <typename T>
+void swap_vectors(T* base, int64_t stride, int a, int b, int64_t n, hipStream_t st);
+
 template <typename R>
 void lanczos_run(const MatvecFn<R>& A, int64_t n, int nvec, int m, bool reorth, const R* Z, LanczosBuffers<R>& B,
                  hipStream_t st);
+// gamma for nvec outputs; output v uses recurrence src[v] shifted by
+// shift[v] when those (device) arrays are given.
 void quadrature(const double* alpha, const double* beta, const int* steps, const double* znorm2, int nvec,
-                int64_t coef_stride, double* gamma, hipStream_t st);
+                int64_t coef_stride, double* gamma, hipStream_t st, const int* src = nullptr,
+                const double* shift = nullptr);
 // CG on nvec systems; vector v stops at ||r|| <= rtol ||b|| or after
 // limits[v] iterations (limits == nullptr: maxit for all).
 template <typename R>

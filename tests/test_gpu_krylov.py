@@ -294,3 +294,66 @@ def test_error_paths():
         assert e.value.status == K.KRY_ENOMEM
     finally:
         K.kry_ctx_destroy(small)
+
+
+def _shift_case():
+    n1, n2 = 24, 24
+    g, mask, y, yo = _problem(n1, n2, CONFIG1, 0.3)
+    thetas = [theta(r, 1.5, tau2=e) for r in (0.05, 0.15) for e in (0.02, 0.2, 1.0)]
+    thetas.append(theta(0.1, 0.5, tau2=0.3))  # a group of one
+    return n1, n2, g, mask, y, yo, thetas
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_shift_share_matches_oracle(precision):
+    # one Lanczos recurrence on Sigma_oo per group and probe, quadrature of
+    # T + eta I per point, and one multi-shift CG per group: the oracle runs
+    # Lanczos on each K = Sigma_oo + eta I and solves each K densely
+    n1, n2, g, mask, y, yo, thetas = _shift_case()
+    r, c = observed_cells(mask)
+    m, npr = 40, 6
+    opts = K.kry_opts_default(lanczos_steps=m, num_probes=npr, reorth=1, cg_rtol=1e-10, shift_share=1,
+                              precision=precision)
+    with K.Problem(n1, n2, mask, y) as P:
+        res = K.kry_loglik_batch(P.h, [K.theta_from_dict(t) for t in thetas], opts)
+    Z = philox.probe_matrix(r, c, npr, opts.seed)
+    for got, t in zip(res, thetas):
+        Kd = dense.covariance(g, mask, t)
+        est, _, _, _ = lanczos.slq_logdet(lambda v: Kd @ v, Z, m, reorth=True)
+        tol = 1e-9 if precision == 0 else 1e-5
+        assert abs(got["logdet"] - est) <= tol * abs(est), (t, got["logdet"], est)
+        ref = dense.loglik(g, mask, t, yo)
+        # the quadratic form runs in FP64 in both forms
+        assert abs(got["quad"] - ref["quad"]) <= 1e-8 * ref["quad"]
+        assert got["cg_relres"] <= 1e-10 and got["cg_iters"] > 0
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_shift_share_same_alone_and_in_mix(precision):
+    n1, n2, g, mask, y, yo, thetas = _shift_case()
+    opts = K.kry_opts_default(lanczos_steps=20, num_probes=5, shift_share=1, precision=precision)
+    with K.Problem(n1, n2, mask, y) as P:
+        mix = K.kry_loglik_batch(P.h, [K.theta_from_dict(t) for t in thetas], opts)
+        # reversed order changes every group's position and its packing
+        rev = K.kry_loglik_batch(P.h, [K.theta_from_dict(t) for t in thetas[::-1]], opts)[::-1]
+        alone = [K.kry_loglik(P.h, K.theta_from_dict(t), opts) for t in thetas]
+    for a, b, s in zip(mix, rev, alone):
+        for k in ("logdet", "quad", "cg_iters", "cg_relres", "lanczos_steps_used"):
+            assert a[k] == s[k] and b[k] == s[k], k
+
+
+def test_shift_share_zero_nugget_and_unshared_agreement():
+    # a zero nugget makes the point its group's base system; the shared and
+    # unshared forms agree to rounding of the two recurrences
+    n1, n2 = 20, 20
+    th = theta(0.05, 0.5, tau2=0.0)
+    g, mask, y, yo = _problem(n1, n2, th, 0.3, cholesky=False)
+    thetas = [th, theta(0.05, 0.5, tau2=0.1)]
+    base = dict(lanczos_steps=30, num_probes=4, reorth=1, cg_rtol=1e-10)
+    with K.Problem(n1, n2, mask, y) as P:
+        sh = K.kry_loglik_batch(P.h, [K.theta_from_dict(t) for t in thetas], K.kry_opts_default(shift_share=1, **base))
+        un = K.kry_loglik_batch(P.h, [K.theta_from_dict(t) for t in thetas], K.kry_opts_default(**base))
+    for a, b, t in zip(sh, un, thetas):
+        ref = dense.loglik(g, mask, t, yo)
+        assert abs(a["quad"] - ref["quad"]) <= 1e-8 * ref["quad"]
+        assert abs(a["logdet"] - b["logdet"]) <= 1e-8 * abs(b["logdet"])
