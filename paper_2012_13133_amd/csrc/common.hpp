@@ -88,4 +88,16 @@ __device__ __forceinline__ double philox_normal(uint32_t index, uint32_t stream,
     return sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
 }
 
+// Workgroups go to the chip's 8 XCDs round-robin by linear id.  This maps a
+// workgroup's linear id to a logical id such that each XCD receives one
+// contiguous range of logical ids, so neighbouring tiles (which share cache
+// lines or read the same spectrum) meet in the same L2.  A bijection on
+// [0, nblocks).
+__device__ __forceinline__ int xcd_remap(int lid, int nblocks) {
+    constexpr int NX = 8;
+    const int xcd = lid % NX, slot = lid / NX;
+    const int q = nblocks / NX, r = nblocks % NX;
+    return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+}
+
 }  // namespace kry

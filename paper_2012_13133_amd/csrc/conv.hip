@@ -150,34 +150,48 @@ __device__ __forceinline__ void load_pair(const StageAArgs& a, int vec, int row,
 
 // Stage A: per row, z[m] = x[2m] + i x[2m+1] -> FFT of length M -> split into
 // the real transform X[k], k = 0..M, written as Y[k][row] in RT-row runs.
+// A row is transformed by TR = M / (8 VT) threads holding 8 VT values each;
+// when those lie in one wavefront the passes need no workgroup barrier, and
+// the only barrier is the one before the split, which mixes rows.
 template <typename R, int LOG2M, int IN>
-__global__ void __launch_bounds__(1024) k_row_fwd(StageAArgs a, const cpx<R>* __restrict__ twp,
+__global__ void __launch_bounds__((row_vt<R, LOG2M>() > 1 ? 512 : 1024)) k_row_fwd(StageAArgs a, const cpx<R>* __restrict__ twp,
                                                   const cpx<R>* __restrict__ twb) {
     using S = Sched<LOG2M>;
     constexpr int M = S::L, T = M / 8, PM = padded(M) + 1;
+    constexpr int VT = row_vt<R, LOG2M>(), TR = T / VT;
+    constexpr bool WAVE = TR <= 64;
     constexpr bool LOW = (IN == IN_COMPACT);  // row_len <= M: z[m] = 0 for m >= M/2
     extern __shared__ unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
     const int tid = threadIdx.x;
-    const int rr = tid / T, t = tid % T;
-    const int row0 = blockIdx.x * a.RT;
+    const int rr = tid / TR, t = tid % TR;
+    // row tiles of one vector run consecutively on one XCD, so the halves of
+    // a cache line written by neighbouring tiles merge in its L2
+    const int lid = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int row0 = (lid % gridDim.x) * a.RT;
     const int row = row0 + rr;
-    const int vec = blockIdx.y;
+    const int vec = lid / gridDim.x;
     cpx<R>* buf = lds + rr * PM;
-    cpx<R> v[8];
+    cpx<R> v[8 * VT];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        v[r] = cpx<R>{(R)0, (R)0};
-        if (LOW && r >= 4) continue;
-        if (row < a.rows_in) load_pair<R, IN>(a, vec, row, 2 * (t + r * T), v[r]);
+    for (int u = 0; u < VT; ++u)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            v[u * 8 + r] = cpx<R>{(R)0, (R)0};
+            if (LOW && r >= 4) continue;
+            if (row < a.rows_in) load_pair<R, IN>(a, vec, row, 2 * (t + u * TR + r * T), v[u * 8 + r]);
+        }
+#pragma unroll
+    for (int u = 0; u < VT; ++u) {
+        pass_compute<R, LOG2M, false, 0, LOW>(v + u * 8, t + u * TR, twp);
+        pass_write<R, LOG2M, false, 0>(v + u * 8, buf, t + u * TR);
     }
-    pass_compute<R, LOG2M, false, 0, LOW>(v, t, twp);
-    pass_write<R, LOG2M, false, 0>(v, buf, t);
-    __syncthreads();
-    LdsPasses<R, LOG2M, false, 1, S::npass>::run(v, buf, 0, t, twp);
+    lds_sync<WAVE>();
+    LdsPassesVT<R, LOG2M, false, 1, S::npass, VT, WAVE>::run(v, buf, t, twp);
+    if constexpr (WAVE) __syncthreads();
 
     // split Z into the real transform X[k] = (s - i w d) / 2, k = 0..M:
-    // 8 outputs per thread for k < M plus the Nyquist column k = M
+    // 8 VT outputs per thread for k < M plus the Nyquist column k = M
     cpx<R>* Y = reinterpret_cast<cpx<R>*>(a.Y) + vec * a.Y_vstride;
     const int nt = blockDim.x;
     auto split = [&](int r2, int k) {
@@ -190,7 +204,7 @@ __global__ void __launch_bounds__(1024) k_row_fwd(StageAArgs a, const cpx<R>* __
         Y[(int64_t)k * a.ldY + row0 + r2] = cpx<R>{(R)0.5 * (s.x + wd.y), (R)0.5 * (s.y - wd.x)};
     };
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < 8 * VT; ++i) {
         const int o = tid + i * nt;
         split(o & (a.RT - 1), o >> a.log2RT);
     }
@@ -229,9 +243,12 @@ __global__ void __launch_bounds__(1024) k_col(StageBArgs a, const cpx<R>* __rest
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
     const int tid = threadIdx.x;
     const int cl = tid / T, t = tid % T;
-    const int col = blockIdx.x * a.CB + cl;
+    // the vectors of one column block run consecutively on one XCD, so the
+    // spectrum columns they share stay in its L2
+    const int lid = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int col = (lid / gridDim.y) * a.CB + cl;
     const bool valid = col < a.ncols;
-    const int vbase = blockIdx.y * V;  // first vector of this workgroup (within the launch)
+    const int vbase = (lid % gridDim.y) * V;  // first vector of this workgroup (within the launch)
     cpx<R>* buf = lds + cl * V * PL;
     cpx<R>* Ycol = reinterpret_cast<cpx<R>*>(a.Y) + (int64_t)(valid ? col : 0) * a.ldY;
     cpx<R> v[V * 8];
@@ -321,71 +338,65 @@ struct StageCArgs {
 // Stage C: read RT-row runs of X[k], k = 0..M, merge the even/odd split into
 // Z[k] = (X[k] + X*[M-k]) + i W^{-k} (X[k] - X*[M-k]), inverse FFT of length M,
 // then x[2m], x[2m+1] = Re, Im z[m] go to the observed cells (+ eta v) or the
-// grid.
+// grid.  Row threads as in stage A: the barriers are after the tile load and
+// after the merge; the passes of a row stay within its wavefront.
 template <typename R, int LOG2M, int OUT>
-__global__ void __launch_bounds__(1024) k_row_inv(StageCArgs a, const cpx<R>* __restrict__ twp,
+__global__ void __launch_bounds__((row_vt<R, LOG2M>() > 1 ? 512 : 1024)) k_row_inv(StageCArgs a, const cpx<R>* __restrict__ twp,
                                                   const cpx<R>* __restrict__ twb) {
     using S = Sched<LOG2M>;
     constexpr int M = S::L, T = M / 8, PM = padded(M) + 1;
+    constexpr int VT = row_vt<R, LOG2M>(), TR = T / VT;
+    constexpr bool WAVE = TR <= 64;
+    constexpr int NV = 8 * VT;  // values per thread
     constexpr int LRL = S::lr(true, S::npass - 1);
     extern __shared__ unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
     const int tid = threadIdx.x;
-    const int row0 = blockIdx.x * a.RT;
-    const int vec = blockIdx.y;
+    // neighbouring row tiles on one XCD share the cache lines of their runs
+    const int lid = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int row0 = (lid % gridDim.x) * a.RT;
+    const int vec = lid / gridDim.x;
     const cpx<R>* Y = reinterpret_cast<const cpx<R>*>(a.Y) + vec * a.Y_vstride;
-    const int rr = tid / T, t = tid % T;
+    const int rr = tid / TR, t = tid % TR;
     const int row = row0 + rr;
-    // Output cells of this thread (columns 2m, 2m+1 for its 8 values m) do
-    // not depend on the transform: look up their compact indices now (and,
-    // in FP64 where registers allow, the nugget-term inputs), so the loads
-    // overlap the transform.
-    constexpr bool PRE_V = (OUT == OUT_COMPACT) && sizeof(R) == 8;
-    int32_t oci[8];
-    uint32_t obits = 0u;  // 2 bits per value: columns 2m and 2m+1 observed
-    R vx[PRE_V ? 8 : 1], vy[PRE_V ? 8 : 1];
+    // Output cells of this thread (columns 2m, 2m+1 for its values m) do not
+    // depend on the transform: look up their compact indices now, so the
+    // loads overlap the transform.
+    int32_t oci[NV];
+    uint64_t obits = 0u;  // 2 bits per value: columns 2m and 2m+1 observed
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < NV; ++k) {
         oci[k] = 0;
         if constexpr (OUT == OUT_COMPACT) {
-            const int c0 = 2 * edge_pos<LOG2M, LRL>(t, k);
+            const int c0 = 2 * edge_pos<LOG2M, LRL>(t + (k / 8) * TR, k % 8);
             if (row < a.rows_out && c0 < a.cols_out) {
                 const int w = row * a.mask.words_per_row + (c0 >> 5);
                 const uint32_t word = a.mask.bits[w];
                 const uint32_t b0 = 1u << (c0 & 31);
-                obits |= ((word & b0 ? 1u : 0u) | (word & (b0 << 1) ? 2u : 0u)) << (2 * k);
+                obits |= (uint64_t)((word & b0 ? 1u : 0u) | (word & (b0 << 1) ? 2u : 0u)) << (2 * k);
                 oci[k] = (int32_t)(a.mask.base[w] + __popc(word & (b0 - 1u)));
             }
         }
     }
-    if constexpr (PRE_V) {
-        const R* vi = reinterpret_cast<const R*>(a.vin) + vec * a.vin_vstride;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const uint32_t b = (obits >> (2 * k)) & 3u;
-            vx[k] = (b & 1u) ? vi[oci[k]] : (R)0;
-            vy[k] = (b & 2u) ? vi[oci[k] + (b & 1u)] : (R)0;
-        }
-    }
-    // the tile holds RT x (M + 1) values: exactly 8 per thread for k < M (all
+    // the tile holds RT x (M + 1) values: exactly NV per thread for k < M (all
     // loads issued before any is used) plus the Nyquist column k = M
     {
-        const int nt = blockDim.x;  // = RT * M / 8
-        cpx<R> t8[8];
+        const int nt = blockDim.x;  // = RT * M / NV
+        cpx<R> tv[NV];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < NV; ++i) {
             const int o = tid + i * nt;
             const int r2 = o & (a.RT - 1);
             const int k = o >> a.log2RT;
             const int row = row0 + r2;
-            t8[i] = (row < a.rows_out) ? Y[(int64_t)k * a.ldY + row] : cpx<R>{(R)0, (R)0};
+            tv[i] = (row < a.rows_out) ? Y[(int64_t)k * a.ldY + row] : cpx<R>{(R)0, (R)0};
         }
         cpx<R> ny{(R)0, (R)0};
         if (tid < a.RT && row0 + tid < a.rows_out) ny = Y[(int64_t)M * a.ldY + row0 + tid];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < NV; ++i) {
             const int o = tid + i * nt;
-            lds[(o & (a.RT - 1)) * PM + pad8(o >> a.log2RT)] = t8[i];
+            lds[(o & (a.RT - 1)) * PM + pad8(o >> a.log2RT)] = tv[i];
         }
         if (tid < a.RT) lds[tid * PM + pad8(M)] = ny;
     }
@@ -410,29 +421,31 @@ __global__ void __launch_bounds__(1024) k_row_inv(StageCArgs a, const cpx<R>* __
     }
     __syncthreads();
     cpx<R>* buf = lds + rr * PM;
-    cpx<R> v[8];
-    LdsPasses<R, LOG2M, true, 0, S::npass - 1>::run(v, buf, 0, t, twp);
-    pass_read<R, LOG2M, true, S::npass - 1>(v, buf, t);
-    pass_compute<R, LOG2M, true, S::npass - 1>(v, t, twp);
+    cpx<R> v[NV];
+    LdsPassesVT<R, LOG2M, true, 0, S::npass - 1, VT, WAVE>::run(v, buf, t, twp);
+#pragma unroll
+    for (int u = 0; u < VT; ++u) pass_read<R, LOG2M, true, S::npass - 1>(v + u * 8, buf, t + u * TR);
+#pragma unroll
+    for (int u = 0; u < VT; ++u) pass_compute<R, LOG2M, true, S::npass - 1>(v + u * 8, t + u * TR, twp);
     if (row >= a.rows_out) return;
     const int theta = (a.vec0 + vec) / a.vecs_per_theta;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-        const int m = edge_pos<LOG2M, LRL>(t, k);
+    for (int k = 0; k < NV; ++k) {
+        const int m = edge_pos<LOG2M, LRL>(t + (k / 8) * TR, k % 8);
         const int c0 = 2 * m;
         if (c0 >= a.cols_out) continue;
         if constexpr (OUT == OUT_COMPACT) {
-            const uint32_t b = (obits >> (2 * k)) & 3u;
+            const uint32_t b = (uint32_t)(obits >> (2 * k)) & 3u;
             if (!b) continue;
             int64_t ci = oci[k];
             const R e = (R)a.eta[theta];
             const R* vi = reinterpret_cast<const R*>(a.vin) + vec * a.vin_vstride;
             R* o = reinterpret_cast<R*>(a.out) + vec * a.out_vstride;
             if (b & 1u) {
-                o[ci] = v[k].x + e * (PRE_V ? vx[PRE_V ? k : 0] : vi[ci]);
+                o[ci] = v[k].x + e * vi[ci];
                 ++ci;
             }
-            if (b & 2u) o[ci] = v[k].y + e * (PRE_V ? vy[PRE_V ? k : 0] : vi[ci]);
+            if (b & 2u) o[ci] = v[k].y + e * vi[ci];
         } else {
             R* o = reinterpret_cast<R*>(a.out) + vec * a.out_vstride + (int64_t)row * a.cols_out;
             o[c0] = (R)a.scale * v[k].x;
@@ -523,15 +536,23 @@ struct RowTiling {
 
 // Rows per tile: transposed runs of RT * sizeof(cpx) = 64 bytes where the
 // workgroup (<= 1024 threads) and LDS allow; more rows for short rows.
+// Host mirror of row_vt: virtual threads per thread of a row transform.
+template <typename R>
+static int row_vt_host(int) {
+    return 1;
+}
+
 template <typename R>
 static RowTiling row_tiling(int M) {
     const size_t cs = sizeof(cpx<R>);
-    const int T = M / 8;
+    const int T = M / 8 / row_vt_host<R>(M);  // threads per row
     const size_t PM = (size_t)M + M / 8 + 1;
     int RT = (int)(64 / cs);
     while (RT > 1 && RT * T > 1024) RT /= 2;
     while (RT > 1 && RT * PM * cs > 150 * 1024) RT /= 2;
     while (RT * T < 256 && RT < 64 && (size_t)(2 * RT) * PM * cs <= 64 * 1024) RT *= 2;
+    // kernels with several virtual threads are compiled for <= 512 threads
+    KRY_REQUIRE(RT * T <= (row_vt_host<R>(M) > 1 ? 512 : 1024), "row tiling exceeds the kernel's thread bound");
     RowTiling t;
     t.RT = RT;
     t.T = T;

@@ -192,4 +192,50 @@ struct LdsPasses {
     }
 };
 
+// Ordering point for LDS exchanges among the lanes of one wavefront: a
+// wavefront's LDS instructions are performed in program order, so fences that
+// stop the compiler (and the memory model) from moving accesses across this
+// point are enough; no workgroup barrier is needed.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool WAVE>
+__device__ __forceinline__ void lds_sync() {
+    if constexpr (WAVE) wave_sync();
+    else __syncthreads();
+}
+
+// Passes P..PE-1 through LDS for one transform at buf handled by TR = T / VT
+// threads, thread t acting for the virtual threads t + u TR, u < VT (values
+// v[u * 8 + k]).  WAVE: the transform's threads lie in one wavefront, so the
+// exchanges need wave_sync only.
+template <typename R, int LOG2L, bool INV, int P, int PE, int VT, bool WAVE>
+struct LdsPassesVT {
+    __device__ __forceinline__ static void run(cpx<R>* v, cpx<R>* buf, int t, const cpx<R>* __restrict__ tw) {
+        if constexpr (P < PE) {
+            constexpr int TR = (1 << LOG2L) / 8 / VT;
+#pragma unroll
+            for (int u = 0; u < VT; ++u) pass_read<R, LOG2L, INV, P>(v + u * 8, buf, t + u * TR);
+            lds_sync<WAVE>();
+#pragma unroll
+            for (int u = 0; u < VT; ++u) pass_compute<R, LOG2L, INV, P>(v + u * 8, t + u * TR, tw);
+#pragma unroll
+            for (int u = 0; u < VT; ++u) pass_write<R, LOG2L, INV, P>(v + u * 8, buf, t + u * TR);
+            lds_sync<WAVE>();
+            LdsPassesVT<R, LOG2L, INV, P + 1, PE, VT, WAVE>::run(v, buf, t, tw);
+        }
+    }
+};
+
+// Virtual threads per thread of a row transform of length 2^LOG2M.  One (8
+// values per thread) measured fastest at the embeddings used here; rows of
+// at most 512 points then fit one wavefront and exchange with wave_sync.
+template <typename R, int LOG2M>
+constexpr int row_vt() {
+    return 1;
+}
+
 }  // namespace kry
