@@ -237,6 +237,18 @@ kry_status kry_loglik(kry_problem* prob, const kry_matern* theta, const kry_opts
  * residual |zeta| ||r|| / ||y||. */
 kry_status kry_loglik_batch(kry_problem* prob, const kry_matern* thetas, int32_t count,
                             const kry_opts* opts, kry_loglik_result* out /* count */);
+/* Independent problems (grids of any sizes, created on one context), one
+ * parameter point each: thetas[i] applies to probs[i], out[i] receives its
+ * result.  Problems whose embeddings are equal run together: each stage of
+ * every masked product is one launch over all their vectors, the kernels
+ * reading a per-vector table of masks, blocks and spectra; Krylov vectors are
+ * stored with the group's largest observed count as stride (zero past each
+ * problem's own count).  Each problem uses its own probes (the Philox
+ * streams of kry_loglik with opts->seed), so out[i] matches kry_loglik on
+ * probs[i] up to rounding.  Requires opts->solver = CG and shift_share = 0.
+ * KRY_ENOCONV as for kry_loglik_batch. */
+kry_status kry_loglik_multi(kry_problem* const* probs, const kry_matern* thetas, int32_t count,
+                            const kry_opts* opts, kry_loglik_result* out);
 /* Maximise l_p over (log range, log eta) -- bit 0 of free_mask frees the
  * range, bit 1 the nugget ratio -- by Nelder-Mead from `init`, with the same
  * probes at every point.  est receives the estimate with sigma2 = sigma2_hat

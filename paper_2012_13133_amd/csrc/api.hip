@@ -164,6 +164,8 @@ MatvecFn<R> masked_op(Problem& P, const void* lam, int64_t lam_tstride, int vpt,
         s.lam = lam;
         s.lam_tstride = lam_tstride;
         s.vecs_per_theta = vpt;
+        s.tab = Q.tab;
+        s.tab_vpp = vpt;
         conv_apply<R>(Q, s, st);
     };
 }
@@ -416,7 +418,7 @@ struct ShiftQuad {
 template <typename R>
 void slq_device(Problem& P, const kry_opts* o, const void* lam, int64_t lam_tstride, const double* d_eta, int count,
                 LoglikWork& W, std::vector<double>* alpha_out, std::vector<double>* beta_out, hipStream_t st,
-                const ShiftQuad* sq = nullptr) {
+                const ShiftQuad* sq = nullptr, const std::function<void(R*)>* fill_probes = nullptr) {
     const int np = nprobes_of(o);
     const int nvec = count * np;
     const int m = o->lanczos_steps;
@@ -441,9 +443,14 @@ void slq_device(Problem& P, const kry_opts* o, const void* lam, int64_t lam_tstr
         gamma = a.take<double>(sq ? std::max(nvec, sq->nout) : nvec);
     };
     with_arena(P, lay);
-    make_probes<R>(P, np, o->seed, o->probe_kind == KRY_PROBE_COLOURED ? o->colour_period : 0, Z, st);
-    for (int t = 1; t < count; ++t)
-        KRY_HIP(hipMemcpyAsync(Z + (size_t)t * np * p, Z, (size_t)np * p * sizeof(R), hipMemcpyDeviceToDevice, st));
+    if (fill_probes) {
+        (*fill_probes)(Z);
+    } else {
+        make_probes<R>(P, np, o->seed, o->probe_kind == KRY_PROBE_COLOURED ? o->colour_period : 0, Z, st);
+        for (int t = 1; t < count; ++t)
+            KRY_HIP(hipMemcpyAsync(Z + (size_t)t * np * p, Z, (size_t)np * p * sizeof(R), hipMemcpyDeviceToDevice,
+                                   st));
+    }
     auto A = masked_op<R>(P, lam, lam_tstride, np, d_eta);
     lanczos_run<R>(A, p, nvec, m, reorth, Z, B, st);
     const int nout = sq ? sq->nout : nvec;
@@ -765,6 +772,93 @@ void loglik_points_shared(Problem& P, const kry_matern* thetas, int count, const
         r.cg_iters = iters[t];
         r.cg_relres = relres[t];
     }
+}
+
+// Likelihood of one parameter point per problem for problems that share an
+// embedding.  Every masked product covers all of them at once: the stage
+// kernels read a per-vector problem table (mask, block, spectrum), and the
+// Krylov vectors are stored with the largest observed count as stride, zero
+// past each problem's own count.  Probes and data are each problem's own.
+template <typename R>
+void loglik_multi_group(const std::vector<Problem*>& probs, const kry_matern* th, const kry_opts* o,
+                        kry_loglik_result* out, hipStream_t st) {
+    Problem& P0 = *probs[0];
+    Ctx& C = *P0.ctx;
+    const int G = (int)probs.size();
+    const int np = nprobes_of(o);
+    Problem Q = P0.view();  // P0's immutable data; its own workspace
+    int n1m = 0, n2m = 0;
+    int64_t pm = 0;
+    for (Problem* q : probs) {
+        n1m = std::max(n1m, q->n1);
+        n2m = std::max(n2m, q->n2);
+        pm = std::max(pm, q->p);
+    }
+    Q.n1 = n1m;
+    Q.n2 = n2m;
+    Q.p = pm;
+    const int64_t nspec = (int64_t)(Q.N2 / 2 + 1) * Q.N1;
+    Q.spec_multi64.ensure(C, (size_t)G * nspec * sizeof(double));
+    if (sizeof(R) == 4) Q.spec_multi32.ensure(C, (size_t)G * nspec * sizeof(float));
+    std::vector<ProbDesc> tab(G);
+    std::vector<double> eta(G);
+    for (int g = 0; g < G; ++g) {
+        Problem& Pg = *probs[g];
+        double lo, hi;
+        double* d64 = Q.spec_multi64.as<double>() + (size_t)g * nspec;
+        float* d32 = sizeof(R) == 4 ? Q.spec_multi32.as<float>() + (size_t)g * nspec : nullptr;
+        spectrum_device(Pg, Q.N1, Q.N2, to_matern(&th[g]), d64, &lo, &hi, st);
+        spectrum_scale(d64, nspec, 1.0 / ((double)Q.N1 * Q.N2), false, d64, d32, st);
+        tab[g] = ProbDesc{Pg.bits.as<uint32_t>(), Pg.base.as<uint32_t>(), Pg.words_per_row, Pg.n1, Pg.n2, Pg.p,
+                          d64, d32};
+        eta[g] = th[g].tau2 / th[g].sigma2;
+    }
+    // table, nugget ratios, padded data and solutions
+    const size_t tab_b = ((size_t)G * sizeof(ProbDesc) + 255) & ~size_t(255);
+    const size_t eta_b = ((size_t)G * 8 + 255) & ~size_t(255);
+    DevBuf& tb = Q.tmp3;
+    tb.ensure(C, tab_b + eta_b + 2 * (size_t)G * pm * sizeof(double) + ((size_t)G * 257 + 8) * sizeof(double));
+    ProbDesc* d_tab = tb.as<ProbDesc>();
+    double* d_eta = reinterpret_cast<double*>(tb.as<char>() + tab_b);
+    double* Yd = reinterpret_cast<double*>(tb.as<char>() + tab_b + eta_b);
+    double* Xd = Yd + (size_t)G * pm;
+    double* part = Xd + (size_t)G * pm;
+    KRY_HIP(hipMemcpyAsync(d_tab, tab.data(), G * sizeof(ProbDesc), hipMemcpyHostToDevice, st));
+    KRY_HIP(hipMemcpyAsync(d_eta, eta.data(), G * sizeof(double), hipMemcpyHostToDevice, st));
+    Q.tab = d_tab;
+    // log-determinants: each problem's probes, zero past its count
+    const int period = o->probe_kind == KRY_PROBE_COLOURED ? o->colour_period : 0;
+    std::function<void(R*)> fill = [&](R* Z) {
+        KRY_HIP(hipMemsetAsync(Z, 0, (size_t)G * np * pm * sizeof(R), st));
+        for (int g = 0; g < G; ++g) make_probes<R>(*probs[g], np, o->seed, period, Z + (size_t)g * np * pm, st, pm);
+    };
+    LoglikWork W;
+    slq_device<R>(Q, o, nullptr, 0, d_eta, G, W, nullptr, nullptr, st, nullptr, &fill);
+    // quadratic forms
+    KRY_HIP(hipMemsetAsync(Yd, 0, (size_t)G * pm * sizeof(double), st));
+    for (int g = 0; g < G; ++g)
+        KRY_HIP(hipMemcpyAsync(Yd + (size_t)g * pm, probs[g]->y64.ptr, probs[g]->p * sizeof(double),
+                               hipMemcpyDeviceToDevice, st));
+    SolveStats ss;
+    solve_device(Q, o->precision, nullptr, nullptr, 0, 1, d_eta, G, Yd, Xd, o->cg_rtol, o->cg_maxit, ss, st);
+    std::vector<double> Qf(G);
+    dot_batched<double>(Yd, pm, Xd, pm, pm, G, part, part + (size_t)G * 256, st);
+    KRY_HIP(hipMemcpyAsync(Qf.data(), part + (size_t)G * 256, G * sizeof(double), hipMemcpyDeviceToHost, st));
+    KRY_HIP(hipStreamSynchronize(st));
+    for (int g = 0; g < G; ++g) {
+        double est, se;
+        combine(W.gamma.data() + (size_t)g * np, np, o->probe_kind == KRY_PROBE_COLOURED, &est, &se);
+        kry_loglik_result& r = out[g];
+        std::memset(&r, 0, sizeof(r));
+        assemble(&r, probs[g]->p, est, se, Qf[g], th[g].sigma2);
+        int smax = 0;
+        for (int k = 0; k < np; ++k) smax = std::max(smax, W.steps[(size_t)g * np + k]);
+        r.lanczos_steps_used = smax;
+        r.cg_iters = ss.iters[g];
+        r.cg_relres = ss.relres[g];
+    }
+    Q.tab = nullptr;
+    Q.release_work();
 }
 
 bool any_not_converged(const kry_loglik_result* r, int count, const kry_opts* o) {
@@ -1514,6 +1608,71 @@ kry_status kry_loglik_batch(kry_problem* prob, const kry_matern* thetas, int32_t
             for (int t0 = 0; t0 < count; t0 += chunk) {
                 const int c = std::min(chunk, (int)count - t0);
                 loglik_points(P, thetas + t0, c, opts, res.data() + t0, st);
+            }
+        }
+        std::copy(res.begin(), res.end(), out);
+        noconv = any_not_converged(out, count, opts);
+    });
+    if (s == KRY_OK && noconv) {
+        g_last_error = "CG reached cg_maxit before cg_rtol";
+        return KRY_ENOCONV;
+    }
+    return s;
+}
+
+kry_status kry_loglik_multi(kry_problem* const* probs, const kry_matern* thetas, int32_t count, const kry_opts* opts,
+                            kry_loglik_result* out) {
+    bool noconv = false;
+    kry_status s = guard([&] {
+        KRY_REQUIRE(probs && thetas && out, "NULL argument");
+        KRY_REQUIRE(count >= 1, "count must be >= 1");
+        check_opts(opts);
+        KRY_REQUIRE(opts->solver == KRY_SOLVER_CG, "kry_loglik_multi takes the CG quadratic form");
+        KRY_REQUIRE(opts->shift_share == 0, "kry_loglik_multi does not share Krylov spaces across nuggets");
+        for (int i = 0; i < count; ++i) {
+            KRY_REQUIRE(probs[i] != nullptr, "NULL problem");
+            KRY_REQUIRE(probs[i]->P.ctx == probs[0]->P.ctx, "problems of one call must share a context");
+            check_theta(&thetas[i]);
+        }
+        Ctx& C = *probs[0]->P.ctx;
+        bind(C);
+        hipStream_t st = C.stream;
+        const int np = nprobes_of(opts);
+        const size_t es = opts->precision == KRY_FP32 ? 4 : 8;
+        size_t cap = (size_t)48e9;
+        if (C.budget > 0) cap = std::min<size_t>(cap, C.budget / 2);
+        // problems with equal embeddings go together, in order of first appearance
+        std::vector<std::vector<int>> groups;
+        std::vector<std::pair<int, int>> keys;
+        for (int i = 0; i < count; ++i) {
+            const std::pair<int, int> k{probs[i]->P.N1, probs[i]->P.N2};
+            size_t g = 0;
+            for (; g < keys.size() && keys[g] != k; ++g) {}
+            if (g == keys.size()) {
+                keys.push_back(k);
+                groups.emplace_back();
+            }
+            groups[g].push_back(i);
+        }
+        std::vector<kry_loglik_result> res(count);
+        for (const auto& grp : groups) {
+            int64_t pm = 0;
+            for (int i : grp) pm = std::max(pm, probs[i]->P.p);
+            // per problem: Lanczos block and CG / refinement vectors at the padded length
+            const size_t per = (size_t)np * pm * es * (opts->reorth ? opts->lanczos_steps + 3 : 5) + 12 * (size_t)pm * 8;
+            const size_t chunk = std::max<size_t>(1, cap / std::max<size_t>(per, 1));
+            for (size_t a = 0; a < grp.size(); a += chunk) {
+                const size_t b = std::min(grp.size(), a + chunk);
+                std::vector<Problem*> ps;
+                std::vector<kry_matern> th;
+                for (size_t j = a; j < b; ++j) {
+                    ps.push_back(&probs[grp[j]]->P);
+                    th.push_back(thetas[grp[j]]);
+                }
+                std::vector<kry_loglik_result> r(ps.size());
+                if (opts->precision == KRY_FP32) loglik_multi_group<float>(ps, th.data(), opts, r.data(), st);
+                else loglik_multi_group<double>(ps, th.data(), opts, r.data(), st);
+                for (size_t j = a; j < b; ++j) res[grp[j]] = r[j - a];
             }
         }
         std::copy(res.begin(), res.end(), out);

@@ -119,32 +119,35 @@ struct StageAArgs {
     uint64_t seed;
     int stream0;
     int vec0;
+    const ProbDesc* tab;  // several problems: per-vector mask and block
+    int tab_vpp;
 };
 
 // Value of input column c of a row (0 beyond the data or off the mask).
 template <typename R, int IN>
-__device__ __forceinline__ void load_pair(const StageAArgs& a, int vec, int row, int c0, cpx<R>& out) {
+__device__ __forceinline__ void load_pair(const StageAArgs& a, const MaskView& mask, int row_len, int vec, int row,
+                                          int c0, cpx<R>& out) {
     out = cpx<R>{(R)0, (R)0};
-    if (c0 >= a.row_len) return;
+    if (c0 >= row_len) return;
     if constexpr (IN == IN_COMPACT) {
-        const int w = row * a.mask.words_per_row + (c0 >> 5);
-        const uint32_t word = a.mask.bits[w];
+        const int w = row * mask.words_per_row + (c0 >> 5);
+        const uint32_t word = mask.bits[w];
         const uint32_t b0 = 1u << (c0 & 31);
         const uint32_t pair = word & (b0 | (b0 << 1));
         if (!pair) return;
         const R* vin = reinterpret_cast<const R*>(a.in) + vec * a.in_vstride;
-        int64_t ci = (int64_t)a.mask.base[w] + __popc(word & (b0 - 1u));
+        int64_t ci = (int64_t)mask.base[w] + __popc(word & (b0 - 1u));
         if (word & b0) out.x = vin[ci++];
         if (word & (b0 << 1)) out.y = vin[ci];
     } else if constexpr (IN == IN_DENSE) {
         const double* src = reinterpret_cast<const double*>(a.in) + vec * a.in_vstride + (int64_t)row * a.in_rstride;
         out.x = (R)src[c0];
-        if (c0 + 1 < a.row_len) out.y = (R)src[c0 + 1];
+        if (c0 + 1 < row_len) out.y = (R)src[c0 + 1];
     } else {
         const uint32_t idx = (uint32_t)(row * a.in_rstride + c0);
         const uint32_t stream = (uint32_t)(a.stream0 + a.vec0 + vec);
         out.x = (R)philox_normal(idx, stream, DOMAIN_FIELD, a.seed);
-        if (c0 + 1 < a.row_len) out.y = (R)philox_normal(idx + 1u, stream, DOMAIN_FIELD, a.seed);
+        if (c0 + 1 < row_len) out.y = (R)philox_normal(idx + 1u, stream, DOMAIN_FIELD, a.seed);
     }
 }
 
@@ -171,6 +174,15 @@ __global__ void __launch_bounds__((row_vt<R, LOG2M>() > 1 ? 512 : 1024)) k_row_f
     const int row0 = (lid % gridDim.x) * a.RT;
     const int row = row0 + rr;
     const int vec = lid / gridDim.x;
+    MaskView mask = a.mask;
+    int rows_in = a.rows_in, row_len = a.row_len;
+    if (a.tab) {
+        const ProbDesc& d = a.tab[(a.vec0 + vec) / a.tab_vpp];
+        mask = MaskView{d.bits, d.base, d.wpr};
+        rows_in = d.n1;
+        row_len = d.n2;
+        if (row0 >= rows_in) return;  // rows the column transform never reads
+    }
     cpx<R>* buf = lds + rr * PM;
     cpx<R> v[8 * VT];
 #pragma unroll
@@ -179,7 +191,7 @@ __global__ void __launch_bounds__((row_vt<R, LOG2M>() > 1 ? 512 : 1024)) k_row_f
         for (int r = 0; r < 8; ++r) {
             v[u * 8 + r] = cpx<R>{(R)0, (R)0};
             if (LOW && r >= 4) continue;
-            if (row < a.rows_in) load_pair<R, IN>(a, vec, row, 2 * (t + u * TR + r * T), v[u * 8 + r]);
+            if (row < rows_in) load_pair<R, IN>(a, mask, row_len, vec, row, 2 * (t + u * TR + r * T), v[u * 8 + r]);
         }
 #pragma unroll
     for (int u = 0; u < VT; ++u) {
@@ -226,6 +238,8 @@ struct StageBArgs {
     int vecs_per_theta;
     int vec0;
     double* spec_out;
+    const ProbDesc* tab;  // several problems: per-vector rows and spectrum
+    int tab_vpp;
 };
 
 // Stage B: per column of the half spectrum, forward FFT of length L (rows
@@ -256,13 +270,29 @@ __global__ void __launch_bounds__(1024) k_col(StageBArgs a, const cpx<R>* __rest
     // overlaps the forward transform (an unused slot, vbase + u >= nvec,
     // reads the last vector's spectrum, never past the end)
     R lamv[MODE == B_SPEC ? 1 : V * 8];
+    int rows_in[V], rows_out[V];
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+        rows_in[u] = a.rows_in;
+        rows_out[u] = a.rows_out;
+        if (a.tab) {
+            const ProbDesc& d = a.tab[(a.vec0 + min(vbase + u, a.nvec - 1)) / a.tab_vpp];
+            rows_in[u] = d.n1;
+            rows_out[u] = d.n1;
+        }
+    }
     if constexpr (MODE != B_SPEC) {
 #pragma unroll
         for (int u = 0; u < V; ++u) {
             const int vl = min(vbase + u, a.nvec - 1);
-            const R* lam = reinterpret_cast<const R*>(a.lam) +
-                           (int64_t)((a.vec0 + vl) / a.vecs_per_theta) * a.lam_tstride +
-                           (int64_t)(valid ? col : 0) * L;
+            const R* lam;
+            if (a.tab) {
+                const ProbDesc& d = a.tab[(a.vec0 + vl) / a.tab_vpp];
+                lam = reinterpret_cast<const R*>(sizeof(R) == 8 ? (const void*)d.lam64 : (const void*)d.lam32);
+            } else {
+                lam = reinterpret_cast<const R*>(a.lam) + (int64_t)((a.vec0 + vl) / a.vecs_per_theta) * a.lam_tstride;
+            }
+            lam += (int64_t)(valid ? col : 0) * L;
 #pragma unroll
             for (int k = 0; k < 8; ++k) lamv[u * 8 + k] = lam[edge_pos<LOG2L, LRF>(t, k)];
         }
@@ -276,7 +306,7 @@ __global__ void __launch_bounds__(1024) k_col(StageBArgs a, const cpx<R>* __rest
             const int idx = t + r * T;
             v[u * 8 + r] = cpx<R>{(R)0, (R)0};
             if (LOW && r >= 4) continue;
-            if (vu && idx < a.rows_in) v[u * 8 + r] = Yv[idx];
+            if (vu && idx < rows_in[u]) v[u * 8 + r] = Yv[idx];
         }
     }
     pass_compute<R, LOG2L, false, 0, LOW, V>(v, t, twp);
@@ -312,7 +342,7 @@ __global__ void __launch_bounds__(1024) k_col(StageBArgs a, const cpx<R>* __rest
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const int idx = t + k * T;
-                if (idx < a.rows_out) Yv[idx] = v[u * 8 + k];
+                if (idx < rows_out[u]) Yv[idx] = v[u * 8 + k];
             }
         }
     }
@@ -333,7 +363,9 @@ struct StageCArgs {
     void* out;
     int64_t out_vstride;
     double scale;
-};
+    const ProbDesc* tab;  // several problems: per-vector mask and block;
+    int tab_vpp;          // compact outputs are zero from the problem's count
+};                        // up to out_vstride
 
 // Stage C: read RT-row runs of X[k], k = 0..M, merge the even/odd split into
 // Z[k] = (X[k] + X*[M-k]) + i W^{-k} (X[k] - X*[M-k]), inverse FFT of length M,
@@ -354,11 +386,29 @@ __global__ void __launch_bounds__((row_vt<R, LOG2M>() > 1 ? 512 : 1024)) k_row_i
     const int tid = threadIdx.x;
     // neighbouring row tiles on one XCD share the cache lines of their runs
     const int lid = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-    const int row0 = (lid % gridDim.x) * a.RT;
+    const int tile = lid % gridDim.x;
+    const int row0 = tile * a.RT;
     const int vec = lid / gridDim.x;
     const cpx<R>* Y = reinterpret_cast<const cpx<R>*>(a.Y) + vec * a.Y_vstride;
     const int rr = tid / TR, t = tid % TR;
     const int row = row0 + rr;
+    MaskView mask = a.mask;
+    int rows_out = a.rows_out, cols_out = a.cols_out;
+    if (a.tab) {
+        const ProbDesc& d = a.tab[(a.vec0 + vec) / a.tab_vpp];
+        mask = MaskView{d.bits, d.base, d.wpr};
+        rows_out = d.n1;
+        cols_out = d.n2;
+        if constexpr (OUT == OUT_COMPACT) {
+            // this tile's share of the zero padding [p, out_vstride)
+            const int64_t len = a.out_vstride - d.p;
+            const int64_t per = (len + gridDim.x - 1) / gridDim.x;
+            const int64_t b = d.p + tile * per, e = min(b + per, a.out_vstride);
+            R* o = reinterpret_cast<R*>(a.out) + vec * a.out_vstride;
+            for (int64_t i = b + tid; i < e; i += blockDim.x) o[i] = (R)0;
+        }
+        if (row0 >= rows_out) return;  // rows past this problem's block
+    }
     // Output cells of this thread (columns 2m, 2m+1 for its values m) do not
     // depend on the transform: look up their compact indices now, so the
     // loads overlap the transform.
@@ -369,12 +419,12 @@ __global__ void __launch_bounds__((row_vt<R, LOG2M>() > 1 ? 512 : 1024)) k_row_i
         oci[k] = 0;
         if constexpr (OUT == OUT_COMPACT) {
             const int c0 = 2 * edge_pos<LOG2M, LRL>(t + (k / 8) * TR, k % 8);
-            if (row < a.rows_out && c0 < a.cols_out) {
-                const int w = row * a.mask.words_per_row + (c0 >> 5);
-                const uint32_t word = a.mask.bits[w];
+            if (row < rows_out && c0 < cols_out) {
+                const int w = row * mask.words_per_row + (c0 >> 5);
+                const uint32_t word = mask.bits[w];
                 const uint32_t b0 = 1u << (c0 & 31);
                 obits |= (uint64_t)((word & b0 ? 1u : 0u) | (word & (b0 << 1) ? 2u : 0u)) << (2 * k);
-                oci[k] = (int32_t)(a.mask.base[w] + __popc(word & (b0 - 1u)));
+                oci[k] = (int32_t)(mask.base[w] + __popc(word & (b0 - 1u)));
             }
         }
     }
@@ -389,10 +439,10 @@ __global__ void __launch_bounds__((row_vt<R, LOG2M>() > 1 ? 512 : 1024)) k_row_i
             const int r2 = o & (a.RT - 1);
             const int k = o >> a.log2RT;
             const int row = row0 + r2;
-            tv[i] = (row < a.rows_out) ? Y[(int64_t)k * a.ldY + row] : cpx<R>{(R)0, (R)0};
+            tv[i] = (row < rows_out) ? Y[(int64_t)k * a.ldY + row] : cpx<R>{(R)0, (R)0};
         }
         cpx<R> ny{(R)0, (R)0};
-        if (tid < a.RT && row0 + tid < a.rows_out) ny = Y[(int64_t)M * a.ldY + row0 + tid];
+        if (tid < a.RT && row0 + tid < rows_out) ny = Y[(int64_t)M * a.ldY + row0 + tid];
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
             const int o = tid + i * nt;
@@ -427,13 +477,13 @@ __global__ void __launch_bounds__((row_vt<R, LOG2M>() > 1 ? 512 : 1024)) k_row_i
     for (int u = 0; u < VT; ++u) pass_read<R, LOG2M, true, S::npass - 1>(v + u * 8, buf, t + u * TR);
 #pragma unroll
     for (int u = 0; u < VT; ++u) pass_compute<R, LOG2M, true, S::npass - 1>(v + u * 8, t + u * TR, twp);
-    if (row >= a.rows_out) return;
+    if (row >= rows_out) return;
     const int theta = (a.vec0 + vec) / a.vecs_per_theta;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         const int m = edge_pos<LOG2M, LRL>(t + (k / 8) * TR, k % 8);
         const int c0 = 2 * m;
-        if (c0 >= a.cols_out) continue;
+        if (c0 >= cols_out) continue;
         if constexpr (OUT == OUT_COMPACT) {
             const uint32_t b = (uint32_t)(obits >> (2 * k)) & 3u;
             if (!b) continue;
@@ -447,9 +497,9 @@ __global__ void __launch_bounds__((row_vt<R, LOG2M>() > 1 ? 512 : 1024)) k_row_i
             }
             if (b & 2u) o[ci] = v[k].y + e * vi[ci];
         } else {
-            R* o = reinterpret_cast<R*>(a.out) + vec * a.out_vstride + (int64_t)row * a.cols_out;
+            R* o = reinterpret_cast<R*>(a.out) + vec * a.out_vstride + (int64_t)row * cols_out;
             o[c0] = (R)a.scale * v[k].x;
-            if (c0 + 1 < a.cols_out) o[c0 + 1] = (R)a.scale * v[k].y;
+            if (c0 + 1 < cols_out) o[c0 + 1] = (R)a.scale * v[k].y;
         }
     }
 }
@@ -616,6 +666,8 @@ static void run_stage_a(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R
     a.seed = s.seed;
     a.stream0 = s.stream0;
     a.vec0 = vec0;
+    a.tab = s.tab;
+    a.tab_vpp = s.tab_vpp;
     dim3 grid((s.rows_in + t.RT - 1) / t.RT, nvec);
     const int lg = ilog2(M);
     Ctx& c = *P.ctx;
@@ -635,7 +687,7 @@ static void run_stage_a(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R
 template <typename R>
 static void run_stage_b(Problem& P, int N1, int M, int vec0, int nvec, cpx<R>* Y, int ldY, int64_t Yvs, int rows_in,
                         int rows_out, const void* lam, int64_t lam_tstride, int vpt, double* spec_out,
-                        hipStream_t st) {
+                        hipStream_t st, const ProbDesc* tab = nullptr, int tab_vpp = 1) {
     const int T = N1 / 8;
     StageBArgs b;
     b.Y = Y;
@@ -650,6 +702,8 @@ static void run_stage_b(Problem& P, int N1, int M, int vec0, int nvec, cpx<R>* Y
     b.vecs_per_theta = vpt;
     b.vec0 = vec0;
     b.spec_out = spec_out;
+    b.tab = tab;
+    b.tab_vpp = tab_vpp;
     const int mode = spec_out ? B_SPEC : (2 * rows_in <= N1 ? B_LOW : B_FULL);
     const int lg = ilog2(N1);
     Ctx& c = *P.ctx;
@@ -688,6 +742,8 @@ static void run_stage_c(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R
     c.out = (void*)((R*)s.out + vec0 * s.out_vstride);
     c.out_vstride = s.out_vstride;
     c.scale = s.scale;
+    c.tab = s.tab;
+    c.tab_vpp = s.tab_vpp;
     dim3 grid((s.rows_out + t.RT - 1) / t.RT, nvec);
     const int lg = ilog2(M);
     Ctx& cx = *P.ctx;
@@ -710,6 +766,7 @@ void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st) {
     KRY_REQUIRE(s.rows_in <= s.N1 && s.row_len <= s.N2 && s.rows_out <= s.N1 && s.cols_out <= s.N2,
                 "block larger than the torus");
     KRY_REQUIRE(s.in_mode != IN_COMPACT || 2 * s.row_len <= s.N2, "compact input wider than half the torus");
+    KRY_REQUIRE(!s.tab || (s.in_mode == IN_COMPACT && s.tab_vpp >= 1), "problem tables take compact inputs");
     if (s.nvec <= 0) return;
     const int M = s.N2 / 2;
     const RowTiling ta = row_tiling<R>(M);
@@ -740,7 +797,7 @@ void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st) {
         run_stage_a<R>(P, s, v0, nv, Y, ldY, Yvs, st);
         mark(1);
         run_stage_b<R>(P, s.N1, M, v0, nv, Y, ldY, Yvs, s.rows_in, s.rows_out, s.lam, s.lam_tstride,
-                       s.vecs_per_theta, nullptr, st);
+                       s.vecs_per_theta, nullptr, st, s.tab, s.tab_vpp);
         mark(2);
         run_stage_c<R>(P, s, v0, nv, Y, ldY, Yvs, st);
         mark(3);

@@ -93,6 +93,20 @@ struct Spectrum {
     DevBuf s64, s32;
 };
 
+// One problem of a product over several problems that share an embedding:
+// its packed mask, grid block, observed count and spectra.  Compact vectors
+// of such a product are stored with a common stride (the largest observed
+// count); entries past a problem's own count are zero.
+struct ProbDesc {
+    const uint32_t* bits;
+    const uint32_t* base;
+    int wpr;
+    int n1, n2;
+    int64_t p;
+    const double* lam64;
+    const float* lam32;
+};
+
 // A problem: grid, packed mask, compact data (immutable after creation and
 // shared with views) plus a mutable workspace.  A view shares the immutable
 // part and owns a fresh workspace, so requests on one problem can run
@@ -110,6 +124,7 @@ struct Problem {
     std::shared_ptr<const std::vector<int64_t>> h_cell;  // compact index -> cell id (host)
     std::shared_ptr<const std::vector<uint8_t>> h_mask;
     bool is_view = false;
+    const ProbDesc* tab = nullptr;  // set on a group of problems sharing an embedding
     // workspace (per problem or per view)
     Spectrum spec;               // cache of the last parameter point
     DevBuf Y;                    // transform workspace
@@ -178,6 +193,11 @@ struct ConvSpec {
     const void* lam = nullptr;  // [theta][k2][k1], element type R, scaled
     int64_t lam_tstride = 0;
     int vecs_per_theta = 1;
+    // several problems (device table): vector v belongs to tab[(v) / tab_vpp],
+    // whose mask, block and spectrum replace the ones above; compact outputs
+    // are zero from the problem's count up to out_vstride
+    const ProbDesc* tab = nullptr;
+    int tab_vpp = 1;
 };
 
 template <typename R>

@@ -114,7 +114,7 @@ template void convert<double, double>(const double*, double*, int64_t, hipStream
 // only on cells of colour k = (row mod c) + c (col mod c).
 template <typename R>
 __global__ void k_probes(const int32_t* __restrict__ cell, int64_t p, int n2, int nprobe, uint64_t seed,
-                         int period, R* __restrict__ out) {
+                         int period, R* __restrict__ out, int64_t stride) {
     const int k = blockIdx.y;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < p; i += (int64_t)gridDim.x * blockDim.x) {
         double v = rademacher((uint32_t)i, (uint32_t)k, seed);
@@ -124,18 +124,18 @@ __global__ void k_probes(const int32_t* __restrict__ cell, int64_t p, int n2, in
             const int colour = (row % period) + period * (col % period);
             if (colour != k) v = 0.0;
         }
-        out[k * p + i] = (R)v;
+        out[k * stride + i] = (R)v;
     }
 }
 
 template <typename R>
-void make_probes(const Problem& P, int nprobe, uint64_t seed, int period, R* out, hipStream_t st) {
+void make_probes(const Problem& P, int nprobe, uint64_t seed, int period, R* out, hipStream_t st, int64_t stride) {
     hipLaunchKernelGGL(k_probes<R>, vec_grid(P.p, nprobe), dim3(256), 0, st, P.cell.as<int32_t>(), P.p, P.n2, nprobe,
-                       seed, period, out);
+                       seed, period, out, stride > 0 ? stride : P.p);
     KRY_HIP(hipGetLastError());
 }
-template void make_probes<double>(const Problem&, int, uint64_t, int, double*, hipStream_t);
-template void make_probes<float>(const Problem&, int, uint64_t, int, float*, hipStream_t);
+template void make_probes<double>(const Problem&, int, uint64_t, int, double*, hipStream_t, int64_t);
+template void make_probes<float>(const Problem&, int, uint64_t, int, float*, hipStream_t, int64_t);
 
 // ---- Lanczos ----------------------------------------------------------------------
 // start: znorm2 known -> scale = 1/||z|| (0 for an all-zero probe)

@@ -73,8 +73,10 @@ template <typename R>
 void cg_run(const MatvecFn<R>& A, int64_t n, int nvec, const R* b, R* x, double rtol, int maxit, CgBuffers<R>& B,
             std::vector<int>& iters, std::vector<double>& relres, hipStream_t st,
             const std::vector<int>* limits = nullptr);
+// Probe k of the problem at out + k * stride (stride 0: the problem's p).
 template <typename R>
-void make_probes(const Problem& P, int nprobe, uint64_t seed, int period, R* out, hipStream_t st);
+void make_probes(const Problem& P, int nprobe, uint64_t seed, int period, R* out, hipStream_t st,
+                 int64_t stride = 0);
 template <typename A, typename B>
 void convert(const A* x, B* y, int64_t n, hipStream_t st);
 template <typename R>

@@ -97,6 +97,8 @@ _SIGS = {
     "kry_loglik": (C.c_int, [_P, C.POINTER(kry_matern), C.POINTER(kry_opts), C.POINTER(kry_loglik_result)]),
     "kry_loglik_batch": (C.c_int, [_P, C.POINTER(kry_matern), C.c_int32, C.POINTER(kry_opts),
                                    C.POINTER(kry_loglik_result)]),
+    "kry_loglik_multi": (C.c_int, [C.POINTER(_P), C.POINTER(kry_matern), C.c_int32, C.POINTER(kry_opts),
+                                   C.POINTER(kry_loglik_result)]),
     "kry_fit": (C.c_int, [_P, C.POINTER(kry_matern), C.c_uint32, C.POINTER(kry_opts), C.c_double, C.c_int32,
                           C.POINTER(kry_matern), C.POINTER(kry_loglik_result)]),
     "kry_krige": (C.c_int, [_P, C.POINTER(kry_matern), C.POINTER(kry_opts), C.POINTER(C.c_int64), C.c_int64,
@@ -323,6 +325,19 @@ def kry_loglik_batch(prob, thetas, opts, allow_noconv=False):
     arr = (kry_matern * len(thetas))(*thetas)
     res = (kry_loglik_result * len(thetas))()
     s = lib.kry_loglik_batch(prob, arr, len(thetas), C.byref(opts), res)
+    if not (allow_noconv and s == KRY_ENOCONV):
+        _check(s)
+    return [r.as_dict() for r in res]
+
+
+def kry_loglik_multi(probs, thetas, opts, allow_noconv=False):
+    """One parameter point per problem (handles from kry_problem_create or
+    Problem.h), all problems on one context."""
+    assert len(probs) == len(thetas)
+    ps = (_P * len(probs))(*[p.value if isinstance(p, _P) else p for p in probs])
+    arr = (kry_matern * len(thetas))(*thetas)
+    res = (kry_loglik_result * len(thetas))()
+    s = lib.kry_loglik_multi(ps, arr, len(thetas), C.byref(opts), res)
     if not (allow_noconv and s == KRY_ENOCONV):
         _check(s)
     return [r.as_dict() for r in res]

@@ -357,3 +357,51 @@ def test_shift_share_zero_nugget_and_unshared_agreement():
         ref = dense.loglik(g, mask, t, yo)
         assert abs(a["quad"] - ref["quad"]) <= 1e-8 * ref["quad"]
         assert abs(a["logdet"] - b["logdet"]) <= 1e-8 * abs(b["logdet"])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_loglik_multi_matches_single_problems(precision):
+    # grids of different sizes: three share a 64 x 64 embedding, two a 32 x 32
+    # one; each problem's result must match its own single-problem run
+    shapes = [(20, 20), (12, 12), (24, 30), (17, 32), (9, 14)]
+    thetas = [theta(0.1, 0.5, tau2=0.2), theta(0.15, 1.5, tau2=0.05), theta(0.08, 2.5, tau2=0.3),
+              dict(theta(0.2, 1.0, tau2=0.1), aniso_ratio=2.0, aniso_angle=0.5), theta(0.3, 0.5, tau2=0.5)]
+    opts = K.kry_opts_default(lanczos_steps=25, num_probes=5, reorth=1, cg_rtol=1e-10, precision=precision)
+    ctx = K.kry_ctx_create()
+    hs = []
+    try:
+        for i, ((n1, n2), t) in enumerate(zip(shapes, thetas)):
+            mask = synth.uniform_mask(n1, n2, 0.15 + 0.1 * i, seed=40 + i)
+            y = synth.random_vectors(n1 * n2, 1, seed=50 + i)[0]
+            hs.append(K.kry_problem_create(ctx, n1, n2, mask, y))
+        th = [K.theta_from_dict(t) for t in thetas]
+        multi = K.kry_loglik_multi(hs, th, opts)
+        single = [K.kry_loglik(h, t, opts) for h, t in zip(hs, th)]
+        # reversed order: a problem's result does not depend on its neighbours
+        rev = K.kry_loglik_multi(hs[::-1], th[::-1], opts)[::-1]
+    finally:
+        for h in hs:
+            K.kry_problem_destroy(h)
+        K.kry_ctx_destroy(ctx)
+    tol_ld = 1e-10 if precision == 0 else 1e-5
+    for m, s, r in zip(multi, single, rev):
+        assert m["p"] == s["p"]
+        assert abs(m["logdet"] - s["logdet"]) <= tol_ld * abs(s["logdet"])
+        assert abs(m["quad"] - s["quad"]) <= 1e-8 * s["quad"]
+        assert m["logdet"] == r["logdet"] and m["quad"] == r["quad"]
+        assert m["cg_relres"] <= 1e-10
+
+
+def test_loglik_multi_errors():
+    ctx = K.kry_ctx_create()
+    h = K.kry_problem_create(ctx, 8, 8, np.ones((8, 8)), np.zeros((8, 8)))
+    try:
+        with pytest.raises(K.KryError):
+            K.kry_loglik_multi([h], [K.theta(sigma2=1.0, tau2=0.1, range=0.1, nu=0.5)],
+                               K.kry_opts_default(shift_share=1))
+        with pytest.raises(K.KryError):
+            K.kry_loglik_multi([h], [K.theta(sigma2=1.0, tau2=0.1, range=0.1, nu=0.5)],
+                               K.kry_opts_default(solver=K.KRY_SOLVER_GENGK))
+    finally:
+        K.kry_problem_destroy(h)
+        K.kry_ctx_destroy(ctx)
