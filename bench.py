@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--serve-sides", type=str, default="128,512",
                     help="grid sides log-uniform in [lo,hi] for the served stream (the full served workload uses 128,2048)")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--multi", type=int, default=64, help="independent problems in the multi-problem form (0: skip)")
+    ap.add_argument("--multi-sides", type=str, default="64,1024")
+    ap.add_argument("--multi-only", action="store_true", help="only the multi-problem form")
     return ap.parse_args()
 
 
@@ -70,6 +73,9 @@ def main():
 
     from paper_2012_13133_amd import kryging as K, synth
 
+    if args.multi_only:
+        print(json.dumps({"multi": multi_bench(args, K, synth, np)}))
+        return
     n = args.n
     nu, rho, eta = 1.5, 0.05, 0.2
     mask = synth.uniform_mask(n, n, 0.3, seed=101)
@@ -208,6 +214,9 @@ def main():
         torch.cuda.empty_cache()
         serve = serve_bench(args, K, synth, np)
 
+    # ---- multi-problem form: independent grids of different sizes ----
+    multi = multi_bench(args, K, synth, np) if args.multi > 0 else None
+
     # ---- CPU oracle on a bounded sample ----
     cpu = None
     if not args.no_cpu:
@@ -251,6 +260,7 @@ def main():
         "results_first_point": results[0],
     }
     out["serve"] = serve
+    out["multi"] = multi
     print(json.dumps(out))
     if P is not None:
         P.close()
@@ -349,6 +359,65 @@ def serve_bench(args, K, synth, np):
     log("serve: p50 %.1f ms p99 %.1f ms, %.1f req/s vs plain fp64 sequential %.1f req/s" %
         (out["p50_ms"], out["p99_ms"], out["req_per_s"], out["plain_fp64_sequential_req_per_s"]))
     return out
+
+
+def multi_bench(args, K, synth, np):
+    """Multi-problem form: independent problems on square grids with sides
+    log-uniform in the given range, 20-50 % missing uniformly at random, nu in
+    {0.5, 1.5}, range log-uniform in [0.02, 0.2], nugget ratio 0.1, data drawn
+    by circulant embedding plus nugget noise; 32 probes x 50 Lanczos steps
+    (reorthogonalised) and CG to 1e-8 per problem, FP32 transforms.  Times one
+    kry_loglik_multi call against the same problems one at a time (FP32) and
+    in the plain FP64 form, and reports the largest relative difference of
+    the batched log-likelihoods from the FP64 ones."""
+    import torch
+
+    lo, hi = (int(x) for x in args.multi_sides.split(","))
+    rng = np.random.default_rng(808)
+    ctx = K.kry_ctx_create()
+    sides = synth.log_uniform_sides(args.multi, lo, hi, seed=809)
+    hs, ths, cells = [], [], 0
+    for i, n in enumerate(sides):
+        n = int(n)
+        mask = synth.uniform_mask(n, n, float(rng.uniform(0.2, 0.5)), seed=3000 + i)
+        th = K.theta(sigma2=1.0, tau2=0.1, range=float(np.exp(rng.uniform(np.log(0.02), np.log(0.2)))),
+                     nu=float(rng.choice([0.5, 1.5])))
+        h = K.kry_problem_create(ctx, n, n, mask)
+        Nt = K.kry_psd_torus(h, th)
+        x, _ = K.kry_sample(h, th, Nt[0], Nt[1], 4000 + i, 0, 1, n, n)
+        K.kry_problem_set_data(h, x[0] + np.sqrt(0.1) * rng.standard_normal((n, n)))
+        hs.append(h)
+        ths.append(th)
+        cells += n * n
+    o32 = K.kry_opts_default(lanczos_steps=50, num_probes=32, reorth=1, precision=K.KRY_FP32, cg_rtol=1e-8,
+                             cg_maxit=100000)
+    o64 = K.kry_opts_default(lanczos_steps=50, num_probes=32, reorth=1, precision=K.KRY_FP64, cg_rtol=1e-8,
+                             cg_maxit=100000)
+    try:
+        K.kry_loglik_multi(hs[:2], ths[:2], o32)  # warm-up (kernels, buffers)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        multi = K.kry_loglik_multi(hs, ths, o32)
+        t_multi = time.perf_counter() - t0
+        log("multi: %d problems (%d cells) in %.2f s" % (len(hs), cells, t_multi))
+        t0 = time.perf_counter()
+        for h, th in zip(hs, ths):
+            K.kry_loglik(h, th, o32)
+        t_seq32 = time.perf_counter() - t0
+        log("one at a time FP32: %.2f s" % t_seq32)
+        t0 = time.perf_counter()
+        plain = [K.kry_loglik(h, th, o64) for h, th in zip(hs, ths)]
+        t_seq64 = time.perf_counter() - t0
+        log("plain FP64 one at a time: %.2f s" % t_seq64)
+    finally:
+        for h in hs:
+            K.kry_problem_destroy(h)
+        K.kry_ctx_destroy(ctx)
+    err = max(abs(m["loglik"] - p_["loglik"]) / abs(p_["loglik"]) for m, p_ in zip(multi, plain))
+    return {"problems": len(hs), "sides": [lo, hi], "cells": cells, "seconds": t_multi,
+            "evals_per_s": len(hs) / t_multi, "one_at_a_time_fp32_evals_per_s": len(hs) / t_seq32,
+            "plain_fp64_evals_per_s": len(hs) / t_seq64, "multi_vs_plain_fp64": t_seq64 / t_multi,
+            "multi_vs_one_at_a_time_fp32": t_seq32 / t_multi, "max_rel_err_vs_fp64": err}
 
 
 def cpu_baseline(n, mask, th, p, budget_s=15.0):

@@ -142,7 +142,7 @@ void bind(Ctx& c) { KRY_HIP(hipSetDevice(c.device)); }
 template <typename R>
 MatvecFn<R> masked_op(Problem& P, const void* lam, int64_t lam_tstride, int vpt, const double* d_eta) {
     Problem* pp = &P;
-    return [pp, lam, lam_tstride, vpt, d_eta](const R* x, R* y, int nvec, hipStream_t st) {
+    return [pp, lam, lam_tstride, vpt, d_eta](const R* x, R* y, int nvec, hipStream_t st, const int* active) {
         Problem& Q = *pp;
         ConvSpec s;
         s.N1 = Q.N1;
@@ -166,6 +166,7 @@ MatvecFn<R> masked_op(Problem& P, const void* lam, int64_t lam_tstride, int vpt,
         s.vecs_per_theta = vpt;
         s.tab = Q.tab;
         s.tab_vpp = vpt;
+        s.active = active;
         conv_apply<R>(Q, s, st);
     };
 }
@@ -392,7 +393,7 @@ void solve_device(Problem& P, int precision, const void* lam64, const void* lam3
         cg_run<float>(A32, p, nrhs, b32, x32, inner, maxit, cb, it, rr, st, &lim);
         for (int v = 0; v < nrhs; ++v) out.iters[v] += it[v];
         add_f32(x32, X, vn, st);
-        A64(X, t64, nrhs, st);
+        A64(X, t64, nrhs, st, nullptr);
         KRY_HIP(hipMemcpyAsync(r64, B, vn * sizeof(double), hipMemcpyDeviceToDevice, st));
         axpby<double>(t64, r64, -1.0, 1.0, p, nrhs, st);
     }
@@ -1258,7 +1259,7 @@ static void matvec_dev_impl(Problem& P, const Matern& th, int nvec, const void* 
     P.scal.ensure(*P.ctx, 256);
     KRY_HIP(hipMemcpyAsync(P.scal.ptr, &eta, sizeof(double), hipMemcpyHostToDevice, st));
     auto A = masked_op<R>(P, spec_ptr<R>(S), 0, nvec, P.scal.as<double>());
-    A(static_cast<const R*>(in), static_cast<R*>(out), nvec, st);
+    A(static_cast<const R*>(in), static_cast<R*>(out), nvec, st, nullptr);
 }
 
 kry_status kry_matvec_device(kry_problem* prob, const kry_matern* theta, int32_t precision, int32_t nvec,

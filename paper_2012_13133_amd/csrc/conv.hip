@@ -121,6 +121,7 @@ struct StageAArgs {
     int vec0;
     const ProbDesc* tab;  // several problems: per-vector mask and block
     int tab_vpp;
+    const int* active;    // per-vector skip flags (nullable)
 };
 
 // Value of input column c of a row (0 beyond the data or off the mask).
@@ -174,6 +175,7 @@ __global__ void __launch_bounds__((row_vt<R, LOG2M>() > 1 ? 512 : 1024)) k_row_f
     const int row0 = (lid % gridDim.x) * a.RT;
     const int row = row0 + rr;
     const int vec = lid / gridDim.x;
+    if (a.active && !a.active[vec]) return;
     MaskView mask = a.mask;
     int rows_in = a.rows_in, row_len = a.row_len;
     if (a.tab) {
@@ -240,6 +242,7 @@ struct StageBArgs {
     double* spec_out;
     const ProbDesc* tab;  // several problems: per-vector rows and spectrum
     int tab_vpp;
+    const int* active;    // per-vector skip flags (nullable)
 };
 
 // Stage B: per column of the half spectrum, forward FFT of length L (rows
@@ -270,6 +273,12 @@ __global__ void __launch_bounds__(1024) k_col(StageBArgs a, const cpx<R>* __rest
     // overlaps the forward transform (an unused slot, vbase + u >= nvec,
     // reads the last vector's spectrum, never past the end)
     R lamv[MODE == B_SPEC ? 1 : V * 8];
+    if (a.active) {
+        bool any = false;
+#pragma unroll
+        for (int u = 0; u < V; ++u) any = any || (vbase + u < a.nvec && a.active[vbase + u]);
+        if (!any) return;
+    }
     int rows_in[V], rows_out[V];
 #pragma unroll
     for (int u = 0; u < V; ++u) {
@@ -365,7 +374,9 @@ struct StageCArgs {
     double scale;
     const ProbDesc* tab;  // several problems: per-vector mask and block;
     int tab_vpp;          // compact outputs are zero from the problem's count
-};                        // up to out_vstride
+                          // up to out_vstride
+    const int* active;    // per-vector skip flags (nullable)
+};
 
 // Stage C: read RT-row runs of X[k], k = 0..M, merge the even/odd split into
 // Z[k] = (X[k] + X*[M-k]) + i W^{-k} (X[k] - X*[M-k]), inverse FFT of length M,
@@ -392,6 +403,7 @@ __global__ void __launch_bounds__((row_vt<R, LOG2M>() > 1 ? 512 : 1024)) k_row_i
     const cpx<R>* Y = reinterpret_cast<const cpx<R>*>(a.Y) + vec * a.Y_vstride;
     const int rr = tid / TR, t = tid % TR;
     const int row = row0 + rr;
+    if (a.active && !a.active[vec]) return;
     MaskView mask = a.mask;
     int rows_out = a.rows_out, cols_out = a.cols_out;
     if (a.tab) {
@@ -668,6 +680,7 @@ static void run_stage_a(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R
     a.vec0 = vec0;
     a.tab = s.tab;
     a.tab_vpp = s.tab_vpp;
+    a.active = s.active ? s.active + vec0 : nullptr;
     dim3 grid((s.rows_in + t.RT - 1) / t.RT, nvec);
     const int lg = ilog2(M);
     Ctx& c = *P.ctx;
@@ -687,7 +700,8 @@ static void run_stage_a(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R
 template <typename R>
 static void run_stage_b(Problem& P, int N1, int M, int vec0, int nvec, cpx<R>* Y, int ldY, int64_t Yvs, int rows_in,
                         int rows_out, const void* lam, int64_t lam_tstride, int vpt, double* spec_out,
-                        hipStream_t st, const ProbDesc* tab = nullptr, int tab_vpp = 1) {
+                        hipStream_t st, const ProbDesc* tab = nullptr, int tab_vpp = 1,
+                        const int* active = nullptr) {
     const int T = N1 / 8;
     StageBArgs b;
     b.Y = Y;
@@ -704,6 +718,7 @@ static void run_stage_b(Problem& P, int N1, int M, int vec0, int nvec, cpx<R>* Y
     b.spec_out = spec_out;
     b.tab = tab;
     b.tab_vpp = tab_vpp;
+    b.active = active ? active + vec0 : nullptr;
     const int mode = spec_out ? B_SPEC : (2 * rows_in <= N1 ? B_LOW : B_FULL);
     const int lg = ilog2(N1);
     Ctx& c = *P.ctx;
@@ -744,6 +759,7 @@ static void run_stage_c(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R
     c.scale = s.scale;
     c.tab = s.tab;
     c.tab_vpp = s.tab_vpp;
+    c.active = s.active ? s.active + vec0 : nullptr;
     dim3 grid((s.rows_out + t.RT - 1) / t.RT, nvec);
     const int lg = ilog2(M);
     Ctx& cx = *P.ctx;
@@ -797,7 +813,7 @@ void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st) {
         run_stage_a<R>(P, s, v0, nv, Y, ldY, Yvs, st);
         mark(1);
         run_stage_b<R>(P, s.N1, M, v0, nv, Y, ldY, Yvs, s.rows_in, s.rows_out, s.lam, s.lam_tstride,
-                       s.vecs_per_theta, nullptr, st, s.tab, s.tab_vpp);
+                       s.vecs_per_theta, nullptr, st, s.tab, s.tab_vpp, s.active);
         mark(2);
         run_stage_c<R>(P, s, v0, nv, Y, ldY, Yvs, st);
         mark(3);

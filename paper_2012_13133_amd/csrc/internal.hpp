@@ -198,6 +198,9 @@ struct ConvSpec {
     // are zero from the problem's count up to out_vstride
     const ProbDesc* tab = nullptr;
     int tab_vpp = 1;
+    // per-vector flags (device, nullable): vectors flagged 0 are skipped and
+    // their outputs left as they were
+    const int* active = nullptr;
 };
 
 template <typename R>

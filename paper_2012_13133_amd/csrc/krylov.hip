@@ -208,31 +208,67 @@ __global__ void __launch_bounds__(RB) k_lanczos_beta(const double* __restrict__ 
 }
 
 // Classical Gram-Schmidt against stored basis vectors: h[v][i] = q_i . r
+constexpr int MQ = 8;  // dots per sweep of k_multidot_partial
+
 template <typename R>
 __global__ void __launch_bounds__(RB) k_multidot_partial(const R* __restrict__ Q, int64_t qslot, const R* __restrict__ r,
                                                          int nq, int64_t n, double* __restrict__ partial) {
-    __shared__ double sh[RB];
+    // MQ dots per sweep over the block's elements (r read once per sweep),
+    // each reduced across the wavefront by shuffles and across the block's
+    // wavefronts through LDS, always in the same order
+    __shared__ double sh[RB / 64][MQ];
     const int nblk = gridDim.x, vec = blockIdx.y;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const R* rv = r + vec * n;
-    for (int q = 0; q < nq; ++q) {
-        const R* qv = Q + q * qslot + vec * n;
-        double acc = 0.0;
-        for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)nblk * RB)
-            acc += (double)qv[i] * (double)rv[i];
-        acc = block_sum(acc, sh);
-        if (threadIdx.x == 0) partial[((int64_t)vec * nq + q) * nblk + blockIdx.x] = acc;
+    const R* qb = Q + vec * n;
+    for (int q0 = 0; q0 < nq; q0 += MQ) {
+        const int cnt = min(MQ, nq - q0);
+        double acc[MQ];
+#pragma unroll
+        for (int k = 0; k < MQ; ++k) acc[k] = 0.0;
+        for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)nblk * RB) {
+            const double ri = (double)rv[i];
+#pragma unroll
+            for (int k = 0; k < MQ; ++k)
+                if (k < cnt) acc[k] += (double)qb[(int64_t)(q0 + k) * qslot + i] * ri;
+        }
+#pragma unroll
+        for (int k = 0; k < MQ; ++k) {
+            if (k >= cnt) break;
+            double v = acc[k];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+            if (lane == 0) sh[wv][k] = v;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < cnt) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < RB / 64; ++w) t += sh[w][threadIdx.x];
+            partial[((int64_t)vec * nq + q0 + threadIdx.x) * nblk + blockIdx.x] = t;
+        }
+        __syncthreads();
     }
 }
 
-// r -= sum_i h_i q_i
+// r -= sum_i h_i q_i (subtracted in order of i; loads issued eight at a time)
 template <typename R>
 __global__ void k_multi_axpy(const R* __restrict__ Q, int64_t qslot, const double* __restrict__ h, int nq,
                              R* __restrict__ r, int64_t n) {
     const int vec = blockIdx.y;
     const double* hv = h + (int64_t)vec * nq;
+    const R* qb = Q + vec * n;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double acc = (double)r[vec * n + i];
-        for (int q = 0; q < nq; ++q) acc -= hv[q] * (double)Q[q * qslot + vec * n + i];
+        int q = 0;
+        for (; q + 8 <= nq; q += 8) {
+            R qv[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) qv[k] = qb[(int64_t)(q + k) * qslot + i];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc -= hv[q + k] * (double)qv[k];
+        }
+        for (; q < nq; ++q) acc -= hv[q] * (double)qb[(int64_t)q * qslot + i];
         r[vec * n + i] = (R)acc;
     }
 }
@@ -259,7 +295,7 @@ void lanczos_run(const MatvecFn<R>& A, int64_t n, int nvec, int m, bool reorth, 
         double* aj = B.alpha + (int64_t)j * nvec;
         double* bj = B.beta + (int64_t)j * nvec;
         const double* bprev = j > 0 ? B.beta + (int64_t)(j - 1) * nvec : nullptr;
-        A(q, B.W, nvec, st);
+        A(q, B.W, nvec, st, nullptr);
         dot_batched<R>(q, n, B.W, n, n, nvec, B.partial, aj, st);
         if (!reorth) {
             hipLaunchKernelGGL(k_lanczos_update<R>, dim3(nblk, nvec), dim3(RB), 0, st, B.W, q, qp, aj, bprev, n,
@@ -466,7 +502,7 @@ void cg_run(const MatvecFn<R>& A, int64_t n, int nvec, const R* b, R* x, double 
     std::vector<int> act(nvec);
     const int check = 16;
     for (int it = 0; it < loop_max; ++it) {
-        A(B.p, B.w, nvec, st);
+        A(B.p, B.w, nvec, st, B.active);
         dot_batched<R>(B.p, n, B.w, n, n, nvec, B.partial, B.pw, st);
         hipLaunchKernelGGL(k_cg_xr<R>, dim3(nblk, nvec), dim3(RB), 0, st, x, B.r, B.p, B.w, B.rr, B.pw, B.active, n,
                            B.partial);
@@ -703,7 +739,7 @@ void mscg_run(const MatvecFn<double>& A, const std::function<void(int, int)>& sw
     if (ublocks > 1024) ublocks = 1024;
     const int check = 16;
     for (int it = 0; it < maxit && Gact > 0; ++it) {
-        A(B.p, B.w, Gact, st);
+        A(B.p, B.w, Gact, st, nullptr);
         dot_batched<double>(B.p, n, B.w, n, n, Gact, B.partial, B.pw, st);
         hipLaunchKernelGGL(k_ms_alpha, dim3(1), dim3(256), 0, st, Gact, B.rr, B.pw, B.alpha, B.alpha_old, B.beta_old,
                            B.list, nlist, B.pos, B.sigma, B.zeta, B.zeta_old, B.zeta_new, B.alpha_s, B.active);

@@ -9,9 +9,11 @@ namespace kry {
 
 constexpr int KRY_MAX_LANCZOS = 512;
 
-// y_v = K x_v for nvec vectors of length n (contiguous, stride n).
+// y_v = K x_v for nvec vectors of length n (contiguous, stride n).  With
+// active (device, nvec flags) given, vectors whose flag is 0 may be skipped:
+// their y is left unspecified.
 template <typename R>
-using MatvecFn = std::function<void(const R* x, R* y, int nvec, hipStream_t st)>;
+using MatvecFn = std::function<void(const R* x, R* y, int nvec, hipStream_t st, const int* active)>;
 
 // Device buffers of one batched Lanczos run.  Coefficients are stored
 // step-major: alpha[j * nvec + v].
