@@ -127,6 +127,33 @@ kry_status kry_profile_begin(kry_ctx* ctx);
  * launches[3], and the number of vectors the recorded products processed. */
 kry_status kry_profile_end(kry_ctx* ctx, double* ms, int64_t* launches, int64_t* vectors);
 
+/* ---- launch configuration of the masked product ----------------------------- */
+/* Per (embedding, precision) choice of how the product's stage kernels are
+ * laid out.  Every choice computes bit-identical results; only speed
+ * differs. */
+typedef struct {
+    int32_t col_vectors;    /* vectors per workgroup of the column stage: 1 or 2          */
+    int32_t row_tile_scale; /* rows per row-stage tile: 64-byte runs of the transposed
+                               intermediate times this (1 or 2; capped by LDS)           */
+    int32_t row_vthreads;   /* values per thread in the row stages: 8 x this (1 or 2;
+                               2 only for rows of >= 1024 points)                         */
+    double ms;              /* kry_autotune: time of one product of nvec vectors        */
+} kry_tuning;
+
+/* Time every configuration on the problem's own embedding with a product of
+ * nvec (1..4096) compact vectors in `precision`, keep the fastest for that
+ * embedding and precision in the problem's context (used by every later
+ * product there) and return it.  Each candidate runs 2 untimed and 5 timed
+ * products (HIP events on the context's stream); ms is the fastest's median. */
+kry_status kry_autotune(kry_problem* prob, int32_t precision, int32_t nvec, kry_tuning* out);
+/* Set (t != NULL) or reset to the built-in default (t == NULL) the
+ * configuration used for embedding N1 x N2 in `precision` on this context;
+ * KRY_EINVAL for values outside the ranges above. */
+kry_status kry_set_tuning(kry_ctx* ctx, int32_t N1, int32_t N2, int32_t precision, const kry_tuning* t);
+/* The configuration in use for N1 x N2 in `precision` (ms = 0 unless set by
+ * kry_autotune). */
+kry_status kry_get_tuning(kry_ctx* ctx, int32_t N1, int32_t N2, int32_t precision, kry_tuning* out);
+
 /* ---- context and problems ----------------------------------------------- */
 /* Binds HIP device `device`; hbm_budget_bytes = 0 means no limit beyond the
  * device.  Creates the library's stream (default priority). */

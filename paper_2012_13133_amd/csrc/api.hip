@@ -1621,6 +1621,134 @@ kry_status kry_loglik_batch(kry_problem* prob, const kry_matern* thetas, int32_t
     return s;
 }
 
+// ---- launch configuration ---------------------------------------------------------------
+namespace {
+void check_tuning(const kry_tuning* t) {
+    KRY_REQUIRE(t->col_vectors == 1 || t->col_vectors == 2, "col_vectors must be 1 or 2");
+    KRY_REQUIRE(t->row_tile_scale == 1 || t->row_tile_scale == 2, "row_tile_scale must be 1 or 2");
+    KRY_REQUIRE(t->row_vthreads == 1 || t->row_vthreads == 2, "row_vthreads must be 1 or 2");
+}
+
+kry_tuning to_abi(const Tuning& t, int real_bytes) {
+    kry_tuning o;
+    o.col_vectors = t.col_v ? t.col_v : (real_bytes == 4 ? 2 : 1);
+    o.row_tile_scale = t.rt_scale;
+    o.row_vthreads = t.row_vt;
+    o.ms = t.ms;
+    return o;
+}
+
+template <typename R>
+Tuning autotune_impl(Problem& P, int nvec, hipStream_t st) {
+    Ctx& C = *P.ctx;
+    const int rb = (int)sizeof(R);
+    const auto key = std::make_tuple(P.N1, P.N2, rb);
+    std::vector<Tuning> cand;
+    for (int cv : {1, 2})
+        for (int rs : {1, 2})
+            for (int vt : {1, 2}) {
+                if (vt == 2 && P.N2 / 2 < 1024) continue;
+                Tuning t;
+                t.col_v = cv;
+                t.rt_scale = rs;
+                t.row_vt = vt;
+                cand.push_back(t);
+            }
+    // inputs: Rademacher vectors on the problem and the spectrum of a fixed point
+    const kry_matern th{1.0, 0.1, 0.1, 0.5, 1.0, 0.0};
+    Spectrum& S = problem_spectrum(P, to_matern(&th), st);
+    const size_t vb = (size_t)nvec * P.p * sizeof(R);
+    DevBuf& buf = P.tmp4;
+    buf.ensure(C, 2 * vb + 256);
+    R* in = buf.as<R>();
+    R* outv = reinterpret_cast<R*>(buf.as<char>() + vb);
+    double* d_eta = reinterpret_cast<double*>(buf.as<char>() + 2 * vb);
+    const double eta = 0.1;
+    KRY_HIP(hipMemcpyAsync(d_eta, &eta, sizeof(double), hipMemcpyHostToDevice, st));
+    make_probes<R>(P, nvec, 1, 0, in, st);
+    auto A = masked_op<R>(P, spec_ptr<R>(S), 0, nvec, d_eta);
+    hipEvent_t e0, e1;
+    KRY_HIP(hipEventCreate(&e0));
+    KRY_HIP(hipEventCreate(&e1));
+    Tuning best;
+    best.ms = 1e300;
+    try {
+        for (Tuning t : cand) {
+            {
+                std::lock_guard<std::mutex> g(C.tune_mu);
+                C.tuning[key] = t;
+            }
+            for (int w = 0; w < 2; ++w) A(in, outv, nvec, st, nullptr);
+            std::vector<float> ms(5);
+            for (float& m : ms) {
+                KRY_HIP(hipEventRecord(e0, st));
+                A(in, outv, nvec, st, nullptr);
+                KRY_HIP(hipEventRecord(e1, st));
+                KRY_HIP(hipEventSynchronize(e1));
+                KRY_HIP(hipEventElapsedTime(&m, e0, e1));
+            }
+            std::sort(ms.begin(), ms.end());
+            t.ms = ms[2];
+            if (t.ms < best.ms) best = t;
+        }
+    } catch (...) {
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        std::lock_guard<std::mutex> g(C.tune_mu);
+        C.tuning.erase(key);
+        throw;
+    }
+    KRY_HIP(hipEventDestroy(e0));
+    KRY_HIP(hipEventDestroy(e1));
+    std::lock_guard<std::mutex> g(C.tune_mu);
+    C.tuning[key] = best;
+    return best;
+}
+}  // namespace
+
+kry_status kry_autotune(kry_problem* prob, int32_t precision, int32_t nvec, kry_tuning* out) {
+    return guard([&] {
+        KRY_REQUIRE(prob && out, "NULL argument");
+        KRY_REQUIRE(precision == KRY_FP64 || precision == KRY_FP32, "bad precision");
+        KRY_REQUIRE(nvec >= 1 && nvec <= 4096, "nvec must be in [1, 4096]");
+        Problem& P = prob->P;
+        bind(*P.ctx);
+        const Tuning t = precision == KRY_FP32 ? autotune_impl<float>(P, nvec, P.ctx->stream)
+                                               : autotune_impl<double>(P, nvec, P.ctx->stream);
+        *out = to_abi(t, precision == KRY_FP32 ? 4 : 8);
+    });
+}
+
+kry_status kry_set_tuning(kry_ctx* ctx, int32_t N1, int32_t N2, int32_t precision, const kry_tuning* t) {
+    return guard([&] {
+        KRY_REQUIRE(ctx != nullptr, "NULL context");
+        KRY_REQUIRE(precision == KRY_FP64 || precision == KRY_FP32, "bad precision");
+        KRY_REQUIRE(N1 >= 16 && N2 >= 16 && N1 <= 8192 && N2 <= 8192 && (N1 & (N1 - 1)) == 0 && (N2 & (N2 - 1)) == 0,
+                    "N1, N2 must be powers of two in [16, 8192]");
+        const auto key = std::make_tuple((int)N1, (int)N2, precision == KRY_FP32 ? 4 : 8);
+        std::lock_guard<std::mutex> g(ctx->c.tune_mu);
+        if (!t) {
+            ctx->c.tuning.erase(key);
+            return;
+        }
+        check_tuning(t);
+        Tuning u;
+        u.col_v = t->col_vectors;
+        u.rt_scale = t->row_tile_scale;
+        u.row_vt = t->row_vthreads;
+        ctx->c.tuning[key] = u;
+    });
+}
+
+kry_status kry_get_tuning(kry_ctx* ctx, int32_t N1, int32_t N2, int32_t precision, kry_tuning* out) {
+    return guard([&] {
+        KRY_REQUIRE(ctx && out, "NULL argument");
+        KRY_REQUIRE(precision == KRY_FP64 || precision == KRY_FP32, "bad precision");
+        const int rb = precision == KRY_FP32 ? 4 : 8;
+        *out = to_abi(ctx->c.tuning_for(N1, N2, rb), rb);
+    });
+}
+
 kry_status kry_loglik_multi(kry_problem* const* probs, const kry_matern* thetas, int32_t count, const kry_opts* opts,
                             kry_loglik_result* out) {
     bool noconv = false;

@@ -157,12 +157,12 @@ __device__ __forceinline__ void load_pair(const StageAArgs& a, const MaskView& m
 // A row is transformed by TR = M / (8 VT) threads holding 8 VT values each;
 // when those lie in one wavefront the passes need no workgroup barrier, and
 // the only barrier is the one before the split, which mixes rows.
-template <typename R, int LOG2M, int IN>
-__global__ void __launch_bounds__((row_vt<R, LOG2M>() > 1 ? 512 : 1024)) k_row_fwd(StageAArgs a, const cpx<R>* __restrict__ twp,
-                                                  const cpx<R>* __restrict__ twb) {
+template <typename R, int LOG2M, int IN, int VT>
+__global__ void __launch_bounds__((VT > 1 ? 512 : 1024)) k_row_fwd(StageAArgs a, const cpx<R>* __restrict__ twp,
+                                                                   const cpx<R>* __restrict__ twb) {
     using S = Sched<LOG2M>;
     constexpr int M = S::L, T = M / 8, PM = padded(M) + 1;
-    constexpr int VT = row_vt<R, LOG2M>(), TR = T / VT;
+    constexpr int TR = T / VT;
     constexpr bool WAVE = TR <= 64;
     constexpr bool LOW = (IN == IN_COMPACT);  // row_len <= M: z[m] = 0 for m >= M/2
     extern __shared__ unsigned char smem_raw[];
@@ -383,12 +383,12 @@ struct StageCArgs {
 // then x[2m], x[2m+1] = Re, Im z[m] go to the observed cells (+ eta v) or the
 // grid.  Row threads as in stage A: the barriers are after the tile load and
 // after the merge; the passes of a row stay within its wavefront.
-template <typename R, int LOG2M, int OUT>
-__global__ void __launch_bounds__((row_vt<R, LOG2M>() > 1 ? 512 : 1024)) k_row_inv(StageCArgs a, const cpx<R>* __restrict__ twp,
-                                                  const cpx<R>* __restrict__ twb) {
+template <typename R, int LOG2M, int OUT, int VT>
+__global__ void __launch_bounds__((VT > 1 ? 512 : 1024)) k_row_inv(StageCArgs a, const cpx<R>* __restrict__ twp,
+                                                                   const cpx<R>* __restrict__ twb) {
     using S = Sched<LOG2M>;
     constexpr int M = S::L, T = M / 8, PM = padded(M) + 1;
-    constexpr int VT = row_vt<R, LOG2M>(), TR = T / VT;
+    constexpr int TR = T / VT;
     constexpr bool WAVE = TR <= 64;
     constexpr int NV = 8 * VT;  // values per thread
     constexpr int LRL = S::lr(true, S::npass - 1);
@@ -596,25 +596,19 @@ struct RowTiling {
     size_t lds;
 };
 
-// Rows per tile: transposed runs of RT * sizeof(cpx) = 64 bytes where the
-// workgroup (<= 1024 threads) and LDS allow; more rows for short rows.
-// Host mirror of row_vt: virtual threads per thread of a row transform.
+// Rows per tile: transposed runs of RT * sizeof(cpx) = 64 * rt_scale bytes
+// where the workgroup and LDS allow; more rows for short rows.  Each thread
+// holds 8 vt values of its row.
 template <typename R>
-static int row_vt_host(int) {
-    return 1;
-}
-
-template <typename R>
-static RowTiling row_tiling(int M) {
+static RowTiling row_tiling(int M, int rt_scale = 1, int vt = 1) {
     const size_t cs = sizeof(cpx<R>);
-    const int T = M / 8 / row_vt_host<R>(M);  // threads per row
+    const int T = M / 8 / vt;  // threads per row
+    const int tmax = vt > 1 ? 512 : 1024;
     const size_t PM = (size_t)M + M / 8 + 1;
-    int RT = (int)(64 / cs);
-    while (RT > 1 && RT * T > 1024) RT /= 2;
+    int RT = (int)(64 * rt_scale / cs);
+    while (RT > 1 && RT * T > tmax) RT /= 2;
     while (RT > 1 && RT * PM * cs > 150 * 1024) RT /= 2;
     while (RT * T < 256 && RT < 64 && (size_t)(2 * RT) * PM * cs <= 64 * 1024) RT *= 2;
-    // kernels with several virtual threads are compiled for <= 512 threads
-    KRY_REQUIRE(RT * T <= (row_vt_host<R>(M) > 1 ? 512 : 1024), "row tiling exceeds the kernel's thread bound");
     RowTiling t;
     t.RT = RT;
     t.T = T;
@@ -623,27 +617,35 @@ static RowTiling row_tiling(int M) {
     return t;
 }
 
+// Row kernels with two virtual threads exist for rows of >= 1024 points.
+template <int LG>
+constexpr bool has_vt2() { return LG >= 10; }
+
 template <typename R, int LG, int IN>
-static void launch_row_fwd(const StageAArgs& a, dim3 grid, const RowTiling& t, Ctx& c, hipStream_t st) {
-    auto k = k_row_fwd<R, LG, IN>;
+static void launch_row_fwd(const StageAArgs& a, dim3 grid, const RowTiling& t, int vt, Ctx& c, hipStream_t st) {
+    auto k = k_row_fwd<R, LG, IN, 1>;
+    if constexpr (has_vt2<LG>()) {
+        if (vt == 2) k = k_row_fwd<R, LG, IN, 2>;
+    }
     set_lds(k, t.lds);
     hipLaunchKernelGGL(k, grid, dim3(t.threads), t.lds, st, a, plan_table<R>(c, LG), twiddles<R>(c));
     KRY_HIP(hipGetLastError());
 }
 
 template <typename R, int LG, int OUT>
-static void launch_row_inv(const StageCArgs& a, dim3 grid, const RowTiling& t, Ctx& c, hipStream_t st) {
-    auto k = k_row_inv<R, LG, OUT>;
+static void launch_row_inv(const StageCArgs& a, dim3 grid, const RowTiling& t, int vt, Ctx& c, hipStream_t st) {
+    auto k = k_row_inv<R, LG, OUT, 1>;
+    if constexpr (has_vt2<LG>()) {
+        if (vt == 2) k = k_row_inv<R, LG, OUT, 2>;
+    }
     set_lds(k, t.lds);
     hipLaunchKernelGGL(k, grid, dim3(t.threads), t.lds, st, a, plan_table<R>(c, LG), twiddles<R>(c));
     KRY_HIP(hipGetLastError());
 }
 
-template <typename R, int LG, int MODE>
-static void launch_col(const StageBArgs& b, int nvec, Ctx& c, hipStream_t st) {
+template <typename R, int LG, int MODE, int V>
+static void launch_col_v(const StageBArgs& b, int nvec, Ctx& c, hipStream_t st) {
     constexpr int L = 1 << LG, T = L / 8;
-    // two vectors per workgroup in FP32 (shared twiddles and spectrum), one in FP64
-    constexpr int V = (sizeof(R) == 4 && MODE != B_SPEC) ? 2 : 1;
     const size_t lds = (size_t)b.CB * V * padded(L) * sizeof(cpx<R>);
     dim3 grid((b.ncols + b.CB - 1) / b.CB, (nvec + V - 1) / V);
     auto k = k_col<R, LG, MODE, V>;
@@ -654,13 +656,25 @@ static void launch_col(const StageBArgs& b, int nvec, Ctx& c, hipStream_t st) {
     KRY_HIP(hipGetLastError());
 }
 
+// V vectors per workgroup share twiddle and spectrum loads; the spectrum
+// transform takes one.
+template <typename R, int LG, int MODE>
+static void launch_col(const StageBArgs& b, int nvec, int V, Ctx& c, hipStream_t st) {
+    if constexpr (MODE != B_SPEC) {
+        if (V == 2) {
+            launch_col_v<R, LG, MODE, 2>(b, nvec, c, st);
+            return;
+        }
+    }
+    launch_col_v<R, LG, MODE, 1>(b, nvec, c, st);
+}
+
 #define KRY_SIZES(X) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
 
 template <typename R>
 static void run_stage_a(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R>* Y, int ldY, int64_t Yvs,
-                        hipStream_t st) {
+                        const RowTiling& t, int vt, hipStream_t st) {
     const int M = s.N2 / 2;
-    const RowTiling t = row_tiling<R>(M);
     StageAArgs a;
     a.in = s.in_mode == IN_COMPACT ? (const void*)((const R*)s.in + vec0 * s.in_vstride)
                                    : (const void*)((const double*)s.in + vec0 * s.in_vstride);
@@ -686,9 +700,9 @@ static void run_stage_a(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R
     Ctx& c = *P.ctx;
 #define KRY_A(LG)                                                                             \
     case LG:                                                                                  \
-        if (s.in_mode == IN_COMPACT) launch_row_fwd<R, LG, IN_COMPACT>(a, grid, t, c, st);    \
-        else if (s.in_mode == IN_DENSE) launch_row_fwd<R, LG, IN_DENSE>(a, grid, t, c, st);   \
-        else launch_row_fwd<R, LG, IN_NOISE>(a, grid, t, c, st);                              \
+        if (s.in_mode == IN_COMPACT) launch_row_fwd<R, LG, IN_COMPACT>(a, grid, t, vt, c, st);\
+        else if (s.in_mode == IN_DENSE) launch_row_fwd<R, LG, IN_DENSE>(a, grid, t, vt, c, st);\
+        else launch_row_fwd<R, LG, IN_NOISE>(a, grid, t, vt, c, st);                          \
         break;
     switch (lg) {
         KRY_SIZES(KRY_A)
@@ -701,7 +715,7 @@ template <typename R>
 static void run_stage_b(Problem& P, int N1, int M, int vec0, int nvec, cpx<R>* Y, int ldY, int64_t Yvs, int rows_in,
                         int rows_out, const void* lam, int64_t lam_tstride, int vpt, double* spec_out,
                         hipStream_t st, const ProbDesc* tab = nullptr, int tab_vpp = 1,
-                        const int* active = nullptr) {
+                        const int* active = nullptr, int V = 1) {
     const int T = N1 / 8;
     StageBArgs b;
     b.Y = Y;
@@ -724,9 +738,9 @@ static void run_stage_b(Problem& P, int N1, int M, int vec0, int nvec, cpx<R>* Y
     Ctx& c = *P.ctx;
 #define KRY_B(LG)                                                                          \
     case LG + 1:                                                                           \
-        if (mode == B_LOW) launch_col<R, LG + 1, B_LOW>(b, nvec, c, st);                   \
-        else if (mode == B_FULL) launch_col<R, LG + 1, B_FULL>(b, nvec, c, st);            \
-        else launch_col<R, LG + 1, B_SPEC>(b, nvec, c, st);                                \
+        if (mode == B_LOW) launch_col<R, LG + 1, B_LOW>(b, nvec, V, c, st);                \
+        else if (mode == B_FULL) launch_col<R, LG + 1, B_FULL>(b, nvec, V, c, st);         \
+        else launch_col<R, LG + 1, B_SPEC>(b, nvec, 1, c, st);                             \
         break;
     switch (lg) {
         KRY_SIZES(KRY_B)
@@ -737,9 +751,8 @@ static void run_stage_b(Problem& P, int N1, int M, int vec0, int nvec, cpx<R>* Y
 
 template <typename R>
 static void run_stage_c(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R>* Y, int ldY, int64_t Yvs,
-                        hipStream_t st) {
+                        const RowTiling& t, int vt, hipStream_t st) {
     const int M = s.N2 / 2;
-    const RowTiling t = row_tiling<R>(M);
     StageCArgs c;
     c.Y = Y;
     c.ldY = ldY;
@@ -765,8 +778,8 @@ static void run_stage_c(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R
     Ctx& cx = *P.ctx;
 #define KRY_C(LG)                                                                             \
     case LG:                                                                                  \
-        if (s.out_mode == OUT_COMPACT) launch_row_inv<R, LG, OUT_COMPACT>(c, grid, t, cx, st);\
-        else launch_row_inv<R, LG, OUT_GRID>(c, grid, t, cx, st);                             \
+        if (s.out_mode == OUT_COMPACT) launch_row_inv<R, LG, OUT_COMPACT>(c, grid, t, vt, cx, st);\
+        else launch_row_inv<R, LG, OUT_GRID>(c, grid, t, vt, cx, st);                         \
         break;
     switch (lg) {
         KRY_SIZES(KRY_C)
@@ -785,7 +798,11 @@ void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st) {
     KRY_REQUIRE(!s.tab || (s.in_mode == IN_COMPACT && s.tab_vpp >= 1), "problem tables take compact inputs");
     if (s.nvec <= 0) return;
     const int M = s.N2 / 2;
-    const RowTiling ta = row_tiling<R>(M);
+    // launch configuration of this embedding and precision (bit-identical results)
+    const Tuning tu = P.ctx->tuning_for(s.N1, s.N2, (int)sizeof(R));
+    const int vt = (M >= 1024 && tu.row_vt == 2) ? 2 : 1;
+    const int V = tu.col_v ? tu.col_v : (sizeof(R) == 4 ? 2 : 1);
+    const RowTiling ta = row_tiling<R>(M, tu.rt_scale, vt);
     const int rows_max = s.rows_in > s.rows_out ? s.rows_in : s.rows_out;
     const int ldY = ((rows_max + ta.RT - 1) / ta.RT) * ta.RT;
     const int64_t Yvs = (int64_t)(M + 1) * ldY;
@@ -810,12 +827,12 @@ void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st) {
             KRY_HIP(hipEventRecord(pr.pool[pr.next++], st));
         };
         mark(0);
-        run_stage_a<R>(P, s, v0, nv, Y, ldY, Yvs, st);
+        run_stage_a<R>(P, s, v0, nv, Y, ldY, Yvs, ta, vt, st);
         mark(1);
         run_stage_b<R>(P, s.N1, M, v0, nv, Y, ldY, Yvs, s.rows_in, s.rows_out, s.lam, s.lam_tstride,
-                       s.vecs_per_theta, nullptr, st, s.tab, s.tab_vpp, s.active);
+                       s.vecs_per_theta, nullptr, st, s.tab, s.tab_vpp, s.active, V);
         mark(2);
-        run_stage_c<R>(P, s, v0, nv, Y, ldY, Yvs, st);
+        run_stage_c<R>(P, s, v0, nv, Y, ldY, Yvs, ta, vt, st);
         mark(3);
         if (pr.on) {
             rec[4] = nv;
@@ -906,7 +923,7 @@ void spectrum_device(Problem& P, int N1, int N2, const Matern& th, double* d_lam
     s.in_rstride = N2;
     s.rows_in = N1;
     s.row_len = N2;
-    run_stage_a<double>(P, s, 0, 1, Y, ldY, Yvs, st);
+    run_stage_a<double>(P, s, 0, 1, Y, ldY, Yvs, ta, 1, st);
     run_stage_b<double>(P, N1, M, 0, 1, Y, ldY, Yvs, N1, N1, nullptr, 0, 1, d_lam, st);
     // min / max
     double* part = reinterpret_cast<double*>(reinterpret_cast<char*>(P.spectmp.ptr) + (size_t)Yvs * sizeof(cpx<double>));

@@ -230,12 +230,4 @@ struct LdsPassesVT {
     }
 };
 
-// Virtual threads per thread of a row transform of length 2^LOG2M.  One (8
-// values per thread) measured fastest at the embeddings used here; rows of
-// at most 512 points then fit one wavefront and exchange with wave_sync.
-template <typename R, int LOG2M>
-constexpr int row_vt() {
-    return 1;
-}
-
 }  // namespace kry

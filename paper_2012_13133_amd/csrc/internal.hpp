@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <map>
+#include <tuple>
 #include <cstdint>
 #include <memory>
 #include <mutex>
@@ -43,6 +45,14 @@ struct StageProfile {
     size_t next = 0;
 };
 
+// Launch configuration of the product's stage kernels (see kry_tuning).
+struct Tuning {
+    int col_v = 0;       // 0: default for the precision
+    int rt_scale = 1;
+    int row_vt = 1;
+    double ms = 0.0;
+};
+
 struct Ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -54,6 +64,13 @@ struct Ctx {
     void* plan64[14] = {};  // per-length pass twiddle tables (index log2 length)
     void* plan32[14] = {};
     std::mutex alloc_mu;     // guards `allocated` (server slots allocate concurrently)
+    std::map<std::tuple<int, int, int>, Tuning> tuning;  // (N1, N2, bytes per real) -> configuration
+    std::mutex tune_mu;
+    Tuning tuning_for(int N1, int N2, int real_bytes) {
+        std::lock_guard<std::mutex> g(tune_mu);
+        auto it = tuning.find(std::make_tuple(N1, N2, real_bytes));
+        return it == tuning.end() ? Tuning{} : it->second;
+    }
 };
 
 void* dev_alloc(Ctx& c, size_t bytes);

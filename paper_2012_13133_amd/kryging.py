@@ -54,6 +54,14 @@ class kry_loglik_result(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class kry_tuning(C.Structure):
+    _fields_ = [("col_vectors", C.c_int32), ("row_tile_scale", C.c_int32), ("row_vthreads", C.c_int32),
+                ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class kry_request(C.Structure):
     _fields_ = [("kind", C.c_int32), ("prob", C.c_void_p), ("theta", kry_matern), ("opts", kry_opts),
                 ("targets", C.POINTER(C.c_int64)), ("ntargets", C.c_int64), ("variances", C.c_int32),
@@ -97,6 +105,9 @@ _SIGS = {
     "kry_loglik": (C.c_int, [_P, C.POINTER(kry_matern), C.POINTER(kry_opts), C.POINTER(kry_loglik_result)]),
     "kry_loglik_batch": (C.c_int, [_P, C.POINTER(kry_matern), C.c_int32, C.POINTER(kry_opts),
                                    C.POINTER(kry_loglik_result)]),
+    "kry_autotune": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(kry_tuning)]),
+    "kry_set_tuning": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(kry_tuning)]),
+    "kry_get_tuning": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(kry_tuning)]),
     "kry_loglik_multi": (C.c_int, [C.POINTER(_P), C.POINTER(kry_matern), C.c_int32, C.POINTER(kry_opts),
                                    C.POINTER(kry_loglik_result)]),
     "kry_fit": (C.c_int, [_P, C.POINTER(kry_matern), C.c_uint32, C.POINTER(kry_opts), C.c_double, C.c_int32,
@@ -341,6 +352,27 @@ def kry_loglik_multi(probs, thetas, opts, allow_noconv=False):
     if not (allow_noconv and s == KRY_ENOCONV):
         _check(s)
     return [r.as_dict() for r in res]
+
+
+def kry_autotune(prob, precision, nvec=32):
+    t = kry_tuning()
+    _check(lib.kry_autotune(prob, precision, nvec, C.byref(t)))
+    return t.as_dict()
+
+
+def kry_set_tuning(ctx, N1, N2, precision, col_vectors=None, row_tile_scale=1, row_vthreads=1):
+    """col_vectors None resets the configuration to the built-in default."""
+    if col_vectors is None:
+        _check(lib.kry_set_tuning(ctx, N1, N2, precision, None))
+    else:
+        t = kry_tuning(col_vectors, row_tile_scale, row_vthreads, 0.0)
+        _check(lib.kry_set_tuning(ctx, N1, N2, precision, C.byref(t)))
+
+
+def kry_get_tuning(ctx, N1, N2, precision):
+    t = kry_tuning()
+    _check(lib.kry_get_tuning(ctx, N1, N2, precision, C.byref(t)))
+    return t.as_dict()
 
 
 def kry_fit(prob, init, free_mask, opts, xtol=1e-3, maxiter=200):

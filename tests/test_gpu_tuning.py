@@ -1,0 +1,52 @@
+"""GPU: launch configurations of the masked product (autotuner) compute
+bit-identical results; the autotuner keeps a valid configuration."""
+import itertools
+
+import numpy as np
+import pytest
+
+from paper_2012_13133_amd import synth
+from tests.oracle_cases import theta
+
+pytestmark = pytest.mark.gpu
+
+K = pytest.importorskip("paper_2012_13133_amd.kryging")
+
+TH = theta(0.1, 1.5, tau2=0.2, ratio=1.5, angle=0.4)
+
+
+@pytest.mark.parametrize("shape", [(40, 36), (600, 530)])  # 128 x 128 and 2048 x 2048 embeddings
+def test_every_configuration_is_bit_identical(shape):
+    n1, n2 = shape
+    mask = synth.uniform_mask(n1, n2, 0.3, seed=3)
+    th = K.theta_from_dict(TH)
+    with K.Problem(n1, n2, mask) as P:
+        v = synth.random_vectors(P.p, 3, seed=4)
+        for prec in (K.KRY_FP64, K.KRY_FP32):
+            K.kry_set_tuning(P.ctx, P.N1, P.N2, prec)
+            ref = K.kry_matvec(P.h, th, v, prec)
+            for cv, rs, vt in itertools.product((1, 2), (1, 2), (1, 2)):
+                K.kry_set_tuning(P.ctx, P.N1, P.N2, prec, cv, rs, vt)
+                got = K.kry_matvec(P.h, th, v, prec)
+                assert np.array_equal(got, ref), (prec, cv, rs, vt)
+            K.kry_set_tuning(P.ctx, P.N1, P.N2, prec)
+
+
+def test_autotune_keeps_a_valid_configuration():
+    n1, n2 = 200, 180
+    mask = synth.uniform_mask(n1, n2, 0.3, seed=5)
+    with K.Problem(n1, n2, mask) as P:
+        for prec in (K.KRY_FP64, K.KRY_FP32):
+            t = K.kry_autotune(P.h, prec, 8)
+            assert t["col_vectors"] in (1, 2) and t["row_tile_scale"] in (1, 2) and t["row_vthreads"] in (1, 2)
+            assert t["ms"] > 0
+            assert K.kry_get_tuning(P.ctx, P.N1, P.N2, prec) == t
+            K.kry_set_tuning(P.ctx, P.N1, P.N2, prec)
+            d = K.kry_get_tuning(P.ctx, P.N1, P.N2, prec)
+            assert d["ms"] == 0 and d["col_vectors"] == (2 if prec == K.KRY_FP32 else 1)
+        with pytest.raises(K.KryError):
+            K.kry_set_tuning(P.ctx, P.N1, P.N2, K.KRY_FP32, 3, 1, 1)
+        with pytest.raises(K.KryError):
+            K.kry_set_tuning(P.ctx, 100, P.N2, K.KRY_FP32, 1, 1, 1)
+        with pytest.raises(K.KryError):
+            K.kry_autotune(P.h, K.KRY_FP32, 0)
