@@ -62,6 +62,28 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per launch of the FP32 column stage (batch 32, 1024 x 1024
+    workload) from the committed rocprofv3 counter summary, or None when the
+    kernel sources have changed since those counters were taken."""
+    import hashlib
+    import re
+
+    try:
+        with open(os.path.join(ROOT, "profiles", "masked_product_1024sq_b32.md")) as f:
+            txt = f.read()
+    except OSError:
+        return None
+    vals = dict(re.findall(r"^(traffic_stage_b_fp32_bytes|kernel_sources_sha256): (\S+)$", txt, re.M))
+    h = hashlib.sha256()
+    for name in ("conv.hip", "fftk.hpp", "fft.hpp", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_2012_13133_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if vals.get("kernel_sources_sha256") != h.hexdigest() or "traffic_stage_b_fp32_bytes" not in vals:
+        return None
+    return int(vals["traffic_stage_b_fp32_bytes"])
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -89,6 +111,11 @@ def main():
     y = x[0] + np.sqrt(eta) * rng.standard_normal((n, n))
     K.kry_problem_set_data(P.h, y)
     log("data sampled on a %dx%d torus" % N)
+
+    # ---- launch configuration picked by the autotuner for this embedding ----
+    tuning = {"fp32": K.kry_autotune(P.h, K.KRY_FP32, args.mv_batch),
+              "fp64": K.kry_autotune(P.h, K.KRY_FP64, args.mv_batch)}
+    log("autotuned: %s" % tuning)
 
     # ---- isolated batched masked product (FP32 and FP64) with stage timing ----
     dev = torch.device("cuda:0")
@@ -245,6 +272,7 @@ def main():
             "embedding": emb,
         },
         "loglik_evals_per_s": evals_per_s,
+        "tuning": tuning,
         "matvec_batched": {"fp32": mv[K.KRY_FP32], "fp64": mv[K.KRY_FP64],
                            "bytes_per_launch_fp32": mv_bytes, "achieved_GBs_fp32": mv_achieved},
         "plain_fp64": plain,
@@ -252,7 +280,8 @@ def main():
         "batched_cg_iters_per_range": [max(r["cg_iters"] for r in g_) for g_ in groups],
         "products_per_step": per_step,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if (dom == 1 and Bv == 32 and n == 1024) else None,
                      "kernel": ["stage A (row transform)", "stage B (column transform x spectrum)",
                                 "stage C (inverse row transform, gather)"][dom],
                      "bytes_per_launch": stage_bytes[dom], "launch_ms": stage_ms[dom], "batch": Bv},

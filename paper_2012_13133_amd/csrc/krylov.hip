@@ -208,46 +208,19 @@ __global__ void __launch_bounds__(RB) k_lanczos_beta(const double* __restrict__ 
 }
 
 // Classical Gram-Schmidt against stored basis vectors: h[v][i] = q_i . r
-constexpr int MQ = 8;  // dots per sweep of k_multidot_partial
-
 template <typename R>
 __global__ void __launch_bounds__(RB) k_multidot_partial(const R* __restrict__ Q, int64_t qslot, const R* __restrict__ r,
                                                          int nq, int64_t n, double* __restrict__ partial) {
-    // MQ dots per sweep over the block's elements (r read once per sweep),
-    // each reduced across the wavefront by shuffles and across the block's
-    // wavefronts through LDS, always in the same order
-    __shared__ double sh[RB / 64][MQ];
+    __shared__ double sh[RB];
     const int nblk = gridDim.x, vec = blockIdx.y;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const R* rv = r + vec * n;
-    const R* qb = Q + vec * n;
-    for (int q0 = 0; q0 < nq; q0 += MQ) {
-        const int cnt = min(MQ, nq - q0);
-        double acc[MQ];
-#pragma unroll
-        for (int k = 0; k < MQ; ++k) acc[k] = 0.0;
-        for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)nblk * RB) {
-            const double ri = (double)rv[i];
-#pragma unroll
-            for (int k = 0; k < MQ; ++k)
-                if (k < cnt) acc[k] += (double)qb[(int64_t)(q0 + k) * qslot + i] * ri;
-        }
-#pragma unroll
-        for (int k = 0; k < MQ; ++k) {
-            if (k >= cnt) break;
-            double v = acc[k];
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-            if (lane == 0) sh[wv][k] = v;
-        }
-        __syncthreads();
-        if ((int)threadIdx.x < cnt) {
-            double t = 0.0;
-#pragma unroll
-            for (int w = 0; w < RB / 64; ++w) t += sh[w][threadIdx.x];
-            partial[((int64_t)vec * nq + q0 + threadIdx.x) * nblk + blockIdx.x] = t;
-        }
-        __syncthreads();
+    for (int q = 0; q < nq; ++q) {
+        const R* qv = Q + q * qslot + vec * n;
+        double acc = 0.0;
+        for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)nblk * RB)
+            acc += (double)qv[i] * (double)rv[i];
+        acc = block_sum(acc, sh);
+        if (threadIdx.x == 0) partial[((int64_t)vec * nq + q) * nblk + blockIdx.x] = acc;
     }
 }
 
