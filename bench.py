@@ -1,21 +1,23 @@
 """Benchmark of the Kryging hot path on one MI355X.
 
 Workload (the metric shape): a 1024 x 1024 grid on the unit square with 30 %
-of the cells missing uniformly at random (p = 734,003 observed cells),
-Matern nu = 1.5, range 0.05, nugget ratio 0.2, data drawn by circulant
-embedding on a PSD torus plus nugget noise (synthetic, seeded).
+of the cells missing uniformly at random (p = 734,003 observed cells), data
+drawn by circulant embedding (Matern nu = 1.5, range 0.05) on a PSD torus plus
+nugget noise (ratio 0.2), synthetic and seeded.
 
-One step = one pass of the whole hot path over one batch of parameter
-points: lag grid and spectrum for every point, Rademacher probes, batched
-Lanczos (20 probes x 50 steps per point), Gauss quadrature, multi-RHS CG for
-the quadratic forms and the likelihood assembly (kry_loglik_batch, FP32
-transforms with FP64 scalars).  `value` is the masked products per second
-inside the timed steps (Lanczos products + CG iterations; the FP64
-refinement products are not counted).  The JSON line also carries the
-isolated batched product rate, likelihood evaluations per second of the
-batched FP32 form and of the plain FP64 single-point form, their accuracy
-against FP64 with the same probes, the roofline of the dominant kernel and
-the CPU oracle timed on a bounded sample.
+One step = one pass of the whole hot path over one batch of parameter points:
+kry_loglik_batch over the 10 x 10 grid of range in [0.01, 0.2] x nugget ratio
+in [0.01, 1] (log-spaced) with shift sharing -- lag grid and spectrum per
+range, Rademacher probes, batched Lanczos (20 probes x 50 steps,
+reorthogonalised; FP32 products, FP64 coefficients) on the nugget-free
+covariance, Gauss quadrature per point, FP64 multi-shift CG to 1e-8 per range
+and the likelihood assembly.  `value` is the masked products per second
+applied inside the timed steps.  The JSON line also carries the likelihood
+evaluations per second, the plain FP64 single-point form on a stratified
+sample of the same grid and the batched form's accuracy against it, the
+isolated batched product rates, the roofline of the dominant kernel (with the
+counter-measured traffic from the committed profile), the served form, the
+multi-problem form and the CPU oracle timed on a bounded sample.
 """
 import argparse
 import json
@@ -260,7 +262,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32/f64",
         "data": "synthetic",
         "config": {
             "workload": "1024x1024 grid, 30%% uniform missing (p=%d), Matern nu=1.5, data at range 0.05 nugget "
