@@ -187,14 +187,49 @@ __global__ void __launch_bounds__((VT > 1 ? 512 : 1024)) k_row_fwd(StageAArgs a,
     }
     cpx<R>* buf = lds + rr * PM;
     cpx<R> v[8 * VT];
+    if constexpr (IN == IN_COMPACT) {
+        // every mask word and offset first, then every value: two rounds of
+        // independent loads instead of a dependent chain per pair.  Pairs
+        // outside the row read word 0 and element 0 and are discarded.
+        constexpr int NP = LOW ? 4 : 8;
+        const R* vin = reinterpret_cast<const R*>(a.in) + vec * a.in_vstride;
+        uint32_t wd[VT * NP], bs[VT * NP];
 #pragma unroll
-    for (int u = 0; u < VT; ++u)
+        for (int u = 0; u < VT; ++u)
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            v[u * 8 + r] = cpx<R>{(R)0, (R)0};
-            if (LOW && r >= 4) continue;
-            if (row < rows_in) load_pair<R, IN>(a, mask, row_len, vec, row, 2 * (t + u * TR + r * T), v[u * 8 + r]);
-        }
+            for (int r = 0; r < NP; ++r) {
+                const int c0 = 2 * (t + u * TR + r * T);
+                const bool ok = row < rows_in && c0 < row_len;
+                const int w = ok ? row * mask.words_per_row + (c0 >> 5) : 0;
+                const uint32_t word = mask.bits[w];
+                bs[u * NP + r] = mask.base[w];
+                wd[u * NP + r] = ok ? word : 0u;
+            }
+#pragma unroll
+        for (int u = 0; u < VT; ++u)
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                v[u * 8 + r] = cpx<R>{(R)0, (R)0};
+                if (r >= NP) continue;
+                const int c0 = 2 * (t + u * TR + r * T);
+                const uint32_t word = wd[u * NP + r];
+                const uint32_t b0 = 1u << (c0 & 31);
+                const bool lo = (word & b0) != 0u, hi = (word & (b0 << 1)) != 0u;
+                const int64_t ci = (int64_t)bs[u * NP + r] + __popc(word & (b0 - 1u));
+                const R x = vin[lo ? ci : 0];
+                const R y = vin[hi ? ci + (lo ? 1 : 0) : 0];
+                v[u * 8 + r] = cpx<R>{lo ? x : (R)0, hi ? y : (R)0};
+            }
+    } else {
+#pragma unroll
+        for (int u = 0; u < VT; ++u)
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                v[u * 8 + r] = cpx<R>{(R)0, (R)0};
+                if (LOW && r >= 4) continue;
+                if (row < rows_in) load_pair<R, IN>(a, mask, row_len, vec, row, 2 * (t + u * TR + r * T), v[u * 8 + r]);
+            }
+    }
 #pragma unroll
     for (int u = 0; u < VT; ++u) {
         pass_compute<R, LOG2M, false, 0, LOW>(v + u * 8, t + u * TR, twp);
@@ -384,7 +419,7 @@ struct StageCArgs {
 // grid.  Row threads as in stage A: the barriers are after the tile load and
 // after the merge; the passes of a row stay within its wavefront.
 template <typename R, int LOG2M, int OUT, int VT>
-__global__ void __launch_bounds__((VT > 1 ? 512 : 1024)) k_row_inv(StageCArgs a, const cpx<R>* __restrict__ twp,
+__global__ void __launch_bounds__((VT > 1 ? 512 : 1024), (sizeof(R) == 4 && VT == 1 ? 8 : 4)) k_row_inv(StageCArgs a, const cpx<R>* __restrict__ twp,
                                                                    const cpx<R>* __restrict__ twb) {
     using S = Sched<LOG2M>;
     constexpr int M = S::L, T = M / 8, PM = padded(M) + 1;
@@ -491,27 +526,53 @@ __global__ void __launch_bounds__((VT > 1 ? 512 : 1024)) k_row_inv(StageCArgs a,
     for (int u = 0; u < VT; ++u) pass_compute<R, LOG2M, true, S::npass - 1>(v + u * 8, t + u * TR, twp);
     if (row >= rows_out) return;
     const int theta = (a.vec0 + vec) / a.vecs_per_theta;
+    // outputs in groups of two values: the group's nugget-term inputs are
+    // loaded together (none when eta = 0), then its stores go out
+    constexpr int GK = 2;
+    const R e = (OUT == OUT_COMPACT && a.vin) ? (R)a.eta[theta] : (R)0;
+    const R* vi = reinterpret_cast<const R*>(a.vin) + vec * a.vin_vstride;
+    R* oc = reinterpret_cast<R*>(a.out) + vec * a.out_vstride;
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        const int m = edge_pos<LOG2M, LRL>(t + (k / 8) * TR, k % 8);
-        const int c0 = 2 * m;
-        if (c0 >= cols_out) continue;
+    for (int k0 = 0; k0 < NV; k0 += GK) {
+        R vx[GK], vy[GK];
+#pragma unroll
+        for (int g = 0; g < GK; ++g) {
+            vx[g] = (R)0;
+            vy[g] = (R)0;
+        }
         if constexpr (OUT == OUT_COMPACT) {
-            const uint32_t b = (uint32_t)(obits >> (2 * k)) & 3u;
-            if (!b) continue;
-            int64_t ci = oci[k];
-            const R e = (R)a.eta[theta];
-            const R* vi = reinterpret_cast<const R*>(a.vin) + vec * a.vin_vstride;
-            R* o = reinterpret_cast<R*>(a.out) + vec * a.out_vstride;
-            if (b & 1u) {
-                o[ci] = v[k].x + e * vi[ci];
-                ++ci;
+            if (e != (R)0) {
+#pragma unroll
+                for (int g = 0; g < GK; ++g) {
+                    const uint32_t b = (uint32_t)(obits >> (2 * (k0 + g))) & 3u;
+                    const int64_t ci = oci[k0 + g];
+                    const R x = vi[(b & 1u) ? ci : 0];
+                    const R y = vi[(b & 2u) ? ci + (b & 1u) : 0];
+                    vx[g] = (b & 1u) ? x : (R)0;
+                    vy[g] = (b & 2u) ? y : (R)0;
+                }
             }
-            if (b & 2u) o[ci] = v[k].y + e * vi[ci];
-        } else {
-            R* o = reinterpret_cast<R*>(a.out) + vec * a.out_vstride + (int64_t)row * cols_out;
-            o[c0] = (R)a.scale * v[k].x;
-            if (c0 + 1 < cols_out) o[c0 + 1] = (R)a.scale * v[k].y;
+        }
+#pragma unroll
+        for (int g = 0; g < GK; ++g) {
+            const int k = k0 + g;
+            const int m = edge_pos<LOG2M, LRL>(t + (k / 8) * TR, k % 8);
+            const int c0 = 2 * m;
+            if (c0 >= cols_out) continue;
+            if constexpr (OUT == OUT_COMPACT) {
+                const uint32_t b = (uint32_t)(obits >> (2 * k)) & 3u;
+                if (!b) continue;
+                int64_t ci = oci[k];
+                if (b & 1u) {
+                    oc[ci] = v[k].x + e * vx[g];
+                    ++ci;
+                }
+                if (b & 2u) oc[ci] = v[k].y + e * vy[g];
+            } else {
+                R* o = reinterpret_cast<R*>(a.out) + vec * a.out_vstride + (int64_t)row * cols_out;
+                o[c0] = (R)a.scale * v[k].x;
+                if (c0 + 1 < cols_out) o[c0 + 1] = (R)a.scale * v[k].y;
+            }
         }
     }
 }
