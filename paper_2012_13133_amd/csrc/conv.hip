@@ -158,7 +158,7 @@ __device__ __forceinline__ void load_pair(const StageAArgs& a, const MaskView& m
 // when those lie in one wavefront the passes need no workgroup barrier, and
 // the only barrier is the one before the split, which mixes rows.
 template <typename R, int LOG2M, int IN, int VT>
-__global__ void __launch_bounds__((VT > 1 ? 512 : 1024)) k_row_fwd(StageAArgs a, const cpx<R>* __restrict__ twp,
+__global__ void __launch_bounds__((VT > 1 ? 512 : 1024), (sizeof(R) == 4 && VT == 1 && IN == IN_COMPACT ? 8 : 4)) k_row_fwd(StageAArgs a, const cpx<R>* __restrict__ twp,
                                                                    const cpx<R>* __restrict__ twb) {
     using S = Sched<LOG2M>;
     constexpr int M = S::L, T = M / 8, PM = padded(M) + 1;
@@ -186,6 +186,7 @@ __global__ void __launch_bounds__((VT > 1 ? 512 : 1024)) k_row_fwd(StageAArgs a,
         if (row0 >= rows_in) return;  // rows the column transform never reads
     }
     cpx<R>* buf = lds + rr * PM;
+    const int nt = blockDim.x;
     cpx<R> v[8 * VT];
     if constexpr (IN == IN_COMPACT) {
         // every mask word and offset first, then every value: two rounds of
@@ -242,12 +243,10 @@ __global__ void __launch_bounds__((VT > 1 ? 512 : 1024)) k_row_fwd(StageAArgs a,
     // split Z into the real transform X[k] = (s - i w d) / 2, k = 0..M:
     // 8 VT outputs per thread for k < M plus the Nyquist column k = M
     cpx<R>* Y = reinterpret_cast<cpx<R>*>(a.Y) + vec * a.Y_vstride;
-    const int nt = blockDim.x;
-    auto split = [&](int r2, int k) {
+    auto split = [&](int r2, int k, cpx<R> w) {
         const cpx<R>* bp = lds + r2 * PM;
         const cpx<R> zk = bp[pad8(k & (M - 1))];
         const cpx<R> zc = cconj(bp[pad8((M - k) & (M - 1))]);
-        const cpx<R> w = twiddle<R, false>(twb, k, LOG2M + 1);
         const cpx<R> s = cadd(zk, zc);
         const cpx<R> wd = cmul(w, csub(zk, zc));
         Y[(int64_t)k * a.ldY + row0 + r2] = cpx<R>{(R)0.5 * (s.x + wd.y), (R)0.5 * (s.y - wd.x)};
@@ -255,9 +254,9 @@ __global__ void __launch_bounds__((VT > 1 ? 512 : 1024)) k_row_fwd(StageAArgs a,
 #pragma unroll
     for (int i = 0; i < 8 * VT; ++i) {
         const int o = tid + i * nt;
-        split(o & (a.RT - 1), o >> a.log2RT);
+        split(o & (a.RT - 1), o >> a.log2RT, twiddle<R, false>(twb, o >> a.log2RT, LOG2M + 1));
     }
-    if (tid < a.RT) split(tid, M);
+    if (tid < a.RT) split(tid, M, twiddle<R, false>(twb, M, LOG2M + 1));
 }
 
 enum { B_LOW = 0, B_FULL = 1, B_SPEC = 2 };
@@ -286,7 +285,7 @@ struct StageBArgs {
 // vectors, sharing twiddle and spectrum loads.  B_SPEC: forward only, real
 // part to spec_out.
 template <typename R, int LOG2L, int MODE, int V>
-__global__ void __launch_bounds__(1024) k_col(StageBArgs a, const cpx<R>* __restrict__ twp) {
+__global__ void __launch_bounds__(((1 << LOG2L) / 8 > 256 ? (1 << LOG2L) / 8 : 256)) k_col(StageBArgs a, const cpx<R>* __restrict__ twp) {
     using S = Sched<LOG2L>;
     constexpr int L = S::L, T = L / 8, PL = padded(L);
     constexpr bool LOW = (MODE == B_LOW);

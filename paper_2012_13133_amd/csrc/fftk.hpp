@@ -79,29 +79,49 @@ __device__ __forceinline__ void dft8_low(cpx<R>* v) {
     v[7] = csub(e3, o3);
 }
 
-// Twiddle and butterfly of pass P on V independent sets of 8 register values
-// (v[u * 8 + k]); the twiddles are loaded once and applied to every set.
-template <typename R, int LOG2L, bool INV, int P, bool LOWHALF = false, int V = 1>
-__device__ __forceinline__ void pass_compute(cpx<R>* v, int t, const cpx<R>* __restrict__ tw) {
+// Twiddles of pass P for thread t (R - 1 per butterfly), loaded ahead of the
+// pass so their latency overlaps the LDS exchange and barrier before it.
+template <typename R, int LOG2L, bool INV, int P>
+struct PassTw {
+    static constexpr int RADIX = 1 << Sched<LOG2L>::lr(INV, P);
+    static constexpr int BPT = 8 / RADIX;
+    cpx<R> w[P > 0 ? BPT * RADIX : 1];
+};
+
+template <typename R, int LOG2L, bool INV, int P>
+__device__ __forceinline__ PassTw<R, LOG2L, INV, P> pass_twiddles(int t, const cpx<R>* __restrict__ tw) {
     using S = Sched<LOG2L>;
-    constexpr int LR = S::lr(INV, P);
-    constexpr int RADIX = 1 << LR;
+    using PT = PassTw<R, LOG2L, INV, P>;
+    constexpr int RADIX = PT::RADIX;
     constexpr int NS = 1 << S::lns(INV, P);
     constexpr int T = S::L / 8;
-    constexpr int BPT = 8 / RADIX;
+    PT out;
+    if constexpr (P > 0) {
 #pragma unroll
-    for (int b = 0; b < BPT; ++b) {
-        if constexpr (P > 0) {
-            const int j = t + b * T;
-            const int jn = j & (NS - 1);
+        for (int b = 0; b < PT::BPT; ++b) {
+            const int jn = (t + b * T) & (NS - 1);
             const cpx<R>* wp = tw + S::tw_off(INV, P) + jn * RADIX;
-            cpx<R> w[RADIX];
 #pragma unroll
-            for (int r = 1; r < RADIX; ++r) w[r] = wp[r];
+            for (int r = 1; r < RADIX; ++r) out.w[b * RADIX + r] = wp[r];
+        }
+    }
+    return out;
+}
+
+// Twiddle and butterfly of pass P on V independent sets of 8 register values
+// (v[u * 8 + k]) with twiddles already loaded, applied to every set.
+template <typename R, int LOG2L, bool INV, int P, bool LOWHALF = false, int V = 1>
+__device__ __forceinline__ void pass_compute_tw(cpx<R>* v, const PassTw<R, LOG2L, INV, P>& tw) {
+    using PT = PassTw<R, LOG2L, INV, P>;
+    constexpr int RADIX = PT::RADIX;
+#pragma unroll
+    for (int b = 0; b < PT::BPT; ++b) {
+        if constexpr (P > 0) {
 #pragma unroll
             for (int u = 0; u < V; ++u)
 #pragma unroll
-                for (int r = 1; r < RADIX; ++r) v[u * 8 + b * RADIX + r] = cmul(v[u * 8 + b * RADIX + r], w[r]);
+                for (int r = 1; r < RADIX; ++r)
+                    v[u * 8 + b * RADIX + r] = cmul(v[u * 8 + b * RADIX + r], tw.w[b * RADIX + r]);
         }
 #pragma unroll
         for (int u = 0; u < V; ++u) {
@@ -109,6 +129,11 @@ __device__ __forceinline__ void pass_compute(cpx<R>* v, int t, const cpx<R>* __r
             else dft<R, RADIX, INV>(v + u * 8 + b * RADIX);
         }
     }
+}
+
+template <typename R, int LOG2L, bool INV, int P, bool LOWHALF = false, int V = 1>
+__device__ __forceinline__ void pass_compute(cpx<R>* v, int t, const cpx<R>* __restrict__ tw) {
+    pass_compute_tw<R, LOG2L, INV, P, LOWHALF, V>(v, pass_twiddles<R, LOG2L, INV, P>(t, tw));
 }
 
 // Padded LDS offset of element base + d when base + d stays in the same
@@ -180,10 +205,11 @@ struct LdsPasses {
     __device__ __forceinline__ static void run(cpx<R>* v, cpx<R>* buf, int stride, int t,
                                                const cpx<R>* __restrict__ tw) {
         if constexpr (P < PE) {
+            const auto w = pass_twiddles<R, LOG2L, INV, P>(t, tw);
 #pragma unroll
             for (int u = 0; u < V; ++u) pass_read<R, LOG2L, INV, P>(v + u * 8, buf + u * stride, t);
             __syncthreads();
-            pass_compute<R, LOG2L, INV, P, false, V>(v, t, tw);
+            pass_compute_tw<R, LOG2L, INV, P, false, V>(v, w);
 #pragma unroll
             for (int u = 0; u < V; ++u) pass_write<R, LOG2L, INV, P>(v + u * 8, buf + u * stride, t);
             __syncthreads();
@@ -217,11 +243,14 @@ struct LdsPassesVT {
     __device__ __forceinline__ static void run(cpx<R>* v, cpx<R>* buf, int t, const cpx<R>* __restrict__ tw) {
         if constexpr (P < PE) {
             constexpr int TR = (1 << LOG2L) / 8 / VT;
+            PassTw<R, LOG2L, INV, P> w[VT];
+#pragma unroll
+            for (int u = 0; u < VT; ++u) w[u] = pass_twiddles<R, LOG2L, INV, P>(t + u * TR, tw);
 #pragma unroll
             for (int u = 0; u < VT; ++u) pass_read<R, LOG2L, INV, P>(v + u * 8, buf, t + u * TR);
             lds_sync<WAVE>();
 #pragma unroll
-            for (int u = 0; u < VT; ++u) pass_compute<R, LOG2L, INV, P>(v + u * 8, t + u * TR, tw);
+            for (int u = 0; u < VT; ++u) pass_compute_tw<R, LOG2L, INV, P>(v + u * 8, w[u]);
 #pragma unroll
             for (int u = 0; u < VT; ++u) pass_write<R, LOG2L, INV, P>(v + u * 8, buf, t + u * TR);
             lds_sync<WAVE>();
