@@ -154,6 +154,13 @@ kry_status kry_set_tuning(kry_ctx* ctx, int32_t N1, int32_t N2, int32_t precisio
  * kry_autotune). */
 kry_status kry_get_tuning(kry_ctx* ctx, int32_t N1, int32_t N2, int32_t precision, kry_tuning* out);
 
+/* CG solves run their iterations in blocks of 16 between convergence reads;
+ * with graphs enabled (the default) every block after the first replays one
+ * captured HIP graph of the block's kernel launches instead of launching them
+ * one by one (the first block runs directly and sizes the workspaces).
+ * Results are bit-identical either way.  Not while stage profiling is on. */
+kry_status kry_set_graphs(kry_ctx* ctx, int32_t enable);
+
 /* ---- context and problems ----------------------------------------------- */
 /* Binds HIP device `device`; hbm_budget_bytes = 0 means no limit beyond the
  * device.  Creates the library's stream (default priority). */
@@ -333,6 +340,9 @@ typedef struct {
     int32_t status;          /* kry_status of the request (KRY_ENOCONV: outputs   */
                              /* written, CG stopped at cg_maxit)                   */
     int32_t batch;           /* requests evaluated together with this one         */
+    int32_t problems;        /* distinct problems in that batch (1: results are
+                                bit-identical to the request alone; more: equal to
+                                rounding, the Krylov vectors being padded)        */
     kry_loglik_result loglik;
     double t_submit, t_start, t_end;  /* seconds since the server was created  */
 } kry_response;

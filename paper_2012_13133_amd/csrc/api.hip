@@ -323,7 +323,8 @@ void solve_device(Problem& P, int precision, const void* lam64, const void* lam3
         a.base = P.scal.as<char>();
         lay(a);
         auto A = masked_op<double>(P, lam64, lam_tstride, vpt, d_eta);
-        cg_run<double>(A, p, nrhs, B, X, rtol, maxit, cb, out.iters, out.relres, st);
+        cg_run<double>(A, p, nrhs, B, X, rtol, maxit, cb, out.iters, out.relres, st, nullptr,
+                       P.ctx->graphs && !P.ctx->prof.on);
         return;
     }
     // mixed form
@@ -390,7 +391,7 @@ void solve_device(Problem& P, int precision, const void* lam64, const void* lam3
         if (!any) break;
         std::vector<int> it;
         std::vector<double> rr;
-        cg_run<float>(A32, p, nrhs, b32, x32, inner, maxit, cb, it, rr, st, &lim);
+        cg_run<float>(A32, p, nrhs, b32, x32, inner, maxit, cb, it, rr, st, &lim, P.ctx->graphs && !P.ctx->prof.on);
         for (int v = 0; v < nrhs; ++v) out.iters[v] += it[v];
         add_f32(x32, X, vn, st);
         A64(X, t64, nrhs, st, nullptr);
@@ -780,14 +781,28 @@ void loglik_points_shared(Problem& P, const kry_matern* thetas, int count, const
 // kernels read a per-vector problem table (mask, block, spectrum), and the
 // Krylov vectors are stored with the largest observed count as stride, zero
 // past each problem's own count.  Probes and data are each problem's own.
+// Q carries the workspace (a view of any problem on the same context); its
+// block sizes and table are set for the call and restored after it.
 template <typename R>
-void loglik_multi_group(const std::vector<Problem*>& probs, const kry_matern* th, const kry_opts* o,
+void loglik_multi_group(Problem& Q, const std::vector<Problem*>& probs, const kry_matern* th, const kry_opts* o,
                         kry_loglik_result* out, hipStream_t st) {
-    Problem& P0 = *probs[0];
-    Ctx& C = *P0.ctx;
+    Ctx& C = *Q.ctx;
     const int G = (int)probs.size();
     const int np = nprobes_of(o);
-    Problem Q = P0.view();  // P0's immutable data; its own workspace
+    struct Restore {
+        Problem& q;
+        int n1, n2;
+        int64_t p;
+        double dx1, dx2;
+        ~Restore() {
+            q.tab = nullptr;
+            q.n1 = n1;
+            q.n2 = n2;
+            q.p = p;
+            q.dx1 = dx1;
+            q.dx2 = dx2;
+        }
+    } restore{Q, Q.n1, Q.n2, Q.p, Q.dx1, Q.dx2};
     int n1m = 0, n2m = 0;
     int64_t pm = 0;
     for (Problem* q : probs) {
@@ -808,7 +823,11 @@ void loglik_multi_group(const std::vector<Problem*>& probs, const kry_matern* th
         double lo, hi;
         double* d64 = Q.spec_multi64.as<double>() + (size_t)g * nspec;
         float* d32 = sizeof(R) == 4 ? Q.spec_multi32.as<float>() + (size_t)g * nspec : nullptr;
-        spectrum_device(Pg, Q.N1, Q.N2, to_matern(&th[g]), d64, &lo, &hi, st);
+        // the spectrum uses Q's workspace with Pg's spacing (the problems'
+        // own workspaces may be in use elsewhere)
+        Q.dx1 = Pg.dx1;
+        Q.dx2 = Pg.dx2;
+        spectrum_device(Q, Q.N1, Q.N2, to_matern(&th[g]), d64, &lo, &hi, st);
         spectrum_scale(d64, nspec, 1.0 / ((double)Q.N1 * Q.N2), false, d64, d32, st);
         tab[g] = ProbDesc{Pg.bits.as<uint32_t>(), Pg.base.as<uint32_t>(), Pg.words_per_row, Pg.n1, Pg.n2, Pg.p,
                           d64, d32};
@@ -858,8 +877,6 @@ void loglik_multi_group(const std::vector<Problem*>& probs, const kry_matern* th
         r.cg_iters = ss.iters[g];
         r.cg_relres = ss.relres[g];
     }
-    Q.tab = nullptr;
-    Q.release_work();
 }
 
 bool any_not_converged(const kry_loglik_result* r, int count, const kry_opts* o) {
@@ -872,6 +889,12 @@ bool any_not_converged(const kry_loglik_result* r, int count, const kry_opts* o)
 }  // namespace
 
 namespace kry {
+void loglik_multi(Problem& work, const std::vector<Problem*>& probs, const kry_matern* th, const kry_opts* o,
+                  kry_loglik_result* out, hipStream_t st) {
+    if (o->precision == KRY_FP32) loglik_multi_group<float>(work, probs, th, o, out, st);
+    else loglik_multi_group<double>(work, probs, th, o, out, st);
+}
+
 // log-likelihood for `count` parameter points that share nu and anisotropy
 // handling (each with its own spectrum) on one problem.
 void loglik_points(Problem& P, const kry_matern* thetas, int count, const kry_opts* o, kry_loglik_result* out,
@@ -1719,6 +1742,14 @@ kry_status kry_autotune(kry_problem* prob, int32_t precision, int32_t nvec, kry_
     });
 }
 
+kry_status kry_set_graphs(kry_ctx* ctx, int32_t enable) {
+    return guard([&] {
+        KRY_REQUIRE(ctx != nullptr, "NULL context");
+        KRY_REQUIRE(enable == 0 || enable == 1, "enable must be 0 or 1");
+        ctx->c.graphs = enable != 0;
+    });
+}
+
 kry_status kry_set_tuning(kry_ctx* ctx, int32_t N1, int32_t N2, int32_t precision, const kry_tuning* t) {
     return guard([&] {
         KRY_REQUIRE(ctx != nullptr, "NULL context");
@@ -1799,8 +1830,14 @@ kry_status kry_loglik_multi(kry_problem* const* probs, const kry_matern* thetas,
                     th.push_back(thetas[grp[j]]);
                 }
                 std::vector<kry_loglik_result> r(ps.size());
-                if (opts->precision == KRY_FP32) loglik_multi_group<float>(ps, th.data(), opts, r.data(), st);
-                else loglik_multi_group<double>(ps, th.data(), opts, r.data(), st);
+                Problem work = ps[0]->view();  // a fresh workspace for the group
+                try {
+                    loglik_multi(work, ps, th.data(), opts, r.data(), st);
+                } catch (...) {
+                    work.release_work();
+                    throw;
+                }
+                work.release_work();
                 for (size_t j = a; j < b; ++j) res[grp[j]] = r[j - a];
             }
         }

@@ -861,7 +861,8 @@ void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st) {
     // launch configuration of this embedding and precision (bit-identical results)
     const Tuning tu = P.ctx->tuning_for(s.N1, s.N2, (int)sizeof(R));
     const int vt = (M >= 1024 && tu.row_vt == 2) ? 2 : 1;
-    const int V = tu.col_v ? tu.col_v : (sizeof(R) == 4 ? 2 : 1);
+    // (two vectors per column workgroup only when there are two to pair)
+    const int V = s.nvec < 2 ? 1 : (tu.col_v ? tu.col_v : (sizeof(R) == 4 ? 2 : 1));
     const RowTiling ta = row_tiling<R>(M, tu.rt_scale, vt);
     const int rows_max = s.rows_in > s.rows_out ? s.rows_in : s.rows_out;
     const int ldY = ((rows_max + ta.RT - 1) / ta.RT) * ta.RT;

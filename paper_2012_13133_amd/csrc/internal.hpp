@@ -64,6 +64,7 @@ struct Ctx {
     void* plan64[14] = {};  // per-length pass twiddle tables (index log2 length)
     void* plan32[14] = {};
     std::mutex alloc_mu;     // guards `allocated` (server slots allocate concurrently)
+    bool graphs = true;  // replay captured graphs for CG iteration blocks
     std::map<std::tuple<int, int, int>, Tuning> tuning;  // (N1, N2, bytes per real) -> configuration
     std::mutex tune_mu;
     Tuning tuning_for(int N1, int N2, int real_bytes) {
@@ -239,6 +240,10 @@ Spectrum& problem_spectrum(Problem& P, const Matern& th, hipStream_t st);
 // ---- drivers (api.hip), used by the ABI and by the server ----------------------
 void loglik_points(Problem& P, const kry_matern* thetas, int count, const kry_opts* o, kry_loglik_result* out,
                    hipStream_t st);
+// One parameter point per problem for problems sharing an embedding (CG,
+// no shift sharing); `work` is a view whose workspace the call uses.
+void loglik_multi(Problem& work, const std::vector<Problem*>& probs, const kry_matern* th, const kry_opts* o,
+                  kry_loglik_result* out, hipStream_t st);
 // Kriging; sets *noconv when a CG solve stopped at cg_maxit.
 void krige_impl(Problem& P, const kry_matern* theta, const kry_opts* opts, const std::vector<int64_t>& targets,
                 double* mean_x, double* var_x, double* var_y, int bootstrap_B, bool* noconv, hipStream_t st);

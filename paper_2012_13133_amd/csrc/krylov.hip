@@ -453,9 +453,38 @@ __global__ void k_cg_p(R* __restrict__ p, const R* __restrict__ r, const double*
         p[vec * n + i] = r[vec * n + i] + b * p[vec * n + i];
 }
 
+// A block of stream work captured once into a HIP graph and replayed; the
+// graph holds kernel launches only (no memset or copy nodes).
+struct GraphBlock {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    template <typename F>
+    void run(hipStream_t st, F&& body) {
+        if (!exec) {
+            KRY_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            try {
+                body();
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(st, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            KRY_HIP(hipStreamEndCapture(st, &graph));
+            KRY_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        }
+        KRY_HIP(hipGraphLaunch(exec, st));
+    }
+    ~GraphBlock() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
 template <typename R>
 void cg_run(const MatvecFn<R>& A, int64_t n, int nvec, const R* b, R* x, double rtol, int maxit, CgBuffers<R>& B,
-            std::vector<int>& iters, std::vector<double>& relres, hipStream_t st, const std::vector<int>* limits) {
+            std::vector<int>& iters, std::vector<double>& relres, hipStream_t st, const std::vector<int>* limits,
+            bool graphs) {
     const int nblk = dot_blocks(n);
     std::vector<int> lim(nvec, maxit);
     if (limits) {
@@ -474,7 +503,7 @@ void cg_run(const MatvecFn<R>& A, int64_t n, int nvec, const R* b, R* x, double 
     KRY_HIP(hipGetLastError());
     std::vector<int> act(nvec);
     const int check = 16;
-    for (int it = 0; it < loop_max; ++it) {
+    auto step = [&]() {
         A(B.p, B.w, nvec, st, B.active);
         dot_batched<R>(B.p, n, B.w, n, n, nvec, B.partial, B.pw, st);
         hipLaunchKernelGGL(k_cg_xr<R>, dim3(nblk, nvec), dim3(RB), 0, st, x, B.r, B.p, B.w, B.rr, B.pw, B.active, n,
@@ -485,13 +514,25 @@ void cg_run(const MatvecFn<R>& A, int64_t n, int nvec, const R* b, R* x, double 
         KRY_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_cg_p<R>, vec_grid(n, nvec), dim3(256), 0, st, B.p, B.r, B.beta, B.active, n);
         KRY_HIP(hipGetLastError());
-        if ((it + 1) % check == 0 || it + 1 == loop_max) {
-            KRY_HIP(hipMemcpyAsync(act.data(), B.active, nvec * sizeof(int), hipMemcpyDeviceToHost, st));
-            KRY_HIP(hipStreamSynchronize(st));
-            bool any = false;
-            for (int v = 0; v < nvec; ++v) any = any || act[v];
-            if (!any) break;
-        }
+    };
+    // Iterations go in blocks of `check` between convergence reads.  The
+    // first block runs eagerly (it also sizes every workspace the product
+    // allocates); with graphs on, later full blocks replay one captured
+    // graph of `check` iterations (same kernels, same arguments).
+    GraphBlock gb;
+    for (int it = 0; it < loop_max;) {
+        const int blk = std::min(check, loop_max - it);
+        if (graphs && it > 0 && blk == check) gb.run(st, [&] {
+            for (int k = 0; k < check; ++k) step();
+        });
+        else
+            for (int k = 0; k < blk; ++k) step();
+        it += blk;
+        KRY_HIP(hipMemcpyAsync(act.data(), B.active, nvec * sizeof(int), hipMemcpyDeviceToHost, st));
+        KRY_HIP(hipStreamSynchronize(st));
+        bool any = false;
+        for (int v = 0; v < nvec; ++v) any = any || act[v];
+        if (!any) break;
     }
     std::vector<double> rr(nvec), bn(nvec);
     iters.resize(nvec);
@@ -504,9 +545,9 @@ void cg_run(const MatvecFn<R>& A, int64_t n, int nvec, const R* b, R* x, double 
 }
 template void cg_run<double>(const MatvecFn<double>&, int64_t, int, const double*, double*, double, int,
                              CgBuffers<double>&, std::vector<int>&, std::vector<double>&, hipStream_t,
-                             const std::vector<int>*);
+                             const std::vector<int>*, bool);
 template void cg_run<float>(const MatvecFn<float>&, int64_t, int, const float*, float*, double, int, CgBuffers<float>&,
-                            std::vector<int>&, std::vector<double>&, hipStream_t, const std::vector<int>*);
+                            std::vector<int>&, std::vector<double>&, hipStream_t, const std::vector<int>*, bool);
 
 // ---- multi-shift conjugate gradients ---------------------------------------------------
 // One CG recurrence per group on its base operator A; the shifted system

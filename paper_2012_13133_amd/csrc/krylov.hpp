@@ -70,11 +70,14 @@ void quadrature(const double* alpha, const double* beta, const int* steps, const
                 int64_t coef_stride, double* gamma, hipStream_t st, const int* src = nullptr,
                 const double* shift = nullptr);
 // CG on nvec systems; vector v stops at ||r|| <= rtol ||b|| or after
-// limits[v] iterations (limits == nullptr: maxit for all).
+// limits[v] iterations (limits == nullptr: maxit for all).  graphs: replay
+// a captured graph for each block of 16 iterations after the first (the
+// operator must then launch the same kernels with the same arguments on
+// every call and allocate nothing after its first call).
 template <typename R>
 void cg_run(const MatvecFn<R>& A, int64_t n, int nvec, const R* b, R* x, double rtol, int maxit, CgBuffers<R>& B,
             std::vector<int>& iters, std::vector<double>& relres, hipStream_t st,
-            const std::vector<int>* limits = nullptr);
+            const std::vector<int>* limits = nullptr, bool graphs = false);
 // Probe k of the problem at out + k * stride (stride 0: the problem's p).
 template <typename R>
 void make_probes(const Problem& P, int nprobe, uint64_t seed, int period, R* out, hipStream_t st,

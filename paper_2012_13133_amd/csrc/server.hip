@@ -6,11 +6,14 @@
 // device footprint of everything in flight stays within the HBM budget, so
 // requests that arrive while others run start as soon as a slot and memory
 // free up, and their kernels overlap on the device.  A worker that takes a
-// likelihood request also takes every queued likelihood request on the same
-// problem with identical options (up to max_batch) and runs them as one
-// batched evaluation (every (point, probe) vector in the same products).
-// Reductions are fixed-order per vector, so a request's result is the same
-// whether it runs alone or batched with others.
+// likelihood request also takes every queued likelihood request with
+// identical options on the same problem, or on another problem with the same
+// embedding, (up to max_batch) and runs them as one batched evaluation
+// (every (point, probe) vector in the same products; several problems through
+// a per-vector problem table).  Reductions are fixed-order per vector, so a
+// request batched with others on its own problem gets bit-identical results;
+// batched with other problems, its Krylov vectors are padded to the largest
+// observed count, which changes the reduction blocks and so the rounding.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -105,7 +108,17 @@ struct kry_server {
         return a.lanczos_steps == b.lanczos_steps && a.num_probes == b.num_probes && a.probe_kind == b.probe_kind &&
                a.colour_period == b.colour_period && a.seed == b.seed && a.reorth == b.reorth &&
                a.precision == b.precision && a.cg_rtol == b.cg_rtol && a.cg_maxit == b.cg_maxit &&
-               a.solver == b.solver && a.gk_steps == b.gk_steps;
+               a.solver == b.solver && a.gk_steps == b.gk_steps && a.shift_share == b.shift_share;
+    }
+
+    // Likelihood requests that can run in one batch with the head h: the same
+    // problem, or (CG, no shift sharing) a problem with the same embedding,
+    // whose products then share launches through a problem table.
+    static bool mergeable(const kry_request& h, const kry_request& r) {
+        if (r.kind != KRY_REQ_LOGLIK || !same_opts(r.opts, h.opts)) return false;
+        if (r.prob == h.prob) return true;
+        return h.opts.solver == KRY_SOLVER_CG && h.opts.shift_share == 0 && r.prob->P.N1 == h.prob->P.N1 &&
+               r.prob->P.N2 == h.prob->P.N2;
     }
 
     void run_slot(int slot) {
@@ -131,8 +144,7 @@ struct kry_server {
                 if (h.kind == KRY_REQ_LOGLIK) {
                     for (auto it = queue.begin(); it != queue.end() && (int)batch.size() < max_batch;) {
                         const kry_request& r = it->req;
-                        if (r.kind == KRY_REQ_LOGLIK && r.prob == h.prob && same_opts(r.opts, h.opts) &&
-                            inflight + fp + it->footprint <= budget) {
+                        if (mergeable(h, r) && inflight + fp + it->footprint <= budget) {
                             fp += it->footprint;
                             batch.push_back(std::move(*it));
                             it = queue.erase(it);
@@ -176,8 +188,22 @@ struct kry_server {
             if (h.kind == KRY_REQ_LOGLIK) {
                 std::vector<kry_matern> th(batch.size());
                 std::vector<kry_loglik_result> res(batch.size());
-                for (size_t i = 0; i < batch.size(); ++i) th[i] = batch[i].req.theta;
-                loglik_points(v, th.data(), (int)th.size(), &h.opts, res.data(), st);
+                std::vector<Problem*> ps(batch.size());
+                bool one_problem = true;
+                for (size_t i = 0; i < batch.size(); ++i) {
+                    th[i] = batch[i].req.theta;
+                    ps[i] = &batch[i].req.prob->P;
+                    one_problem = one_problem && batch[i].req.prob == h.prob;
+                }
+                if (one_problem) loglik_points(v, th.data(), (int)th.size(), &h.opts, res.data(), st);
+                else loglik_multi(v, ps, th.data(), &h.opts, res.data(), st);
+                int nprob = 0;
+                for (size_t i = 0; i < batch.size(); ++i) {
+                    bool seen = false;
+                    for (size_t j = 0; j < i; ++j) seen = seen || batch[j].req.prob == batch[i].req.prob;
+                    nprob += seen ? 0 : 1;
+                }
+                for (auto& r : resp) r.problems = nprob;
                 for (size_t i = 0; i < batch.size(); ++i) {
                     resp[i].loglik = res[i];
                     resp[i].status = (h.opts.solver == KRY_SOLVER_CG && res[i].cg_relres > h.opts.cg_rtol)
@@ -189,6 +215,7 @@ struct kry_server {
                 krige_impl(v, &h.theta, &h.opts, batch[0].targets, h.mean_x, h.variances ? h.var_x : nullptr,
                            h.variances ? h.var_y : nullptr, 0, &noconv, st);
                 resp[0].status = noconv ? KRY_ENOCONV : KRY_OK;
+                resp[0].problems = 1;
             }
         } catch (const Error& e) {
             status = e.status;

@@ -70,7 +70,7 @@ class kry_request(C.Structure):
 
 
 class kry_response(C.Structure):
-    _fields_ = [("status", C.c_int32), ("batch", C.c_int32), ("loglik", kry_loglik_result),
+    _fields_ = [("status", C.c_int32), ("batch", C.c_int32), ("problems", C.c_int32), ("loglik", kry_loglik_result),
                 ("t_submit", C.c_double), ("t_start", C.c_double), ("t_end", C.c_double)]
 
 
@@ -105,6 +105,7 @@ _SIGS = {
     "kry_loglik": (C.c_int, [_P, C.POINTER(kry_matern), C.POINTER(kry_opts), C.POINTER(kry_loglik_result)]),
     "kry_loglik_batch": (C.c_int, [_P, C.POINTER(kry_matern), C.c_int32, C.POINTER(kry_opts),
                                    C.POINTER(kry_loglik_result)]),
+    "kry_set_graphs": (C.c_int, [_P, C.c_int32]),
     "kry_autotune": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(kry_tuning)]),
     "kry_set_tuning": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(kry_tuning)]),
     "kry_get_tuning": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(kry_tuning)]),
@@ -352,6 +353,10 @@ def kry_loglik_multi(probs, thetas, opts, allow_noconv=False):
     if not (allow_noconv and s == KRY_ENOCONV):
         _check(s)
     return [r.as_dict() for r in res]
+
+
+def kry_set_graphs(ctx, enable):
+    _check(lib.kry_set_graphs(ctx, 1 if enable else 0))
 
 
 def kry_autotune(prob, precision, nvec=32):

@@ -81,8 +81,12 @@ def test_server_same_alone_and_in_mix():
             batches = max(batches, r.batch)
             if kind == "loglik":
                 got = r.loglik.as_dict()
-                for key in ("loglik", "loglik_profiled", "logdet", "logdet_se", "quad", "cg_iters"):
-                    assert got[key] == a[key], (key, got[key], a[key])
+                if r.problems == 1:
+                    # batched on its own problem: bit-identical
+                    for key in ("loglik", "loglik_profiled", "logdet", "logdet_se", "quad", "cg_iters"):
+                        assert got[key] == a[key], (key, got[key], a[key])
+                else:
+                    _close_to_alone(got, a, opts)
             else:
                 np.testing.assert_array_equal(p.outputs["mean_x"], a[0])
                 np.testing.assert_array_equal(p.outputs["var_x"], a[1])
@@ -91,6 +95,46 @@ def test_server_same_alone_and_in_mix():
         # requests ran concurrently on different slots
         spans = sorted((r.t_start, r.t_end) for r in resp)
         assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
+    finally:
+        for h in probs:
+            K.kry_problem_destroy(h)
+        K.kry_ctx_destroy(ctx)
+
+
+def _close_to_alone(got, a, opts):
+    # batched with other problems of the same embedding: the Krylov vectors
+    # are padded to the largest observed count, which regroups the dot
+    # products' partial sums; equal to rounding (FP32 Lanczos amplifies it)
+    tol = 1e-9 if opts.precision == K.KRY_FP64 else 1e-4
+    for key in ("loglik", "loglik_profiled", "logdet"):
+        assert abs(got[key] - a[key]) <= tol * abs(a[key]), (key, got[key], a[key])
+    assert abs(got["quad"] - a["quad"]) <= 1e-7 * a["quad"]
+    assert got["cg_relres"] <= opts.cg_rtol
+
+
+def test_server_merges_problems_sharing_an_embedding():
+    # problems 0 and 1 share a 128 x 128 embedding; with one slot busy on a
+    # kriging request, likelihood requests on both queue up and run together
+    ctx = K.kry_ctx_create()
+    probs, masks = _problems(ctx)
+    try:
+        opts = K.kry_opts_default(lanczos_steps=20, num_probes=6, precision=K.KRY_FP64, cg_rtol=1e-8)
+        ths = [K.theta(sigma2=1.0, tau2=0.1 + 0.05 * i, range=0.05 + 0.02 * i, nu=1.5) for i in range(6)]
+        alone = [K.kry_loglik(probs[i % 2], th, opts) for i, th in enumerate(ths)]
+        miss = np.flatnonzero(masks[1].ravel() == 0)
+        srv = K.kry_server_create(ctx, slots=1, max_batch=8)
+        try:
+            first = K.kry_server_submit(srv, K.KRY_REQ_KRIGE, probs[1], ths[0], K.kry_opts_default(cg_rtol=1e-10),
+                                        miss[:64], variances=True)
+            pend = [K.kry_server_submit(srv, K.KRY_REQ_LOGLIK, probs[i % 2], th, opts) for i, th in enumerate(ths)]
+            K.kry_server_wait(srv, first)
+            resp = [K.kry_server_wait(srv, p) for p in pend]
+        finally:
+            K.kry_server_destroy(srv)
+        assert max(r.problems for r in resp) == 2
+        for r, a in zip(resp, alone):
+            assert r.status == K.KRY_OK
+            _close_to_alone(r.loglik.as_dict(), a, opts)
     finally:
         for h in probs:
             K.kry_problem_destroy(h)
