@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--multi", type=int, default=64, help="independent problems in the multi-problem form (0: skip)")
     ap.add_argument("--multi-sides", type=str, default="64,1024")
     ap.add_argument("--multi-only", action="store_true", help="only the multi-problem form")
+    ap.add_argument("--serve-only", action="store_true", help="only the served form")
     return ap.parse_args()
 
 
@@ -99,6 +100,9 @@ def main():
 
     if args.multi_only:
         print(json.dumps({"multi": multi_bench(args, K, synth, np)}))
+        return
+    if args.serve_only:
+        print(json.dumps({"serve": serve_bench(args, K, synth, np)}))
         return
     n = args.n
     nu, rho, eta = 1.5, 0.05, 0.2

@@ -158,7 +158,8 @@ kry_status kry_get_tuning(kry_ctx* ctx, int32_t N1, int32_t N2, int32_t precisio
  * with graphs enabled (the default) every block after the first replays one
  * captured HIP graph of the block's kernel launches instead of launching them
  * one by one (the first block runs directly and sizes the workspaces).
- * Results are bit-identical either way.  Not while stage profiling is on. */
+ * Results are bit-identical either way.  Not while stage profiling is on,
+ * and not inside the request server, whose slots run in several threads. */
 kry_status kry_set_graphs(kry_ctx* ctx, int32_t enable);
 
 /* ---- context and problems ----------------------------------------------- */

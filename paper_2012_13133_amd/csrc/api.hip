@@ -324,7 +324,7 @@ void solve_device(Problem& P, int precision, const void* lam64, const void* lam3
         lay(a);
         auto A = masked_op<double>(P, lam64, lam_tstride, vpt, d_eta);
         cg_run<double>(A, p, nrhs, B, X, rtol, maxit, cb, out.iters, out.relres, st, nullptr,
-                       P.ctx->graphs && !P.ctx->prof.on);
+                       P.ctx->graphs && !P.ctx->prof.on && !P.no_graphs);
         return;
     }
     // mixed form
@@ -391,7 +391,8 @@ void solve_device(Problem& P, int precision, const void* lam64, const void* lam3
         if (!any) break;
         std::vector<int> it;
         std::vector<double> rr;
-        cg_run<float>(A32, p, nrhs, b32, x32, inner, maxit, cb, it, rr, st, &lim, P.ctx->graphs && !P.ctx->prof.on);
+        cg_run<float>(A32, p, nrhs, b32, x32, inner, maxit, cb, it, rr, st, &lim,
+                      P.ctx->graphs && !P.ctx->prof.on && !P.no_graphs);
         for (int v = 0; v < nrhs; ++v) out.iters[v] += it[v];
         add_f32(x32, X, vn, st);
         A64(X, t64, nrhs, st, nullptr);

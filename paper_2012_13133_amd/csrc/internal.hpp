@@ -142,6 +142,7 @@ struct Problem {
     std::shared_ptr<const std::vector<int64_t>> h_cell;  // compact index -> cell id (host)
     std::shared_ptr<const std::vector<uint8_t>> h_mask;
     bool is_view = false;
+    bool no_graphs = false;  // set on the server's request views (several threads)
     const ProbDesc* tab = nullptr;  // set on a group of problems sharing an embedding
     // workspace (per problem or per view)
     Spectrum spec;               // cache of the last parameter point

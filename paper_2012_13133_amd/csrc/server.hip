@@ -178,6 +178,9 @@ struct kry_server {
     void execute(std::vector<Pending>& batch, std::vector<kry_response>& resp, SlotWork& w, hipStream_t st) {
         const Problem& base = batch[0].req.prob->P;
         Problem v = base.view();
+        // slots run concurrently in several threads: no stream capture there
+        // (a capture crashed inside the runtime under a kernel tracer)
+        v.no_graphs = true;
         w.spec.valid = false;  // the cached spectrum may belong to another problem
         w.last = &base;
         swap_work(v, w);
