@@ -74,3 +74,48 @@ def test_loglik_fp32_form_matches_fp64_with_common_probes():
                                                       cg_rtol=1e-6))
     assert abs(r32["loglik"] - r64["loglik"]) <= 1e-3 * abs(r64["loglik"])
     assert abs(r32["quad"] - r64["quad"]) <= 1e-6 * r64["quad"]
+
+
+def test_masked_product_largest_embedding():
+    # the largest grid the library takes: 4096 x 4096 (8192 x 8192 torus)
+    n = 4096
+    th = theta(0.02, 1.5, sigma2=1.0, tau2=0.2)
+    mask = synth.uniform_mask(n, n, 0.3, seed=103)
+    g = (n, n, 1.0 / n, 1.0 / n)
+    p = int(mask.sum())
+    rng = np.random.default_rng(11)
+    v = rng.standard_normal((2, p))
+    rows = np.sort(rng.choice(p, size=6, replace=False))
+    T = lag_table(n, n, 1.0 / n, 1.0 / n, th)
+    ref = direct.masked_matvec(g, mask, th, v.T, rows=rows, table=T)
+    with K.Problem(n, n, mask) as P:
+        assert (P.N1, P.N2) == (8192, 8192)
+        got64 = K.kry_matvec(P.h, K.theta_from_dict(th), v, K.KRY_FP64)
+        got32 = K.kry_matvec(P.h, K.theta_from_dict(th), v, K.KRY_FP32)
+    for got, tol in ((got64, 1e-12), (got32, 1e-5)):
+        for j in range(2):
+            scale = np.sqrt(np.mean(got[j] ** 2))
+            assert np.abs(got[j][rows] - ref[:, j]).max() <= tol * scale, tol
+
+
+def test_range_nugget_grid_fp32_shared_matches_plain_fp64():
+    # 512^2 with 30 % missing (the plain-vs-precision workload): the FP32
+    # shift-shared batch over a 3 x 3 (range, nugget) grid against the plain
+    # FP64 form point by point, same probes
+    n = 512
+    mask = synth.uniform_mask(n, n, 0.3, seed=104)
+    ranges, nuggets = (0.01, 0.05, 0.2), (0.01, 0.1, 1.0)
+    thetas = [K.theta(sigma2=1.0, tau2=e, range=r, nu=1.5) for r in ranges for e in nuggets]
+    base = dict(lanczos_steps=50, num_probes=10, reorth=1, cg_rtol=1e-8, cg_maxit=100000)
+    with K.Problem(n, n, mask) as P:
+        th0 = K.theta(sigma2=1.0, tau2=0.2, range=0.05, nu=1.5)
+        N = K.kry_psd_torus(P.h, th0)
+        x, _ = K.kry_sample(P.h, th0, N[0], N[1], 202, 0, 1, n, n)
+        y = x[0] + np.sqrt(0.2) * np.random.default_rng(5).standard_normal((n, n))
+        K.kry_problem_set_data(P.h, y)
+        batch = K.kry_loglik_batch(P.h, thetas, K.kry_opts_default(precision=K.KRY_FP32, shift_share=1, **base))
+        for k in (2, 4, 6):  # (0.01, 1), (0.05, 0.1), (0.2, 0.01)
+            plain = K.kry_loglik(P.h, thetas[k], K.kry_opts_default(precision=K.KRY_FP64, **base))
+            for key in ("loglik", "loglik_profiled"):
+                assert abs(batch[k][key] - plain[key]) <= 1e-3 * abs(plain[key]), (k, key)
+            assert abs(batch[k]["quad"] - plain["quad"]) <= 1e-7 * plain["quad"]
