@@ -158,7 +158,7 @@ __device__ __forceinline__ void load_pair(const StageAArgs& a, const MaskView& m
 // when those lie in one wavefront the passes need no workgroup barrier, and
 // the only barrier is the one before the split, which mixes rows.
 template <typename R, int LOG2M, int IN, int VT>
-__global__ void __launch_bounds__((VT > 1 ? 512 : 1024), (sizeof(R) == 4 && VT == 1 && IN == IN_COMPACT ? 8 : 4)) k_row_fwd(StageAArgs a, const cpx<R>* __restrict__ twp,
+__global__ void __launch_bounds__((VT > 1 ? 512 : 1024), (VT > 1 ? 2 : (sizeof(R) == 4 && IN == IN_COMPACT ? 8 : 4))) k_row_fwd(StageAArgs a, const cpx<R>* __restrict__ twp,
                                                                    const cpx<R>* __restrict__ twb) {
     using S = Sched<LOG2M>;
     constexpr int M = S::L, T = M / 8, PM = padded(M) + 1;
@@ -415,10 +415,10 @@ struct StageCArgs {
 // Stage C: read RT-row runs of X[k], k = 0..M, merge the even/odd split into
 // Z[k] = (X[k] + X*[M-k]) + i W^{-k} (X[k] - X*[M-k]), inverse FFT of length M,
 // then x[2m], x[2m+1] = Re, Im z[m] go to the observed cells (+ eta v) or the
-// grid.  Row threads as in stage A: the barriers are after the tile load and
-// after the merge; the passes of a row stay within its wavefront.
+// grid.  Row threads as in stage A: one workgroup barrier after the tile
+// load; the merge is folded into the first pass's reads.
 template <typename R, int LOG2M, int OUT, int VT>
-__global__ void __launch_bounds__((VT > 1 ? 512 : 1024), (sizeof(R) == 4 && VT == 1 ? 8 : 4)) k_row_inv(StageCArgs a, const cpx<R>* __restrict__ twp,
+__global__ void __launch_bounds__((VT > 1 ? 512 : 1024), (VT > 1 ? 2 : (sizeof(R) == 4 ? 8 : 4))) k_row_inv(StageCArgs a, const cpx<R>* __restrict__ twp,
                                                                    const cpx<R>* __restrict__ twb) {
     using S = Sched<LOG2M>;
     constexpr int M = S::L, T = M / 8, PM = padded(M) + 1;
@@ -497,32 +497,47 @@ __global__ void __launch_bounds__((VT > 1 ? 512 : 1024), (sizeof(R) == 4 && VT =
         if (tid < a.RT) lds[tid * PM + pad8(M)] = ny;
     }
     __syncthreads();
-    const int npair = a.RT * (M / 2 + 1);
-    for (int o = tid; o < npair; o += blockDim.x) {
-        const int r2 = o & (a.RT - 1);
-        const int k = o >> a.log2RT;
-        cpx<R>* bp = lds + r2 * PM;
-        const cpx<R> xk = bp[pad8(k)];
-        const cpx<R> xm = bp[pad8(M - k)];
-        {
-            const cpx<R> s = cadd(xk, cconj(xm));
-            const cpx<R> d = cmul(twiddle<R, true>(twb, k, LOG2M + 1), csub(xk, cconj(xm)));
-            bp[pad8(k)] = cpx<R>{s.x - d.y, s.y + d.x};
-        }
-        if (k > 0 && k < M - k) {
-            const cpx<R> s = cadd(xm, cconj(xk));
-            const cpx<R> d = cmul(twiddle<R, true>(twb, M - k, LOG2M + 1), csub(xm, cconj(xk)));
-            bp[pad8(M - k)] = cpx<R>{s.x - d.y, s.y + d.x};
-        }
-    }
-    __syncthreads();
+    // The first inverse pass reads its inputs merged from the split half
+    // spectrum X of its row: Z[k] = (X[k] + X*[M-k]) + i W^{-k} (X[k] - X*[M-k])
+    // (X[M] is the Nyquist column), so no separate merge pass is needed.
     cpx<R>* buf = lds + rr * PM;
+    auto merged = [&](int k) {
+        const cpx<R> xk = buf[pad8(k)];
+        const cpx<R> xm = buf[pad8(M - k)];
+        const cpx<R> s = cadd(xk, cconj(xm));
+        const cpx<R> d = cmul(twiddle<R, true>(twb, k, LOG2M + 1), csub(xk, cconj(xm)));
+        return cpx<R>{s.x - d.y, s.y + d.x};
+    };
     cpx<R> v[NV];
-    LdsPassesVT<R, LOG2M, true, 0, S::npass - 1, VT, WAVE>::run(v, buf, t, twp);
+    {
+        constexpr int R0 = 1 << S::lr(true, 0);
+        constexpr int Q0 = M / R0;
 #pragma unroll
-    for (int u = 0; u < VT; ++u) pass_read<R, LOG2M, true, S::npass - 1>(v + u * 8, buf, t + u * TR);
+        for (int u = 0; u < VT; ++u)
 #pragma unroll
-    for (int u = 0; u < VT; ++u) pass_compute<R, LOG2M, true, S::npass - 1>(v + u * 8, t + u * TR, twp);
+            for (int b = 0; b < 8 / R0; ++b) {
+                const int j = t + u * TR + b * T;
+#pragma unroll
+                for (int r = 0; r < R0; ++r) v[u * 8 + b * R0 + r] = merged(j + r * Q0);
+            }
+    }
+    if constexpr (S::npass == 1) {
+#pragma unroll
+        for (int u = 0; u < VT; ++u) pass_compute<R, LOG2M, true, 0>(v + u * 8, t + u * TR, twp);
+    } else {
+        lds_sync<WAVE>();  // every read of X before the pass overwrites it
+#pragma unroll
+        for (int u = 0; u < VT; ++u) {
+            pass_compute<R, LOG2M, true, 0>(v + u * 8, t + u * TR, twp);
+            pass_write<R, LOG2M, true, 0>(v + u * 8, buf, t + u * TR);
+        }
+        lds_sync<WAVE>();
+        LdsPassesVT<R, LOG2M, true, 1, S::npass - 1, VT, WAVE>::run(v, buf, t, twp);
+#pragma unroll
+        for (int u = 0; u < VT; ++u) pass_read<R, LOG2M, true, S::npass - 1>(v + u * 8, buf, t + u * TR);
+#pragma unroll
+        for (int u = 0; u < VT; ++u) pass_compute<R, LOG2M, true, S::npass - 1>(v + u * 8, t + u * TR, twp);
+    }
     if (row >= rows_out) return;
     const int theta = (a.vec0 + vec) / a.vecs_per_theta;
     // outputs in groups of two values: the group's nugget-term inputs are
