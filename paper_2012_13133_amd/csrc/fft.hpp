@@ -1,20 +1,6 @@
-// Workgroup-cooperative power-of-two FFTs in LDS (Stockham autosort form).
-//
-// A workgroup transforms `nfft` independent sequences of length L = 2^log2L
-// held in LDS at buf + f * fstride.  Each pass of radix R splits every
-// transform into L/R butterflies; with VPT values per thread the workgroup
-// must have exactly nfft * L / VPT threads, and each thread owns VPT / R
-// butterflies per pass.  Every pass first loads all of a thread's inputs into
-// registers, synchronises, then writes the butterfly outputs to their
-// autosorted positions, so one LDS buffer suffices (no ping-pong copy).
-//
-// Pass with current span Ns (product of earlier radices), butterfly j:
-//   inputs   x[j + r * L/R],                  r = 0..R-1
-//   twiddle  x_r *= W_{Ns R}^{r (j mod Ns)}   (W_n = exp(-2 pi i / n); conj for inverse)
-//   outputs  y[(j div Ns) Ns R + (j mod Ns) + r Ns] = DFT_R(x)_r
-// Radix-8 passes are used while at least three factors of two remain, then
-// one radix-4 or radix-2 pass.  Forward transforms are unnormalised and
-// inverse transforms use the conjugate twiddles (also unnormalised).
+// FFT primitives: twiddle-table access, multiplication by -i / +i and the
+// radix-2, -4 and -8 butterflies (unnormalised forward DFTs; the inverse
+// ones use conjugate twiddles).  The passes that use them are in fftk.hpp.
 #pragma once
 #include "common.hpp"
 
@@ -84,61 +70,6 @@ __device__ __forceinline__ void dft(cpx<R>* v) {
     if constexpr (RADIX == 8) dft8<R, INV>(v);
     else if constexpr (RADIX == 4) dft4<R, INV>(v);
     else dft2<R, INV>(v);
-}
-
-template <int RADIX>
-constexpr int ilog2c() { return RADIX == 8 ? 3 : (RADIX == 4 ? 2 : 1); }
-
-template <typename R, int RADIX, bool INV, int VPT>
-__device__ __forceinline__ void stockham_pass(cpx<R>* buf, int log2L, int log2Ns, int fstride,
-                                              int tid, int nthreads, const cpx<R>* __restrict__ tw) {
-    constexpr int BPT = VPT / RADIX;
-    constexpr int LR = ilog2c<RADIX>();
-    const int log2nb = log2L - LR;  // butterflies per transform = L / RADIX
-    const int nbmask = (1 << log2nb) - 1;
-    const int nsmask = (1 << log2Ns) - 1;
-    cpx<R> v[BPT][RADIX];
-    int dst[BPT];
-#pragma unroll
-    for (int b = 0; b < BPT; ++b) {
-        const int g = tid + b * nthreads;
-        const int f = g >> log2nb;
-        const int j = g & nbmask;
-        const int base = f * fstride;
-#pragma unroll
-        for (int r = 0; r < RADIX; ++r) v[b][r] = buf[base + j + (r << log2nb)];
-        const int jn = j & nsmask;
-        if (log2Ns > 0) {
-#pragma unroll
-            for (int r = 1; r < RADIX; ++r) v[b][r] = cmul(v[b][r], twiddle<R, INV>(tw, r * jn, log2Ns + LR));
-        }
-        dst[b] = base + ((j >> log2Ns) << (log2Ns + LR)) + jn;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < BPT; ++b) {
-        dft<R, RADIX, INV>(v[b]);
-#pragma unroll
-        for (int r = 0; r < RADIX; ++r) buf[dst[b] + (r << log2Ns)] = v[b][r];
-    }
-    __syncthreads();
-}
-
-// In-place FFT of nfft sequences of length 2^log2L in LDS.  Requires
-// blockDim == nfft * 2^log2L / VPT and log2L >= 3.  Caller synchronises
-// before (data written) and the function synchronises after the last pass.
-template <typename R, bool INV, int VPT>
-__device__ void fft_lds(cpx<R>* buf, int log2L, int fstride, int tid, int nthreads,
-                        const cpx<R>* __restrict__ tw) {
-    int s = 0;
-    int rem = log2L;
-    while (rem >= 3) {
-        stockham_pass<R, 8, INV, VPT>(buf, log2L, s, fstride, tid, nthreads, tw);
-        s += 3;
-        rem -= 3;
-    }
-    if (rem == 2) stockham_pass<R, 4, INV, VPT>(buf, log2L, s, fstride, tid, nthreads, tw);
-    else if (rem == 1) stockham_pass<R, 2, INV, VPT>(buf, log2L, s, fstride, tid, nthreads, tw);
 }
 
 }  // namespace kry
