@@ -180,6 +180,18 @@ def main():
     words = n * ((n + 31) // 32) * 8           # mask words + word offsets
     stage_bytes = [Bv * (4 * p + inter) + words, stage_b_bytes, Bv * (inter + 4 * p + 4 * p) + words]
     achieved = stage_bytes[dom] / (stage_ms[dom] / 1e3) / 1e9
+    # the same kernel against the vector ALU: 5 L log2 L flops per complex
+    # transform of length L (row stages: M-point transforms plus the 10-flop
+    # split or merge per output; column stage: forward and inverse N1-point
+    # transforms plus the 2-flop spectrum scaling per point), FP32 without
+    # packed instructions: 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
+    M_ = P.N2 // 2
+    lgM, lgN1 = int(np.log2(M_)), int(np.log2(P.N1))
+    row_fl = n * (5 * M_ * lgM + 10 * (M_ + 1))
+    col_fl = (M_ + 1) * (2 * 5 * P.N1 * lgN1 + 2 * P.N1)
+    stage_flops = [Bv * row_fl, Bv * col_fl, Bv * row_fl]
+    ALU_PEAK_TFS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+    alu_achieved = stage_flops[dom] / (stage_ms[dom] / 1e3) / 1e12
     mv_bytes = sum(stage_bytes)
     mv_achieved = mv_bytes / (sum(stage_ms) / 1e3) / 1e9
 
@@ -291,6 +303,9 @@ def main():
                      "kernel": ["stage A (row transform)", "stage B (column transform x spectrum)",
                                 "stage C (inverse row transform, gather)"][dom],
                      "bytes_per_launch": stage_bytes[dom], "launch_ms": stage_ms[dom], "batch": Bv},
+        "roofline_alu": {"bound": "alu", "achieved": alu_achieved, "peak": ALU_PEAK_TFS, "unit": "TFLOP/s",
+                         "frac": alu_achieved / ALU_PEAK_TFS, "flops_per_launch": stage_flops[dom],
+                         "note": "same kernel; FP32 vector rate without packed instructions"},
         "cpu_baseline": cpu,
         "results_first_point": results[0],
     }
