@@ -30,7 +30,8 @@ def test_header_declares_the_boundary():
     for must in ("kry_matvec", "kry_matvec_device", "kry_loglik", "kry_loglik_batch", "kry_krige", "kry_fit",
                  "kry_lanczos", "kry_logdet", "kry_gauss_quadrature", "kry_solve", "kry_gengk", "kry_lag_grid",
                  "kry_spectrum", "kry_sample", "kry_psd_torus", "kry_probes", "kry_server_create",
-                 "kry_server_submit", "kry_server_poll", "kry_server_wait", "kry_server_destroy"):
+                 "kry_server_submit", "kry_server_poll", "kry_server_wait", "kry_server_destroy",
+                 "kry_loglik_multi", "kry_autotune", "kry_set_tuning", "kry_get_tuning", "kry_set_graphs"):
         assert must in names
 
 
@@ -60,6 +61,16 @@ def test_host_side_paths_without_gpu():
     assert b"steps" in K.lib.kry_last_error()
     # server creation rejects bad arguments
     assert K.lib.kry_server_create(None, 2, 0, 4, 16, ctypes.byref(h)) == K.KRY_EINVAL
+    # shift sharing is off by default; tuning, graphs and the multi-problem
+    # call reject NULL handles before any device work
+    assert o.shift_share == 0
+    t = K.kry_tuning(2, 1, 1, 0.0)
+    assert K.lib.kry_set_tuning(None, 64, 64, 1, ctypes.byref(t)) == K.KRY_EINVAL
+    assert K.lib.kry_get_tuning(None, 64, 64, 1, ctypes.byref(t)) == K.KRY_EINVAL
+    assert K.lib.kry_set_graphs(None, 1) == K.KRY_EINVAL
+    assert K.lib.kry_autotune(None, 1, 8, ctypes.byref(t)) == K.KRY_EINVAL
+    res = K.kry_loglik_result()
+    assert K.lib.kry_loglik_multi(None, None, 1, ctypes.byref(o), ctypes.byref(res)) == K.KRY_EINVAL
 
 
 @pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="a GPU is present")
