@@ -321,9 +321,10 @@ def serve_bench(args, K, synth, np):
     at 16 held-out cells with exact variances) on grids with sides log-uniform
     in the given range, 10-50 % missing (uniform or blob masks), nu in
     {0.5, 1.5, 2.5}.  Problems are created once and stay device-resident.
-    Reports p50/p99 latency (submit to completion) and throughput at 80 % of
-    the measured saturation rate, and the same requests run sequentially in
-    the plain FP64 single-request form on the same GPU."""
+    Reports p50/p99 latency (submit to completion) and throughput with
+    Poisson arrivals at 50, 80 and 100 % of the measured saturation rate (80 %
+    is the headline), and the same requests run sequentially in the plain FP64
+    single-request form on the same GPU."""
     lo, hi = (int(x) for x in args.serve_sides.split(","))
     rng = np.random.default_rng(505)
     ctx = K.kry_ctx_create()
@@ -371,22 +372,29 @@ def serve_bench(args, K, synth, np):
             K.kry_server_wait(srv, p_)
         sat = len(reqs) / (time.perf_counter() - t0)
         log("serve: saturation %.1f requests/s" % sat)
-        # Poisson arrivals at 80 % of saturation
-        rate = 0.8 * sat
-        gaps = rng.exponential(1.0 / rate, size=len(reqs))
-        t0 = time.perf_counter()
-        pend = []
-        tnext = t0
-        for r, gap in zip(reqs, gaps):
-            tnext += gap
-            while time.perf_counter() < tnext:
-                time.sleep(min(0.0005, max(0.0, tnext - time.perf_counter())))
-            pend.append(submit(srv, r, o32))
-        resp = [K.kry_server_wait(srv, p_) for p_ in pend]
-        wall = time.perf_counter() - t0
+        # Poisson arrivals at 50, 80 and 100 % of saturation; the 80 % run is
+        # the headline
+        sweep = {}
+        for frac in (0.5, 0.8, 1.0):
+            rate = frac * sat
+            gaps = rng.exponential(1.0 / rate, size=len(reqs))
+            t0 = time.perf_counter()
+            pend = []
+            tnext = t0
+            for r, gap in zip(reqs, gaps):
+                tnext += gap
+                while time.perf_counter() < tnext:
+                    time.sleep(min(0.0005, max(0.0, tnext - time.perf_counter())))
+                pend.append(submit(srv, r, o32))
+            resp_f = [K.kry_server_wait(srv, p_) for p_ in pend]
+            wall_f = time.perf_counter() - t0
+            lat_f = np.array([r.t_end - r.t_submit for r in resp_f]) * 1e3
+            sweep[frac] = (rate, resp_f, wall_f, lat_f)
+            log("serve at %d%% of saturation: p50 %.1f ms p99 %.1f ms, %.1f req/s" %
+                (100 * frac, np.percentile(lat_f, 50), np.percentile(lat_f, 99), len(reqs) / wall_f))
+        rate, resp, wall, lat = sweep[0.8]
     finally:
         K.kry_server_destroy(srv)
-    lat = np.array([r.t_end - r.t_submit for r in resp]) * 1e3
     n_ll = sum(1 for r in reqs if r[0] == "loglik")
     # sequential plain FP64 form of the same requests
     t1 = time.perf_counter()
@@ -405,7 +413,10 @@ def serve_bench(args, K, synth, np):
            "max_batch_seen": int(max(r.batch for r in resp)),
            "plain_fp64_sequential_req_per_s": len(reqs) / seq,
            "plain_fp64_sequential_loglik_evals_per_s": n_ll / seq,
-           "served_vs_plain": (len(reqs) / wall) / (len(reqs) / seq)}
+           "served_vs_plain": (len(reqs) / wall) / (len(reqs) / seq),
+           "arrival_sweep": [{"fraction_of_saturation": f, "arrival_rate_per_s": v[0],
+                              "p50_ms": float(np.percentile(v[3], 50)), "p99_ms": float(np.percentile(v[3], 99)),
+                              "req_per_s": len(reqs) / v[2]} for f, v in sweep.items()]}
     log("serve: p50 %.1f ms p99 %.1f ms, %.1f req/s vs plain fp64 sequential %.1f req/s" %
         (out["p50_ms"], out["p99_ms"], out["req_per_s"], out["plain_fp64_sequential_req_per_s"]))
     return out
