@@ -95,6 +95,65 @@ def slq_logdet(matvec, probes, m, reorth=True, coloured=False):
     return est, se, np.array(vals), np.array(steps)
 
 
+def adaptive_steps(alphas, betas, znorm2s, rtol, every=5, first=10):
+    """Step count at which the adaptive mode stops: after each multiple of
+    `every` steps from `first` on, every probe's quadrature value with the
+    steps so far must have moved by at most rtol times its size since
+    `every` steps earlier; otherwise (including when every recurrence ended
+    before the first check) all the steps that were run.  A probe whose
+    recurrence ended earlier keeps its final value (it no longer moves).
+    alphas / betas: per-probe coefficient arrays of the full run."""
+    longest = max((len(a) for a in alphas), default=0)
+
+    def gammas(j):
+        out = []
+        for a, b, zz in zip(alphas, betas, znorm2s):
+            if zz == 0.0 or len(a) == 0:
+                out.append(0.0)
+                continue
+            s = min(j, len(a))
+            out.append(quadrature(a[:s], b[: s - 1], zz))
+        return np.array(out)
+
+    prev = None
+    for j in range(every, longest + 1, every):
+        cur = gammas(j)
+        if j >= first and prev is not None and np.all(np.abs(cur - prev) <= rtol * np.abs(cur)):
+            return j
+        prev = cur
+    return longest
+
+
+def slq_logdet_adaptive(matvec, probes, max_steps, rtol, reorth=True, coloured=False):
+    """SLQ with the adaptive stopping rule of `adaptive_steps` (Lanczos run
+    to max_steps, then cut where the rule stops; the coefficients of the first
+    j steps do not depend on later ones).  Returns (estimate, standard error,
+    per-probe values, steps used)."""
+    probes = np.asarray(probes, dtype=np.float64)
+    alphas, betas, zzs = [], [], []
+    for k in range(probes.shape[1]):
+        z = probes[:, k]
+        zz = float(z @ z)
+        zzs.append(zz)
+        if zz == 0.0:
+            alphas.append(np.zeros(0))
+            betas.append(np.zeros(0))
+            continue
+        a, b = lanczos(matvec, z, max_steps, reorth=reorth)
+        alphas.append(a)
+        betas.append(b)
+    m = adaptive_steps(alphas, betas, zzs, rtol)
+    vals = []
+    for a, b, zz in zip(alphas, betas, zzs):
+        if zz == 0.0:
+            vals.append(0.0)
+            continue
+        s = min(m, len(a))
+        vals.append(quadrature(a[:s], b[: s - 1], zz))
+    est, se = combine(vals, coloured)
+    return est, se, np.array(vals), m
+
+
 def exact_hutchinson(K, probes, coloured=False):
     """The probe estimate with every z^T log(K) z computed exactly from a dense
     eigendecomposition (separates probe error from quadrature error)."""

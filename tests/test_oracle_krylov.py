@@ -106,3 +106,28 @@ def test_gengk_full_steps_reproduce_dense_solution():
     # sigma^2 J is the marginal quadratic form y^T K^-1 y of the dense oracle
     out = dense.loglik(g, mask, th, b)
     assert th["sigma2"] * J == pytest.approx(out["quad"], rel=1e-10)
+
+
+def test_adaptive_slq_stopping_rule():
+    g, mask, th, K = _problem(8, 8)
+    p = K.shape[0]
+    r, c = observed_cells(mask)
+    Z = philox.probe_matrix(r, c, 5, seed=21)
+    mv = lambda v: K @ v  # noqa: E731
+    hut, _ = lanczos.exact_hutchinson(K, Z)
+    # a loose tolerance stops at the first check (10 steps), equal to m = 10
+    est, _, vals, m = lanczos.slq_logdet_adaptive(mv, Z, max_steps=p, rtol=10.0)
+    ref, _, rvals, _ = lanczos.slq_logdet(mv, Z, m=10, reorth=True)
+    assert m == 10 and est == ref and np.array_equal(vals, rvals)
+    # rtol = 0 stops only once every recurrence has ended: exact Hutchinson
+    est0, _, _, m0 = lanczos.slq_logdet_adaptive(mv, Z, max_steps=p, rtol=0.0)
+    assert est0 == pytest.approx(hut, rel=1e-10)
+    # a tight tolerance converges well before p steps, close to the exact value
+    est1, _, _, m1 = lanczos.slq_logdet_adaptive(mv, Z, max_steps=p, rtol=1e-9)
+    assert m1 < p and abs(est1 - hut) <= 1e-7 * abs(hut)
+    # a nugget-only covariance ends every recurrence after one step, before
+    # any check: the steps run (one) are used, and the value is exact
+    eta = 0.3
+    _, _, _, Kn = _problem(8, 8, th=theta(1e-6, 0.5, tau2=eta))
+    estn, _, _, mn = lanczos.slq_logdet_adaptive(lambda v: Kn @ v, Z, max_steps=40, rtol=1e-12)
+    assert mn == 1 and estn == pytest.approx(p * np.log1p(eta), rel=1e-14)
