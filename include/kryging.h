@@ -93,6 +93,13 @@ typedef struct {
     int32_t gk_steps;        /* k for genGK                                 */
     int32_t shift_share;     /* 1 = points of one call that differ only in
                                 the nugget ratio share Krylov spaces (below) */
+    int32_t lanczos_max_steps; /* adaptive mode: cap on the steps (10..512)  */
+    double lanczos_rtol;     /* > 0: adaptive mode for the log-determinants:
+                                after every 5th step from step 10 on, stop once
+                                every probe's quadrature value moved by at most
+                                lanczos_rtol times its size over the last 5
+                                steps (or at lanczos_max_steps); lanczos_steps
+                                is then unused.  0 = exactly lanczos_steps.  */
 } kry_opts;
 
 typedef struct {
@@ -113,7 +120,8 @@ const char* kry_status_string(kry_status s);
 const char* kry_last_error(void);
 
 /* Defaults: m = 30, N = 10 Rademacher, seed 303, no reorth, FP64,
- * cg_rtol 1e-8, cg_maxit 20000, CG, gk_steps 100, no shift sharing. */
+ * cg_rtol 1e-8, cg_maxit 20000, CG, gk_steps 100, no shift sharing, fixed
+ * step count (lanczos_rtol 0, lanczos_max_steps 500). */
 kry_status kry_opts_default(kry_opts* out);
 
 /* ---- stage timing ----------------------------------------------------------- */

@@ -117,11 +117,17 @@ void check_opts(const kry_opts* o) {
     KRY_REQUIRE(o->solver == KRY_SOLVER_CG || o->solver == KRY_SOLVER_GENGK, "bad solver");
     KRY_REQUIRE(o->gk_steps >= 1 && o->gk_steps <= 2000, "gk_steps must be in [1, 2000]");
     KRY_REQUIRE(o->shift_share == 0 || o->shift_share == 1, "shift_share must be 0 or 1");
+    KRY_REQUIRE(std::isfinite(o->lanczos_rtol) && o->lanczos_rtol >= 0, "lanczos_rtol must be >= 0");
+    if (o->lanczos_rtol > 0)
+        KRY_REQUIRE(o->lanczos_max_steps >= 10 && o->lanczos_max_steps <= KRY_MAX_LANCZOS,
+                    "lanczos_max_steps must be in [10, 512] in the adaptive mode");
 }
 
 int nprobes_of(const kry_opts* o) {
     return o->probe_kind == KRY_PROBE_COLOURED ? o->colour_period * o->colour_period : o->num_probes;
 }
+
+int lanczos_cap(const kry_opts* o) { return o->lanczos_rtol > 0 ? o->lanczos_max_steps : o->lanczos_steps; }
 }  // namespace kry
 
 namespace {
@@ -405,7 +411,17 @@ void solve_device(Problem& P, int precision, const void* lam64, const void* lam3
 struct LoglikWork {
     std::vector<double> gamma;  // per vector
     std::vector<int> steps;
+    std::vector<int> point_stop;  // adaptive mode: step where each point settled (0: ran to the cap)
 };
+
+// Lanczos steps reported for point t: the most any of its probes ran, or the
+// step where the point settled in the adaptive mode.
+int steps_used(const LoglikWork& W, int t, int np, int first_recurrence) {
+    int smax = 0;
+    for (int k = 0; k < np; ++k) smax = std::max(smax, W.steps[(size_t)first_recurrence + k]);
+    if (t < (int)W.point_stop.size() && W.point_stop[t]) smax = std::min(smax, W.point_stop[t]);
+    return smax;
+}
 
 // Quadrature outputs that read shifted copies of the recurrences' tridiagonals:
 // output v uses recurrence src[v] with T + shift[v] I (device arrays).
@@ -424,14 +440,26 @@ void slq_device(Problem& P, const kry_opts* o, const void* lam, int64_t lam_tstr
                 const ShiftQuad* sq = nullptr, const std::function<void(R*)>* fill_probes = nullptr) {
     const int np = nprobes_of(o);
     const int nvec = count * np;
-    const int m = o->lanczos_steps;
+    // the adaptive mode applies to log-determinants, not to a caller that
+    // asks for the coefficients of exactly lanczos_steps steps
+    const bool adaptive = o->lanczos_rtol > 0 && !alpha_out;
+    const int m = adaptive ? o->lanczos_max_steps : o->lanczos_steps;
     const bool reorth = o->reorth != 0;
     const int64_t p = P.p;
     const int nblk = dot_blocks(p);
+    const int nout = sq ? sq->nout : nvec;
     LanczosBuffers<R> B{};
+    LanczosAdaptive ad{};
     R* Z = nullptr;
     double* gamma = nullptr;
     auto lay = [&](Arena& a) {
+        if (adaptive) {
+            ad.g_prev = a.take<double>(nout);
+            ad.g_cur = a.take<double>(nout);
+            ad.g_final = a.take<double>(nout);
+            ad.stop = a.take<int>(nout / np);
+            ad.done = a.take<int>(1);
+        }
         Z = a.take<R>((size_t)nvec * p);
         B.Q = a.take<R>((size_t)(reorth ? m + 1 : 3) * nvec * p);
         B.W = a.take<R>((size_t)nvec * p);
@@ -455,13 +483,29 @@ void slq_device(Problem& P, const kry_opts* o, const void* lam, int64_t lam_tstr
                                    st));
     }
     auto A = masked_op<R>(P, lam, lam_tstride, np, d_eta);
-    lanczos_run<R>(A, p, nvec, m, reorth, Z, B, st);
-    const int nout = sq ? sq->nout : nvec;
+    if (adaptive) {
+        ad.rtol = o->lanczos_rtol;
+        ad.nout = nout;
+        ad.per_point = np;
+        ad.src = sq ? sq->src : nullptr;
+        ad.shift = sq ? sq->shift : nullptr;
+    }
+    lanczos_run<R>(A, p, nvec, m, reorth, Z, B, st, adaptive ? &ad : nullptr);
     if (sq) quadrature(B.alpha, B.beta, B.steps, B.znorm2, nout, nvec, gamma, st, sq->src, sq->shift);
     else quadrature(B.alpha, B.beta, B.steps, B.znorm2, nvec, nvec, gamma, st);
     W.gamma.resize(nout);
     W.steps.resize(nvec);
+    W.point_stop.assign(nout / np, 0);
     KRY_HIP(hipMemcpyAsync(W.gamma.data(), gamma, nout * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (adaptive) {
+        // settled points keep the values of the step where they settled
+        std::vector<double> gf(nout);
+        KRY_HIP(hipMemcpyAsync(gf.data(), ad.g_final, nout * sizeof(double), hipMemcpyDeviceToHost, st));
+        KRY_HIP(hipMemcpyAsync(W.point_stop.data(), ad.stop, (nout / np) * sizeof(int), hipMemcpyDeviceToHost, st));
+        KRY_HIP(hipStreamSynchronize(st));
+        for (int v = 0; v < nout; ++v)
+            if (W.point_stop[v / np]) W.gamma[v] = gf[v];
+    }
     KRY_HIP(hipMemcpyAsync(W.steps.data(), B.steps, nvec * sizeof(int), hipMemcpyDeviceToHost, st));
     if (alpha_out) {
         alpha_out->resize((size_t)m * nvec);
@@ -769,9 +813,7 @@ void loglik_points_shared(Problem& P, const kry_matern* thetas, int count, const
         kry_loglik_result& r = out[t];
         std::memset(&r, 0, sizeof(r));
         assemble(&r, p, est, se, Q[t], thetas[t].sigma2);
-        int smax = 0;
-        for (int k = 0; k < np; ++k) smax = std::max(smax, W.steps[(size_t)grp[t] * np + k]);
-        r.lanczos_steps_used = smax;
+        r.lanczos_steps_used = steps_used(W, t, np, grp[t] * np);
         r.cg_iters = iters[t];
         r.cg_relres = relres[t];
     }
@@ -872,9 +914,7 @@ void loglik_multi_group(Problem& Q, const std::vector<Problem*>& probs, const kr
         kry_loglik_result& r = out[g];
         std::memset(&r, 0, sizeof(r));
         assemble(&r, probs[g]->p, est, se, Qf[g], th[g].sigma2);
-        int smax = 0;
-        for (int k = 0; k < np; ++k) smax = std::max(smax, W.steps[(size_t)g * np + k]);
-        r.lanczos_steps_used = smax;
+        r.lanczos_steps_used = steps_used(W, g, np, g * np);
         r.cg_iters = ss.iters[g];
         r.cg_relres = ss.relres[g];
     }
@@ -968,9 +1008,7 @@ void loglik_points(Problem& P, const kry_matern* thetas, int count, const kry_op
         kry_loglik_result& r = out[t];
         std::memset(&r, 0, sizeof(r));
         assemble(&r, P.p, est, se, Q[t], thetas[t].sigma2);
-        int smax = 0;
-        for (int k = 0; k < np; ++k) smax = std::max(smax, W.steps[(size_t)t * np + k]);
-        r.lanczos_steps_used = smax;
+        r.lanczos_steps_used = steps_used(W, t, np, t * np);
         r.cg_iters = iters[t];
         r.cg_relres = relres[t];
     }
@@ -1014,6 +1052,8 @@ kry_status kry_opts_default(kry_opts* out) {
         o.solver = KRY_SOLVER_CG;
         o.gk_steps = 100;
         o.shift_share = 0;
+        o.lanczos_max_steps = 500;
+        o.lanczos_rtol = 0.0;
         *out = o;
     });
 }
@@ -1588,7 +1628,7 @@ kry_status kry_loglik_batch(kry_problem* prob, const kry_matern* thetas, int32_t
         // points go through in chunks that bound the Krylov workspace
         const int np = nprobes_of(opts);
         const size_t per_point = (size_t)np * P.p * (opts->precision == KRY_FP32 ? 4 : 8) *
-                                 (opts->reorth ? opts->lanczos_steps + 3 : 5);
+                                 (opts->reorth ? lanczos_cap(opts) + 3 : 5);
         // workspace per chunk: 48 GB, or half the context's budget when one is set
         size_t cap = (size_t)48e9;
         if (P.ctx->budget > 0) cap = std::min<size_t>(cap, P.ctx->budget / 2);
@@ -1820,7 +1860,7 @@ kry_status kry_loglik_multi(kry_problem* const* probs, const kry_matern* thetas,
             int64_t pm = 0;
             for (int i : grp) pm = std::max(pm, probs[i]->P.p);
             // per problem: Lanczos block and CG / refinement vectors at the padded length
-            const size_t per = (size_t)np * pm * es * (opts->reorth ? opts->lanczos_steps + 3 : 5) + 12 * (size_t)pm * 8;
+            const size_t per = (size_t)np * pm * es * (opts->reorth ? lanczos_cap(opts) + 3 : 5) + 12 * (size_t)pm * 8;
             const size_t chunk = std::max<size_t>(1, cap / std::max<size_t>(per, 1));
             for (size_t a = 0; a < grp.size(); a += chunk) {
                 const size_t b = std::min(grp.size(), a + chunk);

@@ -251,6 +251,8 @@ void krige_impl(Problem& P, const kry_matern* theta, const kry_opts* opts, const
 void check_theta(const kry_matern* t);
 void check_opts(const kry_opts* o);
 int nprobes_of(const kry_opts* o);
+// Lanczos steps the workspace must hold: lanczos_steps, or the adaptive cap.
+int lanczos_cap(const kry_opts* o);
 
 // ---- Krylov building blocks (krylov.hip) --------------------------------------
 int dot_blocks(int64_t n);

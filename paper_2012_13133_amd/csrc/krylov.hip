@@ -246,9 +246,32 @@ __global__ void k_multi_axpy(const R* __restrict__ Q, int64_t qslot, const doubl
     }
 }
 
+// Points whose outputs all settled since the last check record the step and
+// their values; done = every point settled.  One block, fixed order.
+__global__ void k_lanczos_settle(const double* __restrict__ g_cur, const double* __restrict__ g_prev,
+                                 double* __restrict__ g_final, int* __restrict__ stop, int nout, int per_point,
+                                 double rtol, int step, int* __restrict__ done) {
+    const int npoints = nout / per_point;
+    for (int pt = threadIdx.x; pt < npoints; pt += blockDim.x) {
+        if (stop[pt]) continue;
+        bool settled = true;
+        for (int o = pt * per_point; o < (pt + 1) * per_point; ++o)
+            settled = settled && fabs(g_cur[o] - g_prev[o]) <= rtol * fabs(g_cur[o]);
+        if (!settled) continue;
+        stop[pt] = step;
+        for (int o = pt * per_point; o < (pt + 1) * per_point; ++o) g_final[o] = g_cur[o];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int all = 1;
+        for (int pt = 0; pt < npoints; ++pt) all = all && stop[pt] != 0;
+        done[0] = all;
+    }
+}
+
 template <typename R>
 void lanczos_run(const MatvecFn<R>& A, int64_t n, int nvec, int m, bool reorth, const R* Z, LanczosBuffers<R>& B,
-                 hipStream_t st) {
+                 hipStream_t st, const LanczosAdaptive* ad) {
     const int nblk = dot_blocks(n);
     const double tol = sizeof(R) == 8 ? 1e-12 : 1e-6;
     const int64_t slot = (int64_t)nvec * n;
@@ -262,6 +285,12 @@ void lanczos_run(const MatvecFn<R>& A, int64_t n, int nvec, int m, bool reorth, 
     hipLaunchKernelGGL(k_scale_vec<R>, vec_grid(n, nvec), dim3(256), 0, st, Z, B.scale, Qs(0), n);
     KRY_HIP(hipGetLastError());
     (void)nslots;
+    double *g_prev = nullptr, *g_cur = nullptr;
+    if (ad) {
+        KRY_HIP(hipMemsetAsync(ad->stop, 0, (ad->nout / ad->per_point) * sizeof(int), st));
+        g_prev = ad->g_prev;
+        g_cur = ad->g_cur;
+    }
     for (int j = 0; j < m; ++j) {
         R* q = Qs(j);
         const R* qp = j > 0 ? Qs(j - 1) : nullptr;
@@ -293,6 +322,19 @@ void lanczos_run(const MatvecFn<R>& A, int64_t n, int nvec, int m, bool reorth, 
         hipLaunchKernelGGL(k_lanczos_beta, dim3(nvec), dim3(RB), 0, st, B.partial, nblk, j, aj, bprev, bj, B.scale,
                            B.active, B.steps, tol);
         KRY_HIP(hipGetLastError());
+        if (ad && (j + 1) % 5 == 0) {
+            quadrature(B.alpha, B.beta, B.steps, B.znorm2, ad->nout, nvec, g_cur, st, ad->src, ad->shift);
+            if (j + 1 >= 10) {
+                hipLaunchKernelGGL(k_lanczos_settle, dim3(1), dim3(256), 0, st, g_cur, g_prev, ad->g_final, ad->stop,
+                                   ad->nout, ad->per_point, ad->rtol, j + 1, ad->done);
+                KRY_HIP(hipGetLastError());
+                int done = 0;
+                KRY_HIP(hipMemcpyAsync(&done, ad->done, sizeof(int), hipMemcpyDeviceToHost, st));
+                KRY_HIP(hipStreamSynchronize(st));
+                if (done) break;
+            }
+            std::swap(g_prev, g_cur);
+        }
         if (j + 1 < m) {
             hipLaunchKernelGGL(k_scale_vec<R>, vec_grid(n, nvec), dim3(256), 0, st, B.W, B.scale, Qs(j + 1), n);
             KRY_HIP(hipGetLastError());
@@ -300,9 +342,9 @@ void lanczos_run(const MatvecFn<R>& A, int64_t n, int nvec, int m, bool reorth, 
     }
 }
 template void lanczos_run<double>(const MatvecFn<double>&, int64_t, int, int, bool, const double*,
-                                  LanczosBuffers<double>&, hipStream_t);
+                                  LanczosBuffers<double>&, hipStream_t, const LanczosAdaptive*);
 template void lanczos_run<float>(const MatvecFn<float>&, int64_t, int, int, bool, const float*,
-                                 LanczosBuffers<float>&, hipStream_t);
+                                 LanczosBuffers<float>&, hipStream_t, const LanczosAdaptive*);
 
 // ---- Gauss quadrature ---------------------------------------------------------------
 // For each probe: eigen-decomposition of its Lanczos tridiagonal T (steps

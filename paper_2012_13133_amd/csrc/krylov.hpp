@@ -61,9 +61,26 @@ void mscg_run(const MatvecFn<double>& A, const std::function<void(int, int)>& sw
 template <typename T>
 void swap_vectors(T* base, int64_t stride, int a, int b, int64_t n, hipStream_t st);
 
+// Adaptive stopping for lanczos_run: after every 5th step from step 10 on,
+// the quadrature values of nout outputs (output v reads recurrence src[v]
+// shifted by shift[v], or v itself when src is NULL) are compared with those
+// 5 steps earlier; a point (per_point consecutive outputs) settles at the
+// first check where all of its outputs moved by at most rtol times their
+// size, and keeps those values (g_final) and that step (stop, 0 = not
+// settled).  The run ends when every point has settled or at m steps.
+struct LanczosAdaptive {
+    double rtol;
+    int nout, per_point;
+    const int* src;
+    const double* shift;
+    double *g_prev, *g_cur, *g_final;  // nout each (device)
+    int* stop;                         // nout / per_point (device)
+    int* done;                         // 1 (device)
+};
+
 template <typename R>
 void lanczos_run(const MatvecFn<R>& A, int64_t n, int nvec, int m, bool reorth, const R* Z, LanczosBuffers<R>& B,
-                 hipStream_t st);
+                 hipStream_t st, const LanczosAdaptive* ad = nullptr);
 // gamma for nvec outputs; output v uses recurrence src[v] shifted by
 // shift[v] when those (device) arrays are given.
 void quadrature(const double* alpha, const double* beta, const int* steps, const double* znorm2, int nvec,

@@ -72,7 +72,7 @@ uint64_t footprint(const Problem& P, const kry_request& r, int count) {
     const uint64_t inter = (M + 1) * (uint64_t)P.n1 * 2 * el;
     if (r.kind == KRY_REQ_LOGLIK) {
         const uint64_t np = nprobes_of(&r.opts);
-        const uint64_t slots = r.opts.reorth ? r.opts.lanczos_steps + 3 : 5;
+        const uint64_t slots = r.opts.reorth ? lanczos_cap(&r.opts) + 3 : 5;
         const uint64_t vecs = count * np;
         return vecs * p * el * slots + std::min<uint64_t>(vecs, 64) * inter + count * nspec * 12 +
                count * p * 8 * 6 + P.N1 * (uint64_t)P.N2 * 8;
@@ -108,7 +108,8 @@ struct kry_server {
         return a.lanczos_steps == b.lanczos_steps && a.num_probes == b.num_probes && a.probe_kind == b.probe_kind &&
                a.colour_period == b.colour_period && a.seed == b.seed && a.reorth == b.reorth &&
                a.precision == b.precision && a.cg_rtol == b.cg_rtol && a.cg_maxit == b.cg_maxit &&
-               a.solver == b.solver && a.gk_steps == b.gk_steps && a.shift_share == b.shift_share;
+               a.solver == b.solver && a.gk_steps == b.gk_steps && a.shift_share == b.shift_share &&
+               a.lanczos_max_steps == b.lanczos_max_steps && a.lanczos_rtol == b.lanczos_rtol;
     }
 
     // Likelihood requests that can run in one batch with the head h: the same

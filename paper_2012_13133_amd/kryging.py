@@ -42,7 +42,8 @@ class kry_opts(C.Structure):
     _fields_ = [("lanczos_steps", C.c_int32), ("num_probes", C.c_int32), ("probe_kind", C.c_int32),
                 ("colour_period", C.c_int32), ("seed", C.c_uint64), ("reorth", C.c_int32),
                 ("precision", C.c_int32), ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32),
-                ("solver", C.c_int32), ("gk_steps", C.c_int32), ("shift_share", C.c_int32)]
+                ("solver", C.c_int32), ("gk_steps", C.c_int32), ("shift_share", C.c_int32),
+                ("lanczos_max_steps", C.c_int32), ("lanczos_rtol", C.c_double)]
 
 
 class kry_loglik_result(C.Structure):

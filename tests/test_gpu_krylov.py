@@ -405,3 +405,39 @@ def test_loglik_multi_errors():
     finally:
         K.kry_problem_destroy(h)
         K.kry_ctx_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_adaptive_lanczos_matches_oracle_rule(precision):
+    # the adaptive mode stops where every probe's quadrature value settled
+    # over 5 steps (checks from step 10); the oracle applies the same rule
+    n1, n2 = 24, 24
+    th = theta(0.15, 1.5, tau2=0.05)
+    g, mask, y, yo = _problem(n1, n2, th, 0.3)
+    Kd = dense.covariance(g, mask, th)
+    r, c = observed_cells(mask)
+    opts = K.kry_opts_default(num_probes=6, reorth=1, lanczos_rtol=1e-6, lanczos_max_steps=120,
+                              precision=precision, cg_rtol=1e-10)
+    Z = philox.probe_matrix(r, c, 6, opts.seed)
+    est, _, vals, m = lanczos.slq_logdet_adaptive(lambda v: Kd @ v, Z, 120, 1e-6, reorth=True)
+    assert 10 <= m < 120
+    with K.Problem(n1, n2, mask, y) as P:
+        ld, _, per = K.kry_logdet(P.h, K.theta_from_dict(th), opts)
+        res = K.kry_loglik(P.h, K.theta_from_dict(th), opts)
+    tol = 1e-9 if precision == 0 else 1e-5
+    assert abs(ld - est) <= tol * abs(est)
+    np.testing.assert_allclose(per, vals, rtol=tol * 10)
+    assert res["lanczos_steps_used"] == m and res["logdet"] == ld
+
+
+@pytest.mark.parametrize("share", [0, 1])
+def test_adaptive_lanczos_same_alone_and_in_mix(share):
+    n1, n2, g, mask, y, yo, thetas = _shift_case()
+    opts = K.kry_opts_default(num_probes=5, reorth=1, lanczos_rtol=1e-5, lanczos_max_steps=100, shift_share=share)
+    with K.Problem(n1, n2, mask, y) as P:
+        mix = K.kry_loglik_batch(P.h, [K.theta_from_dict(t) for t in thetas], opts)
+        alone = [K.kry_loglik(P.h, K.theta_from_dict(t), opts) for t in thetas]
+    for a, s in zip(mix, alone):
+        for k in ("logdet", "quad", "lanczos_steps_used"):
+            assert a[k] == s[k], k
+    assert len({a["lanczos_steps_used"] for a in mix}) > 1  # points settle at different steps
