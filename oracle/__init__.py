@@ -24,7 +24,7 @@ philox      counter-based RNG (Philox4x32-10) shared by definition with the
 matern      Matern correlation (Sec. 2) and the anisotropic lag distance
 geometry    cell coordinates, lag tables, circulant-embedding lag grid
 direct      direct O(p^2) masked covariance product
-dense       dense Cholesky log-likelihood and kriging
+dense       dense Cholesky log-likelihood and kriging, with covariates (GLS)
 lanczos     stochastic Lanczos quadrature for log det (Sec. 3.3 alternative)
 cg          textbook conjugate gradients
 gengk       generalized Golub-Kahan bidiagonalization (Algorithm 1)

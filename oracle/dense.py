@@ -2,9 +2,11 @@
 
 Test infrastructure only (see ``oracle/__init__``).
 
-Model (Sec. 2, observation model): y = A x + eps, x ~ N(0, sigma^2 Sigma),
-eps ~ N(0, tau^2 I); zero mean (no covariates).  The observations are
-therefore y ~ N(0, sigma^2 K) with K = A Sigma A^T + eta I, eta = tau^2/sigma^2.
+Model (Sec. 2, eq. obs_mod): y = X beta + A x + eps, x ~ N(0, sigma^2 Sigma),
+eps ~ N(0, tau^2 I).  The observations are therefore y ~ N(X beta, sigma^2 K)
+with K = A Sigma A^T + eta I, eta = tau^2/sigma^2.  The functions without
+covariates take beta = 0 (X empty); the ``*_covariates`` functions below
+estimate beta.
 
 Log-likelihood (reading of the profile-likelihood objective of Sec. 3.1 and
 3.4 for the marginal model; x integrated out, sigma^2 profiled):
@@ -99,3 +101,88 @@ def posterior_mean_all(grid, mask, theta, y_obs):
     S = full_correlation(grid, theta)
     obs = np.flatnonzero(np.asarray(mask).ravel())
     return S[:, obs] @ w
+
+
+# ---- covariates (eq. obs_mod with X beta) --------------------------------------------
+
+
+def gls(K, X, y):
+    """Generalised least squares for y ~ N(X beta, sigma^2 K): the beta that
+    maximises the likelihood at fixed covariance parameters solves the
+    normal equations X^T K^{-1} (y - X beta) = 0 (the beta-gradient of the
+    appendix's profile likelihood, set to zero, in the marginal form), so
+
+        beta_hat = (X^T K^{-1} X)^{-1} X^T K^{-1} y,
+        Q        = (y - X beta_hat)^T K^{-1} (y - X beta_hat).
+
+    Returns beta_hat, G = X^T K^{-1} X and Q."""
+    X = np.asarray(X, dtype=np.float64).reshape(K.shape[0], -1)
+    y = np.asarray(y, dtype=np.float64)
+    cf = cho_factor(K, lower=True)
+    KX = cho_solve(cf, X)
+    G = X.T @ KX
+    g = KX.T @ y
+    beta = np.linalg.solve(G, g) if X.shape[1] else np.zeros(0)
+    r = y - X @ beta
+    Q = float(r @ cho_solve(cf, r))
+    return beta, G, Q
+
+
+def loglik_covariates(grid, mask, theta, y_obs, X_obs, reml=False):
+    """Log-likelihood with the mean X beta profiled at beta_hat (``gls``).
+
+    X_obs: (p, q) covariates at the observed cells, increasing cell id.
+
+    Maximum likelihood (reml=False): the formulas of ``loglik`` with
+    Q = (y - X beta_hat)^T K^{-1} (y - X beta_hat).
+
+    Restricted likelihood (reml=True; not in the paper, the standard
+    alternative for the covariance parameters): the likelihood of the error
+    contrasts L y, L with orthonormal rows spanning the complement of X's
+    columns, which is (m = p - q)
+        l_R   = -1/2 [ m log(2 pi sigma^2) + log det K + log det(X^T K^{-1} X)
+                       - log det(X^T X) + Q / sigma^2 ],
+        sigma2_hat = Q / m,
+        l_R,p = -1/2 [ m (log 2 pi + log sigma2_hat + 1) + log det K
+                       + log det(X^T K^{-1} X) - log det(X^T X) ].
+
+    Also returns beta, beta_se = sqrt(diag(sigma2_hat (X^T K^{-1} X)^{-1}))
+    and logdet_xkx = log det(X^T K^{-1} X).
+    """
+    K = covariance(grid, mask, theta)
+    X = np.asarray(X_obs, dtype=np.float64).reshape(K.shape[0], -1)
+    p, q = X.shape
+    L = np.linalg.cholesky(K)
+    logdet = 2.0 * np.sum(np.log(np.diag(L)))
+    beta, G, Q = gls(K, X, y_obs)
+    ld_xkx = float(np.linalg.slogdet(G)[1]) if q else 0.0
+    ld_xx = float(np.linalg.slogdet(X.T @ X)[1]) if q else 0.0
+    if not reml:
+        out = assemble(p, logdet, Q, theta["sigma2"])
+    else:
+        m = p - q
+        s2 = Q / m
+        extra = logdet + ld_xkx - ld_xx
+        out = dict(logdet=float(logdet), quad=float(Q),
+                   loglik=float(-0.5 * (m * np.log(2.0 * np.pi * theta["sigma2"]) + extra + Q / theta["sigma2"])),
+                   sigma2_hat=float(s2),
+                   loglik_profiled=float(-0.5 * (m * (np.log(2.0 * np.pi) + np.log(s2) + 1.0) + extra)),
+                   p=int(p))
+    cov = out["sigma2_hat"] * np.linalg.inv(G) if q else np.zeros((0, 0))
+    out.update(beta=beta, beta_se=np.sqrt(np.diag(cov)), logdet_xkx=ld_xkx)
+    return out
+
+
+def krige_covariates(grid, mask, theta, y_obs, X_obs, X_targets, targets):
+    """Kriging with the mean at its GLS estimate (plug-in: beta treated as
+    known at beta_hat, as the bootstrap of Sec. 3.5 does):
+        mean_t = X_t beta_hat + c_t^T K^{-1} (y - X beta_hat),
+    and the variances of ``krige`` (they do not involve the mean).
+    X_targets: (T, q) covariates at the targets."""
+    K = covariance(grid, mask, theta)
+    X = np.asarray(X_obs, dtype=np.float64).reshape(K.shape[0], -1)
+    beta, _, _ = gls(K, X, y_obs)
+    r = np.asarray(y_obs, dtype=np.float64) - X @ beta
+    mean, var_x, var_y = krige(grid, mask, theta, r, targets)
+    Xt = np.asarray(X_targets, dtype=np.float64).reshape(len(targets), -1)
+    return Xt @ beta + mean, var_x, var_y, beta

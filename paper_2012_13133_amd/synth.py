@@ -75,3 +75,17 @@ def held_out_cells(mask, count, seed):
 def log_uniform_sides(count, lo, hi, seed):
     rng = np.random.default_rng(seed)
     return np.round(np.exp(rng.uniform(np.log(lo), np.log(hi), size=count))).astype(int)
+
+
+def covariates(n1, n2, q, seed):
+    """q covariate columns over every cell, shape (q, n1, n2): an intercept
+    (ones), then the column and row coordinates of the cell centres on the
+    unit square, then standard normal columns (the paper's experiments use
+    the intercept alone; the others give regressions with several columns)."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((q, n1, n2))
+    jj, ii = np.meshgrid((np.arange(n2) + 0.5) / n2, (np.arange(n1) + 0.5) / n1)
+    fixed = [np.ones((n1, n2)), jj, ii]
+    for c in range(q):
+        out[c] = fixed[c] if c < 3 else rng.standard_normal((n1, n2))
+    return out
