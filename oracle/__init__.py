@@ -27,10 +27,14 @@ direct      direct O(p^2) masked covariance product
 dense       dense Cholesky log-likelihood and kriging, with covariates (GLS)
 lanczos     stochastic Lanczos quadrature for log det (Sec. 3.3 alternative)
 cg          textbook conjugate gradients
-gengk       generalized Golub-Kahan bidiagonalization (Algorithm 1)
+gengk       generalized Golub-Kahan bidiagonalization (Algorithm 1), low-rank
+            posterior variance
 sampler     Cholesky and circulant-embedding Gaussian field samplers
 bootstrap   parametric bootstrap prediction variance (Sec. 3.5)
 fit         profile-likelihood maximisation over (range, nugget ratio)
+plik        the paper's own profile likelihood (exact and approximate), the
+            quadrant log-determinant, the approximate gradient and the
+            rank-one-Hessian trust-region fit
 
 Parity unpinned: none.  Every function has at least one test in
 ``tests/test_oracle_*.py`` that checks it against something other than

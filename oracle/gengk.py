@@ -13,6 +13,15 @@ factor, but its first step uses ||b||/tau and eq. exact_arith requires
 U^T U = tau^2 I; both hold only if every beta is the 2-norm divided by tau.
 That reading is used here.
 
+Posterior covariance (Sec. 3.5 and the appendix, eq. bgamma_approx):
+Gamma = (Sigma^{-1}/sigma^2 + A^T A/tau^2)^{-1} is approximated from the same
+bidiagonalization as sigma^2 (Sigma - Z_k Delta_k Z_k^T), Z_k = Sigma V_k W_k,
+B_k^T B_k = W_k Theta_k W_k^T.  Reading of a garbled factor: the text gives
+Delta_k = (I + lambda^{-2} Theta_k)^{-1}; the form that reproduces Gamma
+exactly once the Krylov space is complete (k = p) is
+Delta_k = (I + lambda^2 Theta_k^{-1})^{-1} = Theta_k (Theta_k + I/sigma^2)^{-1},
+lambda^2 = 1/sigma^2, and that is the one used here.
+
 Projected problem (eq. xhat_est): z_k = (B_k^T B_k + I/sigma^2)^{-1} B_k^T beta_1 e_1,
 x_k* = Sigma V_k z_k, and the quadratic term x^T Sigma^{-1} x ~ ||z_k||^2.
 The minimum value (1/tau^2)||A x - b||^2 + (1/sigma^2) x^T Sigma^{-1} x
@@ -78,3 +87,14 @@ def gengk_solve(A, Sigma, b, sigma2, tau2, k, reorth=False):
     z, J = projected_solve(B, beta1, sigma2)
     x = Sigma @ (V @ z)
     return x, J, z
+
+
+def posterior_variance(A, Sigma, b, sigma2, tau2, k, reorth=True):
+    """Diagonal of the low-rank posterior covariance of eq. bgamma_approx
+    (with the Delta_k reading in the module docstring) over every cell:
+    var x_i = sigma2 (Sigma_ii - sum_j Z_ij^2 Delta_j)."""
+    beta1, U, V, B, _, _ = gengk(A, Sigma, b, tau2, k, reorth=reorth)
+    theta, W = np.linalg.eigh(B.T @ B)
+    Z = Sigma @ V @ W
+    delta = theta / (theta + 1.0 / sigma2)
+    return sigma2 * (np.diag(Sigma) - (Z * Z) @ delta)

@@ -26,14 +26,14 @@ def observed_cells(mask):
     return r.astype(np.int64), c.astype(np.int64)
 
 
-def lag_table(n1, n2, dx1, dx2, theta):
+def lag_table(n1, n2, dx1, dx2, theta, drange=False):
     """Correlation at every lag (h1, h2), |h1| < n1, |h2| < n2, as an array T
     with T[h1 + n1 - 1, h2 + n2 - 1] = C(h2 dx2, h1 dx1) (Sec. 2 Matern,
-    BTTB structure of Sec. 3)."""
+    BTTB structure of Sec. 3); the range derivative of it when drange."""
     h1 = np.arange(-(n1 - 1), n1, dtype=np.float64)
     h2 = np.arange(-(n2 - 1), n2, dtype=np.float64)
     H1, H2 = np.meshgrid(h1, h2, indexing="ij")
-    return correlation(H2 * dx2, H1 * dx1, theta)
+    return correlation(H2 * dx2, H1 * dx1, theta, drange)
 
 
 def wrapped_lag(l, N):
@@ -43,7 +43,7 @@ def wrapped_lag(l, N):
     return np.where(l <= N // 2, l, l - N)
 
 
-def embedding_lags(N1, N2, dx1, dx2, theta):
+def embedding_lags(N1, N2, dx1, dx2, theta, drange=False):
     """Lag grid c (N1 x N2) of the block-circulant embedding (Sec. 3.3: the
     circulant C is built exactly as for the circulant-embedding product).
 
@@ -52,7 +52,8 @@ def embedding_lags(N1, N2, dx1, dx2, theta):
     is the mean of the correlation over all aliases.  This keeps
     c[l] = c[-l], hence a real spectrum.  The masked product only needs lags
     |h| <= n - 1, and n - 1 < N/2 whenever N >= 2n - 1, so it never reads a
-    Nyquist line.
+    Nyquist line.  With drange the lag grid holds the derivative of the
+    correlation with respect to the range instead.
     """
     def aliases(N):
         out = []
@@ -69,11 +70,11 @@ def embedding_lags(N1, N2, dx1, dx2, theta):
     h1 = np.array([a[0] for a in a1], dtype=np.float64)
     h2 = np.array([a[0] for a in a2], dtype=np.float64)
     H1, H2 = np.meshgrid(h1, h2, indexing="ij")
-    c[:] = correlation(H2 * dx2, H1 * dx1, theta)
+    c[:] = correlation(H2 * dx2, H1 * dx1, theta, drange)
     for i, al1 in enumerate(a1):
         for j, al2 in (list(enumerate(a2)) if len(al1) > 1 else
                        [(j, a) for j, a in enumerate(a2) if len(a) > 1]):
-            vals = [correlation(s2 * dx2, s1 * dx1, theta) for s1 in al1 for s2 in al2]
+            vals = [correlation(s2 * dx2, s1 * dx1, theta, drange) for s1 in al1 for s2 in al2]
             c[i, j] = float(np.mean(vals))
     return c
 

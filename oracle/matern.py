@@ -54,6 +54,39 @@ def matern_half_integer(d, rho, nu):
     raise ValueError("closed form only for nu in {0.5, 1.5, 2.5}")
 
 
+def matern_drange(d, rho, nu):
+    """Derivative of the Matern correlation with respect to the range rho
+    (the d Sigma(rho) of the appendix's gradient).  With x = sqrt(2 nu) d / rho,
+    d/dx [x^nu K_nu(x)] = -x^nu K_{nu-1}(x) (DLMF 10.29.4) and dx/drho = -x/rho,
+    so  dM/drho = 2^(1-nu) / Gamma(nu) * x^(nu+1) K_{nu-1}(x) / rho,  0 at d = 0."""
+    d = np.asarray(d, dtype=np.float64)
+    x = np.sqrt(2.0 * nu) * d / rho
+    out = np.zeros_like(x)
+    pos = x > 0
+    xp = x[pos]
+    with np.errstate(under="ignore", invalid="ignore", over="ignore"):
+        val = 2.0 ** (1.0 - nu) / _gamma(nu) * xp ** (nu + 1.0) * _kv(nu - 1.0, xp) / rho
+    out[pos] = np.where(np.isfinite(val), val, 0.0)
+    return out
+
+
+def matern_drange_half_integer(d, rho, nu):
+    """Closed forms of d/drho of the Matern correlation for nu = 1/2, 3/2,
+    5/2, by differentiating ``matern_half_integer`` (a pin for
+    ``matern_drange``)."""
+    d = np.asarray(d, dtype=np.float64)
+    if nu == 0.5:
+        t = d / rho
+        return t * np.exp(-t) / rho
+    if nu == 1.5:
+        u = np.sqrt(3.0) * d / rho
+        return u * u * np.exp(-u) / rho
+    if nu == 2.5:
+        u = np.sqrt(5.0) * d / rho
+        return u * u * (1.0 + u) * np.exp(-u) / (3.0 * rho)
+    raise ValueError("closed form only for nu in {0.5, 1.5, 2.5}")
+
+
 def aniso_distance(dx, dy, ratio=1.0, angle=0.0):
     """Distance of displacement (dx along columns, dy along rows) under the
     rotated geometric anisotropy (reading of the Sec. 2 remark): components
@@ -66,8 +99,9 @@ def aniso_distance(dx, dy, ratio=1.0, angle=0.0):
     return np.sqrt(a * a + (ratio * b) ** 2)
 
 
-def correlation(dx, dy, theta):
+def correlation(dx, dy, theta, drange=False):
     """Unit-variance Matern correlation for displacement (dx, dy) given a
-    parameter dict with keys range, nu, aniso_ratio, aniso_angle."""
+    parameter dict with keys range, nu, aniso_ratio, aniso_angle (its
+    derivative with respect to the range when drange)."""
     d = aniso_distance(dx, dy, theta.get("aniso_ratio", 1.0), theta.get("aniso_angle", 0.0))
-    return matern(d, theta["range"], theta["nu"])
+    return (matern_drange if drange else matern)(d, theta["range"], theta["nu"])
