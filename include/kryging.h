@@ -6,14 +6,17 @@
  * Majumder, Guan, Reich & Saibaba, "Kryging: Geostatistical analysis of
  * large-scale datasets using Krylov subspace methods":
  *
- *   model (Sec. 2, eq. obs_mod):  y = A x + eps,  x ~ N(0, sigma^2 Sigma),
+ *   model (Sec. 2, eq. obs_mod):  y = X beta + A x + eps,  x ~ N(0, sigma^2 Sigma),
  *                                 eps ~ N(0, tau^2 I), A = identity with the
  *                                 rows of unobserved cells removed;
  *   Sigma (Sec. 2):               Matern correlation with range, smoothness
  *                                 and (rotated) geometric anisotropy; on a
  *                                 grid it is symmetric BTTB (Sec. 3);
  *   K  = A Sigma A^T + eta I,     eta = tau^2 / sigma^2, the unit-variance
- *                                 covariance of the observations.
+ *                                 covariance of the observations;
+ *   X beta:                       covariates (kry_problem_set_covariates),
+ *                                 beta estimated by generalised least
+ *                                 squares; without covariates the mean is 0.
  *
  * Every device step runs in the library's own HIP kernels.  Conventions that
  * hold for every entry point:
@@ -100,7 +103,13 @@ typedef struct {
                                 lanczos_rtol times its size over the last 5
                                 steps (or at lanczos_max_steps); lanczos_steps
                                 is then unused.  0 = exactly lanczos_steps.  */
+    int32_t reml;            /* with covariates: 0 = likelihood with beta at its
+                                GLS estimate, 1 = restricted likelihood (of
+                                the error contrasts; see kry_loglik)        */
 } kry_opts;
+
+/* Largest number of covariate columns a problem takes. */
+#define KRY_MAX_COVARIATES 8
 
 typedef struct {
     double loglik;           /* l at the given sigma2                       */
@@ -113,6 +122,12 @@ typedef struct {
     int32_t lanczos_steps_used; /* max over probes                          */
     int32_t cg_iters;        /* CG iterations (or genGK steps)              */
     double cg_relres;        /* final relative residual                     */
+    /* covariates (all 0 without): */
+    int32_t ncov;            /* q, covariate columns of the problem         */
+    double beta[KRY_MAX_COVARIATES];    /* GLS estimate of beta (first q)   */
+    double beta_se[KRY_MAX_COVARIATES]; /* sqrt diag(sigma2_hat G^{-1}),
+                                           G = X^T K^{-1} X                 */
+    double logdet_xkx;       /* log det G                                   */
 } kry_loglik_result;
 
 /* ---- status, options ---------------------------------------------------- */
@@ -121,7 +136,7 @@ const char* kry_last_error(void);
 
 /* Defaults: m = 30, N = 10 Rademacher, seed 303, no reorth, FP64,
  * cg_rtol 1e-8, cg_maxit 20000, CG, gk_steps 100, no shift sharing, fixed
- * step count (lanczos_rtol 0, lanczos_max_steps 500). */
+ * step count (lanczos_rtol 0, lanczos_max_steps 500), reml 0. */
 kry_status kry_opts_default(kry_opts* out);
 
 /* ---- stage timing ----------------------------------------------------------- */
@@ -185,6 +200,15 @@ kry_status kry_problem_create(kry_ctx* ctx, const kry_grid* grid, const uint8_t*
                               const double* y, kry_problem** out);
 /* Replace the data (n1*n2 doubles, read where observed). */
 kry_status kry_problem_set_data(kry_problem* prob, const double* y);
+/* Covariates of the mean X beta (Sec. 2, eq. obs_mod): q columns of n1*n2
+ * doubles each (X is q x n1*n2, row-major), read where observed and, for
+ * kriging, at the targets; finite.  0 <= q <= KRY_MAX_COVARIATES, q < p, and
+ * the columns restricted to the observed cells must be linearly independent
+ * (KRY_EINVAL otherwise).  q = 0 (X may be NULL) restores the zero mean.
+ * With covariates the likelihoods take beta at its generalised least-squares
+ * estimate for each parameter point, kriging adds X_t beta_hat to the mean,
+ * and solves and products are unchanged. */
+kry_status kry_problem_set_covariates(kry_problem* prob, int32_t q, const double* X);
 /* Observed count p and embedding sizes N1, N2 (any pointer may be NULL). */
 kry_status kry_problem_info(const kry_problem* prob, int64_t* p, int32_t* N1, int32_t* N2);
 void kry_problem_destroy(kry_problem* prob);
@@ -256,7 +280,17 @@ kry_status kry_gengk(kry_problem* prob, const kry_matern* theta, const kry_opts*
 /* ---- likelihood, fit, kriging ------------------------------------------- */
 /* Log-likelihood of the problem's data: logdet by SLQ, Q by CG (or genGK),
  * l = -1/2 [p log(2 pi sigma2) + logdet + Q / sigma2], sigma2_hat = Q / p,
- * l_p = -1/2 [p (log 2 pi + log sigma2_hat + 1) + logdet]. */
+ * l_p = -1/2 [p (log 2 pi + log sigma2_hat + 1) + logdet].
+ *
+ * With q covariates, beta_hat = G^{-1} X^T K^{-1} y with G = X^T K^{-1} X
+ * (the beta that maximises l at the given covariance parameters) and
+ * Q = (y - X beta_hat)^T K^{-1} (y - X beta_hat).  The K^{-1} X columns are
+ * solved together with the data (q + 1 right-hand sides per point; genGK
+ * runs on the residual y - X beta_hat).  With opts->reml = 1 the restricted
+ * likelihood replaces l (m = p - q):
+ *   l = -1/2 [m log(2 pi sigma2) + logdet + log det G - log det X^T X + Q / sigma2],
+ *   sigma2_hat = Q / m,
+ *   l_p = -1/2 [m (log 2 pi + log sigma2_hat + 1) + logdet + log det G - log det X^T X]. */
 kry_status kry_loglik(kry_problem* prob, const kry_matern* theta, const kry_opts* opts,
                       kry_loglik_result* out);
 /* `count` parameter points on one problem, evaluated together: every
@@ -288,7 +322,8 @@ kry_status kry_loglik_batch(kry_problem* prob, const kry_matern* thetas, int32_t
  * stored with the group's largest observed count as stride (zero past each
  * problem's own count).  Each problem uses its own probes (the Philox
  * streams of kry_loglik with opts->seed), so out[i] matches kry_loglik on
- * probs[i] up to rounding.  Requires opts->solver = CG and shift_share = 0.
+ * probs[i] up to rounding.  Problems with covariates are evaluated one at a
+ * time, as by kry_loglik.  Requires opts->solver = CG and shift_share = 0.
  * KRY_ENOCONV as for kry_loglik_batch. */
 kry_status kry_loglik_multi(kry_problem* const* probs, const kry_matern* thetas, int32_t count,
                             const kry_opts* opts, kry_loglik_result* out);
@@ -300,7 +335,9 @@ kry_status kry_fit(kry_problem* prob, const kry_matern* init, uint32_t free_mask
                    const kry_opts* opts, double xtol, int32_t maxiter,
                    kry_matern* est, kry_loglik_result* at_est);
 /* Kriging at target cell ids (or every unobserved cell if targets == NULL):
- * mean_x = c_t^T K^{-1} y; with bootstrap_B == 0 the exact variances
+ * mean_x = c_t^T K^{-1} y (with covariates X_t beta_hat + c_t^T K^{-1}
+ * (y - X beta_hat), beta_hat as in kry_loglik, treated as known in the
+ * variances, as the bootstrap of Sec. 3.5 does); with bootstrap_B == 0 the exact variances
  * var_x = sigma2 (1 - c_t^T K^{-1} c_t), var_y = var_x + tau2 (multi-RHS
  * CG); with bootstrap_B > 0 the parametric bootstrap of Sec. 3.5
  * (eq. bootstrap_uq) with B circulant-embedding fields.  var_x, var_y are

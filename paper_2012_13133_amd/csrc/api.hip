@@ -121,6 +121,7 @@ void check_opts(const kry_opts* o) {
     if (o->lanczos_rtol > 0)
         KRY_REQUIRE(o->lanczos_max_steps >= 10 && o->lanczos_max_steps <= KRY_MAX_LANCZOS,
                     "lanczos_max_steps must be in [10, 512] in the adaptive mode");
+    KRY_REQUIRE(o->reml == 0 || o->reml == 1, "reml must be 0 or 1");
 }
 
 int nprobes_of(const kry_opts* o) {
@@ -543,6 +544,120 @@ void assemble(kry_loglik_result* r, int64_t p, double logdet, double se, double 
     r->loglik_profiled = -0.5 * ((double)p * (std::log(two_pi) + std::log(r->sigma2_hat) + 1.0) + logdet);
 }
 
+// ---- covariates: generalised least squares ---------------------------------------------
+// Small dense symmetric positive definite matrices (q <= KRY_MAX_COVARIATES),
+// row-major, on the host.  In-place lower Cholesky factor; false when a
+// pivot falls to rel_tol times its column's diagonal or below (the column is
+// numerically a combination of the earlier ones).
+bool chol_small(std::vector<double>& A, int q, double rel_tol) {
+    for (int j = 0; j < q; ++j) {
+        double d = A[j * q + j];
+        const double ajj = d;
+        for (int k = 0; k < j; ++k) d -= A[j * q + k] * A[j * q + k];
+        if (!(d > rel_tol * ajj) || !(ajj > 0)) return false;
+        const double l = std::sqrt(d);
+        A[j * q + j] = l;
+        for (int i = j + 1; i < q; ++i) {
+            double v = A[i * q + j];
+            for (int k = 0; k < j; ++k) v -= A[i * q + k] * A[j * q + k];
+            A[i * q + j] = v / l;
+        }
+    }
+    return true;
+}
+
+// x = (L L^T)^{-1} b with the factor from chol_small.
+std::vector<double> chol_solve(const std::vector<double>& L, int q, std::vector<double> b) {
+    for (int i = 0; i < q; ++i) {
+        for (int k = 0; k < i; ++k) b[i] -= L[i * q + k] * b[k];
+        b[i] /= L[i * q + i];
+    }
+    for (int i = q - 1; i >= 0; --i) {
+        for (int k = i + 1; k < q; ++k) b[i] -= L[k * q + i] * b[k];
+        b[i] /= L[i * q + i];
+    }
+    return b;
+}
+
+double chol_logdet(const std::vector<double>& L, int q) {
+    double s = 0;
+    for (int i = 0; i < q; ++i) s += 2.0 * std::log(L[i * q + i]);
+    return s;
+}
+
+// GLS pieces at one parameter point from M[a * nd + b] = D_b^T K^{-1} D_a,
+// nd = q + 1, D_0 = yc = y - X beta_ols, D_j = X_j:
+//   G = X^T K^{-1} X,  g = X^T K^{-1} yc,  delta = G^{-1} g,
+//   beta_hat = beta_ols + delta,  Q = yc^T K^{-1} yc - g^T delta
+// (the GLS residual y - X beta_hat = yc - X delta, and Q is its K^{-1} norm;
+// off-diagonal pairs are averaged, K being symmetric).
+struct Gls {
+    double Q = 0, logdet_G = 0;
+    std::vector<double> delta, beta, Ginv_diag;
+};
+
+Gls gls_combine(const Problem& P, const double* M) {
+    const int q = P.q, nd = q + 1;
+    Gls r;
+    std::vector<double> G((size_t)q * q), g(q);
+    for (int i = 0; i < q; ++i) {
+        g[i] = 0.5 * (M[0 * nd + (i + 1)] + M[(i + 1) * nd + 0]);
+        for (int j = 0; j < q; ++j) G[i * q + j] = 0.5 * (M[(i + 1) * nd + (j + 1)] + M[(j + 1) * nd + (i + 1)]);
+    }
+    KRY_REQUIRE(chol_small(G, q, 1e-13), "X^T K^{-1} X is not numerically positive definite");
+    r.logdet_G = chol_logdet(G, q);
+    r.delta = chol_solve(G, q, g);
+    double gd = 0;
+    for (int i = 0; i < q; ++i) gd += g[i] * r.delta[i];
+    r.Q = M[0] - gd;
+    r.beta.resize(q);
+    for (int i = 0; i < q; ++i) r.beta[i] = P.beta_ols[i] + r.delta[i];
+    r.Ginv_diag.resize(q);
+    for (int i = 0; i < q; ++i) {
+        std::vector<double> e(q, 0.0);
+        e[i] = 1.0;
+        r.Ginv_diag[i] = chol_solve(G, q, e)[i];
+    }
+    return r;
+}
+
+// Likelihood assembly with covariates: maximum likelihood at beta_hat
+// (assemble with the GLS Q), or the restricted likelihood (reml) of the
+// error contrasts with m = p - q:
+//   l = -1/2 [m log(2 pi sigma2) + logdet + log det G - log det X^T X + Q / sigma2],
+//   sigma2_hat = Q / m,  l_p = -1/2 [m (log 2 pi + log sigma2_hat + 1) + logdet + log det G - log det X^T X];
+// beta_se from sigma2_hat G^{-1}.
+void assemble_gls(kry_loglik_result* r, const Problem& P, double logdet, double se, const Gls& g, double sigma2,
+                  bool reml) {
+    assemble(r, P.p, logdet, se, g.Q, sigma2);
+    if (reml) {
+        const double two_pi = 6.283185307179586476925286766559;
+        const double m = (double)(P.p - P.q);
+        const double extra = logdet + g.logdet_G - P.logdet_xx;
+        r->loglik = -0.5 * (m * std::log(two_pi * sigma2) + extra + g.Q / sigma2);
+        r->sigma2_hat = g.Q / m;
+        r->loglik_profiled = -0.5 * (m * (std::log(two_pi) + std::log(r->sigma2_hat) + 1.0) + extra);
+    }
+    r->ncov = P.q;
+    for (int i = 0; i < P.q; ++i) {
+        r->beta[i] = g.beta[i];
+        r->beta_se[i] = std::sqrt(r->sigma2_hat * g.Ginv_diag[i]);
+    }
+    r->logdet_xkx = g.logdet_G;
+}
+
+// The nd = q + 1 vectors D_0 = yc, D_j = X_j (D_0 = y without covariates),
+// copied contiguously to dst (nd x p, FP64).
+void copy_rhs_set(const Problem& P, double* dst, hipStream_t st) {
+    const size_t vb = (size_t)P.p * sizeof(double);
+    if (P.q == 0) {
+        KRY_HIP(hipMemcpyAsync(dst, P.y64.ptr, vb, hipMemcpyDeviceToDevice, st));
+        return;
+    }
+    KRY_HIP(hipMemcpyAsync(dst, P.yc64.ptr, vb, hipMemcpyDeviceToDevice, st));
+    KRY_HIP(hipMemcpyAsync(dst + P.p, P.X64.ptr, (size_t)P.q * vb, hipMemcpyDeviceToDevice, st));
+}
+
 // genGK quadratic form and x_k* (Algorithm 1 with the one-product reading:
 // s_i = Sigma v_i is carried along, so each step needs one product Sigma A^T u).
 struct GkOut {
@@ -551,8 +666,10 @@ struct GkOut {
     double beta1 = 0;
 };
 
+// data64 (device, compact FP64, nullable) replaces the problem's data as b.
 template <typename R>
-void gengk_device(Problem& P, const Matern& th, const kry_opts* o, GkOut& G, double* x_full_host, hipStream_t st) {
+void gengk_device(Problem& P, const Matern& th, const kry_opts* o, GkOut& G, double* x_full_host, hipStream_t st,
+                  const double* data64 = nullptr) {
     const int k = o->gk_steps;
     const bool reorth = o->reorth != 0;
     const int64_t p = P.p, n = (int64_t)P.n1 * P.n2;
@@ -583,7 +700,8 @@ void gengk_device(Problem& P, const Matern& th, const kry_opts* o, GkOut& G, dou
     (void)u;
     const int32_t* cell = P.cell.as<int32_t>();
     // b = y (compact data in the working precision)
-    if (sizeof(R) == 8) KRY_HIP(hipMemcpyAsync(b, P.y64.ptr, p * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (data64) convert<double, R>(data64, b, p, st);
+    else if (sizeof(R) == 8) KRY_HIP(hipMemcpyAsync(b, P.y64.ptr, p * sizeof(double), hipMemcpyDeviceToDevice, st));
     else KRY_HIP(hipMemcpyAsync(b, P.y32.ptr, p * sizeof(float), hipMemcpyDeviceToDevice, st));
     auto dot = [&](const R* x, const R* y, int64_t len) {
         double h;
@@ -740,19 +858,31 @@ void loglik_points_shared(Problem& P, const kry_matern* thetas, int count, const
     std::vector<int> rep;
     const std::vector<int> grp = shift_groups(thetas, count, rep);
     const int G = (int)rep.size();
-    P.spec_multi64.ensure(C, (size_t)G * nspec * sizeof(double));
+    // Multi-shift CG runs one Krylov space per (group, right-hand side): the
+    // data and, with covariates, every covariate column (nd in all), each
+    // position holding its own copy of the group's spectrum (positions are
+    // permuted as groups finish).  The SLQ uses copy 0 of every group.
+    const int nd = 1 + P.q;
+    const bool need_ms = o->solver == KRY_SOLVER_CG || P.q > 0;
+    const int Gm = need_ms ? G * nd : G;
+    const int64_t gstride = (int64_t)(need_ms ? nd : 1) * nspec;
+    P.spec_multi64.ensure(C, (size_t)Gm * nspec * sizeof(double));
     if (fp32) P.spec_multi32.ensure(C, (size_t)G * nspec * sizeof(float));
     for (int g = 0; g < G; ++g) {
         const Matern th = to_matern(&thetas[rep[g]]);
         double lo, hi;
-        double* dst = P.spec_multi64.as<double>() + (size_t)g * nspec;
+        double* dst = P.spec_multi64.as<double>() + (size_t)g * gstride;
         spectrum_device(P, P.N1, P.N2, th, dst, &lo, &hi, st);
         spectrum_scale(dst, nspec, 1.0 / ((double)P.N1 * P.N2), false, dst,
                        fp32 ? P.spec_multi32.as<float>() + (size_t)g * nspec : nullptr, st);
+        if (need_ms)
+            for (int a = 1; a < nd; ++a)
+                KRY_HIP(hipMemcpyAsync(dst + (size_t)a * nspec, dst, nspec * sizeof(double), hipMemcpyDeviceToDevice,
+                                       st));
     }
-    // zero nugget per group, and per (point, probe) output its recurrence and shift
+    // zero nugget per position, and per (point, probe) output its recurrence and shift
     const int nout = count * np;
-    std::vector<double> eta(count), shift(nout), zeros(G, 0.0);
+    std::vector<double> eta(count), shift(nout), zeros(Gm, 0.0);
     std::vector<int> src(nout);
     for (int t = 0; t < count; ++t) {
         eta[t] = thetas[t].tau2 / thetas[t].sigma2;
@@ -762,49 +892,96 @@ void loglik_points_shared(Problem& P, const kry_matern* thetas, int count, const
         }
     }
     DevBuf& sb = P.tmp3;
-    const size_t zoff = 0, soff = ((size_t)G * 8 + 255) & ~size_t(255);
+    const size_t zoff = 0, soff = ((size_t)Gm * 8 + 255) & ~size_t(255);
     const size_t ioff = soff + (((size_t)nout * 8 + 255) & ~size_t(255));
     sb.ensure(C, ioff + (size_t)nout * 4 + 256);
     double* d_zero = reinterpret_cast<double*>(sb.as<char>() + zoff);
     double* d_shift = reinterpret_cast<double*>(sb.as<char>() + soff);
     int* d_src = reinterpret_cast<int*>(sb.as<char>() + ioff);
-    KRY_HIP(hipMemcpyAsync(d_zero, zeros.data(), G * sizeof(double), hipMemcpyHostToDevice, st));
+    KRY_HIP(hipMemcpyAsync(d_zero, zeros.data(), Gm * sizeof(double), hipMemcpyHostToDevice, st));
     KRY_HIP(hipMemcpyAsync(d_shift, shift.data(), nout * sizeof(double), hipMemcpyHostToDevice, st));
     KRY_HIP(hipMemcpyAsync(d_src, src.data(), nout * sizeof(int), hipMemcpyHostToDevice, st));
     ShiftQuad sq{nout, d_src, d_shift};
     LoglikWork W;
     if (fp32) slq_device<float>(P, o, P.spec_multi32.ptr, nspec, d_zero, G, W, nullptr, nullptr, st, &sq);
-    else slq_device<double>(P, o, P.spec_multi64.ptr, nspec, d_zero, G, W, nullptr, nullptr, st, &sq);
-    std::vector<double> Q(count, 0.0), relres(count, 0.0);
+    else slq_device<double>(P, o, P.spec_multi64.ptr, gstride, d_zero, G, W, nullptr, nullptr, st, &sq);
+    std::vector<double> Q(count, 0.0), relres(count, 0.0), M;
     std::vector<int> iters(count, 0);
-    if (o->solver == KRY_SOLVER_CG) {
+    std::vector<Gls> gls(P.q > 0 ? count : 0);
+    double* D = nullptr;  // the nd right-hand-side vectors
+    if (need_ms) {
+        if (P.q == 0) {
+            D = P.y64.as<double>();
+        } else {
+            P.tmp2.ensure(C, (size_t)nd * p * sizeof(double) + 256);
+            D = P.tmp2.as<double>();
+            copy_rhs_set(P, D, st);
+        }
+        const int S = count * nd;
         const int nblk = dot_blocks(p);
         MsCgBuffers B{};
         auto lay = [&](Arena& a) {
-            B.r = a.take<double>((size_t)G * p);
-            B.p = a.take<double>((size_t)G * p);
-            B.w = a.take<double>((size_t)G * p);
+            B.r = a.take<double>((size_t)Gm * p);
+            B.p = a.take<double>((size_t)Gm * p);
+            B.w = a.take<double>((size_t)Gm * p);
             for (double** d : {&B.rr, &B.pw, &B.alpha, &B.alpha_old, &B.beta, &B.beta_old, &B.bnorm2})
-                *d = a.take<double>(G);
-            B.rc = a.take<double>(2 * (size_t)G);
-            for (double** d : {&B.zeta, &B.zeta_old, &B.zeta_new, &B.alpha_s, &B.sigma, &B.d, &B.Q, &B.relres})
-                *d = a.take<double>(count);
-            for (int** d : {&B.active, &B.iters, &B.limit, &B.pos, &B.list}) *d = a.take<int>(count);
-            B.partial = a.take<double>(2 * (size_t)G * nblk);
+                *d = a.take<double>(Gm);
+            B.rc = a.take<double>((size_t)(1 + nd) * Gm);
+            for (double** d : {&B.zeta, &B.zeta_old, &B.zeta_new, &B.alpha_s, &B.sigma, &B.relres})
+                *d = a.take<double>(S);
+            B.d = a.take<double>((size_t)S * nd);
+            B.Q = a.take<double>((size_t)S * nd);
+            for (int** d : {&B.active, &B.iters, &B.limit, &B.pos, &B.list}) *d = a.take<int>(S);
+            B.gram = a.take<double>((size_t)nd * nd);
+            B.rhs = a.take<int>(Gm);
+            B.partial = a.take<double>((size_t)(1 + nd) * Gm * nblk);
         };
         with_arena(P, lay);
         auto A = masked_op<double>(P, P.spec_multi64.ptr, nspec, 1, d_zero);
         double* lam64 = P.spec_multi64.as<double>();
         auto swp = [&](int a, int b) { swap_vectors<double>(lam64, nspec, a, b, nspec, st); };
-        mscg_run(A, swp, p, G, grp, eta, P.y64.as<double>(), o->cg_rtol, o->cg_maxit, B, iters, relres, Q, st);
-    } else {
+        // shift entry t nd + a: point t's system with right-hand side D_a
+        std::vector<int> gos(S), rhs(Gm);
+        std::vector<double> sig(S);
+        for (int t = 0; t < count; ++t)
+            for (int a = 0; a < nd; ++a) {
+                gos[(size_t)t * nd + a] = grp[t] * nd + a;
+                sig[(size_t)t * nd + a] = eta[t];
+            }
+        for (int g = 0; g < Gm; ++g) rhs[g] = g % nd;
+        std::vector<int> it;
+        std::vector<double> rr;
+        mscg_run(A, swp, p, Gm, gos, sig, D, nd, rhs, o->cg_rtol, o->cg_maxit, B, it, rr, M, st);
+        for (int t = 0; t < count; ++t) {
+            for (int a = 0; a < nd; ++a) {
+                iters[t] = std::max(iters[t], it[(size_t)t * nd + a]);
+                relres[t] = std::max(relres[t], rr[(size_t)t * nd + a]);
+            }
+            const double* Mt = M.data() + (size_t)t * nd * nd;
+            if (P.q > 0) gls[t] = gls_combine(P, Mt);
+            Q[t] = P.q > 0 ? gls[t].Q : Mt[0];
+        }
+    }
+    if (o->solver != KRY_SOLVER_CG) {
+        double* resid = nullptr;
+        if (P.q > 0) {
+            P.tmp4.ensure(C, (size_t)p * sizeof(double) + 256);
+            resid = P.tmp4.as<double>();
+        }
         for (int t = 0; t < count; ++t) {
             GkOut Gk;
             const Matern th = to_matern(&thetas[t]);
-            if (fp32) gengk_device<float>(P, th, o, Gk, nullptr, st);
-            else gengk_device<double>(P, th, o, Gk, nullptr, st);
+            if (P.q > 0) {  // genGK on the GLS residual yc - X delta
+                KRY_HIP(hipMemcpyAsync(resid, P.yc64.ptr, p * sizeof(double), hipMemcpyDeviceToDevice, st));
+                for (int j = 0; j < P.q; ++j)
+                    axpby<double>(P.X64.as<double>() + (size_t)j * p, resid, -gls[t].delta[j], 1.0, p, 1, st);
+            }
+            if (fp32) gengk_device<float>(P, th, o, Gk, nullptr, st, resid);
+            else gengk_device<double>(P, th, o, Gk, nullptr, st, resid);
             Q[t] = Gk.J;
+            if (P.q > 0) gls[t].Q = Gk.J;
             iters[t] = o->gk_steps;
+            relres[t] = 0.0;
         }
     }
     for (int t = 0; t < count; ++t) {
@@ -812,7 +989,8 @@ void loglik_points_shared(Problem& P, const kry_matern* thetas, int count, const
         combine(W.gamma.data() + (size_t)t * np, np, o->probe_kind == KRY_PROBE_COLOURED, &est, &se);
         kry_loglik_result& r = out[t];
         std::memset(&r, 0, sizeof(r));
-        assemble(&r, p, est, se, Q[t], thetas[t].sigma2);
+        if (P.q > 0) assemble_gls(&r, P, est, se, gls[t], thetas[t].sigma2, o->reml != 0);
+        else assemble(&r, p, est, se, Q[t], thetas[t].sigma2);
         r.lanczos_steps_used = steps_used(W, t, np, grp[t] * np);
         r.cg_iters = iters[t];
         r.cg_relres = relres[t];
@@ -961,12 +1139,16 @@ void loglik_points(Problem& P, const kry_matern* thetas, int count, const kry_op
         spectrum_scale(dst, nspec, 1.0 / ((double)P.N1 * P.N2), false, dst,
                        fp32 ? P.spec_multi32.as<float>() + (size_t)t * nspec : nullptr, st);
     }
-    // eta and the data for every point live in a small device buffer
+    // eta and the right-hand sides of every point: the data and, with
+    // covariates, every covariate column (nd per point, point-major)
+    const int nd = 1 + P.q;
+    const bool need_cg = o->solver == KRY_SOLVER_CG || P.q > 0;
+    const int64_t nv = (int64_t)count * nd;
     DevBuf& etab = P.tmp1;
-    etab.ensure(C, count * sizeof(double) + (size_t)count * P.p * 2 * sizeof(double) + 512);
+    etab.ensure(C, count * sizeof(double) + (size_t)nv * P.p * 2 * sizeof(double) + 512);
     double* d_eta = etab.as<double>();
     double* Y = reinterpret_cast<double*>(etab.as<char>() + 256);
-    double* X = Y + (size_t)count * P.p;
+    double* X = Y + (size_t)nv * P.p;
     KRY_HIP(hipMemcpyAsync(d_eta, eta.data(), count * sizeof(double), hipMemcpyHostToDevice, st));
     // log-determinants
     LoglikWork W;
@@ -976,30 +1158,53 @@ void loglik_points(Problem& P, const kry_matern* thetas, int count, const kry_op
     std::vector<double> Q(count, 0.0);
     std::vector<int> iters(count, 0);
     std::vector<double> relres(count, 0.0);
-    if (o->solver == KRY_SOLVER_CG) {
-        for (int t = 0; t < count; ++t)
-            KRY_HIP(hipMemcpyAsync(Y + (size_t)t * P.p, P.y64.ptr, P.p * sizeof(double), hipMemcpyDeviceToDevice, st));
+    std::vector<Gls> gls(P.q > 0 ? count : 0);
+    if (need_cg) {
+        for (int t = 0; t < count; ++t) copy_rhs_set(P, Y + (size_t)t * nd * P.p, st);
         SolveStats ss;
-        solve_device(P, o->precision, P.spec_multi64.ptr, fp32 ? P.spec_multi32.ptr : nullptr, nspec, 1, d_eta, count,
-                     Y, X, o->cg_rtol, o->cg_maxit, ss, st);
-        // Q_t = y . x_t
-        std::vector<double> h((size_t)count * P.p);
-        double* part = nullptr;
-        P.lagtmp.ensure(C, (size_t)(count * 256 + count + 8) * sizeof(double));
-        part = P.lagtmp.as<double>();
-        dot_batched<double>(Y, P.p, X, P.p, P.p, count, part, part + count * 256, st);
-        KRY_HIP(hipMemcpyAsync(Q.data(), part + count * 256, count * sizeof(double), hipMemcpyDeviceToHost, st));
+        solve_device(P, o->precision, P.spec_multi64.ptr, fp32 ? P.spec_multi32.ptr : nullptr, nspec, nd, d_eta,
+                     (int)nv, Y, X, o->cg_rtol, o->cg_maxit, ss, st);
+        // M_t[a][b] = D_b . x_{t,a}, x_{t,a} = K_t^{-1} D_a
+        P.lagtmp.ensure(C, (size_t)(nv * 256 + nv * nd + 8) * sizeof(double));
+        double* part = P.lagtmp.as<double>();
+        double* dots = part + nv * 256;
+        for (int b = 0; b < nd; ++b) dot_batched<double>(Y + (size_t)b * P.p, 0, X, P.p, P.p, (int)nv, part,
+                                                         dots + (size_t)b * nv, st);
+        std::vector<double> h((size_t)nv * nd);
+        KRY_HIP(hipMemcpyAsync(h.data(), dots, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
         KRY_HIP(hipStreamSynchronize(st));
-        iters = ss.iters;
-        relres = ss.relres;
-    } else {
+        std::vector<double> Mt((size_t)nd * nd);
+        for (int t = 0; t < count; ++t) {
+            for (int a = 0; a < nd; ++a) {
+                const int64_t v = (int64_t)t * nd + a;
+                iters[t] = std::max(iters[t], ss.iters[v]);
+                relres[t] = std::max(relres[t], ss.relres[v]);
+                for (int b = 0; b < nd; ++b) Mt[(size_t)a * nd + b] = h[(size_t)b * nv + v];
+            }
+            if (P.q > 0) gls[t] = gls_combine(P, Mt.data());
+            Q[t] = P.q > 0 ? gls[t].Q : Mt[0];
+        }
+    }
+    if (o->solver != KRY_SOLVER_CG) {
+        double* resid = nullptr;
+        if (P.q > 0) {
+            P.tmp4.ensure(C, (size_t)P.p * sizeof(double) + 256);
+            resid = P.tmp4.as<double>();
+        }
         for (int t = 0; t < count; ++t) {
             GkOut G;
             const Matern th = to_matern(&thetas[t]);
-            if (fp32) gengk_device<float>(P, th, o, G, nullptr, st);
-            else gengk_device<double>(P, th, o, G, nullptr, st);
+            if (P.q > 0) {  // genGK on the GLS residual yc - X delta
+                KRY_HIP(hipMemcpyAsync(resid, P.yc64.ptr, P.p * sizeof(double), hipMemcpyDeviceToDevice, st));
+                for (int j = 0; j < P.q; ++j)
+                    axpby<double>(P.X64.as<double>() + (size_t)j * P.p, resid, -gls[t].delta[j], 1.0, P.p, 1, st);
+            }
+            if (fp32) gengk_device<float>(P, th, o, G, nullptr, st, resid);
+            else gengk_device<double>(P, th, o, G, nullptr, st, resid);
             Q[t] = G.J;  // unit-variance form: sigma^2 = 1 so Q = J
+            if (P.q > 0) gls[t].Q = G.J;
             iters[t] = o->gk_steps;
+            relres[t] = 0.0;
         }
     }
     for (int t = 0; t < count; ++t) {
@@ -1007,7 +1212,8 @@ void loglik_points(Problem& P, const kry_matern* thetas, int count, const kry_op
         combine(W.gamma.data() + (size_t)t * np, np, o->probe_kind == KRY_PROBE_COLOURED, &est, &se);
         kry_loglik_result& r = out[t];
         std::memset(&r, 0, sizeof(r));
-        assemble(&r, P.p, est, se, Q[t], thetas[t].sigma2);
+        if (P.q > 0) assemble_gls(&r, P, est, se, gls[t], thetas[t].sigma2, o->reml != 0);
+        else assemble(&r, P.p, est, se, Q[t], thetas[t].sigma2);
         r.lanczos_steps_used = steps_used(W, t, np, t * np);
         r.cg_iters = iters[t];
         r.cg_relres = relres[t];
@@ -1054,6 +1260,7 @@ kry_status kry_opts_default(kry_opts* out) {
         o.shift_share = 0;
         o.lanczos_max_steps = 500;
         o.lanczos_rtol = 0.0;
+        o.reml = 0;
         *out = o;
     });
 }
@@ -1145,6 +1352,47 @@ void kry_ctx_destroy(kry_ctx* ctx) {
     delete ctx;
 }
 
+// OLS centring for the GLS forms (host, FP64): from the covariates at the
+// observed cells, X^T X and its Cholesky factor, beta_ols = (X^T X)^{-1} X^T y
+// and yc = y - X beta_ols.  Removing any X b from the data leaves the GLS
+// residual unchanged; removing the OLS fit keeps Q = c - g^T G^{-1} g free of
+// the mean's magnitude.  Computes into the outputs only; throws on
+// dependent columns.
+static void ols_centre(const Problem& P, int q, const std::vector<double>& Xfull, const std::vector<double>& y,
+                       std::vector<double>& Xc, std::vector<double>& yc, std::vector<double>& beta,
+                       double& logdet_xx) {
+    const int64_t p = P.p, n = (int64_t)P.n1 * P.n2;
+    Xc.assign((size_t)q * p, 0.0);
+    for (int j = 0; j < q; ++j)
+        for (int64_t i = 0; i < p; ++i) Xc[(size_t)j * p + i] = Xfull[(size_t)j * n + (*P.h_cell)[i]];
+    std::vector<double> A((size_t)q * q, 0.0), b(q, 0.0);
+    for (int i = 0; i < q; ++i) {
+        const double* xi = Xc.data() + (size_t)i * p;
+        for (int j = 0; j <= i; ++j) {
+            const double* xj = Xc.data() + (size_t)j * p;
+            double acc = 0;
+            for (int64_t k = 0; k < p; ++k) acc += xi[k] * xj[k];
+            A[i * q + j] = A[j * q + i] = acc;
+        }
+        double acc = 0;
+        for (int64_t k = 0; k < p; ++k) acc += xi[k] * y[k];
+        b[i] = acc;
+    }
+    KRY_REQUIRE(chol_small(A, q, 1e-10), "covariate columns are linearly dependent on the observed cells");
+    logdet_xx = chol_logdet(A, q);
+    beta = chol_solve(A, q, b);
+    yc = y;
+    for (int j = 0; j < q; ++j)
+        for (int64_t k = 0; k < p; ++k) yc[k] -= Xc[(size_t)j * p + k] * beta[j];
+}
+
+static void upload_centred(Problem& P, const std::vector<double>& Xc, const std::vector<double>& yc) {
+    P.X64.ensure(*P.ctx, Xc.size() * sizeof(double));
+    P.yc64.ensure(*P.ctx, yc.size() * sizeof(double));
+    KRY_HIP(hipMemcpy(P.X64.ptr, Xc.data(), Xc.size() * sizeof(double), hipMemcpyHostToDevice));
+    KRY_HIP(hipMemcpy(P.yc64.ptr, yc.data(), yc.size() * sizeof(double), hipMemcpyHostToDevice));
+}
+
 static void upload_data(Problem& P, const double* y) {
     std::vector<double> yc(P.p, 0.0);
     if (y) {
@@ -1154,9 +1402,17 @@ static void upload_data(Problem& P, const double* y) {
             yc[i] = v;
         }
     }
+    std::vector<double> Xc, ycent, beta;
+    double ldxx = 0;
+    if (P.q > 0) ols_centre(P, P.q, *P.h_X, yc, Xc, ycent, beta, ldxx);
     std::vector<float> yf(yc.begin(), yc.end());
     KRY_HIP(hipMemcpy(P.y64.ptr, yc.data(), P.p * sizeof(double), hipMemcpyHostToDevice));
     KRY_HIP(hipMemcpy(P.y32.ptr, yf.data(), P.p * sizeof(float), hipMemcpyHostToDevice));
+    if (P.q > 0) {
+        upload_centred(P, Xc, ycent);
+        P.beta_ols = beta;
+        P.logdet_xx = ldxx;
+    }
 }
 
 kry_status kry_problem_create(kry_ctx* ctx, const kry_grid* grid, const uint8_t* mask, const double* y,
@@ -1240,6 +1496,41 @@ kry_status kry_problem_set_data(kry_problem* prob, const double* y) {
     });
 }
 
+kry_status kry_problem_set_covariates(kry_problem* prob, int32_t q, const double* X) {
+    return guard([&] {
+        KRY_REQUIRE(prob != nullptr, "prob is NULL");
+        Problem& P = prob->P;
+        KRY_REQUIRE(q >= 0 && q <= KRY_MAX_COVARIATES, "q must be in [0, KRY_MAX_COVARIATES]");
+        KRY_REQUIRE(q < P.p, "q must be below the observed count");
+        KRY_REQUIRE(q == 0 || X != nullptr, "X is NULL");
+        const int64_t n = (int64_t)P.n1 * P.n2;
+        for (int64_t i = 0; i < (int64_t)q * n; ++i) KRY_REQUIRE(std::isfinite(X[i]), "X has a non-finite value");
+        bind(*P.ctx);
+        if (q == 0) {
+            KRY_HIP(hipStreamSynchronize(P.ctx->stream));
+            P.X64.release(*P.ctx);
+            P.yc64.release(*P.ctx);
+            P.h_X.reset();
+            P.beta_ols.clear();
+            P.logdet_xx = 0;
+            P.q = 0;
+            return;
+        }
+        auto hx = std::make_shared<std::vector<double>>(X, X + (size_t)q * n);
+        std::vector<double> y(P.p);
+        KRY_HIP(hipStreamSynchronize(P.ctx->stream));
+        KRY_HIP(hipMemcpy(y.data(), P.y64.ptr, P.p * sizeof(double), hipMemcpyDeviceToHost));
+        std::vector<double> Xc, yc, beta;
+        double ldxx = 0;
+        ols_centre(P, q, *hx, y, Xc, yc, beta, ldxx);  // validates before any change
+        upload_centred(P, Xc, yc);
+        P.q = q;
+        P.h_X = hx;
+        P.beta_ols = beta;
+        P.logdet_xx = ldxx;
+    });
+}
+
 kry_status kry_problem_info(const kry_problem* prob, int64_t* p, int32_t* N1, int32_t* N2) {
     return guard([&] {
         KRY_REQUIRE(prob != nullptr, "prob is NULL");
@@ -1256,7 +1547,7 @@ void kry_problem_destroy(kry_problem* prob) {
         Ctx& c = *P.ctx;
         (void)hipSetDevice(c.device);
         (void)hipStreamSynchronize(c.stream);
-        for (DevBuf* b : {&P.bits, &P.base, &P.cell, &P.y64, &P.y32})
+        for (DevBuf* b : {&P.bits, &P.base, &P.cell, &P.y64, &P.y32, &P.X64, &P.yc64})
             b->release(c);
         P.release_work();
     }
@@ -1627,8 +1918,10 @@ kry_status kry_loglik_batch(kry_problem* prob, const kry_matern* thetas, int32_t
         hipStream_t st = P.ctx->stream;
         // points go through in chunks that bound the Krylov workspace
         const int np = nprobes_of(opts);
+        const int nd = 1 + P.q;  // right-hand sides per point (data, covariate columns)
         const size_t per_point = (size_t)np * P.p * (opts->precision == KRY_FP32 ? 4 : 8) *
-                                 (opts->reorth ? lanczos_cap(opts) + 3 : 5);
+                                     (opts->reorth ? lanczos_cap(opts) + 3 : 5) +
+                                 (size_t)nd * P.p * 8 * 8;
         // workspace per chunk: 48 GB, or half the context's budget when one is set
         size_t cap = (size_t)48e9;
         if (P.ctx->budget > 0) cap = std::min<size_t>(cap, P.ctx->budget / 2);
@@ -1639,7 +1932,7 @@ kry_status kry_loglik_batch(kry_problem* prob, const kry_matern* thetas, int32_t
             // the chunking
             std::vector<int> rep;
             const std::vector<int> grp = shift_groups(thetas, count, rep);
-            const size_t per_group = per_point + 3 * (size_t)P.p * 8, per_shift = 2 * (size_t)P.p * 8;
+            const size_t per_group = per_point + 3 * (size_t)nd * P.p * 8, per_shift = 2 * (size_t)P.p * 8;
             std::vector<std::vector<int>> members(rep.size());
             for (int t = 0; t < count; ++t) members[grp[t]].push_back(t);
             std::vector<int> idx;
@@ -1856,7 +2149,17 @@ kry_status kry_loglik_multi(kry_problem* const* probs, const kry_matern* thetas,
             groups[g].push_back(i);
         }
         std::vector<kry_loglik_result> res(count);
+        for (auto& grp : groups) {
+            // problems with covariates go one at a time
+            std::vector<int> plain;
+            for (int i : grp) {
+                if (probs[i]->P.q > 0) loglik_points(probs[i]->P, &thetas[i], 1, opts, &res[i], st);
+                else plain.push_back(i);
+            }
+            grp = plain;
+        }
         for (const auto& grp : groups) {
+            if (grp.empty()) continue;
             int64_t pm = 0;
             for (int i : grp) pm = std::max(pm, probs[i]->P.p);
             // per problem: Lanczos block and CG / refinement vectors at the padded length
@@ -2019,15 +2322,47 @@ void kry::krige_impl(Problem& P, const kry_matern* theta, const kry_opts* opts, 
     KRY_HIP(hipMemcpyAsync(d_eta, &eta, sizeof(double), hipMemcpyHostToDevice, st));
     KRY_HIP(hipMemcpyAsync(d_tg, tg.data(), nt * sizeof(int64_t), hipMemcpyHostToDevice, st));
     // mean: w = K^{-1} y, xhat = Sigma A^T w
-    SolveStats ss;
-    solve_device(P, opts->precision, S.s64.ptr, S.s32.ptr, 0, 1, d_eta, 1, P.y64.as<double>(), d_w, opts->cg_rtol,
-                 opts->cg_maxit, ss, st);
-    if (ss.relres[0] > opts->cg_rtol) *noconv = true;
+    std::vector<double> beta;
+    if (P.q == 0) {
+        SolveStats ss;
+        solve_device(P, opts->precision, S.s64.ptr, S.s32.ptr, 0, 1, d_eta, 1, P.y64.as<double>(), d_w,
+                     opts->cg_rtol, opts->cg_maxit, ss, st);
+        if (ss.relres[0] > opts->cg_rtol) *noconv = true;
+    } else {
+        // covariates: K^{-1} of the data and of every column in one solve,
+        // beta_hat by GLS, then w = K^{-1} (y - X beta_hat) = K^{-1} yc - K^{-1} X delta
+        const int nd = 1 + P.q;
+        P.tmp2.ensure(*P.ctx, ((size_t)2 * nd * p + (size_t)nd * 256 + (size_t)nd * nd + 8) * sizeof(double));
+        double* Dset = P.tmp2.as<double>();
+        double* Wset = Dset + (size_t)nd * p;
+        double* part = Wset + (size_t)nd * p;
+        double* dots = part + (size_t)nd * 256;
+        copy_rhs_set(P, Dset, st);
+        SolveStats ss;
+        solve_device(P, opts->precision, S.s64.ptr, S.s32.ptr, 0, nd, d_eta, nd, Dset, Wset, opts->cg_rtol,
+                     opts->cg_maxit, ss, st);
+        for (int v = 0; v < nd; ++v)
+            if (ss.relres[v] > opts->cg_rtol) *noconv = true;
+        for (int b = 0; b < nd; ++b) dot_batched<double>(Dset + (size_t)b * p, 0, Wset, p, p, nd, part, dots + b * nd, st);
+        std::vector<double> h((size_t)nd * nd), M((size_t)nd * nd);
+        KRY_HIP(hipMemcpyAsync(h.data(), dots, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        KRY_HIP(hipStreamSynchronize(st));
+        for (int a2 = 0; a2 < nd; ++a2)
+            for (int b = 0; b < nd; ++b) M[(size_t)a2 * nd + b] = h[(size_t)b * nd + a2];
+        const Gls g = gls_combine(P, M.data());
+        beta = g.beta;
+        KRY_HIP(hipMemcpyAsync(d_w, Wset, p * sizeof(double), hipMemcpyDeviceToDevice, st));
+        for (int j = 0; j < P.q; ++j) axpby<double>(Wset + (size_t)(j + 1) * p, d_w, -g.delta[j], 1.0, p, 1, st);
+    }
     cov_full<double>(P, S.s64.ptr, d_w, d_full, 1, st);
     hipLaunchKernelGGL(k_pick, grid1(nt), dim3(256), 0, st, d_full, d_tg, nt, d_t1);
     KRY_HIP(hipGetLastError());
     KRY_HIP(hipMemcpyAsync(mean_x, d_t1, nt * sizeof(double), hipMemcpyDeviceToHost, st));
     KRY_HIP(hipStreamSynchronize(st));
+    for (int j = 0; j < P.q; ++j) {  // + X_t beta_hat
+        const double* xj = P.h_X->data() + (size_t)j * n;
+        for (int64_t i = 0; i < nt; ++i) mean_x[i] += xj[tg[i]] * beta[j];
+    }
     if (!var_x && !var_y) return;
     if (bootstrap_B == 0) {
         // exact: multi-RHS CG on the cross-correlation columns, in chunks

@@ -32,6 +32,7 @@ namespace kry {
 // ---------------------------------------------------------------------------
 struct MaternDev {
     double range, nu, ratio, ca, sa, dx1, dx2;
+    int drange;  // 1: the derivative with respect to the range instead
 };
 
 // e^x K_nu(x) by the trapezoidal rule on the integral representation
@@ -70,12 +71,33 @@ __device__ double matern_t(double t, double nu) {
     return exp(lg) * bessel_k_scaled(nu, x);
 }
 
+// Derivative of the Matern correlation with respect to the range at scaled
+// distance t = d / range: with x = sqrt(2 nu) t, d/dx [x^nu K_nu(x)] =
+// -x^nu K_{nu-1}(x) and dx/drange = -x / range, so the derivative is
+// 2^(1-nu) / Gamma(nu) x^(nu+1) K_{nu-1}(x) / range (K of order |nu - 1|);
+// elementary forms for nu = 1/2, 3/2, 5/2.
+__device__ double matern_drange_t(double t, double nu, double range) {
+    if (t <= 0.0) return 0.0;
+    if (nu == 0.5) return t * exp(-t) / range;
+    if (nu == 1.5) {
+        const double u = 1.7320508075688772935274463415058723669 * t;
+        return u * u * exp(-u) / range;
+    }
+    if (nu == 2.5) {
+        const double u = 2.2360679774997896964091736687312762354 * t;
+        return u * u * (1.0 + u) * exp(-u) / (3.0 * range);
+    }
+    const double x = sqrt(2.0 * nu) * t;
+    const double lg = (1.0 - nu) * 0.69314718055994530941723212145817656808 - lgamma(nu) + nu * log(x) - x;
+    return exp(lg) * x * bessel_k_scaled(fabs(nu - 1.0), x) / range;
+}
+
 __device__ double corr_lag(const MaternDev& m, double h1, double h2) {
     const double dx = h2 * m.dx2, dy = h1 * m.dx1;  // column (x), row (y) displacements
     const double a = dx * m.ca + dy * m.sa;
     const double b = -dx * m.sa + dy * m.ca;
     const double d = sqrt(a * a + (m.ratio * b) * (m.ratio * b));
-    return matern_t(d / m.range, m.nu);
+    return m.drange ? matern_drange_t(d / m.range, m.nu, m.range) : matern_t(d / m.range, m.nu);
 }
 
 // c[l1][l2] at the wrapped lags; mean over both aliases on a Nyquist line.
@@ -924,9 +946,10 @@ template void conv_apply<float>(Problem&, const ConvSpec&, hipStream_t);
 // Lag grid and spectrum
 // ---------------------------------------------------------------------------
 void lag_grid_device(Ctx& c, int N1, int N2, double dx1, double dx2, const Matern& th, double* d_c,
-                     hipStream_t st) {
+                     hipStream_t st, bool drange) {
     (void)c;
     MaternDev m;
+    m.drange = drange ? 1 : 0;
     m.range = th.range;
     m.nu = th.nu;
     m.ratio = th.ratio;
@@ -978,11 +1001,11 @@ __global__ void k_minmax_final(const double* __restrict__ part, int nb, double* 
 }
 
 void spectrum_device(Problem& P, int N1, int N2, const Matern& th, double* d_lam, double* lam_min,
-                     double* lam_max, hipStream_t st) {
+                     double* lam_max, hipStream_t st, bool drange) {
     Ctx& C = *P.ctx;
     const int M = N2 / 2;
     P.lagtmp.ensure(C, (size_t)N1 * N2 * sizeof(double));
-    lag_grid_device(C, N1, N2, P.dx1, P.dx2, th, P.lagtmp.as<double>(), st);
+    lag_grid_device(C, N1, N2, P.dx1, P.dx2, th, P.lagtmp.as<double>(), st, drange);
     // stage A over every row of the lag grid, then the forward column pass
     const RowTiling ta = row_tiling<double>(M);
     const int ldY = ((N1 + ta.RT - 1) / ta.RT) * ta.RT;

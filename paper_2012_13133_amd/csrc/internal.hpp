@@ -139,6 +139,15 @@ struct Problem {
     DevBuf bits, base;           // packed mask
     DevBuf cell;                 // compact index -> cell id (int32)
     DevBuf y64, y32;             // compact data
+    // covariates of the mean X beta: q compact columns (FP64, q x p), the data
+    // with its ordinary least-squares fit removed, yc = y - X beta_ols
+    // (FP64, p), and on the host every cell's covariates (q x n1*n2),
+    // beta_ols and log det X^T X over the observed cells
+    int q = 0;
+    DevBuf X64, yc64;
+    std::shared_ptr<const std::vector<double>> h_X;
+    std::vector<double> beta_ols;
+    double logdet_xx = 0;
     std::shared_ptr<const std::vector<int64_t>> h_cell;  // compact index -> cell id (host)
     std::shared_ptr<const std::vector<uint8_t>> h_mask;
     bool is_view = false;
@@ -170,6 +179,12 @@ struct Problem {
         v.cell = cell;
         v.y64 = y64;
         v.y32 = y32;
+        v.q = q;
+        v.X64 = X64;
+        v.yc64 = yc64;
+        v.h_X = h_X;
+        v.beta_ols = beta_ols;
+        v.logdet_xx = logdet_xx;
         v.h_cell = h_cell;
         v.h_mask = h_mask;
         v.is_view = true;
@@ -225,12 +240,13 @@ struct ConvSpec {
 template <typename R>
 void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st);
 
-// Lag grid (N1 x N2 doubles) of the embedding on device.
+// Lag grid (N1 x N2 doubles, any sizes >= 1) of the embedding on device;
+// with drange the range derivative of the correlation instead.
 void lag_grid_device(Ctx& c, int N1, int N2, double dx1, double dx2, const Matern& th, double* d_c,
-                     hipStream_t st);
+                     hipStream_t st, bool drange = false);
 // Unscaled FP64 half spectrum [k2][k1] of the torus; returns min and max.
 void spectrum_device(Problem& P, int N1, int N2, const Matern& th, double* d_lam, double* lam_min,
-                     double* lam_max, hipStream_t st);
+                     double* lam_max, hipStream_t st, bool drange = false);
 // Scale a half spectrum by s into FP64 and FP32 copies; optional sqrt of
 // max(lam, 0) first (sampling).
 void spectrum_scale(const double* lam, int64_t n, double s, bool sqrt_clip, double* out64,

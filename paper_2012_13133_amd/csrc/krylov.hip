@@ -607,23 +607,29 @@ template void cg_run<float>(const MatvecFn<float>&, int64_t, int, const float*, 
 // A shift stops once |zeta_{k+1}| ||r_{k+1}|| <= rtol ||b|| (or at its
 // iteration cap); its values never depend on the other shifts or groups.
 
-__global__ void k_ms_init(const double* __restrict__ bb, int G, int S, double* __restrict__ rr,
-                          double* __restrict__ bnorm2, double* __restrict__ alpha_old, double* __restrict__ beta_old,
-                          double* __restrict__ zeta, double* __restrict__ zeta_old, double* __restrict__ d,
-                          double* __restrict__ Q, double* __restrict__ relres, int* __restrict__ active,
-                          int* __restrict__ iters, const int* __restrict__ limit) {
-    const double b2 = bb[0];
+__global__ void k_ms_init(const double* __restrict__ gram, const int* __restrict__ rhs, int nd, int G, int S,
+                          const int* __restrict__ pos, double* __restrict__ rr, double* __restrict__ bnorm2,
+                          double* __restrict__ alpha_old, double* __restrict__ beta_old, double* __restrict__ zeta,
+                          double* __restrict__ zeta_old, double* __restrict__ d, double* __restrict__ Q,
+                          double* __restrict__ relres, int* __restrict__ active, int* __restrict__ iters,
+                          const int* __restrict__ limit) {
     for (int q = threadIdx.x; q < G; q += blockDim.x) {
+        const int a = rhs[q];
+        const double b2 = gram[a * nd + a];
         rr[q] = b2;
         bnorm2[q] = b2;
         alpha_old[q] = 1.0;
         beta_old[q] = 0.0;
     }
     for (int s = threadIdx.x; s < S; s += blockDim.x) {
+        const int a = rhs[pos[s]];
+        const double b2 = gram[a * nd + a];
         zeta[s] = 1.0;
         zeta_old[s] = 1.0;
-        d[s] = b2;
-        Q[s] = 0.0;
+        for (int j = 0; j < nd; ++j) {  // p_0 = b: d_j = D_j^T b
+            d[s * nd + j] = gram[a * nd + j];
+            Q[s * nd + j] = 0.0;
+        }
         relres[s] = b2 > 0.0 ? 1.0 : 0.0;
         active[s] = b2 > 0.0 && limit[s] > 0;
         iters[s] = 0;
@@ -656,34 +662,63 @@ __global__ void k_ms_alpha(int Gact, const double* __restrict__ rr, const double
     }
 }
 
-// r_q -= alpha_q w_q; partials of r_q . r_q (rows 0..Gact-1) and b . r_q
-// (rows Gact..2 Gact-1)
+// r_q -= alpha_q w_q; partials of r_q . r_q (rows 0..Gact-1) and D_j . r_q
+// (row Gact + q nd + j)
+template <int ND>
 __global__ void __launch_bounds__(RB) k_ms_r(double* __restrict__ r, const double* __restrict__ w,
-                                             const double* __restrict__ b, const double* __restrict__ alpha,
+                                             const double* __restrict__ D, const double* __restrict__ alpha,
                                              int Gact, int64_t n, double* __restrict__ partial) {
     __shared__ double sh[RB];
     const int nblk = gridDim.x, q = blockIdx.y;
     const double a = alpha[q];
-    double acc = 0.0, accb = 0.0;
+    double acc = 0.0, accb[ND];
+#pragma unroll
+    for (int j = 0; j < ND; ++j) accb[j] = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)nblk * RB) {
         const int64_t k = q * n + i;
         const double ri = r[k] - a * w[k];
         r[k] = ri;
         acc += ri * ri;
-        accb += b[i] * ri;
+#pragma unroll
+        for (int j = 0; j < ND; ++j) accb[j] += D[j * n + i] * ri;
     }
     acc = block_sum(acc, sh);
-    accb = block_sum(accb, sh);
+#pragma unroll
+    for (int j = 0; j < ND; ++j) accb[j] = block_sum(accb[j], sh);
     if (threadIdx.x == 0) {
         partial[q * nblk + blockIdx.x] = acc;
-        partial[(Gact + q) * nblk + blockIdx.x] = accb;
+#pragma unroll
+        for (int j = 0; j < ND; ++j) partial[(Gact + q * ND + j) * nblk + blockIdx.x] = accb[j];
     }
+}
+
+template <int ND>
+void launch_ms_r(int nblk, int Gact, hipStream_t st, double* r, const double* w, const double* D,
+                 const double* alpha, int64_t n, double* partial) {
+    hipLaunchKernelGGL(k_ms_r<ND>, dim3(nblk, Gact), dim3(RB), 0, st, r, w, D, alpha, Gact, n, partial);
+}
+
+void ms_r(int nd, int nblk, int Gact, hipStream_t st, double* r, const double* w, const double* D,
+          const double* alpha, int64_t n, double* partial) {
+    switch (nd) {
+        case 1: launch_ms_r<1>(nblk, Gact, st, r, w, D, alpha, n, partial); break;
+        case 2: launch_ms_r<2>(nblk, Gact, st, r, w, D, alpha, n, partial); break;
+        case 3: launch_ms_r<3>(nblk, Gact, st, r, w, D, alpha, n, partial); break;
+        case 4: launch_ms_r<4>(nblk, Gact, st, r, w, D, alpha, n, partial); break;
+        case 5: launch_ms_r<5>(nblk, Gact, st, r, w, D, alpha, n, partial); break;
+        case 6: launch_ms_r<6>(nblk, Gact, st, r, w, D, alpha, n, partial); break;
+        case 7: launch_ms_r<7>(nblk, Gact, st, r, w, D, alpha, n, partial); break;
+        case 8: launch_ms_r<8>(nblk, Gact, st, r, w, D, alpha, n, partial); break;
+        case 9: launch_ms_r<9>(nblk, Gact, st, r, w, D, alpha, n, partial); break;
+        default: KRY_REQUIRE(false, "multi-shift CG takes 1..9 dot vectors");
+    }
+    KRY_HIP(hipGetLastError());
 }
 
 // base beta and roll of the position scalars; Q^s and d^s, beta^s, the
 // stopping test and the zeta roll of the listed shifts.  rc holds ||r_{k+1}||^2
-// (rows 0..Gact-1) and b . r_{k+1} (rows Gact..).
-__global__ void k_ms_beta(int Gact, double* __restrict__ rr, const double* __restrict__ rc,
+// (rows 0..Gact-1) and D_j . r_{k+1} (row Gact + q nd + j).
+__global__ void k_ms_beta(int Gact, int nd, double* __restrict__ rr, const double* __restrict__ rc,
                           double* __restrict__ beta, const double* __restrict__ alpha, double* __restrict__ alpha_old,
                           double* __restrict__ beta_old, const double* __restrict__ bnorm2,
                           const int* __restrict__ list, int nlist, const int* __restrict__ pos,
@@ -701,8 +736,12 @@ __global__ void k_ms_beta(int Gact, double* __restrict__ rr, const double* __res
         const double z = zeta[s], zn = zeta_new[s];
         const double ratio = zn / z;
         const double bs = b * ratio * ratio;
-        Q[s] += alpha_s[s] * d[s];
-        d[s] = zn * rc[Gact + q] + bs * d[s];
+        const double as = alpha_s[s];
+        for (int j = 0; j < nd; ++j) {
+            double& dj = d[s * nd + j];
+            Q[s * nd + j] += as * dj;
+            dj = zn * rc[Gact + q * nd + j] + bs * dj;
+        }
         const int it = iters[s] + 1;
         iters[s] = it;
         const double res = fabs(zn) * sqrt(rn);
@@ -765,13 +804,15 @@ __global__ void k_ms_swap_scalars(double* rr, double* bnorm2, double* alpha_old,
 }
 
 void mscg_run(const MatvecFn<double>& A, const std::function<void(int, int)>& swap, int64_t n, int G,
-              const std::vector<int>& group_of_shift, const std::vector<double>& sigma, const double* b, double rtol,
-              int maxit, MsCgBuffers& B, std::vector<int>& iters, std::vector<double>& relres,
-              std::vector<double>& Q, hipStream_t st) {
+              const std::vector<int>& group_of_shift, const std::vector<double>& sigma, const double* D, int nd,
+              const std::vector<int>& rhs_of_group, double rtol, int maxit, MsCgBuffers& B, std::vector<int>& iters,
+              std::vector<double>& relres, std::vector<double>& Q, hipStream_t st) {
+    KRY_REQUIRE(nd >= 1 && nd <= KRY_MS_MAX_ND && (int)rhs_of_group.size() == G, "bad multi-shift right-hand sides");
     const int S = (int)group_of_shift.size();
     const int nblk = dot_blocks(n);
     const size_t vb = (size_t)n * sizeof(double);
     for (int q = 0; q < G; ++q) {
+        const double* b = D + (size_t)rhs_of_group[q] * n;
         KRY_HIP(hipMemcpyAsync(B.r + (size_t)q * n, b, vb, hipMemcpyDeviceToDevice, st));
         KRY_HIP(hipMemcpyAsync(B.p + (size_t)q * n, b, vb, hipMemcpyDeviceToDevice, st));
     }
@@ -786,9 +827,12 @@ void mscg_run(const MatvecFn<double>& A, const std::function<void(int, int)>& sw
     KRY_HIP(hipMemcpyAsync(B.list, list.data(), S * sizeof(int), hipMemcpyHostToDevice, st));
     KRY_HIP(hipMemcpyAsync(B.limit, lim.data(), S * sizeof(int), hipMemcpyHostToDevice, st));
     KRY_HIP(hipMemcpyAsync(B.sigma, sigma.data(), S * sizeof(double), hipMemcpyHostToDevice, st));
-    dot_batched<double>(b, 0, b, 0, n, 1, B.partial, B.rc, st);
-    hipLaunchKernelGGL(k_ms_init, dim3(1), dim3(256), 0, st, B.rc, G, S, B.rr, B.bnorm2, B.alpha_old, B.beta_old,
-                       B.zeta, B.zeta_old, B.d, B.Q, B.relres, B.active, B.iters, B.limit);
+    KRY_HIP(hipMemcpyAsync(B.rhs, rhs_of_group.data(), G * sizeof(int), hipMemcpyHostToDevice, st));
+    // gram[j][a] = D_j . D_a
+    for (int j = 0; j < nd; ++j)
+        dot_batched<double>(D + (size_t)j * n, 0, D, n, n, nd, B.partial, B.gram + (size_t)j * nd, st);
+    hipLaunchKernelGGL(k_ms_init, dim3(1), dim3(256), 0, st, B.gram, B.rhs, nd, G, S, B.pos, B.rr, B.bnorm2,
+                       B.alpha_old, B.beta_old, B.zeta, B.zeta_old, B.d, B.Q, B.relres, B.active, B.iters, B.limit);
     KRY_HIP(hipGetLastError());
     int Gact = G, nlist = S;
     int64_t ublocks = (n + 255) / 256;
@@ -800,11 +844,10 @@ void mscg_run(const MatvecFn<double>& A, const std::function<void(int, int)>& sw
         hipLaunchKernelGGL(k_ms_alpha, dim3(1), dim3(256), 0, st, Gact, B.rr, B.pw, B.alpha, B.alpha_old, B.beta_old,
                            B.list, nlist, B.pos, B.sigma, B.zeta, B.zeta_old, B.zeta_new, B.alpha_s, B.active);
         KRY_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_ms_r, dim3(nblk, Gact), dim3(RB), 0, st, B.r, B.w, b, B.alpha, Gact, n, B.partial);
+        ms_r(nd, nblk, Gact, st, B.r, B.w, D, B.alpha, n, B.partial);
+        hipLaunchKernelGGL(k_reduce, dim3((1 + nd) * Gact), dim3(RB), 0, st, B.partial, nblk, B.rc, (int64_t)1);
         KRY_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_reduce, dim3(2 * Gact), dim3(RB), 0, st, B.partial, nblk, B.rc, (int64_t)1);
-        KRY_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_ms_beta, dim3(1), dim3(256), 0, st, Gact, B.rr, B.rc, B.beta, B.alpha, B.alpha_old,
+        hipLaunchKernelGGL(k_ms_beta, dim3(1), dim3(256), 0, st, Gact, nd, B.rr, B.rc, B.beta, B.alpha, B.alpha_old,
                            B.beta_old, B.bnorm2, B.list, nlist, B.pos, B.zeta, B.zeta_old, B.zeta_new, B.alpha_s, B.d,
                            B.Q, B.relres, B.active, B.iters, B.limit, rtol);
         KRY_HIP(hipGetLastError());
@@ -851,10 +894,10 @@ void mscg_run(const MatvecFn<double>& A, const std::function<void(int, int)>& sw
     }
     iters.resize(S);
     relres.resize(S);
-    Q.resize(S);
+    Q.resize((size_t)S * nd);
     KRY_HIP(hipMemcpyAsync(iters.data(), B.iters, S * sizeof(int), hipMemcpyDeviceToHost, st));
     KRY_HIP(hipMemcpyAsync(relres.data(), B.relres, S * sizeof(double), hipMemcpyDeviceToHost, st));
-    KRY_HIP(hipMemcpyAsync(Q.data(), B.Q, S * sizeof(double), hipMemcpyDeviceToHost, st));
+    KRY_HIP(hipMemcpyAsync(Q.data(), B.Q, (size_t)S * nd * sizeof(double), hipMemcpyDeviceToHost, st));
     KRY_HIP(hipStreamSynchronize(st));
 }
 

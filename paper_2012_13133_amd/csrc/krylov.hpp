@@ -39,24 +39,33 @@ struct CgBuffers {
     int* limit;  // per-vector iteration cap (device, nvec)
 };
 
-// Multi-shift CG: Q_s = b^T (A_g + sigma_s I)^{-1} b for shifts s, each tied
-// to a group g whose base operator A_g supplies the shared Krylov space; the
-// shifted solutions themselves are not formed.  Group state lives at packed
-// positions 0..G-1; a group whose shifts have all stopped is moved behind the
-// active ones so products run on active groups only.  All FP64.
+// Multi-shift CG: for shifts s, each tied to a group g whose base operator
+// A_g supplies the shared Krylov space of the group's right-hand side
+// b_g = D_{rhs(g)} (one of nd vectors D_0..D_{nd-1}),
+//   Q[s * nd + j] = D_j^T (A_g + sigma_s I)^{-1} b_g    for j < nd,
+// from scalar recurrences; the shifted solutions themselves are not formed.
+// Group state lives at packed positions 0..G-1; a group whose shifts have all
+// stopped is moved behind the active ones so products run on active groups
+// only.  All FP64.
+constexpr int KRY_MS_MAX_ND = 9;
 struct MsCgBuffers {
     double *r, *p, *w;      // G x n, by position
-    double *rr, *rc, *pw, *alpha, *alpha_old, *beta, *beta_old, *bnorm2;  // G (rc: 2 G), by position
-    double *zeta, *zeta_old, *zeta_new, *alpha_s, *sigma, *d, *Q, *relres; // S
+    double *rr, *rc, *pw, *alpha, *alpha_old, *beta, *beta_old, *bnorm2;  // G (rc: (1 + nd) G), by position
+    double *zeta, *zeta_old, *zeta_new, *alpha_s, *sigma, *relres;        // S
+    double *d, *Q;                                                        // S x nd
     int *active, *iters, *limit, *pos, *list;                             // S
-    double* partial;        // 2 G x nblk
+    double* gram;           // nd x nd
+    int* rhs;               // G
+    double* partial;        // (1 + nd) G x nblk (at least nd x nd x nblk)
 };
 // A(x, y, k, st) applies the base operators of positions 0..k-1;
 // swap(a, b) exchanges whatever the caller keeps per position (spectra).
+// D: nd (<= KRY_MS_MAX_ND) vectors of n, contiguous; rhs_of_group: index of
+// each group's right-hand side in D.
 void mscg_run(const MatvecFn<double>& A, const std::function<void(int, int)>& swap, int64_t n, int G,
-              const std::vector<int>& group_of_shift, const std::vector<double>& sigma, const double* b, double rtol,
-              int maxit, MsCgBuffers& B, std::vector<int>& iters, std::vector<double>& relres,
-              std::vector<double>& Q, hipStream_t st);
+              const std::vector<int>& group_of_shift, const std::vector<double>& sigma, const double* D, int nd,
+              const std::vector<int>& rhs_of_group, double rtol, int maxit, MsCgBuffers& B, std::vector<int>& iters,
+              std::vector<double>& relres, std::vector<double>& Q, hipStream_t st);
 // Exchange vectors a and b (each n elements) of base + k * stride.
 template <typename T>
 void swap_vectors(T* base, int64_t stride, int a, int b, int64_t n, hipStream_t st);

@@ -74,10 +74,11 @@ uint64_t footprint(const Problem& P, const kry_request& r, int count) {
         const uint64_t np = nprobes_of(&r.opts);
         const uint64_t slots = r.opts.reorth ? lanczos_cap(&r.opts) + 3 : 5;
         const uint64_t vecs = count * np;
-        return vecs * p * el * slots + std::min<uint64_t>(vecs, 64) * inter + count * nspec * 12 +
-               count * p * 8 * 6 + P.N1 * (uint64_t)P.N2 * 8;
+        const uint64_t nd = 1 + (uint64_t)P.q;  // right-hand sides per point
+        return vecs * p * el * slots + std::min<uint64_t>(vecs, 64) * inter + count * nd * nspec * 12 +
+               count * nd * p * 8 * 6 + P.N1 * (uint64_t)P.N2 * 8;
     }
-    return inter + nspec * 12 + p * 8 * 8 + n * 8 * 2 + P.N1 * (uint64_t)P.N2 * 8 +
+    return inter + nspec * 12 + p * 8 * 8 * (1 + (uint64_t)P.q) + n * 8 * 2 + P.N1 * (uint64_t)P.N2 * 8 +
            (r.variances ? std::min<uint64_t>(r.ntargets, 256) * p * 8 * 8 : 0);
 }
 
@@ -109,17 +110,18 @@ struct kry_server {
                a.colour_period == b.colour_period && a.seed == b.seed && a.reorth == b.reorth &&
                a.precision == b.precision && a.cg_rtol == b.cg_rtol && a.cg_maxit == b.cg_maxit &&
                a.solver == b.solver && a.gk_steps == b.gk_steps && a.shift_share == b.shift_share &&
-               a.lanczos_max_steps == b.lanczos_max_steps && a.lanczos_rtol == b.lanczos_rtol;
+               a.lanczos_max_steps == b.lanczos_max_steps && a.lanczos_rtol == b.lanczos_rtol && a.reml == b.reml;
     }
 
     // Likelihood requests that can run in one batch with the head h: the same
-    // problem, or (CG, no shift sharing) a problem with the same embedding,
-    // whose products then share launches through a problem table.
+    // problem, or (CG, no shift sharing, no covariates) a problem with the
+    // same embedding, whose products then share launches through a problem
+    // table.
     static bool mergeable(const kry_request& h, const kry_request& r) {
         if (r.kind != KRY_REQ_LOGLIK || !same_opts(r.opts, h.opts)) return false;
         if (r.prob == h.prob) return true;
         return h.opts.solver == KRY_SOLVER_CG && h.opts.shift_share == 0 && r.prob->P.N1 == h.prob->P.N1 &&
-               r.prob->P.N2 == h.prob->P.N2;
+               r.prob->P.N2 == h.prob->P.N2 && r.prob->P.q == 0 && h.prob->P.q == 0;
     }
 
     void run_slot(int slot) {

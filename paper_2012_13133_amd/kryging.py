@@ -43,16 +43,24 @@ class kry_opts(C.Structure):
                 ("colour_period", C.c_int32), ("seed", C.c_uint64), ("reorth", C.c_int32),
                 ("precision", C.c_int32), ("cg_rtol", C.c_double), ("cg_maxit", C.c_int32),
                 ("solver", C.c_int32), ("gk_steps", C.c_int32), ("shift_share", C.c_int32),
-                ("lanczos_max_steps", C.c_int32), ("lanczos_rtol", C.c_double)]
+                ("lanczos_max_steps", C.c_int32), ("lanczos_rtol", C.c_double), ("reml", C.c_int32)]
+
+
+KRY_MAX_COVARIATES = 8
 
 
 class kry_loglik_result(C.Structure):
     _fields_ = [("loglik", C.c_double), ("loglik_profiled", C.c_double), ("sigma2_hat", C.c_double),
                 ("logdet", C.c_double), ("logdet_se", C.c_double), ("quad", C.c_double), ("p", C.c_int64),
-                ("lanczos_steps_used", C.c_int32), ("cg_iters", C.c_int32), ("cg_relres", C.c_double)]
+                ("lanczos_steps_used", C.c_int32), ("cg_iters", C.c_int32), ("cg_relres", C.c_double),
+                ("ncov", C.c_int32), ("beta", C.c_double * KRY_MAX_COVARIATES),
+                ("beta_se", C.c_double * KRY_MAX_COVARIATES), ("logdet_xkx", C.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["beta"] = np.array(d["beta"][:self.ncov])
+        d["beta_se"] = np.array(d["beta_se"][:self.ncov])
+        return d
 
 
 class kry_tuning(C.Structure):
@@ -90,6 +98,7 @@ _SIGS = {
     "kry_profile_end": (C.c_int, [_P, _DP, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "kry_problem_create": (C.c_int, [_P, C.POINTER(kry_grid), C.POINTER(C.c_uint8), _DP, C.POINTER(_P)]),
     "kry_problem_set_data": (C.c_int, [_P, _DP]),
+    "kry_problem_set_covariates": (C.c_int, [_P, C.c_int32, _DP]),
     "kry_problem_info": (C.c_int, [_P, C.POINTER(C.c_int64), _I32P, _I32P]),
     "kry_problem_destroy": (None, [_P]),
     "kry_lag_grid": (C.c_int, [_P, C.POINTER(kry_matern), C.c_int32, C.c_int32, _DP]),
@@ -211,6 +220,18 @@ def kry_problem_create(ctx, n1, n2, mask, y=None, dx1=None, dx2=None):
 def kry_problem_set_data(prob, y):
     yy = _f64(np.asarray(y).ravel())
     _check(lib.kry_problem_set_data(prob, _dp(yy)))
+
+
+def kry_problem_set_covariates(prob, X):
+    """X: (q, n1, n2) or (q, n1*n2) covariates over every cell; q = 0 or
+    None restores the zero mean."""
+    if X is None or np.size(X) == 0:
+        _check(lib.kry_problem_set_covariates(prob, 0, None))
+        return
+    X = np.asarray(X)
+    q = X.shape[0]
+    xx = _f64(X.reshape(q, -1))
+    _check(lib.kry_problem_set_covariates(prob, q, _dp(xx)))
 
 
 def kry_problem_info(prob):

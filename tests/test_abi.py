@@ -31,7 +31,8 @@ def test_header_declares_the_boundary():
                  "kry_lanczos", "kry_logdet", "kry_gauss_quadrature", "kry_solve", "kry_gengk", "kry_lag_grid",
                  "kry_spectrum", "kry_sample", "kry_psd_torus", "kry_probes", "kry_server_create",
                  "kry_server_submit", "kry_server_poll", "kry_server_wait", "kry_server_destroy",
-                 "kry_loglik_multi", "kry_autotune", "kry_set_tuning", "kry_get_tuning", "kry_set_graphs"):
+                 "kry_loglik_multi", "kry_autotune", "kry_set_tuning", "kry_get_tuning", "kry_set_graphs",
+                 "kry_problem_set_covariates"):
         assert must in names
 
 
@@ -71,6 +72,10 @@ def test_host_side_paths_without_gpu():
     assert K.lib.kry_autotune(None, 1, 8, ctypes.byref(t)) == K.KRY_EINVAL
     res = K.kry_loglik_result()
     assert K.lib.kry_loglik_multi(None, None, 1, ctypes.byref(o), ctypes.byref(res)) == K.KRY_EINVAL
+    # covariates: NULL problem rejected; the restricted-likelihood switch is off by default
+    assert K.lib.kry_problem_set_covariates(None, 1, None) == K.KRY_EINVAL
+    assert o.reml == 0
+    assert ctypes.sizeof(K.kry_loglik_result) == 8 * 7 + 4 * 2 + 8 + 8 + 8 * 2 * K.KRY_MAX_COVARIATES + 8
 
 
 @pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="a GPU is present")
