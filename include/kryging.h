@@ -346,6 +346,71 @@ kry_status kry_krige(kry_problem* prob, const kry_matern* theta, const kry_opts*
                      const int64_t* targets, int64_t ntargets, double* mean_x, double* var_x,
                      double* var_y, int32_t bootstrap_B);
 
+/* ---- the paper's own objective (Sec. 3.1 - 3.4 and the appendix) -------------
+ * pl~(theta) of eq. prof_lik: with b = y - X beta and k = opts->gk_steps
+ * steps of Algorithm 1 (reorthogonalisation per opts->reorth),
+ *   pl~ = -(p/2) log tau2 - psi^T psi / (2 tau2) - (n/2) log sigma2
+ *         - (1/2) logdet_bccb - ||z_k||^2 / (2 sigma2),
+ * psi = b - A x_k*, x_k* and z_k of eq. xhat_est, and logdet_bccb the
+ * block-circulant approximation of Sec. 3.3 taken literally: the logs of the
+ * eigenvalues of the (2 n1 - 1) x (2 n2 - 1) block-circulant extension of
+ * Sigma at the frequencies p < n1, q < n2.  The approximate gradient of the
+ * appendix (eq. approx_grad), with lambda^2 = 1/sigma2, lambda_e^2 = 1/tau2:
+ *   d/d beta       = X^T psi / tau2
+ *   d/d lambda^2   = n sigma2 / 2 - ||z_k||^2 / 2
+ *   d/d range      = -dlogdet_bccb / 2 + (V_k z_k)^T dSigma (V_k z_k) / (2 sigma2)
+ *   d/d lambda_e^2 = p tau2 / 2 - psi^T psi / 2
+ * where dSigma is the range derivative of Sigma (applied by circulant
+ * embedding) and dlogdet_bccb = trace(D1^{-1} D2) over the same frequencies
+ * (eq. trace_approx).  The constants the paper drops (2 pi) are left out.
+ * KRY_ENOTPSD when an eigenvalue of the quadrant is not positive. */
+typedef struct {
+    double pl;               /* pl~                                          */
+    double logdet_bccb;      /* quadrant log det of Sigma                    */
+    double dlogdet_bccb;     /* its range derivative                         */
+    double psi2;             /* psi^T psi                                    */
+    double z2;               /* ||z_k||^2                                    */
+    double grad_lam2, grad_range, grad_lame2;   /* eq. approx_grad            */
+    double grad_beta[KRY_MAX_COVARIATES];       /* first ncov entries         */
+    int32_t ncov;            /* covariate columns                            */
+    int32_t gk_steps;        /* k                                            */
+} kry_plik_result;
+/* pl~ and its approximate gradient at theta and beta (q values; NULL when
+ * the problem has no covariates).  Requires tau2 > 0. */
+kry_status kry_plik(kry_problem* prob, const kry_matern* theta, const double* beta, const kry_opts* opts,
+                    kry_plik_result* out);
+/* Maximise pl~ by the trust-region method of Sec. 3.4 with the rank-one
+ * Hessian g g^T (the outer product of the approximate gradient g, in the
+ * coordinates log sigma2, log tau2, log range, beta): each step is the
+ * shortest s with g^T s = 1, cut back to the trust radius (initially
+ * delta0) along g; the radius shrinks 4-fold when the gain is under a
+ * quarter of the model's and doubles when it exceeds three quarters at the
+ * boundary; steps with a gain are taken.  Stops when ||g|| <= gtol, the
+ * radius falls below 1e-8 or after maxiter steps.  free_mask: bit 0 range,
+ * bit 1 sigma2, bit 2 tau2, bit 3 beta.  beta0: q starting values (NULL:
+ * the GLS estimate at init).  Outputs est, beta_est (q, nullable), the
+ * result at the estimate (nullable) and the steps taken (nullable).  The
+ * objective need not have an interior maximum (it grows without bound as
+ * tau2 -> 0 on small grids); the fit reports where the iteration stopped. */
+kry_status kry_plik_fit(kry_problem* prob, const kry_matern* init, const double* beta0, uint32_t free_mask,
+                        const kry_opts* opts, double delta0, double gtol, int32_t maxiter, kry_matern* est,
+                        double* beta_est, kry_plik_result* at_est, int32_t* iters);
+/* Low-rank posterior variance of the latent field at every cell (eq.
+ * bgamma_approx): with k = opts->gk_steps steps of Algorithm 1 on
+ * b = y - X beta (beta NULL: the GLS estimate; ignored without covariates),
+ * B_k^T B_k = W Theta W^T, Z = Sigma V_k W and Delta = Theta (Theta + I/sigma2)^{-1},
+ *   var_x[i] = sigma2 (1 - sum_j Z_ij^2 Delta_j),  var_y = var_x + tau2,
+ * which is exact once the Krylov space is complete and otherwise at least
+ * the exact variance.  mean_x (nullable): x_k* + X beta at every cell.
+ * Outputs n1*n2 doubles each; var_y nullable.  Requires tau2 > 0. */
+kry_status kry_posterior_variance(kry_problem* prob, const kry_matern* theta, const double* beta,
+                                  const kry_opts* opts, double* var_x, double* var_y, double* mean_x);
+/* Eigen-decomposition of the symmetric tridiagonal matrix with diagonal d
+ * (k values) and off-diagonal e (k - 1) on the host (implicit QL): theta
+ * (k, ascending) and W (k x k, column-major, column j the unit eigenvector
+ * of theta[j]).  The step the posterior variance uses for B_k^T B_k. */
+kry_status kry_tridiag_eigen(int32_t k, const double* d, const double* e, double* theta, double* W);
+
 /* ---- sampling (Sec. 3.5 fields; Sec. 3.6 embedding caveat) -------------- */
 /* Smallest torus N1 x N2 (powers of two, from the product's embedding,
  * doubling) whose spectrum satisfies min >= -1e-10 max, up to 8192.

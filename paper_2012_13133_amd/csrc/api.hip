@@ -664,6 +664,8 @@ struct GkOut {
     std::vector<double> alpha, beta, z;
     double J = 0;
     double beta1 = 0;
+    const void* V = nullptr;   // V_k, k full-grid vectors (workspace)
+    const void* Sv = nullptr;  // Sigma V_k
 };
 
 // data64 (device, compact FP64, nullable) replaces the problem's data as b.
@@ -799,6 +801,8 @@ void gengk_device(Problem& P, const Matern& th, const kry_opts* o, GkOut& G, dou
         cp[i] = (i + 1 < k) ? od[i] / den : 0.0;
         dp[i] = (rhs[i] - od[i - 1] * dp[i - 1]) / den;
     }
+    G.V = V;
+    G.Sv = Sv;
     G.z.assign(k, 0.0);
     G.z[k - 1] = dp[k - 1];
     for (int i = k - 2; i >= 0; --i) G.z[i] = dp[i] - cp[i] * G.z[i + 1];
@@ -1108,6 +1112,57 @@ bool any_not_converged(const kry_loglik_result* r, int count, const kry_opts* o)
 }  // namespace
 
 namespace kry {
+Matern to_matern_abi(const kry_matern* t) { return to_matern(t); }
+
+void gengk_run(Problem& P, const Matern& th, const kry_opts* o, GkRun& G, const double* data64, hipStream_t st) {
+    GkOut g;
+    if (o->precision == KRY_FP32) gengk_device<float>(P, th, o, g, nullptr, st, data64);
+    else gengk_device<double>(P, th, o, g, nullptr, st, data64);
+    G.alpha = g.alpha;
+    G.beta = g.beta;
+    G.z = g.z;
+    G.J = g.J;
+    G.beta1 = g.beta1;
+    G.V = g.V;
+    G.Sv = g.Sv;
+    G.real_bytes = o->precision == KRY_FP32 ? 4 : 8;
+}
+
+std::vector<double> gls_beta(Problem& P, const kry_matern* theta, const kry_opts* o, double* d_w, bool* noconv,
+                             hipStream_t st) {
+    KRY_REQUIRE(P.q > 0, "the problem has no covariates");
+    const Matern th = to_matern(theta);
+    const double eta = th.tau2 / th.sigma2;
+    Spectrum& S = problem_spectrum(P, th, st);
+    const int64_t p = P.p;
+    const int nd = 1 + P.q;
+    P.tmp2.ensure(*P.ctx, ((size_t)2 * nd * p + (size_t)nd * 256 + (size_t)nd * nd + 64) * sizeof(double));
+    double* Dset = P.tmp2.as<double>();
+    double* Wset = Dset + (size_t)nd * p;
+    double* part = Wset + (size_t)nd * p;
+    double* dots = part + (size_t)nd * 256;
+    double* d_eta = dots + (size_t)nd * nd;
+    KRY_HIP(hipMemcpyAsync(d_eta, &eta, sizeof(double), hipMemcpyHostToDevice, st));
+    copy_rhs_set(P, Dset, st);
+    SolveStats ss;
+    solve_device(P, o->precision, S.s64.ptr, S.s32.ptr, 0, nd, d_eta, nd, Dset, Wset, o->cg_rtol, o->cg_maxit, ss,
+                 st);
+    for (int v = 0; v < nd; ++v)
+        if (ss.relres[v] > o->cg_rtol && noconv) *noconv = true;
+    for (int b = 0; b < nd; ++b) dot_batched<double>(Dset + (size_t)b * p, 0, Wset, p, p, nd, part, dots + b * nd, st);
+    std::vector<double> h((size_t)nd * nd), M((size_t)nd * nd);
+    KRY_HIP(hipMemcpyAsync(h.data(), dots, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    KRY_HIP(hipStreamSynchronize(st));
+    for (int a2 = 0; a2 < nd; ++a2)
+        for (int b = 0; b < nd; ++b) M[(size_t)a2 * nd + b] = h[(size_t)b * nd + a2];
+    const Gls g = gls_combine(P, M.data());
+    if (d_w) {
+        KRY_HIP(hipMemcpyAsync(d_w, Wset, p * sizeof(double), hipMemcpyDeviceToDevice, st));
+        for (int j = 0; j < P.q; ++j) axpby<double>(Wset + (size_t)(j + 1) * p, d_w, -g.delta[j], 1.0, p, 1, st);
+    }
+    return g.beta;
+}
+
 void loglik_multi(Problem& work, const std::vector<Problem*>& probs, const kry_matern* th, const kry_opts* o,
                   kry_loglik_result* out, hipStream_t st) {
     if (o->precision == KRY_FP32) loglik_multi_group<float>(work, probs, th, o, out, st);
@@ -1346,6 +1401,7 @@ void kry_ctx_destroy(kry_ctx* ctx) {
         if (ctx->c.plan64[i]) (void)hipFree(ctx->c.plan64[i]);
         if (ctx->c.plan32[i]) (void)hipFree(ctx->c.plan32[i]);
     }
+    release_blas(ctx->c);
     dev_free(ctx->c, ctx->c.tw64, TW_N * sizeof(cpx<double>));
     dev_free(ctx->c, ctx->c.tw32, TW_N * sizeof(cpx<float>));
     if (ctx->c.stream) (void)hipStreamDestroy(ctx->c.stream);
@@ -2331,28 +2387,7 @@ void kry::krige_impl(Problem& P, const kry_matern* theta, const kry_opts* opts, 
     } else {
         // covariates: K^{-1} of the data and of every column in one solve,
         // beta_hat by GLS, then w = K^{-1} (y - X beta_hat) = K^{-1} yc - K^{-1} X delta
-        const int nd = 1 + P.q;
-        P.tmp2.ensure(*P.ctx, ((size_t)2 * nd * p + (size_t)nd * 256 + (size_t)nd * nd + 8) * sizeof(double));
-        double* Dset = P.tmp2.as<double>();
-        double* Wset = Dset + (size_t)nd * p;
-        double* part = Wset + (size_t)nd * p;
-        double* dots = part + (size_t)nd * 256;
-        copy_rhs_set(P, Dset, st);
-        SolveStats ss;
-        solve_device(P, opts->precision, S.s64.ptr, S.s32.ptr, 0, nd, d_eta, nd, Dset, Wset, opts->cg_rtol,
-                     opts->cg_maxit, ss, st);
-        for (int v = 0; v < nd; ++v)
-            if (ss.relres[v] > opts->cg_rtol) *noconv = true;
-        for (int b = 0; b < nd; ++b) dot_batched<double>(Dset + (size_t)b * p, 0, Wset, p, p, nd, part, dots + b * nd, st);
-        std::vector<double> h((size_t)nd * nd), M((size_t)nd * nd);
-        KRY_HIP(hipMemcpyAsync(h.data(), dots, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-        KRY_HIP(hipStreamSynchronize(st));
-        for (int a2 = 0; a2 < nd; ++a2)
-            for (int b = 0; b < nd; ++b) M[(size_t)a2 * nd + b] = h[(size_t)b * nd + a2];
-        const Gls g = gls_combine(P, M.data());
-        beta = g.beta;
-        KRY_HIP(hipMemcpyAsync(d_w, Wset, p * sizeof(double), hipMemcpyDeviceToDevice, st));
-        for (int j = 0; j < P.q; ++j) axpby<double>(Wset + (size_t)(j + 1) * p, d_w, -g.delta[j], 1.0, p, 1, st);
+        beta = gls_beta(P, theta, opts, d_w, noconv, st);
     }
     cov_full<double>(P, S.s64.ptr, d_w, d_full, 1, st);
     hipLaunchKernelGGL(k_pick, grid1(nt), dim3(256), 0, st, d_full, d_tg, nt, d_t1);
@@ -2568,3 +2603,160 @@ kry_status kry_fit(kry_problem* prob, const kry_matern* init, uint32_t free_mask
     });
 }
 
+
+// ---- the paper's objective, its trust-region fit and the low-rank posterior variance -----------
+static std::vector<double> start_beta(Problem& P, const kry_matern* theta, const kry_opts* opts, const double* beta,
+                                      hipStream_t st) {
+    if (P.q == 0) return {};
+    if (beta) {
+        for (int j = 0; j < P.q; ++j) KRY_REQUIRE(std::isfinite(beta[j]), "beta has a non-finite entry");
+        return std::vector<double>(beta, beta + P.q);
+    }
+    return gls_beta(P, theta, opts, nullptr, nullptr, st);
+}
+
+static void check_gk_opts(const kry_matern* theta, const kry_opts* opts) {
+    check_theta(theta);
+    check_opts(opts);
+    KRY_REQUIRE(theta->tau2 > 0, "tau2 must be > 0 for Algorithm 1");
+}
+
+kry_status kry_plik(kry_problem* prob, const kry_matern* theta, const double* beta, const kry_opts* opts,
+                    kry_plik_result* out) {
+    return guard([&] {
+        KRY_REQUIRE(prob && out, "NULL argument");
+        check_gk_opts(theta, opts);
+        Problem& P = prob->P;
+        KRY_REQUIRE(P.q == 0 || beta != nullptr, "beta is NULL but the problem has covariates");
+        bind(*P.ctx);
+        const std::vector<double> b = start_beta(P, theta, opts, beta, P.ctx->stream);
+        kry_plik_result r;
+        plik_device(P, theta, b.data(), opts, &r, P.ctx->stream);
+        *out = r;
+    });
+}
+
+kry_status kry_plik_fit(kry_problem* prob, const kry_matern* init, const double* beta0, uint32_t free_mask,
+                        const kry_opts* opts, double delta0, double gtol, int32_t maxiter, kry_matern* est,
+                        double* beta_est, kry_plik_result* at_est, int32_t* iters) {
+    return guard([&] {
+        KRY_REQUIRE(prob && est, "NULL argument");
+        check_gk_opts(init, opts);
+        KRY_REQUIRE((free_mask & 15u) != 0 && (free_mask & ~15u) == 0, "free_mask must select from bits 0..3");
+        KRY_REQUIRE(std::isfinite(delta0) && delta0 > 0, "delta0 must be > 0");
+        KRY_REQUIRE(std::isfinite(gtol) && gtol >= 0, "gtol must be >= 0");
+        KRY_REQUIRE(maxiter >= 1, "maxiter must be >= 1");
+        Problem& P = prob->P;
+        bind(*P.ctx);
+        hipStream_t st = P.ctx->stream;
+        const int q = P.q;
+        const std::vector<double> b0 = start_beta(P, init, opts, beta0, st);
+        // coordinates: log sigma2, log tau2, log range, beta
+        std::vector<double> x0 = {std::log(init->sigma2), std::log(init->tau2), std::log(init->range)};
+        x0.insert(x0.end(), b0.begin(), b0.end());
+        std::vector<int> freec;
+        if (free_mask & 2u) freec.push_back(0);
+        if (free_mask & 4u) freec.push_back(1);
+        if (free_mask & 1u) freec.push_back(2);
+        if (free_mask & 8u)
+            for (int j = 0; j < q; ++j) freec.push_back(3 + j);
+        KRY_REQUIRE(!freec.empty(), "nothing to fit (bit 3 frees beta, which the problem does not have)");
+        const int d = (int)freec.size();
+        auto full_of = [&](const std::vector<double>& xf) {
+            std::vector<double> x = x0;
+            for (int i = 0; i < d; ++i) x[freec[i]] = xf[i];
+            return x;
+        };
+        auto theta_of = [&](const std::vector<double>& x) {
+            kry_matern t = *init;
+            t.sigma2 = std::exp(x[0]);
+            t.tau2 = std::exp(x[1]);
+            t.range = std::exp(x[2]);
+            return t;
+        };
+        auto eval = [&](const std::vector<double>& xf, double& f, std::vector<double>& g, kry_plik_result& r) {
+            const std::vector<double> x = full_of(xf);
+            const kry_matern t = theta_of(x);
+            plik_device(P, &t, q ? x.data() + 3 : nullptr, opts, &r, st);
+            std::vector<double> gf = {-r.grad_lam2 / t.sigma2, -r.grad_lame2 / t.tau2, t.range * r.grad_range};
+            for (int j = 0; j < q; ++j) gf.push_back(r.grad_beta[j]);
+            g.assign(d, 0.0);
+            for (int i = 0; i < d; ++i) g[i] = gf[freec[i]];
+            f = r.pl;
+        };
+        std::vector<double> x(d);
+        for (int i = 0; i < d; ++i) x[i] = x0[freec[i]];
+        double fx;
+        std::vector<double> g;
+        kry_plik_result rx;
+        eval(x, fx, g, rx);
+        double delta = delta0;
+        int it = 0;
+        for (it = 1; it <= maxiter; ++it) {
+            double gn = 0;
+            for (double v : g) gn += v * v;
+            gn = std::sqrt(gn);
+            if (gn <= gtol) break;
+            // model gain t - t^2 / 2 in f with t = g^T s; largest at t = 1
+            std::vector<double> s(d);
+            bool boundary;
+            if (1.0 / gn <= delta) {
+                for (int i = 0; i < d; ++i) s[i] = g[i] / (gn * gn);
+                boundary = false;
+            } else {
+                for (int i = 0; i < d; ++i) s[i] = delta * g[i] / gn;
+                boundary = true;
+            }
+            double t = 0;
+            for (int i = 0; i < d; ++i) t += g[i] * s[i];
+            const double pred = t - 0.5 * t * t;
+            std::vector<double> xn(d);
+            for (int i = 0; i < d; ++i) xn[i] = x[i] + s[i];
+            double fn;
+            std::vector<double> gnew;
+            kry_plik_result rn;
+            eval(xn, fn, gnew, rn);
+            const double ratio = (pred > 0 && std::isfinite(fn)) ? (fn - fx) / pred : -1.0;
+            if (ratio < 0.25) delta *= 0.25;
+            else if (ratio > 0.75 && boundary) delta *= 2.0;
+            if (ratio > 0) {
+                x = xn;
+                fx = fn;
+                g = gnew;
+                rx = rn;
+            }
+            if (delta < 1e-8) break;
+        }
+        const std::vector<double> xf = full_of(x);
+        *est = theta_of(xf);
+        if (beta_est)
+            for (int j = 0; j < q; ++j) beta_est[j] = xf[3 + j];
+        if (at_est) *at_est = rx;
+        if (iters) *iters = std::min(it, (int)maxiter);
+    });
+}
+
+kry_status kry_posterior_variance(kry_problem* prob, const kry_matern* theta, const double* beta,
+                                  const kry_opts* opts, double* var_x, double* var_y, double* mean_x) {
+    return guard([&] {
+        KRY_REQUIRE(prob && var_x, "NULL argument");
+        check_gk_opts(theta, opts);
+        Problem& P = prob->P;
+        bind(*P.ctx);
+        const std::vector<double> b = start_beta(P, theta, opts, beta, P.ctx->stream);
+        posterior_variance_device(P, theta, b.data(), opts, var_x, var_y, mean_x, P.ctx->stream);
+    });
+}
+
+kry_status kry_tridiag_eigen(int32_t k, const double* d, const double* e, double* theta, double* W) {
+    return guard([&] {
+        KRY_REQUIRE(k >= 1 && k <= 8192, "k must be in [1, 8192]");
+        KRY_REQUIRE(d && theta && W && (k == 1 || e), "NULL argument");
+        std::vector<double> dd(d, d + k), ee(e ? e : d, e ? e + (k - 1) : d), WW;
+        for (double v : dd) KRY_REQUIRE(std::isfinite(v), "d has a non-finite entry");
+        for (double v : ee) KRY_REQUIRE(std::isfinite(v), "e has a non-finite entry");
+        tridiag_eigen(dd, ee, WW);
+        std::copy(dd.begin(), dd.end(), theta);
+        std::copy(WW.begin(), WW.end(), W);
+    });
+}

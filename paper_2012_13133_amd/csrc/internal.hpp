@@ -67,6 +67,8 @@ struct Ctx {
     bool graphs = true;  // replay captured graphs for CG iteration blocks
     std::map<std::tuple<int, int, int>, Tuning> tuning;  // (N1, N2, bytes per real) -> configuration
     std::mutex tune_mu;
+    void* blas = nullptr;    // rocBLAS handle for the dense DFT / low-rank products (lazily created)
+    std::mutex blas_mu;
     Tuning tuning_for(int N1, int N2, int real_bytes) {
         std::lock_guard<std::mutex> g(tune_mu);
         auto it = tuning.find(std::make_tuple(N1, N2, real_bytes));
@@ -269,6 +271,30 @@ void check_opts(const kry_opts* o);
 int nprobes_of(const kry_opts* o);
 // Lanczos steps the workspace must hold: lanczos_steps, or the adaptive cap.
 int lanczos_cap(const kry_opts* o);
+// One run of Algorithm 1 (k = o->gk_steps, reorthogonalisation per o) on
+// the data (or on data64, compact FP64, when given).  V_k and Sigma V_k stay
+// in the problem's Krylov workspace until its next use: k full-grid vectors
+// each, of the precision's element type.
+struct GkRun {
+    std::vector<double> alpha, beta, z;  // B_k (alpha_1..k, beta_1..k+1), z_k
+    double J = 0, beta1 = 0;
+    const void* V = nullptr;
+    const void* Sv = nullptr;
+    int real_bytes = 8;
+};
+void gengk_run(Problem& P, const Matern& th, const kry_opts* o, GkRun& G, const double* data64, hipStream_t st);
+// GLS estimate of beta at theta (the problem must have covariates); with d_w
+// (compact, FP64) also K^{-1} (y - X beta_hat).
+std::vector<double> gls_beta(Problem& P, const kry_matern* theta, const kry_opts* o, double* d_w, bool* noconv,
+                             hipStream_t st);
+Matern to_matern_abi(const kry_matern* t);
+// The paper's objective and the low-rank posterior variance (plik.hip).
+void plik_device(Problem& P, const kry_matern* theta, const double* beta, const kry_opts* o, kry_plik_result* r,
+                 hipStream_t st);
+void posterior_variance_device(Problem& P, const kry_matern* theta, const double* beta, const kry_opts* o,
+                               double* var_x, double* var_y, double* mean_x, hipStream_t st);
+void tridiag_eigen(std::vector<double>& d, std::vector<double> e, std::vector<double>& W);
+void release_blas(Ctx& C);
 
 // ---- Krylov building blocks (krylov.hip) --------------------------------------
 int dot_blocks(int64_t n);

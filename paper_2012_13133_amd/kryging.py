@@ -63,6 +63,18 @@ class kry_loglik_result(C.Structure):
         return d
 
 
+class kry_plik_result(C.Structure):
+    _fields_ = [("pl", C.c_double), ("logdet_bccb", C.c_double), ("dlogdet_bccb", C.c_double),
+                ("psi2", C.c_double), ("z2", C.c_double), ("grad_lam2", C.c_double), ("grad_range", C.c_double),
+                ("grad_lame2", C.c_double), ("grad_beta", C.c_double * KRY_MAX_COVARIATES),
+                ("ncov", C.c_int32), ("gk_steps", C.c_int32)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["grad_beta"] = np.array(d["grad_beta"][:self.ncov])
+        return d
+
+
 class kry_tuning(C.Structure):
     _fields_ = [("col_vectors", C.c_int32), ("row_tile_scale", C.c_int32), ("row_vthreads", C.c_int32),
                 ("ms", C.c_double)]
@@ -126,6 +138,12 @@ _SIGS = {
     "kry_krige": (C.c_int, [_P, C.POINTER(kry_matern), C.POINTER(kry_opts), C.POINTER(C.c_int64), C.c_int64,
                             _DP, _DP, _DP, C.c_int32]),
     "kry_psd_torus": (C.c_int, [_P, C.POINTER(kry_matern), _I32P, _I32P]),
+    "kry_plik": (C.c_int, [_P, C.POINTER(kry_matern), _DP, C.POINTER(kry_opts), C.POINTER(kry_plik_result)]),
+    "kry_plik_fit": (C.c_int, [_P, C.POINTER(kry_matern), _DP, C.c_uint32, C.POINTER(kry_opts), C.c_double,
+                               C.c_double, C.c_int32, C.POINTER(kry_matern), _DP, C.POINTER(kry_plik_result),
+                               _I32P]),
+    "kry_posterior_variance": (C.c_int, [_P, C.POINTER(kry_matern), _DP, C.POINTER(kry_opts), _DP, _DP, _DP]),
+    "kry_tridiag_eigen": (C.c_int, [C.c_int32, _DP, _DP, _DP, _DP]),
     "kry_sample": (C.c_int, [_P, C.POINTER(kry_matern), C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_int32,
                              _DP, _DP]),
     "kry_server_create": (C.c_int, [_P, C.c_int32, C.c_uint64, C.c_int32, C.c_int32, C.POINTER(_P)]),
@@ -439,6 +457,47 @@ def kry_sample(prob, th, N1, N2, seed, first_stream, count, n1, n2):
     mm = np.empty(2)
     _check(lib.kry_sample(prob, C.byref(th), N1, N2, seed, first_stream, count, _dp(out), _dp(mm)))
     return out, mm
+
+
+def _beta_arg(beta):
+    return None if beta is None else _f64(np.asarray(beta, dtype=np.float64).ravel())
+
+
+def kry_plik(prob, th, opts, beta=None):
+    r = kry_plik_result()
+    b = _beta_arg(beta)
+    _check(lib.kry_plik(prob, C.byref(th), _dp(b), C.byref(opts), C.byref(r)))
+    return r.as_dict()
+
+
+def kry_plik_fit(prob, init, opts, free_mask=7, beta0=None, delta0=0.5, gtol=1e-6, maxiter=100, q=0):
+    est = kry_matern()
+    b0 = _beta_arg(beta0)
+    be = np.empty(max(q, 1))
+    r = kry_plik_result()
+    it = C.c_int32()
+    _check(lib.kry_plik_fit(prob, C.byref(init), _dp(b0), free_mask, C.byref(opts), delta0, gtol, maxiter,
+                            C.byref(est), _dp(be), C.byref(r), C.byref(it)))
+    return est, be[:q], r.as_dict(), it.value
+
+
+def kry_posterior_variance(prob, th, opts, n, beta=None, want_mean=False):
+    vx = np.empty(n)
+    vy = np.empty(n)
+    mean = np.empty(n) if want_mean else None
+    b = _beta_arg(beta)
+    _check(lib.kry_posterior_variance(prob, C.byref(th), _dp(b), C.byref(opts), _dp(vx), _dp(vy), _dp(mean)))
+    return vx, vy, mean
+
+
+def kry_tridiag_eigen(d, e):
+    d = _f64(np.asarray(d, dtype=np.float64))
+    e = _f64(np.asarray(e, dtype=np.float64))
+    k = d.size
+    theta = np.empty(k)
+    W = np.empty(k * k)
+    _check(lib.kry_tridiag_eigen(k, _dp(d), _dp(e) if k > 1 else None, _dp(theta), _dp(W)))
+    return theta, W.reshape(k, k).T  # column j = eigenvector j
 
 
 def kry_server_create(ctx, slots=4, hbm_budget_bytes=0, max_batch=16, max_queue=4096):

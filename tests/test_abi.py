@@ -85,3 +85,26 @@ def test_context_without_device_reports_edevice():
     with pytest.raises(K.KryError) as e:
         K.kry_ctx_create()
     assert e.value.status == K.KRY_EDEVICE
+
+
+@pytest.mark.parametrize("k", [1, 2, 7, 60, 300])
+def test_host_tridiagonal_eigen_solver(k):
+    # the host step of the low-rank posterior variance, against numpy
+    _lib_path()
+    from paper_2012_13133_amd import kryging as K
+    import numpy as np
+    rng = np.random.default_rng(k)
+    d = rng.uniform(0.1, 5.0, k)
+    e = rng.uniform(-1.0, 1.0, max(k - 1, 0))
+    if k >= 7:
+        e[3] = 0.0  # a split
+        d[:3] = 1.0  # a repeated diagonal block
+        e[:2] = 0.0
+    T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+    theta, W = K.kry_tridiag_eigen(d, e)
+    ref = np.linalg.eigvalsh(T)
+    scale = np.abs(ref).max()
+    assert np.all(np.diff(theta) >= 0)
+    assert np.abs(theta - ref).max() <= 1e-13 * scale * max(1, k) ** 0.5
+    assert np.abs(W.T @ W - np.eye(k)).max() <= 1e-13 * k
+    assert np.abs(W @ np.diag(theta) @ W.T - T).max() <= 1e-13 * scale * k
