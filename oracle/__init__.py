@@ -32,6 +32,7 @@ gengk       generalized Golub-Kahan bidiagonalization (Algorithm 1), low-rank
 sampler     Cholesky and circulant-embedding Gaussian field samplers
 bootstrap   parametric bootstrap prediction variance (Sec. 3.5)
 fit         profile-likelihood maximisation over (range, nugget ratio)
+irregular   Wendland mapping of irregularly spaced observations (Sec. 2)
 plik        the paper's own profile likelihood (exact and approximate), the
             quadrant log-determinant, the approximate gradient and the
             rank-one-Hessian trust-region fit

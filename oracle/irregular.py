@@ -1,0 +1,73 @@
+"""Irregularly spaced observations (Sec. 2): the latent field lives on the
+grid and each observation is a convex combination of the grid values near
+it, y = X beta + A x + eps.
+
+Test infrastructure only (see ``oracle/__init__``).
+
+The mapping matrix (Sec. 2): with d_ij = max(|s_i1 - s*_j1| / Delta_1,
+|s_i2 - s*_j2| / Delta_2) between observation i and grid point j and the
+Wendland function w(d) = (1 - d)_+^4 (1 + 4 d),
+    A_ij = w(d_ij) / sum_k w(d_ik).
+Coordinates (reading): locations are given in grid units, (u1, u2) =
+(s1 / Delta_1, s2 / Delta_2) with grid point (row a, column b) at (a, b),
+so d_ij = max(|u_i1 - a_j|, |u_i2 - b_j|) exactly.  Everything else is the
+gridded model with A in place of the selection: K = A Sigma A^T + eta I,
+and the likelihood and kriging of ``oracle.dense`` carry over.
+"""
+import numpy as np
+from scipy.linalg import cho_factor, cho_solve
+
+from .dense import assemble, full_correlation
+
+
+def wendland(d):
+    d = np.asarray(d, dtype=np.float64)
+    t = np.clip(1.0 - d, 0.0, None)
+    return t ** 4 * (1.0 + 4.0 * d)
+
+
+def mapping_matrix(grid, locs):
+    """Dense A (p x n) by the definition: the weight of every grid point,
+    normalised per observation."""
+    n1, n2 = grid[0], grid[1]
+    locs = np.asarray(locs, dtype=np.float64).reshape(-1, 2)
+    ii, jj = np.divmod(np.arange(n1 * n2), n2)
+    d = np.maximum(np.abs(locs[:, :1] - ii[None, :]), np.abs(locs[:, 1:] - jj[None, :]))
+    W = wendland(d)
+    return W / W.sum(axis=1, keepdims=True)
+
+
+def covariance(grid, A, theta):
+    """K = A Sigma A^T + eta I (unit variance)."""
+    S = full_correlation(grid, theta)
+    return A @ S @ A.T + (theta["tau2"] / theta["sigma2"]) * np.eye(A.shape[0])
+
+
+def loglik(grid, locs, theta, y):
+    """Exact marginal log-likelihood pieces (zero mean), as ``dense.loglik``."""
+    A = mapping_matrix(grid, locs)
+    K = covariance(grid, A, theta)
+    L = np.linalg.cholesky(K)
+    logdet = 2.0 * np.sum(np.log(np.diag(L)))
+    z = np.linalg.solve(L, np.asarray(y, dtype=np.float64))
+    return assemble(A.shape[0], logdet, float(z @ z), theta["sigma2"])
+
+
+def krige_cells(grid, locs, theta, y, targets):
+    """Kriging of the latent field at grid cells (ids): with c_t = A Sigma e_t,
+        E[x_t | y] = c_t^T K^{-1} y,  var x_t = sigma2 (1 - c_t^T K^{-1} c_t),
+        var y_t = var x_t + tau2."""
+    A = mapping_matrix(grid, locs)
+    S = full_correlation(grid, theta)
+    K = A @ S @ A.T + (theta["tau2"] / theta["sigma2"]) * np.eye(A.shape[0])
+    cf = cho_factor(K, lower=True)
+    C = A @ S[:, np.asarray(targets, dtype=np.int64)]
+    mean = C.T @ cho_solve(cf, np.asarray(y, dtype=np.float64))
+    var_x = theta["sigma2"] * (1.0 - np.sum(C * cho_solve(cf, C), axis=0))
+    return mean, var_x, var_x + theta["tau2"]
+
+
+def matvec(grid, locs, theta, V):
+    """K v for the columns of V by the dense definition."""
+    A = mapping_matrix(grid, locs)
+    return covariance(grid, A, theta) @ np.asarray(V, dtype=np.float64)

@@ -89,3 +89,13 @@ def covariates(n1, n2, q, seed):
     for c in range(q):
         out[c] = fixed[c] if c < 3 else rng.standard_normal((n1, n2))
     return out
+
+
+def irregular_locations(grid, count, seed):
+    """count observation locations uniform over the grid's extent, in grid
+    units (fractional row, fractional column; grid point (a, b) at (a, b)),
+    inside [0, n1 - 1] x [0, n2 - 1] (the paper's third study: a fine field
+    thinned at random to an irregular sample)."""
+    n1, n2 = grid[0], grid[1]
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.uniform(0, n1 - 1, count), rng.uniform(0, n2 - 1, count)], axis=1)
