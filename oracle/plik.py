@@ -41,20 +41,22 @@ def _residual_data(y_obs, X_obs, beta):
     return b
 
 
-def exact_plik(grid, mask, theta, y_obs, X_obs=None, beta=None):
+def exact_plik(grid, mask, theta, y_obs, X_obs=None, beta=None, A=None):
     """eq. exact_plik, densely: x_hat of eq. act_xhat,
         x_hat = (Sigma^{-1}/sigma2 + A^T A/tau2)^{-1} A^T b / tau2,
         psi   = b - A x_hat,
         pl    = -(p/2) log tau2 - psi^T psi / (2 tau2) - (n/2) log sigma2
                 - (1/2) log det Sigma - x_hat^T Sigma^{-1} x_hat / (2 sigma2).
     Also the exact gradient of eq. anal_grad with respect to (beta,
-    lambda^2, rho, lambda_e^2), with dL = trace(Sigma^{-1} d Sigma)."""
+    lambda^2, rho, lambda_e^2), with dL = trace(Sigma^{-1} d Sigma).  A
+    given (p x n) replaces the selection of the masked cells."""
     n1, n2 = grid[0], grid[1]
     n = n1 * n2
     s2, t2 = theta["sigma2"], theta["tau2"]
     S = full_correlation(grid, theta)
-    obs, A = _selection(mask)
-    p = obs.size
+    if A is None:
+        _, A = _selection(mask)
+    p = A.shape[0]
     b = _residual_data(y_obs, X_obs, beta)
     Si = np.linalg.inv(S)
     Gam = np.linalg.inv(Si / s2 + A.T @ A / t2)
@@ -101,7 +103,7 @@ def quadrant_dlogdet(grid, theta):
     return float(np.sum(quadrant_lambdas(grid, theta, drange=True) / quadrant_lambdas(grid, theta)))
 
 
-def approx_plik(grid, mask, theta, y_obs, k, X_obs=None, beta=None, reorth=True):
+def approx_plik(grid, mask, theta, y_obs, k, X_obs=None, beta=None, reorth=True, A=None):
     """eq. prof_lik with x_k* and z_k from k steps of Algorithm 1
     (``oracle.gengk``) and the quadrant log-determinant:
         pl~ = -(p/2) log tau2 - psi*^T psi* / (2 tau2) - (n/2) log sigma2
@@ -110,13 +112,15 @@ def approx_plik(grid, mask, theta, y_obs, k, X_obs=None, beta=None, reorth=True)
         d/d beta        lambda_e^2 X^T psi*
         d/d lambda^2    n / (2 lambda^2) - ||z_k||^2 / 2
         d/d rho         -dL-hat / 2 + (lambda^2 / 2) z^T V^T dSigma V z
-        d/d lambda_e^2  p / (2 lambda_e^2) - psi*^T psi* / 2."""
+        d/d lambda_e^2  p / (2 lambda_e^2) - psi*^T psi* / 2.
+    A given (p x n) replaces the selection of the masked cells."""
     n1, n2 = grid[0], grid[1]
     n = n1 * n2
     s2, t2 = theta["sigma2"], theta["tau2"]
     S = full_correlation(grid, theta)
-    obs, A = _selection(mask)
-    p = obs.size
+    if A is None:
+        _, A = _selection(mask)
+    p = A.shape[0]
     b = _residual_data(y_obs, X_obs, beta)
     beta1, U, V, B, _, _ = gengk(A, S, b, t2, k, reorth=reorth)
     z, J = projected_solve(B, beta1, s2)

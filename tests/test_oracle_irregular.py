@@ -65,3 +65,17 @@ def test_kriging_interpolates_an_on_grid_observation_without_nugget():
     # (A Sigma A^T is poorly conditioned without a nugget: 1e-6)
     assert m[0] == pytest.approx(y[4], rel=1e-6)
     assert abs(v[0]) <= 1e-6
+
+
+def test_sparse_mapping_and_sampled_rows_match_the_dense_definition():
+    g = grid(11, 9)
+    th = theta(0.2, 1.5, sigma2=1.0, tau2=0.3, ratio=2.0, angle=0.4)
+    locs = synth.irregular_locations(g, 120, seed=12)
+    locs[7] = (10.0, 8.0)  # the far corner
+    Ad = irregular.mapping_matrix(g, locs)
+    As = irregular.mapping_sparse(g, locs).toarray()
+    np.testing.assert_allclose(As, Ad, rtol=1e-15, atol=1e-300)
+    v = synth.random_vectors(120, 1, seed=13)[0]
+    rows = np.array([0, 7, 33, 119])
+    full = irregular.matvec(g, locs, th, v[:, None])[:, 0]
+    np.testing.assert_allclose(irregular.matvec_rows(g, locs, th, v, rows), full[rows], rtol=1e-12)
