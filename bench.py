@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--multi-sides", type=str, default="64,1024")
     ap.add_argument("--multi-only", action="store_true", help="only the multi-problem form")
     ap.add_argument("--serve-only", action="store_true", help="only the served form")
+    ap.add_argument("--no-ext", action="store_true", help="skip the extension rows (irregular data, covariates, "
+                                                          "the paper's objective, posterior variance)")
+    ap.add_argument("--ext-only", action="store_true", help="only the extension rows")
     return ap.parse_args()
 
 
@@ -103,6 +106,9 @@ def main():
         return
     if args.serve_only:
         print(json.dumps({"serve": serve_bench(args, K, synth, np)}))
+        return
+    if args.ext_only:
+        print(json.dumps({"extensions": ext_bench(args, K, synth, np)}))
         return
     n = args.n
     nu, rho, eta = 1.5, 0.05, 0.2
@@ -262,6 +268,9 @@ def main():
     # ---- multi-problem form: independent grids of different sizes ----
     multi = multi_bench(args, K, synth, np) if args.multi > 0 else None
 
+    # ---- extension rows ----
+    ext = None if args.no_ext else ext_bench(args, K, synth, np)
+
     # ---- CPU oracle on a bounded sample ----
     cpu = None
     if not args.no_cpu:
@@ -311,6 +320,7 @@ def main():
     }
     out["serve"] = serve
     out["multi"] = multi
+    out["extensions"] = ext
     print(json.dumps(out))
     if P is not None:
         P.close()
@@ -479,6 +489,100 @@ def multi_bench(args, K, synth, np):
             "evals_per_s": len(hs) / t_multi, "one_at_a_time_fp32_evals_per_s": len(hs) / t_seq32,
             "plain_fp64_evals_per_s": len(hs) / t_seq64, "multi_vs_plain_fp64": t_seq64 / t_multi,
             "multi_vs_one_at_a_time_fp32": t_seq32 / t_multi, "max_rel_err_vs_fp64": err}
+
+
+def _timed(fn, reps=1):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps, r
+
+
+def ext_bench(args, K, synth, np):
+    """Extension rows, each timed once on its own workload (not part of the
+    headline step):
+    * irregular observations (the paper's third study: 40,000 locations on a
+      400 x 400 latent grid; and 734,003 locations on the 1024 x 1024 grid):
+      batched FP32 / FP64 product rates and one FP64 likelihood evaluation;
+    * covariates: a 3 x 3 (range, nugget) shift-shared FP32 batch at 1024^2
+      with an intercept (mean 44.49) against the same batch without;
+    * the paper's objective at 1024^2: one pl~ evaluation with its gradient
+      (k = 1: the quadrant log-determinant and its derivative dominate, FP64
+      DFT contractions of about 24 n^3 flops per lag grid pair; k = 50);
+    * the low-rank posterior variance at every cell of 1024^2 (k = 50)."""
+    out = {}
+    th = K.theta(sigma2=3.0, tau2=0.5, range=0.1, nu=0.5)
+    B = args.mv_batch
+    for name, n, p in (("irregular_400sq_40k", 400, 40000), ("irregular_1024sq_734k", 1024, 734003)):
+        g = (n, n, 1.0 / n, 1.0 / n)
+        locs = synth.irregular_locations(g, p, seed=61)
+        rng = np.random.default_rng(62)
+        P = K.IrregularProblem(n, n, locs, rng.standard_normal(p))
+        row = {"grid": n, "observations": p}
+        for prec, key in ((K.KRY_FP32, "fp32"), (K.KRY_FP64, "fp64")):
+            V = synth.random_vectors(p, B, seed=63, dtype=np.float32 if prec == K.KRY_FP32 else np.float64)
+            import torch
+            dv = torch.from_numpy(V).cuda()
+            do = torch.empty_like(dv)
+            st = torch.cuda.current_stream().cuda_stream
+            K.kry_matvec_device(P.h, th, prec, B, dv.data_ptr(), do.data_ptr(), st)
+            dt, _ = _timed(lambda: K.kry_matvec_device(P.h, th, prec, B, dv.data_ptr(), do.data_ptr(), st), 10)
+            row["matvecs_per_s_" + key] = B / dt
+        opts = K.kry_opts_default(lanczos_steps=30, num_probes=10, reorth=1, cg_rtol=1e-8, cg_maxit=100000)
+        K.kry_loglik(P.h, th, opts)
+        dt, r = _timed(lambda: K.kry_loglik(P.h, th, opts))
+        row["loglik_fp64_s"] = dt
+        row["loglik_cg_iters"] = r["cg_iters"]
+        log("ext %s: fp32 %.0f fp64 %.0f matvecs/s, fp64 loglik %.2f s" % (name, row["matvecs_per_s_fp32"],
+                                                                          row["matvecs_per_s_fp64"], dt))
+        out[name] = row
+        P.close()
+    # covariates and the paper's objective on the metric workload
+    n = args.n
+    mask = synth.uniform_mask(n, n, 0.3, seed=101)
+    P = K.Problem(n, n, mask)
+    th0 = K.theta(sigma2=1.0, tau2=0.2, range=0.05, nu=1.5)
+    N = K.kry_psd_torus(P.h, th0)
+    x, _ = K.kry_sample(P.h, th0, N[0], N[1], 202, 0, 1, n, n)
+    y = 44.49 + x[0] + np.sqrt(0.2) * np.random.default_rng(303).standard_normal((n, n))
+    K.kry_problem_set_data(P.h, y)
+    pts = [K.theta(sigma2=1.0, tau2=e, range=r, nu=1.5) for r in (0.02, 0.05, 0.1) for e in (0.05, 0.2, 0.8)]
+    opts = K.kry_opts_default(lanczos_steps=50, num_probes=20, reorth=1, cg_rtol=1e-8, cg_maxit=100000,
+                              precision=K.KRY_FP32, shift_share=1)
+    K.kry_problem_set_covariates(P.h, synth.covariates(n, n, 1, seed=64))
+    t_cov, rc = _timed(lambda: K.kry_loglik_batch(P.h, pts, opts))
+    K.kry_problem_set_covariates(P.h, None)
+    K.kry_problem_set_data(P.h, y - 44.49)
+    t_plain, _ = _timed(lambda: K.kry_loglik_batch(P.h, pts, opts))
+    out["covariates_1024sq_3x3"] = {"points": len(pts), "s_with_intercept": t_cov, "s_zero_mean": t_plain,
+                                    "ratio": t_cov / t_plain, "beta_hat": float(rc[4]["beta"][0]),
+                                    "beta_se": float(rc[4]["beta_se"][0])}
+    log("ext covariates: %.2f s with an intercept vs %.2f s zero mean" % (t_cov, t_plain))
+    K.kry_problem_set_data(P.h, y)
+    K.kry_problem_set_covariates(P.h, synth.covariates(n, n, 1, seed=64))
+    beta = [44.49]
+    row = {}
+    for k in (1, 50):
+        o = K.kry_opts_default(gk_steps=k, reorth=1, precision=K.KRY_FP32)
+        K.kry_plik(P.h, th0, o, beta=beta)
+        dt, r = _timed(lambda: K.kry_plik(P.h, th0, o, beta=beta))
+        row["k%d_s" % k] = dt
+    M = 2 * n - 1
+    flops = 2.0 * (2 * n) * (2 * M) * M + 4 * 2.0 * n * n * M
+    row["quadrant_flops"] = flops
+    row["quadrant_tflops_upper_bound_from_k1"] = flops / row["k1_s"] / 1e12
+    out["plik_1024sq"] = row
+    log("ext plik: k=1 %.3f s, k=50 %.3f s" % (row["k1_s"], row["k50_s"]))
+    o = K.kry_opts_default(gk_steps=50, reorth=1, precision=K.KRY_FP32)
+    K.kry_posterior_variance(P.h, th0, o, n * n, beta=beta)
+    dt, _ = _timed(lambda: K.kry_posterior_variance(P.h, th0, o, n * n, beta=beta))
+    out["posterior_variance_1024sq_k50_s"] = dt
+    log("ext posterior variance: %.3f s" % dt)
+    P.close()
+    return out
 
 
 def cpu_baseline(n, mask, th, p, budget_s=15.0):

@@ -198,7 +198,25 @@ void kry_ctx_destroy(kry_ctx* ctx);
  * smallest power of two >= max(16, 2 n - 1) per axis. */
 kry_status kry_problem_create(kry_ctx* ctx, const kry_grid* grid, const uint8_t* mask,
                               const double* y, kry_problem** out);
-/* Replace the data (n1*n2 doubles, read where observed). */
+/* A problem with irregularly spaced observations (Sec. 2): the latent field
+ * on the grid and p observations at locs (p x 2 doubles: fractional row and
+ * fractional column in grid units, grid point (a, b) at (a, b), each inside
+ * [0, n1 - 1] x [0, n2 - 1]).  Observation j is the convex combination
+ * A_ji = w(d_ji) / sum_k w(d_jk) of the grid values, with the Wendland
+ * function w(d) = (1 - d)_+^4 (1 + 4 d) and d = max(|u1 - a|, |u2 - b|) (at
+ * most the four corners of its cell; an observation on a grid point takes
+ * that value exactly).  y: p doubles (NULL = zeros).  The covariance of the
+ * observations is K = A Sigma A^T + eta I, applied as A^T, the grid product
+ * and A.  Every entry point taking a problem works on it except:
+ * kry_loglik_multi (KRY_EINVAL) and kriging with covariates (KRY_ENOTIMPL);
+ * kriging targets are grid cells (NULL = every cell, ntargets = n1*n2),
+ * kry_problem_set_data takes p values and kry_problem_set_covariates q x p
+ * values (one per observation); coloured probes colour an observation by
+ * its nearest grid cell; bootstrap noise uses the observation index. */
+kry_status kry_problem_create_irregular(kry_ctx* ctx, const kry_grid* grid, int64_t p, const double* locs,
+                                        const double* y, kry_problem** out);
+/* Replace the data (n1*n2 doubles, read where observed; p doubles for an
+ * irregular problem). */
 kry_status kry_problem_set_data(kry_problem* prob, const double* y);
 /* Covariates of the mean X beta (Sec. 2, eq. obs_mod): q columns of n1*n2
  * doubles each (X is q x n1*n2, row-major), read where observed and, for

@@ -148,6 +148,7 @@ void bind(Ctx& c) { KRY_HIP(hipSetDevice(c.device)); }
 // ---- product operators ----------------------------------------------------------------
 template <typename R>
 MatvecFn<R> masked_op(Problem& P, const void* lam, int64_t lam_tstride, int vpt, const double* d_eta) {
+    if (P.irregular) return irregular_op<R>(P, lam, lam_tstride, vpt, d_eta);
     Problem* pp = &P;
     return [pp, lam, lam_tstride, vpt, d_eta](const R* x, R* y, int nvec, hipStream_t st, const int* active) {
         Problem& Q = *pp;
@@ -188,6 +189,15 @@ void cov_full(Problem& P, const void* lam, const R* w, R* out, int nvec, hipStre
     s.in_mode = IN_COMPACT;
     s.in = w;
     s.in_vstride = P.p;
+    if (P.irregular) {  // A^T w on the grid first (FP64), then the dense product
+        const int64_t n = (int64_t)P.n1 * P.n2;
+        P.irr.ensure(*P.ctx, (size_t)nvec * n * sizeof(double) + 256);
+        irr_scatter<R, double>(P, w, P.p, nvec, P.irr.as<double>(), 1.0, nullptr, st);
+        s.in_mode = IN_DENSE;
+        s.in = P.irr.ptr;
+        s.in_vstride = n;
+        s.in_rstride = P.n2;
+    }
     s.rows_in = P.n1;
     s.row_len = P.n2;
     s.out_mode = OUT_GRID;
@@ -712,12 +722,20 @@ void gengk_device(Problem& P, const Matern& th, const kry_opts* o, GkOut& G, dou
         KRY_HIP(hipStreamSynchronize(st));
         return h;
     };
-    auto scatter = [&](const R* src, R* full, double sc) {
+    auto scatter = [&](const R* src, R* full, double sc) {  // sc A^T src
+        if (P.irregular) {
+            irr_scatter<R, R>(P, src, p, 1, full, sc, nullptr, st);
+            return;
+        }
         KRY_HIP(hipMemsetAsync(full, 0, n * sizeof(R), st));
         hipLaunchKernelGGL(k_scatter<R>, grid1(p), dim3(256), 0, st, src, cell, p, full, sc);
         KRY_HIP(hipGetLastError());
     };
-    auto gather = [&](const R* full, R* out) {
+    auto gather = [&](const R* full, R* out) {  // A full
+        if (P.irregular) {
+            irr_gather<R, R>(P, full, 1, out, nullptr, nullptr, 1, nullptr, st);
+            return;
+        }
         hipLaunchKernelGGL(k_gather<R>, grid1(p), dim3(256), 0, st, full, cell, p, n, out);
         KRY_HIP(hipGetLastError());
     };
@@ -1420,7 +1438,8 @@ static void ols_centre(const Problem& P, int q, const std::vector<double>& Xfull
     const int64_t p = P.p, n = (int64_t)P.n1 * P.n2;
     Xc.assign((size_t)q * p, 0.0);
     for (int j = 0; j < q; ++j)
-        for (int64_t i = 0; i < p; ++i) Xc[(size_t)j * p + i] = Xfull[(size_t)j * n + (*P.h_cell)[i]];
+        for (int64_t i = 0; i < p; ++i)  // irregular problems take the covariates per observation
+            Xc[(size_t)j * p + i] = P.irregular ? Xfull[(size_t)j * p + i] : Xfull[(size_t)j * n + (*P.h_cell)[i]];
     std::vector<double> A((size_t)q * q, 0.0), b(q, 0.0);
     for (int i = 0; i < q; ++i) {
         const double* xi = Xc.data() + (size_t)i * p;
@@ -1453,7 +1472,7 @@ static void upload_data(Problem& P, const double* y) {
     std::vector<double> yc(P.p, 0.0);
     if (y) {
         for (int64_t i = 0; i < P.p; ++i) {
-            const double v = y[(*P.h_cell)[i]];
+            const double v = P.irregular ? y[i] : y[(*P.h_cell)[i]];
             KRY_REQUIRE(std::isfinite(v), "y has a non-finite value at an observed cell");
             yc[i] = v;
         }
@@ -1546,9 +1565,108 @@ kry_status kry_problem_set_data(kry_problem* prob, const double* y) {
         KRY_REQUIRE(prob && y, "NULL argument");
         Problem& P = prob->P;
         for (int64_t i = 0; i < P.p; ++i)
-            KRY_REQUIRE(std::isfinite(y[(*P.h_cell)[i]]), "y has a non-finite value at an observed cell");
+            KRY_REQUIRE(std::isfinite(P.irregular ? y[i] : y[(*P.h_cell)[i]]),
+                        "y has a non-finite value at an observed cell");
         bind(*P.ctx);
         upload_data(P, y);
+    });
+}
+
+kry_status kry_problem_create_irregular(kry_ctx* ctx, const kry_grid* grid, int64_t p, const double* locs,
+                                        const double* y, kry_problem** out) {
+    return guard([&] {
+        KRY_REQUIRE(ctx && grid && locs && out, "NULL argument");
+        KRY_REQUIRE(grid->n1 >= 2 && grid->n2 >= 2 && grid->n1 <= 4096 && grid->n2 <= 4096,
+                    "grid sides must be in [2, 4096]");
+        KRY_REQUIRE(std::isfinite(grid->dx1) && std::isfinite(grid->dx2) && grid->dx1 > 0 && grid->dx2 > 0,
+                    "grid spacings must be finite and > 0");
+        KRY_REQUIRE(p >= 1 && p <= ((int64_t)1 << 30), "p must be in [1, 2^30]");
+        const int n1 = grid->n1, n2 = grid->n2;
+        const int64_t n = (int64_t)n1 * n2;
+        for (int64_t i = 0; i < p; ++i) {
+            const double u1 = locs[2 * i], u2 = locs[2 * i + 1];
+            KRY_REQUIRE(std::isfinite(u1) && std::isfinite(u2) && u1 >= 0 && u2 >= 0 && u1 <= n1 - 1 && u2 <= n2 - 1,
+                        "observation locations must lie in [0, n1 - 1] x [0, n2 - 1] (grid units)");
+            if (y) KRY_REQUIRE(std::isfinite(y[i]), "y has a non-finite value");
+        }
+        // A: the Wendland weights of the corners of each observation's cell
+        // (Sec. 2), normalised; A^T by rows over the cells
+        std::vector<int32_t> cell4((size_t)4 * p, -1), near(p);
+        std::vector<double> w4((size_t)4 * p, 0.0);
+        std::vector<int32_t> cnt(n + 1, 0);
+        auto hc = std::make_shared<std::vector<int64_t>>(p);
+        for (int64_t i = 0; i < p; ++i) {
+            const double u1 = locs[2 * i], u2 = locs[2 * i + 1];
+            const int a0 = std::min((int)std::floor(u1), n1 - 1), b0 = std::min((int)std::floor(u2), n2 - 1);
+            double sum = 0;
+            int s = 0;
+            for (int da = 0; da < 2; ++da)
+                for (int db = 0; db < 2; ++db) {
+                    const int a = a0 + da, b = b0 + db;
+                    if (a >= n1 || b >= n2) continue;
+                    const double d = std::max(std::fabs(u1 - a), std::fabs(u2 - b));
+                    if (!(d < 1.0)) continue;
+                    const double t = 1.0 - d;
+                    const double wv = t * t * t * t * (1.0 + 4.0 * d);
+                    cell4[4 * i + s] = a * n2 + b;
+                    w4[4 * i + s] = wv;
+                    sum += wv;
+                    ++s;
+                }
+            KRY_REQUIRE(s > 0 && sum > 0, "an observation has no grid neighbour");
+            for (int k = 0; k < s; ++k) {
+                w4[4 * i + k] /= sum;
+                ++cnt[cell4[4 * i + k] + 1];
+            }
+            const int ra = std::min((int)std::lround(u1), n1 - 1), rb = std::min((int)std::lround(u2), n2 - 1);
+            near[i] = ra * n2 + rb;
+            (*hc)[i] = near[i];
+        }
+        for (int64_t c = 0; c < n; ++c) cnt[c + 1] += cnt[c];
+        const int64_t nnz = cnt[n];
+        std::vector<int32_t> at_obs(std::max<int64_t>(nnz, 1)), fill(cnt.begin(), cnt.end() - 1);
+        std::vector<double> at_w(std::max<int64_t>(nnz, 1));
+        for (int64_t i = 0; i < p; ++i)  // increasing observation id within every cell
+            for (int k = 0; k < 4; ++k) {
+                const int c = cell4[4 * i + k];
+                if (c < 0) continue;
+                at_obs[fill[c]] = (int32_t)i;
+                at_w[fill[c]] = w4[4 * i + k];
+                ++fill[c];
+            }
+        bind(ctx->c);
+        auto* kp = new kry_problem();
+        Problem& P = kp->P;
+        try {
+            P.ctx = &ctx->c;
+            P.n1 = n1;
+            P.n2 = n2;
+            P.dx1 = grid->dx1;
+            P.dx2 = grid->dx2;
+            P.N1 = pow2_at_least(2 * n1 - 1);
+            P.N2 = pow2_at_least(2 * n2 - 1);
+            P.p = p;
+            P.irregular = true;
+            P.h_cell = hc;
+            P.h_mask = std::make_shared<std::vector<uint8_t>>(n, 0);
+            auto up = [&](DevBuf& b, const void* src, size_t bytes) {
+                b.ensure(ctx->c, bytes);
+                KRY_HIP(hipMemcpy(b.ptr, src, bytes, hipMemcpyHostToDevice));
+            };
+            up(P.cell, near.data(), p * sizeof(int32_t));
+            up(P.a_cell, cell4.data(), cell4.size() * sizeof(int32_t));
+            up(P.a_w, w4.data(), w4.size() * sizeof(double));
+            up(P.at_off, cnt.data(), cnt.size() * sizeof(int32_t));
+            up(P.at_obs, at_obs.data(), at_obs.size() * sizeof(int32_t));
+            up(P.at_w, at_w.data(), at_w.size() * sizeof(double));
+            P.y64.ensure(ctx->c, p * sizeof(double));
+            P.y32.ensure(ctx->c, p * sizeof(float));
+            upload_data(P, y);
+        } catch (...) {
+            kry_problem_destroy(kp);
+            throw;
+        }
+        *out = kp;
     });
 }
 
@@ -1559,7 +1677,7 @@ kry_status kry_problem_set_covariates(kry_problem* prob, int32_t q, const double
         KRY_REQUIRE(q >= 0 && q <= KRY_MAX_COVARIATES, "q must be in [0, KRY_MAX_COVARIATES]");
         KRY_REQUIRE(q < P.p, "q must be below the observed count");
         KRY_REQUIRE(q == 0 || X != nullptr, "X is NULL");
-        const int64_t n = (int64_t)P.n1 * P.n2;
+        const int64_t n = P.irregular ? P.p : (int64_t)P.n1 * P.n2;  // values per column
         for (int64_t i = 0; i < (int64_t)q * n; ++i) KRY_REQUIRE(std::isfinite(X[i]), "X has a non-finite value");
         bind(*P.ctx);
         if (q == 0) {
@@ -1603,7 +1721,8 @@ void kry_problem_destroy(kry_problem* prob) {
         Ctx& c = *P.ctx;
         (void)hipSetDevice(c.device);
         (void)hipStreamSynchronize(c.stream);
-        for (DevBuf* b : {&P.bits, &P.base, &P.cell, &P.y64, &P.y32, &P.X64, &P.yc64})
+        for (DevBuf* b : {&P.bits, &P.base, &P.cell, &P.y64, &P.y32, &P.X64, &P.yc64, &P.a_cell, &P.a_w, &P.at_off,
+                          &P.at_obs, &P.at_w})
             b->release(c);
         P.release_work();
     }
@@ -2182,6 +2301,7 @@ kry_status kry_loglik_multi(kry_problem* const* probs, const kry_matern* thetas,
         for (int i = 0; i < count; ++i) {
             KRY_REQUIRE(probs[i] != nullptr, "NULL problem");
             KRY_REQUIRE(probs[i]->P.ctx == probs[0]->P.ctx, "problems of one call must share a context");
+            KRY_REQUIRE(!probs[i]->P.irregular, "kry_loglik_multi takes gridded problems");
             check_theta(&thetas[i]);
         }
         Ctx& C = *probs[0]->P.ctx;
@@ -2385,6 +2505,7 @@ void kry::krige_impl(Problem& P, const kry_matern* theta, const kry_opts* opts, 
                      opts->cg_rtol, opts->cg_maxit, ss, st);
         if (ss.relres[0] > opts->cg_rtol) *noconv = true;
     } else {
+        if (P.irregular) throw Error(KRY_ENOTIMPL, "kriging with covariates needs them at the grid cells, which an irregular problem does not hold");
         // covariates: K^{-1} of the data and of every column in one solve,
         // beta_hat by GLS, then w = K^{-1} (y - X beta_hat) = K^{-1} yc - K^{-1} X delta
         beta = gls_beta(P, theta, opts, d_w, noconv, st);
@@ -2413,9 +2534,13 @@ void kry::krige_impl(Problem& P, const kry_matern* theta, const kry_opts* opts, 
         std::vector<double> q(chunk);
         for (int64_t t0 = 0; t0 < nt; t0 += chunk) {
             const int c = (int)std::min<int64_t>(chunk, nt - t0);
-            hipLaunchKernelGGL(k_cross_corr, grid1(p, c), dim3(256), 0, st, P.lagtmp.as<double>(), P.N1, P.N2,
-                               P.cell.as<int32_t>(), p, P.n2, d_tg + t0, Cc);
-            KRY_HIP(hipGetLastError());
+            if (P.irregular) {
+                irr_cross_corr(P, P.lagtmp.as<double>(), d_tg + t0, c, Cc, st);
+            } else {
+                hipLaunchKernelGGL(k_cross_corr, grid1(p, c), dim3(256), 0, st, P.lagtmp.as<double>(), P.N1, P.N2,
+                                   P.cell.as<int32_t>(), p, P.n2, d_tg + t0, Cc);
+                KRY_HIP(hipGetLastError());
+            }
             SolveStats s2;
             solve_device(P, opts->precision, S.s64.ptr, S.s32.ptr, 0, c, d_eta, c, Cc, Wc, opts->cg_rtol,
                          opts->cg_maxit, s2, st);
@@ -2444,8 +2569,13 @@ void kry::krige_impl(Problem& P, const kry_matern* theta, const kry_opts* opts, 
     double* WB = YB + (size_t)B * p;
     double lo, hi;
     sample_fields(P, th, N1s, N2s, opts->seed, 0, B, F, &lo, &hi, st);
-    hipLaunchKernelGGL(k_boot_obs, grid1(p, B), dim3(256), 0, st, F, n, P.cell.as<int32_t>(), p, tau, opts->seed, YB);
-    KRY_HIP(hipGetLastError());
+    if (P.irregular) {
+        irr_boot_obs(P, F, B, tau, opts->seed, YB, st);
+    } else {
+        hipLaunchKernelGGL(k_boot_obs, grid1(p, B), dim3(256), 0, st, F, n, P.cell.as<int32_t>(), p, tau, opts->seed,
+                           YB);
+        KRY_HIP(hipGetLastError());
+    }
     SolveStats s3;
     solve_device(P, opts->precision, S.s64.ptr, S.s32.ptr, 0, B, d_eta, B, YB, WB, opts->cg_rtol, opts->cg_maxit, s3,
                  st);
@@ -2475,6 +2605,10 @@ kry_status kry_krige(kry_problem* prob, const kry_matern* theta, const kry_opts*
             KRY_REQUIRE(ntargets >= 1, "ntargets must be >= 1");
             tg.assign(targets, targets + ntargets);
             for (int64_t t : tg) KRY_REQUIRE(t >= 0 && t < n, "target cell id out of range");
+        } else if (P.irregular) {  // every grid cell
+            tg.resize(n);
+            for (int64_t c = 0; c < n; ++c) tg[c] = c;
+            KRY_REQUIRE(ntargets == n, "ntargets must equal the number of grid cells");
         } else {
             for (int64_t c = 0; c < n; ++c)
                 if (!(*P.h_mask)[c]) tg.push_back(c);

@@ -893,6 +893,8 @@ void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st) {
                 "block larger than the torus");
     KRY_REQUIRE(s.in_mode != IN_COMPACT || 2 * s.row_len <= s.N2, "compact input wider than half the torus");
     KRY_REQUIRE(!s.tab || (s.in_mode == IN_COMPACT && s.tab_vpp >= 1), "problem tables take compact inputs");
+    KRY_REQUIRE(!P.irregular || (s.in_mode != IN_COMPACT && s.out_mode != OUT_COMPACT),
+                "irregular problems have no observation mask");
     if (s.nvec <= 0) return;
     const int M = s.N2 / 2;
     // launch configuration of this embedding and precision (bit-identical results)

@@ -150,6 +150,12 @@ struct Problem {
     std::shared_ptr<const std::vector<double>> h_X;
     std::vector<double> beta_ols;
     double logdet_xx = 0;
+    // irregularly spaced observations: A as four (cell, weight) slots per
+    // observation (cell -1 = unused) and A^T as rows over the grid cells
+    // (offsets n + 1, observation ids, weights); cell / h_cell then hold
+    // each observation's nearest cell (coloured probes)
+    bool irregular = false;
+    DevBuf a_cell, a_w, at_off, at_obs, at_w;
     std::shared_ptr<const std::vector<int64_t>> h_cell;  // compact index -> cell id (host)
     std::shared_ptr<const std::vector<uint8_t>> h_mask;
     bool is_view = false;
@@ -162,6 +168,7 @@ struct Problem {
     DevBuf kws;                  // Krylov workspace
     DevBuf scal;                 // device scalars
     DevBuf tmp1, tmp2, tmp3, tmp4;  // per-call scratch of the drivers
+    DevBuf irr;                  // grid vectors of the irregular product
     MaskView mask_view() const {
         return MaskView{bits.as<uint32_t>(), base.as<uint32_t>(), words_per_row};
     }
@@ -181,6 +188,12 @@ struct Problem {
         v.cell = cell;
         v.y64 = y64;
         v.y32 = y32;
+        v.irregular = irregular;
+        v.a_cell = a_cell;
+        v.a_w = a_w;
+        v.at_off = at_off;
+        v.at_obs = at_obs;
+        v.at_w = at_w;
         v.q = q;
         v.X64 = X64;
         v.yc64 = yc64;
@@ -194,7 +207,7 @@ struct Problem {
     }
     void release_work() {
         for (DevBuf* b : {&Y, &lagtmp, &spectmp, &spec_multi64, &spec_multi32, &kws, &scal, &tmp1, &tmp2, &tmp3,
-                          &tmp4, &spec.s64, &spec.s32})
+                          &tmp4, &irr, &spec.s64, &spec.s32})
             b->release(*ctx);
         spec.valid = false;
     }

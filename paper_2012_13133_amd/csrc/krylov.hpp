@@ -66,6 +66,28 @@ void mscg_run(const MatvecFn<double>& A, const std::function<void(int, int)>& sw
               const std::vector<int>& group_of_shift, const std::vector<double>& sigma, const double* D, int nd,
               const std::vector<int>& rhs_of_group, double rtol, int maxit, MsCgBuffers& B, std::vector<int>& iters,
               std::vector<double>& relres, std::vector<double>& Q, hipStream_t st);
+// ---- irregularly spaced observations (irregular.hip) ----------------------------
+// K x = A Sigma A^T x + eta x for compact vectors of an irregular problem:
+// A^T by rows over the grid (FP64 sums), the circulant-embedding product on
+// the grid, A by its four-slot rows (FP64 sums) plus the nugget term.
+template <typename R>
+MatvecFn<R> irregular_op(Problem& P, const void* lam, int64_t lam_tstride, int vpt, const double* d_eta);
+// out (nvec grid vectors, stride n) = scale * A^T x (x: nvec compact, stride xs).
+template <typename RI, typename RO>
+void irr_scatter(const Problem& P, const RI* x, int64_t xs, int nvec, RO* out, double scale, const int* active,
+                 hipStream_t st);
+// out (nvec compact, stride p) = A grid (+ eta[v / vpt] xin when xin).
+template <typename RI, typename RO>
+void irr_gather(const Problem& P, const RI* grid, int nvec, RO* out, const RO* xin, const double* eta, int vpt,
+                const int* active, hipStream_t st);
+// out[v * p + j] = (A Sigma e_t)_j for target cell t = targets[v], from the
+// embedding lag grid (row-major N1 x N2).
+void irr_cross_corr(const Problem& P, const double* lag, const int64_t* targets, int nt, double* out,
+                    hipStream_t st);
+// y_b = A x_b + tau eps_b (eps from Philox stream b, domain NOISE, index j).
+void irr_boot_obs(const Problem& P, const double* fields, int B, double tau, uint64_t seed, double* yb,
+                  hipStream_t st);
+
 // Exchange vectors a and b (each n elements) of base + k * stride.
 template <typename T>
 void swap_vectors(T* base, int64_t stride, int a, int b, int64_t n, hipStream_t st);

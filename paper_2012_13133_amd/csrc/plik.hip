@@ -430,8 +430,13 @@ void plik_device(Problem& P, const kry_matern* theta, const double* beta, const 
     gengk_run(P, th, o, G, b, st);
     const int k = (int)G.z.size();
     gk_fields(G, n, dz, xs, wv, st);
-    hipLaunchKernelGGL(k_residual, grid_for(p), dim3(256), 0, st, b, xs, P.cell.as<int32_t>(), p, psi);
-    KRY_HIP(hipGetLastError());
+    if (P.irregular) {  // psi = b - A x*
+        irr_gather<double, double>(P, xs, 1, psi, nullptr, nullptr, 1, nullptr, st);
+        axpby<double>(b, psi, 1.0, -1.0, p, 1, st);
+    } else {
+        hipLaunchKernelGGL(k_residual, grid_for(p), dim3(256), 0, st, b, xs, P.cell.as<int32_t>(), p, psi);
+        KRY_HIP(hipGetLastError());
+    }
     // psi . psi and X_j . psi
     dot_batched<double>(psi, 0, psi, 0, p, 1, part, dots, st);
     if (q > 0) dot_batched<double>(P.X64.as<double>(), p, psi, 0, p, q, part, dots + 1, st);

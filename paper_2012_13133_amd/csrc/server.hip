@@ -38,7 +38,7 @@ struct Pending {
 // Workspace of one slot, moved into a problem view for the duration of a
 // request.
 struct SlotWork {
-    DevBuf Y, lagtmp, spectmp, spec_multi64, spec_multi32, kws, scal, tmp1, tmp2, tmp3, tmp4;
+    DevBuf Y, lagtmp, spectmp, spec_multi64, spec_multi32, kws, scal, tmp1, tmp2, tmp3, tmp4, irr;
     Spectrum spec;
     const Problem* last = nullptr;
 };
@@ -55,6 +55,7 @@ void swap_work(Problem& v, SlotWork& w) {
     std::swap(v.tmp2, w.tmp2);
     std::swap(v.tmp3, w.tmp3);
     std::swap(v.tmp4, w.tmp4);
+    std::swap(v.irr, w.irr);
     std::swap(v.spec.s64, w.spec.s64);
     std::swap(v.spec.s32, w.spec.s32);
     std::swap(v.spec.theta, w.spec.theta);
@@ -121,7 +122,8 @@ struct kry_server {
         if (r.kind != KRY_REQ_LOGLIK || !same_opts(r.opts, h.opts)) return false;
         if (r.prob == h.prob) return true;
         return h.opts.solver == KRY_SOLVER_CG && h.opts.shift_share == 0 && r.prob->P.N1 == h.prob->P.N1 &&
-               r.prob->P.N2 == h.prob->P.N2 && r.prob->P.q == 0 && h.prob->P.q == 0;
+               r.prob->P.N2 == h.prob->P.N2 && r.prob->P.q == 0 && h.prob->P.q == 0 && !r.prob->P.irregular &&
+               !h.prob->P.irregular;
     }
 
     void run_slot(int slot) {
@@ -344,7 +346,7 @@ void kry_server_destroy(kry_server* s) {
     (void)hipSetDevice(s->ctx->device);
     for (auto& w : s->work)
         for (DevBuf* b : {&w.Y, &w.lagtmp, &w.spectmp, &w.spec_multi64, &w.spec_multi32, &w.kws, &w.scal, &w.tmp1,
-                          &w.tmp2, &w.tmp3, &w.tmp4, &w.spec.s64, &w.spec.s32})
+                          &w.tmp2, &w.tmp3, &w.tmp4, &w.irr, &w.spec.s64, &w.spec.s32})
             b->release(*s->ctx);
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
     delete s;

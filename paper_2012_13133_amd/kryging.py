@@ -110,6 +110,7 @@ _SIGS = {
     "kry_profile_end": (C.c_int, [_P, _DP, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "kry_problem_create": (C.c_int, [_P, C.POINTER(kry_grid), C.POINTER(C.c_uint8), _DP, C.POINTER(_P)]),
     "kry_problem_set_data": (C.c_int, [_P, _DP]),
+    "kry_problem_create_irregular": (C.c_int, [_P, C.POINTER(kry_grid), C.c_int64, _DP, _DP, C.POINTER(_P)]),
     "kry_problem_set_covariates": (C.c_int, [_P, C.c_int32, _DP]),
     "kry_problem_info": (C.c_int, [_P, C.POINTER(C.c_int64), _I32P, _I32P]),
     "kry_problem_destroy": (None, [_P]),
@@ -232,6 +233,16 @@ def kry_problem_create(ctx, n1, n2, mask, y=None, dx1=None, dx2=None):
     yy = None if y is None else _f64(np.asarray(y).reshape(n1 * n2))
     h = _P()
     _check(lib.kry_problem_create(ctx, C.byref(g), m.ctypes.data_as(C.POINTER(C.c_uint8)), _dp(yy), C.byref(h)))
+    return h
+
+
+def kry_problem_create_irregular(ctx, n1, n2, locs, y=None, dx1=None, dx2=None):
+    """locs: (p, 2) fractional (row, column) grid coordinates."""
+    g = kry_grid(n1, n2, 1.0 / n1 if dx1 is None else dx1, 1.0 / n2 if dx2 is None else dx2)
+    L = _f64(np.asarray(locs).reshape(-1, 2))
+    yy = None if y is None else _f64(np.asarray(y).ravel())
+    h = _P()
+    _check(lib.kry_problem_create_irregular(ctx, C.byref(g), L.shape[0], _dp(L), _dp(yy), C.byref(h)))
     return h
 
 
@@ -588,3 +599,17 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+class IrregularProblem(Problem):
+    """Owns a context and an irregular problem handle (closes both)."""
+
+    def __init__(self, n1, n2, locs, y=None, device=0, dx1=None, dx2=None, hbm_budget_bytes=0):
+        self.n1, self.n2 = n1, n2
+        self.ctx = kry_ctx_create(device, hbm_budget_bytes)
+        try:
+            self.h = kry_problem_create_irregular(self.ctx, n1, n2, locs, y, dx1, dx2)
+        except Exception:
+            kry_ctx_destroy(self.ctx)
+            raise
+        self.p, self.N1, self.N2 = kry_problem_info(self.h)
