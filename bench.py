@@ -505,8 +505,9 @@ def ext_bench(args, K, synth, np):
     """Extension rows, each timed once on its own workload (not part of the
     headline step):
     * irregular observations (the paper's third study: 40,000 locations on a
-      400 x 400 latent grid; and 734,003 locations on the 1024 x 1024 grid):
-      batched FP32 / FP64 product rates and one FP64 likelihood evaluation;
+      400 x 400 latent grid; and 734,003 locations on the 1024 x 1024 grid,
+      listed at random and by grid cell): batched FP32 / FP64 product rates
+      and one FP64 likelihood evaluation;
     * covariates: a 3 x 3 (range, nugget) shift-shared FP32 batch at 1024^2
       with an intercept (mean 44.49) against the same batch without;
     * the paper's objective at 1024^2: one pl~ evaluation with its gradient
@@ -516,12 +517,16 @@ def ext_bench(args, K, synth, np):
     out = {}
     th = K.theta(sigma2=3.0, tau2=0.5, range=0.1, nu=0.5)
     B = args.mv_batch
-    for name, n, p in (("irregular_400sq_40k", 400, 40000), ("irregular_1024sq_734k", 1024, 734003)):
+    for name, n, p, order in (("irregular_400sq_40k", 400, 40000, "random"),
+                              ("irregular_1024sq_734k", 1024, 734003, "random"),
+                              ("irregular_1024sq_734k_cell_order", 1024, 734003, "cell")):
         g = (n, n, 1.0 / n, 1.0 / n)
         locs = synth.irregular_locations(g, p, seed=61)
+        if order == "cell":  # the caller lists observations by grid cell: coherent gathers
+            locs = locs[np.lexsort((np.floor(locs[:, 1]), np.floor(locs[:, 0])))]
         rng = np.random.default_rng(62)
         P = K.IrregularProblem(n, n, locs, rng.standard_normal(p))
-        row = {"grid": n, "observations": p}
+        row = {"grid": n, "observations": p, "order": order}
         for prec, key in ((K.KRY_FP32, "fp32"), (K.KRY_FP64, "fp64")):
             V = synth.random_vectors(p, B, seed=63, dtype=np.float32 if prec == K.KRY_FP32 else np.float64)
             import torch

@@ -189,10 +189,10 @@ void cov_full(Problem& P, const void* lam, const R* w, R* out, int nvec, hipStre
     s.in_mode = IN_COMPACT;
     s.in = w;
     s.in_vstride = P.p;
-    if (P.irregular) {  // A^T w on the grid first (FP64), then the dense product
+    if (P.irregular) {  // A^T w on the grid first (FP64 sums), then the dense product
         const int64_t n = (int64_t)P.n1 * P.n2;
-        P.irr.ensure(*P.ctx, (size_t)nvec * n * sizeof(double) + 256);
-        irr_scatter<R, double>(P, w, P.p, nvec, P.irr.as<double>(), 1.0, nullptr, st);
+        P.irr.ensure(*P.ctx, (size_t)nvec * n * sizeof(R) + 256);
+        irr_scatter<R, R>(P, w, P.p, nvec, P.irr.as<R>(), 1.0, nullptr, st);
         s.in_mode = IN_DENSE;
         s.in = P.irr.ptr;
         s.in_vstride = n;

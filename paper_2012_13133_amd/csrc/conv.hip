@@ -163,9 +163,9 @@ __device__ __forceinline__ void load_pair(const StageAArgs& a, const MaskView& m
         if (word & b0) out.x = vin[ci++];
         if (word & (b0 << 1)) out.y = vin[ci];
     } else if constexpr (IN == IN_DENSE) {
-        const double* src = reinterpret_cast<const double*>(a.in) + vec * a.in_vstride + (int64_t)row * a.in_rstride;
-        out.x = (R)src[c0];
-        if (c0 + 1 < row_len) out.y = (R)src[c0 + 1];
+        const R* src = reinterpret_cast<const R*>(a.in) + vec * a.in_vstride + (int64_t)row * a.in_rstride;
+        out.x = src[c0];
+        if (c0 + 1 < row_len) out.y = src[c0 + 1];
     } else {
         const uint32_t idx = (uint32_t)(row * a.in_rstride + c0);
         const uint32_t stream = (uint32_t)(a.stream0 + a.vec0 + vec);
@@ -773,8 +773,7 @@ static void run_stage_a(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R
                         const RowTiling& t, int vt, hipStream_t st) {
     const int M = s.N2 / 2;
     StageAArgs a;
-    a.in = s.in_mode == IN_COMPACT ? (const void*)((const R*)s.in + vec0 * s.in_vstride)
-                                   : (const void*)((const double*)s.in + vec0 * s.in_vstride);
+    a.in = (const void*)((const R*)s.in + vec0 * s.in_vstride);
     if (s.in_mode == IN_NOISE) a.in = nullptr;
     a.in_vstride = s.in_vstride;
     a.in_rstride = s.in_rstride;

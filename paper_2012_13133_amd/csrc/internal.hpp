@@ -225,7 +225,7 @@ struct ConvSpec {
     int N1 = 0, N2 = 0;
     int nvec = 0;
     int in_mode = IN_COMPACT;
-    const void* in = nullptr;   // compact (element type R) or dense rows (double)
+    const void* in = nullptr;   // compact or dense rows (element type R)
     int64_t in_vstride = 0;
     int in_rstride = 0;         // dense / noise: row stride of the input
     int rows_in = 0, row_len = 0;

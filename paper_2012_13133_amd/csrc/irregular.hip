@@ -5,7 +5,8 @@
 // K = A Sigma A^T + eta I; its product runs as A^T (rows over the grid, so
 // every cell sums its own observations in a fixed order), the
 // circulant-embedding product on the full grid, and A (four slots per
-// observation) with the nugget term.  All sums over A are in FP64.
+// observation) with the nugget term.  All sums over A are in FP64, rounded
+// once to the working precision.
 #include "internal.hpp"
 #include "krylov.hpp"
 
@@ -19,42 +20,78 @@ dim3 vgrid(int64_t n, int nvec) {
     return dim3((unsigned)b, nvec);
 }
 
+// Up to IV vectors per thread, so every entry of A or A^T is read once per
+// group of IV vectors rather than once per vector.
+constexpr int IV = 8;
+
 // out[v][c] = scale * sum_{e in row c of A^T} w_e x[v][obs_e]
 template <typename RI, typename RO>
 __global__ void k_irr_scatter(const RI* __restrict__ x, int64_t xs, const int32_t* __restrict__ off,
-                              const int32_t* __restrict__ obs, const double* __restrict__ w, int64_t n,
+                              const int32_t* __restrict__ obs, const double* __restrict__ w, int64_t n, int nvec,
                               RO* __restrict__ out, int64_t os, double scale, const int* __restrict__ active) {
-    const int v = blockIdx.y;
-    if (active && !active[v]) return;
-    const RI* xv = x + (int64_t)v * xs;
-    RO* ov = out + (int64_t)v * os;
+    const int v0 = blockIdx.y * IV;
+    bool on[IV];
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < IV; ++u) {
+        on[u] = v0 + u < nvec && (!active || active[v0 + u]);
+        any = any || on[u];
+    }
+    if (!any) return;
     for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n; c += (int64_t)gridDim.x * blockDim.x) {
-        double acc = 0.0;
+        double acc[IV];
+#pragma unroll
+        for (int u = 0; u < IV; ++u) acc[u] = 0.0;
         const int e1 = off[c + 1];
-        for (int e = off[c]; e < e1; ++e) acc += w[e] * (double)xv[obs[e]];
-        ov[c] = (RO)(scale * acc);
+        for (int e = off[c]; e < e1; ++e) {
+            const int64_t o = obs[e];
+            const double we = w[e];
+#pragma unroll
+            for (int u = 0; u < IV; ++u)
+                if (on[u]) acc[u] += we * (double)x[(int64_t)(v0 + u) * xs + o];
+        }
+#pragma unroll
+        for (int u = 0; u < IV; ++u)
+            if (on[u]) out[(int64_t)(v0 + u) * os + c] = (RO)(scale * acc[u]);
     }
 }
 
 // out[v][j] = sum_s w_js grid[v][cell_js] (+ eta[v / vpt] xin[v][j])
 template <typename RI, typename RO>
 __global__ void k_irr_gather(const RI* __restrict__ grid, int64_t gs, const int32_t* __restrict__ cell4,
-                             const double* __restrict__ w4, int64_t p, RO* __restrict__ out, int64_t os,
+                             const double* __restrict__ w4, int64_t p, int nvec, RO* __restrict__ out, int64_t os,
                              const RO* __restrict__ xin, const double* __restrict__ eta, int vpt,
                              const int* __restrict__ active) {
-    const int v = blockIdx.y;
-    if (active && !active[v]) return;
-    const RI* gv = grid + (int64_t)v * gs;
-    const double e = xin ? eta[v / vpt] : 0.0;
+    const int v0 = blockIdx.y * IV;
+    bool on[IV];
+    double e[IV];
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < IV; ++u) {
+        on[u] = v0 + u < nvec && (!active || active[v0 + u]);
+        e[u] = (on[u] && xin) ? eta[(v0 + u) / vpt] : 0.0;
+        any = any || on[u];
+    }
+    if (!any) return;
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < p; j += (int64_t)gridDim.x * blockDim.x) {
-        double acc = 0.0;
+        int c[4];
+        double wv[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const int c = cell4[4 * j + s];
-            if (c >= 0) acc += w4[4 * j + s] * (double)gv[c];
+            c[s] = cell4[4 * j + s];
+            wv[s] = w4[4 * j + s];
         }
-        if (xin) acc += e * (double)xin[(int64_t)v * os + j];
-        out[(int64_t)v * os + j] = (RO)acc;
+#pragma unroll
+        for (int u = 0; u < IV; ++u) {
+            if (!on[u]) continue;
+            const RI* gv = grid + (int64_t)(v0 + u) * gs;
+            double acc = 0.0;
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                if (c[s] >= 0) acc += wv[s] * (double)gv[c[s]];
+            if (xin) acc += e[u] * (double)xin[(int64_t)(v0 + u) * os + j];
+            out[(int64_t)(v0 + u) * os + j] = (RO)acc;
+        }
     }
 }
 
@@ -101,8 +138,9 @@ template <typename RI, typename RO>
 void irr_scatter(const Problem& P, const RI* x, int64_t xs, int nvec, RO* out, double scale, const int* active,
                  hipStream_t st) {
     const int64_t n = (int64_t)P.n1 * P.n2;
-    hipLaunchKernelGGL((k_irr_scatter<RI, RO>), vgrid(n, nvec), dim3(256), 0, st, x, xs, P.at_off.as<int32_t>(),
-                       P.at_obs.as<int32_t>(), P.at_w.as<double>(), n, out, n, scale, active);
+    hipLaunchKernelGGL((k_irr_scatter<RI, RO>), vgrid(n, (nvec + IV - 1) / IV), dim3(256), 0, st, x, xs,
+                       P.at_off.as<int32_t>(), P.at_obs.as<int32_t>(), P.at_w.as<double>(), n, nvec, out, n, scale,
+                       active);
     KRY_HIP(hipGetLastError());
 }
 
@@ -110,15 +148,13 @@ template <typename RI, typename RO>
 void irr_gather(const Problem& P, const RI* grid, int nvec, RO* out, const RO* xin, const double* eta, int vpt,
                 const int* active, hipStream_t st) {
     const int64_t n = (int64_t)P.n1 * P.n2;
-    hipLaunchKernelGGL((k_irr_gather<RI, RO>), vgrid(P.p, nvec), dim3(256), 0, st, grid, n, P.a_cell.as<int32_t>(),
-                       P.a_w.as<double>(), P.p, out, P.p, xin, eta, vpt, active);
+    hipLaunchKernelGGL((k_irr_gather<RI, RO>), vgrid(P.p, (nvec + IV - 1) / IV), dim3(256), 0, st, grid, n,
+                       P.a_cell.as<int32_t>(), P.a_w.as<double>(), P.p, nvec, out, P.p, xin, eta, vpt, active);
     KRY_HIP(hipGetLastError());
 }
 
 template void irr_scatter<double, double>(const Problem&, const double*, int64_t, int, double*, double, const int*,
                                           hipStream_t);
-template void irr_scatter<float, double>(const Problem&, const float*, int64_t, int, double*, double, const int*,
-                                         hipStream_t);
 template void irr_scatter<float, float>(const Problem&, const float*, int64_t, int, float*, double, const int*,
                                         hipStream_t);
 template void irr_gather<double, double>(const Problem&, const double*, int, double*, const double*, const double*,
@@ -132,12 +168,12 @@ MatvecFn<R> irregular_op(Problem& P, const void* lam, int64_t lam_tstride, int v
     return [pp, lam, lam_tstride, vpt, d_eta](const R* x, R* y, int nvec, hipStream_t st, const int* active) {
         Problem& Q = *pp;
         const int64_t n = (int64_t)Q.n1 * Q.n2;
-        // grid vectors: A^T x (FP64, the dense input of the product) and the product (R)
-        const size_t gin = ((size_t)nvec * n * sizeof(double) + 255) & ~size_t(255);
+        // grid vectors: A^T x (FP64 sums rounded once, the dense input of the product) and the product
+        const size_t gin = ((size_t)nvec * n * sizeof(R) + 255) & ~size_t(255);
         Q.irr.ensure(*Q.ctx, gin + (size_t)nvec * n * sizeof(R) + 256);
-        double* Gin = Q.irr.as<double>();
+        R* Gin = Q.irr.as<R>();
         R* Gout = reinterpret_cast<R*>(Q.irr.as<char>() + gin);
-        irr_scatter<R, double>(Q, x, Q.p, nvec, Gin, 1.0, active, st);
+        irr_scatter<R, R>(Q, x, Q.p, nvec, Gin, 1.0, active, st);
         ConvSpec s;
         s.N1 = Q.N1;
         s.N2 = Q.N2;
