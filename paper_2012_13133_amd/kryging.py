@@ -58,8 +58,8 @@ class kry_loglik_result(C.Structure):
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
-        d["beta"] = np.array(d["beta"][:self.ncov])
-        d["beta_se"] = np.array(d["beta_se"][:self.ncov])
+        d["beta"] = list(d["beta"][:self.ncov])
+        d["beta_se"] = list(d["beta_se"][:self.ncov])
         return d
 
 
@@ -71,7 +71,7 @@ class kry_plik_result(C.Structure):
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
-        d["grad_beta"] = np.array(d["grad_beta"][:self.ncov])
+        d["grad_beta"] = list(d["grad_beta"][:self.ncov])
         return d
 
 
