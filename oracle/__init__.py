@@ -30,7 +30,8 @@ cg          textbook conjugate gradients
 gengk       generalized Golub-Kahan bidiagonalization (Algorithm 1), low-rank
             posterior variance
 sampler     Cholesky and circulant-embedding Gaussian field samplers
-bootstrap   parametric bootstrap prediction variance (Sec. 3.5)
+bootstrap   parametric bootstrap prediction variance and parameter estimates
+            (Sec. 3.5)
 fit         profile-likelihood maximisation over (range, nugget ratio)
 irregular   Wendland mapping of irregularly spaced observations (Sec. 2)
 plik        the paper's own profile likelihood (exact and approximate), the

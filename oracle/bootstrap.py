@@ -16,6 +16,7 @@ import numpy as np
 
 from . import philox
 from .dense import krige
+from .fit import fit
 from .sampler import circulant_field
 
 
@@ -36,3 +37,26 @@ def bootstrap_variance(grid, mask, theta, targets, B, N1, N2, seed):
         sx += (xf[targets] - xhat) ** 2
         sy += (yt - xhat) ** 2
     return sx / B, sy / B
+
+
+def bootstrap_data(grid, mask, theta, b, N1, N2, seed):
+    """Simulated observations of draw b, the y_b of ``bootstrap_variance``:
+    x_b on the torus (Philox stream b, domain FIELD) at the observed cells
+    plus tau eps_b (stream b, domain NOISE, cell id as index)."""
+    obs = np.flatnonzero(np.asarray(mask).astype(bool).ravel())
+    x, _ = circulant_field(grid, theta, N1, N2, seed, stream=b)
+    return x.ravel()[obs] + np.sqrt(theta["tau2"]) * philox.normals(obs, b, seed, philox.DOMAIN_NOISE)
+
+
+def bootstrap_theta(grid, mask, theta_hat, B, N1, N2, seed, xatol=1e-4):
+    """The extension Sec. 3.5 mentions: estimate the covariance parameters
+    again on every simulated data set of the parametric bootstrap.  Draw b
+    uses the y_b above; each is fitted from theta_hat by ``oracle.fit`` over
+    (log range, log nugget ratio).  Returns (B, 2) estimates (range, eta)."""
+    out = np.empty((B, 2))
+    x0 = [np.log(theta_hat["range"]), np.log(theta_hat["tau2"] / theta_hat["sigma2"])]
+    for b in range(B):
+        yb = bootstrap_data(grid, mask, theta_hat, b, N1, N2, seed)
+        rho, eta, _ = fit(grid, mask, yb, theta_hat, x0, xatol=xatol)
+        out[b] = (rho, eta)
+    return out
