@@ -352,6 +352,18 @@ kry_status kry_loglik_multi(kry_problem* const* probs, const kry_matern* thetas,
 kry_status kry_fit(kry_problem* prob, const kry_matern* init, uint32_t free_mask,
                    const kry_opts* opts, double xtol, int32_t maxiter,
                    kry_matern* est, kry_loglik_result* at_est);
+/* Parametric bootstrap of the estimates (the extension Sec. 3.5 mentions):
+ * for b = 0..B-1 the data set y_b of the prediction-variance bootstrap
+ * (kry_krige with bootstrap_B: field of Philox stream b on the smallest PSD
+ * torus at theta_hat, nugget noise of stream b) plus X beta_hat (GLS at
+ * theta_hat) when the problem has covariates, fitted by kry_fit from
+ * theta_hat with the same free_mask, options, xtol and maxiter; est
+ * receives the B estimates, sd (nullable, 2 values) the standard deviations
+ * over b of log range and log eta.  The problem's data are restored
+ * afterwards (also on error). */
+kry_status kry_bootstrap_theta(kry_problem* prob, const kry_matern* theta_hat, uint32_t free_mask,
+                               const kry_opts* opts, double xtol, int32_t maxiter, int32_t B, kry_matern* est,
+                               double* sd);
 /* Kriging at target cell ids (or every unobserved cell if targets == NULL):
  * mean_x = c_t^T K^{-1} y (with covariates X_t beta_hat + c_t^T K^{-1}
  * (y - X beta_hat), beta_hat as in kry_loglik, treated as known in the

@@ -1468,6 +1468,8 @@ static void upload_centred(Problem& P, const std::vector<double>& Xc, const std:
     KRY_HIP(hipMemcpy(P.yc64.ptr, yc.data(), yc.size() * sizeof(double), hipMemcpyHostToDevice));
 }
 
+static void upload_compact(Problem& P, const std::vector<double>& yc);
+
 static void upload_data(Problem& P, const double* y) {
     std::vector<double> yc(P.p, 0.0);
     if (y) {
@@ -1477,6 +1479,12 @@ static void upload_data(Problem& P, const double* y) {
             yc[i] = v;
         }
     }
+    upload_compact(P, yc);
+}
+
+// Compact data (p values) to the device, with the OLS centring when the
+// problem has covariates.
+static void upload_compact(Problem& P, const std::vector<double>& yc) {
     std::vector<double> Xc, ycent, beta;
     double ldxx = 0;
     if (P.q > 0) ols_centre(P, P.q, *P.h_X, yc, Xc, ycent, beta, ldxx);
@@ -2625,17 +2633,9 @@ kry_status kry_krige(kry_problem* prob, const kry_matern* theta, const kry_opts*
 }
 
 // ---- fit ----------------------------------------------------------------------------------------
-kry_status kry_fit(kry_problem* prob, const kry_matern* init, uint32_t free_mask, const kry_opts* opts,
-                              double xtol, int32_t maxiter, kry_matern* est, kry_loglik_result* at_est) {
-    return guard([&] {
-        KRY_REQUIRE(prob && init && est, "NULL argument");
-        check_theta(init);
-        check_opts(opts);
-        KRY_REQUIRE((free_mask & 3u) != 0, "free_mask must free the range and/or the nugget ratio");
-        KRY_REQUIRE(xtol > 0 && maxiter >= 1, "bad xtol or maxiter");
-        KRY_REQUIRE(init->tau2 > 0, "the nugget ratio needs tau2 > 0 to be fitted on the log scale");
-        Problem& P = prob->P;
-        bind(*P.ctx);
+static void fit_impl(Problem& P, const kry_matern* init, uint32_t free_mask, const kry_opts* opts, double xtol,
+                     int32_t maxiter, kry_matern* est, kry_loglik_result* at_est) {
+    {
         hipStream_t st = P.ctx->stream;
         // free coordinates: log range, log eta
         std::vector<int> which;
@@ -2733,6 +2733,95 @@ kry_status kry_fit(kry_problem* prob, const kry_matern* init, uint32_t free_mask
         if (at_est) {
             kry_matern t2 = t;
             loglik_points(P, &t2, 1, opts, at_est, st);
+        }
+    }
+}
+
+static void check_fit_args(const kry_matern* init, uint32_t free_mask, const kry_opts* opts, double xtol,
+                           int32_t maxiter) {
+    check_theta(init);
+    check_opts(opts);
+    KRY_REQUIRE((free_mask & 3u) != 0, "free_mask must free the range and/or the nugget ratio");
+    KRY_REQUIRE(xtol > 0 && maxiter >= 1, "bad xtol or maxiter");
+    KRY_REQUIRE(init->tau2 > 0, "the nugget ratio needs tau2 > 0 to be fitted on the log scale");
+}
+
+kry_status kry_fit(kry_problem* prob, const kry_matern* init, uint32_t free_mask, const kry_opts* opts,
+                   double xtol, int32_t maxiter, kry_matern* est, kry_loglik_result* at_est) {
+    return guard([&] {
+        KRY_REQUIRE(prob && init && est, "NULL argument");
+        check_fit_args(init, free_mask, opts, xtol, maxiter);
+        Problem& P = prob->P;
+        bind(*P.ctx);
+        fit_impl(P, init, free_mask, opts, xtol, maxiter, est, at_est);
+    });
+}
+
+kry_status kry_bootstrap_theta(kry_problem* prob, const kry_matern* theta_hat, uint32_t free_mask,
+                               const kry_opts* opts, double xtol, int32_t maxiter, int32_t B, kry_matern* est,
+                               double* sd) {
+    return guard([&] {
+        KRY_REQUIRE(prob && theta_hat && est, "NULL argument");
+        check_fit_args(theta_hat, free_mask, opts, xtol, maxiter);
+        KRY_REQUIRE(B >= 1 && B <= 4096, "B must be in [1, 4096]");
+        Problem& P = prob->P;
+        bind(*P.ctx);
+        hipStream_t st = P.ctx->stream;
+        const Matern th = to_matern(theta_hat);
+        const int64_t n = (int64_t)P.n1 * P.n2, p = P.p;
+        // the mean at the estimates: X beta_hat (GLS at theta_hat)
+        std::vector<double> mean(p, 0.0);
+        if (P.q > 0) {
+            const std::vector<double> beta = gls_beta(P, theta_hat, opts, nullptr, nullptr, st);
+            for (int j = 0; j < P.q; ++j)
+                for (int64_t i = 0; i < p; ++i)
+                    mean[i] += beta[j] * (P.irregular ? (*P.h_X)[(size_t)j * p + i]
+                                                      : (*P.h_X)[(size_t)j * n + (*P.h_cell)[i]]);
+        }
+        // every simulated data set, as the prediction-variance bootstrap draws them
+        int N1s, N2s;
+        psd_torus(P, th, &N1s, &N2s, st);
+        DevBuf& bb = P.tmp3;
+        bb.ensure(*P.ctx, ((size_t)B * n + (size_t)B * p) * sizeof(double) + 512);
+        double* F = bb.as<double>();
+        double* YB = F + (size_t)B * n;
+        double lo, hi;
+        sample_fields(P, th, N1s, N2s, opts->seed, 0, B, F, &lo, &hi, st);
+        const double tau = std::sqrt(th.tau2);
+        if (P.irregular) {
+            irr_boot_obs(P, F, B, tau, opts->seed, YB, st);
+        } else {
+            hipLaunchKernelGGL(k_boot_obs, grid1(p, B), dim3(256), 0, st, F, n, P.cell.as<int32_t>(), p, tau,
+                               opts->seed, YB);
+            KRY_HIP(hipGetLastError());
+        }
+        std::vector<double> ys((size_t)B * p), saved(p);
+        KRY_HIP(hipMemcpyAsync(ys.data(), YB, ys.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        KRY_HIP(hipMemcpyAsync(saved.data(), P.y64.ptr, p * sizeof(double), hipMemcpyDeviceToHost, st));
+        KRY_HIP(hipStreamSynchronize(st));
+        try {
+            for (int b = 0; b < B; ++b) {
+                std::vector<double> yb(ys.begin() + (size_t)b * p, ys.begin() + (size_t)(b + 1) * p);
+                for (int64_t i = 0; i < p; ++i) yb[i] += mean[i];
+                upload_compact(P, yb);
+                fit_impl(P, theta_hat, free_mask, opts, xtol, maxiter, &est[b], nullptr);
+            }
+        } catch (...) {
+            upload_compact(P, saved);
+            throw;
+        }
+        upload_compact(P, saved);
+        if (sd) {
+            for (int c = 0; c < 2; ++c) {
+                double m = 0, ss = 0;
+                for (int b = 0; b < B; ++b) m += c == 0 ? std::log(est[b].range) : std::log(est[b].tau2 / est[b].sigma2);
+                m /= B;
+                for (int b = 0; b < B; ++b) {
+                    const double v = (c == 0 ? std::log(est[b].range) : std::log(est[b].tau2 / est[b].sigma2)) - m;
+                    ss += v * v;
+                }
+                sd[c] = B > 1 ? std::sqrt(ss / (B - 1)) : 0.0;
+            }
         }
     });
 }

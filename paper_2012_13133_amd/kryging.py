@@ -136,6 +136,8 @@ _SIGS = {
                                    C.POINTER(kry_loglik_result)]),
     "kry_fit": (C.c_int, [_P, C.POINTER(kry_matern), C.c_uint32, C.POINTER(kry_opts), C.c_double, C.c_int32,
                           C.POINTER(kry_matern), C.POINTER(kry_loglik_result)]),
+    "kry_bootstrap_theta": (C.c_int, [_P, C.POINTER(kry_matern), C.c_uint32, C.POINTER(kry_opts), C.c_double,
+                                      C.c_int32, C.c_int32, C.POINTER(kry_matern), _DP]),
     "kry_krige": (C.c_int, [_P, C.POINTER(kry_matern), C.POINTER(kry_opts), C.POINTER(C.c_int64), C.c_int64,
                             _DP, _DP, _DP, C.c_int32]),
     "kry_psd_torus": (C.c_int, [_P, C.POINTER(kry_matern), _I32P, _I32P]),
@@ -468,6 +470,14 @@ def kry_sample(prob, th, N1, N2, seed, first_stream, count, n1, n2):
     mm = np.empty(2)
     _check(lib.kry_sample(prob, C.byref(th), N1, N2, seed, first_stream, count, _dp(out), _dp(mm)))
     return out, mm
+
+
+def kry_bootstrap_theta(prob, theta_hat, opts, B, free_mask=3, xtol=1e-4, maxiter=300):
+    est = (kry_matern * B)()
+    sd = np.empty(2)
+    _check(lib.kry_bootstrap_theta(prob, C.byref(theta_hat), free_mask, C.byref(opts), xtol, maxiter, B, est,
+                                   _dp(sd)))
+    return list(est), sd
 
 
 def _beta_arg(beta):
