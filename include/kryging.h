@@ -160,6 +160,9 @@ typedef struct {
                                intermediate times this (1 or 2; capped by LDS)           */
     int32_t row_vthreads;   /* values per thread in the row stages: 8 x this (1 or 2;
                                2 only for rows of >= 1024 points)                         */
+    int32_t col_split;      /* 1: the column stage exchanges real and imaginary parts
+                               through LDS separately (half the LDS per workgroup, more
+                               workgroups per CU; columns of >= 256 points), 0: together */
     double ms;              /* kry_autotune: time of one product of nvec vectors        */
 } kry_tuning;
 

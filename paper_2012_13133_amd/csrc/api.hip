@@ -2167,6 +2167,7 @@ void check_tuning(const kry_tuning* t) {
     KRY_REQUIRE(t->col_vectors == 1 || t->col_vectors == 2, "col_vectors must be 1 or 2");
     KRY_REQUIRE(t->row_tile_scale == 1 || t->row_tile_scale == 2, "row_tile_scale must be 1 or 2");
     KRY_REQUIRE(t->row_vthreads == 1 || t->row_vthreads == 2, "row_vthreads must be 1 or 2");
+    KRY_REQUIRE(t->col_split == 0 || t->col_split == 1, "col_split must be 0 or 1");
 }
 
 kry_tuning to_abi(const Tuning& t, int real_bytes) {
@@ -2174,6 +2175,7 @@ kry_tuning to_abi(const Tuning& t, int real_bytes) {
     o.col_vectors = t.col_v ? t.col_v : (real_bytes == 4 ? 2 : 1);
     o.row_tile_scale = t.rt_scale;
     o.row_vthreads = t.row_vt;
+    o.col_split = t.col_split;
     o.ms = t.ms;
     return o;
 }
@@ -2186,14 +2188,17 @@ Tuning autotune_impl(Problem& P, int nvec, hipStream_t st) {
     std::vector<Tuning> cand;
     for (int cv : {1, 2})
         for (int rs : {1, 2})
-            for (int vt : {1, 2}) {
-                if (vt == 2 && P.N2 / 2 < 1024) continue;
-                Tuning t;
-                t.col_v = cv;
-                t.rt_scale = rs;
-                t.row_vt = vt;
-                cand.push_back(t);
-            }
+            for (int vt : {1, 2})
+                for (int cs : {0, 1}) {
+                    if (vt == 2 && P.N2 / 2 < 1024) continue;
+                    if (cs == 1 && P.N1 < 256) continue;
+                    Tuning t;
+                    t.col_v = cv;
+                    t.rt_scale = rs;
+                    t.row_vt = vt;
+                    t.col_split = cs;
+                    cand.push_back(t);
+                }
     // inputs: Rademacher vectors on the problem and the spectrum of a fixed point
     const kry_matern th{1.0, 0.1, 0.1, 0.5, 1.0, 0.0};
     Spectrum& S = problem_spectrum(P, to_matern(&th), st);
@@ -2284,6 +2289,7 @@ kry_status kry_set_tuning(kry_ctx* ctx, int32_t N1, int32_t N2, int32_t precisio
         u.col_v = t->col_vectors;
         u.rt_scale = t->row_tile_scale;
         u.row_vt = t->row_vthreads;
+        u.col_split = t->col_split;
         ctx->c.tuning[key] = u;
     });
 }

@@ -306,7 +306,7 @@ struct StageBArgs {
 // rows_out rows.  Each thread carries the same column of V consecutive
 // vectors, sharing twiddle and spectrum loads.  B_SPEC: forward only, real
 // part to spec_out.
-template <typename R, int LOG2L, int MODE, int V>
+template <typename R, int LOG2L, int MODE, int V, bool SPLIT>
 __global__ void __launch_bounds__(((1 << LOG2L) / 8 > 256 ? (1 << LOG2L) / 8 : 256)) k_col(StageBArgs a, const cpx<R>* __restrict__ twp) {
     using S = Sched<LOG2L>;
     constexpr int L = S::L, T = L / 8, PL = padded(L);
@@ -323,6 +323,7 @@ __global__ void __launch_bounds__(((1 << LOG2L) / 8 > 256 ? (1 << LOG2L) / 8 : 2
     const bool valid = col < a.ncols;
     const int vbase = (lid % gridDim.y) * V;  // first vector of this workgroup (within the launch)
     cpx<R>* buf = lds + cl * V * PL;
+    R* rbuf = reinterpret_cast<R*>(smem_raw) + cl * V * PL;  // split exchanges: reals
     cpx<R>* Ycol = reinterpret_cast<cpx<R>*>(a.Y) + (int64_t)(valid ? col : 0) * a.ldY;
     cpx<R> v[V * 8];
     // spectrum values for this column, fetched up front so their latency
@@ -375,13 +376,17 @@ __global__ void __launch_bounds__(((1 << LOG2L) / 8 > 256 ? (1 << LOG2L) / 8 : 2
         }
     }
     pass_compute<R, LOG2L, false, 0, LOW, V>(v, t, twp);
+    if constexpr (SPLIT) {
+        SplitPasses<R, LOG2L, false, 1, S::npass - 1, V>::run(v, rbuf, PL, t, twp);
+    } else {
 #pragma unroll
-    for (int u = 0; u < V; ++u) pass_write<R, LOG2L, false, 0>(v + u * 8, buf + u * PL, t);
-    __syncthreads();
-    LdsPasses<R, LOG2L, false, 1, S::npass - 1, V>::run(v, buf, PL, t, twp);
+        for (int u = 0; u < V; ++u) pass_write<R, LOG2L, false, 0>(v + u * 8, buf + u * PL, t);
+        __syncthreads();
+        LdsPasses<R, LOG2L, false, 1, S::npass - 1, V>::run(v, buf, PL, t, twp);
 #pragma unroll
-    for (int u = 0; u < V; ++u) pass_read<R, LOG2L, false, S::npass - 1>(v + u * 8, buf + u * PL, t);
-    pass_compute<R, LOG2L, false, S::npass - 1, false, V>(v, t, twp);
+        for (int u = 0; u < V; ++u) pass_read<R, LOG2L, false, S::npass - 1>(v + u * 8, buf + u * PL, t);
+        pass_compute<R, LOG2L, false, S::npass - 1, false, V>(v, t, twp);
+    }
     if constexpr (MODE == B_SPEC) {
         if (valid) {
 #pragma unroll
@@ -391,15 +396,20 @@ __global__ void __launch_bounds__(((1 << LOG2L) / 8 > 256 ? (1 << LOG2L) / 8 : 2
     } else {
 #pragma unroll
         for (int k = 0; k < V * 8; ++k) v[k] = cscale(v[k], lamv[k]);
-        __syncthreads();
-        pass_compute<R, LOG2L, true, 0, false, V>(v, t, twp);
+        if constexpr (SPLIT) {
+            pass_compute<R, LOG2L, true, 0, false, V>(v, t, twp);
+            SplitPasses<R, LOG2L, true, 1, S::npass - 1, V>::run(v, rbuf, PL, t, twp);
+        } else {
+            __syncthreads();
+            pass_compute<R, LOG2L, true, 0, false, V>(v, t, twp);
 #pragma unroll
-        for (int u = 0; u < V; ++u) pass_write<R, LOG2L, true, 0>(v + u * 8, buf + u * PL, t);
-        __syncthreads();
-        LdsPasses<R, LOG2L, true, 1, S::npass - 1, V>::run(v, buf, PL, t, twp);
+            for (int u = 0; u < V; ++u) pass_write<R, LOG2L, true, 0>(v + u * 8, buf + u * PL, t);
+            __syncthreads();
+            LdsPasses<R, LOG2L, true, 1, S::npass - 1, V>::run(v, buf, PL, t, twp);
 #pragma unroll
-        for (int u = 0; u < V; ++u) pass_read<R, LOG2L, true, S::npass - 1>(v + u * 8, buf + u * PL, t);
-        pass_compute<R, LOG2L, true, S::npass - 1, false, V>(v, t, twp);
+            for (int u = 0; u < V; ++u) pass_read<R, LOG2L, true, S::npass - 1>(v + u * 8, buf + u * PL, t);
+            pass_compute<R, LOG2L, true, S::npass - 1, false, V>(v, t, twp);
+        }
 #pragma unroll
         for (int u = 0; u < V; ++u) {
             if (!(valid && vbase + u < a.nvec)) continue;
@@ -740,12 +750,12 @@ static void launch_row_inv(const StageCArgs& a, dim3 grid, const RowTiling& t, i
     KRY_HIP(hipGetLastError());
 }
 
-template <typename R, int LG, int MODE, int V>
+template <typename R, int LG, int MODE, int V, bool SPLIT>
 static void launch_col_v(const StageBArgs& b, int nvec, Ctx& c, hipStream_t st) {
     constexpr int L = 1 << LG, T = L / 8;
-    const size_t lds = (size_t)b.CB * V * padded(L) * sizeof(cpx<R>);
+    const size_t lds = (size_t)b.CB * V * padded(L) * (SPLIT ? sizeof(R) : sizeof(cpx<R>));
     dim3 grid((b.ncols + b.CB - 1) / b.CB, (nvec + V - 1) / V);
-    auto k = k_col<R, LG, MODE, V>;
+    auto k = k_col<R, LG, MODE, V, SPLIT>;
     set_lds(k, lds);
     StageBArgs bb = b;
     bb.nvec = nvec;
@@ -754,16 +764,24 @@ static void launch_col_v(const StageBArgs& b, int nvec, Ctx& c, hipStream_t st) 
 }
 
 // V vectors per workgroup share twiddle and spectrum loads; the spectrum
-// transform takes one.
+// transform takes one.  split: exchanges through a buffer of reals
+// (transforms of 256 points or more, where LDS bounds the occupancy).
 template <typename R, int LG, int MODE>
-static void launch_col(const StageBArgs& b, int nvec, int V, Ctx& c, hipStream_t st) {
-    if constexpr (MODE != B_SPEC) {
-        if (V == 2) {
-            launch_col_v<R, LG, MODE, 2>(b, nvec, c, st);
+static void launch_col(const StageBArgs& b, int nvec, int V, bool split, Ctx& c, hipStream_t st) {
+    if constexpr (MODE != B_SPEC && LG >= 8) {
+        if (split) {
+            if (V == 2) launch_col_v<R, LG, MODE, 2, true>(b, nvec, c, st);
+            else launch_col_v<R, LG, MODE, 1, true>(b, nvec, c, st);
             return;
         }
     }
-    launch_col_v<R, LG, MODE, 1>(b, nvec, c, st);
+    if constexpr (MODE != B_SPEC) {
+        if (V == 2) {
+            launch_col_v<R, LG, MODE, 2, false>(b, nvec, c, st);
+            return;
+        }
+    }
+    launch_col_v<R, LG, MODE, 1, false>(b, nvec, c, st);
 }
 
 #define KRY_SIZES(X) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
@@ -811,7 +829,7 @@ template <typename R>
 static void run_stage_b(Problem& P, int N1, int M, int vec0, int nvec, cpx<R>* Y, int ldY, int64_t Yvs, int rows_in,
                         int rows_out, const void* lam, int64_t lam_tstride, int vpt, double* spec_out,
                         hipStream_t st, const ProbDesc* tab = nullptr, int tab_vpp = 1,
-                        const int* active = nullptr, int V = 1) {
+                        const int* active = nullptr, int V = 1, bool split = false) {
     const int T = N1 / 8;
     StageBArgs b;
     b.Y = Y;
@@ -834,9 +852,9 @@ static void run_stage_b(Problem& P, int N1, int M, int vec0, int nvec, cpx<R>* Y
     Ctx& c = *P.ctx;
 #define KRY_B(LG)                                                                          \
     case LG + 1:                                                                           \
-        if (mode == B_LOW) launch_col<R, LG + 1, B_LOW>(b, nvec, V, c, st);                \
-        else if (mode == B_FULL) launch_col<R, LG + 1, B_FULL>(b, nvec, V, c, st);         \
-        else launch_col<R, LG + 1, B_SPEC>(b, nvec, 1, c, st);                             \
+        if (mode == B_LOW) launch_col<R, LG + 1, B_LOW>(b, nvec, V, split, c, st);         \
+        else if (mode == B_FULL) launch_col<R, LG + 1, B_FULL>(b, nvec, V, split, c, st);  \
+        else launch_col<R, LG + 1, B_SPEC>(b, nvec, 1, false, c, st);                      \
         break;
     switch (lg) {
         KRY_SIZES(KRY_B)
@@ -929,7 +947,7 @@ void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st) {
         run_stage_a<R>(P, s, v0, nv, Y, ldY, Yvs, ta, vt, st);
         mark(1);
         run_stage_b<R>(P, s.N1, M, v0, nv, Y, ldY, Yvs, s.rows_in, s.rows_out, s.lam, s.lam_tstride,
-                       s.vecs_per_theta, nullptr, st, s.tab, s.tab_vpp, s.active, V);
+                       s.vecs_per_theta, nullptr, st, s.tab, s.tab_vpp, s.active, V, tu.col_split != 0);
         mark(2);
         run_stage_c<R>(P, s, v0, nv, Y, ldY, Yvs, ta, vt, st);
         mark(3);

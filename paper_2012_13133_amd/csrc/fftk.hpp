@@ -188,6 +188,94 @@ __device__ __forceinline__ void pass_write(const cpx<R>* v, cpx<R>* buf, int t) 
     }
 }
 
+// ---- split exchange: real parts, then imaginary parts, through a buffer of
+// reals (padded L per transform).  A workgroup then needs half the LDS of a
+// complex exchange, so more workgroups fit a CU, at four barriers per
+// exchange instead of two.  Index logic as in pass_read / pass_write.
+template <typename R, int C>
+__device__ __forceinline__ R& part(cpx<R>& z) {
+    if constexpr (C == 0) return z.x;
+    else return z.y;
+}
+
+template <typename R, int LOG2L, bool INV, int P, int C>
+__device__ __forceinline__ void pass_read_part(cpx<R>* v, const R* buf, int t) {
+    using S = Sched<LOG2L>;
+    constexpr int RADIX = 1 << S::lr(INV, P);
+    constexpr int T = S::L / 8;
+    constexpr int Q = S::L / RADIX;
+#pragma unroll
+    for (int b = 0; b < 8 / RADIX; ++b) {
+        const int j = t + b * T;
+        if constexpr (Q % 8 == 0) {
+            const R* p = buf + pad8(j);
+#pragma unroll
+            for (int r = 0; r < RADIX; ++r) part<R, C>(v[b * RADIX + r]) = p[pad_off(r * Q)];
+        } else {
+#pragma unroll
+            for (int r = 0; r < RADIX; ++r) part<R, C>(v[b * RADIX + r]) = buf[pad8(j + r * Q)];
+        }
+    }
+}
+
+template <typename R, int LOG2L, bool INV, int P, int C>
+__device__ __forceinline__ void pass_write_part(cpx<R>* v, R* buf, int t) {
+    using S = Sched<LOG2L>;
+    constexpr int LR = S::lr(INV, P);
+    constexpr int RADIX = 1 << LR;
+    constexpr int LNS = S::lns(INV, P);
+    constexpr int NS = 1 << LNS;
+    constexpr int T = S::L / 8;
+    constexpr bool FAST = (NS % 8 == 0) || (8 % NS == 0 && (NS * RADIX) % 8 == 0);
+#pragma unroll
+    for (int b = 0; b < 8 / RADIX; ++b) {
+        const int j = t + b * T;
+        const int dst = ((j >> LNS) << (LNS + LR)) + (j & (NS - 1));
+        if constexpr (FAST) {
+            R* p = buf + pad8(dst);
+#pragma unroll
+            for (int r = 0; r < RADIX; ++r) p[pad_off(r * NS)] = part<R, C>(v[b * RADIX + r]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < RADIX; ++r) buf[pad8(dst + r * NS)] = part<R, C>(v[b * RADIX + r]);
+        }
+    }
+}
+
+// Exchange from the outputs of pass PW to the inputs of pass PW + 1 for V
+// transforms at buf + u * stride (reals).  Starts with a barrier, so the
+// previous exchange's readers are done before the buffer is overwritten.
+template <typename R, int LOG2L, bool INV, int PW, int V>
+__device__ __forceinline__ void exchange_split(cpx<R>* v, R* buf, int stride, int t) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < V; ++u) pass_write_part<R, LOG2L, INV, PW, 0>(v + u * 8, buf + u * stride, t);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < V; ++u) pass_read_part<R, LOG2L, INV, PW + 1, 0>(v + u * 8, buf + u * stride, t);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < V; ++u) pass_write_part<R, LOG2L, INV, PW, 1>(v + u * 8, buf + u * stride, t);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < V; ++u) pass_read_part<R, LOG2L, INV, PW + 1, 1>(v + u * 8, buf + u * stride, t);
+}
+
+// Passes P..PE of a plan after pass P - 1 was computed in registers: for
+// each, its twiddles are fetched, the values exchanged (split) and the pass
+// computed.
+template <typename R, int LOG2L, bool INV, int P, int PE, int V>
+struct SplitPasses {
+    __device__ __forceinline__ static void run(cpx<R>* v, R* buf, int stride, int t, const cpx<R>* __restrict__ tw) {
+        if constexpr (P <= PE) {
+            const auto w = pass_twiddles<R, LOG2L, INV, P>(t, tw);
+            exchange_split<R, LOG2L, INV, P - 1, V>(v, buf, stride, t);
+            pass_compute_tw<R, LOG2L, INV, P, false, V>(v, w);
+            SplitPasses<R, LOG2L, INV, P + 1, PE, V>::run(v, buf, stride, t, tw);
+        }
+    }
+};
+
 // Natural-order position of register value k after the last pass (or before
 // the first pass) of a plan whose boundary radix is 2^LR.
 template <int LOG2L, int LR>

@@ -50,6 +50,7 @@ struct Tuning {
     int col_v = 0;       // 0: default for the precision
     int rt_scale = 1;
     int row_vt = 1;
+    int col_split = 0;   // column stage exchanges real and imaginary parts separately
     double ms = 0.0;
 };
 

@@ -25,10 +25,10 @@ def test_every_configuration_is_bit_identical(shape):
         for prec in (K.KRY_FP64, K.KRY_FP32):
             K.kry_set_tuning(P.ctx, P.N1, P.N2, prec)
             ref = K.kry_matvec(P.h, th, v, prec)
-            for cv, rs, vt in itertools.product((1, 2), (1, 2), (1, 2)):
-                K.kry_set_tuning(P.ctx, P.N1, P.N2, prec, cv, rs, vt)
+            for cv, rs, vt, cs in itertools.product((1, 2), (1, 2), (1, 2), (0, 1)):
+                K.kry_set_tuning(P.ctx, P.N1, P.N2, prec, cv, rs, vt, cs)
                 got = K.kry_matvec(P.h, th, v, prec)
-                assert np.array_equal(got, ref), (prec, cv, rs, vt)
+                assert np.array_equal(got, ref), (prec, cv, rs, vt, cs)
             K.kry_set_tuning(P.ctx, P.N1, P.N2, prec)
 
 
@@ -39,6 +39,7 @@ def test_autotune_keeps_a_valid_configuration():
         for prec in (K.KRY_FP64, K.KRY_FP32):
             t = K.kry_autotune(P.h, prec, 8)
             assert t["col_vectors"] in (1, 2) and t["row_tile_scale"] in (1, 2) and t["row_vthreads"] in (1, 2)
+            assert t["col_split"] in (0, 1)
             assert t["ms"] > 0
             assert K.kry_get_tuning(P.ctx, P.N1, P.N2, prec) == t
             K.kry_set_tuning(P.ctx, P.N1, P.N2, prec)
@@ -48,5 +49,7 @@ def test_autotune_keeps_a_valid_configuration():
             K.kry_set_tuning(P.ctx, P.N1, P.N2, K.KRY_FP32, 3, 1, 1)
         with pytest.raises(K.KryError):
             K.kry_set_tuning(P.ctx, 100, P.N2, K.KRY_FP32, 1, 1, 1)
+        with pytest.raises(K.KryError):
+            K.kry_set_tuning(P.ctx, P.N1, P.N2, K.KRY_FP32, 1, 1, 1, 2)
         with pytest.raises(K.KryError):
             K.kry_autotune(P.h, K.KRY_FP32, 0)
