@@ -177,3 +177,32 @@ def test_paper_third_study_size_sampled_rows_and_precisions():
     assert np.abs(got32[rows] - ref).max() <= 1e-5 * scale
     assert abs(r32["quad"] - r64["quad"]) <= 1e-6 * r64["quad"]
     assert abs(r32["loglik"] - r64["loglik"]) <= 1e-3 * abs(r64["loglik"])
+
+
+def test_server_requests_on_an_irregular_problem():
+    g, locs, A, y = _case(seed=61)
+    ctx = K.kry_ctx_create()
+    h = K.kry_problem_create_irregular(ctx, 24, 20, locs, y)
+    try:
+        opts = K.kry_opts_default(lanczos_steps=20, num_probes=4, cg_rtol=1e-10)
+        pts = [K.theta(sigma2=1.4, tau2=e, range=0.15, nu=1.5) for e in (0.1, 0.25, 0.6)]
+        alone = [K.kry_loglik(h, t, opts) for t in pts]
+        tg = np.array([5, 77, 300])
+        kr = K.kry_krige(h, pts[1], opts, tg)
+        srv = K.kry_server_create(ctx, slots=2, max_batch=8)
+        try:
+            pend = [K.kry_server_submit(srv, K.KRY_REQ_LOGLIK, h, t, opts) for t in pts]
+            pk = K.kry_server_submit(srv, K.KRY_REQ_KRIGE, h, pts[1], opts, targets=tg, variances=True)
+            res = [K.kry_server_wait(srv, pd) for pd in pend]
+            rk = K.kry_server_wait(srv, pk)
+        finally:
+            K.kry_server_destroy(srv)
+        for r, a in zip(res, alone):
+            d = r.loglik.as_dict()
+            assert r.status == 0 and d["quad"] == a["quad"] and d["logdet"] == a["logdet"]
+        assert rk.status == 0
+        np.testing.assert_array_equal(pk.outputs["mean_x"], kr[0])
+        np.testing.assert_array_equal(pk.outputs["var_x"], kr[1])
+    finally:
+        K.kry_problem_destroy(h)
+        K.kry_ctx_destroy(ctx)
