@@ -522,8 +522,9 @@ def ext_bench(args, K, synth, np):
                               ("irregular_1024sq_734k_cell_order", 1024, 734003, "cell")):
         g = (n, n, 1.0 / n, 1.0 / n)
         locs = synth.irregular_locations(g, p, seed=61)
-        if order == "cell":  # the caller lists observations by grid cell: coherent gathers
-            locs = locs[np.lexsort((np.floor(locs[:, 1]), np.floor(locs[:, 0])))]
+        if order == "cell":  # the caller lists observations by nearest grid cell, the library's stored order
+            near = np.minimum(np.floor(locs[:, 0] + 0.5), n - 1) * n + np.minimum(np.floor(locs[:, 1] + 0.5), n - 1)
+            locs = locs[np.argsort(near, kind="stable")]
         rng = np.random.default_rng(62)
         P = K.IrregularProblem(n, n, locs, rng.standard_normal(p))
         row = {"grid": n, "observations": p, "order": order}

@@ -1439,7 +1439,8 @@ static void ols_centre(const Problem& P, int q, const std::vector<double>& Xfull
     Xc.assign((size_t)q * p, 0.0);
     for (int j = 0; j < q; ++j)
         for (int64_t i = 0; i < p; ++i)  // irregular problems take the covariates per observation
-            Xc[(size_t)j * p + i] = P.irregular ? Xfull[(size_t)j * p + i] : Xfull[(size_t)j * n + (*P.h_cell)[i]];
+            Xc[(size_t)j * p + i] = P.irregular ? Xfull[(size_t)j * p + (*P.h_obs_user)[i]]
+                                                : Xfull[(size_t)j * n + (*P.h_cell)[i]];
     std::vector<double> A((size_t)q * q, 0.0), b(q, 0.0);
     for (int i = 0; i < q; ++i) {
         const double* xi = Xc.data() + (size_t)i * p;
@@ -1474,7 +1475,7 @@ static void upload_data(Problem& P, const double* y) {
     std::vector<double> yc(P.p, 0.0);
     if (y) {
         for (int64_t i = 0; i < P.p; ++i) {
-            const double v = P.irregular ? y[i] : y[(*P.h_cell)[i]];
+            const double v = P.irregular ? y[(*P.h_obs_user)[i]] : y[(*P.h_cell)[i]];
             KRY_REQUIRE(std::isfinite(v), "y has a non-finite value at an observed cell");
             yc[i] = v;
         }
@@ -1597,6 +1598,19 @@ kry_status kry_problem_create_irregular(kry_ctx* ctx, const kry_grid* grid, int6
                         "observation locations must lie in [0, n1 - 1] x [0, n2 - 1] (grid units)");
             if (y) KRY_REQUIRE(std::isfinite(y[i]), "y has a non-finite value");
         }
+        // stored order: by nearest grid cell, ties in the caller's order
+        auto nearest = [&](int64_t i) {
+            const int ra = std::min((int)std::lround(locs[2 * i]), n1 - 1);
+            const int rb = std::min((int)std::lround(locs[2 * i + 1]), n2 - 1);
+            return (int64_t)ra * n2 + rb;
+        };
+        auto order = std::make_shared<std::vector<int32_t>>(p);
+        {
+            std::vector<int64_t> key(p);
+            for (int64_t i = 0; i < p; ++i) key[i] = nearest(i);
+            std::iota(order->begin(), order->end(), 0);
+            std::stable_sort(order->begin(), order->end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+        }
         // A: the Wendland weights of the corners of each observation's cell
         // (Sec. 2), normalised; A^T by rows over the cells
         std::vector<int32_t> cell4((size_t)4 * p, -1), near(p);
@@ -1604,7 +1618,8 @@ kry_status kry_problem_create_irregular(kry_ctx* ctx, const kry_grid* grid, int6
         std::vector<int32_t> cnt(n + 1, 0);
         auto hc = std::make_shared<std::vector<int64_t>>(p);
         for (int64_t i = 0; i < p; ++i) {
-            const double u1 = locs[2 * i], u2 = locs[2 * i + 1];
+            const int64_t u = (*order)[i];
+            const double u1 = locs[2 * u], u2 = locs[2 * u + 1];
             const int a0 = std::min((int)std::floor(u1), n1 - 1), b0 = std::min((int)std::floor(u2), n2 - 1);
             double sum = 0;
             int s = 0;
@@ -1626,8 +1641,7 @@ kry_status kry_problem_create_irregular(kry_ctx* ctx, const kry_grid* grid, int6
                 w4[4 * i + k] /= sum;
                 ++cnt[cell4[4 * i + k] + 1];
             }
-            const int ra = std::min((int)std::lround(u1), n1 - 1), rb = std::min((int)std::lround(u2), n2 - 1);
-            near[i] = ra * n2 + rb;
+            near[i] = (int32_t)nearest(u);
             (*hc)[i] = near[i];
         }
         for (int64_t c = 0; c < n; ++c) cnt[c + 1] += cnt[c];
@@ -1656,12 +1670,15 @@ kry_status kry_problem_create_irregular(kry_ctx* ctx, const kry_grid* grid, int6
             P.p = p;
             P.irregular = true;
             P.h_cell = hc;
+            P.h_obs_user = order;
+            for (int64_t i = 0; i < p && !P.obs_permuted; ++i) P.obs_permuted = (*order)[i] != i;
             P.h_mask = std::make_shared<std::vector<uint8_t>>(n, 0);
             auto up = [&](DevBuf& b, const void* src, size_t bytes) {
                 b.ensure(ctx->c, bytes);
                 KRY_HIP(hipMemcpy(b.ptr, src, bytes, hipMemcpyHostToDevice));
             };
             up(P.cell, near.data(), p * sizeof(int32_t));
+            up(P.obs_user, order->data(), p * sizeof(int32_t));
             up(P.a_cell, cell4.data(), cell4.size() * sizeof(int32_t));
             up(P.a_w, w4.data(), w4.size() * sizeof(double));
             up(P.at_off, cnt.data(), cnt.size() * sizeof(int32_t));
@@ -1730,7 +1747,7 @@ void kry_problem_destroy(kry_problem* prob) {
         (void)hipSetDevice(c.device);
         (void)hipStreamSynchronize(c.stream);
         for (DevBuf* b : {&P.bits, &P.base, &P.cell, &P.y64, &P.y32, &P.X64, &P.yc64, &P.a_cell, &P.a_w, &P.at_off,
-                          &P.at_obs, &P.at_w})
+                          &P.at_obs, &P.at_w, &P.obs_user})
             b->release(c);
         P.release_work();
     }
@@ -1797,6 +1814,16 @@ static void matvec_dev_impl(Problem& P, const Matern& th, int nvec, const void* 
     P.scal.ensure(*P.ctx, 256);
     KRY_HIP(hipMemcpyAsync(P.scal.ptr, &eta, sizeof(double), hipMemcpyHostToDevice, st));
     auto A = masked_op<R>(P, spec_ptr<R>(S), 0, nvec, P.scal.as<double>());
+    if (P.obs_permuted) {  // the caller's order to the stored order and back
+        const size_t vb = ((size_t)nvec * P.p * sizeof(R) + 255) & ~size_t(255);
+        P.tmp2.ensure(*P.ctx, 2 * vb);
+        R* a = P.tmp2.as<R>();
+        R* b = reinterpret_cast<R*>(P.tmp2.as<char>() + vb);
+        irr_permute<R>(P, static_cast<const R*>(in), a, nvec, true, st);
+        A(a, b, nvec, st, nullptr);
+        irr_permute<R>(P, b, static_cast<R*>(out), nvec, false, st);
+        return;
+    }
     A(static_cast<const R*>(in), static_cast<R*>(out), nvec, st, nullptr);
 }
 
@@ -1873,7 +1900,16 @@ kry_status kry_cov_apply_full(kry_problem* prob, const kry_matern* theta, int32_
         double* d_in = io.as<double>();
         double* d_out = d_in + nin;
         Spectrum& S = problem_spectrum(P, to_matern(theta), st);
-        KRY_HIP(hipMemcpyAsync(d_in, w, nin * sizeof(double), hipMemcpyHostToDevice, st));
+        if (P.obs_permuted) {  // the caller's order to the stored order
+            std::vector<double> ws(nin);
+            for (int v = 0; v < nvec; ++v)
+                for (int64_t i = 0; i < P.p; ++i)
+                    ws[(size_t)v * P.p + i] = w[(size_t)v * P.p + (*P.h_obs_user)[i]];
+            KRY_HIP(hipMemcpyAsync(d_in, ws.data(), nin * sizeof(double), hipMemcpyHostToDevice, st));
+            KRY_HIP(hipStreamSynchronize(st));
+        } else {
+            KRY_HIP(hipMemcpyAsync(d_in, w, nin * sizeof(double), hipMemcpyHostToDevice, st));
+        }
         if (precision == KRY_FP64) {
             cov_full<double>(P, S.s64.ptr, d_in, d_out, nvec, st);
         } else {
@@ -1911,6 +1947,12 @@ kry_status kry_probes(kry_problem* prob, const kry_opts* opts, int32_t* nprobe, 
                             tmp.as<double>(), st);
         KRY_HIP(hipMemcpyAsync(out, tmp.ptr, (size_t)np * P.p * sizeof(double), hipMemcpyDeviceToHost, st));
         KRY_HIP(hipStreamSynchronize(st));
+        if (P.obs_permuted) {  // the stored order to the caller's order
+            std::vector<double> h(out, out + (size_t)np * P.p);
+            for (int k = 0; k < np; ++k)
+                for (int64_t i = 0; i < P.p; ++i)
+                    out[(size_t)k * P.p + (*P.h_obs_user)[i]] = h[(size_t)k * P.p + i];
+        }
     });
 }
 
@@ -2046,12 +2088,25 @@ kry_status kry_solve(kry_problem* prob, const kry_matern* theta, const kry_opts*
         double* d_b = reinterpret_cast<double*>(io.as<char>() + 256);
         double* d_x = d_b + n;
         KRY_HIP(hipMemcpyAsync(d_eta, &eta, sizeof(double), hipMemcpyHostToDevice, st));
-        KRY_HIP(hipMemcpyAsync(d_b, b, n * sizeof(double), hipMemcpyHostToDevice, st));
+        std::vector<double> hb;
+        const double* bsrc = b;
+        if (P.obs_permuted) {  // the caller's order to the stored order
+            hb.resize(n);
+            for (int v = 0; v < nrhs; ++v)
+                for (int64_t i = 0; i < P.p; ++i) hb[(size_t)v * P.p + i] = b[(size_t)v * P.p + (*P.h_obs_user)[i]];
+            bsrc = hb.data();
+        }
+        KRY_HIP(hipMemcpyAsync(d_b, bsrc, n * sizeof(double), hipMemcpyHostToDevice, st));
         SolveStats ss;
         solve_device(P, opts->precision, S.s64.ptr, S.s32.ptr, 0, nrhs, d_eta, nrhs, d_b, d_x, opts->cg_rtol,
                      opts->cg_maxit, ss, st);
         KRY_HIP(hipMemcpyAsync(x, d_x, n * sizeof(double), hipMemcpyDeviceToHost, st));
         KRY_HIP(hipStreamSynchronize(st));
+        if (P.obs_permuted) {  // back to the caller's order
+            std::vector<double> hx(x, x + n);
+            for (int v = 0; v < nrhs; ++v)
+                for (int64_t i = 0; i < P.p; ++i) x[(size_t)v * P.p + (*P.h_obs_user)[i]] = hx[(size_t)v * P.p + i];
+        }
         for (int v = 0; v < nrhs; ++v) {
             if (iters) iters[v] = ss.iters[v];
             if (relres) relres[v] = ss.relres[v];
@@ -2781,7 +2836,7 @@ kry_status kry_bootstrap_theta(kry_problem* prob, const kry_matern* theta_hat, u
             const std::vector<double> beta = gls_beta(P, theta_hat, opts, nullptr, nullptr, st);
             for (int j = 0; j < P.q; ++j)
                 for (int64_t i = 0; i < p; ++i)
-                    mean[i] += beta[j] * (P.irregular ? (*P.h_X)[(size_t)j * p + i]
+                    mean[i] += beta[j] * (P.irregular ? (*P.h_X)[(size_t)j * p + (*P.h_obs_user)[i]]
                                                       : (*P.h_X)[(size_t)j * n + (*P.h_cell)[i]]);
         }
         // every simulated data set, as the prediction-variance bootstrap draws them

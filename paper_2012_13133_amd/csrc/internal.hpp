@@ -157,6 +157,12 @@ struct Problem {
     // each observation's nearest cell (coloured probes)
     bool irregular = false;
     DevBuf a_cell, a_w, at_off, at_obs, at_w;
+    // irregular problems store observations sorted by nearest grid cell (so
+    // the mapping's gathers are coherent); compact vectors at the ABI keep
+    // the caller's order: obs_user[i] = caller's index of stored observation i
+    DevBuf obs_user;
+    std::shared_ptr<const std::vector<int32_t>> h_obs_user;
+    bool obs_permuted = false;  // false when the caller's order already is the stored order
     std::shared_ptr<const std::vector<int64_t>> h_cell;  // compact index -> cell id (host)
     std::shared_ptr<const std::vector<uint8_t>> h_mask;
     bool is_view = false;
@@ -195,6 +201,9 @@ struct Problem {
         v.at_off = at_off;
         v.at_obs = at_obs;
         v.at_w = at_w;
+        v.obs_user = obs_user;
+        v.h_obs_user = h_obs_user;
+        v.obs_permuted = obs_permuted;
         v.q = q;
         v.X64 = X64;
         v.yc64 = yc64;

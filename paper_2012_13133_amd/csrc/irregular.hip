@@ -118,9 +118,21 @@ __global__ void k_irr_cross_corr(const double* __restrict__ lag, int N1, int N2,
     }
 }
 
+template <typename R>
+__global__ void k_irr_permute(const R* __restrict__ src, R* __restrict__ dst, const int32_t* __restrict__ user,
+                              int64_t p, int to_stored) {
+    const int v = blockIdx.y;
+    const R* s = src + (int64_t)v * p;
+    R* d = dst + (int64_t)v * p;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < p; i += (int64_t)gridDim.x * blockDim.x) {
+        if (to_stored) d[i] = s[user[i]];
+        else d[user[i]] = s[i];
+    }
+}
+
 __global__ void k_irr_boot_obs(const double* __restrict__ fields, int64_t n, const int32_t* __restrict__ cell4,
-                               const double* __restrict__ w4, int64_t p, double tau, uint64_t seed,
-                               double* __restrict__ yb) {
+                               const double* __restrict__ w4, const int32_t* __restrict__ user, int64_t p,
+                               double tau, uint64_t seed, double* __restrict__ yb) {
     const int b = blockIdx.y;
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < p; j += (int64_t)gridDim.x * blockDim.x) {
         double acc = 0.0;
@@ -128,7 +140,7 @@ __global__ void k_irr_boot_obs(const double* __restrict__ fields, int64_t n, con
             const int c = cell4[4 * j + s];
             if (c >= 0) acc += w4[4 * j + s] * fields[(int64_t)b * n + c];
         }
-        yb[(int64_t)b * p + j] = acc + tau * philox_normal((uint32_t)j, (uint32_t)b, DOMAIN_NOISE, seed);
+        yb[(int64_t)b * p + j] = acc + tau * philox_normal((uint32_t)user[j], (uint32_t)b, DOMAIN_NOISE, seed);
     }
 }
 
@@ -211,8 +223,17 @@ void irr_cross_corr(const Problem& P, const double* lag, const int64_t* targets,
 void irr_boot_obs(const Problem& P, const double* fields, int B, double tau, uint64_t seed, double* yb,
                   hipStream_t st) {
     hipLaunchKernelGGL(k_irr_boot_obs, vgrid(P.p, B), dim3(256), 0, st, fields, (int64_t)P.n1 * P.n2,
-                       P.a_cell.as<int32_t>(), P.a_w.as<double>(), P.p, tau, seed, yb);
+                       P.a_cell.as<int32_t>(), P.a_w.as<double>(), P.obs_user.as<int32_t>(), P.p, tau, seed, yb);
     KRY_HIP(hipGetLastError());
 }
+
+template <typename R>
+void irr_permute(const Problem& P, const R* src, R* dst, int nvec, bool to_stored, hipStream_t st) {
+    hipLaunchKernelGGL(k_irr_permute<R>, vgrid(P.p, nvec), dim3(256), 0, st, src, dst, P.obs_user.as<int32_t>(), P.p,
+                       to_stored ? 1 : 0);
+    KRY_HIP(hipGetLastError());
+}
+template void irr_permute<double>(const Problem&, const double*, double*, int, bool, hipStream_t);
+template void irr_permute<float>(const Problem&, const float*, float*, int, bool, hipStream_t);
 
 }  // namespace kry

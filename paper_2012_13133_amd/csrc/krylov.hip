@@ -113,11 +113,12 @@ template void convert<double, double>(const double*, double*, int64_t, hipStream
 // Rademacher sign of (compact index, probe); coloured probes keep the sign
 // only on cells of colour k = (row mod c) + c (col mod c).
 template <typename R>
-__global__ void k_probes(const int32_t* __restrict__ cell, int64_t p, int n2, int nprobe, uint64_t seed,
-                         int period, R* __restrict__ out, int64_t stride) {
+__global__ void k_probes(const int32_t* __restrict__ cell, const int32_t* __restrict__ user, int64_t p, int n2,
+                         int nprobe, uint64_t seed, int period, R* __restrict__ out, int64_t stride) {
     const int k = blockIdx.y;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < p; i += (int64_t)gridDim.x * blockDim.x) {
-        double v = rademacher((uint32_t)i, (uint32_t)k, seed);
+        // the Philox index is the caller's observation index
+        double v = rademacher((uint32_t)(user ? user[i] : i), (uint32_t)k, seed);
         if (period > 0) {
             const int c = cell[i];
             const int row = c / n2, col = c - (c / n2) * n2;
@@ -130,8 +131,9 @@ __global__ void k_probes(const int32_t* __restrict__ cell, int64_t p, int n2, in
 
 template <typename R>
 void make_probes(const Problem& P, int nprobe, uint64_t seed, int period, R* out, hipStream_t st, int64_t stride) {
-    hipLaunchKernelGGL(k_probes<R>, vec_grid(P.p, nprobe), dim3(256), 0, st, P.cell.as<int32_t>(), P.p, P.n2, nprobe,
-                       seed, period, out, stride > 0 ? stride : P.p);
+    hipLaunchKernelGGL(k_probes<R>, vec_grid(P.p, nprobe), dim3(256), 0, st, P.cell.as<int32_t>(),
+                       P.irregular ? P.obs_user.as<int32_t>() : nullptr, P.p, P.n2, nprobe, seed, period, out,
+                       stride > 0 ? stride : P.p);
     KRY_HIP(hipGetLastError());
 }
 template void make_probes<double>(const Problem&, int, uint64_t, int, double*, hipStream_t, int64_t);

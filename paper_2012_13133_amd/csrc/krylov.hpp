@@ -84,7 +84,12 @@ void irr_gather(const Problem& P, const RI* grid, int nvec, RO* out, const RO* x
 // embedding lag grid (row-major N1 x N2).
 void irr_cross_corr(const Problem& P, const double* lag, const int64_t* targets, int nt, double* out,
                     hipStream_t st);
-// y_b = A x_b + tau eps_b (eps from Philox stream b, domain NOISE, index j).
+// dst[v][i] = src[v][obs_user[i]] (to the stored order; gather) or
+// dst[v][obs_user[i]] = src[v][i] (back to the caller's order).
+template <typename R>
+void irr_permute(const Problem& P, const R* src, R* dst, int nvec, bool to_stored, hipStream_t st);
+// y_b = A x_b + tau eps_b (eps from Philox stream b, domain NOISE, the
+// caller's observation index).
 void irr_boot_obs(const Problem& P, const double* fields, int B, double tau, uint64_t seed, double* yb,
                   hipStream_t st);
 

@@ -40,6 +40,40 @@ def test_product_matches_oracle():
         assert normwise(got32[i], ref[i]) <= 1e-5
 
 
+def test_caller_order_is_kept_at_every_entry_point():
+    # the library stores observations by nearest cell: the same observations
+    # given in cell order and in a shuffled order give the same results, in
+    # the caller's order
+    g, locs, A, y = _case(seed=21)
+    near = np.minimum(np.floor(locs[:, 0] + 0.5), 23) * 20 + np.minimum(np.floor(locs[:, 1] + 0.5), 19)
+    srt = np.argsort(near, kind="stable")
+    perm = np.random.default_rng(3).permutation(300)
+    V = synth.random_vectors(300, 2, seed=6)
+    th = K.theta_from_dict(TH)
+    opts = K.kry_opts_default(lanczos_steps=30, num_probes=4, reorth=1, cg_rtol=1e-11)
+    out = {}
+    for name, o in (("sorted", srt), ("shuffled", perm)):
+        with K.IrregularProblem(24, 20, locs[o], y[o]) as P:
+            inv = np.argsort(o)
+            out[name] = dict(
+                mv=K.kry_matvec(P.h, th, V[:, o], K.KRY_FP64)[:, inv],
+                x=K.kry_solve(P.h, th, opts, V[:, o])[0][:, inv],
+                ll=K.kry_loglik(P.h, th, opts),
+                pr=K.kry_probes(P.h, opts),
+                kr=K.kry_krige(P.h, th, opts, np.array([0, 77, 479])))
+    a, b = out["sorted"], out["shuffled"]
+    for i in range(2):
+        assert normwise(b["mv"][i], a["mv"][i]) <= 1e-13
+        assert normwise(b["x"][i], a["x"][i]) <= 1e-9
+    assert b["ll"]["quad"] == pytest.approx(a["ll"]["quad"], rel=1e-10)
+    # probes are drawn by the caller's index
+    Z = probe_matrix(np.zeros(300, dtype=np.int64), np.zeros(300, dtype=np.int64), 4, opts.seed).T
+    np.testing.assert_array_equal(a["pr"], Z)
+    np.testing.assert_array_equal(b["pr"], Z)
+    for u, v in zip(a["kr"], b["kr"]):
+        np.testing.assert_allclose(v, u, rtol=1e-8)
+
+
 def test_on_grid_locations_equal_the_masked_problem():
     n1, n2 = 20, 18
     mask = synth.uniform_mask(n1, n2, 0.3, seed=7)
