@@ -163,14 +163,20 @@ typedef struct {
     int32_t col_split;      /* 1: the column stage exchanges real and imaginary parts
                                through LDS separately (half the LDS per workgroup, more
                                workgroups per CU; columns of >= 256 points), 0: together */
+    int32_t row_split;      /* the row stages likewise, bit 0 the forward (first) stage,
+                               bit 1 the inverse (last) stage: 0..3 (rows of >= 1024
+                               points of the half-length complex transform)               */
     double ms;              /* kry_autotune: time of one product of nvec vectors        */
 } kry_tuning;
 
-/* Time every configuration on the problem's own embedding with a product of
- * nvec (1..4096) compact vectors in `precision`, keep the fastest for that
+/* Time configurations on the problem's own embedding with a product of nvec
+ * (1..4096) compact vectors in `precision`, keep the fastest for that
  * embedding and precision in the problem's context (used by every later
- * product there) and return it.  Each candidate runs 2 untimed and 5 timed
- * products (HIP events on the context's stream); ms is the fastest's median. */
+ * product there) and return it.  The row-stage fields are searched first
+ * (every combination, column stage at its default), then the column-stage
+ * fields with the best row setting.  Each candidate runs 2 untimed and 5
+ * timed products (HIP events on the context's stream); ms is the fastest's
+ * median. */
 kry_status kry_autotune(kry_problem* prob, int32_t precision, int32_t nvec, kry_tuning* out);
 /* Set (t != NULL) or reset to the built-in default (t == NULL) the
  * configuration used for embedding N1 x N2 in `precision` on this context;

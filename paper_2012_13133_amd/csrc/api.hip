@@ -2223,6 +2223,7 @@ void check_tuning(const kry_tuning* t) {
     KRY_REQUIRE(t->row_tile_scale == 1 || t->row_tile_scale == 2, "row_tile_scale must be 1 or 2");
     KRY_REQUIRE(t->row_vthreads == 1 || t->row_vthreads == 2, "row_vthreads must be 1 or 2");
     KRY_REQUIRE(t->col_split == 0 || t->col_split == 1, "col_split must be 0 or 1");
+    KRY_REQUIRE(t->row_split >= 0 && t->row_split <= 3, "row_split must be in 0..3");
 }
 
 kry_tuning to_abi(const Tuning& t, int real_bytes) {
@@ -2231,6 +2232,7 @@ kry_tuning to_abi(const Tuning& t, int real_bytes) {
     o.row_tile_scale = t.rt_scale;
     o.row_vthreads = t.row_vt;
     o.col_split = t.col_split;
+    o.row_split = t.row_split;
     o.ms = t.ms;
     return o;
 }
@@ -2240,20 +2242,23 @@ Tuning autotune_impl(Problem& P, int nvec, hipStream_t st) {
     Ctx& C = *P.ctx;
     const int rb = (int)sizeof(R);
     const auto key = std::make_tuple(P.N1, P.N2, rb);
-    std::vector<Tuning> cand;
-    for (int cv : {1, 2})
-        for (int rs : {1, 2})
-            for (int vt : {1, 2})
-                for (int cs : {0, 1}) {
-                    if (vt == 2 && P.N2 / 2 < 1024) continue;
-                    if (cs == 1 && P.N1 < 256) continue;
-                    Tuning t;
-                    t.col_v = cv;
-                    t.rt_scale = rs;
-                    t.row_vt = vt;
-                    t.col_split = cs;
-                    cand.push_back(t);
-                }
+    // The row stages' parameters (rows per tile, values per thread, split
+    // exchanges) and the column stage's (vectors per workgroup, split
+    // exchange) act on different kernels: the rows are tuned first with the
+    // column stage at its default, then the columns with the best rows.
+    const bool big_rows = P.N2 / 2 >= 1024;
+    std::vector<Tuning> rows_cand;
+    for (int rs : {1, 2})
+        for (int vt : {1, 2})
+            for (int rsp = 0; rsp < 4; ++rsp) {
+                if ((vt == 2 || rsp != 0) && !big_rows) continue;
+                Tuning t;
+                t.col_v = rb == 4 ? 2 : 1;
+                t.rt_scale = rs;
+                t.row_vt = vt;
+                t.row_split = rsp;
+                rows_cand.push_back(t);
+            }
     // inputs: Rademacher vectors on the problem and the spectrum of a fixed point
     const kry_matern th{1.0, 0.1, 0.1, 0.5, 1.0, 0.0};
     Spectrum& S = problem_spectrum(P, to_matern(&th), st);
@@ -2272,25 +2277,36 @@ Tuning autotune_impl(Problem& P, int nvec, hipStream_t st) {
     KRY_HIP(hipEventCreate(&e1));
     Tuning best;
     best.ms = 1e300;
-    try {
-        for (Tuning t : cand) {
-            {
-                std::lock_guard<std::mutex> g(C.tune_mu);
-                C.tuning[key] = t;
-            }
-            for (int w = 0; w < 2; ++w) A(in, outv, nvec, st, nullptr);
-            std::vector<float> ms(5);
-            for (float& m : ms) {
-                KRY_HIP(hipEventRecord(e0, st));
-                A(in, outv, nvec, st, nullptr);
-                KRY_HIP(hipEventRecord(e1, st));
-                KRY_HIP(hipEventSynchronize(e1));
-                KRY_HIP(hipEventElapsedTime(&m, e0, e1));
-            }
-            std::sort(ms.begin(), ms.end());
-            t.ms = ms[2];
-            if (t.ms < best.ms) best = t;
+    auto try_config = [&](Tuning t) {
+        {
+            std::lock_guard<std::mutex> g(C.tune_mu);
+            C.tuning[key] = t;
         }
+        for (int w = 0; w < 2; ++w) A(in, outv, nvec, st, nullptr);
+        std::vector<float> ms(5);
+        for (float& m : ms) {
+            KRY_HIP(hipEventRecord(e0, st));
+            A(in, outv, nvec, st, nullptr);
+            KRY_HIP(hipEventRecord(e1, st));
+            KRY_HIP(hipEventSynchronize(e1));
+            KRY_HIP(hipEventElapsedTime(&m, e0, e1));
+        }
+        std::sort(ms.begin(), ms.end());
+        t.ms = ms[2];
+        if (t.ms < best.ms) best = t;
+    };
+    try {
+        for (const Tuning& t : rows_cand) try_config(t);
+        const Tuning rows = best;
+        for (int cv : {1, 2})
+            for (int cs : {0, 1}) {
+                if (cs == 1 && P.N1 < 256) continue;
+                if (cv == rows.col_v && cs == rows.col_split) continue;  // timed in the first round
+                Tuning t = rows;
+                t.col_v = cv;
+                t.col_split = cs;
+                try_config(t);
+            }
     } catch (...) {
         hipEventDestroy(e0);
         hipEventDestroy(e1);
@@ -2345,6 +2361,7 @@ kry_status kry_set_tuning(kry_ctx* ctx, int32_t N1, int32_t N2, int32_t precisio
         u.rt_scale = t->row_tile_scale;
         u.row_vt = t->row_vthreads;
         u.col_split = t->col_split;
+        u.row_split = t->row_split;
         ctx->c.tuning[key] = u;
     });
 }

@@ -128,6 +128,12 @@ __global__ void k_lag_grid(double* __restrict__ c, int N1, int N2, MaternDev m) 
 // ---------------------------------------------------------------------------
 // Stage kernels (compile-time plans, register hand-off; see fftk.hpp)
 // ---------------------------------------------------------------------------
+
+// Largest workgroup of a row-stage kernel: rows of 8 VT values per thread;
+// FP32 kernels with two values sets per thread take tiles of 16 rows (128-byte
+// runs of the transposed intermediate) in 1024 threads, FP64 ones 512.
+template <typename R>
+constexpr int row_threads_max(int vt) { return vt > 1 && sizeof(R) == 8 ? 512 : 1024; }
 struct StageAArgs {
     const void* in;
     int64_t in_vstride;
@@ -179,8 +185,8 @@ __device__ __forceinline__ void load_pair(const StageAArgs& a, const MaskView& m
 // A row is transformed by TR = M / (8 VT) threads holding 8 VT values each;
 // when those lie in one wavefront the passes need no workgroup barrier, and
 // the only barrier is the one before the split, which mixes rows.
-template <typename R, int LOG2M, int IN, int VT>
-__global__ void __launch_bounds__((VT > 1 ? 512 : 1024), (VT > 1 ? 2 : (sizeof(R) == 4 && IN == IN_COMPACT ? 8 : 4))) k_row_fwd(StageAArgs a, const cpx<R>* __restrict__ twp,
+template <typename R, int LOG2M, int IN, int VT, bool SPLIT>
+__global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(R) == 4 && IN == IN_COMPACT ? 8 : 4))) k_row_fwd(StageAArgs a, const cpx<R>* __restrict__ twp,
                                                                    const cpx<R>* __restrict__ twb) {
     using S = Sched<LOG2M>;
     constexpr int M = S::L, T = M / 8, PM = padded(M) + 1;
@@ -253,6 +259,67 @@ __global__ void __launch_bounds__((VT > 1 ? 512 : 1024), (VT > 1 ? 2 : (sizeof(R
                 if (row < rows_in) load_pair<R, IN>(a, mask, row_len, vec, row, 2 * (t + u * TR + r * T), v[u * 8 + r]);
             }
     }
+    cpx<R>* Y = reinterpret_cast<cpx<R>*>(a.Y) + vec * a.Y_vstride;
+    if constexpr (SPLIT) {
+        // exchanges of reals (half the LDS per row); the split below reads
+        // the transform's real parts, then its imaginary parts
+        R* rl = reinterpret_cast<R*>(smem_raw);
+        R* rbuf = rl + rr * PM;
+#pragma unroll
+        for (int u = 0; u < VT; ++u) pass_compute<R, LOG2M, false, 0, LOW>(v + u * 8, t + u * TR, twp);
+        SplitPassesVT<R, LOG2M, false, 1, S::npass - 1, VT, WAVE>::run(v, rbuf, t, twp);
+        constexpr int PF = S::npass - 1;
+        constexpr int NO = 8 * VT;
+        // output i of this thread: row r2 = tid mod RT, k = k0 + i TR (the
+        // workgroup has RT TR threads); z_0 is copied to position M so that
+        // z_{M-k} needs no wrap.  s = z_k + conj(z_{M-k}), d = z_k - conj(z_{M-k})
+        // in parts; the Nyquist column k = M (s = 2 Re z_0 ...) by thread r2 < RT.
+        const int r2 = tid & (a.RT - 1), k0 = tid >> a.log2RT;
+        // padded positions: pad8(k0 + i TR) = pad8(k0) + i PTR and
+        // pad8(M - k0 - i TR) = pad8(M - k0) - i PTR, TR being a multiple of 8
+        constexpr int PTR = TR + TR / 8;
+        static_assert(TR % 8 == 0, "row threads must be a multiple of 8");
+        const R* bk = rl + r2 * PM + pad8(k0);
+        const R* bc = rl + r2 * PM + pad8(M - k0);
+        R sx[NO], dx[NO], nyx = (R)0, nydx = (R)0;
+        lds_sync<WAVE>();
+#pragma unroll
+        for (int u = 0; u < VT; ++u) pass_write_part<R, LOG2M, false, PF, 0>(v + u * 8, rbuf, t + u * TR);
+        if (t == 0) rbuf[pad8(M)] = v[0].x;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NO; ++i) {
+            const R zk = bk[i * PTR], zc = bc[-i * PTR];
+            sx[i] = zk + zc;
+            dx[i] = zk - zc;
+        }
+        if (tid < a.RT) {
+            const R z0 = rl[tid * PM];
+            nyx = z0 + z0;
+            nydx = z0 - z0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < VT; ++u) pass_write_part<R, LOG2M, false, PF, 1>(v + u * 8, rbuf, t + u * TR);
+        if (t == 0) rbuf[pad8(M)] = v[0].y;
+        __syncthreads();
+        cpx<R>* Yr = Y + row0 + r2;
+#pragma unroll
+        for (int i = 0; i < NO; ++i) {
+            const int k = k0 + i * TR;
+            const R zk = bk[i * PTR], zc = bc[-i * PTR];
+            const R sy = zk - zc, dy = zk + zc;
+            const cpx<R> wd = cmul(twiddle<R, false>(twb, k, LOG2M + 1), cpx<R>{dx[i], dy});
+            Yr[(int64_t)k * a.ldY] = cpx<R>{(R)0.5 * (sx[i] + wd.y), (R)0.5 * (sy - wd.x)};
+        }
+        if (tid < a.RT) {
+            const R z0 = rl[tid * PM];
+            const R sy = z0 - z0, dy = z0 + z0;
+            const cpx<R> wd = cmul(twiddle<R, false>(twb, M, LOG2M + 1), cpx<R>{nydx, dy});
+            Y[(int64_t)M * a.ldY + row0 + tid] = cpx<R>{(R)0.5 * (nyx + wd.y), (R)0.5 * (sy - wd.x)};
+        }
+        return;
+    }
 #pragma unroll
     for (int u = 0; u < VT; ++u) {
         pass_compute<R, LOG2M, false, 0, LOW>(v + u * 8, t + u * TR, twp);
@@ -264,7 +331,6 @@ __global__ void __launch_bounds__((VT > 1 ? 512 : 1024), (VT > 1 ? 2 : (sizeof(R
 
     // split Z into the real transform X[k] = (s - i w d) / 2, k = 0..M:
     // 8 VT outputs per thread for k < M plus the Nyquist column k = M
-    cpx<R>* Y = reinterpret_cast<cpx<R>*>(a.Y) + vec * a.Y_vstride;
     auto split = [&](int r2, int k, cpx<R> w) {
         const cpx<R>* bp = lds + r2 * PM;
         const cpx<R> zk = bp[pad8(k & (M - 1))];
@@ -449,8 +515,8 @@ struct StageCArgs {
 // then x[2m], x[2m+1] = Re, Im z[m] go to the observed cells (+ eta v) or the
 // grid.  Row threads as in stage A: one workgroup barrier after the tile
 // load; the merge is folded into the first pass's reads.
-template <typename R, int LOG2M, int OUT, int VT>
-__global__ void __launch_bounds__((VT > 1 ? 512 : 1024), (VT > 1 ? 2 : (sizeof(R) == 4 ? 8 : 4))) k_row_inv(StageCArgs a, const cpx<R>* __restrict__ twp,
+template <typename R, int LOG2M, int OUT, int VT, bool SPLIT>
+__global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(R) == 4 ? 8 : 4))) k_row_inv(StageCArgs a, const cpx<R>* __restrict__ twp,
                                                                    const cpx<R>* __restrict__ twb) {
     using S = Sched<LOG2M>;
     constexpr int M = S::L, T = M / 8, PM = padded(M) + 1;
@@ -506,69 +572,137 @@ __global__ void __launch_bounds__((VT > 1 ? 512 : 1024), (VT > 1 ? 2 : (sizeof(R
             }
         }
     }
-    // the tile holds RT x (M + 1) values: exactly NV per thread for k < M (all
-    // loads issued before any is used) plus the Nyquist column k = M
-    {
-        const int nt = blockDim.x;  // = RT * M / NV
+    cpx<R> v[NV];
+    if constexpr (SPLIT) {
+        // the tile through a buffer of reals (half the LDS per row): real
+        // parts, then imaginary parts, each merged as it is read; the passes
+        // exchange reals the same way
+        R* rl = reinterpret_cast<R*>(smem_raw);
+        R* rbuf = rl + rr * PM;
+        // tile value i of this thread: row r2 = tid mod RT, k = k0 + i TR
+        // (the workgroup has RT TR threads)
+        const int r2 = tid & (a.RT - 1), k0 = tid >> a.log2RT;
+        // padded positions pad8(k0 + i TR) = pad8(k0) + i PTR (TR a multiple of 8)
+        constexpr int PTR = TR + TR / 8;
+        static_assert(TR % 8 == 0, "row threads must be a multiple of 8");
+        R* tl = rl + r2 * PM + pad8(k0);
+        const bool rin = row0 + r2 < rows_out;
+        const cpx<R>* Yr = Y + row0 + r2;
         cpx<R> tv[NV];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            const int o = tid + i * nt;
-            const int r2 = o & (a.RT - 1);
-            const int k = o >> a.log2RT;
-            const int row = row0 + r2;
-            tv[i] = (row < rows_out) ? Y[(int64_t)k * a.ldY + row] : cpx<R>{(R)0, (R)0};
-        }
+        for (int i = 0; i < NV; ++i) tv[i] = rin ? Yr[(int64_t)(k0 + i * TR) * a.ldY] : cpx<R>{(R)0, (R)0};
         cpx<R> ny{(R)0, (R)0};
         if (tid < a.RT && row0 + tid < rows_out) ny = Y[(int64_t)M * a.ldY + row0 + tid];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            const int o = tid + i * nt;
-            lds[(o & (a.RT - 1)) * PM + pad8(o >> a.log2RT)] = tv[i];
-        }
-        if (tid < a.RT) lds[tid * PM + pad8(M)] = ny;
-    }
-    __syncthreads();
-    // The first inverse pass reads its inputs merged from the split half
-    // spectrum X of its row: Z[k] = (X[k] + X*[M-k]) + i W^{-k} (X[k] - X*[M-k])
-    // (X[M] is the Nyquist column), so no separate merge pass is needed.
-    cpx<R>* buf = lds + rr * PM;
-    auto merged = [&](int k) {
-        const cpx<R> xk = buf[pad8(k)];
-        const cpx<R> xm = buf[pad8(M - k)];
-        const cpx<R> s = cadd(xk, cconj(xm));
-        const cpx<R> d = cmul(twiddle<R, true>(twb, k, LOG2M + 1), csub(xk, cconj(xm)));
-        return cpx<R>{s.x - d.y, s.y + d.x};
-    };
-    cpx<R> v[NV];
-    {
+        for (int i = 0; i < NV; ++i) tl[i * PTR] = tv[i].x;
+        if (tid < a.RT) rl[tid * PM + pad8(M)] = ny.x;
+        __syncthreads();
+        // Z[k] = (X[k] + X*[M-k]) + i W^{-k} (X[k] - X*[M-k]) at the first
+        // inverse pass's input positions: s = X[k] + X*[M-k], e = X[k] - X*[M-k]
         constexpr int R0 = 1 << S::lr(true, 0);
         constexpr int Q0 = M / R0;
+        // positions k = t + c with c = u TR + b T + r Q0 a multiple of 8:
+        // pad8(t + c) = pad8(t) + pad_off(c), pad8(M - t - c) = pad8(M - t) - pad_off(c)
+        static_assert(TR % 8 == 0 && T % 8 == 0 && Q0 % 8 == 0, "merge offsets must be multiples of 8");
+        const R* rk = rbuf + pad8(t);
+        const R* rm = rbuf + pad8(M - t);
+        R sx[NV], ex[NV];
 #pragma unroll
         for (int u = 0; u < VT; ++u)
 #pragma unroll
-            for (int b = 0; b < 8 / R0; ++b) {
-                const int j = t + u * TR + b * T;
+            for (int b = 0; b < 8 / R0; ++b)
 #pragma unroll
-                for (int r = 0; r < R0; ++r) v[u * 8 + b * R0 + r] = merged(j + r * Q0);
-            }
-    }
-    if constexpr (S::npass == 1) {
+                for (int r = 0; r < R0; ++r) {
+                    const int c = u * TR + b * T + r * Q0, q = u * 8 + b * R0 + r;
+                    const R xk = rk[pad_off(c)], xm = rm[-pad_off(c)];
+                    sx[q] = xk + xm;
+                    ex[q] = xk - xm;
+                }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NV; ++i) tl[i * PTR] = tv[i].y;
+        if (tid < a.RT) rl[tid * PM + pad8(M)] = ny.y;
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < VT; ++u)
+#pragma unroll
+            for (int b = 0; b < 8 / R0; ++b)
+#pragma unroll
+                for (int r = 0; r < R0; ++r) {
+                    const int c = u * TR + b * T + r * Q0, q = u * 8 + b * R0 + r;
+                    const int k = t + c;
+                    const R xk = rk[pad_off(c)], xm = rm[-pad_off(c)];
+                    const R sy = xk - xm, ey = xk + xm;
+                    const cpx<R> d = cmul(twiddle<R, true>(twb, k, LOG2M + 1), cpx<R>{ex[q], ey});
+                    v[q] = cpx<R>{sx[q] - d.y, sy + d.x};
+                }
 #pragma unroll
         for (int u = 0; u < VT; ++u) pass_compute<R, LOG2M, true, 0>(v + u * 8, t + u * TR, twp);
+        SplitPassesVT<R, LOG2M, true, 1, S::npass - 1, VT, WAVE>::run(v, rbuf, t, twp);
     } else {
-        lds_sync<WAVE>();  // every read of X before the pass overwrites it
+        // the tile holds RT x (M + 1) values: exactly NV per thread for k < M (all
+        // loads issued before any is used) plus the Nyquist column k = M
+        {
+            const int nt = blockDim.x;  // = RT * M / NV
+            cpx<R> tv[NV];
 #pragma unroll
-        for (int u = 0; u < VT; ++u) {
-            pass_compute<R, LOG2M, true, 0>(v + u * 8, t + u * TR, twp);
-            pass_write<R, LOG2M, true, 0>(v + u * 8, buf, t + u * TR);
+            for (int i = 0; i < NV; ++i) {
+                const int o = tid + i * nt;
+                const int r2 = o & (a.RT - 1);
+                const int k = o >> a.log2RT;
+                const int row = row0 + r2;
+                tv[i] = (row < rows_out) ? Y[(int64_t)k * a.ldY + row] : cpx<R>{(R)0, (R)0};
+            }
+            cpx<R> ny{(R)0, (R)0};
+            if (tid < a.RT && row0 + tid < rows_out) ny = Y[(int64_t)M * a.ldY + row0 + tid];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                const int o = tid + i * nt;
+                lds[(o & (a.RT - 1)) * PM + pad8(o >> a.log2RT)] = tv[i];
+            }
+            if (tid < a.RT) lds[tid * PM + pad8(M)] = ny;
         }
-        lds_sync<WAVE>();
-        LdsPassesVT<R, LOG2M, true, 1, S::npass - 1, VT, WAVE>::run(v, buf, t, twp);
+        __syncthreads();
+        // The first inverse pass reads its inputs merged from the split half
+        // spectrum X of its row: Z[k] = (X[k] + X*[M-k]) + i W^{-k} (X[k] - X*[M-k])
+        // (X[M] is the Nyquist column), so no separate merge pass is needed.
+        cpx<R>* buf = lds + rr * PM;
+        auto merged = [&](int k) {
+            const cpx<R> xk = buf[pad8(k)];
+            const cpx<R> xm = buf[pad8(M - k)];
+            const cpx<R> s = cadd(xk, cconj(xm));
+            const cpx<R> d = cmul(twiddle<R, true>(twb, k, LOG2M + 1), csub(xk, cconj(xm)));
+            return cpx<R>{s.x - d.y, s.y + d.x};
+        };
+        {
+            constexpr int R0 = 1 << S::lr(true, 0);
+            constexpr int Q0 = M / R0;
 #pragma unroll
-        for (int u = 0; u < VT; ++u) pass_read<R, LOG2M, true, S::npass - 1>(v + u * 8, buf, t + u * TR);
+            for (int u = 0; u < VT; ++u)
 #pragma unroll
-        for (int u = 0; u < VT; ++u) pass_compute<R, LOG2M, true, S::npass - 1>(v + u * 8, t + u * TR, twp);
+                for (int b = 0; b < 8 / R0; ++b) {
+                    const int j = t + u * TR + b * T;
+#pragma unroll
+                    for (int r = 0; r < R0; ++r) v[u * 8 + b * R0 + r] = merged(j + r * Q0);
+                }
+        }
+        if constexpr (S::npass == 1) {
+#pragma unroll
+            for (int u = 0; u < VT; ++u) pass_compute<R, LOG2M, true, 0>(v + u * 8, t + u * TR, twp);
+        } else {
+            lds_sync<WAVE>();  // every read of X before the pass overwrites it
+#pragma unroll
+            for (int u = 0; u < VT; ++u) {
+                pass_compute<R, LOG2M, true, 0>(v + u * 8, t + u * TR, twp);
+                pass_write<R, LOG2M, true, 0>(v + u * 8, buf, t + u * TR);
+            }
+            lds_sync<WAVE>();
+            LdsPassesVT<R, LOG2M, true, 1, S::npass - 1, VT, WAVE>::run(v, buf, t, twp);
+#pragma unroll
+            for (int u = 0; u < VT; ++u) pass_read<R, LOG2M, true, S::npass - 1>(v + u * 8, buf, t + u * TR);
+#pragma unroll
+            for (int u = 0; u < VT; ++u) pass_compute<R, LOG2M, true, S::npass - 1>(v + u * 8, t + u * TR, twp);
+        }
     }
     if (row >= rows_out) return;
     const int theta = (a.vec0 + vec) / a.vecs_per_theta;
@@ -707,10 +841,10 @@ struct RowTiling {
 // where the workgroup and LDS allow; more rows for short rows.  Each thread
 // holds 8 vt values of its row.
 template <typename R>
-static RowTiling row_tiling(int M, int rt_scale = 1, int vt = 1) {
+static RowTiling row_tiling(int M, int rt_scale = 1, int vt = 1, bool split = false) {
     const size_t cs = sizeof(cpx<R>);
     const int T = M / 8 / vt;  // threads per row
-    const int tmax = vt > 1 ? 512 : 1024;
+    const int tmax = row_threads_max<R>(vt);
     const size_t PM = (size_t)M + M / 8 + 1;
     int RT = (int)(64 * rt_scale / cs);
     while (RT > 1 && RT * T > tmax) RT /= 2;
@@ -720,7 +854,7 @@ static RowTiling row_tiling(int M, int rt_scale = 1, int vt = 1) {
     t.RT = RT;
     t.T = T;
     t.threads = RT * T;
-    t.lds = RT * PM * cs;
+    t.lds = RT * PM * (split ? sizeof(R) : cs);  // split exchanges: a buffer of reals
     return t;
 }
 
@@ -729,10 +863,12 @@ template <int LG>
 constexpr bool has_vt2() { return LG >= 10; }
 
 template <typename R, int LG, int IN>
-static void launch_row_fwd(const StageAArgs& a, dim3 grid, const RowTiling& t, int vt, Ctx& c, hipStream_t st) {
-    auto k = k_row_fwd<R, LG, IN, 1>;
+static void launch_row_fwd(const StageAArgs& a, dim3 grid, const RowTiling& t, int vt, bool split, Ctx& c,
+                           hipStream_t st) {
+    auto k = k_row_fwd<R, LG, IN, 1, false>;
     if constexpr (has_vt2<LG>()) {
-        if (vt == 2) k = k_row_fwd<R, LG, IN, 2>;
+        if (vt == 2) k = k_row_fwd<R, LG, IN, 2, false>;
+        if (split) k = vt == 2 ? k_row_fwd<R, LG, IN, 2, true> : k_row_fwd<R, LG, IN, 1, true>;
     }
     set_lds(k, t.lds);
     hipLaunchKernelGGL(k, grid, dim3(t.threads), t.lds, st, a, plan_table<R>(c, LG), twiddles<R>(c));
@@ -740,10 +876,12 @@ static void launch_row_fwd(const StageAArgs& a, dim3 grid, const RowTiling& t, i
 }
 
 template <typename R, int LG, int OUT>
-static void launch_row_inv(const StageCArgs& a, dim3 grid, const RowTiling& t, int vt, Ctx& c, hipStream_t st) {
-    auto k = k_row_inv<R, LG, OUT, 1>;
+static void launch_row_inv(const StageCArgs& a, dim3 grid, const RowTiling& t, int vt, bool split, Ctx& c,
+                           hipStream_t st) {
+    auto k = k_row_inv<R, LG, OUT, 1, false>;
     if constexpr (has_vt2<LG>()) {
-        if (vt == 2) k = k_row_inv<R, LG, OUT, 2>;
+        if (vt == 2) k = k_row_inv<R, LG, OUT, 2, false>;
+        if (split) k = vt == 2 ? k_row_inv<R, LG, OUT, 2, true> : k_row_inv<R, LG, OUT, 1, true>;
     }
     set_lds(k, t.lds);
     hipLaunchKernelGGL(k, grid, dim3(t.threads), t.lds, st, a, plan_table<R>(c, LG), twiddles<R>(c));
@@ -788,7 +926,7 @@ static void launch_col(const StageBArgs& b, int nvec, int V, bool split, Ctx& c,
 
 template <typename R>
 static void run_stage_a(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R>* Y, int ldY, int64_t Yvs,
-                        const RowTiling& t, int vt, hipStream_t st) {
+                        const RowTiling& t, int vt, bool split, hipStream_t st) {
     const int M = s.N2 / 2;
     StageAArgs a;
     a.in = (const void*)((const R*)s.in + vec0 * s.in_vstride);
@@ -814,9 +952,9 @@ static void run_stage_a(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R
     Ctx& c = *P.ctx;
 #define KRY_A(LG)                                                                             \
     case LG:                                                                                  \
-        if (s.in_mode == IN_COMPACT) launch_row_fwd<R, LG, IN_COMPACT>(a, grid, t, vt, c, st);\
-        else if (s.in_mode == IN_DENSE) launch_row_fwd<R, LG, IN_DENSE>(a, grid, t, vt, c, st);\
-        else launch_row_fwd<R, LG, IN_NOISE>(a, grid, t, vt, c, st);                          \
+        if (s.in_mode == IN_COMPACT) launch_row_fwd<R, LG, IN_COMPACT>(a, grid, t, vt, split, c, st);\
+        else if (s.in_mode == IN_DENSE) launch_row_fwd<R, LG, IN_DENSE>(a, grid, t, vt, split, c, st);\
+        else launch_row_fwd<R, LG, IN_NOISE>(a, grid, t, vt, split, c, st);                   \
         break;
     switch (lg) {
         KRY_SIZES(KRY_A)
@@ -865,7 +1003,7 @@ static void run_stage_b(Problem& P, int N1, int M, int vec0, int nvec, cpx<R>* Y
 
 template <typename R>
 static void run_stage_c(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R>* Y, int ldY, int64_t Yvs,
-                        const RowTiling& t, int vt, hipStream_t st) {
+                        const RowTiling& t, int vt, bool split, hipStream_t st) {
     const int M = s.N2 / 2;
     StageCArgs c;
     c.Y = Y;
@@ -892,8 +1030,8 @@ static void run_stage_c(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R
     Ctx& cx = *P.ctx;
 #define KRY_C(LG)                                                                             \
     case LG:                                                                                  \
-        if (s.out_mode == OUT_COMPACT) launch_row_inv<R, LG, OUT_COMPACT>(c, grid, t, vt, cx, st);\
-        else launch_row_inv<R, LG, OUT_GRID>(c, grid, t, vt, cx, st);                         \
+        if (s.out_mode == OUT_COMPACT) launch_row_inv<R, LG, OUT_COMPACT>(c, grid, t, vt, split, cx, st);\
+        else launch_row_inv<R, LG, OUT_GRID>(c, grid, t, vt, split, cx, st);                  \
         break;
     switch (lg) {
         KRY_SIZES(KRY_C)
@@ -919,7 +1057,10 @@ void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st) {
     const int vt = (M >= 1024 && tu.row_vt == 2) ? 2 : 1;
     // (two vectors per column workgroup only when there are two to pair)
     const int V = s.nvec < 2 ? 1 : (tu.col_v ? tu.col_v : (sizeof(R) == 4 ? 2 : 1));
-    const RowTiling ta = row_tiling<R>(M, tu.rt_scale, vt);
+    const bool asplit = M >= 1024 && (tu.row_split & 1) != 0;
+    const bool csplit = M >= 1024 && (tu.row_split & 2) != 0;
+    const RowTiling ta = row_tiling<R>(M, tu.rt_scale, vt, asplit);
+    const RowTiling tc = row_tiling<R>(M, tu.rt_scale, vt, csplit);  // same rows per tile
     const int rows_max = s.rows_in > s.rows_out ? s.rows_in : s.rows_out;
     const int ldY = ((rows_max + ta.RT - 1) / ta.RT) * ta.RT;
     const int64_t Yvs = (int64_t)(M + 1) * ldY;
@@ -944,12 +1085,12 @@ void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st) {
             KRY_HIP(hipEventRecord(pr.pool[pr.next++], st));
         };
         mark(0);
-        run_stage_a<R>(P, s, v0, nv, Y, ldY, Yvs, ta, vt, st);
+        run_stage_a<R>(P, s, v0, nv, Y, ldY, Yvs, ta, vt, asplit, st);
         mark(1);
         run_stage_b<R>(P, s.N1, M, v0, nv, Y, ldY, Yvs, s.rows_in, s.rows_out, s.lam, s.lam_tstride,
                        s.vecs_per_theta, nullptr, st, s.tab, s.tab_vpp, s.active, V, tu.col_split != 0);
         mark(2);
-        run_stage_c<R>(P, s, v0, nv, Y, ldY, Yvs, ta, vt, st);
+        run_stage_c<R>(P, s, v0, nv, Y, ldY, Yvs, tc, vt, csplit, st);
         mark(3);
         if (pr.on) {
             rec[4] = nv;
@@ -1041,7 +1182,7 @@ void spectrum_device(Problem& P, int N1, int N2, const Matern& th, double* d_lam
     s.in_rstride = N2;
     s.rows_in = N1;
     s.row_len = N2;
-    run_stage_a<double>(P, s, 0, 1, Y, ldY, Yvs, ta, 1, st);
+    run_stage_a<double>(P, s, 0, 1, Y, ldY, Yvs, ta, 1, false, st);
     run_stage_b<double>(P, N1, M, 0, 1, Y, ldY, Yvs, N1, N1, nullptr, 0, 1, d_lam, st);
     // min / max
     double* part = reinterpret_cast<double*>(reinterpret_cast<char*>(P.spectmp.ptr) + (size_t)Yvs * sizeof(cpx<double>));

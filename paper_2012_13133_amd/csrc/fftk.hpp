@@ -347,4 +347,42 @@ struct LdsPassesVT {
     }
 };
 
+// Split exchange for one transform handled by TR = T / VT threads (thread t
+// acting for the virtual threads t + u TR), as LdsPassesVT: real parts, then
+// imaginary parts, through a buffer of reals (padded L).
+template <typename R, int LOG2L, bool INV, int PW, int VT, bool WAVE>
+__device__ __forceinline__ void exchange_split_vt(cpx<R>* v, R* buf, int t) {
+    constexpr int TR = (1 << LOG2L) / 8 / VT;
+    lds_sync<WAVE>();
+#pragma unroll
+    for (int u = 0; u < VT; ++u) pass_write_part<R, LOG2L, INV, PW, 0>(v + u * 8, buf, t + u * TR);
+    lds_sync<WAVE>();
+#pragma unroll
+    for (int u = 0; u < VT; ++u) pass_read_part<R, LOG2L, INV, PW + 1, 0>(v + u * 8, buf, t + u * TR);
+    lds_sync<WAVE>();
+#pragma unroll
+    for (int u = 0; u < VT; ++u) pass_write_part<R, LOG2L, INV, PW, 1>(v + u * 8, buf, t + u * TR);
+    lds_sync<WAVE>();
+#pragma unroll
+    for (int u = 0; u < VT; ++u) pass_read_part<R, LOG2L, INV, PW + 1, 1>(v + u * 8, buf, t + u * TR);
+}
+
+// Passes P..PE after pass P - 1 was computed in registers, with split
+// exchanges between them (one transform, VT virtual threads per thread).
+template <typename R, int LOG2L, bool INV, int P, int PE, int VT, bool WAVE>
+struct SplitPassesVT {
+    __device__ __forceinline__ static void run(cpx<R>* v, R* buf, int t, const cpx<R>* __restrict__ tw) {
+        if constexpr (P <= PE) {
+            constexpr int TR = (1 << LOG2L) / 8 / VT;
+            PassTw<R, LOG2L, INV, P> w[VT];
+#pragma unroll
+            for (int u = 0; u < VT; ++u) w[u] = pass_twiddles<R, LOG2L, INV, P>(t + u * TR, tw);
+            exchange_split_vt<R, LOG2L, INV, P - 1, VT, WAVE>(v, buf, t);
+#pragma unroll
+            for (int u = 0; u < VT; ++u) pass_compute_tw<R, LOG2L, INV, P>(v + u * 8, w[u]);
+            SplitPassesVT<R, LOG2L, INV, P + 1, PE, VT, WAVE>::run(v, buf, t, tw);
+        }
+    }
+};
+
 }  // namespace kry

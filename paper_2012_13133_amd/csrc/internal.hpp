@@ -51,6 +51,7 @@ struct Tuning {
     int rt_scale = 1;
     int row_vt = 1;
     int col_split = 0;   // column stage exchanges real and imaginary parts separately
+    int row_split = 0;   // row stages likewise: bit 0 stage A, bit 1 stage C (rows of >= 1024 points)
     double ms = 0.0;
 };
 

@@ -77,7 +77,7 @@ class kry_plik_result(C.Structure):
 
 class kry_tuning(C.Structure):
     _fields_ = [("col_vectors", C.c_int32), ("row_tile_scale", C.c_int32), ("row_vthreads", C.c_int32),
-                ("col_split", C.c_int32), ("ms", C.c_double)]
+                ("col_split", C.c_int32), ("row_split", C.c_int32), ("ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -418,12 +418,13 @@ def kry_autotune(prob, precision, nvec=32):
     return t.as_dict()
 
 
-def kry_set_tuning(ctx, N1, N2, precision, col_vectors=None, row_tile_scale=1, row_vthreads=1, col_split=0):
+def kry_set_tuning(ctx, N1, N2, precision, col_vectors=None, row_tile_scale=1, row_vthreads=1, col_split=0,
+                   row_split=0):
     """col_vectors None resets the configuration to the built-in default."""
     if col_vectors is None:
         _check(lib.kry_set_tuning(ctx, N1, N2, precision, None))
     else:
-        t = kry_tuning(col_vectors, row_tile_scale, row_vthreads, col_split, 0.0)
+        t = kry_tuning(col_vectors, row_tile_scale, row_vthreads, col_split, row_split, 0.0)
         _check(lib.kry_set_tuning(ctx, N1, N2, precision, C.byref(t)))
 
 

@@ -65,7 +65,7 @@ def test_host_side_paths_without_gpu():
     # shift sharing is off by default; tuning, graphs and the multi-problem
     # call reject NULL handles before any device work
     assert o.shift_share == 0
-    t = K.kry_tuning(2, 1, 1, 0, 0.0)
+    t = K.kry_tuning(2, 1, 1, 0, 0, 0.0)
     assert K.lib.kry_set_tuning(None, 64, 64, 1, ctypes.byref(t)) == K.KRY_EINVAL
     assert K.lib.kry_get_tuning(None, 64, 64, 1, ctypes.byref(t)) == K.KRY_EINVAL
     assert K.lib.kry_set_graphs(None, 1) == K.KRY_EINVAL

@@ -22,13 +22,23 @@ def test_every_configuration_is_bit_identical(shape):
     th = K.theta_from_dict(TH)
     with K.Problem(n1, n2, mask) as P:
         v = synth.random_vectors(P.p, 3, seed=4)
+        w = synth.random_vectors(P.p, 2, seed=6)
+
+        def outputs(prec):
+            # compact in and out (the product), compact in and grid out (the
+            # full-grid covariance product); the FP64 sampler (noise in, grid out)
+            out = [K.kry_matvec(P.h, th, v, prec), K.kry_cov_apply_full(P.h, th, w, n1 * n2, prec)]
+            if prec == K.KRY_FP64:
+                out.append(K.kry_sample(P.h, th, P.N1, P.N2, 9, 0, 2, n1, n2)[0])
+            return out
+
         for prec in (K.KRY_FP64, K.KRY_FP32):
             K.kry_set_tuning(P.ctx, P.N1, P.N2, prec)
-            ref = K.kry_matvec(P.h, th, v, prec)
-            for cv, rs, vt, cs in itertools.product((1, 2), (1, 2), (1, 2), (0, 1)):
-                K.kry_set_tuning(P.ctx, P.N1, P.N2, prec, cv, rs, vt, cs)
-                got = K.kry_matvec(P.h, th, v, prec)
-                assert np.array_equal(got, ref), (prec, cv, rs, vt, cs)
+            ref = outputs(prec)
+            for cv, rs, vt, cs, rsp in itertools.product((1, 2), (1, 2), (1, 2), (0, 1), (0, 1, 2, 3)):
+                K.kry_set_tuning(P.ctx, P.N1, P.N2, prec, cv, rs, vt, cs, rsp)
+                for i, (got, r) in enumerate(zip(outputs(prec), ref)):
+                    assert np.array_equal(got, r), (prec, i, cv, rs, vt, cs, rsp)
             K.kry_set_tuning(P.ctx, P.N1, P.N2, prec)
 
 
@@ -39,7 +49,7 @@ def test_autotune_keeps_a_valid_configuration():
         for prec in (K.KRY_FP64, K.KRY_FP32):
             t = K.kry_autotune(P.h, prec, 8)
             assert t["col_vectors"] in (1, 2) and t["row_tile_scale"] in (1, 2) and t["row_vthreads"] in (1, 2)
-            assert t["col_split"] in (0, 1)
+            assert t["col_split"] in (0, 1) and t["row_split"] in (0, 1, 2, 3)
             assert t["ms"] > 0
             assert K.kry_get_tuning(P.ctx, P.N1, P.N2, prec) == t
             K.kry_set_tuning(P.ctx, P.N1, P.N2, prec)
@@ -51,5 +61,7 @@ def test_autotune_keeps_a_valid_configuration():
             K.kry_set_tuning(P.ctx, 100, P.N2, K.KRY_FP32, 1, 1, 1)
         with pytest.raises(K.KryError):
             K.kry_set_tuning(P.ctx, P.N1, P.N2, K.KRY_FP32, 1, 1, 1, 2)
+        with pytest.raises(K.KryError):
+            K.kry_set_tuning(P.ctx, P.N1, P.N2, K.KRY_FP32, 1, 1, 1, 0, 4)
         with pytest.raises(K.KryError):
             K.kry_autotune(P.h, K.KRY_FP32, 0)
