@@ -189,7 +189,7 @@ template <typename R, int LOG2M, int IN, int VT, bool SPLIT>
 __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(R) == 4 && IN == IN_COMPACT ? 8 : 4))) k_row_fwd(StageAArgs a, const cpx<R>* __restrict__ twp,
                                                                    const cpx<R>* __restrict__ twb) {
     using S = Sched<LOG2M>;
-    constexpr int M = S::L, T = M / 8, PM = padded(M) + 1;
+    constexpr int M = S::L, T = M / 8, PM = lpadded<cpx<R>>(M) + 1;
     constexpr int TR = T / VT;
     constexpr bool WAVE = TR <= 64;
     constexpr bool LOW = (IN == IN_COMPACT);  // row_len <= M: z[m] = 0 for m >= M/2
@@ -275,17 +275,17 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
         // z_{M-k} needs no wrap.  s = z_k + conj(z_{M-k}), d = z_k - conj(z_{M-k})
         // in parts; the Nyquist column k = M (s = 2 Re z_0 ...) by thread r2 < RT.
         const int r2 = tid & (a.RT - 1), k0 = tid >> a.log2RT;
-        // padded positions: pad8(k0 + i TR) = pad8(k0) + i PTR and
-        // pad8(M - k0 - i TR) = pad8(M - k0) - i PTR, TR being a multiple of 8
-        constexpr int PTR = TR + TR / 8;
-        static_assert(TR % 8 == 0, "row threads must be a multiple of 8");
-        const R* bk = rl + r2 * PM + pad8(k0);
-        const R* bc = rl + r2 * PM + pad8(M - k0);
+        // padded positions: lpad(k0 + i TR) = lpad(k0) + i PTR and
+        // lpad(M - k0 - i TR) = lpad(M - k0) - i PTR, TR being a multiple of the pad group
+        constexpr int PTR = lpad_off<R>(TR);
+        static_assert(TR % pad_group<R>() == 0, "row threads must be a multiple of the pad group");
+        const R* bk = rl + r2 * PM + lpad<R>(k0);
+        const R* bc = rl + r2 * PM + lpad<R>(M - k0);
         R sx[NO], dx[NO], nyx = (R)0, nydx = (R)0;
         lds_sync<WAVE>();
 #pragma unroll
         for (int u = 0; u < VT; ++u) pass_write_part<R, LOG2M, false, PF, 0>(v + u * 8, rbuf, t + u * TR);
-        if (t == 0) rbuf[pad8(M)] = v[0].x;
+        if (t == 0) rbuf[lpad<R>(M)] = v[0].x;
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < NO; ++i) {
@@ -301,7 +301,7 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < VT; ++u) pass_write_part<R, LOG2M, false, PF, 1>(v + u * 8, rbuf, t + u * TR);
-        if (t == 0) rbuf[pad8(M)] = v[0].y;
+        if (t == 0) rbuf[lpad<R>(M)] = v[0].y;
         __syncthreads();
         cpx<R>* Yr = Y + row0 + r2;
 #pragma unroll
@@ -333,8 +333,8 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
     // 8 VT outputs per thread for k < M plus the Nyquist column k = M
     auto split = [&](int r2, int k, cpx<R> w) {
         const cpx<R>* bp = lds + r2 * PM;
-        const cpx<R> zk = bp[pad8(k & (M - 1))];
-        const cpx<R> zc = cconj(bp[pad8((M - k) & (M - 1))]);
+        const cpx<R> zk = bp[lpad<cpx<R>>(k & (M - 1))];
+        const cpx<R> zc = cconj(bp[lpad<cpx<R>>((M - k) & (M - 1))]);
         const cpx<R> s = cadd(zk, zc);
         const cpx<R> wd = cmul(w, csub(zk, zc));
         Y[(int64_t)k * a.ldY + row0 + r2] = cpx<R>{(R)0.5 * (s.x + wd.y), (R)0.5 * (s.y - wd.x)};
@@ -375,7 +375,7 @@ struct StageBArgs {
 template <typename R, int LOG2L, int MODE, int V, bool SPLIT>
 __global__ void __launch_bounds__(((1 << LOG2L) / 8 > 256 ? (1 << LOG2L) / 8 : 256)) k_col(StageBArgs a, const cpx<R>* __restrict__ twp) {
     using S = Sched<LOG2L>;
-    constexpr int L = S::L, T = L / 8, PL = padded(L);
+    constexpr int L = S::L, T = L / 8, PL = lpadded<cpx<R>>(L);  // per transform (complex or reals)
     constexpr bool LOW = (MODE == B_LOW);
     constexpr int LRF = S::lr(false, S::npass - 1);  // last forward radix = first inverse radix
     extern __shared__ unsigned char smem_raw[];
@@ -519,7 +519,7 @@ template <typename R, int LOG2M, int OUT, int VT, bool SPLIT>
 __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(R) == 4 ? 8 : 4))) k_row_inv(StageCArgs a, const cpx<R>* __restrict__ twp,
                                                                    const cpx<R>* __restrict__ twb) {
     using S = Sched<LOG2M>;
-    constexpr int M = S::L, T = M / 8, PM = padded(M) + 1;
+    constexpr int M = S::L, T = M / 8, PM = lpadded<cpx<R>>(M) + 1;
     constexpr int TR = T / VT;
     constexpr bool WAVE = TR <= 64;
     constexpr int NV = 8 * VT;  // values per thread
@@ -582,10 +582,10 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
         // tile value i of this thread: row r2 = tid mod RT, k = k0 + i TR
         // (the workgroup has RT TR threads)
         const int r2 = tid & (a.RT - 1), k0 = tid >> a.log2RT;
-        // padded positions pad8(k0 + i TR) = pad8(k0) + i PTR (TR a multiple of 8)
-        constexpr int PTR = TR + TR / 8;
-        static_assert(TR % 8 == 0, "row threads must be a multiple of 8");
-        R* tl = rl + r2 * PM + pad8(k0);
+        // padded positions lpad(k0 + i TR) = lpad(k0) + i PTR (TR a multiple of the pad group)
+        constexpr int PTR = lpad_off<R>(TR);
+        static_assert(TR % pad_group<R>() == 0, "row threads must be a multiple of the pad group");
+        R* tl = rl + r2 * PM + lpad<R>(k0);
         const bool rin = row0 + r2 < rows_out;
         const cpx<R>* Yr = Y + row0 + r2;
         cpx<R> tv[NV];
@@ -595,17 +595,18 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
         if (tid < a.RT && row0 + tid < rows_out) ny = Y[(int64_t)M * a.ldY + row0 + tid];
 #pragma unroll
         for (int i = 0; i < NV; ++i) tl[i * PTR] = tv[i].x;
-        if (tid < a.RT) rl[tid * PM + pad8(M)] = ny.x;
+        if (tid < a.RT) rl[tid * PM + lpad<R>(M)] = ny.x;
         __syncthreads();
         // Z[k] = (X[k] + X*[M-k]) + i W^{-k} (X[k] - X*[M-k]) at the first
         // inverse pass's input positions: s = X[k] + X*[M-k], e = X[k] - X*[M-k]
         constexpr int R0 = 1 << S::lr(true, 0);
         constexpr int Q0 = M / R0;
-        // positions k = t + c with c = u TR + b T + r Q0 a multiple of 8:
-        // pad8(t + c) = pad8(t) + pad_off(c), pad8(M - t - c) = pad8(M - t) - pad_off(c)
-        static_assert(TR % 8 == 0 && T % 8 == 0 && Q0 % 8 == 0, "merge offsets must be multiples of 8");
-        const R* rk = rbuf + pad8(t);
-        const R* rm = rbuf + pad8(M - t);
+        // positions k = t + c with c = u TR + b T + r Q0 a multiple of the pad group:
+        // lpad(t + c) = lpad(t) + lpad_off(c), lpad(M - t - c) = lpad(M - t) - lpad_off(c)
+        constexpr int G = pad_group<R>();
+        static_assert(TR % G == 0 && T % G == 0 && Q0 % G == 0, "merge offsets must be multiples of the pad group");
+        const R* rk = rbuf + lpad<R>(t);
+        const R* rm = rbuf + lpad<R>(M - t);
         R sx[NV], ex[NV];
 #pragma unroll
         for (int u = 0; u < VT; ++u)
@@ -614,14 +615,14 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
 #pragma unroll
                 for (int r = 0; r < R0; ++r) {
                     const int c = u * TR + b * T + r * Q0, q = u * 8 + b * R0 + r;
-                    const R xk = rk[pad_off(c)], xm = rm[-pad_off(c)];
+                    const R xk = rk[lpad_off<R>(c)], xm = rm[-lpad_off<R>(c)];
                     sx[q] = xk + xm;
                     ex[q] = xk - xm;
                 }
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < NV; ++i) tl[i * PTR] = tv[i].y;
-        if (tid < a.RT) rl[tid * PM + pad8(M)] = ny.y;
+        if (tid < a.RT) rl[tid * PM + lpad<R>(M)] = ny.y;
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < VT; ++u)
@@ -631,7 +632,7 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
                 for (int r = 0; r < R0; ++r) {
                     const int c = u * TR + b * T + r * Q0, q = u * 8 + b * R0 + r;
                     const int k = t + c;
-                    const R xk = rk[pad_off(c)], xm = rm[-pad_off(c)];
+                    const R xk = rk[lpad_off<R>(c)], xm = rm[-lpad_off<R>(c)];
                     const R sy = xk - xm, ey = xk + xm;
                     const cpx<R> d = cmul(twiddle<R, true>(twb, k, LOG2M + 1), cpx<R>{ex[q], ey});
                     v[q] = cpx<R>{sx[q] - d.y, sy + d.x};
@@ -658,9 +659,9 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
 #pragma unroll
             for (int i = 0; i < NV; ++i) {
                 const int o = tid + i * nt;
-                lds[(o & (a.RT - 1)) * PM + pad8(o >> a.log2RT)] = tv[i];
+                lds[(o & (a.RT - 1)) * PM + lpad<cpx<R>>(o >> a.log2RT)] = tv[i];
             }
-            if (tid < a.RT) lds[tid * PM + pad8(M)] = ny;
+            if (tid < a.RT) lds[tid * PM + lpad<cpx<R>>(M)] = ny;
         }
         __syncthreads();
         // The first inverse pass reads its inputs merged from the split half
@@ -668,8 +669,8 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
         // (X[M] is the Nyquist column), so no separate merge pass is needed.
         cpx<R>* buf = lds + rr * PM;
         auto merged = [&](int k) {
-            const cpx<R> xk = buf[pad8(k)];
-            const cpx<R> xm = buf[pad8(M - k)];
+            const cpx<R> xk = buf[lpad<cpx<R>>(k)];
+            const cpx<R> xm = buf[lpad<cpx<R>>(M - k)];
             const cpx<R> s = cadd(xk, cconj(xm));
             const cpx<R> d = cmul(twiddle<R, true>(twb, k, LOG2M + 1), csub(xk, cconj(xm)));
             return cpx<R>{s.x - d.y, s.y + d.x};
@@ -845,7 +846,7 @@ static RowTiling row_tiling(int M, int rt_scale = 1, int vt = 1, bool split = fa
     const size_t cs = sizeof(cpx<R>);
     const int T = M / 8 / vt;  // threads per row
     const int tmax = row_threads_max<R>(vt);
-    const size_t PM = (size_t)M + M / 8 + 1;
+    const size_t PM = (size_t)M + M / 16 + 1;  // lpadded<cpx<R>>(M) + 1, as the kernels
     int RT = (int)(64 * rt_scale / cs);
     while (RT > 1 && RT * T > tmax) RT /= 2;
     while (RT > 1 && RT * PM * cs > 150 * 1024) RT /= 2;
@@ -891,7 +892,7 @@ static void launch_row_inv(const StageCArgs& a, dim3 grid, const RowTiling& t, i
 template <typename R, int LG, int MODE, int V, bool SPLIT>
 static void launch_col_v(const StageBArgs& b, int nvec, Ctx& c, hipStream_t st) {
     constexpr int L = 1 << LG, T = L / 8;
-    const size_t lds = (size_t)b.CB * V * padded(L) * (SPLIT ? sizeof(R) : sizeof(cpx<R>));
+    const size_t lds = (size_t)b.CB * V * lpadded<cpx<R>>(L) * (SPLIT ? sizeof(R) : sizeof(cpx<R>));
     dim3 grid((b.ncols + b.CB - 1) / b.CB, (nvec + V - 1) / V);
     auto k = k_col<R, LG, MODE, V, SPLIT>;
     set_lds(k, lds);

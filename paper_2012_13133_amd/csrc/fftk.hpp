@@ -16,15 +16,29 @@
 // positions j + r L/R and the first inverse pass (radix R, Ns = 1) reads the
 // same positions, a pointwise multiply between them needs no exchange.
 //
-// Values exchanged through LDS use the padded index i + i/8, which spreads
-// the stride-8 accesses of the radix-8 passes over the banks.
+// Values exchanged through LDS use a padded index, one unused slot after
+// every G elements: G = 16 for complex elements and 8-byte reals, 32 for
+// 4-byte reals.  With LDS banks of 4 bytes served 128 bytes per cycle, these
+// make the passes' strided writes and contiguous reads conflict-free for
+// transforms of 256 points and more (one slot per 8 elements left the
+// contiguous 8-byte reads two-way conflicted).
 #pragma once
 #include "fft.hpp"
 
 namespace kry {
 
-__device__ __forceinline__ int pad8(int i) { return i + (i >> 3); }
-constexpr int padded(int L) { return L + L / 8; }
+template <typename E>
+constexpr int pad_log2() { return sizeof(E) == 4 ? 5 : 4; }
+template <typename E>
+__device__ __forceinline__ int lpad(int i) { return i + (i >> pad_log2<E>()); }
+// lpad(base + d) = lpad(base) + lpad_off(d) when d is a multiple of the group
+// or (base mod G) + (d mod G) < G
+template <typename E>
+constexpr int lpad_off(int d) { return d + (d >> pad_log2<E>()); }
+template <typename E>
+constexpr int lpadded(int L) { return L + (L >> pad_log2<E>()); }
+template <typename E>
+constexpr int pad_group() { return 1 << pad_log2<E>(); }
 
 template <int LOG2L>
 struct Sched {
@@ -136,10 +150,6 @@ __device__ __forceinline__ void pass_compute(cpx<R>* v, int t, const cpx<R>* __r
     pass_compute_tw<R, LOG2L, INV, P, LOWHALF, V>(v, pass_twiddles<R, LOG2L, INV, P>(t, tw));
 }
 
-// Padded LDS offset of element base + d when base + d stays in the same
-// 8-aligned structure: the caller guarantees (base mod 8) + (d mod 8) < 8 or
-// d a multiple of 8, so pad8(base + d) = pad8(base) + d + d/8.
-constexpr int pad_off(int d) { return d + d / 8; }
 
 // Inputs of pass P from LDS (transform base `buf`).
 template <typename R, int LOG2L, bool INV, int P>
@@ -148,16 +158,17 @@ __device__ __forceinline__ void pass_read(cpx<R>* v, const cpx<R>* buf, int t) {
     constexpr int RADIX = 1 << S::lr(INV, P);
     constexpr int T = S::L / 8;
     constexpr int Q = S::L / RADIX;
+    using E = cpx<R>;
 #pragma unroll
     for (int b = 0; b < 8 / RADIX; ++b) {
         const int j = t + b * T;
-        if constexpr (Q % 8 == 0) {
-            const cpx<R>* p = buf + pad8(j);
+        if constexpr (Q % pad_group<E>() == 0) {
+            const cpx<R>* p = buf + lpad<E>(j);
 #pragma unroll
-            for (int r = 0; r < RADIX; ++r) v[b * RADIX + r] = p[pad_off(r * Q)];
+            for (int r = 0; r < RADIX; ++r) v[b * RADIX + r] = p[lpad_off<E>(r * Q)];
         } else {
 #pragma unroll
-            for (int r = 0; r < RADIX; ++r) v[b * RADIX + r] = buf[pad8(j + r * Q)];
+            for (int r = 0; r < RADIX; ++r) v[b * RADIX + r] = buf[lpad<E>(j + r * Q)];
         }
     }
 }
@@ -171,25 +182,27 @@ __device__ __forceinline__ void pass_write(const cpx<R>* v, cpx<R>* buf, int t) 
     constexpr int LNS = S::lns(INV, P);
     constexpr int NS = 1 << LNS;
     constexpr int T = S::L / 8;
-    // dst mod 8 = j mod NS when NS divides 8 and NS * RADIX is a multiple of 8
-    constexpr bool FAST = (NS % 8 == 0) || (8 % NS == 0 && (NS * RADIX) % 8 == 0);
+    using E = cpx<R>;
+    constexpr int G = pad_group<E>();
+    // dst mod G = j mod NS when NS divides G and NS * RADIX is a multiple of G
+    constexpr bool FAST = (NS % G == 0) || (G % NS == 0 && (NS * RADIX) % G == 0);
 #pragma unroll
     for (int b = 0; b < 8 / RADIX; ++b) {
         const int j = t + b * T;
         const int dst = ((j >> LNS) << (LNS + LR)) + (j & (NS - 1));
         if constexpr (FAST) {
-            cpx<R>* p = buf + pad8(dst);
+            cpx<R>* p = buf + lpad<E>(dst);
 #pragma unroll
-            for (int r = 0; r < RADIX; ++r) p[pad_off(r * NS)] = v[b * RADIX + r];
+            for (int r = 0; r < RADIX; ++r) p[lpad_off<E>(r * NS)] = v[b * RADIX + r];
         } else {
 #pragma unroll
-            for (int r = 0; r < RADIX; ++r) buf[pad8(dst + r * NS)] = v[b * RADIX + r];
+            for (int r = 0; r < RADIX; ++r) buf[lpad<E>(dst + r * NS)] = v[b * RADIX + r];
         }
     }
 }
 
 // ---- split exchange: real parts, then imaginary parts, through a buffer of
-// reals (padded L per transform).  A workgroup then needs half the LDS of a
+// reals (lpadded<R>(L) per transform at least).  A workgroup then needs half the LDS of a
 // complex exchange, so more workgroups fit a CU, at four barriers per
 // exchange instead of two.  Index logic as in pass_read / pass_write.
 template <typename R, int C>
@@ -207,13 +220,13 @@ __device__ __forceinline__ void pass_read_part(cpx<R>* v, const R* buf, int t) {
 #pragma unroll
     for (int b = 0; b < 8 / RADIX; ++b) {
         const int j = t + b * T;
-        if constexpr (Q % 8 == 0) {
-            const R* p = buf + pad8(j);
+        if constexpr (Q % pad_group<R>() == 0) {
+            const R* p = buf + lpad<R>(j);
 #pragma unroll
-            for (int r = 0; r < RADIX; ++r) part<R, C>(v[b * RADIX + r]) = p[pad_off(r * Q)];
+            for (int r = 0; r < RADIX; ++r) part<R, C>(v[b * RADIX + r]) = p[lpad_off<R>(r * Q)];
         } else {
 #pragma unroll
-            for (int r = 0; r < RADIX; ++r) part<R, C>(v[b * RADIX + r]) = buf[pad8(j + r * Q)];
+            for (int r = 0; r < RADIX; ++r) part<R, C>(v[b * RADIX + r]) = buf[lpad<R>(j + r * Q)];
         }
     }
 }
@@ -226,18 +239,19 @@ __device__ __forceinline__ void pass_write_part(cpx<R>* v, R* buf, int t) {
     constexpr int LNS = S::lns(INV, P);
     constexpr int NS = 1 << LNS;
     constexpr int T = S::L / 8;
-    constexpr bool FAST = (NS % 8 == 0) || (8 % NS == 0 && (NS * RADIX) % 8 == 0);
+    constexpr int G = pad_group<R>();
+    constexpr bool FAST = (NS % G == 0) || (G % NS == 0 && (NS * RADIX) % G == 0);
 #pragma unroll
     for (int b = 0; b < 8 / RADIX; ++b) {
         const int j = t + b * T;
         const int dst = ((j >> LNS) << (LNS + LR)) + (j & (NS - 1));
         if constexpr (FAST) {
-            R* p = buf + pad8(dst);
+            R* p = buf + lpad<R>(dst);
 #pragma unroll
-            for (int r = 0; r < RADIX; ++r) p[pad_off(r * NS)] = part<R, C>(v[b * RADIX + r]);
+            for (int r = 0; r < RADIX; ++r) p[lpad_off<R>(r * NS)] = part<R, C>(v[b * RADIX + r]);
         } else {
 #pragma unroll
-            for (int r = 0; r < RADIX; ++r) buf[pad8(dst + r * NS)] = part<R, C>(v[b * RADIX + r]);
+            for (int r = 0; r < RADIX; ++r) buf[lpad<R>(dst + r * NS)] = part<R, C>(v[b * RADIX + r]);
         }
     }
 }
