@@ -9,8 +9,11 @@
 //   twiddle  x_r *= W_{Ns R}^{r (j mod Ns)}     (table, conjugate for inverse)
 //   outputs  y[(j div Ns) Ns R + (j mod Ns) + r Ns]
 // for butterflies j = t + b T, b = 0..8/R-1.  Twiddles come from a per-length
-// table holding, for every pass with Ns > 1, the R entries of each j mod Ns
-// contiguously, so a butterfly reads one small block.
+// table holding R entries for every j mod Ns of each pass with Ns > 1.  FP64
+// tables hold entry r of every j mod Ns contiguously (index r Ns + j mod Ns),
+// so the lanes of a wavefront, which have consecutive j, read consecutive
+// 16-byte entries of each r; FP32 tables hold the R entries of one j mod Ns
+// contiguously (index (j mod Ns) R + r), which a thread reads as wide loads.
 //
 // Because the last forward pass (radix R, Ns = L/R) leaves thread t holding
 // positions j + r L/R and the first inverse pass (radix R, Ns = 1) reads the
@@ -95,6 +98,10 @@ __device__ __forceinline__ void dft8_low(cpx<R>* v) {
 
 // Twiddles of pass P for thread t (R - 1 per butterfly), loaded ahead of the
 // pass so their latency overlaps the LDS exchange and barrier before it.
+// Layout of the per-pass twiddle tables (see above): true = [r][j mod Ns].
+template <typename R>
+constexpr bool tw_by_r() { return sizeof(R) == 8; }
+
 template <typename R, int LOG2L, bool INV, int P>
 struct PassTw {
     static constexpr int RADIX = 1 << Sched<LOG2L>::lr(INV, P);
@@ -114,9 +121,15 @@ __device__ __forceinline__ PassTw<R, LOG2L, INV, P> pass_twiddles(int t, const c
 #pragma unroll
         for (int b = 0; b < PT::BPT; ++b) {
             const int jn = (t + b * T) & (NS - 1);
-            const cpx<R>* wp = tw + S::tw_off(INV, P) + jn * RADIX;
+            if constexpr (tw_by_r<R>()) {
+                const cpx<R>* wp = tw + S::tw_off(INV, P) + jn;
 #pragma unroll
-            for (int r = 1; r < RADIX; ++r) out.w[b * RADIX + r] = wp[r];
+                for (int r = 1; r < RADIX; ++r) out.w[b * RADIX + r] = wp[r * NS];
+            } else {
+                const cpx<R>* wp = tw + S::tw_off(INV, P) + jn * RADIX;
+#pragma unroll
+                for (int r = 1; r < RADIX; ++r) out.w[b * RADIX + r] = wp[r];
+            }
         }
     }
     return out;

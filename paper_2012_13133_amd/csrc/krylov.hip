@@ -25,14 +25,23 @@ int dot_blocks(int64_t n) {
     return (int)b;
 }
 
+// Sum over a 64-lane wavefront by shifts of 32, 16, ..., 1 lanes; lane 0
+// holds the result, always added in the same order.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum over a block of RB threads: wavefront sums, then the RB / 64 of them
+// in wavefront order (two barriers; the second lets callers reuse sh).
 __device__ __forceinline__ double block_sum(double v, double* sh) {
-    sh[threadIdx.x] = v;
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int s = RB / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-        __syncthreads();
-    }
-    const double r = sh[0];
+    double r = sh[0];
+#pragma unroll
+    for (int w = 1; w < RB / 64; ++w) r += sh[w];
     __syncthreads();
     return r;
 }
@@ -213,7 +222,7 @@ __global__ void __launch_bounds__(RB) k_lanczos_beta(const double* __restrict__ 
 template <typename R>
 __global__ void __launch_bounds__(RB) k_multidot_partial(const R* __restrict__ Q, int64_t qslot, const R* __restrict__ r,
                                                          int nq, int64_t n, double* __restrict__ partial) {
-    __shared__ double sh[RB];
+    __shared__ double sh[RB / 64];
     const int nblk = gridDim.x, vec = blockIdx.y;
     const R* rv = r + vec * n;
     for (int q = 0; q < nq; ++q) {
