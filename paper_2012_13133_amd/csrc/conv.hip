@@ -788,8 +788,8 @@ template <>
 const cpx<float>* twiddles<float>(Ctx& c) { return c.tw32; }
 
 // Per-length pass twiddle tables (fftk.hpp layout), built on first use.
-template <int LOG2L>
-static void fill_plan(std::vector<std::array<long double, 2>>& out, bool by_r) {
+template <typename Real, int LOG2L>
+static void fill_plan(std::vector<std::array<long double, 2>>& out) {
     using S = Sched<LOG2L>;
     out.assign(S::tw_total > 0 ? S::tw_total : 1, {1.0L, 0.0L});
     const long double pi = 3.141592653589793238462643383279502884L;
@@ -800,7 +800,7 @@ static void fill_plan(std::vector<std::array<long double, 2>>& out, bool by_r) {
             for (int jn = 0; jn < NS; ++jn)
                 for (int r = 0; r < R; ++r) {
                     const long double ang = (inv ? 2.0L : -2.0L) * pi * (long double)(r * jn) / (long double)(NS * R);
-                    out[off + (by_r ? r * NS + jn : jn * R + r)] = {cosl(ang), sinl(ang)};
+                    out[off + tw_index<Real>(r, jn, NS)] = {cosl(ang), sinl(ang)};
                 }
         }
 }
@@ -813,17 +813,17 @@ static const cpx<R>* plan_table(Ctx& c, int log2L) {
     if (slot) return static_cast<const cpx<R>*>(slot);
     std::vector<std::array<long double, 2>> tab;
     switch (log2L) {
-        case 3: fill_plan<3>(tab, tw_by_r<R>()); break;
-        case 4: fill_plan<4>(tab, tw_by_r<R>()); break;
-        case 5: fill_plan<5>(tab, tw_by_r<R>()); break;
-        case 6: fill_plan<6>(tab, tw_by_r<R>()); break;
-        case 7: fill_plan<7>(tab, tw_by_r<R>()); break;
-        case 8: fill_plan<8>(tab, tw_by_r<R>()); break;
-        case 9: fill_plan<9>(tab, tw_by_r<R>()); break;
-        case 10: fill_plan<10>(tab, tw_by_r<R>()); break;
-        case 11: fill_plan<11>(tab, tw_by_r<R>()); break;
-        case 12: fill_plan<12>(tab, tw_by_r<R>()); break;
-        case 13: fill_plan<13>(tab, tw_by_r<R>()); break;
+        case 3: fill_plan<R, 3>(tab); break;
+        case 4: fill_plan<R, 4>(tab); break;
+        case 5: fill_plan<R, 5>(tab); break;
+        case 6: fill_plan<R, 6>(tab); break;
+        case 7: fill_plan<R, 7>(tab); break;
+        case 8: fill_plan<R, 8>(tab); break;
+        case 9: fill_plan<R, 9>(tab); break;
+        case 10: fill_plan<R, 10>(tab); break;
+        case 11: fill_plan<R, 11>(tab); break;
+        case 12: fill_plan<R, 12>(tab); break;
+        case 13: fill_plan<R, 13>(tab); break;
         default: throw Error(KRY_EINVAL, "transform length out of range");
     }
     std::vector<cpx<R>> h(tab.size());

@@ -9,11 +9,12 @@
 //   twiddle  x_r *= W_{Ns R}^{r (j mod Ns)}     (table, conjugate for inverse)
 //   outputs  y[(j div Ns) Ns R + (j mod Ns) + r Ns]
 // for butterflies j = t + b T, b = 0..8/R-1.  Twiddles come from a per-length
-// table holding R entries for every j mod Ns of each pass with Ns > 1.  FP64
-// tables hold entry r of every j mod Ns contiguously (index r Ns + j mod Ns),
-// so the lanes of a wavefront, which have consecutive j, read consecutive
-// 16-byte entries of each r; FP32 tables hold the R entries of one j mod Ns
-// contiguously (index (j mod Ns) R + r), which a thread reads as wide loads.
+// table holding R entries for every j mod Ns of each pass with Ns > 1, laid
+// out so that the lanes of a wavefront, which have consecutive j, read
+// consecutive 16-byte pieces: FP64 tables hold entry r of every j mod Ns
+// contiguously (index r Ns + j mod Ns); FP32 tables hold the entries in pairs
+// (r = 2p, 2p + 1) of every j mod Ns contiguously (index 2 (p Ns + j mod Ns)
+// + r mod 2), one 16-byte load per pair.
 //
 // Because the last forward pass (radix R, Ns = L/R) leaves thread t holding
 // positions j + r L/R and the first inverse pass (radix R, Ns = 1) reads the
@@ -98,9 +99,11 @@ __device__ __forceinline__ void dft8_low(cpx<R>* v) {
 
 // Twiddles of pass P for thread t (R - 1 per butterfly), loaded ahead of the
 // pass so their latency overlaps the LDS exchange and barrier before it.
-// Layout of the per-pass twiddle tables (see above): true = [r][j mod Ns].
+// Index of entry r of j mod Ns in a pass's twiddle table (see above).
 template <typename R>
-constexpr bool tw_by_r() { return sizeof(R) == 8; }
+constexpr int tw_index(int r, int jn, int NS) {
+    return sizeof(R) == 8 ? r * NS + jn : 2 * ((r >> 1) * NS + jn) + (r & 1);
+}
 
 template <typename R, int LOG2L, bool INV, int P>
 struct PassTw {
@@ -121,14 +124,19 @@ __device__ __forceinline__ PassTw<R, LOG2L, INV, P> pass_twiddles(int t, const c
 #pragma unroll
         for (int b = 0; b < PT::BPT; ++b) {
             const int jn = (t + b * T) & (NS - 1);
-            if constexpr (tw_by_r<R>()) {
+            if constexpr (sizeof(R) == 8) {
                 const cpx<R>* wp = tw + S::tw_off(INV, P) + jn;
 #pragma unroll
                 for (int r = 1; r < RADIX; ++r) out.w[b * RADIX + r] = wp[r * NS];
             } else {
-                const cpx<R>* wp = tw + S::tw_off(INV, P) + jn * RADIX;
+                // pairs as float4 (the pass offsets are even, the table 16-byte aligned)
+                const float4* wp = reinterpret_cast<const float4*>(tw + S::tw_off(INV, P)) + jn;
 #pragma unroll
-                for (int r = 1; r < RADIX; ++r) out.w[b * RADIX + r] = wp[r];
+                for (int q = 0; q < RADIX / 2; ++q) {
+                    const float4 e = wp[q * NS];
+                    if (q > 0) out.w[b * RADIX + 2 * q] = cpx<R>{e.x, e.y};
+                    out.w[b * RADIX + 2 * q + 1] = cpx<R>{e.z, e.w};
+                }
             }
         }
     }
