@@ -42,6 +42,25 @@ def test_every_configuration_is_bit_identical(shape):
             K.kry_set_tuning(P.ctx, P.N1, P.N2, prec)
 
 
+def test_row_settings_bit_identical_on_a_4096_embedding():
+    # rows of 2048 points: the split row kernels and 1024-thread FP32 tiles at
+    # their largest common size
+    n1, n2 = 1100, 1030
+    mask = synth.uniform_mask(n1, n2, 0.3, seed=13)
+    th = K.theta_from_dict(TH)
+    with K.Problem(n1, n2, mask) as P:
+        assert P.N2 == 4096
+        v = synth.random_vectors(P.p, 2, seed=14)
+        for prec in (K.KRY_FP64, K.KRY_FP32):
+            K.kry_set_tuning(P.ctx, P.N1, P.N2, prec)
+            ref = K.kry_matvec(P.h, th, v, prec)
+            for rs, vt, rsp in itertools.product((1, 2), (1, 2), (0, 1, 2, 3)):
+                K.kry_set_tuning(P.ctx, P.N1, P.N2, prec, 2, rs, vt, 1, rsp)
+                got = K.kry_matvec(P.h, th, v, prec)
+                assert np.array_equal(got, ref), (prec, rs, vt, rsp)
+            K.kry_set_tuning(P.ctx, P.N1, P.N2, prec)
+
+
 def test_autotune_keeps_a_valid_configuration():
     n1, n2 = 200, 180
     mask = synth.uniform_mask(n1, n2, 0.3, seed=5)
