@@ -381,7 +381,9 @@ __global__ void __launch_bounds__(((1 << LOG2L) / 8 > 256 ? (1 << LOG2L) / 8 : 2
     extern __shared__ unsigned char smem_raw[];
     cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
     const int tid = threadIdx.x;
-    const int cl = tid / T, t = tid % T;
+    // (one column per workgroup when a transform has 256 or more threads: the
+    // column, and with it every base address, is then uniform over the workgroup)
+    const int cl = T >= 256 ? 0 : tid / T, t = T >= 256 ? tid : tid % T;
     // the vectors of one column block run consecutively on one XCD, so the
     // spectrum columns they share stay in its L2
     const int lid = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
