@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <type_traits>
 
 namespace kry {
 
@@ -23,6 +24,15 @@ __device__ __forceinline__ cpx<R> csub(cpx<R> a, cpx<R> b) { return {a.x - b.x, 
 // whichever unrolled copy or batch slot computes it.
 __device__ __forceinline__ float fma_rn(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_rn(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Element i of an array addressed by a 32-bit byte offset from its base, so
+// that a base shared by the workgroup stays in scalar registers and each lane
+// adds only its offset.  Callers guarantee i * sizeof(T) < 2^32.
+template <typename T>
+__device__ __forceinline__ T& at32(T* base, uint32_t i) {
+    using C = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return *reinterpret_cast<T*>(reinterpret_cast<C*>(base) + i * (uint32_t)sizeof(T));
+}
 template <typename R>
 __device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
     return {fma_rn(a.x, b.x, -(a.y * b.y)), fma_rn(a.x, b.y, a.y * b.x)};

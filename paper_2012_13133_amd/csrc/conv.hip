@@ -229,9 +229,9 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
             for (int r = 0; r < NP; ++r) {
                 const int c0 = 2 * (t + u * TR + r * T);
                 const bool ok = row < rows_in && c0 < row_len;
-                const int w = ok ? row * mask.words_per_row + (c0 >> 5) : 0;
-                const uint32_t word = mask.bits[w];
-                bs[u * NP + r] = mask.base[w];
+                const uint32_t w = ok ? (uint32_t)(row * mask.words_per_row + (c0 >> 5)) : 0u;
+                const uint32_t word = at32(mask.bits, w);
+                bs[u * NP + r] = at32(mask.base, w);
                 wd[u * NP + r] = ok ? word : 0u;
             }
 #pragma unroll
@@ -244,9 +244,9 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
                 const uint32_t word = wd[u * NP + r];
                 const uint32_t b0 = 1u << (c0 & 31);
                 const bool lo = (word & b0) != 0u, hi = (word & (b0 << 1)) != 0u;
-                const int64_t ci = (int64_t)bs[u * NP + r] + __popc(word & (b0 - 1u));
-                const R x = vin[lo ? ci : 0];
-                const R y = vin[hi ? ci + (lo ? 1 : 0) : 0];
+                const uint32_t ci = bs[u * NP + r] + (uint32_t)__popc(word & (b0 - 1u));
+                const R x = at32(vin, lo ? ci : 0u);
+                const R y = at32(vin, hi ? ci + (lo ? 1u : 0u) : 0u);
                 v[u * 8 + r] = cpx<R>{lo ? x : (R)0, hi ? y : (R)0};
             }
     } else {
@@ -310,13 +310,13 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
             const R zk = bk[i * PTR], zc = bc[-i * PTR];
             const R sy = zk - zc, dy = zk + zc;
             const cpx<R> wd = cmul(twiddle<R, false>(twb, k, LOG2M + 1), cpx<R>{dx[i], dy});
-            Yr[(int64_t)k * a.ldY] = cpx<R>{(R)0.5 * (sx[i] + wd.y), (R)0.5 * (sy - wd.x)};
+            at32(Y, (uint32_t)(k * a.ldY + row0 + r2)) = cpx<R>{(R)0.5 * (sx[i] + wd.y), (R)0.5 * (sy - wd.x)};
         }
         if (tid < a.RT) {
             const R z0 = rl[tid * PM];
             const R sy = z0 - z0, dy = z0 + z0;
             const cpx<R> wd = cmul(twiddle<R, false>(twb, M, LOG2M + 1), cpx<R>{nydx, dy});
-            Y[(int64_t)M * a.ldY + row0 + tid] = cpx<R>{(R)0.5 * (nyx + wd.y), (R)0.5 * (sy - wd.x)};
+            at32(Y, (uint32_t)(M * a.ldY + row0 + tid)) = cpx<R>{(R)0.5 * (nyx + wd.y), (R)0.5 * (sy - wd.x)};
         }
         return;
     }
@@ -337,7 +337,7 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
         const cpx<R> zc = cconj(bp[lpad<cpx<R>>((M - k) & (M - 1))]);
         const cpx<R> s = cadd(zk, zc);
         const cpx<R> wd = cmul(w, csub(zk, zc));
-        Y[(int64_t)k * a.ldY + row0 + r2] = cpx<R>{(R)0.5 * (s.x + wd.y), (R)0.5 * (s.y - wd.x)};
+        at32(Y, (uint32_t)(k * a.ldY + row0 + r2)) = cpx<R>{(R)0.5 * (s.x + wd.y), (R)0.5 * (s.y - wd.x)};
     };
 #pragma unroll
     for (int i = 0; i < 8 * VT; ++i) {
@@ -566,11 +566,11 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
         if constexpr (OUT == OUT_COMPACT) {
             const int c0 = 2 * edge_pos<LOG2M, LRL>(t + (k / 8) * TR, k % 8);
             if (row < rows_out && c0 < cols_out) {
-                const int w = row * mask.words_per_row + (c0 >> 5);
-                const uint32_t word = mask.bits[w];
+                const uint32_t w = (uint32_t)(row * mask.words_per_row + (c0 >> 5));
+                const uint32_t word = at32(mask.bits, w);
                 const uint32_t b0 = 1u << (c0 & 31);
                 obits |= (uint64_t)((word & b0 ? 1u : 0u) | (word & (b0 << 1) ? 2u : 0u)) << (2 * k);
-                oci[k] = (int32_t)(mask.base[w] + __popc(word & (b0 - 1u)));
+                oci[k] = (int32_t)(at32(mask.base, w) + __popc(word & (b0 - 1u)));
             }
         }
     }
@@ -592,9 +592,10 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
         const cpx<R>* Yr = Y + row0 + r2;
         cpx<R> tv[NV];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) tv[i] = rin ? Yr[(int64_t)(k0 + i * TR) * a.ldY] : cpx<R>{(R)0, (R)0};
+        for (int i = 0; i < NV; ++i)
+            tv[i] = rin ? at32(Y, (uint32_t)((k0 + i * TR) * a.ldY + row0 + r2)) : cpx<R>{(R)0, (R)0};
         cpx<R> ny{(R)0, (R)0};
-        if (tid < a.RT && row0 + tid < rows_out) ny = Y[(int64_t)M * a.ldY + row0 + tid];
+        if (tid < a.RT && row0 + tid < rows_out) ny = at32(Y, (uint32_t)(M * a.ldY + row0 + tid));
 #pragma unroll
         for (int i = 0; i < NV; ++i) tl[i * PTR] = tv[i].x;
         if (tid < a.RT) rl[tid * PM + lpad<R>(M)] = ny.x;
@@ -654,10 +655,10 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
                 const int r2 = o & (a.RT - 1);
                 const int k = o >> a.log2RT;
                 const int row = row0 + r2;
-                tv[i] = (row < rows_out) ? Y[(int64_t)k * a.ldY + row] : cpx<R>{(R)0, (R)0};
+                tv[i] = (row < rows_out) ? at32(Y, (uint32_t)(k * a.ldY + row)) : cpx<R>{(R)0, (R)0};
             }
             cpx<R> ny{(R)0, (R)0};
-            if (tid < a.RT && row0 + tid < rows_out) ny = Y[(int64_t)M * a.ldY + row0 + tid];
+            if (tid < a.RT && row0 + tid < rows_out) ny = at32(Y, (uint32_t)(M * a.ldY + row0 + tid));
 #pragma unroll
             for (int i = 0; i < NV; ++i) {
                 const int o = tid + i * nt;
@@ -728,9 +729,9 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
 #pragma unroll
                 for (int g = 0; g < GK; ++g) {
                     const uint32_t b = (uint32_t)(obits >> (2 * (k0 + g))) & 3u;
-                    const int64_t ci = oci[k0 + g];
-                    const R x = vi[(b & 1u) ? ci : 0];
-                    const R y = vi[(b & 2u) ? ci + (b & 1u) : 0];
+                    const uint32_t ci = (uint32_t)oci[k0 + g];
+                    const R x = at32(vi, (b & 1u) ? ci : 0u);
+                    const R y = at32(vi, (b & 2u) ? ci + (b & 1u) : 0u);
                     vx[g] = (b & 1u) ? x : (R)0;
                     vy[g] = (b & 2u) ? y : (R)0;
                 }
@@ -745,16 +746,17 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
             if constexpr (OUT == OUT_COMPACT) {
                 const uint32_t b = (uint32_t)(obits >> (2 * k)) & 3u;
                 if (!b) continue;
-                int64_t ci = oci[k];
+                uint32_t ci = (uint32_t)oci[k];
                 if (b & 1u) {
-                    oc[ci] = v[k].x + e * vx[g];
+                    at32(oc, ci) = v[k].x + e * vx[g];
                     ++ci;
                 }
-                if (b & 2u) oc[ci] = v[k].y + e * vy[g];
+                if (b & 2u) at32(oc, ci) = v[k].y + e * vy[g];
             } else {
-                R* o = reinterpret_cast<R*>(a.out) + vec * a.out_vstride + (int64_t)row * cols_out;
-                o[c0] = (R)a.scale * v[k].x;
-                if (c0 + 1 < cols_out) o[c0 + 1] = (R)a.scale * v[k].y;
+                R* o = reinterpret_cast<R*>(a.out) + vec * a.out_vstride;
+                const uint32_t g0 = (uint32_t)(row * cols_out + c0);
+                at32(o, g0) = (R)a.scale * v[k].x;
+                if (c0 + 1 < cols_out) at32(o, g0 + 1) = (R)a.scale * v[k].y;
             }
         }
     }
