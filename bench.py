@@ -143,17 +143,20 @@ def main():
             K.kry_matvec_device(P.h, th0, prec, B, vin.data_ptr(), vout.data_ptr(), sp)
         torch.cuda.synchronize()
         K.kry_profile_begin(P.ctx)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.mv_reps):
+        # an event between consecutive launches: the total and each launch's time
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.mv_reps + 1)]
+        evs[0].record(stream)
+        for i in range(args.mv_reps):
             K.kry_matvec_device(P.h, th0, prec, B, vin.data_ptr(), vout.data_ptr(), sp)
-        e1.record(stream)
+            evs[i + 1].record(stream)
         torch.cuda.synchronize()
-        ms_total = e0.elapsed_time(e1)
+        ms_total = evs[0].elapsed_time(evs[-1])
+        per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.mv_reps)])
         st_ms, st_n, st_vec = K.kry_profile_end(P.ctx)
         rate = B * args.mv_reps / (ms_total / 1e3)
         mv[prec] = dict(batch=B, matvecs_per_s=rate, ms_per_launch=ms_total / args.mv_reps,
+                        launch_ms_median=float(np.median(per)), launch_ms_p10=float(np.percentile(per, 10)),
+                        launch_ms_p90=float(np.percentile(per, 90)),
                         stage_ms=[float(v / max(c, 1)) for v, c in zip(st_ms, st_n)])
         log("matvec %s B=%d: %.0f matvecs/s, stages A/B/C ms %s" %
             ("fp32" if prec == K.KRY_FP32 else "fp64", B, rate, mv[prec]["stage_ms"]))
