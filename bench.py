@@ -134,6 +134,27 @@ def main():
     stream = torch.cuda.Stream()  # default priority; the library launches on it
     torch.cuda.set_stream(stream)
     sp = stream.cuda_stream
+    # products per second across batch sizes (the configuration tuned above)
+    sweep = {}
+    for prec, dt, key in ((K.KRY_FP32, torch.float32, "fp32"), (K.KRY_FP64, torch.float64, "fp64")):
+        sweep[key] = {}
+        for Bs in (1, 8, 32, 128):
+            vin = torch.randn(Bs, P.p, device=dev, dtype=dt)
+            vout = torch.empty_like(vin)
+            K.kry_matvec_device(P.h, th0, prec, Bs, vin.data_ptr(), vout.data_ptr(), sp)
+            reps = max(4, 640 // Bs) if Bs < 32 else 10
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                K.kry_matvec_device(P.h, th0, prec, Bs, vin.data_ptr(), vout.data_ptr(), sp)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            sweep[key][str(Bs)] = Bs * reps / (e0.elapsed_time(e1) / 1e3)
+            del vin, vout
+        torch.cuda.empty_cache()
+    log("matvec products/s by batch: %s" % {k: {b: round(v) for b, v in d.items()} for k, d in sweep.items()})
+
     mv = {}
     for prec, dt in ((K.KRY_FP32, torch.float32), (K.KRY_FP64, torch.float64)):
         B = args.mv_batch
@@ -142,7 +163,6 @@ def main():
         for _ in range(3):
             K.kry_matvec_device(P.h, th0, prec, B, vin.data_ptr(), vout.data_ptr(), sp)
         torch.cuda.synchronize()
-        K.kry_profile_begin(P.ctx)
         # an event between consecutive launches: the total and each launch's time
         evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.mv_reps + 1)]
         evs[0].record(stream)
@@ -152,6 +172,13 @@ def main():
         torch.cuda.synchronize()
         ms_total = evs[0].elapsed_time(evs[-1])
         per = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.mv_reps)])
+        # stage times in a second run of as many launches (the library's events
+        # between stages cost a few per cent of the rate, so they are kept out
+        # of the run above)
+        K.kry_profile_begin(P.ctx)
+        for i in range(args.mv_reps):
+            K.kry_matvec_device(P.h, th0, prec, B, vin.data_ptr(), vout.data_ptr(), sp)
+        torch.cuda.synchronize()
         st_ms, st_n, st_vec = K.kry_profile_end(P.ctx)
         rate = B * args.mv_reps / (ms_total / 1e3)
         mv[prec] = dict(batch=B, matvecs_per_s=rate, ms_per_launch=ms_total / args.mv_reps,
@@ -162,7 +189,6 @@ def main():
             ("fp32" if prec == K.KRY_FP32 else "fp64", B, rate, mv[prec]["stage_ms"]))
         del vin, vout
     torch.cuda.empty_cache()
-
     if args.matvec_only:
         # a plain device copy of known size: the reference that scales the HBM
         # counters (FETCH_SIZE, WRITE_SIZE) read under a profiler
@@ -172,7 +198,8 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-        print(json.dumps({"matvec_batched": {"fp32": mv[K.KRY_FP32], "fp64": mv[K.KRY_FP64]}}))
+        print(json.dumps({"matvec_batched": {"fp32": mv[K.KRY_FP32], "fp64": mv[K.KRY_FP64]},
+                          "matvec_by_batch": sweep}))
         P.close()
         return
 
@@ -303,6 +330,7 @@ def main():
         },
         "loglik_evals_per_s": evals_per_s,
         "tuning": tuning,
+        "matvec_by_batch": sweep,
         "matvec_batched": {"fp32": mv[K.KRY_FP32], "fp64": mv[K.KRY_FP64],
                            "bytes_per_launch_fp32": mv_bytes, "achieved_GBs_fp32": mv_achieved},
         "plain_fp64": plain,
