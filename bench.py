@@ -126,7 +126,10 @@ def main():
 
     # ---- launch configuration picked by the autotuner for this embedding ----
     tuning = {"fp32": K.kry_autotune(P.h, K.KRY_FP32, args.mv_batch),
-              "fp64": K.kry_autotune(P.h, K.KRY_FP64, args.mv_batch)}
+              "fp64": K.kry_autotune(P.h, K.KRY_FP64, args.mv_batch),
+              # products of at most 8 vectors (the multi-shift CG's, one vector per range group)
+              "fp32_small": K.kry_autotune(P.h, K.KRY_FP32, 4),
+              "fp64_small": K.kry_autotune(P.h, K.KRY_FP64, 4)}
     log("autotuned: %s" % tuning)
 
     # ---- isolated batched masked product (FP32 and FP64) with stage timing ----

@@ -171,16 +171,20 @@ typedef struct {
 
 /* Time configurations on the problem's own embedding with a product of nvec
  * (1..4096) compact vectors in `precision`, keep the fastest for that
- * embedding and precision in the problem's context (used by every later
- * product there) and return it.  The row-stage fields are searched first
+ * embedding, precision and batch class in the problem's context and return
+ * it.  There are two batch classes, products of at most 8 vectors and larger
+ * ones; a product uses its class's setting, else the other class's, else the
+ * built-in default.  The row-stage fields are searched first
  * (every combination, column stage at its default), then the column-stage
  * fields with the best row setting.  Each candidate runs 2 untimed and 5
  * timed products (HIP events on the context's stream); ms is the fastest's
  * median. */
 kry_status kry_autotune(kry_problem* prob, int32_t precision, int32_t nvec, kry_tuning* out);
 /* Set (t != NULL) or reset to the built-in default (t == NULL) the
- * configuration used for embedding N1 x N2 in `precision` on this context;
- * KRY_EINVAL for values outside the ranges above. */
+ * configuration used for embedding N1 x N2 in `precision` on this context,
+ * for both batch classes; KRY_EINVAL for values outside the ranges above.
+ * kry_get_tuning returns the setting of the larger batch class (else the
+ * smaller's, else the default). */
 kry_status kry_set_tuning(kry_ctx* ctx, int32_t N1, int32_t N2, int32_t precision, const kry_tuning* t);
 /* The configuration in use for N1 x N2 in `precision` (ms = 0 unless set by
  * kry_autotune). */

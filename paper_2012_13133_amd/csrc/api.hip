@@ -2241,7 +2241,7 @@ template <typename R>
 Tuning autotune_impl(Problem& P, int nvec, hipStream_t st) {
     Ctx& C = *P.ctx;
     const int rb = (int)sizeof(R);
-    const auto key = std::make_tuple(P.N1, P.N2, rb);
+    const auto key = std::make_tuple(P.N1, P.N2, rb, Ctx::batch_class(nvec));
     // The row stages' parameters (rows per tile, values per thread, split
     // exchanges) and the column stage's (vectors per workgroup, split
     // exchange) act on different kernels: the rows are tuned first with the
@@ -2349,10 +2349,10 @@ kry_status kry_set_tuning(kry_ctx* ctx, int32_t N1, int32_t N2, int32_t precisio
         KRY_REQUIRE(precision == KRY_FP64 || precision == KRY_FP32, "bad precision");
         KRY_REQUIRE(N1 >= 16 && N2 >= 16 && N1 <= 8192 && N2 <= 8192 && (N1 & (N1 - 1)) == 0 && (N2 & (N2 - 1)) == 0,
                     "N1, N2 must be powers of two in [16, 8192]");
-        const auto key = std::make_tuple((int)N1, (int)N2, precision == KRY_FP32 ? 4 : 8);
+        const int rb = precision == KRY_FP32 ? 4 : 8;
         std::lock_guard<std::mutex> g(ctx->c.tune_mu);
-        if (!t) {
-            ctx->c.tuning.erase(key);
+        if (!t) {  // both batch classes
+            for (int cls = 0; cls < 2; ++cls) ctx->c.tuning.erase(std::make_tuple((int)N1, (int)N2, rb, cls));
             return;
         }
         check_tuning(t);
@@ -2362,7 +2362,7 @@ kry_status kry_set_tuning(kry_ctx* ctx, int32_t N1, int32_t N2, int32_t precisio
         u.row_vt = t->row_vthreads;
         u.col_split = t->col_split;
         u.row_split = t->row_split;
-        ctx->c.tuning[key] = u;
+        for (int cls = 0; cls < 2; ++cls) ctx->c.tuning[std::make_tuple((int)N1, (int)N2, rb, cls)] = u;
     });
 }
 

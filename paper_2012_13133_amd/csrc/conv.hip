@@ -1058,7 +1058,7 @@ void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st) {
     if (s.nvec <= 0) return;
     const int M = s.N2 / 2;
     // launch configuration of this embedding and precision (bit-identical results)
-    const Tuning tu = P.ctx->tuning_for(s.N1, s.N2, (int)sizeof(R));
+    const Tuning tu = P.ctx->tuning_for(s.N1, s.N2, (int)sizeof(R), s.nvec);
     const int vt = (M >= 1024 && tu.row_vt == 2) ? 2 : 1;
     // (two vectors per column workgroup only when there are two to pair)
     const int V = s.nvec < 2 ? 1 : (tu.col_v ? tu.col_v : (sizeof(R) == 4 ? 2 : 1));

@@ -67,13 +67,21 @@ struct Ctx {
     void* plan32[14] = {};
     std::mutex alloc_mu;     // guards `allocated` (server slots allocate concurrently)
     bool graphs = true;  // replay captured graphs for CG iteration blocks
-    std::map<std::tuple<int, int, int>, Tuning> tuning;  // (N1, N2, bytes per real) -> configuration
+    // (N1, N2, bytes per real, batch class) -> configuration; class 0 holds
+    // the setting for products of at most kSmallBatch vectors, class 1 the rest
+    std::map<std::tuple<int, int, int, int>, Tuning> tuning;
     std::mutex tune_mu;
+    static constexpr int kSmallBatch = 8;
+    static int batch_class(int nvec) { return nvec <= kSmallBatch ? 0 : 1; }
     void* blas = nullptr;    // rocBLAS handle for the dense DFT / low-rank products (lazily created)
     std::mutex blas_mu;
-    Tuning tuning_for(int N1, int N2, int real_bytes) {
+    // The setting for products of nvec vectors: that batch class's, else the
+    // other class's, else the built-in default.
+    Tuning tuning_for(int N1, int N2, int real_bytes, int nvec = 1 << 30) {
         std::lock_guard<std::mutex> g(tune_mu);
-        auto it = tuning.find(std::make_tuple(N1, N2, real_bytes));
+        const int cls = batch_class(nvec);
+        auto it = tuning.find(std::make_tuple(N1, N2, real_bytes, cls));
+        if (it == tuning.end()) it = tuning.find(std::make_tuple(N1, N2, real_bytes, 1 - cls));
         return it == tuning.end() ? Tuning{} : it->second;
     }
 };
