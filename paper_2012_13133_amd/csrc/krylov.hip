@@ -55,6 +55,7 @@ __global__ void __launch_bounds__(RB) k_dot_partial(const R* __restrict__ a, int
     const R* av = a + vec * sa;
     const R* bv = b + vec * sb;
     double acc = 0.0;
+#pragma unroll 8  // several loads in flight per thread
     for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)nblk * RB)
         acc += (double)av[i] * (double)bv[i];
     acc = block_sum(acc, sh);
@@ -174,6 +175,7 @@ __global__ void __launch_bounds__(RB) k_lanczos_update(R* __restrict__ w, const 
     const R* qv = q + vec * n;
     const R* pv = qprev ? qprev + vec * n : nullptr;
     double acc = 0.0;
+#pragma unroll 8
     for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)nblk * RB) {
         R r = wv[i] - a * qv[i];
         if (pv) r -= b * pv[i];
@@ -228,6 +230,8 @@ __global__ void __launch_bounds__(RB) k_multidot_partial(const R* __restrict__ Q
     for (int q = 0; q < nq; ++q) {
         const R* qv = Q + q * qslot + vec * n;
         double acc = 0.0;
+        // (unrolled so that several loads are in flight per thread)
+#pragma unroll 8
         for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)nblk * RB)
             acc += (double)qv[i] * (double)rv[i];
         acc = block_sum(acc, sh);
@@ -462,6 +466,7 @@ __global__ void __launch_bounds__(RB) k_cg_xr(R* __restrict__ x, R* __restrict__
     const double a = on ? rr[vec] / pw[vec] : 0.0;
     const R ar = (R)a;
     double acc = 0.0;
+#pragma unroll 8
     for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)nblk * RB) {
         const int64_t k = vec * n + i;
         R ri = r[k];
