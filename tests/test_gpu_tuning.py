@@ -84,3 +84,23 @@ def test_autotune_keeps_a_valid_configuration():
             K.kry_set_tuning(P.ctx, P.N1, P.N2, K.KRY_FP32, 1, 1, 1, 0, 4)
         with pytest.raises(K.KryError):
             K.kry_autotune(P.h, K.KRY_FP32, 0)
+
+
+def test_batch_classes_keep_their_own_settings():
+    # products of at most 8 vectors and larger ones are tuned separately; a
+    # product of either size gives the same values whichever setting it uses
+    n1, n2 = 200, 180
+    mask = synth.uniform_mask(n1, n2, 0.3, seed=15)
+    th = K.theta_from_dict(TH)
+    with K.Problem(n1, n2, mask) as P:
+        small = K.kry_autotune(P.h, K.KRY_FP64, 4)
+        assert K.kry_get_tuning(P.ctx, P.N1, P.N2, K.KRY_FP64) == small  # the only class set so far
+        large = K.kry_autotune(P.h, K.KRY_FP64, 32)
+        assert K.kry_get_tuning(P.ctx, P.N1, P.N2, K.KRY_FP64) == large
+        v = synth.random_vectors(P.p, 12, seed=16)
+        tuned = [K.kry_matvec(P.h, th, v[:k], K.KRY_FP64) for k in (3, 12)]
+        K.kry_set_tuning(P.ctx, P.N1, P.N2, K.KRY_FP64)  # resets both classes
+        d = K.kry_get_tuning(P.ctx, P.N1, P.N2, K.KRY_FP64)
+        assert d["ms"] == 0 and d["col_vectors"] == 1
+        for k, got in zip((3, 12), tuned):
+            assert np.array_equal(got, K.kry_matvec(P.h, th, v[:k], K.KRY_FP64))
