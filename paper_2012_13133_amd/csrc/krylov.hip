@@ -220,22 +220,63 @@ __global__ void __launch_bounds__(RB) k_lanczos_beta(const double* __restrict__ 
     }
 }
 
-// Classical Gram-Schmidt against stored basis vectors: h[v][i] = q_i . r
+// NB dot products against one sweep of r: acc[k] += q_k[i] r[i] over the
+// block's elements, each in the order a single dot product takes them.  The
+// vector bases are uniform over the block; lanes add 32-bit byte offsets.
+template <typename R, int NB>
+__device__ __forceinline__ void multidot_sweep(const R* __restrict__ qv, int64_t qslot, const R* __restrict__ rv,
+                                               uint32_t n, double* acc) {
+#pragma unroll
+    for (int k = 0; k < NB; ++k) acc[k] = 0.0;
+    const uint32_t step = gridDim.x * RB;
+#pragma unroll 2
+    for (uint32_t i = blockIdx.x * RB + threadIdx.x; i < n; i += step) {
+        const double x = (double)at32(rv, i);
+#pragma unroll
+        for (int k = 0; k < NB; ++k) acc[k] += (double)at32(qv + k * qslot, i) * x;
+    }
+}
+
+// Classical Gram-Schmidt against stored basis vectors: h[v][i] = q_i . r.
+// Basis vectors go MDB at a time through one sweep of r (more loads in
+// flight, one pair of barriers per group); every partial is the same sum, in
+// the same order, as a block_sum of one dot product.  n * sizeof(R) < 2^32.
+constexpr int MDB = 8;
 template <typename R>
 __global__ void __launch_bounds__(RB) k_multidot_partial(const R* __restrict__ Q, int64_t qslot, const R* __restrict__ r,
                                                          int nq, int64_t n, double* __restrict__ partial) {
-    __shared__ double sh[RB / 64];
+    __shared__ double sh[MDB][RB / 64];
     const int nblk = gridDim.x, vec = blockIdx.y;
     const R* rv = r + vec * n;
-    for (int q = 0; q < nq; ++q) {
-        const R* qv = Q + q * qslot + vec * n;
-        double acc = 0.0;
-        // (unrolled so that several loads are in flight per thread)
-#pragma unroll 8
-        for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)nblk * RB)
-            acc += (double)qv[i] * (double)rv[i];
-        acc = block_sum(acc, sh);
-        if (threadIdx.x == 0) partial[((int64_t)vec * nq + q) * nblk + blockIdx.x] = acc;
+    const R* qb = Q + vec * n;
+    for (int q0 = 0; q0 < nq; q0 += MDB) {
+        const int nb = min(MDB, nq - q0);
+        const R* qv = qb + q0 * qslot;
+        double acc[MDB] = {};
+        switch (nb) {
+            case 1: multidot_sweep<R, 1>(qv, qslot, rv, (uint32_t)n, acc); break;
+            case 2: multidot_sweep<R, 2>(qv, qslot, rv, (uint32_t)n, acc); break;
+            case 3: multidot_sweep<R, 3>(qv, qslot, rv, (uint32_t)n, acc); break;
+            case 4: multidot_sweep<R, 4>(qv, qslot, rv, (uint32_t)n, acc); break;
+            case 5: multidot_sweep<R, 5>(qv, qslot, rv, (uint32_t)n, acc); break;
+            case 6: multidot_sweep<R, 6>(qv, qslot, rv, (uint32_t)n, acc); break;
+            case 7: multidot_sweep<R, 7>(qv, qslot, rv, (uint32_t)n, acc); break;
+            default: multidot_sweep<R, MDB>(qv, qslot, rv, (uint32_t)n, acc); break;
+        }
+#pragma unroll
+        for (int k = 0; k < MDB; ++k) {
+            if (k >= nb) break;
+            const double v = wave_sum(acc[k]);
+            if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = v;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < nb) {
+            double s = sh[threadIdx.x][0];
+#pragma unroll
+            for (int w = 1; w < RB / 64; ++w) s += sh[threadIdx.x][w];
+            partial[((int64_t)vec * nq + q0 + threadIdx.x) * nblk + blockIdx.x] = s;
+        }
+        __syncthreads();
     }
 }
 
@@ -288,6 +329,7 @@ template <typename R>
 void lanczos_run(const MatvecFn<R>& A, int64_t n, int nvec, int m, bool reorth, const R* Z, LanczosBuffers<R>& B,
                  hipStream_t st, const LanczosAdaptive* ad) {
     const int nblk = dot_blocks(n);
+    KRY_REQUIRE(!reorth || (uint64_t)n * sizeof(R) < (uint64_t(1) << 32), "vectors too long for reorthogonalisation");
     const double tol = sizeof(R) == 8 ? 1e-12 : 1e-6;
     const int64_t slot = (int64_t)nvec * n;
     const int nslots = reorth ? m + 1 : 3;
