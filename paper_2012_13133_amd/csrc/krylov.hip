@@ -694,13 +694,60 @@ __global__ void k_ms_init(const double* __restrict__ gram, const int* __restrict
     }
 }
 
-// base alpha per active position, then zeta_{k+1} and alpha^s of the listed shifts
-__global__ void k_ms_alpha(int Gact, const double* __restrict__ rr, const double* __restrict__ pw,
-                           double* __restrict__ alpha, const double* __restrict__ alpha_old,
-                           const double* __restrict__ beta_old, const int* __restrict__ list, int nlist,
-                           const int* __restrict__ pos, const double* __restrict__ sigma,
-                           const double* __restrict__ zeta, const double* __restrict__ zeta_old,
-                           double* __restrict__ zeta_new, double* __restrict__ alpha_s, int* __restrict__ active) {
+// out[row] for rows [0, nrows), one block of RB threads: the sums k_reduce
+// forms (thread t adds partial t, then block_sum), in the same order.  Rows
+// go sixteen at a time: their loads are in flight together and their
+// wavefront sums are independent chains.  nblk <= RB.
+__device__ __forceinline__ void reduce_rows_block(const double* __restrict__ partial, int nblk, int nrows,
+                                                  double* __restrict__ out) {
+    constexpr int RK = 16;
+    __shared__ double sh[64][RB / 64];
+    const int t = threadIdx.x;
+    const int tc = min(t, nblk - 1);
+    for (int r0 = 0; r0 < nrows; r0 += 64) {
+        const int nr = min(64, nrows - r0);
+        for (int k0 = 0; k0 < nr; k0 += RK) {
+            // loads from clamped (in-range) addresses, issued unconditionally
+            // so that they are in flight together; lanes past the row count
+            // or the partial count then take 0
+            double x[RK], v[RK];
+#pragma unroll
+            for (int k = 0; k < RK; ++k) x[k] = partial[(int64_t)(r0 + min(k0 + k, nr - 1)) * nblk + tc];
+#pragma unroll
+            for (int k = 0; k < RK; ++k) {
+                double acc = 0.0;
+                if (k0 + k < nr && t < nblk) acc += x[k];
+                v[k] = acc;
+            }
+#pragma unroll
+            for (int k = 0; k < RK; ++k) v[k] = wave_sum(v[k]);
+            if ((t & 63) == 0) {
+#pragma unroll
+                for (int k = 0; k < RK; ++k)
+                    if (k0 + k < nr) sh[k0 + k][t >> 6] = v[k];
+            }
+        }
+        __syncthreads();
+        if (t < nr) {
+            double r = sh[t][0];
+#pragma unroll
+            for (int w = 1; w < RB / 64; ++w) r += sh[t][w];
+            out[r0 + t] = r;
+        }
+        __syncthreads();
+    }
+}
+
+// p_q . w_q from the dot partials; base alpha per active position, then
+// zeta_{k+1} and alpha^s of the listed shifts
+__global__ void __launch_bounds__(RB)
+    k_ms_alpha(int Gact, const double* __restrict__ partial, int nblk, const double* __restrict__ rr,
+               double* __restrict__ pw, double* __restrict__ alpha, const double* __restrict__ alpha_old,
+               const double* __restrict__ beta_old, const int* __restrict__ list, int nlist,
+               const int* __restrict__ pos, const double* __restrict__ sigma, const double* __restrict__ zeta,
+               const double* __restrict__ zeta_old, double* __restrict__ zeta_new, double* __restrict__ alpha_s,
+               int* __restrict__ active) {
+    reduce_rows_block(partial, nblk, Gact, pw);
     for (int q = threadIdx.x; q < Gact; q += blockDim.x) alpha[q] = pw[q] > 0.0 ? rr[q] / pw[q] : 0.0;
     __syncthreads();
     for (int i = threadIdx.x; i < nlist; i += blockDim.x) {
@@ -774,17 +821,18 @@ void ms_r(int nd, int nblk, int Gact, hipStream_t st, double* r, const double* w
 }
 
 // base beta and roll of the position scalars; Q^s and d^s, beta^s, the
-// stopping test and the zeta roll of the listed shifts.  rc holds ||r_{k+1}||^2
-// (rows 0..Gact-1) and D_j . r_{k+1} (row Gact + q nd + j).
-__global__ void k_ms_beta(int Gact, int nd, double* __restrict__ rr, const double* __restrict__ rc,
-                          double* __restrict__ beta, const double* __restrict__ alpha, double* __restrict__ alpha_old,
-                          double* __restrict__ beta_old, const double* __restrict__ bnorm2,
-                          const int* __restrict__ list, int nlist, const int* __restrict__ pos,
-                          double* __restrict__ zeta, double* __restrict__ zeta_old,
-                          const double* __restrict__ zeta_new, const double* __restrict__ alpha_s,
-                          double* __restrict__ d, double* __restrict__ Q, double* __restrict__ relres,
-                          int* __restrict__ active, int* __restrict__ iters, const int* __restrict__ limit,
-                          double rtol) {
+// stopping test and the zeta roll of the listed shifts.  rc gets, from the
+// partials of k_ms_r, ||r_{k+1}||^2 (rows 0..Gact-1) and D_j . r_{k+1} (row
+// Gact + q nd + j).
+__global__ void __launch_bounds__(RB)
+    k_ms_beta(int Gact, int nd, const double* __restrict__ partial, int nblk, double* __restrict__ rr,
+              double* __restrict__ rc, double* __restrict__ beta, const double* __restrict__ alpha,
+              double* __restrict__ alpha_old, double* __restrict__ beta_old, const double* __restrict__ bnorm2,
+              const int* __restrict__ list, int nlist, const int* __restrict__ pos, double* __restrict__ zeta,
+              double* __restrict__ zeta_old, const double* __restrict__ zeta_new, const double* __restrict__ alpha_s,
+              double* __restrict__ d, double* __restrict__ Q, double* __restrict__ relres, int* __restrict__ active,
+              int* __restrict__ iters, const int* __restrict__ limit, double rtol) {
+    reduce_rows_block(partial, nblk, (1 + nd) * Gact, rc);
     for (int i = threadIdx.x; i < nlist; i += blockDim.x) {
         const int s = list[i];
         if (!active[s]) continue;
@@ -868,6 +916,7 @@ void mscg_run(const MatvecFn<double>& A, const std::function<void(int, int)>& sw
     KRY_REQUIRE(nd >= 1 && nd <= KRY_MS_MAX_ND && (int)rhs_of_group.size() == G, "bad multi-shift right-hand sides");
     const int S = (int)group_of_shift.size();
     const int nblk = dot_blocks(n);
+    KRY_REQUIRE(nblk <= RB, "dot partials exceed one reduction block");
     const size_t vb = (size_t)n * sizeof(double);
     for (int q = 0; q < G; ++q) {
         const double* b = D + (size_t)rhs_of_group[q] * n;
@@ -898,16 +947,16 @@ void mscg_run(const MatvecFn<double>& A, const std::function<void(int, int)>& sw
     const int check = 16;
     for (int it = 0; it < maxit && Gact > 0; ++it) {
         A(B.p, B.w, Gact, st, nullptr);
-        dot_batched<double>(B.p, n, B.w, n, n, Gact, B.partial, B.pw, st);
-        hipLaunchKernelGGL(k_ms_alpha, dim3(1), dim3(256), 0, st, Gact, B.rr, B.pw, B.alpha, B.alpha_old, B.beta_old,
-                           B.list, nlist, B.pos, B.sigma, B.zeta, B.zeta_old, B.zeta_new, B.alpha_s, B.active);
+        hipLaunchKernelGGL(k_dot_partial<double>, dim3(nblk, Gact), dim3(RB), 0, st, B.p, n, B.w, n, n, B.partial);
+        KRY_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_ms_alpha, dim3(1), dim3(RB), 0, st, Gact, B.partial, nblk, B.rr, B.pw, B.alpha,
+                           B.alpha_old, B.beta_old, B.list, nlist, B.pos, B.sigma, B.zeta, B.zeta_old, B.zeta_new,
+                           B.alpha_s, B.active);
         KRY_HIP(hipGetLastError());
         ms_r(nd, nblk, Gact, st, B.r, B.w, D, B.alpha, n, B.partial);
-        hipLaunchKernelGGL(k_reduce, dim3((1 + nd) * Gact), dim3(RB), 0, st, B.partial, nblk, B.rc, (int64_t)1);
-        KRY_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_ms_beta, dim3(1), dim3(256), 0, st, Gact, nd, B.rr, B.rc, B.beta, B.alpha, B.alpha_old,
-                           B.beta_old, B.bnorm2, B.list, nlist, B.pos, B.zeta, B.zeta_old, B.zeta_new, B.alpha_s, B.d,
-                           B.Q, B.relres, B.active, B.iters, B.limit, rtol);
+        hipLaunchKernelGGL(k_ms_beta, dim3(1), dim3(RB), 0, st, Gact, nd, B.partial, nblk, B.rr, B.rc, B.beta, B.alpha,
+                           B.alpha_old, B.beta_old, B.bnorm2, B.list, nlist, B.pos, B.zeta, B.zeta_old, B.zeta_new,
+                           B.alpha_s, B.d, B.Q, B.relres, B.active, B.iters, B.limit, rtol);
         KRY_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_ms_p, dim3((unsigned)ublocks, Gact), dim3(256), 0, st, B.p, B.r, B.beta, n);
         KRY_HIP(hipGetLastError());
