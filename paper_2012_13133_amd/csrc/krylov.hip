@@ -280,6 +280,91 @@ __global__ void __launch_bounds__(RB) k_multidot_partial(const R* __restrict__ Q
     }
 }
 
+// The first pass's update and the second pass's dots of CGS2 in one sweep of
+// the basis: r <- r - sum_k h_k q_k element by element as k_multi_axpy forms
+// it, then the partials of q_k . r as k_multidot_partial forms them (same
+// block partition, same order), from the basis values already in registers.
+// Slots past nq are loaded from slot nq - 1 (in range) and not used.
+// nq <= NQ; n * sizeof(R) < 2^32; grid (dot_blocks(n), vectors).
+template <typename R, int NQ>
+__global__ void __launch_bounds__(RB) k_reorth_axpy_dot(const R* __restrict__ Q, int64_t qslot,
+                                                        const double* __restrict__ h, int nq, R* __restrict__ r,
+                                                        int64_t n, double* __restrict__ partial) {
+    __shared__ double sh[NQ][RB / 64];
+    const int nblk = gridDim.x, vec = blockIdx.y;
+    const double* hv = h + (int64_t)vec * nq;
+    R* rv = r + vec * n;
+    const R* qb = Q + vec * n;
+    double acc[NQ];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) acc[k] = 0.0;
+    const uint32_t n32 = (uint32_t)n, step = nblk * RB;
+    for (uint32_t i = blockIdx.x * RB + threadIdx.x; i < n32; i += step) {
+        R qv[NQ];
+#pragma unroll
+        for (int k = 0; k < NQ; ++k) qv[k] = at32(qb + min(k, nq - 1) * qslot, i);
+        double a = (double)at32(rv, i);
+#pragma unroll
+        for (int k = 0; k < NQ; ++k)
+            if (k < nq) a -= hv[k] * (double)qv[k];
+        const R wn = (R)a;
+        at32(rv, i) = wn;
+        const double x = (double)wn;
+#pragma unroll
+        for (int k = 0; k < NQ; ++k)
+            if (k < nq) acc[k] += (double)qv[k] * x;
+    }
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+        if (k < nq) {
+            const double v = wave_sum(acc[k]);
+            if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = v;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nq) {
+        double s = sh[threadIdx.x][0];
+#pragma unroll
+        for (int w = 1; w < RB / 64; ++w) s += sh[threadIdx.x][w];
+        partial[((int64_t)vec * nq + threadIdx.x) * nblk + blockIdx.x] = s;
+    }
+}
+
+template <typename R, int NQ>
+void launch_axpy_dot(dim3 grid, hipStream_t st, const R* Q, int64_t qslot, const double* h, int nq, R* r, int64_t n,
+                     double* partial) {
+    hipLaunchKernelGGL((k_reorth_axpy_dot<R, NQ>), grid, dim3(RB), 0, st, Q, qslot, h, nq, r, n, partial);
+}
+
+// launches k_reorth_axpy_dot for nq basis vectors (the smallest NQ, a
+// multiple of 8, that holds them); false where nq is above the largest
+// instantiation (64 FP32, 32 FP64 basis vectors)
+template <typename R>
+bool reorth_axpy_dot(const R* Q, int64_t qslot, const double* h, int nq, R* r, int64_t n, int nvec,
+                     double* partial, hipStream_t st) {
+    constexpr int cap = sizeof(R) == 4 ? 64 : 32;
+    if (nq < 1 || nq > cap) return false;
+    const dim3 grid(dot_blocks(n), nvec);
+    switch ((nq + 7) / 8) {
+        case 1: launch_axpy_dot<R, 8>(grid, st, Q, qslot, h, nq, r, n, partial); break;
+        case 2: launch_axpy_dot<R, 16>(grid, st, Q, qslot, h, nq, r, n, partial); break;
+        case 3: launch_axpy_dot<R, 24>(grid, st, Q, qslot, h, nq, r, n, partial); break;
+        case 4: launch_axpy_dot<R, 32>(grid, st, Q, qslot, h, nq, r, n, partial); break;
+        default:
+            if constexpr (cap > 32) {
+                switch ((nq + 7) / 8) {
+                    case 5: launch_axpy_dot<R, 40>(grid, st, Q, qslot, h, nq, r, n, partial); break;
+                    case 6: launch_axpy_dot<R, 48>(grid, st, Q, qslot, h, nq, r, n, partial); break;
+                    case 7: launch_axpy_dot<R, 56>(grid, st, Q, qslot, h, nq, r, n, partial); break;
+                    default: launch_axpy_dot<R, 64>(grid, st, Q, qslot, h, nq, r, n, partial); break;
+                }
+            }
+            break;
+    }
+    KRY_HIP(hipGetLastError());
+    return true;
+}
+
 // r -= sum_i h_i q_i (subtracted in order of i; loads issued eight at a time)
 template <typename R>
 __global__ void k_multi_axpy(const R* __restrict__ Q, int64_t qslot, const double* __restrict__ h, int nq,
@@ -364,15 +449,30 @@ void lanczos_run(const MatvecFn<R>& A, int64_t n, int nvec, int m, bool reorth, 
             hipLaunchKernelGGL(k_lanczos_update<R>, dim3(nblk, nvec), dim3(RB), 0, st, B.W, q, qp, aj, bprev, n,
                                (double*)nullptr);
             KRY_HIP(hipGetLastError());
-            for (int pass = 0; pass < 2; ++pass) {
-                hipLaunchKernelGGL(k_multidot_partial<R>, dim3(nblk, nvec), dim3(RB), 0, st, B.Q, slot, B.W, j + 1, n,
+            // two classical Gram-Schmidt passes; where the basis fits one
+            // fused sweep, the first update and the second pass's dots share it
+            const int nq = j + 1;
+            auto dots = [&] {
+                hipLaunchKernelGGL(k_multidot_partial<R>, dim3(nblk, nvec), dim3(RB), 0, st, B.Q, slot, B.W, nq, n,
                                    B.partial);
                 KRY_HIP(hipGetLastError());
-                hipLaunchKernelGGL(k_reduce, dim3(nvec * (j + 1)), dim3(RB), 0, st, B.partial, nblk, B.h, (int64_t)1);
+            };
+            auto coeffs = [&] {
+                hipLaunchKernelGGL(k_reduce, dim3(nvec * nq), dim3(RB), 0, st, B.partial, nblk, B.h, (int64_t)1);
                 KRY_HIP(hipGetLastError());
-                hipLaunchKernelGGL(k_multi_axpy<R>, vec_grid(n, nvec), dim3(256), 0, st, B.Q, slot, B.h, j + 1, B.W, n);
+            };
+            auto update = [&] {
+                hipLaunchKernelGGL(k_multi_axpy<R>, vec_grid(n, nvec), dim3(256), 0, st, B.Q, slot, B.h, nq, B.W, n);
                 KRY_HIP(hipGetLastError());
+            };
+            dots();
+            coeffs();
+            if (!reorth_axpy_dot<R>(B.Q, slot, B.h, nq, B.W, n, nvec, B.partial, st)) {
+                update();
+                dots();
             }
+            coeffs();
+            update();
             hipLaunchKernelGGL(k_dot_partial<R>, dim3(nblk, nvec), dim3(RB), 0, st, B.W, n, B.W, n, n, B.partial);
             KRY_HIP(hipGetLastError());
         }
