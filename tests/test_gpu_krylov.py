@@ -441,3 +441,26 @@ def test_adaptive_lanczos_same_alone_and_in_mix(share):
         for k in ("logdet", "quad", "lanczos_steps_used"):
             assert a[k] == s[k], k
     assert len({a["lanczos_steps_used"] for a in mix}) > 1  # points settle at different steps
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_reorth_past_the_fused_basis_sizes(precision):
+    # 80 steps with full reorthogonalisation: the first update and the second
+    # dots share one basis sweep up to 64 (FP32) or 32 (FP64) basis vectors,
+    # separate sweeps after that; both stretches must follow the oracle
+    n1, n2 = 24, 24
+    th = theta(0.15, 1.5, tau2=0.05)
+    g, mask, y, yo = _problem(n1, n2, th, 0.3)
+    Kd = dense.covariance(g, mask, th)
+    r, c = observed_cells(mask)
+    m, npr = 80, 4
+    opts = K.kry_opts_default(lanczos_steps=m, num_probes=npr, reorth=1, precision=precision)
+    with K.Problem(n1, n2, mask, y) as P:
+        _, _, steps = K.kry_lanczos(P.h, K.theta_from_dict(th), opts)
+        ld, _, per = K.kry_logdet(P.h, K.theta_from_dict(th), opts)
+    assert list(steps) == [m] * npr
+    Z = philox.probe_matrix(r, c, npr, opts.seed)
+    est, _, vals, _ = lanczos.slq_logdet(lambda v: Kd @ v, Z, m, reorth=True)
+    tol = 1e-9 if precision == 0 else 1e-5
+    assert abs(ld - est) <= tol * abs(est), (ld, est)
+    np.testing.assert_allclose(per, vals, rtol=tol * 10)
