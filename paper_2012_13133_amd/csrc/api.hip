@@ -957,6 +957,7 @@ void loglik_points_shared(Problem& P, const kry_matern* thetas, int count, const
             B.gram = a.take<double>((size_t)nd * nd);
             B.rhs = a.take<int>(Gm);
             B.partial = a.take<double>((size_t)(1 + nd) * Gm * nblk);
+            B.partial_pw = a.take<double>((size_t)Gm * nblk);
         };
         with_arena(P, lay);
         auto A = masked_op<double>(P, P.spec_multi64.ptr, nspec, 1, d_zero);

@@ -839,15 +839,16 @@ __device__ __forceinline__ void reduce_rows_block(const double* __restrict__ par
 }
 
 // p_q . w_q from the dot partials; base alpha per active position, then
-// zeta_{k+1} and alpha^s of the listed shifts
-__global__ void __launch_bounds__(RB)
-    k_ms_alpha(int Gact, const double* __restrict__ partial, int nblk, const double* __restrict__ rr,
-               double* __restrict__ pw, double* __restrict__ alpha, const double* __restrict__ alpha_old,
-               const double* __restrict__ beta_old, const int* __restrict__ list, int nlist,
-               const int* __restrict__ pos, const double* __restrict__ sigma, const double* __restrict__ zeta,
-               const double* __restrict__ zeta_old, double* __restrict__ zeta_new, double* __restrict__ alpha_s,
-               int* __restrict__ active) {
-    reduce_rows_block(partial, nblk, Gact, pw);
+// zeta_{k+1} and alpha^s of the listed shifts.  One block of RB threads.
+__device__ __forceinline__ void ms_alpha_step(int Gact, const double* __restrict__ partial_pw, int nblk,
+                                              const double* __restrict__ rr, double* __restrict__ pw,
+                                              double* __restrict__ alpha, const double* __restrict__ alpha_old,
+                                              const double* __restrict__ beta_old, const int* __restrict__ list,
+                                              int nlist, const int* __restrict__ pos,
+                                              const double* __restrict__ sigma, const double* __restrict__ zeta,
+                                              const double* __restrict__ zeta_old, double* __restrict__ zeta_new,
+                                              double* __restrict__ alpha_s, int* __restrict__ active) {
+    reduce_rows_block(partial_pw, nblk, Gact, pw);
     for (int q = threadIdx.x; q < Gact; q += blockDim.x) alpha[q] = pw[q] > 0.0 ? rr[q] / pw[q] : 0.0;
     __syncthreads();
     for (int i = threadIdx.x; i < nlist; i += blockDim.x) {
@@ -868,14 +869,20 @@ __global__ void __launch_bounds__(RB)
 }
 
 // r_q -= alpha_q w_q; partials of r_q . r_q (rows 0..Gact-1) and D_j . r_q
-// (row Gact + q nd + j)
+// (row Gact + q nd + j).  Every block forms alpha_q = r_q . r_q / p_q . w_q
+// itself, p_q . w_q summed from its partials in k_reduce's order (the value
+// the scalar kernel also forms).  nblk <= RB.
 template <int ND>
 __global__ void __launch_bounds__(RB) k_ms_r(double* __restrict__ r, const double* __restrict__ w,
-                                             const double* __restrict__ D, const double* __restrict__ alpha,
-                                             int Gact, int64_t n, double* __restrict__ partial) {
+                                             const double* __restrict__ D, const double* __restrict__ partial_pw,
+                                             const double* __restrict__ rr, int Gact, int64_t n,
+                                             double* __restrict__ partial) {
     __shared__ double sh[RB];
     const int nblk = gridDim.x, q = blockIdx.y;
-    const double a = alpha[q];
+    double x = 0.0;
+    if ((int)threadIdx.x < nblk) x += partial_pw[q * nblk + threadIdx.x];
+    const double pwq = block_sum(x, sh);
+    const double a = pwq > 0.0 ? rr[q] / pwq : 0.0;
     double acc = 0.0, accb[ND];
 #pragma unroll
     for (int j = 0; j < ND; ++j) accb[j] = 0.0;
@@ -899,39 +906,45 @@ __global__ void __launch_bounds__(RB) k_ms_r(double* __restrict__ r, const doubl
 
 template <int ND>
 void launch_ms_r(int nblk, int Gact, hipStream_t st, double* r, const double* w, const double* D,
-                 const double* alpha, int64_t n, double* partial) {
-    hipLaunchKernelGGL(k_ms_r<ND>, dim3(nblk, Gact), dim3(RB), 0, st, r, w, D, alpha, Gact, n, partial);
+                 const double* partial_pw, const double* rr, int64_t n, double* partial) {
+    hipLaunchKernelGGL(k_ms_r<ND>, dim3(nblk, Gact), dim3(RB), 0, st, r, w, D, partial_pw, rr, Gact, n, partial);
 }
 
 void ms_r(int nd, int nblk, int Gact, hipStream_t st, double* r, const double* w, const double* D,
-          const double* alpha, int64_t n, double* partial) {
+          const double* partial_pw, const double* rr, int64_t n, double* partial) {
     switch (nd) {
-        case 1: launch_ms_r<1>(nblk, Gact, st, r, w, D, alpha, n, partial); break;
-        case 2: launch_ms_r<2>(nblk, Gact, st, r, w, D, alpha, n, partial); break;
-        case 3: launch_ms_r<3>(nblk, Gact, st, r, w, D, alpha, n, partial); break;
-        case 4: launch_ms_r<4>(nblk, Gact, st, r, w, D, alpha, n, partial); break;
-        case 5: launch_ms_r<5>(nblk, Gact, st, r, w, D, alpha, n, partial); break;
-        case 6: launch_ms_r<6>(nblk, Gact, st, r, w, D, alpha, n, partial); break;
-        case 7: launch_ms_r<7>(nblk, Gact, st, r, w, D, alpha, n, partial); break;
-        case 8: launch_ms_r<8>(nblk, Gact, st, r, w, D, alpha, n, partial); break;
-        case 9: launch_ms_r<9>(nblk, Gact, st, r, w, D, alpha, n, partial); break;
+        case 1: launch_ms_r<1>(nblk, Gact, st, r, w, D, partial_pw, rr, n, partial); break;
+        case 2: launch_ms_r<2>(nblk, Gact, st, r, w, D, partial_pw, rr, n, partial); break;
+        case 3: launch_ms_r<3>(nblk, Gact, st, r, w, D, partial_pw, rr, n, partial); break;
+        case 4: launch_ms_r<4>(nblk, Gact, st, r, w, D, partial_pw, rr, n, partial); break;
+        case 5: launch_ms_r<5>(nblk, Gact, st, r, w, D, partial_pw, rr, n, partial); break;
+        case 6: launch_ms_r<6>(nblk, Gact, st, r, w, D, partial_pw, rr, n, partial); break;
+        case 7: launch_ms_r<7>(nblk, Gact, st, r, w, D, partial_pw, rr, n, partial); break;
+        case 8: launch_ms_r<8>(nblk, Gact, st, r, w, D, partial_pw, rr, n, partial); break;
+        case 9: launch_ms_r<9>(nblk, Gact, st, r, w, D, partial_pw, rr, n, partial); break;
         default: KRY_REQUIRE(false, "multi-shift CG takes 1..9 dot vectors");
     }
     KRY_HIP(hipGetLastError());
 }
 
+// The scalars of an iteration, after the residual update: first the alpha
+// step (from the p . w partials; k_ms_r reads none of what it writes), then
 // base beta and roll of the position scalars; Q^s and d^s, beta^s, the
 // stopping test and the zeta roll of the listed shifts.  rc gets, from the
 // partials of k_ms_r, ||r_{k+1}||^2 (rows 0..Gact-1) and D_j . r_{k+1} (row
 // Gact + q nd + j).
 __global__ void __launch_bounds__(RB)
-    k_ms_beta(int Gact, int nd, const double* __restrict__ partial, int nblk, double* __restrict__ rr,
-              double* __restrict__ rc, double* __restrict__ beta, const double* __restrict__ alpha,
-              double* __restrict__ alpha_old, double* __restrict__ beta_old, const double* __restrict__ bnorm2,
-              const int* __restrict__ list, int nlist, const int* __restrict__ pos, double* __restrict__ zeta,
-              double* __restrict__ zeta_old, const double* __restrict__ zeta_new, const double* __restrict__ alpha_s,
+    k_ms_beta(int Gact, int nd, const double* __restrict__ partial_pw, const double* __restrict__ partial, int nblk,
+              double* __restrict__ rr, double* __restrict__ rc, double* __restrict__ pw, double* __restrict__ beta,
+              double* __restrict__ alpha, double* __restrict__ alpha_old, double* __restrict__ beta_old,
+              const double* __restrict__ bnorm2, const int* __restrict__ list, int nlist,
+              const int* __restrict__ pos, const double* __restrict__ sigma, double* __restrict__ zeta,
+              double* __restrict__ zeta_old, double* __restrict__ zeta_new, double* __restrict__ alpha_s,
               double* __restrict__ d, double* __restrict__ Q, double* __restrict__ relres, int* __restrict__ active,
               int* __restrict__ iters, const int* __restrict__ limit, double rtol) {
+    ms_alpha_step(Gact, partial_pw, nblk, rr, pw, alpha, alpha_old, beta_old, list, nlist, pos, sigma, zeta,
+                  zeta_old, zeta_new, alpha_s, active);
+    __syncthreads();
     reduce_rows_block(partial, nblk, (1 + nd) * Gact, rc);
     for (int i = threadIdx.x; i < nlist; i += blockDim.x) {
         const int s = list[i];
@@ -1047,16 +1060,14 @@ void mscg_run(const MatvecFn<double>& A, const std::function<void(int, int)>& sw
     const int check = 16;
     for (int it = 0; it < maxit && Gact > 0; ++it) {
         A(B.p, B.w, Gact, st, nullptr);
-        hipLaunchKernelGGL(k_dot_partial<double>, dim3(nblk, Gact), dim3(RB), 0, st, B.p, n, B.w, n, n, B.partial);
+        hipLaunchKernelGGL(k_dot_partial<double>, dim3(nblk, Gact), dim3(RB), 0, st, B.p, n, B.w, n, n,
+                           B.partial_pw);
         KRY_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_ms_alpha, dim3(1), dim3(RB), 0, st, Gact, B.partial, nblk, B.rr, B.pw, B.alpha,
-                           B.alpha_old, B.beta_old, B.list, nlist, B.pos, B.sigma, B.zeta, B.zeta_old, B.zeta_new,
-                           B.alpha_s, B.active);
-        KRY_HIP(hipGetLastError());
-        ms_r(nd, nblk, Gact, st, B.r, B.w, D, B.alpha, n, B.partial);
-        hipLaunchKernelGGL(k_ms_beta, dim3(1), dim3(RB), 0, st, Gact, nd, B.partial, nblk, B.rr, B.rc, B.beta, B.alpha,
-                           B.alpha_old, B.beta_old, B.bnorm2, B.list, nlist, B.pos, B.zeta, B.zeta_old, B.zeta_new,
-                           B.alpha_s, B.d, B.Q, B.relres, B.active, B.iters, B.limit, rtol);
+        ms_r(nd, nblk, Gact, st, B.r, B.w, D, B.partial_pw, B.rr, n, B.partial);
+        hipLaunchKernelGGL(k_ms_beta, dim3(1), dim3(RB), 0, st, Gact, nd, B.partial_pw, B.partial, nblk, B.rr, B.rc,
+                           B.pw, B.beta, B.alpha, B.alpha_old, B.beta_old, B.bnorm2, B.list, nlist, B.pos, B.sigma,
+                           B.zeta, B.zeta_old, B.zeta_new, B.alpha_s, B.d, B.Q, B.relres, B.active, B.iters, B.limit,
+                           rtol);
         KRY_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_ms_p, dim3((unsigned)ublocks, Gact), dim3(256), 0, st, B.p, B.r, B.beta, n);
         KRY_HIP(hipGetLastError());

@@ -57,6 +57,7 @@ struct MsCgBuffers {
     double* gram;           // nd x nd
     int* rhs;               // G
     double* partial;        // (1 + nd) G x nblk (at least nd x nd x nblk)
+    double* partial_pw;     // G x nblk: p . w partials, read while k_ms_r writes `partial`
 };
 // A(x, y, k, st) applies the base operators of positions 0..k-1;
 // swap(a, b) exchanges whatever the caller keeps per position (spectra).
