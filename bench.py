@@ -50,14 +50,30 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--matvec-only", action="store_true", help="only the isolated batched product (profiling)")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=200)
-    ap.add_argument("--serve-sides", type=str, default="128,512",
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-plain-sample", type=int, default=200,
+                    help="requests of the stream also run in the plain FP64 form (accuracy and rate)")
+    ap.add_argument("--serve-sides", type=str, default="128,2048",
                     help="grid sides log-uniform in [lo,hi] for the served stream (the full served workload uses 128,2048)")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-budget-gib", type=int, default=64, help="the server's HBM budget")
+    ap.add_argument("--serve-sweep", type=str, default="0.5,0.8,1.0", help="arrival rates, fractions of saturation")
     ap.add_argument("--multi", type=int, default=64, help="independent problems in the multi-problem form (0: skip)")
     ap.add_argument("--multi-sides", type=str, default="64,1024")
     ap.add_argument("--multi-only", action="store_true", help="only the multi-problem form")
     ap.add_argument("--serve-only", action="store_true", help="only the served form")
+    ap.add_argument("--no-c4", action="store_true", help="skip the large anisotropic end-to-end problem")
+    ap.add_argument("--c4-only", action="store_true", help="only the large anisotropic end-to-end problem")
+    ap.add_argument("--c4-n", type=int, default=2048)
+    ap.add_argument("--c4-probes", type=int, default=10)
+    ap.add_argument("--c4-steps", type=int, default=50)
+    ap.add_argument("--c4-lanczos-rtol", type=float, default=1e-5)
+    ap.add_argument("--c4-lanczos-max", type=int, default=400)
+    ap.add_argument("--c4-cg-rtol", type=float, default=1e-7)
+    ap.add_argument("--c4-maxiter", type=int, default=20)
+    ap.add_argument("--c4-xtol", type=float, default=2e-2)
+    ap.add_argument("--c4-boot", type=int, default=20)
+    ap.add_argument("--c4-exact", type=int, default=32, help="missing cells with exact variances")
     ap.add_argument("--no-ext", action="store_true", help="skip the extension rows (irregular data, covariates, "
                                                           "the paper's objective, posterior variance)")
     ap.add_argument("--ext-only", action="store_true", help="only the extension rows")
@@ -109,6 +125,9 @@ def main():
         return
     if args.ext_only:
         print(json.dumps({"extensions": ext_bench(args, K, synth, np)}))
+        return
+    if args.c4_only:
+        print(json.dumps({"config4": config4_bench(args, K, synth, np)}))
         return
     n = args.n
     nu, rho, eta = 1.5, 0.05, 0.2
@@ -364,17 +383,21 @@ def serve_bench(args, K, synth, np):
     """Served form: a Poisson stream of requests (70 % likelihood, 30 % kriging
     at 16 held-out cells with exact variances) on grids with sides log-uniform
     in the given range, 10-50 % missing (uniform or blob masks), nu in
-    {0.5, 1.5, 2.5}.  Problems are created once and stay device-resident.
-    Reports p50/p99 latency (submit to completion) and throughput with
-    Poisson arrivals at 50, 80 and 100 % of the measured saturation rate (80 %
-    is the headline), and the same requests run sequentially in the plain FP64
-    single-request form on the same GPU."""
+    {0.5, 1.5, 2.5}.  Problems are created once and stay device-resident; the
+    server runs under a finite HBM budget.  Reports p50/p99 latency (submit to
+    completion) and throughput with Poisson arrivals at 50, 80 and 100 % of
+    the measured saturation rate (80 % is the headline).  Served requests run
+    the precision form (FP32 transforms) at the same CG tolerance as the plain
+    FP64 form; a stratified sample of the stream (every k-th request) is also
+    run in the plain FP64 single-request form on the same GPU, for its rate
+    and for each request's relative log-likelihood difference."""
     lo, hi = (int(x) for x in args.serve_sides.split(","))
     rng = np.random.default_rng(505)
     ctx = K.kry_ctx_create()
     nprob = 8
     sides = synth.log_uniform_sides(nprob, lo, hi, seed=506)
     probs, masks = [], []
+    t_setup = time.perf_counter()
     for i, n in enumerate(sides):
         frac = float(rng.uniform(0.1, 0.5))
         if rng.uniform() < 0.5:
@@ -388,6 +411,8 @@ def serve_bench(args, K, synth, np):
         K.kry_problem_set_data(h, x[0] + np.sqrt(0.2) * rng.standard_normal((int(n), int(n))))
         probs.append(h)
         masks.append(mask)
+    log("serve: %d problems, sides %s (%.1f s set-up)" % (nprob, [int(v) for v in sides],
+                                                          time.perf_counter() - t_setup))
     reqs = []
     for _ in range(args.serve_requests):
         pi = int(rng.integers(nprob))
@@ -398,8 +423,9 @@ def serve_bench(args, K, synth, np):
         else:
             miss = np.flatnonzero(masks[pi].ravel() == 0)
             reqs.append(("krige", pi, th, rng.choice(miss, size=16, replace=False)))
-    o32 = K.kry_opts_default(lanczos_steps=30, num_probes=10, precision=K.KRY_FP32, cg_rtol=1e-6)
+    o32 = K.kry_opts_default(lanczos_steps=30, num_probes=10, precision=K.KRY_FP32, cg_rtol=1e-8)
     o64 = K.kry_opts_default(lanczos_steps=30, num_probes=10, precision=K.KRY_FP64, cg_rtol=1e-8)
+    budget = args.serve_budget_gib << 30
 
     def submit(srv, r, opts):
         kind, pi, th, tg = r
@@ -407,62 +433,101 @@ def serve_bench(args, K, synth, np):
             return K.kry_server_submit(srv, K.KRY_REQ_LOGLIK, probs[pi], th, opts)
         return K.kry_server_submit(srv, K.KRY_REQ_KRIGE, probs[pi], th, opts, tg, variances=True)
 
-    srv = K.kry_server_create(ctx, slots=args.serve_slots, max_batch=16)
+    base_mem, _ = K.kry_ctx_memory(ctx, reset_peak=True)
+    srv = K.kry_server_create(ctx, slots=args.serve_slots, hbm_budget_bytes=budget, max_batch=16)
     try:
         # saturation: everything submitted at once
         t0 = time.perf_counter()
-        pend = [submit(srv, r, o32) for r in reqs]
-        for p_ in pend:
-            K.kry_server_wait(srv, p_)
+        pend0 = [submit(srv, r, o32) for r in reqs]
+        resp0 = []
+        for j, p_ in enumerate(pend0):
+            resp0.append(K.kry_server_wait(srv, p_))
+            if (j + 1) % 25 == 0:
+                log("serve: saturation run, %d of %d done (%.1f s)" % (j + 1, len(reqs), time.perf_counter() - t0))
         sat = len(reqs) / (time.perf_counter() - t0)
         log("serve: saturation %.1f requests/s" % sat)
-        # Poisson arrivals at 50, 80 and 100 % of saturation; the 80 % run is
-        # the headline
+        # Poisson arrivals at fractions of saturation; the 80 % run is the headline
         sweep = {}
-        for frac in (0.5, 0.8, 1.0):
+        for frac in [float(f) for f in args.serve_sweep.split(",")]:
             rate = frac * sat
             gaps = rng.exponential(1.0 / rate, size=len(reqs))
             t0 = time.perf_counter()
             pend = []
             tnext = t0
-            for r, gap in zip(reqs, gaps):
+            for j, (r, gap) in enumerate(zip(reqs, gaps)):
                 tnext += gap
                 while time.perf_counter() < tnext:
                     time.sleep(min(0.0005, max(0.0, tnext - time.perf_counter())))
                 pend.append(submit(srv, r, o32))
-            resp_f = [K.kry_server_wait(srv, p_) for p_ in pend]
+                if (j + 1) % 25 == 0:
+                    log("serve: %d%% run, %d of %d submitted" % (100 * frac, j + 1, len(reqs)))
+            resp_f = []
+            for j, p_ in enumerate(pend):
+                resp_f.append(K.kry_server_wait(srv, p_))
+                if (j + 1) % 25 == 0:
+                    log("serve: %d%% run, %d of %d done" % (100 * frac, j + 1, len(reqs)))
             wall_f = time.perf_counter() - t0
             lat_f = np.array([r.t_end - r.t_submit for r in resp_f]) * 1e3
             sweep[frac] = (rate, resp_f, wall_f, lat_f)
             log("serve at %d%% of saturation: p50 %.1f ms p99 %.1f ms, %.1f req/s" %
                 (100 * frac, np.percentile(lat_f, 50), np.percentile(lat_f, 99), len(reqs) / wall_f))
-        rate, resp, wall, lat = sweep[0.8]
+        head = 0.8 if 0.8 in sweep else sorted(sweep)[-1]
+        rate, resp, wall, lat = sweep[head]
     finally:
         K.kry_server_destroy(srv)
+    _, peak_mem = K.kry_ctx_memory(ctx)
+    statuses = {}
+    for r in resp0 + [x for v in sweep.values() for x in v[1]]:
+        statuses[int(r.status)] = statuses.get(int(r.status), 0) + 1
     n_ll = sum(1 for r in reqs if r[0] == "loglik")
-    # sequential plain FP64 form of the same requests
+    # service time (start to end) of the saturation run's requests, by grid side and kind
+    service = {}
+    for r, rs in zip(reqs, resp0):
+        key = "%d %s" % (int(sides[r[1]]), r[0])
+        service.setdefault(key, []).append(rs.t_end - rs.t_start)
+    service = {k: {"requests": len(v), "mean_s": float(np.mean(v)), "max_s": float(np.max(v))}
+               for k, v in sorted(service.items(), key=lambda kv: (int(kv[0].split()[0]), kv[0]))}
+    # plain FP64 form, one request at a time, on every k-th request
+    k = max(1, len(reqs) // max(1, args.serve_plain_sample))
+    sample = list(range(0, len(reqs), k))
+    errs, kerr = [], []
     t1 = time.perf_counter()
-    for kind, pi, th, tg in reqs:
+    for jj, i in enumerate(sample):
+        if jj % 10 == 0:
+            log("serve: plain FP64 sample, %d of %d" % (jj, len(sample)))
+        kind, pi, th, tg = reqs[i]
         if kind == "loglik":
-            K.kry_loglik(probs[pi], th, o64, allow_noconv=True)
+            ref = K.kry_loglik(probs[pi], th, o64, allow_noconv=True)["loglik"]
+            errs.append(abs(resp0[i].loglik.loglik - ref) / abs(ref))
         else:
-            K.kry_krige(probs[pi], th, o64, tg)
+            m64, _, _ = K.kry_krige(probs[pi], th, o64, tg)
+            m32 = pend0[i].outputs["mean_x"]
+            kerr.append(float(np.max(np.abs(m32 - m64)) / max(np.max(np.abs(m64)), 1e-300)))
     seq = time.perf_counter() - t1
     for h in probs:
         K.kry_problem_destroy(h)
     K.kry_ctx_destroy(ctx)
-    out = {"requests": len(reqs), "loglik_fraction": n_ll / len(reqs), "sides": [lo, hi], "slots": args.serve_slots,
-           "saturation_req_per_s": sat, "arrival_rate_per_s": rate, "p50_ms": float(np.percentile(lat, 50)),
-           "p99_ms": float(np.percentile(lat, 99)), "req_per_s": len(reqs) / wall, "loglik_evals_per_s": n_ll / wall,
-           "max_batch_seen": int(max(r.batch for r in resp)),
-           "plain_fp64_sequential_req_per_s": len(reqs) / seq,
-           "plain_fp64_sequential_loglik_evals_per_s": n_ll / seq,
-           "served_vs_plain": (len(reqs) / wall) / (len(reqs) / seq),
+    plain_rate = len(sample) / seq
+    out = {"requests": len(reqs), "loglik_fraction": n_ll / len(reqs), "sides": [lo, hi],
+           "problem_sides": [int(v) for v in sides], "slots": args.serve_slots,
+           "hbm_budget_bytes": budget, "slot_peak_bytes": int(peak_mem - base_mem), "statuses": statuses,
+           "saturation_req_per_s": sat, "arrival_rate_per_s": rate, "headline_fraction": head,
+           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "req_per_s": len(reqs) / wall, "loglik_evals_per_s": n_ll / wall,
+           "max_batch_seen": int(max(r.batch for r in resp)), "service_time_by_side": service,
+           "served_precision": "fp32 transforms, fp64 reductions, cg_rtol 1e-8",
+           "plain_fp64": {"sample": "every %d-th request (%d of %d), sequential, cg_rtol 1e-8" % (k, len(sample),
+                                                                                                 len(reqs)),
+                          "req_per_s": plain_rate, "loglik_requests": len(errs),
+                          "loglik_rel_err_max": float(max(errs)) if errs else None,
+                          "loglik_rel_err_median": float(np.median(errs)) if errs else None,
+                          "krige_mean_rel_err_max": float(max(kerr)) if kerr else None},
+           "served_vs_plain": (len(reqs) / wall) / plain_rate,
            "arrival_sweep": [{"fraction_of_saturation": f, "arrival_rate_per_s": v[0],
                               "p50_ms": float(np.percentile(v[3], 50)), "p99_ms": float(np.percentile(v[3], 99)),
                               "req_per_s": len(reqs) / v[2]} for f, v in sweep.items()]}
-    log("serve: p50 %.1f ms p99 %.1f ms, %.1f req/s vs plain fp64 sequential %.1f req/s" %
-        (out["p50_ms"], out["p99_ms"], out["req_per_s"], out["plain_fp64_sequential_req_per_s"]))
+    log("serve: p50 %.1f ms p99 %.1f ms, %.1f req/s vs plain fp64 %.1f req/s; loglik rel err max %s" %
+        (out["p50_ms"], out["p99_ms"], out["req_per_s"], plain_rate, out["plain_fp64"]["loglik_rel_err_max"]))
     return out
 
 
@@ -625,6 +690,83 @@ def ext_bench(args, K, synth, np):
     return out
 
 
+def config4_bench(args, K, synth, np):
+    """Large anisotropic problem end to end: a 2048 x 2048 grid with 40 % of
+    the cells missing in blob-shaped (cloud-like) masks, Matern nu = 1, range
+    0.05, geometric anisotropy ratio 2 at 30 degrees, nugget ratio 0.1, data
+    by circulant embedding on a PSD torus; the profile-likelihood fit over
+    (range, nugget ratio) by Nelder-Mead with FP32 transforms and FP64
+    quadrature (common random numbers), then kriging means and bootstrap
+    variances (B draws) at every missing cell, and exact variances at a
+    seeded subset of them to bound the bootstrap's Monte-Carlo error."""
+    n = args.c4_n
+    ang = np.pi / 6
+    truth = K.theta(sigma2=1.0, tau2=0.1, range=0.05, nu=1.0, aniso_ratio=2.0, aniso_angle=ang)
+    mask = synth.blob_mask(n, n, 0.4, seed=401, rmin=10, rmax=80)
+    ctx = K.kry_ctx_create()
+    out = {"grid": n, "missing": float(1 - mask.mean())}
+    try:
+        t0 = time.perf_counter()
+        h = K.kry_problem_create(ctx, n, n, mask)
+        Nt = K.kry_psd_torus(h, truth)
+        x, _ = K.kry_sample(h, truth, Nt[0], Nt[1], 402, 0, 1, n, n)
+        rng = np.random.default_rng(403)
+        K.kry_problem_set_data(h, x[0] + np.sqrt(truth.tau2) * rng.standard_normal((n, n)))
+        del x
+        p, N1, N2 = K.kry_problem_info(h)
+        out.update({"p": int(p), "embedding": [N1, N2], "psd_torus": list(Nt),
+                    "setup_s": time.perf_counter() - t0})
+        log("config 4: %dx%d, p = %d, embedding %dx%d, sampling torus %s" % (n, n, p, N1, N2, Nt))
+        # Lanczos runs to the adaptive stopping rule: with a fixed 50 steps the
+        # quadrature is far from converged at this size (the log-determinant
+        # is off by about 4 % and the fit lands near range 0.03)
+        opts = K.kry_opts_default(lanczos_steps=args.c4_steps, num_probes=args.c4_probes, precision=K.KRY_FP32,
+                                  reorth=0, cg_rtol=args.c4_cg_rtol, seed=303, lanczos_rtol=args.c4_lanczos_rtol,
+                                  lanczos_max_steps=args.c4_lanczos_max)
+        init = K.theta(sigma2=1.0, tau2=0.2, range=0.08, nu=1.0, aniso_ratio=2.0, aniso_angle=ang)
+        t1 = time.perf_counter()
+        est, at = K.kry_fit(h, init, 3, opts, xtol=args.c4_xtol, maxiter=args.c4_maxiter)
+        fit_s = time.perf_counter() - t1
+        eta_hat = est.tau2 / est.sigma2
+        out["fit"] = {"seconds": fit_s, "range": est.range, "nugget_ratio": eta_hat, "sigma2": est.sigma2,
+                      "loglik_profiled": at["loglik_profiled"], "logdet_se": at["logdet_se"],
+                      "lanczos_steps_at_estimate": at["lanczos_steps_used"], "cg_iters_at_estimate": at["cg_iters"],
+                      "xtol": args.c4_xtol, "maxiter": args.c4_maxiter, "probes": args.c4_probes,
+                      "lanczos": "adaptive, rtol %g, at most %d steps" % (args.c4_lanczos_rtol, args.c4_lanczos_max),
+                      "cg_rtol": args.c4_cg_rtol, "start": [0.08, 0.2], "truth": [0.05, 0.1]}
+        log("config 4 fit: range %.4f nugget ratio %.4f sigma2 %.3f in %.1f s" % (est.range, eta_hat, est.sigma2,
+                                                                                 fit_s))
+        # kriging at every missing cell: means and bootstrap variances
+        miss = np.flatnonzero(mask.ravel() == 0)
+        kopts = K.kry_opts_default(precision=K.KRY_FP32, cg_rtol=1e-8, seed=404)
+        t2 = time.perf_counter()
+        mean, vx, vy = K.kry_krige(h, est, kopts, None, ntargets=miss.size, want_var=True,
+                                   bootstrap_B=args.c4_boot)
+        krige_s = time.perf_counter() - t2
+        # exact variances at a seeded subset of the missing cells
+        sub = np.sort(np.random.default_rng(405).choice(miss.size, size=args.c4_exact, replace=False))
+        t3 = time.perf_counter()
+        m2, ex, ey = K.kry_krige(h, est, kopts, miss[sub], want_var=True)
+        exact_s = time.perf_counter() - t3
+        ratio = vx[sub] / ex
+        # each bootstrap variance is the exact one times chi2_B / B: mean
+        # ratio 1 with standard error about sqrt(2 / B) / sqrt(cells), cells
+        # treated as independent
+        se = np.sqrt(2.0 / args.c4_boot) / np.sqrt(sub.size)
+        out["krige"] = {"cells": int(miss.size), "bootstrap_B": args.c4_boot, "seconds": krige_s,
+                        "cells_per_s": miss.size / krige_s, "exact_subset": int(sub.size),
+                        "exact_subset_seconds": exact_s,
+                        "mean_abs_diff_subset": float(np.max(np.abs(m2 - mean[sub]))),
+                        "bootstrap_over_exact_mean": float(ratio.mean()), "bootstrap_over_exact_se": float(se),
+                        "mean_var_x": float(vx.mean()), "mean_var_y": float(vy.mean())}
+        log("config 4 kriging: %d cells, B = %d in %.1f s; bootstrap/exact %.3f +- %.3f" %
+            (miss.size, args.c4_boot, krige_s, ratio.mean(), se))
+        K.kry_problem_destroy(h)
+    finally:
+        K.kry_ctx_destroy(ctx)
+    return out
+
+
 def cpu_baseline(n, mask, th, p, budget_s=15.0):
     """The oracle's direct O(p^2) masked product on a bounded sample of output
     rows of the same workload, scaled to full products per second."""
@@ -636,19 +778,41 @@ def cpu_baseline(n, mask, th, p, budget_s=15.0):
     g = (n, n, 1.0 / n, 1.0 / n)
     rng = np.random.default_rng(5)
     v = rng.standard_normal(p)
-    t0 = time.perf_counter()
-    T = lag_table(n, n, 1.0 / n, 1.0 / n, th)
-    t_table = time.perf_counter() - t0
-    rows = 0
-    t1 = time.perf_counter()
-    while time.perf_counter() - t1 < budget_s:
-        direct.masked_matvec(g, mask, th, v, rows=np.arange(rows, rows + 25), table=T)
-        rows += 25
-    dt = time.perf_counter() - t1
+    host = {"cpu_count": os.cpu_count(), "model": None, "blas_threads": None}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    host["model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        from threadpoolctl import threadpool_limits
+        limit = threadpool_limits(limits=1)  # the oracle on one core, BLAS included
+    except ImportError:
+        limit = None
+    try:
+        if limit is not None:
+            from threadpoolctl import threadpool_info
+            host["blas_threads"] = [i.get("num_threads") for i in threadpool_info()]
+        t0 = time.perf_counter()
+        T = lag_table(n, n, 1.0 / n, 1.0 / n, th)
+        t_table = time.perf_counter() - t0
+        rows = 0
+        t1 = time.perf_counter()
+        while time.perf_counter() - t1 < budget_s:
+            direct.masked_matvec(g, mask, th, v, rows=np.arange(rows, rows + 25), table=T)
+            rows += 25
+        dt = time.perf_counter() - t1
+    finally:
+        if limit is not None:
+            limit.restore_original_limits()
     rate = rows / dt / p
-    return {"value": rate, "unit": "matvecs/s", "cores": 1, "kind": "oracle",
+    return {"value": rate, "unit": "matvecs/s", "cores": 1, "kind": "oracle", "host": host,
             "sample": "direct O(p^2) masked product, %d of %d output rows (%.1f s) plus the lag table (%.1f s, "
-                      "not counted) at 1024x1024, 30%% missing" % (rows, p, dt, t_table)}
+                      "not counted) at 1024x1024, 30%% missing; thread pools limited to one thread" %
+                      (rows, p, dt, t_table)}
 
 
 if __name__ == "__main__":

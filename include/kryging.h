@@ -203,6 +203,12 @@ kry_status kry_set_graphs(kry_ctx* ctx, int32_t enable);
  * device.  Creates the library's stream (default priority). */
 kry_status kry_ctx_create(int32_t device, uint64_t hbm_budget_bytes, kry_ctx** out);
 void kry_ctx_destroy(kry_ctx* ctx);
+/* Device bytes the context holds now (problems, workspaces, tables, server
+ * slots) and the most it has held since creation or the last reset
+ * (reset_peak != 0 sets the peak to the current value after reading it).
+ * Not part of the paper's method: the request server's admission by HBM
+ * footprint is checked against it. */
+kry_status kry_ctx_memory(kry_ctx* ctx, uint64_t* allocated, uint64_t* peak, int32_t reset_peak);
 
 /* A problem: grid, observation mask (n1*n2 bytes, nonzero = observed; at
  * least one observed cell) and data y (n1*n2 doubles read only where
@@ -470,9 +476,11 @@ kry_status kry_sample(kry_problem* prob, const kry_matern* theta, int32_t N1, in
 /* ---- serving ----------------------------------------------------------------
  * A server runs likelihood and kriging requests on device-resident problems
  * with continuous batching: `slots` worker streams take requests as they
- * arrive, admitting one when a slot is free and the estimated device
- * footprint of all requests in flight stays within hbm_budget_bytes (0 = no
- * limit); queued likelihood requests on the same problem with identical
+ * arrive, admitting one when a slot is free and the device memory of the
+ * slots stays within hbm_budget_bytes (0 = no limit): running slots count
+ * the larger of their workspace and an upper bound of their batch's
+ * footprint, idle slots the workspace they keep, which is released when a
+ * request needs the room; queued likelihood requests on the same problem with identical
  * options are evaluated together (up to max_batch).  A request's result is
  * the same alone and in any mix.  Problems must outlive their requests and
  * must not be modified (kry_problem_set_data) while requests on them are
@@ -499,6 +507,8 @@ typedef struct {
                                 rounding, the Krylov vectors being padded)        */
     kry_loglik_result loglik;
     double t_submit, t_start, t_end;  /* seconds since the server was created  */
+    uint64_t footprint_bytes;  /* admission bound of the batch's device memory  */
+    uint64_t workspace_bytes;  /* device bytes the slot held after the batch    */
 } kry_response;
 /* slots in [1, 16]; max_queue bounds pending (not yet started) requests. */
 kry_status kry_server_create(kry_ctx* ctx, int32_t slots, uint64_t hbm_budget_bytes, int32_t max_batch,

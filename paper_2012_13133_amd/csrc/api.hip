@@ -8,6 +8,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "internal.hpp"
@@ -45,6 +46,7 @@ void* dev_alloc(Ctx& c, size_t bytes) {
                                         std::to_string(c.allocated) + " of " + std::to_string(c.budget) +
                                         " in use)");
         c.allocated += bytes;
+        c.peak = std::max(c.peak, c.allocated);
     }
     void* p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess) {
@@ -176,6 +178,39 @@ MatvecFn<R> masked_op(Problem& P, const void* lam, int64_t lam_tstride, int vpt,
         s.tab_vpp = vpt;
         s.active = active;
         conv_apply<R>(Q, s, st);
+    };
+}
+
+// The FP64 masked product of the multi-shift CG with its direction update
+// p = r + beta p folded into the first stage (masked grid problems).
+MsFusedFn masked_op_update(Problem& P, const void* lam, int64_t lam_tstride, const double* d_eta) {
+    Problem* pp = &P;
+    return [pp, lam, lam_tstride, d_eta](const double* r, double* p, const double* beta, double* w, int nvec,
+                                         hipStream_t st) {
+        Problem& Q = *pp;
+        ConvSpec s;
+        s.N1 = Q.N1;
+        s.N2 = Q.N2;
+        s.nvec = nvec;
+        s.in_mode = IN_COMPACT;
+        s.in = p;
+        s.in_vstride = Q.p;
+        s.rows_in = Q.n1;
+        s.row_len = Q.n2;
+        s.out_mode = OUT_COMPACT;
+        s.out = w;
+        s.out_vstride = Q.p;
+        s.rows_out = Q.n1;
+        s.cols_out = Q.n2;
+        s.vin = p;
+        s.vin_vstride = Q.p;
+        s.eta = d_eta;
+        s.lam = lam;
+        s.lam_tstride = lam_tstride;
+        s.vecs_per_theta = 1;
+        s.upd_r = r;
+        s.upd_beta = beta;
+        conv_apply<double>(Q, s, st);
     };
 }
 
@@ -383,7 +418,9 @@ void solve_device(Problem& P, int precision, const void* lam64, const void* lam3
     KRY_HIP(hipMemcpyAsync(bn.data(), nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
     KRY_HIP(hipStreamSynchronize(st));
     const double inner = std::max(1e-5, rtol);
-    for (int outer = 0; outer < 12; ++outer) {
+    // at most 12 corrections; the residual is measured after each of them,
+    // so relres always describes the X that is returned
+    for (int outer = 0;; ++outer) {
         // residual norms of the FP64 residual
         dot_batched<double>(r64, p, r64, p, p, nrhs, part, nrm, st);
         KRY_HIP(hipMemcpyAsync(rn.data(), nrm, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -393,7 +430,7 @@ void solve_device(Problem& P, int precision, const void* lam64, const void* lam3
             out.relres[v] = bn[v] > 0 ? std::sqrt(rn[v] / bn[v]) : 0.0;
             if (out.relres[v] > rtol) done = false;
         }
-        if (done) break;
+        if (done || outer == 12) break;
         // right-hand sides already at tolerance get a zero inner system, so
         // each solution is the same whatever else shares the launch
         convert<double, float>(r64, b32, vn, st);
@@ -958,9 +995,11 @@ void loglik_points_shared(Problem& P, const kry_matern* thetas, int count, const
             B.rhs = a.take<int>(Gm);
             B.partial = a.take<double>((size_t)(1 + nd) * Gm * nblk);
             B.partial_pw = a.take<double>((size_t)Gm * nblk);
+            B.counter = a.take<unsigned>(1);
         };
         with_arena(P, lay);
         auto A = masked_op<double>(P, P.spec_multi64.ptr, nspec, 1, d_zero);
+        const MsFusedFn fused = P.irregular ? MsFusedFn() : masked_op_update(P, P.spec_multi64.ptr, nspec, d_zero);
         double* lam64 = P.spec_multi64.as<double>();
         auto swp = [&](int a, int b) { swap_vectors<double>(lam64, nspec, a, b, nspec, st); };
         // shift entry t nd + a: point t's system with right-hand side D_a
@@ -974,7 +1013,8 @@ void loglik_points_shared(Problem& P, const kry_matern* thetas, int count, const
         for (int g = 0; g < Gm; ++g) rhs[g] = g % nd;
         std::vector<int> it;
         std::vector<double> rr;
-        mscg_run(A, swp, p, Gm, gos, sig, D, nd, rhs, o->cg_rtol, o->cg_maxit, B, it, rr, M, st);
+        mscg_run(A, P.irregular ? nullptr : &fused, swp, p, Gm, gos, sig, D, nd, rhs, o->cg_rtol, o->cg_maxit, B, it,
+                 rr, M, st);
         for (int t = 0; t < count; ++t) {
             for (int a = 0; a < nd; ++a) {
                 iters[t] = std::max(iters[t], it[(size_t)t * nd + a]);
@@ -1367,11 +1407,24 @@ kry_status kry_ctx_create(int32_t device, uint64_t hbm_budget_bytes, kry_ctx** o
             k->c.tw32 = static_cast<cpx<float>*>(dev_alloc(k->c, TW_N * sizeof(cpx<float>)));
             KRY_HIP(hipMemcpy(k->c.tw64, t64.data(), TW_N * sizeof(cpx<double>), hipMemcpyHostToDevice));
             KRY_HIP(hipMemcpy(k->c.tw32, t32.data(), TW_N * sizeof(cpx<float>), hipMemcpyHostToDevice));
+            // every transform length's pass twiddles now, so that products
+            // allocate nothing later
+            build_plan_tables(k->c);
         } catch (...) {
             kry_ctx_destroy(k);
             throw;
         }
         *out = k;
+    });
+}
+
+kry_status kry_ctx_memory(kry_ctx* ctx, uint64_t* allocated, uint64_t* peak, int32_t reset_peak) {
+    return guard([&] {
+        KRY_REQUIRE(ctx && allocated && peak, "NULL argument");
+        std::lock_guard<std::mutex> g(ctx->c.alloc_mu);
+        *allocated = ctx->c.allocated;
+        *peak = ctx->c.peak;
+        if (reset_peak) ctx->c.peak = ctx->c.allocated;
     });
 }
 
@@ -1420,7 +1473,6 @@ void kry_ctx_destroy(kry_ctx* ctx) {
         if (ctx->c.plan64[i]) (void)hipFree(ctx->c.plan64[i]);
         if (ctx->c.plan32[i]) (void)hipFree(ctx->c.plan32[i]);
     }
-    release_blas(ctx->c);
     dev_free(ctx->c, ctx->c.tw64, TW_N * sizeof(cpx<double>));
     dev_free(ctx->c, ctx->c.tw32, TW_N * sizeof(cpx<float>));
     if (ctx->c.stream) (void)hipStreamDestroy(ctx->c.stream);
@@ -2393,7 +2445,6 @@ kry_status kry_loglik_multi(kry_problem* const* probs, const kry_matern* thetas,
         }
         Ctx& C = *probs[0]->P.ctx;
         bind(C);
-        hipStream_t st = C.stream;
         const int np = nprobes_of(opts);
         const size_t es = opts->precision == KRY_FP32 ? 4 : 8;
         size_t cap = (size_t)48e9;
@@ -2411,43 +2462,106 @@ kry_status kry_loglik_multi(kry_problem* const* probs, const kry_matern* thetas,
             }
             groups[g].push_back(i);
         }
-        std::vector<kry_loglik_result> res(count);
-        for (auto& grp : groups) {
-            // problems with covariates go one at a time
+        // Tasks: each problem with covariates alone; the others in chunks of
+        // one embedding group, whose products share every stage launch.
+        // Tasks run concurrently on up to kWorkers streams, each worker with
+        // one workspace that serves views of its tasks' problems; a task's
+        // results do not depend on which worker runs it or what runs beside it.
+        constexpr int kWorkers = 4;
+        struct Task {
+            std::vector<int> idx;
+            bool cov = false;
+            double cost = 0;
+        };
+        std::vector<Task> tasks;
+        for (const auto& grp : groups) {
             std::vector<int> plain;
             for (int i : grp) {
-                if (probs[i]->P.q > 0) loglik_points(probs[i]->P, &thetas[i], 1, opts, &res[i], st);
+                if (probs[i]->P.q > 0) tasks.push_back(Task{{i}, true, (double)probs[i]->P.N1 * probs[i]->P.N2});
                 else plain.push_back(i);
             }
-            grp = plain;
-        }
-        for (const auto& grp : groups) {
-            if (grp.empty()) continue;
+            if (plain.empty()) continue;
             int64_t pm = 0;
-            for (int i : grp) pm = std::max(pm, probs[i]->P.p);
+            for (int i : plain) pm = std::max(pm, probs[i]->P.p);
             // per problem: Lanczos block and CG / refinement vectors at the padded length
             const size_t per = (size_t)np * pm * es * (opts->reorth ? lanczos_cap(opts) + 3 : 5) + 12 * (size_t)pm * 8;
-            const size_t chunk = std::max<size_t>(1, cap / std::max<size_t>(per, 1));
-            for (size_t a = 0; a < grp.size(); a += chunk) {
-                const size_t b = std::min(grp.size(), a + chunk);
-                std::vector<Problem*> ps;
-                std::vector<kry_matern> th;
-                for (size_t j = a; j < b; ++j) {
-                    ps.push_back(&probs[grp[j]]->P);
-                    th.push_back(thetas[grp[j]]);
-                }
-                std::vector<kry_loglik_result> r(ps.size());
-                Problem work = ps[0]->view();  // a fresh workspace for the group
-                try {
-                    loglik_multi(work, ps, th.data(), opts, r.data(), st);
-                } catch (...) {
-                    work.release_work();
-                    throw;
-                }
-                work.release_work();
-                for (size_t j = a; j < b; ++j) res[grp[j]] = r[j - a];
+            const size_t chunk = std::max<size_t>(1, cap / kWorkers / std::max<size_t>(per, 1));
+            for (size_t a = 0; a < plain.size(); a += chunk) {
+                Task t;
+                t.idx.assign(plain.begin() + a, plain.begin() + std::min(plain.size(), a + chunk));
+                t.cost = (double)t.idx.size() * pm + (double)probs[plain[0]]->P.N1 * probs[plain[0]]->P.N2;
+                tasks.push_back(t);
             }
         }
+        // largest first, so that a worker's buffers reach their size early
+        std::stable_sort(tasks.begin(), tasks.end(), [](const Task& a, const Task& b) { return a.cost > b.cost; });
+        std::vector<kry_loglik_result> res(count);
+        std::mutex mu;
+        size_t next = 0;
+        kry_status err = KRY_OK;
+        std::string err_msg;
+        auto worker = [&]() {
+            hipStream_t ws = nullptr;
+            Problem keep;  // the worker's workspace between tasks
+            keep.ctx = &C;
+            try {
+                KRY_HIP(hipSetDevice(C.device));
+                KRY_HIP(hipStreamCreateWithFlags(&ws, hipStreamNonBlocking));
+                while (true) {
+                    size_t ti;
+                    {
+                        std::lock_guard<std::mutex> g(mu);
+                        if (next >= tasks.size() || err != KRY_OK) break;
+                        ti = next++;
+                    }
+                    const Task& t = tasks[ti];
+                    std::vector<Problem*> ps;
+                    std::vector<kry_matern> th;
+                    for (int i : t.idx) {
+                        ps.push_back(&probs[i]->P);
+                        th.push_back(thetas[i]);
+                    }
+                    std::vector<kry_loglik_result> r(ps.size());
+                    Problem work = ps[0]->view();
+                    work.no_graphs = true;  // several host threads: no stream capture
+                    work.swap_work(keep);
+                    try {
+                        if (t.cov) loglik_points(work, th.data(), 1, opts, r.data(), ws);
+                        else loglik_multi(work, ps, th.data(), opts, r.data(), ws);
+                    } catch (...) {
+                        (void)hipStreamSynchronize(ws);
+                        work.swap_work(keep);
+                        throw;
+                    }
+                    KRY_HIP(hipStreamSynchronize(ws));
+                    work.swap_work(keep);
+                    for (size_t j = 0; j < t.idx.size(); ++j) res[t.idx[j]] = r[j];
+                }
+            } catch (const Error& e) {
+                std::lock_guard<std::mutex> g(mu);
+                if (err == KRY_OK) {
+                    err = e.status;
+                    err_msg = e.what();
+                }
+            } catch (const std::exception& e) {
+                std::lock_guard<std::mutex> g(mu);
+                if (err == KRY_OK) {
+                    err = KRY_EDEVICE;
+                    err_msg = e.what();
+                }
+            }
+            if (ws) {
+                (void)hipStreamSynchronize(ws);
+                (void)hipStreamDestroy(ws);
+            }
+            keep.release_work();
+        };
+        const int nw = (int)std::min<size_t>(kWorkers, tasks.size());
+        std::vector<std::thread> pool;
+        for (int w = 1; w < nw; ++w) pool.emplace_back(worker);
+        worker();
+        for (auto& t : pool) t.join();
+        if (err != KRY_OK) throw Error(err, err_msg);
         std::copy(res.begin(), res.end(), out);
         noconv = any_not_converged(out, count, opts);
     });
@@ -2611,7 +2725,8 @@ void kry::krige_impl(Problem& P, const kry_matern* theta, const kry_opts* opts, 
         // exact: multi-RHS CG on the cross-correlation columns, in chunks
         P.lagtmp.ensure(*P.ctx, (size_t)P.N1 * P.N2 * sizeof(double));
         lag_grid_device(*P.ctx, P.N1, P.N2, P.dx1, P.dx2, th, P.lagtmp.as<double>(), st);
-        const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(256, (int64_t)(2e9 / (8.0 * p * 6))));
+        const int chunk = (int)std::max<int64_t>(
+            1, std::min<int64_t>(std::min<int64_t>(256, nt), (int64_t)(2e9 / (8.0 * p * 6))));
         DevBuf& cb = P.tmp2;
         cb.ensure(*P.ctx, (size_t)chunk * p * 2 * sizeof(double) + (size_t)chunk * 257 * sizeof(double) + 1024);
         double* Cc = cb.as<double>();

@@ -150,6 +150,8 @@ struct StageAArgs {
     const ProbDesc* tab;  // several problems: per-vector mask and block
     int tab_vpp;
     const int* active;    // per-vector skip flags (nullable)
+    const void* upd_r;    // direction update of the compact input (nullable; see ConvSpec)
+    const double* upd_beta;
 };
 
 // Value of input column c of a row (0 beyond the data or off the mask).
@@ -234,6 +236,47 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
                 bs[u * NP + r] = at32(mask.base, w);
                 wd[u * NP + r] = ok ? word : 0u;
             }
+        if (sizeof(R) == 8 && a.upd_r) {
+            // p = r + beta p on the fly, written back: both vectors' values
+            // are loaded together, then the updated ones stored
+            const R* rin = reinterpret_cast<const R*>(a.upd_r) + vec * a.in_vstride;
+            R* pio = const_cast<R*>(vin);
+            const R b = (R)a.upd_beta[a.vec0 + vec];
+            uint32_t cx[VT * NP], cy[VT * NP];
+            R px[VT * NP], py[VT * NP], rx[VT * NP], ry[VT * NP];
+#pragma unroll
+            for (int q = 0; q < VT * NP; ++q) {
+                const int u = q / NP, r = q % NP;
+                const int c0 = 2 * (t + u * TR + r * T);
+                const uint32_t word = wd[q];
+                const uint32_t b0 = 1u << (c0 & 31);
+                const bool lo = (word & b0) != 0u, hi = (word & (b0 << 1)) != 0u;
+                const uint32_t ci = bs[q] + (uint32_t)__popc(word & (b0 - 1u));
+                cx[q] = lo ? ci : 0u;
+                cy[q] = hi ? ci + (lo ? 1u : 0u) : 0u;
+                px[q] = at32(vin, cx[q]);
+                py[q] = at32(vin, cy[q]);
+                rx[q] = at32(rin, cx[q]);
+                ry[q] = at32(rin, cy[q]);
+            }
+#pragma unroll
+            for (int u = 0; u < VT; ++u)
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    v[u * 8 + r] = cpx<R>{(R)0, (R)0};
+                    if (r >= NP) continue;
+                    const int q = u * NP + r;
+                    const int c0 = 2 * (t + u * TR + r * T);
+                    const uint32_t word = wd[q];
+                    const uint32_t b0 = 1u << (c0 & 31);
+                    const bool lo = (word & b0) != 0u, hi = (word & (b0 << 1)) != 0u;
+                    const R x = rx[q] + b * px[q];
+                    const R y = ry[q] + b * py[q];
+                    if (lo) at32(pio, cx[q]) = x;
+                    if (hi) at32(pio, cy[q]) = y;
+                    v[u * 8 + r] = cpx<R>{lo ? x : (R)0, hi ? y : (R)0};
+                }
+        } else {
 #pragma unroll
         for (int u = 0; u < VT; ++u)
 #pragma unroll
@@ -249,6 +292,7 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
                 const R y = at32(vin, hi ? ci + (lo ? 1u : 0u) : 0u);
                 v[u * 8 + r] = cpx<R>{lo ? x : (R)0, hi ? y : (R)0};
             }
+        }
     } else {
 #pragma unroll
         for (int u = 0; u < VT; ++u)
@@ -837,6 +881,13 @@ static const cpx<R>* plan_table(Ctx& c, int log2L) {
     return static_cast<const cpx<R>*>(slot);
 }
 
+void build_plan_tables(Ctx& c) {
+    for (int lg = 3; lg <= 13; ++lg) {
+        plan_table<double>(c, lg);
+        plan_table<float>(c, lg);
+    }
+}
+
 struct RowTiling {
     int RT, T, threads;
     size_t lds;
@@ -952,6 +1003,10 @@ static void run_stage_a(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R
     a.tab = s.tab;
     a.tab_vpp = s.tab_vpp;
     a.active = s.active ? s.active + vec0 : nullptr;
+    KRY_REQUIRE(!s.upd_r || (s.in_mode == IN_COMPACT && sizeof(R) == 8 && s.upd_beta && !s.tab),
+                "the direction update takes compact FP64 inputs of one problem");
+    a.upd_r = s.upd_r ? (const void*)((const R*)s.upd_r + vec0 * s.in_vstride) : nullptr;
+    a.upd_beta = s.upd_beta;
     dim3 grid((s.rows_in + t.RT - 1) / t.RT, nvec);
     const int lg = ilog2(M);
     Ctx& c = *P.ctx;
@@ -1069,18 +1124,29 @@ void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st) {
     const int rows_max = s.rows_in > s.rows_out ? s.rows_in : s.rows_out;
     const int ldY = ((rows_max + ta.RT - 1) / ta.RT) * ta.RT;
     const int64_t Yvs = (int64_t)(M + 1) * ldY;
-    // vectors go through in chunks that keep the intermediate near 4 GB
+    // vectors go through in chunks that keep the intermediate near 4 GB (or
+    // within the caller's workspace)
     const int64_t per_vec = Yvs * (int64_t)sizeof(cpx<R>);
     int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(s.nvec, (int64_t)(4LL << 30) / per_vec));
     chunk = std::min(chunk, 65535);
-    P.Y.ensure(*P.ctx, (size_t)Yvs * chunk * sizeof(cpx<R>));
-    cpx<R>* Y = P.Y.as<cpx<R>>();
+    cpx<R>* Y;
+    if (s.ws) {
+        const int64_t fit = (int64_t)(s.ws_bytes / (size_t)per_vec);
+        KRY_REQUIRE(fit >= 1, "workspace smaller than one vector's transform intermediate (" +
+                                  std::to_string(per_vec) + " bytes)");
+        chunk = (int)std::min<int64_t>(chunk, fit);
+        Y = static_cast<cpx<R>*>(s.ws);
+    } else {
+        P.Y.ensure(*P.ctx, (size_t)Yvs * chunk * sizeof(cpx<R>));
+        Y = P.Y.as<cpx<R>>();
+    }
     StageProfile& pr = P.ctx->prof;
+    const bool timing = pr.on && !s.ws;  // (recording events would create them)
     for (int v0 = 0; v0 < s.nvec; v0 += chunk) {
         const int nv = std::min(chunk, s.nvec - v0);
         std::array<int, 5> rec{};
         auto mark = [&](int slot) {
-            if (!pr.on) return;
+            if (!timing) return;
             if (pr.next == pr.pool.size()) {
                 hipEvent_t e;
                 KRY_HIP(hipEventCreate(&e));
@@ -1097,7 +1163,7 @@ void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st) {
         mark(2);
         run_stage_c<R>(P, s, v0, nv, Y, ldY, Yvs, tc, vt, csplit, st);
         mark(3);
-        if (pr.on) {
+        if (timing) {
             rec[4] = nv;
             pr.recs.push_back(rec);
         }
@@ -1106,6 +1172,19 @@ void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st) {
 
 template void conv_apply<double>(Problem&, const ConvSpec&, hipStream_t);
 template void conv_apply<float>(Problem&, const ConvSpec&, hipStream_t);
+
+template <typename R>
+size_t conv_bytes_per_vec(int N1, int N2, int rows, Ctx& c, int nvec) {
+    const int M = N2 / 2;
+    const Tuning tu = c.tuning_for(N1, N2, (int)sizeof(R), nvec);
+    const int vt = (M >= 1024 && tu.row_vt == 2) ? 2 : 1;
+    const bool asplit = M >= 1024 && (tu.row_split & 1) != 0;
+    const RowTiling ta = row_tiling<R>(M, tu.rt_scale, vt, asplit);
+    const int ldY = ((rows + ta.RT - 1) / ta.RT) * ta.RT;
+    return (size_t)(M + 1) * ldY * sizeof(cpx<R>);
+}
+template size_t conv_bytes_per_vec<double>(int, int, int, Ctx&, int);
+template size_t conv_bytes_per_vec<float>(int, int, int, Ctx&, int);
 
 // ---------------------------------------------------------------------------
 // Lag grid and spectrum
@@ -1165,32 +1244,50 @@ __global__ void k_minmax_final(const double* __restrict__ part, int nb, double* 
     out[1] = hi;
 }
 
+size_t spectrum_ws_bytes(int N1, int N2) {
+    const int M = N2 / 2;
+    const RowTiling ta = row_tiling<double>(M);
+    const int ldY = ((N1 + ta.RT - 1) / ta.RT) * ta.RT;
+    const size_t lag = ((size_t)N1 * N2 * sizeof(double) + 255) & ~size_t(255);
+    return lag + (size_t)(M + 1) * ldY * sizeof(cpx<double>) + 1024 * 2 * sizeof(double);
+}
+
 void spectrum_device(Problem& P, int N1, int N2, const Matern& th, double* d_lam, double* lam_min,
-                     double* lam_max, hipStream_t st, bool drange) {
+                     double* lam_max, hipStream_t st, bool drange, void* ws) {
     Ctx& C = *P.ctx;
     const int M = N2 / 2;
-    P.lagtmp.ensure(C, (size_t)N1 * N2 * sizeof(double));
-    lag_grid_device(C, N1, N2, P.dx1, P.dx2, th, P.lagtmp.as<double>(), st, drange);
     // stage A over every row of the lag grid, then the forward column pass
     const RowTiling ta = row_tiling<double>(M);
     const int ldY = ((N1 + ta.RT - 1) / ta.RT) * ta.RT;
     const int64_t Yvs = (int64_t)(M + 1) * ldY;
-    P.spectmp.ensure(C, (size_t)Yvs * sizeof(cpx<double>) + 1024 * 2 * sizeof(double));
-    cpx<double>* Y = P.spectmp.as<cpx<double>>();
+    double* lag;
+    cpx<double>* Y;
+    if (ws) {
+        lag = static_cast<double*>(ws);
+        Y = reinterpret_cast<cpx<double>*>(static_cast<char*>(ws) +
+                                           (((size_t)N1 * N2 * sizeof(double) + 255) & ~size_t(255)));
+    } else {
+        P.lagtmp.ensure(C, (size_t)N1 * N2 * sizeof(double));
+        P.spectmp.ensure(C, (size_t)Yvs * sizeof(cpx<double>) + 1024 * 2 * sizeof(double));
+        lag = P.lagtmp.as<double>();
+        Y = P.spectmp.as<cpx<double>>();
+    }
+    lag_grid_device(C, N1, N2, P.dx1, P.dx2, th, lag, st, drange);
     ConvSpec s;
     s.N1 = N1;
     s.N2 = N2;
     s.nvec = 1;
     s.in_mode = IN_DENSE;
-    s.in = P.lagtmp.ptr;
+    s.in = lag;
     s.in_vstride = 0;
     s.in_rstride = N2;
     s.rows_in = N1;
     s.row_len = N2;
     run_stage_a<double>(P, s, 0, 1, Y, ldY, Yvs, ta, 1, false, st);
     run_stage_b<double>(P, N1, M, 0, 1, Y, ldY, Yvs, N1, N1, nullptr, 0, 1, d_lam, st);
+    if (!lam_min) return;
     // min / max
-    double* part = reinterpret_cast<double*>(reinterpret_cast<char*>(P.spectmp.ptr) + (size_t)Yvs * sizeof(cpx<double>));
+    double* part = reinterpret_cast<double*>(reinterpret_cast<char*>(Y) + (size_t)Yvs * sizeof(cpx<double>));
     const int64_t n = (int64_t)(M + 1) * N1;
     int nb = (int)((n + 255) / 256);
     if (nb > 512) nb = 512;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <array>
+#include <functional>
 #include <map>
 #include <tuple>
 #include <cstdint>
@@ -61,6 +62,7 @@ struct Ctx {
     StageProfile prof;
     uint64_t budget = 0;     // 0 = unlimited
     uint64_t allocated = 0;  // bytes currently held through dev_alloc
+    uint64_t peak = 0;       // largest `allocated` since creation or the last reset
     cpx<double>* tw64 = nullptr;
     cpx<float>* tw32 = nullptr;
     void* plan64[14] = {};  // per-length pass twiddle tables (index log2 length)
@@ -73,8 +75,6 @@ struct Ctx {
     std::mutex tune_mu;
     static constexpr int kSmallBatch = 8;
     static int batch_class(int nvec) { return nvec <= kSmallBatch ? 0 : 1; }
-    void* blas = nullptr;    // rocBLAS handle for the dense DFT / low-rank products (lazily created)
-    std::mutex blas_mu;
     // The setting for products of nvec vectors: that batch class's, else the
     // other class's, else the built-in default.
     Tuning tuning_for(int N1, int N2, int real_bytes, int nvec = 1 << 30) {
@@ -224,6 +224,22 @@ struct Problem {
         v.is_view = true;
         return v;
     }
+    // exchange workspaces with another problem or view (the immutable part
+    // stays), so that one worker's buffers serve views of several problems
+    void swap_work(Problem& o) {
+        for (auto pr : {std::make_pair(&Y, &o.Y), std::make_pair(&lagtmp, &o.lagtmp),
+                        std::make_pair(&spectmp, &o.spectmp), std::make_pair(&spec_multi64, &o.spec_multi64),
+                        std::make_pair(&spec_multi32, &o.spec_multi32), std::make_pair(&kws, &o.kws),
+                        std::make_pair(&scal, &o.scal), std::make_pair(&tmp1, &o.tmp1), std::make_pair(&tmp2, &o.tmp2),
+                        std::make_pair(&tmp3, &o.tmp3), std::make_pair(&tmp4, &o.tmp4), std::make_pair(&irr, &o.irr)})
+            std::swap(*pr.first, *pr.second);
+        std::swap(spec.s64, o.spec.s64);
+        std::swap(spec.s32, o.spec.s32);
+        std::swap(spec.theta, o.spec.theta);
+        std::swap(spec.valid, o.spec.valid);
+        std::swap(spec.lam_min, o.spec.lam_min);
+        std::swap(spec.lam_max, o.spec.lam_max);
+    }
     void release_work() {
         for (DevBuf* b : {&Y, &lagtmp, &spectmp, &spec_multi64, &spec_multi32, &kws, &scal, &tmp1, &tmp2, &tmp3,
                           &tmp4, &irr, &spec.s64, &spec.s32})
@@ -269,7 +285,23 @@ struct ConvSpec {
     // per-vector flags (device, nullable): vectors flagged 0 are skipped and
     // their outputs left as they were
     const int* active = nullptr;
+    // compact FP64 input only: with upd_r set, the input vector is first
+    // replaced, element by element, by upd_r + upd_beta[vector] * input (the
+    // conjugate-gradient direction update p = r + beta p, written back to
+    // the input; every element is read and written by exactly one thread)
+    const void* upd_r = nullptr;
+    const double* upd_beta = nullptr;
+    // caller-provided workspace for the transform intermediate (nullable):
+    // vectors then go through in chunks that fit it, and nothing is allocated
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
 };
+
+// Bytes of the transform intermediate per vector (element type R) of a
+// product on an N1 x N2 torus whose input and output blocks have at most
+// `rows` rows, as conv_apply lays it out.
+template <typename R>
+size_t conv_bytes_per_vec(int N1, int N2, int rows, Ctx& c, int nvec);
 
 template <typename R>
 void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st);
@@ -279,8 +311,15 @@ void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st);
 void lag_grid_device(Ctx& c, int N1, int N2, double dx1, double dx2, const Matern& th, double* d_c,
                      hipStream_t st, bool drange = false);
 // Unscaled FP64 half spectrum [k2][k1] of the torus; returns min and max.
+// With ws (spectrum_ws_bytes(N1, N2) bytes, device) the lag grid and the
+// intermediate go there instead of the problem's workspace, and with
+// lam_min == nullptr the min / max (and the wait for them) are skipped.
 void spectrum_device(Problem& P, int N1, int N2, const Matern& th, double* d_lam, double* lam_min,
-                     double* lam_max, hipStream_t st, bool drange = false);
+                     double* lam_max, hipStream_t st, bool drange = false, void* ws = nullptr);
+size_t spectrum_ws_bytes(int N1, int N2);
+// Every per-length twiddle table of the transforms, both precisions (so
+// later products allocate none).
+void build_plan_tables(Ctx& c);
 // Scale a half spectrum by s into FP64 and FP32 copies; optional sqrt of
 // max(lam, 0) first (sampling).
 void spectrum_scale(const double* lam, int64_t n, double s, bool sqrt_clip, double* out64,
@@ -326,7 +365,6 @@ void plik_device(Problem& P, const kry_matern* theta, const double* beta, const 
 void posterior_variance_device(Problem& P, const kry_matern* theta, const double* beta, const kry_opts* o,
                                double* var_x, double* var_y, double* mean_x, hipStream_t st);
 void tridiag_eigen(std::vector<double>& d, std::vector<double> e, std::vector<double>& W);
-void release_blas(Ctx& C);
 
 // ---- Krylov building blocks (krylov.hip) --------------------------------------
 int dot_blocks(int64_t n);

@@ -767,7 +767,8 @@ template void cg_run<float>(const MatvecFn<float>&, int64_t, int, const float*, 
 
 __global__ void k_ms_init(const double* __restrict__ gram, const int* __restrict__ rhs, int nd, int G, int S,
                           const int* __restrict__ pos, double* __restrict__ rr, double* __restrict__ bnorm2,
-                          double* __restrict__ alpha_old, double* __restrict__ beta_old, double* __restrict__ zeta,
+                          double* __restrict__ alpha_old, double* __restrict__ beta_old, double* __restrict__ beta,
+                          double* __restrict__ zeta,
                           double* __restrict__ zeta_old, double* __restrict__ d, double* __restrict__ Q,
                           double* __restrict__ relres, int* __restrict__ active, int* __restrict__ iters,
                           const int* __restrict__ limit) {
@@ -778,6 +779,7 @@ __global__ void k_ms_init(const double* __restrict__ gram, const int* __restrict
         bnorm2[q] = b2;
         alpha_old[q] = 1.0;
         beta_old[q] = 0.0;
+        beta[q] = 0.0;  // p_0 = r_0: a deferred direction update leaves it so
     }
     for (int s = threadIdx.x; s < S; s += blockDim.x) {
         const int a = rhs[pos[s]];
@@ -868,27 +870,74 @@ __device__ __forceinline__ void ms_alpha_step(int Gact, const double* __restrict
     }
 }
 
-// r_q -= alpha_q w_q; partials of r_q . r_q (rows 0..Gact-1) and D_j . r_q
-// (row Gact + q nd + j).  Every block forms alpha_q = r_q . r_q / p_q . w_q
-// itself, p_q . w_q summed from its partials in k_reduce's order (the value
-// the scalar kernel also forms).  nblk <= RB.
+// The scalars of an iteration, after the residual update: first the alpha
+// step (from the p . w partials; the residual kernel reads none of what it
+// writes), then base beta and roll of the position scalars; Q^s and d^s,
+// beta^s, the stopping test and the zeta roll of the listed shifts.  rc gets,
+// from the residual kernel's partials, ||r_{k+1}||^2 (rows 0..Gact-1) and
+// D_j . r_{k+1} (row Gact + q nd + j).  One block of RB threads.
+__device__ void ms_scalar_step(const MsScalarArgs& a) {
+    ms_alpha_step(a.Gact, a.partial_pw, a.nblk, a.rr, a.pw, a.alpha, a.alpha_old, a.beta_old, a.list, a.nlist, a.pos,
+                  a.sigma, a.zeta, a.zeta_old, a.zeta_new, a.alpha_s, a.active);
+    __syncthreads();
+    const int Gact = a.Gact, nd = a.nd;
+    reduce_rows_block(a.partial, a.nblk, (1 + nd) * Gact, a.rc);
+    for (int i = threadIdx.x; i < a.nlist; i += blockDim.x) {
+        const int s = a.list[i];
+        if (!a.active[s]) continue;
+        const int q = a.pos[s];
+        const double rn = a.rc[q];
+        const double b = a.rr[q] > 0.0 ? rn / a.rr[q] : 0.0;
+        const double z = a.zeta[s], zn = a.zeta_new[s];
+        const double ratio = zn / z;
+        const double bs = b * ratio * ratio;
+        const double as = a.alpha_s[s];
+        for (int j = 0; j < nd; ++j) {
+            double& dj = a.d[s * nd + j];
+            a.Q[s * nd + j] += as * dj;
+            dj = zn * a.rc[Gact + q * nd + j] + bs * dj;
+        }
+        const int it = a.iters[s] + 1;
+        a.iters[s] = it;
+        const double res = fabs(zn) * sqrt(rn);
+        const double bn = sqrt(a.bnorm2[q]);
+        a.relres[s] = res / bn;
+        if (!(res > a.rtol * bn) || it >= a.limit[s]) a.active[s] = 0;
+        a.zeta_old[s] = z;
+        a.zeta[s] = zn;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < Gact; q += blockDim.x) {
+        const double b = a.rr[q] > 0.0 ? a.rc[q] / a.rr[q] : 0.0;
+        a.beta[q] = b;
+        a.alpha_old[q] = a.alpha[q];
+        a.beta_old[q] = b;
+        a.rr[q] = a.rc[q];
+    }
+}
+
+// The residual update of k_ms_r, then the iteration's scalar step in the
+// block that finishes last (counted on the device: each block publishes its
+// partials with a device-scope release before it counts itself; the last
+// one acquires them all and resets the counter for the next launch).  No
+// block waits for another.
 template <int ND>
-__global__ void __launch_bounds__(RB) k_ms_r(double* __restrict__ r, const double* __restrict__ w,
-                                             const double* __restrict__ D, const double* __restrict__ partial_pw,
-                                             const double* __restrict__ rr, int Gact, int64_t n,
-                                             double* __restrict__ partial) {
+__global__ void __launch_bounds__(RB) k_ms_r_last(double* __restrict__ r, const double* __restrict__ w,
+                                                  const double* __restrict__ D, int64_t n, MsScalarArgs a,
+                                                  unsigned* __restrict__ counter) {
     __shared__ double sh[RB];
+    __shared__ int last;
     const int nblk = gridDim.x, q = blockIdx.y;
     double x = 0.0;
-    if ((int)threadIdx.x < nblk) x += partial_pw[q * nblk + threadIdx.x];
+    if ((int)threadIdx.x < nblk) x += a.partial_pw[q * nblk + threadIdx.x];
     const double pwq = block_sum(x, sh);
-    const double a = pwq > 0.0 ? rr[q] / pwq : 0.0;
+    const double al = pwq > 0.0 ? a.rr[q] / pwq : 0.0;
     double acc = 0.0, accb[ND];
 #pragma unroll
     for (int j = 0; j < ND; ++j) accb[j] = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)nblk * RB) {
         const int64_t k = q * n + i;
-        const double ri = r[k] - a * w[k];
+        const double ri = r[k] - al * w[k];
         r[k] = ri;
         acc += ri * ri;
 #pragma unroll
@@ -898,86 +947,46 @@ __global__ void __launch_bounds__(RB) k_ms_r(double* __restrict__ r, const doubl
 #pragma unroll
     for (int j = 0; j < ND; ++j) accb[j] = block_sum(accb[j], sh);
     if (threadIdx.x == 0) {
-        partial[q * nblk + blockIdx.x] = acc;
+        a.partial[q * nblk + blockIdx.x] = acc;
 #pragma unroll
-        for (int j = 0; j < ND; ++j) partial[(Gact + q * ND + j) * nblk + blockIdx.x] = accb[j];
+        for (int j = 0; j < ND; ++j) a.partial[(a.Gact + q * ND + j) * nblk + blockIdx.x] = accb[j];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned total = (unsigned)nblk * gridDim.y;
+        const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        last = prev + 1u == total;
     }
+    __syncthreads();
+    if (!last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    ms_scalar_step(a);
+    if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int ND>
-void launch_ms_r(int nblk, int Gact, hipStream_t st, double* r, const double* w, const double* D,
-                 const double* partial_pw, const double* rr, int64_t n, double* partial) {
-    hipLaunchKernelGGL(k_ms_r<ND>, dim3(nblk, Gact), dim3(RB), 0, st, r, w, D, partial_pw, rr, Gact, n, partial);
+void launch_ms_r_last(int nblk, int Gact, hipStream_t st, double* r, const double* w, const double* D, int64_t n,
+                      const MsScalarArgs& a, unsigned* counter) {
+    hipLaunchKernelGGL(k_ms_r_last<ND>, dim3(nblk, Gact), dim3(RB), 0, st, r, w, D, n, a, counter);
 }
 
-void ms_r(int nd, int nblk, int Gact, hipStream_t st, double* r, const double* w, const double* D,
-          const double* partial_pw, const double* rr, int64_t n, double* partial) {
+void ms_r_last(int nd, int nblk, int Gact, hipStream_t st, double* r, const double* w, const double* D, int64_t n,
+               const MsScalarArgs& a, unsigned* counter) {
     switch (nd) {
-        case 1: launch_ms_r<1>(nblk, Gact, st, r, w, D, partial_pw, rr, n, partial); break;
-        case 2: launch_ms_r<2>(nblk, Gact, st, r, w, D, partial_pw, rr, n, partial); break;
-        case 3: launch_ms_r<3>(nblk, Gact, st, r, w, D, partial_pw, rr, n, partial); break;
-        case 4: launch_ms_r<4>(nblk, Gact, st, r, w, D, partial_pw, rr, n, partial); break;
-        case 5: launch_ms_r<5>(nblk, Gact, st, r, w, D, partial_pw, rr, n, partial); break;
-        case 6: launch_ms_r<6>(nblk, Gact, st, r, w, D, partial_pw, rr, n, partial); break;
-        case 7: launch_ms_r<7>(nblk, Gact, st, r, w, D, partial_pw, rr, n, partial); break;
-        case 8: launch_ms_r<8>(nblk, Gact, st, r, w, D, partial_pw, rr, n, partial); break;
-        case 9: launch_ms_r<9>(nblk, Gact, st, r, w, D, partial_pw, rr, n, partial); break;
+        case 1: launch_ms_r_last<1>(nblk, Gact, st, r, w, D, n, a, counter); break;
+        case 2: launch_ms_r_last<2>(nblk, Gact, st, r, w, D, n, a, counter); break;
+        case 3: launch_ms_r_last<3>(nblk, Gact, st, r, w, D, n, a, counter); break;
+        case 4: launch_ms_r_last<4>(nblk, Gact, st, r, w, D, n, a, counter); break;
+        case 5: launch_ms_r_last<5>(nblk, Gact, st, r, w, D, n, a, counter); break;
+        case 6: launch_ms_r_last<6>(nblk, Gact, st, r, w, D, n, a, counter); break;
+        case 7: launch_ms_r_last<7>(nblk, Gact, st, r, w, D, n, a, counter); break;
+        case 8: launch_ms_r_last<8>(nblk, Gact, st, r, w, D, n, a, counter); break;
+        case 9: launch_ms_r_last<9>(nblk, Gact, st, r, w, D, n, a, counter); break;
         default: KRY_REQUIRE(false, "multi-shift CG takes 1..9 dot vectors");
     }
     KRY_HIP(hipGetLastError());
 }
 
-// The scalars of an iteration, after the residual update: first the alpha
-// step (from the p . w partials; k_ms_r reads none of what it writes), then
-// base beta and roll of the position scalars; Q^s and d^s, beta^s, the
-// stopping test and the zeta roll of the listed shifts.  rc gets, from the
-// partials of k_ms_r, ||r_{k+1}||^2 (rows 0..Gact-1) and D_j . r_{k+1} (row
-// Gact + q nd + j).
-__global__ void __launch_bounds__(RB)
-    k_ms_beta(int Gact, int nd, const double* __restrict__ partial_pw, const double* __restrict__ partial, int nblk,
-              double* __restrict__ rr, double* __restrict__ rc, double* __restrict__ pw, double* __restrict__ beta,
-              double* __restrict__ alpha, double* __restrict__ alpha_old, double* __restrict__ beta_old,
-              const double* __restrict__ bnorm2, const int* __restrict__ list, int nlist,
-              const int* __restrict__ pos, const double* __restrict__ sigma, double* __restrict__ zeta,
-              double* __restrict__ zeta_old, double* __restrict__ zeta_new, double* __restrict__ alpha_s,
-              double* __restrict__ d, double* __restrict__ Q, double* __restrict__ relres, int* __restrict__ active,
-              int* __restrict__ iters, const int* __restrict__ limit, double rtol) {
-    ms_alpha_step(Gact, partial_pw, nblk, rr, pw, alpha, alpha_old, beta_old, list, nlist, pos, sigma, zeta,
-                  zeta_old, zeta_new, alpha_s, active);
-    __syncthreads();
-    reduce_rows_block(partial, nblk, (1 + nd) * Gact, rc);
-    for (int i = threadIdx.x; i < nlist; i += blockDim.x) {
-        const int s = list[i];
-        if (!active[s]) continue;
-        const int q = pos[s];
-        const double rn = rc[q];
-        const double b = rr[q] > 0.0 ? rn / rr[q] : 0.0;
-        const double z = zeta[s], zn = zeta_new[s];
-        const double ratio = zn / z;
-        const double bs = b * ratio * ratio;
-        const double as = alpha_s[s];
-        for (int j = 0; j < nd; ++j) {
-            double& dj = d[s * nd + j];
-            Q[s * nd + j] += as * dj;
-            dj = zn * rc[Gact + q * nd + j] + bs * dj;
-        }
-        const int it = iters[s] + 1;
-        iters[s] = it;
-        const double res = fabs(zn) * sqrt(rn);
-        const double bn = sqrt(bnorm2[q]);
-        relres[s] = res / bn;
-        if (!(res > rtol * bn) || it >= limit[s]) active[s] = 0;
-        zeta_old[s] = z;
-        zeta[s] = zn;
-    }
-    __syncthreads();
-    for (int q = threadIdx.x; q < Gact; q += blockDim.x) {
-        const double b = rr[q] > 0.0 ? rc[q] / rr[q] : 0.0;
-        beta[q] = b;
-        alpha_old[q] = alpha[q];
-        beta_old[q] = b;
-        rr[q] = rc[q];
-    }
+__global__ void k_zero_u32(unsigned* __restrict__ c) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) __hip_atomic_store(c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // p_q = r_q + beta_q p_q
@@ -1012,9 +1021,10 @@ void swap_vectors(T* base, int64_t stride, int a, int b, int64_t n, hipStream_t 
 template void swap_vectors<double>(double*, int64_t, int, int, int64_t, hipStream_t);
 template void swap_vectors<float>(float*, int64_t, int, int, int64_t, hipStream_t);
 
-__global__ void k_ms_swap_scalars(double* rr, double* bnorm2, double* alpha_old, double* beta_old, int a, int b) {
+__global__ void k_ms_swap_scalars(double* rr, double* bnorm2, double* alpha_old, double* beta_old, double* beta,
+                                  int a, int b) {
     if (threadIdx.x != 0) return;
-    double* arr[4] = {rr, bnorm2, alpha_old, beta_old};
+    double* arr[5] = {rr, bnorm2, alpha_old, beta_old, beta};
     for (double* v : arr) {
         const double t = v[a];
         v[a] = v[b];
@@ -1022,7 +1032,8 @@ __global__ void k_ms_swap_scalars(double* rr, double* bnorm2, double* alpha_old,
     }
 }
 
-void mscg_run(const MatvecFn<double>& A, const std::function<void(int, int)>& swap, int64_t n, int G,
+void mscg_run(const MatvecFn<double>& A, const MsFusedFn* fused, const std::function<void(int, int)>& swap,
+              int64_t n, int G,
               const std::vector<int>& group_of_shift, const std::vector<double>& sigma, const double* D, int nd,
               const std::vector<int>& rhs_of_group, double rtol, int maxit, MsCgBuffers& B, std::vector<int>& iters,
               std::vector<double>& relres, std::vector<double>& Q, hipStream_t st) {
@@ -1052,25 +1063,59 @@ void mscg_run(const MatvecFn<double>& A, const std::function<void(int, int)>& sw
     for (int j = 0; j < nd; ++j)
         dot_batched<double>(D + (size_t)j * n, 0, D, n, n, nd, B.partial, B.gram + (size_t)j * nd, st);
     hipLaunchKernelGGL(k_ms_init, dim3(1), dim3(256), 0, st, B.gram, B.rhs, nd, G, S, B.pos, B.rr, B.bnorm2,
-                       B.alpha_old, B.beta_old, B.zeta, B.zeta_old, B.d, B.Q, B.relres, B.active, B.iters, B.limit);
+                       B.alpha_old, B.beta_old, B.beta, B.zeta, B.zeta_old, B.d, B.Q, B.relres, B.active, B.iters,
+                       B.limit);
     KRY_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, B.counter);
+    KRY_HIP(hipGetLastError());
+    MsScalarArgs sa;
+    sa.nd = nd;
+    sa.nblk = nblk;
+    sa.partial_pw = B.partial_pw;
+    sa.partial = B.partial;
+    sa.rr = B.rr;
+    sa.rc = B.rc;
+    sa.pw = B.pw;
+    sa.beta = B.beta;
+    sa.alpha = B.alpha;
+    sa.alpha_old = B.alpha_old;
+    sa.beta_old = B.beta_old;
+    sa.bnorm2 = B.bnorm2;
+    sa.list = B.list;
+    sa.pos = B.pos;
+    sa.sigma = B.sigma;
+    sa.zeta = B.zeta;
+    sa.zeta_old = B.zeta_old;
+    sa.zeta_new = B.zeta_new;
+    sa.alpha_s = B.alpha_s;
+    sa.d = B.d;
+    sa.Q = B.Q;
+    sa.relres = B.relres;
+    sa.active = B.active;
+    sa.iters = B.iters;
+    sa.limit = B.limit;
+    sa.rtol = rtol;
     int Gact = G, nlist = S;
     int64_t ublocks = (n + 255) / 256;
     if (ublocks > 1024) ublocks = 1024;
     const int check = 16;
+    // An iteration: the product (with the previous iteration's direction
+    // update folded in when `fused` is given), the p . w partials, and the
+    // residual update, whose last block takes the scalar step; without
+    // `fused`, the direction update is a pass of its own at the end.
     for (int it = 0; it < maxit && Gact > 0; ++it) {
-        A(B.p, B.w, Gact, st, nullptr);
+        if (fused) (*fused)(B.r, B.p, B.beta, B.w, Gact, st);
+        else A(B.p, B.w, Gact, st, nullptr);
         hipLaunchKernelGGL(k_dot_partial<double>, dim3(nblk, Gact), dim3(RB), 0, st, B.p, n, B.w, n, n,
                            B.partial_pw);
         KRY_HIP(hipGetLastError());
-        ms_r(nd, nblk, Gact, st, B.r, B.w, D, B.partial_pw, B.rr, n, B.partial);
-        hipLaunchKernelGGL(k_ms_beta, dim3(1), dim3(RB), 0, st, Gact, nd, B.partial_pw, B.partial, nblk, B.rr, B.rc,
-                           B.pw, B.beta, B.alpha, B.alpha_old, B.beta_old, B.bnorm2, B.list, nlist, B.pos, B.sigma,
-                           B.zeta, B.zeta_old, B.zeta_new, B.alpha_s, B.d, B.Q, B.relres, B.active, B.iters, B.limit,
-                           rtol);
-        KRY_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_ms_p, dim3((unsigned)ublocks, Gact), dim3(256), 0, st, B.p, B.r, B.beta, n);
-        KRY_HIP(hipGetLastError());
+        sa.Gact = Gact;
+        sa.nlist = nlist;
+        ms_r_last(nd, nblk, Gact, st, B.r, B.w, D, n, sa, B.counter);
+        if (!fused) {
+            hipLaunchKernelGGL(k_ms_p, dim3((unsigned)ublocks, Gact), dim3(256), 0, st, B.p, B.r, B.beta, n);
+            KRY_HIP(hipGetLastError());
+        }
         if ((it + 1) % check != 0 && it + 1 != maxit) continue;
         KRY_HIP(hipMemcpyAsync(act.data(), B.active, S * sizeof(int), hipMemcpyDeviceToHost, st));
         KRY_HIP(hipStreamSynchronize(st));
@@ -1094,7 +1139,7 @@ void mscg_run(const MatvecFn<double>& A, const std::function<void(int, int)>& sw
                 swap_vectors<double>(B.r, n, q, last, n, st);
                 swap_vectors<double>(B.p, n, q, last, n, st);
                 hipLaunchKernelGGL(k_ms_swap_scalars, dim3(1), dim3(64), 0, st, B.rr, B.bnorm2, B.alpha_old,
-                                   B.beta_old, q, last);
+                                   B.beta_old, B.beta, q, last);
                 KRY_HIP(hipGetLastError());
                 swap(q, last);
                 std::swap(grp_at[q], grp_at[last]);

@@ -57,13 +57,36 @@ struct MsCgBuffers {
     double* gram;           // nd x nd
     int* rhs;               // G
     double* partial;        // (1 + nd) G x nblk (at least nd x nd x nblk)
-    double* partial_pw;     // G x nblk: p . w partials, read while k_ms_r writes `partial`
+    double* partial_pw;     // G x nblk: p . w partials, read while the residual kernel writes `partial`
+    unsigned* counter;      // blocks of the residual kernel that have finished (reset by the last)
 };
+// Arguments of an iteration's scalar step (see ms_scalar_step).
+struct MsScalarArgs {
+    int Gact, nd, nblk, nlist;
+    const double* partial_pw;
+    double* partial;
+    double *rr, *rc, *pw, *beta, *alpha, *alpha_old, *beta_old;
+    const double* bnorm2;
+    const int *list, *pos;
+    const double* sigma;
+    double *zeta, *zeta_old, *zeta_new, *alpha_s, *d, *Q, *relres;
+    int *active, *iters;
+    const int* limit;
+    double rtol;
+};
+// The base product with the direction update folded into it: applies the
+// operators of positions 0..k-1 to p after replacing p by r + beta p (per
+// position), as the update would have done.
+using MsFusedFn = std::function<void(const double* r, double* p, const double* beta, double* w, int k,
+                                     hipStream_t st)>;
 // A(x, y, k, st) applies the base operators of positions 0..k-1;
 // swap(a, b) exchanges whatever the caller keeps per position (spectra).
 // D: nd (<= KRY_MS_MAX_ND) vectors of n, contiguous; rhs_of_group: index of
 // each group's right-hand side in D.
-void mscg_run(const MatvecFn<double>& A, const std::function<void(int, int)>& swap, int64_t n, int G,
+// With `fused` (nullable) the products go through it and the direction
+// update has no pass of its own.
+void mscg_run(const MatvecFn<double>& A, const MsFusedFn* fused, const std::function<void(int, int)>& swap,
+              int64_t n, int G,
               const std::vector<int>& group_of_shift, const std::vector<double>& sigma, const double* D, int nd,
               const std::vector<int>& rhs_of_group, double rtol, int maxit, MsCgBuffers& B, std::vector<int>& iters,
               std::vector<double>& relres, std::vector<double>& Q, hipStream_t st);

@@ -1,7 +1,7 @@
 // The paper's own objective and its companions on the device:
 //  - the quadrant block-circulant log-determinant of Sec. 3.3 and its range
 //    derivative (eq. circ_diag, eq. trace_approx), as two dense DFT
-//    contractions per lag grid (rocBLAS FP64 GEMMs against twiddle tables);
+//    contractions per lag grid (FP64 tiled products against twiddle tables);
 //  - pl~ of eq. prof_lik with the genGK terms of Sec. 3.2 and the
 //    approximate gradient of eq. approx_grad;
 //  - the low-rank posterior variance of eq. bgamma_approx;
@@ -12,8 +12,6 @@
 // with cos / sin tables: T = c F2 over the column lags (both grids at once),
 // then lam = G1 T_cos + H1 T_sin over the row lags (G1 = cos, H1 = -sin);
 // the lag grid is even, so the DFT is real and this is its real part.
-#include <rocblas/rocblas.h>
-
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -27,17 +25,87 @@ namespace {
 
 constexpr int PB = 256;
 
-rocblas_handle blas_of(Ctx& C) {
-    if (!C.blas) {
-        rocblas_handle h;
-        KRY_REQUIRE(rocblas_create_handle(&h) == rocblas_status_success, "rocblas_create_handle failed");
-        C.blas = h;
+// ---- dense products (row-major): C = A B, or C += A B -------------------------------------
+// A is m x k (row stride lda), B is k x n (ldb), C is m x n (ldc).  A
+// workgroup of 256 threads computes a 64 x 64 tile of C, each thread a 4 x 4
+// block, over k in steps of 16 staged through LDS (A transposed there, so a
+// thread's four rows are adjacent); fused multiply-adds in a fixed order, so
+// results do not depend on the launch.  Edges are zero-filled.
+constexpr int GT = 64, GK = 16;
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_gemm_rm(int m, int n, int k, const R* __restrict__ A, int64_t lda,
+                                                  const R* __restrict__ B, int64_t ldb, R* __restrict__ C,
+                                                  int64_t ldc, int accumulate) {
+    __shared__ R As[GK][GT + 4];
+    __shared__ R Bs[GK][GT + 4];
+    const int tid = threadIdx.x;
+    const int tx = tid % 16, ty = tid / 16;
+    const int64_t row0 = (int64_t)blockIdx.y * GT, col0 = (int64_t)blockIdx.x * GT;
+    R acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = (R)0;
+    // loader positions: A tile 64 rows x 16 k (4 consecutive k per thread),
+    // B tile 16 k x 64 columns (4 consecutive columns per thread)
+    const int ar = tid / 4, ak = (tid % 4) * 4;
+    const int bk = tid / 16, bc = (tid % 16) * 4;
+    for (int k0 = 0; k0 < k; k0 += GK) {
+        R av[4], bv[4];
+        const int64_t gr = row0 + ar;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int kk = k0 + ak + q;
+            av[q] = (gr < m && kk < k) ? A[gr * lda + kk] : (R)0;
+        }
+        const int kb = k0 + bk;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t gc = col0 + bc + q;
+            bv[q] = (kb < k && gc < n) ? B[(int64_t)kb * ldb + gc] : (R)0;
+        }
+        __syncthreads();  // the previous step's reads are done
+#pragma unroll
+        for (int q = 0; q < 4; ++q) As[ak + q][ar] = av[q];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Bs[bk][bc + q] = bv[q];
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GK; ++kk) {
+            R a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma_rn(a[i], b[j], acc[i][j]);
+        }
     }
-    return static_cast<rocblas_handle>(C.blas);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t r = row0 + ty * 4 + i;
+        if (r >= m) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t c = col0 + tx * 4 + j;
+            if (c >= n) continue;
+            R& o = C[r * ldc + c];
+            o = accumulate ? o + acc[i][j] : acc[i][j];
+        }
+    }
 }
 
-void blas_check(rocblas_status s, const char* what) {
-    if (s != rocblas_status_success) throw Error(KRY_EDEVICE, std::string(what) + ": rocBLAS status " + std::to_string((int)s));
+template <typename R>
+void gemm_rm(int m, int n, int k, const R* A, int64_t lda, const R* B, int64_t ldb, R* C, int64_t ldc,
+             bool accumulate, hipStream_t st) {
+    if (m <= 0 || n <= 0) return;
+    const dim3 grid((unsigned)((n + GT - 1) / GT), (unsigned)((m + GT - 1) / GT));
+    KRY_REQUIRE(grid.y <= 65535u, "product too tall for one launch");
+    hipLaunchKernelGGL(k_gemm_rm<R>, grid, dim3(256), 0, st, m, n, k, A, lda, B, ldb, C, ldc, accumulate ? 1 : 0);
+    KRY_HIP(hipGetLastError());
 }
 
 // out[l * 2 nf + j]: cos(2 pi l j / M) for j < nf, sin(2 pi l (j - nf) / M)
@@ -201,26 +269,14 @@ Quadrant quadrant_device(Problem& P, const Matern& th, bool deriv, hipStream_t s
     KRY_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_twiddle_freq_major, grid_for((int64_t)n1 * M1), dim3(256), 0, st, G1, H1, n1, M1);
     KRY_HIP(hipGetLastError());
-    {
-        std::lock_guard<std::mutex> g(C.blas_mu);
-        rocblas_handle h = blas_of(C);
-        blas_check(rocblas_set_stream(h, st), "rocblas_set_stream");
-        const double one = 1.0, zero = 0.0;
-        // T (row-major ng M1 x 2 n2) = c (ng M1 x M2) F2 (M2 x 2 n2); column-major: T^T = F2^T c^T
-        blas_check(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, 2 * n2, ng * M1, M2, &one, F2,
-                                 2 * n2, c, M2, &zero, T, 2 * n2),
-                   "rocblas_dgemm (column lags)");
-        for (int gi = 0; gi < ng; ++gi) {
-            const double* Tg = T + (size_t)gi * M1 * 2 * n2;
-            double* lg = lam + (size_t)gi * nq;
-            // lam (row-major n1 x n2) = G1 T_cos + H1 T_sin; column-major: lam^T = T_cos^T G1^T + T_sin^T H1^T
-            blas_check(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, n2, n1, M1, &one, Tg, 2 * n2,
-                                     G1, M1, &zero, lg, n2),
-                       "rocblas_dgemm (row lags, cos)");
-            blas_check(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, n2, n1, M1, &one, Tg + n2,
-                                     2 * n2, H1, M1, &one, lg, n2),
-                       "rocblas_dgemm (row lags, sin)");
-        }
+    // T (ng M1 x 2 n2) = c (ng M1 x M2) F2 (M2 x 2 n2): the column lags, both grids
+    gemm_rm<double>(ng * M1, 2 * n2, M2, c, M2, F2, 2 * n2, T, 2 * n2, false, st);
+    for (int gi = 0; gi < ng; ++gi) {
+        const double* Tg = T + (size_t)gi * M1 * 2 * n2;
+        double* lg = lam + (size_t)gi * nq;
+        // lam (n1 x n2) = G1 (n1 x M1) T_cos (M1 x n2) + H1 T_sin: the row lags
+        gemm_rm<double>(n1, n2, M1, G1, M1, Tg, 2 * n2, lg, n2, false, st);
+        gemm_rm<double>(n1, n2, M1, H1, M1, Tg + n2, 2 * n2, lg, n2, true, st);
     }
     hipLaunchKernelGGL(k_quadrant_partial, dim3(nb), dim3(PB), 0, st, lam, deriv ? lam + nq : nullptr, nq, part);
     KRY_HIP(hipGetLastError());
@@ -345,26 +401,19 @@ void postvar_device(Problem& P, const GkRun& G, double sigma2, double* d_var, hi
         KRY_HIP(hipMemcpyAsync(Wd, Wf.data(), Wf.size() * sizeof(float), hipMemcpyHostToDevice, st));
     }
     KRY_HIP(hipMemcpyAsync(dd, delta.data(), k * sizeof(double), hipMemcpyHostToDevice, st));
-    std::lock_guard<std::mutex> g(C.blas_mu);
-    rocblas_handle h = blas_of(C);
-    blas_check(rocblas_set_stream(h, st), "rocblas_set_stream");
     for (int64_t i0 = 0; i0 < n; i0 += chunk) {
         const int c = (int)std::min<int64_t>(chunk, n - i0);
-        // Z (c x k, column-major) = Sv[i0 .. i0 + c, 0 .. k] (column-major, ld n) W (k x k)
+        // Z[j][i] = sum_l W[l][j] (Sigma v_l)[i0 + i]: with the basis stored
+        // vector by vector (k rows of n), Z (k x c, row-major) = W^T Sv; W is
+        // held column by column, so row j of W^T is W's column j, contiguous
         if (rb == 8) {
-            const double one = 1.0, zero = 0.0;
-            blas_check(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, c, k, k, &one,
-                                     static_cast<const double*>(G.Sv) + i0, (int)n, static_cast<const double*>(Wd), k,
-                                     &zero, static_cast<double*>(Z), c),
-                       "rocblas_dgemm (posterior variance)");
+            gemm_rm<double>(k, c, k, static_cast<const double*>(Wd), k, static_cast<const double*>(G.Sv) + i0, n,
+                            static_cast<double*>(Z), c, false, st);
             hipLaunchKernelGGL(k_postvar<double>, grid_for(c), dim3(256), 0, st, static_cast<const double*>(Z),
                                (int64_t)c, (int64_t)c, k, dd, sigma2, d_var + i0);
         } else {
-            const float one = 1.0f, zero = 0.0f;
-            blas_check(rocblas_sgemm(h, rocblas_operation_none, rocblas_operation_none, c, k, k, &one,
-                                     static_cast<const float*>(G.Sv) + i0, (int)n, static_cast<const float*>(Wd), k,
-                                     &zero, static_cast<float*>(Z), c),
-                       "rocblas_sgemm (posterior variance)");
+            gemm_rm<float>(k, c, k, static_cast<const float*>(Wd), k, static_cast<const float*>(G.Sv) + i0, n,
+                           static_cast<float*>(Z), c, false, st);
             hipLaunchKernelGGL(k_postvar<float>, grid_for(c), dim3(256), 0, st, static_cast<const float*>(Z),
                                (int64_t)c, (int64_t)c, k, dd, sigma2, d_var + i0);
         }
@@ -524,11 +573,5 @@ void posterior_variance_device(Problem& P, const kry_matern* theta, const double
     }
 }
 
-void release_blas(Ctx& C) {
-    if (C.blas) {
-        (void)rocblas_destroy_handle(static_cast<rocblas_handle>(C.blas));
-        C.blas = nullptr;
-    }
-}
 
 }  // namespace kry

@@ -14,6 +14,8 @@
 // request batched with others on its own problem gets bit-identical results;
 // batched with other problems, its Krylov vectors are padded to the largest
 // observed count, which changes the reduction blocks and so the rounding.
+#include <algorithm>
+#include <array>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -41,6 +43,20 @@ struct SlotWork {
     DevBuf Y, lagtmp, spectmp, spec_multi64, spec_multi32, kws, scal, tmp1, tmp2, tmp3, tmp4, irr;
     Spectrum spec;
     const Problem* last = nullptr;
+    std::array<DevBuf*, 14> bufs() {
+        return {&Y, &lagtmp, &spectmp, &spec_multi64, &spec_multi32, &kws, &scal, &tmp1,
+                &tmp2, &tmp3, &tmp4, &irr, &spec.s64, &spec.s32};
+    }
+    // device bytes the slot keeps between requests (its buffers only grow)
+    uint64_t bytes() {
+        uint64_t b = 0;
+        for (DevBuf* d : bufs()) b += d->bytes;
+        return b;
+    }
+    void release(Ctx& c) {
+        for (DevBuf* d : bufs()) d->release(c);
+        spec.valid = false;
+    }
 };
 
 void swap_work(Problem& v, SlotWork& w) {
@@ -64,25 +80,48 @@ void swap_work(Problem& v, SlotWork& w) {
     std::swap(v.spec.lam_max, w.spec.lam_max);
 }
 
-// Rough device footprint of a request (bytes): Krylov vectors, transform
-// intermediate, spectra and solver vectors.
-uint64_t footprint(const Problem& P, const kry_request& r, int count) {
+// Device bytes a request's workspace can reach (an upper bound that follows
+// the drivers' allocations: spectrum and lag grid, Krylov basis, transform
+// intermediates, solver vectors).  A batch of merged requests is bounded by
+// the sum of its requests' bounds.
+uint64_t footprint(const Problem& P, const kry_request& r) {
     const uint64_t p = P.p, n = (uint64_t)P.n1 * P.n2;
     const uint64_t M = P.N2 / 2, nspec = (M + 1) * P.N1;
-    const uint64_t el = r.opts.precision == KRY_FP32 ? 4 : 8;
-    const uint64_t inter = (M + 1) * (uint64_t)P.n1 * 2 * el;
+    const bool fp32 = r.opts.precision == KRY_FP32;
+    const uint64_t el = fp32 ? 4 : 8;
+    // transform intermediate per vector: complex values on (M + 1) x (rows
+    // rounded up to a row tile of at most 64 rows)
+    const uint64_t inter = (M + 1) * ((uint64_t)P.n1 + 64) * 2;  // times bytes per real
+    const uint64_t lagspec = (uint64_t)P.N1 * P.N2 * 8 + (M + 1) * (uint64_t)P.N1 * 16 + 16384;
+    const uint64_t nd = 1 + (uint64_t)P.q;  // right-hand sides per point
+    const uint64_t grid = P.irregular ? 2 * n * 8 : 0;  // grid vectors of the irregular product (per vector)
+    // a solve of k right-hand sides: CG vectors (FP64 or FP32 with FP64
+    // refinement), partials, products in both precisions
+    auto solve = [&](uint64_t k) {
+        return k * p * (fp32 ? 36 : 24) + k * 4096 + 4096;
+    };
+    auto prod = [&](uint64_t k, uint64_t e) { return k * (inter * e + grid); };
     if (r.kind == KRY_REQ_LOGLIK) {
         const uint64_t np = nprobes_of(&r.opts);
-        const uint64_t slots = r.opts.reorth ? lanczos_cap(&r.opts) + 3 : 5;
-        const uint64_t vecs = count * np;
-        const uint64_t nd = 1 + (uint64_t)P.q;  // right-hand sides per point
-        return vecs * p * el * slots + std::min<uint64_t>(vecs, 64) * inter + count * nd * nspec * 12 +
-               count * nd * p * 8 * 6 + P.N1 * (uint64_t)P.N2 * 8;
+        const uint64_t m = lanczos_cap(&r.opts);
+        const uint64_t slots = r.opts.reorth ? m + 1 : 3;
+        const uint64_t nblk = 256;
+        const uint64_t kws = np * p * el * (slots + 2) + np * (m + 1) * nblk * 8 + np * (3 * m + 8) * 8 + 65536;
+        const uint64_t spec = nd * nspec * 12;
+        const uint64_t rhs = nd * p * 16 + 4096 + nd * 257 * 8;
+        const uint64_t gk = r.opts.solver == KRY_SOLVER_GENGK
+                                ? (uint64_t)(r.opts.gk_steps + 2) * 2 * n * el + 4 * n * 8 + p * 8 * 4
+                                : 0;
+        const uint64_t Y = std::max({prod(np, el), prod(nd, 8), prod(nd, el), prod(1, 8)});
+        return lagspec + spec + rhs + kws + solve(nd) + Y + gk + nspec * 12;
     }
-    return inter + nspec * 12 + p * 8 * 8 * (1 + (uint64_t)P.q) + n * 8 * 2 + P.N1 * (uint64_t)P.N2 * 8 +
-           (r.variances ? std::min<uint64_t>(r.ntargets, 256) * p * 8 * 8 : 0);
+    const uint64_t nt = std::max<int64_t>(r.ntargets, 1);
+    const uint64_t c = r.variances ? std::min<uint64_t>(nt, 256) : 1;
+    const uint64_t io = 8192 + nt * 32 + p * 16 + n * 8;
+    const uint64_t var = r.variances ? c * p * 16 + c * 257 * 8 + 1024 : 0;
+    const uint64_t Y = std::max(prod(c * nd, 8), prod(1, 8));
+    return lagspec + nspec * 12 + io + var + solve(c * nd) + Y + nd * p * 8 * 4;
 }
-
 }  // namespace
 
 struct kry_server {
@@ -95,7 +134,10 @@ struct kry_server {
     std::unordered_map<uint64_t, kry_response> done;
     std::unordered_map<uint64_t, bool> known;
     uint64_t next_ticket = 1;
-    uint64_t inflight = 0;
+    // Device memory of the slots: a running slot may use up to the larger of
+    // its retained workspace and its batch's estimated footprint; an idle one
+    // holds its retained workspace, which can be released to admit a request.
+    std::vector<uint64_t> retained, running;
     bool stop = false;
     std::vector<std::thread> workers;
     std::vector<hipStream_t> streams;
@@ -126,6 +168,42 @@ struct kry_server {
                !h.prob->P.irregular;
     }
 
+    // Memory held by the running slots (requires mu).
+    uint64_t busy_bytes() const {
+        uint64_t b = 0;
+        for (size_t s = 0; s < running.size(); ++s)
+            if (running[s]) b += std::max(retained[s], running[s]);
+        return b;
+    }
+    bool any_running() const {
+        for (uint64_t r : running)
+            if (r) return true;
+        return false;
+    }
+    // Memory held by every slot other than `slot` (requires mu).
+    uint64_t other_bytes(int slot) const {
+        uint64_t b = 0;
+        for (size_t s = 0; s < running.size(); ++s)
+            if ((int)s != slot) b += running[s] ? std::max(retained[s], running[s]) : retained[s];
+        return b;
+    }
+    // Make room for a batch of footprint fp on `slot` by releasing idle
+    // slots' workspaces, its own first (requires mu; the idle slots' threads
+    // are waiting for work, so their buffers are not in use).
+    void make_room(int slot, uint64_t fp) {
+        auto need = [&] { return other_bytes(slot) + std::max(retained[slot], fp); };
+        if (need() <= budget) return;
+        if (retained[slot]) {
+            work[slot].release(*ctx);
+            retained[slot] = 0;
+        }
+        for (size_t s = 0; s < running.size() && need() > budget; ++s) {
+            if ((int)s == slot || running[s] || !retained[s]) continue;
+            work[s].release(*ctx);
+            retained[s] = 0;
+        }
+    }
+
     void run_slot(int slot) {
         (void)hipSetDevice(ctx->device);
         hipStream_t st = streams[slot];
@@ -135,8 +213,11 @@ struct kry_server {
             uint64_t fp = 0;
             {
                 std::unique_lock<std::mutex> lk(mu);
+                // a request is admitted when it fits beside the running
+                // slots (idle slots' workspaces can be released), or when
+                // nothing runs (it alone is within the budget, checked at submit)
                 cv_work.wait(lk, [&] {
-                    return stop || (!queue.empty() && (inflight + queue.front().footprint <= budget || inflight == 0));
+                    return stop || (!queue.empty() && (busy_bytes() + queue.front().footprint <= budget || !any_running()));
                 });
                 if (queue.empty()) {
                     if (stop) return;
@@ -149,7 +230,7 @@ struct kry_server {
                 if (h.kind == KRY_REQ_LOGLIK) {
                     for (auto it = queue.begin(); it != queue.end() && (int)batch.size() < max_batch;) {
                         const kry_request& r = it->req;
-                        if (mergeable(h, r) && inflight + fp + it->footprint <= budget) {
+                        if (mergeable(h, r) && busy_bytes() + fp + it->footprint <= budget) {
                             fp += it->footprint;
                             batch.push_back(std::move(*it));
                             it = queue.erase(it);
@@ -158,7 +239,8 @@ struct kry_server {
                         }
                     }
                 }
-                inflight += fp;
+                make_room(slot, fp);
+                running[slot] = fp;
             }
             const double t_start = now();
             std::vector<kry_response> resp(batch.size());
@@ -166,8 +248,11 @@ struct kry_server {
             const double t_end = now();
             {
                 std::lock_guard<std::mutex> lk(mu);
-                inflight -= fp;
+                running[slot] = 0;
+                retained[slot] = w.bytes();
                 for (size_t i = 0; i < batch.size(); ++i) {
+                    resp[i].footprint_bytes = fp;
+                    resp[i].workspace_bytes = retained[slot];
                     resp[i].t_submit = batch[i].t_submit;
                     resp[i].t_start = t_start;
                     resp[i].t_end = t_end;
@@ -257,6 +342,8 @@ kry_status kry_server_create(kry_ctx* kctx, int32_t slots, uint64_t hbm_budget_b
         }
         s->streams.resize(slots, nullptr);
         s->work.resize(slots);
+        s->retained.assign(slots, 0);
+        s->running.assign(slots, 0);
         for (int i = 0; i < slots; ++i) {
             if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess) {
                 for (int j = 0; j < i; ++j) (void)hipStreamDestroy(s->streams[j]);
@@ -288,7 +375,7 @@ kry_status kry_server_submit(kry_server* s, const kry_request* req, uint64_t* ti
             for (int64_t t : pd.targets)
                 if (t < 0 || t >= n) return KRY_EINVAL;
         }
-        pd.footprint = footprint(P, *req, 1);
+        pd.footprint = footprint(P, *req);
         if (pd.footprint > s->budget) return KRY_ENOMEM;
         {
             std::lock_guard<std::mutex> lk(s->mu);
@@ -344,10 +431,7 @@ void kry_server_destroy(kry_server* s) {
     s->cv_work.notify_all();
     for (auto& t : s->workers) t.join();
     (void)hipSetDevice(s->ctx->device);
-    for (auto& w : s->work)
-        for (DevBuf* b : {&w.Y, &w.lagtmp, &w.spectmp, &w.spec_multi64, &w.spec_multi32, &w.kws, &w.scal, &w.tmp1,
-                          &w.tmp2, &w.tmp3, &w.tmp4, &w.irr, &w.spec.s64, &w.spec.s32})
-            b->release(*s->ctx);
+    for (auto& w : s->work) w.release(*s->ctx);
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
     delete s;
 }

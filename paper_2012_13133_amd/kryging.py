@@ -92,7 +92,8 @@ class kry_request(C.Structure):
 
 class kry_response(C.Structure):
     _fields_ = [("status", C.c_int32), ("batch", C.c_int32), ("problems", C.c_int32), ("loglik", kry_loglik_result),
-                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_end", C.c_double)]
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_end", C.c_double),
+                ("footprint_bytes", C.c_uint64), ("workspace_bytes", C.c_uint64)]
 
 
 KRY_REQ_LOGLIK, KRY_REQ_KRIGE = 0, 1
@@ -106,6 +107,7 @@ _SIGS = {
     "kry_opts_default": (C.c_int, [C.POINTER(kry_opts)]),
     "kry_ctx_create": (C.c_int, [C.c_int32, C.c_uint64, C.POINTER(_P)]),
     "kry_ctx_destroy": (None, [_P]),
+    "kry_ctx_memory": (C.c_int, [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.c_int32]),
     "kry_profile_begin": (C.c_int, [_P]),
     "kry_profile_end": (C.c_int, [_P, _DP, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "kry_problem_create": (C.c_int, [_P, C.POINTER(kry_grid), C.POINTER(C.c_uint8), _DP, C.POINTER(_P)]),
@@ -215,6 +217,13 @@ def kry_ctx_create(device=0, hbm_budget_bytes=0):
 
 def kry_ctx_destroy(ctx):
     lib.kry_ctx_destroy(ctx)
+
+
+def kry_ctx_memory(ctx, reset_peak=False):
+    """(bytes held now, most bytes held since creation or the last reset)"""
+    a, pk = C.c_uint64(), C.c_uint64()
+    _check(lib.kry_ctx_memory(ctx, C.byref(a), C.byref(pk), 1 if reset_peak else 0))
+    return a.value, pk.value
 
 
 def kry_profile_begin(ctx):

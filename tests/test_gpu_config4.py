@@ -1,0 +1,61 @@
+"""GPU: the large anisotropic workload end to end at 512 x 512 (the recipe of
+the 2048 x 2048 bench row: 40 % blob-shaped missingness, Matern nu = 1,
+anisotropy ratio 2 at 30 degrees, nugget ratio 0.1): the profile-likelihood
+fit with FP32 transforms reaches the plain FP64 fit (same probes), and the
+bootstrap prediction variances at every missing cell agree with the exact
+ones within their Monte-Carlo error (Sec. 3.4, 3.5)."""
+import numpy as np
+import pytest
+
+from paper_2012_13133_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+K = pytest.importorskip("paper_2012_13133_amd.kryging")
+
+
+def test_config4_recipe_fit_and_all_cell_kriging():
+    n = 512
+    ang = np.pi / 6
+    truth = K.theta(sigma2=1.0, tau2=0.1, range=0.05, nu=1.0, aniso_ratio=2.0, aniso_angle=ang)
+    mask = synth.blob_mask(n, n, 0.4, seed=41, rmin=3, rmax=20)
+    assert abs((1 - mask.mean()) - 0.4) < 0.005
+    with K.Problem(n, n, mask) as P:
+        Nt = K.kry_psd_torus(P.h, truth)
+        x, _ = K.kry_sample(P.h, truth, Nt[0], Nt[1], 42, 0, 1, n, n)
+        rng = np.random.default_rng(43)
+        K.kry_problem_set_data(P.h, x[0] + np.sqrt(truth.tau2) * rng.standard_normal((n, n)))
+        init = K.theta(sigma2=1.0, tau2=0.2, range=0.08, nu=1.0, aniso_ratio=2.0, aniso_angle=ang)
+        fits = {}
+        for prec in (K.KRY_FP32, K.KRY_FP64):
+            opts = K.kry_opts_default(lanczos_steps=50, num_probes=20, precision=prec, reorth=1, cg_rtol=1e-8,
+                                      seed=303)
+            print("fit, precision", prec, flush=True)
+            est, at = K.kry_fit(P.h, init, 3, opts, xtol=1e-3, maxiter=200)
+            fits[prec] = (np.log(est.range), np.log(est.tau2 / est.sigma2), at, est)
+        lr32, le32, a32, est = fits[K.KRY_FP32]
+        lr64, le64, a64, _ = fits[K.KRY_FP64]
+        assert abs(lr32 - lr64) < 5e-3 and abs(le32 - le64) < 5e-3, (lr32, lr64, le32, le64)
+        assert abs(a32["loglik_profiled"] - a64["loglik_profiled"]) <= 1e-3 * abs(a64["loglik_profiled"])
+        # the fit is a maximum of the likelihood it evaluates: at least as high
+        # as at the true parameters, with the same probes
+        tru = K.kry_loglik(P.h, truth, K.kry_opts_default(lanczos_steps=50, num_probes=20, precision=K.KRY_FP64,
+                                                            reorth=1, cg_rtol=1e-8, seed=303))
+        assert a64["loglik_profiled"] >= tru["loglik_profiled"] - 1e-6 * abs(tru["loglik_profiled"])
+        # every missing cell: means and bootstrap variances (B = 20)
+        miss = np.flatnonzero(mask.ravel() == 0)
+        kopts = K.kry_opts_default(precision=K.KRY_FP32, cg_rtol=1e-8, seed=404)
+        B = 20
+        print("kriging at every missing cell", miss.size, flush=True)
+        mean, vx, vy = K.kry_krige(P.h, est, kopts, None, ntargets=miss.size, want_var=True, bootstrap_B=B)
+        assert np.all(np.isfinite(mean)) and np.all(vx > 0) and np.all(vy > 0)
+        # var y - var x is the simulated observation noise: tau^2 on average
+        assert abs(np.mean(vy - vx) / est.tau2 - 1) < 0.05
+        sub = np.sort(np.random.default_rng(45).choice(miss.size, size=128, replace=False))
+        m2, ex, ey = K.kry_krige(P.h, est, kopts, miss[sub], want_var=True)
+        np.testing.assert_allclose(m2, mean[sub], rtol=0, atol=1e-12)
+        np.testing.assert_allclose(ey - ex, est.tau2, rtol=1e-12)
+        # bootstrap / exact: mean 1, standard error sqrt(2 / B) / sqrt(cells)
+        ratio = vx[sub] / ex
+        se = np.sqrt(2.0 / B) / np.sqrt(sub.size)
+        assert abs(ratio.mean() - 1.0) < 3 * se, (ratio.mean(), se)

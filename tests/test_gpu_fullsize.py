@@ -98,14 +98,15 @@ def test_masked_product_largest_embedding():
             assert np.abs(got[j][rows] - ref[:, j]).max() <= tol * scale, tol
 
 
-def test_range_nugget_grid_fp32_shared_matches_plain_fp64():
-    # 512^2 with 30 % missing (the plain-vs-precision workload): the FP32
-    # shift-shared batch over a 3 x 3 (range, nugget) grid against the plain
-    # FP64 form point by point, same probes
+@pytest.mark.parametrize("nu", [0.5, 1.5, 2.5])
+def test_range_nugget_grid_fp32_shared_matches_plain_fp64(nu):
+    # 512^2 with 30 % missing (the plain-vs-precision workload, every
+    # smoothness it names): the FP32 shift-shared batch over a 3 x 3 (range,
+    # nugget) grid against the plain FP64 form point by point, same probes
     n = 512
     mask = synth.uniform_mask(n, n, 0.3, seed=104)
     ranges, nuggets = (0.01, 0.05, 0.2), (0.01, 0.1, 1.0)
-    thetas = [K.theta(sigma2=1.0, tau2=e, range=r, nu=1.5) for r in ranges for e in nuggets]
+    thetas = [K.theta(sigma2=1.0, tau2=e, range=r, nu=nu) for r in ranges for e in nuggets]
     base = dict(lanczos_steps=50, num_probes=10, reorth=1, cg_rtol=1e-8, cg_maxit=100000)
     with K.Problem(n, n, mask) as P:
         th0 = K.theta(sigma2=1.0, tau2=0.2, range=0.05, nu=1.5)

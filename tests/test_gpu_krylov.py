@@ -148,6 +148,24 @@ def test_cg_solve_fp64_and_mixed():
             assert rows_rel(x, ref) <= 1e-8
 
 
+def test_mixed_refinement_reports_the_residual_of_the_returned_solution():
+    # a tolerance below the FP64 rounding floor keeps the refinement running
+    # to its cap of corrections: the residual reported must still be the one
+    # of the X returned, b - K x with the library's own FP64 product
+    n1, n2 = 24, 24
+    th = theta(0.1, 1.5, tau2=0.05)
+    g, mask, y, yo = _problem(n1, n2, th, 0.3, cholesky=False)
+    with K.Problem(n1, n2, mask, y) as P:
+        B = synth.random_vectors(P.p, 3, seed=9)
+        t = K.theta_from_dict(th)
+        x, it, rr = K.kry_solve(P.h, t, K.kry_opts_default(precision=1, cg_rtol=1e-300), B, allow_noconv=True)
+        kx = K.kry_matvec(P.h, t, x, K.KRY_FP64)
+        for i in range(3):
+            true = np.linalg.norm(B[i] - kx[i]) / np.linalg.norm(B[i])
+            assert rr[i] == pytest.approx(true, rel=1e-6), (i, rr[i], true)
+            assert rr[i] < 1e-12
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_gengk_matches_algorithm1_oracle(precision):
     n1, n2 = 12, 12
@@ -287,7 +305,9 @@ def test_error_paths():
             K.kry_problem_destroy(h)
     finally:
         K.kry_ctx_destroy(ctx)
-    small = K.kry_ctx_create(0, 1 << 20)
+    # a budget that holds the context's tables (about 1.4 MB) but not a
+    # 512 x 512 problem
+    small = K.kry_ctx_create(0, 3 << 20)
     try:
         with pytest.raises(K.KryError) as e:
             K.kry_problem_create(small, 512, 512, np.ones((512, 512)))

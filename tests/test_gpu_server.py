@@ -155,16 +155,83 @@ def test_server_admission_by_footprint():
             assert e.value.status == K.KRY_ENOMEM
         finally:
             K.kry_server_destroy(srv)
-        # a budget that fits one request at a time still completes every request
-        srv = K.kry_server_create(ctx, slots=3, hbm_budget_bytes=300 << 20, max_batch=1)
-        try:
+        # the reference values first: the problems' own workspaces are then
+        # in place, and what the server allocates on top is its slots'
+        ref = [K.kry_loglik(probs[i % 3], th, opts)["loglik"] for i in range(6)]
+        kopts = K.kry_opts_default(cg_rtol=1e-9)
+        tg = [np.flatnonzero(m.ravel() == 0)[:8] for m in masks]
+        kref = [K.kry_krige(probs[i], th, kopts, tg[i], want_var=True) for i in range(3)]
+        # a budget that fits one request at a time still completes every
+        # request, and the slots' device memory (kept between requests) never
+        # exceeds it: an idle slot's workspace is released to admit another
+        def submit_all(srv):
             pend = [K.kry_server_submit(srv, K.KRY_REQ_LOGLIK, probs[i % 3], th, opts) for i in range(6)]
-            resp = [K.kry_server_wait(srv, p) for p in pend]
-            assert all(r.status == K.KRY_OK for r in resp)
-            ref = [K.kry_loglik(probs[i % 3], th, opts)["loglik"] for i in range(6)]
-            assert [r.loglik.loglik for r in resp] == ref
+            pend += [K.kry_server_submit(srv, K.KRY_REQ_KRIGE, probs[i], th, kopts, targets=tg[i], variances=True)
+                     for i in range(3)]
+            return pend, [K.kry_server_wait(srv, p) for p in pend]
+
+        # every request's admission bound, from an unlimited server
+        srv = K.kry_server_create(ctx, slots=3, max_batch=1)
+        try:
+            _, r0 = submit_all(srv)
         finally:
             K.kry_server_destroy(srv)
+        fps = [r.footprint_bytes for r in r0]
+        # room for the largest request but not for two of them: slots must
+        # give back what they keep for others to start
+        budget = max(fps) + min(fps) // 2
+        base, _ = K.kry_ctx_memory(ctx, reset_peak=True)
+        srv = K.kry_server_create(ctx, slots=3, hbm_budget_bytes=budget, max_batch=1)
+        try:
+            pend, resp = submit_all(srv)
+            assert all(r.status == K.KRY_OK for r in resp)
+            assert [r.loglik.loglik for r in resp[:6]] == ref
+            for pd, (m, vx, vy) in zip(pend[6:], kref):
+                np.testing.assert_array_equal(pd.outputs["mean_x"], m)
+                np.testing.assert_array_equal(pd.outputs["var_x"], vx)
+            _, peak = K.kry_ctx_memory(ctx)
+            assert peak - base <= budget, (peak - base, budget)
+        finally:
+            K.kry_server_destroy(srv)
+    finally:
+        for h in probs:
+            K.kry_problem_destroy(h)
+        K.kry_ctx_destroy(ctx)
+
+
+def test_server_footprint_bounds_each_request():
+    # the admission bound of a request covers the workspace it needs: run
+    # each kind alone on a fresh one-slot server, whose workspace then holds
+    # exactly what that request allocated
+    ctx = K.kry_ctx_create()
+    probs, masks = _problems(ctx)
+    try:
+        th = K.theta(range=0.1, nu=1.5, tau2=0.2)
+        cases = [
+            ("loglik", K.kry_opts_default(lanczos_steps=12, num_probes=5)),
+            ("loglik", K.kry_opts_default(lanczos_steps=12, num_probes=5, precision=1, reorth=1)),
+            ("loglik", K.kry_opts_default(lanczos_steps=8, num_probes=3, solver=1, gk_steps=10)),
+            ("loglik", K.kry_opts_default(lanczos_steps=8, num_probes=3, probe_kind=K.KRY_PROBE_COLOURED,
+                                          colour_period=3, lanczos_rtol=1e-6, lanczos_max_steps=40)),
+            ("krige", K.kry_opts_default(cg_rtol=1e-9)),
+            ("krige", K.kry_opts_default(cg_rtol=1e-9, precision=1)),
+        ]
+        for pi in range(3):
+            miss = np.flatnonzero(masks[pi].ravel() == 0)
+            for kind, opts in cases:
+                srv = K.kry_server_create(ctx, slots=1)
+                try:
+                    if kind == "loglik":
+                        pd = K.kry_server_submit(srv, K.KRY_REQ_LOGLIK, probs[pi], th, opts)
+                    else:
+                        pd = K.kry_server_submit(srv, K.KRY_REQ_KRIGE, probs[pi], th, opts, targets=miss[:20],
+                                                 variances=True)
+                    r = K.kry_server_wait(srv, pd)
+                    assert r.status == K.KRY_OK
+                    assert 0 < r.workspace_bytes <= r.footprint_bytes, (pi, kind, r.workspace_bytes,
+                                                                        r.footprint_bytes)
+                finally:
+                    K.kry_server_destroy(srv)
     finally:
         for h in probs:
             K.kry_problem_destroy(h)

@@ -63,6 +63,10 @@ def test_masked_product_fp64_and_fp32(shape, ti):
         got32 = K.kry_matvec(P.h, t, v, K.KRY_FP32)
     assert rows_rel(got64, ref) <= 1e-12
     assert rows_rel(got32, ref) <= 1e-5
+    # element by element, against the largest entry of each output vector
+    scale = np.abs(ref).max(axis=1, keepdims=True)
+    assert np.all(np.abs(got64 - ref) <= 1e-12 * scale)
+    assert np.all(np.abs(got32 - ref) <= 1e-5 * scale)
 
 
 def test_all_missing_but_one_and_fully_observed():
