@@ -273,6 +273,22 @@ kry_status kry_matvec(kry_problem* prob, const kry_matern* theta, int32_t precis
  * by the problem and reused by later calls on the same stream. */
 kry_status kry_matvec_device(kry_problem* prob, const kry_matern* theta, int32_t precision,
                              int32_t nvec, const void* d_v, void* d_out, void* hip_stream);
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, serving loops, harnesses that forbid hipMalloc): the product of
+ * kry_matvec_device, same arguments, layout and results, with every
+ * intermediate (lag grid, spectrum, transform intermediate) in one
+ * file-scope device array of KRY_NOALLOC_SCRATCH_BYTES per GPU, held from
+ * library load until the process ends.  Nothing is allocated and nothing
+ * waits: the spectrum is recomputed and the work only enqueued on
+ * `hip_stream`.  Masked grid problems only (KRY_EINVAL for irregular ones);
+ * KRY_EINVAL with a message when the embedding's spectrum or one vector's
+ * intermediate does not fit (embeddings up to 2048 x 2048 fit; larger
+ * batches go through in chunks).  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams, other threads) race
+ * and must be serialised by the caller. */
+#define KRY_NOALLOC_SCRATCH_BYTES (256ull << 20)
+kry_status kry_matvec_device_noalloc(kry_problem* prob, const kry_matern* theta, int32_t precision,
+                                     int32_t nvec, const void* d_v, void* d_out, void* hip_stream);
 /* Sigma A^T w: compact vectors in, full-grid vectors out (nvec x n1*n2),
  * no nugget -- the kriging-mean product (eq. act_xhat) and the Sigma
  * product of Algorithm 1. */

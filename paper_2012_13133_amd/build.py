@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libkryging.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["conv.hip", "krylov.hip", "api.hip", "server.hip", "plik.hip", "irregular.hip"]
+SOURCES = ["conv.hip", "krylov.hip", "api.hip", "server.hip", "plik.hip", "irregular.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

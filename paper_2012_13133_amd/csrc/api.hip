@@ -37,6 +37,8 @@ static kry_status guard(F&& f) {
 
 namespace kry {
 
+kry_status run_guarded(const std::function<void()>& f) { return guard(f); }
+
 void* dev_alloc(Ctx& c, size_t bytes) {
     if (bytes == 0) bytes = 256;
     {
@@ -1408,8 +1410,9 @@ kry_status kry_ctx_create(int32_t device, uint64_t hbm_budget_bytes, kry_ctx** o
             KRY_HIP(hipMemcpy(k->c.tw64, t64.data(), TW_N * sizeof(cpx<double>), hipMemcpyHostToDevice));
             KRY_HIP(hipMemcpy(k->c.tw32, t32.data(), TW_N * sizeof(cpx<float>), hipMemcpyHostToDevice));
             // every transform length's pass twiddles now, so that products
-            // allocate nothing later
+            // allocate nothing later; and the no-allocation product's scratch
             build_plan_tables(k->c);
+            k->c.scratch = noalloc_scratch_init(device);
         } catch (...) {
             kry_ctx_destroy(k);
             throw;

@@ -75,6 +75,7 @@ struct Ctx {
     std::mutex tune_mu;
     static constexpr int kSmallBatch = 8;
     static int batch_class(int nvec) { return nvec <= kSmallBatch ? 0 : 1; }
+    void* scratch = nullptr;  // device address of the no-allocation product's scratch array
     // The setting for products of nvec vectors: that batch class's, else the
     // other class's, else the built-in default.
     Tuning tuning_for(int N1, int N2, int real_bytes, int nvec = 1 << 30) {
@@ -88,6 +89,11 @@ struct Ctx {
 
 void* dev_alloc(Ctx& c, size_t bytes);
 void dev_free(Ctx& c, void* p, size_t bytes);
+// Device address of the no-allocation product's scratch array on `device`
+// (the current device), looked up once per device.
+void* noalloc_scratch_init(int device);
+// Runs f, turning an exception into a status and the thread's error message.
+kry_status run_guarded(const std::function<void()>& f);
 
 // A device buffer that only grows; freed with its owner.
 struct DevBuf {

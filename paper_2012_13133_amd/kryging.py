@@ -120,6 +120,7 @@ _SIGS = {
     "kry_spectrum": (C.c_int, [_P, C.POINTER(kry_matern), C.c_int32, C.c_int32, _DP, _DP]),
     "kry_matvec": (C.c_int, [_P, C.POINTER(kry_matern), C.c_int32, C.c_int32, _DP, _DP]),
     "kry_matvec_device": (C.c_int, [_P, C.POINTER(kry_matern), C.c_int32, C.c_int32, _P, _P, _P]),
+    "kry_matvec_device_noalloc": (C.c_int, [_P, C.POINTER(kry_matern), C.c_int32, C.c_int32, _P, _P, _P]),
     "kry_cov_apply_full": (C.c_int, [_P, C.POINTER(kry_matern), C.c_int32, C.c_int32, _DP, _DP]),
     "kry_probes": (C.c_int, [_P, C.POINTER(kry_opts), _I32P, _DP]),
     "kry_lanczos": (C.c_int, [_P, C.POINTER(kry_matern), C.POINTER(kry_opts), _DP, _DP, _I32P]),
@@ -308,6 +309,12 @@ def kry_matvec(prob, th, v, precision=KRY_FP64):
     out = np.empty_like(v)
     _check(lib.kry_matvec(prob, C.byref(th), precision, v.shape[0], _dp(v), _dp(out)))
     return out
+
+
+def kry_matvec_device_noalloc(prob, th, precision, nvec, d_v, d_out, stream=None):
+    """kry_matvec_device without device allocation (scratch array; see the header)."""
+    _check(lib.kry_matvec_device_noalloc(prob, C.byref(th), precision, nvec, C.c_void_p(d_v), C.c_void_p(d_out),
+                                         C.c_void_p(stream) if stream else None))
 
 
 def kry_matvec_device(prob, th, precision, nvec, d_v, d_out, stream=None):
