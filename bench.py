@@ -50,14 +50,15 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--matvec-only", action="store_true", help="only the isolated batched product (profiling)")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--serve-plain-sample", type=int, default=200,
+    ap.add_argument("--serve-requests", type=int, default=100)
+    ap.add_argument("--serve-targets", type=int, default=4, help="kriging targets per request (with exact variances)")
+    ap.add_argument("--serve-plain-sample", type=int, default=100,
                     help="requests of the stream also run in the plain FP64 form (accuracy and rate)")
     ap.add_argument("--serve-sides", type=str, default="128,2048",
                     help="grid sides log-uniform in [lo,hi] for the served stream (the full served workload uses 128,2048)")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-budget-gib", type=int, default=64, help="the server's HBM budget")
-    ap.add_argument("--serve-sweep", type=str, default="0.5,0.8,1.0", help="arrival rates, fractions of saturation")
+    ap.add_argument("--serve-sweep", type=str, default="0.8", help="arrival rates, fractions of saturation")
     ap.add_argument("--multi", type=int, default=64, help="independent problems in the multi-problem form (0: skip)")
     ap.add_argument("--multi-sides", type=str, default="64,1024")
     ap.add_argument("--multi-only", action="store_true", help="only the multi-problem form")
@@ -65,13 +66,13 @@ def parse():
     ap.add_argument("--no-c4", action="store_true", help="skip the large anisotropic end-to-end problem")
     ap.add_argument("--c4-only", action="store_true", help="only the large anisotropic end-to-end problem")
     ap.add_argument("--c4-n", type=int, default=2048)
-    ap.add_argument("--c4-probes", type=int, default=10)
+    ap.add_argument("--c4-probes", type=int, default=8)
     ap.add_argument("--c4-steps", type=int, default=50)
     ap.add_argument("--c4-lanczos-rtol", type=float, default=1e-5)
-    ap.add_argument("--c4-lanczos-max", type=int, default=400)
+    ap.add_argument("--c4-lanczos-max", type=int, default=512)
     ap.add_argument("--c4-cg-rtol", type=float, default=1e-7)
     ap.add_argument("--c4-maxiter", type=int, default=20)
-    ap.add_argument("--c4-xtol", type=float, default=2e-2)
+    ap.add_argument("--c4-xtol", type=float, default=1e-2)
     ap.add_argument("--c4-boot", type=int, default=20)
     ap.add_argument("--c4-exact", type=int, default=32, help="missing cells with exact variances")
     ap.add_argument("--no-ext", action="store_true", help="skip the extension rows (irregular data, covariates, "
@@ -98,7 +99,7 @@ def measured_traffic():
         return None
     vals = dict(re.findall(r"^(traffic_stage_b_fp32_bytes|kernel_sources_sha256): (\S+)$", txt, re.M))
     h = hashlib.sha256()
-    for name in ("conv.hip", "fftk.hpp", "fft.hpp", "common.hpp"):
+    for name in ("conv.hip", "fftk.hpp", "fftm.hpp", "fft.hpp", "common.hpp"):
         with open(os.path.join(ROOT, "paper_2012_13133_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     if vals.get("kernel_sources_sha256") != h.hexdigest() or "traffic_stage_b_fp32_bytes" not in vals:
@@ -323,6 +324,9 @@ def main():
     # ---- extension rows ----
     ext = None if args.no_ext else ext_bench(args, K, synth, np)
 
+    # ---- the large anisotropic problem end to end (2048 x 2048) ----
+    c4 = None if args.no_c4 else config4_bench(args, K, synth, np)
+
     # ---- CPU oracle on a bounded sample ----
     cpu = None
     if not args.no_cpu:
@@ -374,6 +378,7 @@ def main():
     out["serve"] = serve
     out["multi"] = multi
     out["extensions"] = ext
+    out["config4"] = c4
     print(json.dumps(out))
     if P is not None:
         P.close()
@@ -422,16 +427,24 @@ def serve_bench(args, K, synth, np):
             reqs.append(("loglik", pi, th, None))
         else:
             miss = np.flatnonzero(masks[pi].ravel() == 0)
-            reqs.append(("krige", pi, th, rng.choice(miss, size=16, replace=False)))
-    o32 = K.kry_opts_default(lanczos_steps=30, num_probes=10, precision=K.KRY_FP32, cg_rtol=1e-8)
-    o64 = K.kry_opts_default(lanczos_steps=30, num_probes=10, precision=K.KRY_FP64, cg_rtol=1e-8)
+            reqs.append(("krige", pi, th, rng.choice(miss, size=args.serve_targets, replace=False)))
+    # served likelihoods: FP32 Lanczos products with reorthogonalisation (FP64
+    # coefficients) and the FP64 multi-shift CG; served kriging: FP64 solves
+    # (on these grids the condition numbers reach 1e6-1e7, where FP32 solves
+    # inside FP64 refinement take more iterations than they save).  The plain
+    # form: everything FP64, the same probes, steps, reorthogonalisation and
+    # CG tolerance.
+    common = dict(lanczos_steps=30, num_probes=10, reorth=1, cg_rtol=1e-8, cg_maxit=200000)
+    o32 = K.kry_opts_default(precision=K.KRY_FP32, shift_share=1, **common)
+    o64 = K.kry_opts_default(precision=K.KRY_FP64, **common)
+    ok = K.kry_opts_default(precision=K.KRY_FP64, **common)
     budget = args.serve_budget_gib << 30
 
     def submit(srv, r, opts):
         kind, pi, th, tg = r
         if kind == "loglik":
             return K.kry_server_submit(srv, K.KRY_REQ_LOGLIK, probs[pi], th, opts)
-        return K.kry_server_submit(srv, K.KRY_REQ_KRIGE, probs[pi], th, opts, tg, variances=True)
+        return K.kry_server_submit(srv, K.KRY_REQ_KRIGE, probs[pi], th, ok, tg, variances=True)
 
     base_mem, _ = K.kry_ctx_memory(ctx, reset_peak=True)
     srv = K.kry_server_create(ctx, slots=args.serve_slots, hbm_budget_bytes=budget, max_batch=16)
@@ -500,7 +513,7 @@ def serve_bench(args, K, synth, np):
             ref = K.kry_loglik(probs[pi], th, o64, allow_noconv=True)["loglik"]
             errs.append(abs(resp0[i].loglik.loglik - ref) / abs(ref))
         else:
-            m64, _, _ = K.kry_krige(probs[pi], th, o64, tg)
+            m64, _, _ = K.kry_krige(probs[pi], th, o64, tg)  # (the served kriging is FP64 too)
             m32 = pend0[i].outputs["mean_x"]
             kerr.append(float(np.max(np.abs(m32 - m64)) / max(np.max(np.abs(m64)), 1e-300)))
     seq = time.perf_counter() - t1
@@ -515,7 +528,8 @@ def serve_bench(args, K, synth, np):
            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
            "req_per_s": len(reqs) / wall, "loglik_evals_per_s": n_ll / wall,
            "max_batch_seen": int(max(r.batch for r in resp)), "service_time_by_side": service,
-           "served_precision": "fp32 transforms, fp64 reductions, cg_rtol 1e-8",
+           "served_precision": "likelihood: fp32 Lanczos products (reorthogonalised, fp64 coefficients), fp64 "
+                                "multi-shift CG; kriging: fp64; cg_rtol 1e-8",
            "plain_fp64": {"sample": "every %d-th request (%d of %d), sequential, cg_rtol 1e-8" % (k, len(sample),
                                                                                                  len(reqs)),
                           "req_per_s": plain_rate, "loglik_requests": len(errs),
@@ -723,8 +737,20 @@ def config4_bench(args, K, synth, np):
         opts = K.kry_opts_default(lanczos_steps=args.c4_steps, num_probes=args.c4_probes, precision=K.KRY_FP32,
                                   reorth=0, cg_rtol=args.c4_cg_rtol, seed=303, lanczos_rtol=args.c4_lanczos_rtol,
                                   lanczos_max_steps=args.c4_lanczos_max)
-        init = K.theta(sigma2=1.0, tau2=0.2, range=0.08, nu=1.0, aniso_ratio=2.0, aniso_angle=ang)
+        # a coarse (range, nugget ratio) grid in one shift-shared batch (the
+        # nugget values of a range share Krylov spaces), then Nelder-Mead from
+        # its best point, the same probes throughout (common random numbers)
         t1 = time.perf_counter()
+        grid_r, grid_e = (0.02, 0.035, 0.06, 0.1), (0.03, 0.1, 0.3)
+        pts = [K.theta(sigma2=1.0, tau2=e, range=r, nu=1.0, aniso_ratio=2.0, aniso_angle=ang)
+               for r in grid_r for e in grid_e]
+        gopts = dict((f, getattr(opts, f)) for f, _ in opts._fields_)
+        gopts["shift_share"] = 1
+        gres = K.kry_loglik_batch(h, pts, K.kry_opts_default(**gopts), allow_noconv=True)
+        best = int(np.argmax([g["loglik_profiled"] for g in gres]))
+        init = pts[best]
+        grid_s = time.perf_counter() - t1
+        log("config 4 coarse grid: best range %.3f nugget ratio %.3f (%.1f s)" % (init.range, init.tau2, grid_s))
         est, at = K.kry_fit(h, init, 3, opts, xtol=args.c4_xtol, maxiter=args.c4_maxiter)
         fit_s = time.perf_counter() - t1
         eta_hat = est.tau2 / est.sigma2
@@ -733,7 +759,9 @@ def config4_bench(args, K, synth, np):
                       "lanczos_steps_at_estimate": at["lanczos_steps_used"], "cg_iters_at_estimate": at["cg_iters"],
                       "xtol": args.c4_xtol, "maxiter": args.c4_maxiter, "probes": args.c4_probes,
                       "lanczos": "adaptive, rtol %g, at most %d steps" % (args.c4_lanczos_rtol, args.c4_lanczos_max),
-                      "cg_rtol": args.c4_cg_rtol, "start": [0.08, 0.2], "truth": [0.05, 0.1]}
+                      "cg_rtol": args.c4_cg_rtol, "coarse_grid": {"ranges": list(grid_r), "nugget_ratios": list(grid_e),
+                                                                  "seconds": grid_s, "start": [init.range, init.tau2]},
+                      "truth": [0.05, 0.1]}
         log("config 4 fit: range %.4f nugget ratio %.4f sigma2 %.3f in %.1f s" % (est.range, eta_hat, est.sigma2,
                                                                                  fit_s))
         # kriging at every missing cell: means and bootstrap variances

@@ -87,9 +87,15 @@ def spectrum(c):
 
 
 def fast_size(m):
-    """Smallest power of two >= m (the embedding size the library uses for the
-    masked product; any size >= 2n - 1 gives the exact product)."""
-    N = 1
-    while N < m:
-        N *= 2
-    return N
+    """Smallest side >= max(16, m) of the form 2^a 3^b 5^c with 16 | side whose
+    half has at most one factor 3 or 5 beyond 2^3, within 8192 (the sides the
+    library's transforms take: powers of two, 3 * 2^a, 5 * 2^a; any side
+    >= 2n - 1 gives the exact product, so this only sets the cost)."""
+    N = max(16, int(m))
+    while N <= 8192:
+        k = N // 16
+        if N % 16 == 0 and (k & (k - 1) == 0 or (k % 3 == 0 and (k // 3) & (k // 3 - 1) == 0)
+                            or (k % 5 == 0 and (k // 5) & (k // 5 - 1) == 0)):
+            return N
+        N += 1
+    return None

@@ -964,8 +964,62 @@ void loglik_points_shared(Problem& P, const kry_matern* thetas, int count, const
     KRY_HIP(hipMemcpyAsync(d_src, src.data(), nout * sizeof(int), hipMemcpyHostToDevice, st));
     ShiftQuad sq{nout, d_src, d_shift};
     LoglikWork W;
-    if (fp32) slq_device<float>(P, o, P.spec_multi32.ptr, nspec, d_zero, G, W, nullptr, nullptr, st, &sq);
-    else slq_device<double>(P, o, P.spec_multi64.ptr, gstride, d_zero, G, W, nullptr, nullptr, st, &sq);
+    auto run_slq = [&](Problem& Qp, hipStream_t s) {
+        if (fp32) slq_device<float>(Qp, o, P.spec_multi32.ptr, nspec, d_zero, G, W, nullptr, nullptr, s, &sq);
+        else slq_device<double>(Qp, o, P.spec_multi64.ptr, gstride, d_zero, G, W, nullptr, nullptr, s, &sq);
+    };
+    // The log-determinants and the multi-shift solves are independent: on a
+    // problem (not a request view of the server) the Lanczos recurrences run
+    // on a second stream with a workspace of their own while the solves run
+    // here, so the solves' small products no longer leave the device idle.
+    // Every kernel sees the same inputs as in sequence: the results are the same.
+    // (FP32 form only: the FP64 recurrences read the FP64 spectra, whose
+    // positions the solves permute as groups finish.)
+    const bool overlap = fp32 && need_ms && !P.is_view && !C.prof.on;
+    std::thread lz;
+    hipStream_t st2 = nullptr;
+    Problem lv;
+    std::string lz_err;
+    kry_status lz_status = KRY_OK;
+    if (overlap) {
+        if (!P.side) {
+            P.side = std::make_shared<Problem>();
+            P.side->ctx = &C;
+        }
+        lv = P.view();
+        lv.no_graphs = true;
+        lv.swap_work(*P.side);
+        KRY_HIP(hipStreamCreateWithFlags(&st2, hipStreamNonBlocking));
+        KRY_HIP(hipStreamSynchronize(st));  // spectra, shifts and nugget ratios are in place
+        lz = std::thread([&] {
+            try {
+                KRY_HIP(hipSetDevice(C.device));
+                run_slq(lv, st2);
+            } catch (const Error& e) {
+                lz_status = e.status;
+                lz_err = e.what();
+            } catch (const std::exception& e) {
+                lz_status = KRY_EDEVICE;
+                lz_err = e.what();
+            }
+        });
+    } else {
+        run_slq(P, st);
+    }
+    struct Join {
+        std::thread& t;
+        hipStream_t& s;
+        Problem& v;
+        Problem& P;
+        ~Join() {
+            if (t.joinable()) t.join();
+            if (s) {
+                (void)hipStreamSynchronize(s);
+                (void)hipStreamDestroy(s);
+                v.swap_work(*P.side);
+            }
+        }
+    } join{lz, st2, lv, P};
     std::vector<double> Q(count, 0.0), relres(count, 0.0), M;
     std::vector<int> iters(count, 0);
     std::vector<Gls> gls(P.q > 0 ? count : 0);
@@ -1027,6 +1081,8 @@ void loglik_points_shared(Problem& P, const kry_matern* thetas, int count, const
             Q[t] = P.q > 0 ? gls[t].Q : Mt[0];
         }
     }
+    if (lz.joinable()) lz.join();
+    if (lz_status != KRY_OK) throw Error(lz_status, lz_err);
     if (o->solver != KRY_SOLVER_CG) {
         double* resid = nullptr;
         if (P.q > 0) {
@@ -1476,6 +1532,8 @@ void kry_ctx_destroy(kry_ctx* ctx) {
         if (ctx->c.plan64[i]) (void)hipFree(ctx->c.plan64[i]);
         if (ctx->c.plan32[i]) (void)hipFree(ctx->c.plan32[i]);
     }
+    for (auto& kv : ctx->c.mplan64) (void)hipFree(kv.second);
+    for (auto& kv : ctx->c.mplan32) (void)hipFree(kv.second);
     dev_free(ctx->c, ctx->c.tw64, TW_N * sizeof(cpx<double>));
     dev_free(ctx->c, ctx->c.tw32, TW_N * sizeof(cpx<float>));
     if (ctx->c.stream) (void)hipStreamDestroy(ctx->c.stream);
@@ -1580,8 +1638,8 @@ kry_status kry_problem_create(kry_ctx* ctx, const kry_grid* grid, const uint8_t*
             P.n2 = n2;
             P.dx1 = grid->dx1;
             P.dx2 = grid->dx2;
-            P.N1 = pow2_at_least(2 * n1 - 1);
-            P.N2 = pow2_at_least(2 * n2 - 1);
+            P.N1 = embedding_side(2 * n1 - 1);
+            P.N2 = embedding_side(2 * n2 - 1);
             P.p = p;
             P.words_per_row = (n2 + 31) / 32;
             const int64_t nw = (int64_t)n1 * P.words_per_row;
@@ -1721,8 +1779,8 @@ kry_status kry_problem_create_irregular(kry_ctx* ctx, const kry_grid* grid, int6
             P.n2 = n2;
             P.dx1 = grid->dx1;
             P.dx2 = grid->dx2;
-            P.N1 = pow2_at_least(2 * n1 - 1);
-            P.N2 = pow2_at_least(2 * n2 - 1);
+            P.N1 = embedding_side(2 * n1 - 1);
+            P.N2 = embedding_side(2 * n2 - 1);
             P.p = p;
             P.irregular = true;
             P.h_cell = hc;
@@ -1815,8 +1873,8 @@ static void torus_args(Problem& P, int32_t& N1, int32_t& N2) {
         N1 = P.N1;
         N2 = P.N2;
     }
-    KRY_REQUIRE(N1 >= 16 && N2 >= 16 && N1 <= 8192 && N2 <= 8192, "torus sizes must be in [16, 8192]");
-    KRY_REQUIRE((N1 & (N1 - 1)) == 0 && (N2 & (N2 - 1)) == 0, "torus sizes must be powers of two");
+    KRY_REQUIRE(torus_side_ok(N1) && torus_side_ok(N2),
+                "torus sides must be in [16, 8192], powers of two or 2^a 3^b 5^c transform lengths");
 }
 
 kry_status kry_lag_grid(kry_problem* prob, const kry_matern* theta, int32_t N1, int32_t N2, double* c_out) {
@@ -2403,8 +2461,7 @@ kry_status kry_set_tuning(kry_ctx* ctx, int32_t N1, int32_t N2, int32_t precisio
     return guard([&] {
         KRY_REQUIRE(ctx != nullptr, "NULL context");
         KRY_REQUIRE(precision == KRY_FP64 || precision == KRY_FP32, "bad precision");
-        KRY_REQUIRE(N1 >= 16 && N2 >= 16 && N1 <= 8192 && N2 <= 8192 && (N1 & (N1 - 1)) == 0 && (N2 & (N2 - 1)) == 0,
-                    "N1, N2 must be powers of two in [16, 8192]");
+        KRY_REQUIRE(torus_side_ok(N1) && torus_side_ok(N2), "N1, N2 must be supported torus sides");
         const int rb = precision == KRY_FP32 ? 4 : 8;
         std::lock_guard<std::mutex> g(ctx->c.tune_mu);
         if (!t) {  // both batch classes

@@ -23,6 +23,7 @@
 #include <unordered_map>
 
 #include "fftk.hpp"
+#include "fftm.hpp"
 #include "internal.hpp"
 
 namespace kry {
@@ -182,42 +183,13 @@ __device__ __forceinline__ void load_pair(const StageAArgs& a, const MaskView& m
     }
 }
 
-// Stage A: per row, z[m] = x[2m] + i x[2m+1] -> FFT of length M -> split into
-// the real transform X[k], k = 0..M, written as Y[k][row] in RT-row runs.
-// A row is transformed by TR = M / (8 VT) threads holding 8 VT values each;
-// when those lie in one wavefront the passes need no workgroup barrier, and
-// the only barrier is the one before the split, which mixes rows.
-template <typename R, int LOG2M, int IN, int VT, bool SPLIT>
-__global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(R) == 4 && IN == IN_COMPACT ? 8 : 4))) k_row_fwd(StageAArgs a, const cpx<R>* __restrict__ twp,
-                                                                   const cpx<R>* __restrict__ twb) {
-    using S = Sched<LOG2M>;
-    constexpr int M = S::L, T = M / 8, PM = lpadded<cpx<R>>(M) + 1;
-    constexpr int TR = T / VT;
-    constexpr bool WAVE = TR <= 64;
-    constexpr bool LOW = (IN == IN_COMPACT);  // row_len <= M: z[m] = 0 for m >= M/2
-    extern __shared__ unsigned char smem_raw[];
-    cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
-    const int tid = threadIdx.x;
-    const int rr = tid / TR, t = tid % TR;
-    // row tiles of one vector run consecutively on one XCD, so the halves of
-    // a cache line written by neighbouring tiles merge in its L2
-    const int lid = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-    const int row0 = (lid % gridDim.x) * a.RT;
-    const int row = row0 + rr;
-    const int vec = lid / gridDim.x;
-    if (a.active && !a.active[vec]) return;
-    MaskView mask = a.mask;
-    int rows_in = a.rows_in, row_len = a.row_len;
-    if (a.tab) {
-        const ProbDesc& d = a.tab[(a.vec0 + vec) / a.tab_vpp];
-        mask = MaskView{d.bits, d.base, d.wpr};
-        rows_in = d.n1;
-        row_len = d.n2;
-        if (row0 >= rows_in) return;  // rows the column transform never reads
-    }
-    cpx<R>* buf = lds + rr * PM;
-    const int nt = blockDim.x;
-    cpx<R> v[8 * VT];
+// The inputs of a row-forward thread: 8 VT values of row `row` at columns
+// 2 (t + u TR + r T) and the next one (pairs packed as complex values), 0
+// beyond the data or off the mask; with a compact input and a direction
+// update (StageAArgs::upd_r), the input is updated and written back first.
+template <typename R, int IN, int VT, bool LOW>
+__device__ __forceinline__ void row_inputs(const StageAArgs& a, const MaskView& mask, int vec, int row, int rows_in,
+                                           int row_len, int t, int TR, int T, cpx<R>* v) {
     if constexpr (IN == IN_COMPACT) {
         // every mask word and offset first, then every value: two rounds of
         // independent loads instead of a dependent chain per pair.  Pairs
@@ -303,6 +275,45 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
                 if (row < rows_in) load_pair<R, IN>(a, mask, row_len, vec, row, 2 * (t + u * TR + r * T), v[u * 8 + r]);
             }
     }
+}
+
+// Stage A: per row, z[m] = x[2m] + i x[2m+1] -> FFT of length M -> split into
+// the real transform X[k], k = 0..M, written as Y[k][row] in RT-row runs.
+// A row is transformed by TR = M / (8 VT) threads holding 8 VT values each;
+// when those lie in one wavefront the passes need no workgroup barrier, and
+// the only barrier is the one before the split, which mixes rows.
+template <typename R, int LOG2M, int IN, int VT, bool SPLIT>
+__global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(R) == 4 && IN == IN_COMPACT ? 8 : 4))) k_row_fwd(StageAArgs a, const cpx<R>* __restrict__ twp,
+                                                                   const cpx<R>* __restrict__ twb) {
+    using S = Sched<LOG2M>;
+    constexpr int M = S::L, T = M / 8, PM = lpadded<cpx<R>>(M) + 1;
+    constexpr int TR = T / VT;
+    constexpr bool WAVE = TR <= 64;
+    constexpr bool LOW = (IN == IN_COMPACT);  // row_len <= M: z[m] = 0 for m >= M/2
+    extern __shared__ unsigned char smem_raw[];
+    cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int rr = tid / TR, t = tid % TR;
+    // row tiles of one vector run consecutively on one XCD, so the halves of
+    // a cache line written by neighbouring tiles merge in its L2
+    const int lid = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int row0 = (lid % gridDim.x) * a.RT;
+    const int row = row0 + rr;
+    const int vec = lid / gridDim.x;
+    if (a.active && !a.active[vec]) return;
+    MaskView mask = a.mask;
+    int rows_in = a.rows_in, row_len = a.row_len;
+    if (a.tab) {
+        const ProbDesc& d = a.tab[(a.vec0 + vec) / a.tab_vpp];
+        mask = MaskView{d.bits, d.base, d.wpr};
+        rows_in = d.n1;
+        row_len = d.n2;
+        if (row0 >= rows_in) return;  // rows the column transform never reads
+    }
+    cpx<R>* buf = lds + rr * PM;
+    const int nt = blockDim.x;
+    cpx<R> v[8 * VT];
+    row_inputs<R, IN, VT, LOW>(a, mask, vec, row, rows_in, row_len, t, TR, T, v);
     cpx<R>* Y = reinterpret_cast<cpx<R>*>(a.Y) + vec * a.Y_vstride;
     if constexpr (SPLIT) {
         // exchanges of reals (half the LDS per row); the split below reads
@@ -556,6 +567,86 @@ struct StageCArgs {
     const int* active;    // per-vector skip flags (nullable)
 };
 
+// Compact indices of a row-inverse thread's output cells (columns 2 m and
+// 2 m + 1 for its values, m = pos(k)), looked up before the transform so the
+// loads overlap it; 2 bits per value in obits: which of the two is observed.
+template <int OUT, int NV, typename PosF>
+__device__ __forceinline__ void row_output_cells(const MaskView& mask, int row, int rows_out, int cols_out,
+                                                 int32_t* oci, uint64_t& obits, PosF pos) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        oci[k] = 0;
+        if constexpr (OUT == OUT_COMPACT) {
+            const int c0 = 2 * pos(k);
+            if (row < rows_out && c0 < cols_out) {
+                const uint32_t w = (uint32_t)(row * mask.words_per_row + (c0 >> 5));
+                const uint32_t word = at32(mask.bits, w);
+                const uint32_t b0 = 1u << (c0 & 31);
+                obits |= (uint64_t)((word & b0 ? 1u : 0u) | (word & (b0 << 1) ? 2u : 0u)) << (2 * k);
+                oci[k] = (int32_t)(at32(mask.base, w) + __popc(word & (b0 - 1u)));
+            }
+        }
+    }
+}
+
+// A row-inverse thread's outputs: x[2m], x[2m+1] = Re, Im of value k (m =
+// pos(k)) to the observed cells plus eta v, or to the grid row scaled.
+template <typename R, int OUT, int NV, typename PosF>
+__device__ __forceinline__ void row_outputs(const StageCArgs& a, int row, int cols_out, int vec, const int32_t* oci,
+                                            uint64_t obits, const cpx<R>* v, PosF pos) {
+    const int theta = (a.vec0 + vec) / a.vecs_per_theta;
+    // outputs in groups of two values: the group's nugget-term inputs are
+    // loaded together (none when eta = 0), then its stores go out
+    constexpr int GK = 2;
+    const R e = (OUT == OUT_COMPACT && a.vin) ? (R)a.eta[theta] : (R)0;
+    const R* vi = reinterpret_cast<const R*>(a.vin) + vec * a.vin_vstride;
+    R* oc = reinterpret_cast<R*>(a.out) + vec * a.out_vstride;
+#pragma unroll
+    for (int k0 = 0; k0 < NV; k0 += GK) {
+        R vx[GK], vy[GK];
+#pragma unroll
+        for (int g = 0; g < GK; ++g) {
+            vx[g] = (R)0;
+            vy[g] = (R)0;
+        }
+        if constexpr (OUT == OUT_COMPACT) {
+            if (e != (R)0) {
+#pragma unroll
+                for (int g = 0; g < GK; ++g) {
+                    const uint32_t b = (uint32_t)(obits >> (2 * (k0 + g))) & 3u;
+                    const uint32_t ci = (uint32_t)oci[k0 + g];
+                    const R x = at32(vi, (b & 1u) ? ci : 0u);
+                    const R y = at32(vi, (b & 2u) ? ci + (b & 1u) : 0u);
+                    vx[g] = (b & 1u) ? x : (R)0;
+                    vy[g] = (b & 2u) ? y : (R)0;
+                }
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < GK; ++g) {
+            const int k = k0 + g;
+            const int m = pos(k);
+            const int c0 = 2 * m;
+            if (c0 >= cols_out) continue;
+            if constexpr (OUT == OUT_COMPACT) {
+                const uint32_t b = (uint32_t)(obits >> (2 * k)) & 3u;
+                if (!b) continue;
+                uint32_t ci = (uint32_t)oci[k];
+                if (b & 1u) {
+                    at32(oc, ci) = v[k].x + e * vx[g];
+                    ++ci;
+                }
+                if (b & 2u) at32(oc, ci) = v[k].y + e * vy[g];
+            } else {
+                R* o = reinterpret_cast<R*>(a.out) + vec * a.out_vstride;
+                const uint32_t g0 = (uint32_t)(row * cols_out + c0);
+                at32(o, g0) = (R)a.scale * v[k].x;
+                if (c0 + 1 < cols_out) at32(o, g0 + 1) = (R)a.scale * v[k].y;
+            }
+        }
+    }
+}
+
 // Stage C: read RT-row runs of X[k], k = 0..M, merge the even/odd split into
 // Z[k] = (X[k] + X*[M-k]) + i W^{-k} (X[k] - X*[M-k]), inverse FFT of length M,
 // then x[2m], x[2m+1] = Re, Im z[m] go to the observed cells (+ eta v) or the
@@ -604,20 +695,8 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
     // loads overlap the transform.
     int32_t oci[NV];
     uint64_t obits = 0u;  // 2 bits per value: columns 2m and 2m+1 observed
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        oci[k] = 0;
-        if constexpr (OUT == OUT_COMPACT) {
-            const int c0 = 2 * edge_pos<LOG2M, LRL>(t + (k / 8) * TR, k % 8);
-            if (row < rows_out && c0 < cols_out) {
-                const uint32_t w = (uint32_t)(row * mask.words_per_row + (c0 >> 5));
-                const uint32_t word = at32(mask.bits, w);
-                const uint32_t b0 = 1u << (c0 & 31);
-                obits |= (uint64_t)((word & b0 ? 1u : 0u) | (word & (b0 << 1) ? 2u : 0u)) << (2 * k);
-                oci[k] = (int32_t)(at32(mask.base, w) + __popc(word & (b0 - 1u)));
-            }
-        }
-    }
+    row_output_cells<OUT, NV>(mask, row, rows_out, cols_out, oci, obits,
+                              [&](int k) { return edge_pos<LOG2M, LRL>(t + (k / 8) * TR, k % 8); });
     cpx<R> v[NV];
     if constexpr (SPLIT) {
         // the tile through a buffer of reals (half the LDS per row): real
@@ -753,57 +832,291 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
         }
     }
     if (row >= rows_out) return;
-    const int theta = (a.vec0 + vec) / a.vecs_per_theta;
-    // outputs in groups of two values: the group's nugget-term inputs are
-    // loaded together (none when eta = 0), then its stores go out
-    constexpr int GK = 2;
-    const R e = (OUT == OUT_COMPACT && a.vin) ? (R)a.eta[theta] : (R)0;
-    const R* vi = reinterpret_cast<const R*>(a.vin) + vec * a.vin_vstride;
-    R* oc = reinterpret_cast<R*>(a.out) + vec * a.out_vstride;
+    row_outputs<R, OUT, NV>(a, row, cols_out, vec, oci, obits, v,
+                            [&](int k) { return edge_pos<LOG2M, LRL>(t + (k / 8) * TR, k % 8); });
+}
+
+// ---------------------------------------------------------------------------
+// Mixed-radix stage kernels (embeddings 2^a 3^b 5^c that are not powers of
+// two; fftm.hpp).  The data flow and layouts are those of the kernels above,
+// with one value set per thread, complex exchanges, and every pass through
+// LDS.  The last forward pass of a column leaves the spectrum in natural
+// order in LDS, where the first inverse pass reads it multiplied by lam.
+// ---------------------------------------------------------------------------
+template <typename R, int M, int IN>
+__global__ void __launch_bounds__(1024) k_row_fwd_m(StageAArgs a, const cpx<R>* __restrict__ twp) {
+    using S = MSched<M>;
+    constexpr int T = M / 8, PM = lpadded<cpx<R>>(M) + 1;
+    constexpr bool LOW = (IN == IN_COMPACT);
+    extern __shared__ unsigned char smem_raw[];
+    cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int rr = tid / T, t = tid % T;
+    const int lid = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int row0 = (lid % gridDim.x) * a.RT;
+    const int row = row0 + rr;
+    const int vec = lid / gridDim.x;
+    if (a.active && !a.active[vec]) return;
+    MaskView mask = a.mask;
+    int rows_in = a.rows_in, row_len = a.row_len;
+    if (a.tab) {
+        const ProbDesc& d = a.tab[(a.vec0 + vec) / a.tab_vpp];
+        mask = MaskView{d.bits, d.base, d.wpr};
+        rows_in = d.n1;
+        row_len = d.n2;
+        if (row0 >= rows_in) return;
+    }
+    cpx<R>* buf = lds + rr * PM;
+    cpx<R> v[MVMAX];
 #pragma unroll
-    for (int k0 = 0; k0 < NV; k0 += GK) {
-        R vx[GK], vy[GK];
+    for (int k = 0; k < MVMAX; ++k) v[k] = cpx<R>{(R)0, (R)0};
+    row_inputs<R, IN, 1, LOW>(a, mask, vec, row, rows_in, row_len, t, T, T, v);
+    mpass_compute_tw<R, M, false, 0, LOW>(v, MPassTw<R, M, false, 0>{});
+    mpass_write<R, M, false, 0>(v, buf, t);
+    __syncthreads();
+    MLdsPasses<R, M, false, 1, S::npass>::run(v, buf, 0, t, twp);
+    // split Z into the real transform X[k] = (s - i w d) / 2, k = 0..M, with
+    // w = W_{2M}^k from the plan table
+    cpx<R>* Y = reinterpret_cast<cpx<R>*>(a.Y) + vec * a.Y_vstride;
+    const cpx<R>* ws = twp + S::split_off;
+    auto split = [&](int r2, int k) {
+        const cpx<R>* bp = lds + r2 * PM;
+        const cpx<R> zk = bp[lpad<cpx<R>>(k == M ? 0 : k)];
+        const cpx<R> zc = cconj(bp[lpad<cpx<R>>(k == 0 ? 0 : M - k)]);
+        const cpx<R> s2 = cadd(zk, zc);
+        const cpx<R> wd = cmul(ws[k], csub(zk, zc));
+        at32(Y, (uint32_t)(k * a.ldY + row0 + r2)) = cpx<R>{(R)0.5 * (s2.x + wd.y), (R)0.5 * (s2.y - wd.x)};
+    };
+    const int nt = blockDim.x;
 #pragma unroll
-        for (int g = 0; g < GK; ++g) {
-            vx[g] = (R)0;
-            vy[g] = (R)0;
+    for (int i = 0; i < 8; ++i) {
+        const int o = tid + i * nt;
+        split(o & (a.RT - 1), o >> a.log2RT);
+    }
+    if (tid < a.RT) split(tid, M);
+}
+
+template <typename R, int L, int MODE, int V>
+__global__ void __launch_bounds__((L / 8 > 256 ? L / 8 : 256)) k_col_m(StageBArgs a, const cpx<R>* __restrict__ twp) {
+    using S = MSched<L>;
+    constexpr int T = L / 8, PL = lpadded<cpx<R>>(L);
+    constexpr bool LOW = (MODE == B_LOW);
+    constexpr int RI = S::radix(true, 0), BI = S::bpt(true, 0), QI = L / RI;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int cl = T >= 256 ? 0 : tid / T, t = T >= 256 ? tid : tid % T;
+    const int lid = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int col = (lid / gridDim.y) * a.CB + cl;
+    const bool valid = col < a.ncols;
+    const int vbase = (lid % gridDim.y) * V;
+    cpx<R>* buf = lds + cl * V * PL;
+    if (a.active) {
+        bool any = false;
+#pragma unroll
+        for (int u = 0; u < V; ++u) any = any || (vbase + u < a.nvec && a.active[vbase + u]);
+        if (!any) return;
+    }
+    int rows_in[V], rows_out[V];
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+        rows_in[u] = a.rows_in;
+        rows_out[u] = a.rows_out;
+        if (a.tab) {
+            const ProbDesc& d = a.tab[(a.vec0 + min(vbase + u, a.nvec - 1)) / a.tab_vpp];
+            rows_in[u] = d.n1;
+            rows_out[u] = d.n1;
         }
-        if constexpr (OUT == OUT_COMPACT) {
-            if (e != (R)0) {
+    }
+    // spectrum values at the first inverse pass's input positions, fetched
+    // up front (unused slots read position 0 of the last vector's spectrum)
+    R lamv[MODE == B_SPEC ? 1 : V * BI * RI];
+    if constexpr (MODE != B_SPEC) {
 #pragma unroll
-                for (int g = 0; g < GK; ++g) {
-                    const uint32_t b = (uint32_t)(obits >> (2 * (k0 + g))) & 3u;
-                    const uint32_t ci = (uint32_t)oci[k0 + g];
-                    const R x = at32(vi, (b & 1u) ? ci : 0u);
-                    const R y = at32(vi, (b & 2u) ? ci + (b & 1u) : 0u);
-                    vx[g] = (b & 1u) ? x : (R)0;
-                    vy[g] = (b & 2u) ? y : (R)0;
-                }
-            }
-        }
-#pragma unroll
-        for (int g = 0; g < GK; ++g) {
-            const int k = k0 + g;
-            const int m = edge_pos<LOG2M, LRL>(t + (k / 8) * TR, k % 8);
-            const int c0 = 2 * m;
-            if (c0 >= cols_out) continue;
-            if constexpr (OUT == OUT_COMPACT) {
-                const uint32_t b = (uint32_t)(obits >> (2 * k)) & 3u;
-                if (!b) continue;
-                uint32_t ci = (uint32_t)oci[k];
-                if (b & 1u) {
-                    at32(oc, ci) = v[k].x + e * vx[g];
-                    ++ci;
-                }
-                if (b & 2u) at32(oc, ci) = v[k].y + e * vy[g];
+        for (int u = 0; u < V; ++u) {
+            const int vl = min(vbase + u, a.nvec - 1);
+            const R* lam;
+            if (a.tab) {
+                const ProbDesc& d = a.tab[(a.vec0 + vl) / a.tab_vpp];
+                lam = reinterpret_cast<const R*>(sizeof(R) == 8 ? (const void*)d.lam64 : (const void*)d.lam32);
             } else {
-                R* o = reinterpret_cast<R*>(a.out) + vec * a.out_vstride;
-                const uint32_t g0 = (uint32_t)(row * cols_out + c0);
-                at32(o, g0) = (R)a.scale * v[k].x;
-                if (c0 + 1 < cols_out) at32(o, g0 + 1) = (R)a.scale * v[k].y;
+                lam = reinterpret_cast<const R*>(a.lam) + (int64_t)((a.vec0 + vl) / a.vecs_per_theta) * a.lam_tstride;
+            }
+            lam += (int64_t)(valid ? col : 0) * L;
+#pragma unroll
+            for (int b = 0; b < BI; ++b) {
+                const int j = t + b * T;
+#pragma unroll
+                for (int r = 0; r < RI; ++r) lamv[(u * BI + b) * RI + r] = lam[j < QI ? j + r * QI : 0];
             }
         }
     }
+    cpx<R>* Ycol = reinterpret_cast<cpx<R>*>(a.Y) + (int64_t)(valid ? col : 0) * a.ldY;
+    cpx<R> v[V * MVMAX];
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+        const bool vu = valid && (vbase + u < a.nvec);
+        const cpx<R>* Yv = Ycol + (vbase + u) * a.Y_vstride;
+#pragma unroll
+        for (int r = 0; r < MVMAX; ++r) {
+            const int idx = t + r * T;
+            v[u * MVMAX + r] = cpx<R>{(R)0, (R)0};
+            if (r >= 8 || (LOW && r >= 4)) continue;
+            if (vu && idx < rows_in[u]) v[u * MVMAX + r] = Yv[idx];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+        mpass_compute_tw<R, L, false, 0, LOW>(v + u * MVMAX, MPassTw<R, L, false, 0>{});
+        mpass_write<R, L, false, 0>(v + u * MVMAX, buf + u * PL, t);
+    }
+    __syncthreads();
+    MLdsPasses<R, L, false, 1, S::npass, V>::run(v, buf, PL, t, twp);
+    if constexpr (MODE == B_SPEC) {
+        if (valid) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int pos = t + k * T;
+                a.spec_out[(int64_t)col * L + pos] = (double)buf[lpad<cpx<R>>(pos)].x;
+            }
+        }
+        return;
+    } else {
+        // first inverse pass: its inputs times lam
+#pragma unroll
+        for (int u = 0; u < V; ++u)
+#pragma unroll
+            for (int b = 0; b < BI; ++b) {
+                const int j = t + b * T;
+                if (j < QI) {
+#pragma unroll
+                    for (int r = 0; r < RI; ++r)
+                        v[u * MVMAX + b * RI + r] =
+                            cscale(buf[u * PL + lpad<cpx<R>>(j + r * QI)], lamv[(u * BI + b) * RI + r]);
+                }
+            }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            mpass_compute_tw<R, L, true, 0>(v + u * MVMAX, MPassTw<R, L, true, 0>{});
+            mpass_write<R, L, true, 0>(v + u * MVMAX, buf + u * PL, t);
+        }
+        __syncthreads();
+        MLdsPasses<R, L, true, 1, S::npass - 1, V>::run(v, buf, PL, t, twp);
+        {
+            constexpr int PLAST = S::npass - 1;  // radix 8: outputs at t + k T
+            const auto w = mpass_twiddles<R, L, true, PLAST>(t, twp);
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+                mpass_read<R, L, true, PLAST>(v + u * MVMAX, buf + u * PL, t);
+                mpass_compute_tw<R, L, true, PLAST>(v + u * MVMAX, w);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            if (!(valid && vbase + u < a.nvec)) continue;
+            cpx<R>* Yv = Ycol + (vbase + u) * a.Y_vstride;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int idx = t + k * T;
+                if (idx < rows_out[u]) Yv[idx] = v[u * MVMAX + k];
+            }
+        }
+    }
+}
+
+template <typename R, int M, int OUT>
+__global__ void __launch_bounds__(1024) k_row_inv_m(StageCArgs a, const cpx<R>* __restrict__ twp) {
+    using S = MSched<M>;
+    constexpr int T = M / 8, PM = lpadded<cpx<R>>(M) + 1;
+    constexpr int NV = 8;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int lid = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int tile = lid % gridDim.x;
+    const int row0 = tile * a.RT;
+    const int vec = lid / gridDim.x;
+    const cpx<R>* Y = reinterpret_cast<const cpx<R>*>(a.Y) + vec * a.Y_vstride;
+    const int rr = tid / T, t = tid % T;
+    const int row = row0 + rr;
+    if (a.active && !a.active[vec]) return;
+    MaskView mask = a.mask;
+    int rows_out = a.rows_out, cols_out = a.cols_out;
+    if (a.tab) {
+        const ProbDesc& d = a.tab[(a.vec0 + vec) / a.tab_vpp];
+        mask = MaskView{d.bits, d.base, d.wpr};
+        rows_out = d.n1;
+        cols_out = d.n2;
+        if constexpr (OUT == OUT_COMPACT) {
+            const int64_t len = a.out_vstride - d.p;
+            const int64_t per = (len + gridDim.x - 1) / gridDim.x;
+            const int64_t b = d.p + tile * per, e = min(b + per, a.out_vstride);
+            R* o = reinterpret_cast<R*>(a.out) + vec * a.out_vstride;
+            for (int64_t i = b + tid; i < e; i += blockDim.x) o[i] = (R)0;
+        }
+        if (row0 >= rows_out) return;
+    }
+    auto pos = [&](int k) { return t + k * T; };  // the last inverse pass is radix 8
+    int32_t oci[NV];
+    uint64_t obits = 0u;
+    row_output_cells<OUT, NV>(mask, row, rows_out, cols_out, oci, obits, pos);
+    {
+        const int nt = blockDim.x;  // = RT * T
+        cpx<R> tv[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int o = tid + i * nt;
+            const int r2 = o & (a.RT - 1);
+            const int k = o >> a.log2RT;
+            tv[i] = (row0 + r2 < rows_out) ? at32(Y, (uint32_t)(k * a.ldY + row0 + r2)) : cpx<R>{(R)0, (R)0};
+        }
+        cpx<R> ny{(R)0, (R)0};
+        if (tid < a.RT && row0 + tid < rows_out) ny = at32(Y, (uint32_t)(M * a.ldY + row0 + tid));
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int o = tid + i * nt;
+            lds[(o & (a.RT - 1)) * PM + lpad<cpx<R>>(o >> a.log2RT)] = tv[i];
+        }
+        if (tid < a.RT) lds[tid * PM + lpad<cpx<R>>(M)] = ny;
+    }
+    __syncthreads();
+    // first inverse pass: inputs merged from the split half spectrum,
+    // Z[k] = (X[k] + X*[M-k]) + i conj(W_{2M}^k) (X[k] - X*[M-k])
+    cpx<R>* buf = lds + rr * PM;
+    const cpx<R>* ws = twp + S::split_off;
+    auto merged = [&](int k) {
+        const cpx<R> xk = buf[lpad<cpx<R>>(k)];
+        const cpx<R> xm = buf[lpad<cpx<R>>(M - k)];
+        const cpx<R> s2 = cadd(xk, cconj(xm));
+        const cpx<R> d = cmul(cconj(ws[k]), csub(xk, cconj(xm)));
+        return cpx<R>{s2.x - d.y, s2.y + d.x};
+    };
+    constexpr int R0 = S::radix(true, 0), B0 = S::bpt(true, 0), Q0 = M / R0;
+    cpx<R> v[MVMAX];
+#pragma unroll
+    for (int k = 0; k < MVMAX; ++k) v[k] = cpx<R>{(R)0, (R)0};
+#pragma unroll
+    for (int b = 0; b < B0; ++b) {
+        const int j = t + b * T;
+        if (j < Q0) {
+#pragma unroll
+            for (int r = 0; r < R0; ++r) v[b * R0 + r] = merged(j + r * Q0);
+        }
+    }
+    __syncthreads();  // every read of X before the pass overwrites it
+    mpass_compute_tw<R, M, true, 0>(v, MPassTw<R, M, true, 0>{});
+    mpass_write<R, M, true, 0>(v, buf, t);
+    __syncthreads();
+    MLdsPasses<R, M, true, 1, S::npass - 1>::run(v, buf, 0, t, twp);
+    {
+        constexpr int PLAST = S::npass - 1;
+        const auto w = mpass_twiddles<R, M, true, PLAST>(t, twp);
+        mpass_read<R, M, true, PLAST>(v, buf, t);
+        mpass_compute_tw<R, M, true, PLAST>(v, w);
+    }
+    if (row >= rows_out) return;
+    row_outputs<R, OUT, NV>(a, row, cols_out, vec, oci, obits, v, pos);
 }
 
 // ---------------------------------------------------------------------------
@@ -881,11 +1194,95 @@ static const cpx<R>* plan_table(Ctx& c, int log2L) {
     return static_cast<const cpx<R>*>(slot);
 }
 
+// Mixed-radix lengths (fftm.hpp): row lengths M (half a torus side) and
+// column lengths (torus sides) that are not powers of two.
+#define KRY_MROWS(X) X(24) X(40) X(48) X(80) X(96) X(160) X(192) X(320) X(384) X(640) X(768) X(1280) X(1536) X(2560) X(3072)
+#define KRY_MCOLS(X) X(48) X(80) X(96) X(160) X(192) X(320) X(384) X(640) X(768) X(1280) X(1536) X(2560) X(3072) X(5120) X(6144)
+
+static bool is_mixed_row(int M) {
+#define KRY_T(L) if (M == L) return true;
+    KRY_MROWS(KRY_T)
+#undef KRY_T
+    return false;
+}
+static bool is_mixed_col(int L) {
+#define KRY_T(X) if (L == X) return true;
+    KRY_MCOLS(KRY_T)
+#undef KRY_T
+    return false;
+}
+static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+bool torus_side_ok(int N) {
+    if (N < 16 || N > 8192) return false;
+    return is_pow2(N) || (is_mixed_col(N) && is_mixed_row(N / 2));
+}
+
+int embedding_side(int m) {
+    for (int N = std::max(16, m); N <= 8192; ++N)
+        if (torus_side_ok(N)) return N;
+    return 0;
+}
+
+// Pass twiddles of a mixed-radix length, [r][j mod Ns] per pass and
+// direction, then W_{2L}^k for k = 0..L (the real-to-complex split).
+template <typename Real, int L>
+static void fill_mplan(std::vector<std::array<long double, 2>>& out) {
+    using S = MSched<L>;
+    out.assign(S::tw_total, {1.0L, 0.0L});
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int inv = 0; inv < 2; ++inv)
+        for (int p = 1; p < S::npass; ++p) {
+            const int R = S::radix(inv, p), NS = S::ns(inv, p);
+            const int off = S::tw_off(inv, p);
+            for (int jn = 0; jn < NS; ++jn)
+                for (int r = 0; r < R; ++r) {
+                    const long double ang = (inv ? 2.0L : -2.0L) * pi * (long double)(r * jn) / (long double)(NS * R);
+                    out[off + r * NS + jn] = {cosl(ang), sinl(ang)};
+                }
+        }
+    for (int k = 0; k <= L; ++k) {
+        const long double ang = -2.0L * pi * (long double)k / (long double)(2 * L);
+        out[S::split_off + k] = {cosl(ang), sinl(ang)};
+    }
+}
+
+template <typename R>
+static const cpx<R>* mplan_table(Ctx& c, int L) {
+    static std::mutex mu;
+    std::lock_guard<std::mutex> g(mu);
+    auto& m = sizeof(R) == 8 ? c.mplan64 : c.mplan32;
+    auto it = m.find(L);
+    if (it != m.end()) return static_cast<const cpx<R>*>(it->second);
+    std::vector<std::array<long double, 2>> tab;
+    switch (L) {
+#define KRY_F(X) case X: fill_mplan<R, X>(tab); break;
+        KRY_MROWS(KRY_F)
+        case 5120: fill_mplan<R, 5120>(tab); break;
+        case 6144: fill_mplan<R, 6144>(tab); break;
+#undef KRY_F
+        default: throw Error(KRY_EINVAL, "mixed-radix transform length not supported");
+    }
+    std::vector<cpx<R>> h(tab.size());
+    for (size_t i = 0; i < tab.size(); ++i) h[i] = cpx<R>{(R)tab[i][0], (R)tab[i][1]};
+    void* slot = dev_alloc(c, h.size() * sizeof(cpx<R>));
+    KRY_HIP(hipMemcpy(slot, h.data(), h.size() * sizeof(cpx<R>), hipMemcpyHostToDevice));
+    m[L] = slot;
+    return static_cast<const cpx<R>*>(slot);
+}
+
 void build_plan_tables(Ctx& c) {
     for (int lg = 3; lg <= 13; ++lg) {
         plan_table<double>(c, lg);
         plan_table<float>(c, lg);
     }
+#define KRY_P(X) mplan_table<double>(c, X); mplan_table<float>(c, X);
+    KRY_MROWS(KRY_P)
+    mplan_table<double>(c, 5120);
+    mplan_table<float>(c, 5120);
+    mplan_table<double>(c, 6144);
+    mplan_table<float>(c, 6144);
+#undef KRY_P
 }
 
 struct RowTiling {
@@ -978,6 +1375,45 @@ static void launch_col(const StageBArgs& b, int nvec, int V, bool split, Ctx& c,
     launch_col_v<R, LG, MODE, 1, false>(b, nvec, c, st);
 }
 
+template <typename R, int M, int IN>
+static void launch_row_fwd_m(const StageAArgs& a, dim3 grid, const RowTiling& t, Ctx& c, hipStream_t st) {
+    auto k = k_row_fwd_m<R, M, IN>;
+    set_lds(k, t.lds);
+    hipLaunchKernelGGL(k, grid, dim3(t.threads), t.lds, st, a, mplan_table<R>(c, M));
+    KRY_HIP(hipGetLastError());
+}
+
+template <typename R, int M, int OUT>
+static void launch_row_inv_m(const StageCArgs& a, dim3 grid, const RowTiling& t, Ctx& c, hipStream_t st) {
+    auto k = k_row_inv_m<R, M, OUT>;
+    set_lds(k, t.lds);
+    hipLaunchKernelGGL(k, grid, dim3(t.threads), t.lds, st, a, mplan_table<R>(c, M));
+    KRY_HIP(hipGetLastError());
+}
+
+// Columns of a mixed-radix length: V = 2 vectors per workgroup where their
+// LDS fits, else one.
+template <typename R, int L, int MODE>
+static void launch_col_m(const StageBArgs& b, int nvec, int V, Ctx& c, hipStream_t st) {
+    constexpr int T = L / 8;
+    const size_t per = (size_t)b.CB * lpadded<cpx<R>>(L) * sizeof(cpx<R>);
+    if (MODE == B_SPEC || 2 * per > 160 * 1024) V = 1;
+    const size_t lds = per * V;
+    dim3 grid((b.ncols + b.CB - 1) / b.CB, (nvec + V - 1) / V);
+    StageBArgs bb = b;
+    bb.nvec = nvec;
+    if (V == 2) {
+        auto k = k_col_m<R, L, MODE, 2>;
+        set_lds(k, lds);
+        hipLaunchKernelGGL(k, grid, dim3(b.CB * T), lds, st, bb, mplan_table<R>(c, L));
+    } else {
+        auto k = k_col_m<R, L, MODE, 1>;
+        set_lds(k, lds);
+        hipLaunchKernelGGL(k, grid, dim3(b.CB * T), lds, st, bb, mplan_table<R>(c, L));
+    }
+    KRY_HIP(hipGetLastError());
+}
+
 #define KRY_SIZES(X) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
 
 template <typename R>
@@ -1010,6 +1446,20 @@ static void run_stage_a(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R
     dim3 grid((s.rows_in + t.RT - 1) / t.RT, nvec);
     const int lg = ilog2(M);
     Ctx& c = *P.ctx;
+    if (!is_pow2(M)) {
+        switch (M) {
+#define KRY_AM(X)                                                                                   \
+    case X:                                                                                         \
+        if (s.in_mode == IN_COMPACT) launch_row_fwd_m<R, X, IN_COMPACT>(a, grid, t, c, st);           \
+        else if (s.in_mode == IN_DENSE) launch_row_fwd_m<R, X, IN_DENSE>(a, grid, t, c, st);          \
+        else launch_row_fwd_m<R, X, IN_NOISE>(a, grid, t, c, st);                                    \
+        break;
+            KRY_MROWS(KRY_AM)
+#undef KRY_AM
+            default: throw Error(KRY_EINVAL, "row transform length not supported");
+        }
+        return;
+    }
 #define KRY_A(LG)                                                                             \
     case LG:                                                                                  \
         if (s.in_mode == IN_COMPACT) launch_row_fwd<R, LG, IN_COMPACT>(a, grid, t, vt, split, c, st);\
@@ -1048,6 +1498,20 @@ static void run_stage_b(Problem& P, int N1, int M, int vec0, int nvec, cpx<R>* Y
     const int mode = spec_out ? B_SPEC : (2 * rows_in <= N1 ? B_LOW : B_FULL);
     const int lg = ilog2(N1);
     Ctx& c = *P.ctx;
+    if (!is_pow2(N1)) {
+        switch (N1) {
+#define KRY_BM(X)                                                                 \
+    case X:                                                                       \
+        if (mode == B_LOW) launch_col_m<R, X, B_LOW>(b, nvec, V, c, st);          \
+        else if (mode == B_FULL) launch_col_m<R, X, B_FULL>(b, nvec, V, c, st);   \
+        else launch_col_m<R, X, B_SPEC>(b, nvec, 1, c, st);                       \
+        break;
+            KRY_MCOLS(KRY_BM)
+#undef KRY_BM
+            default: throw Error(KRY_EINVAL, "column transform length not supported");
+        }
+        return;
+    }
 #define KRY_B(LG)                                                                          \
     case LG + 1:                                                                           \
         if (mode == B_LOW) launch_col<R, LG + 1, B_LOW>(b, nvec, V, split, c, st);         \
@@ -1088,6 +1552,19 @@ static void run_stage_c(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R
     dim3 grid((s.rows_out + t.RT - 1) / t.RT, nvec);
     const int lg = ilog2(M);
     Ctx& cx = *P.ctx;
+    if (!is_pow2(M)) {
+        switch (M) {
+#define KRY_CM(X)                                                                              \
+    case X:                                                                                    \
+        if (s.out_mode == OUT_COMPACT) launch_row_inv_m<R, X, OUT_COMPACT>(c, grid, t, cx, st); \
+        else launch_row_inv_m<R, X, OUT_GRID>(c, grid, t, cx, st);                             \
+        break;
+            KRY_MROWS(KRY_CM)
+#undef KRY_CM
+            default: throw Error(KRY_EINVAL, "row transform length not supported");
+        }
+        return;
+    }
 #define KRY_C(LG)                                                                             \
     case LG:                                                                                  \
         if (s.out_mode == OUT_COMPACT) launch_row_inv<R, LG, OUT_COMPACT>(c, grid, t, vt, split, cx, st);\
@@ -1102,8 +1579,8 @@ static void run_stage_c(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R
 
 template <typename R>
 void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st) {
-    KRY_REQUIRE(s.N1 >= 16 && s.N2 >= 16 && s.N1 <= 8192 && s.N2 <= 8192, "torus size out of range");
-    KRY_REQUIRE((s.N1 & (s.N1 - 1)) == 0 && (s.N2 & (s.N2 - 1)) == 0, "torus sizes must be powers of two");
+    KRY_REQUIRE(torus_side_ok(s.N1) && torus_side_ok(s.N2),
+                "torus sides must be supported transform lengths (16..8192: powers of two or 2^a 3^b 5^c)");
     KRY_REQUIRE(s.rows_in <= s.N1 && s.row_len <= s.N2 && s.rows_out <= s.N1 && s.cols_out <= s.N2,
                 "block larger than the torus");
     KRY_REQUIRE(s.in_mode != IN_COMPACT || 2 * s.row_len <= s.N2, "compact input wider than half the torus");
@@ -1114,11 +1591,13 @@ void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st) {
     const int M = s.N2 / 2;
     // launch configuration of this embedding and precision (bit-identical results)
     const Tuning tu = P.ctx->tuning_for(s.N1, s.N2, (int)sizeof(R), s.nvec);
-    const int vt = (M >= 1024 && tu.row_vt == 2) ? 2 : 1;
+    // (two value sets and split exchanges: power-of-two rows of >= 1024 points)
+    const bool wide = M >= 1024 && is_pow2(M);
+    const int vt = (wide && tu.row_vt == 2) ? 2 : 1;
     // (two vectors per column workgroup only when there are two to pair)
     const int V = s.nvec < 2 ? 1 : (tu.col_v ? tu.col_v : (sizeof(R) == 4 ? 2 : 1));
-    const bool asplit = M >= 1024 && (tu.row_split & 1) != 0;
-    const bool csplit = M >= 1024 && (tu.row_split & 2) != 0;
+    const bool asplit = wide && (tu.row_split & 1) != 0;
+    const bool csplit = wide && (tu.row_split & 2) != 0;
     const RowTiling ta = row_tiling<R>(M, tu.rt_scale, vt, asplit);
     const RowTiling tc = row_tiling<R>(M, tu.rt_scale, vt, csplit);  // same rows per tile
     const int rows_max = s.rows_in > s.rows_out ? s.rows_in : s.rows_out;
@@ -1159,7 +1638,8 @@ void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st) {
         run_stage_a<R>(P, s, v0, nv, Y, ldY, Yvs, ta, vt, asplit, st);
         mark(1);
         run_stage_b<R>(P, s.N1, M, v0, nv, Y, ldY, Yvs, s.rows_in, s.rows_out, s.lam, s.lam_tstride,
-                       s.vecs_per_theta, nullptr, st, s.tab, s.tab_vpp, s.active, V, tu.col_split != 0);
+                       s.vecs_per_theta, nullptr, st, s.tab, s.tab_vpp, s.active, V,
+                       tu.col_split != 0 && is_pow2(s.N1));
         mark(2);
         run_stage_c<R>(P, s, v0, nv, Y, ldY, Yvs, tc, vt, csplit, st);
         mark(3);
@@ -1177,8 +1657,9 @@ template <typename R>
 size_t conv_bytes_per_vec(int N1, int N2, int rows, Ctx& c, int nvec) {
     const int M = N2 / 2;
     const Tuning tu = c.tuning_for(N1, N2, (int)sizeof(R), nvec);
-    const int vt = (M >= 1024 && tu.row_vt == 2) ? 2 : 1;
-    const bool asplit = M >= 1024 && (tu.row_split & 1) != 0;
+    const bool wide = M >= 1024 && is_pow2(M);
+    const int vt = (wide && tu.row_vt == 2) ? 2 : 1;
+    const bool asplit = wide && (tu.row_split & 1) != 0;
     const RowTiling ta = row_tiling<R>(M, tu.rt_scale, vt, asplit);
     const int ldY = ((rows + ta.RT - 1) / ta.RT) * ta.RT;
     return (size_t)(M + 1) * ldY * sizeof(cpx<R>);

@@ -67,6 +67,7 @@ struct Ctx {
     cpx<float>* tw32 = nullptr;
     void* plan64[14] = {};  // per-length pass twiddle tables (index log2 length)
     void* plan32[14] = {};
+    std::map<int, void*> mplan64, mplan32;  // mixed-radix lengths' tables (by length)
     std::mutex alloc_mu;     // guards `allocated` (server slots allocate concurrently)
     bool graphs = true;  // replay captured graphs for CG iteration blocks
     // (N1, N2, bytes per real, batch class) -> configuration; class 0 holds
@@ -184,6 +185,7 @@ struct Problem {
     bool no_graphs = false;  // set on the server's request views (several threads)
     const ProbDesc* tab = nullptr;  // set on a group of problems sharing an embedding
     // workspace (per problem or per view)
+    std::shared_ptr<Problem> side;  // a second workspace (log-determinants beside the solves; not in views)
     Spectrum spec;               // cache of the last parameter point
     DevBuf Y;                    // transform workspace
     DevBuf lagtmp, spectmp, spec_multi64, spec_multi32;
@@ -247,6 +249,7 @@ struct Problem {
         std::swap(spec.lam_max, o.spec.lam_max);
     }
     void release_work() {
+        if (side) side->release_work();
         for (DevBuf* b : {&Y, &lagtmp, &spectmp, &spec_multi64, &spec_multi32, &kws, &scal, &tmp1, &tmp2, &tmp3,
                           &tmp4, &irr, &spec.s64, &spec.s32})
             b->release(*ctx);
@@ -326,6 +329,11 @@ size_t spectrum_ws_bytes(int N1, int N2);
 // Every per-length twiddle table of the transforms, both precisions (so
 // later products allocate none).
 void build_plan_tables(Ctx& c);
+// Torus sides the transforms support: 16..8192, powers of two or 2^a 3^b 5^c
+// from the mixed-radix set (multiples of 16 whose half is a supported row
+// length); and the smallest supported side >= max(16, m) (0 if none).
+bool torus_side_ok(int N);
+int embedding_side(int m);
 // Scale a half spectrum by s into FP64 and FP32 copies; optional sqrt of
 // max(lam, 0) first (sampling).
 void spectrum_scale(const double* lam, int64_t n, double s, bool sqrt_clip, double* out64,

@@ -28,20 +28,40 @@ def test_config4_recipe_fit_and_all_cell_kriging():
         init = K.theta(sigma2=1.0, tau2=0.2, range=0.08, nu=1.0, aniso_ratio=2.0, aniso_angle=ang)
         fits = {}
         for prec in (K.KRY_FP32, K.KRY_FP64):
-            opts = K.kry_opts_default(lanczos_steps=50, num_probes=20, precision=prec, reorth=1, cg_rtol=1e-8,
+            # 256 Lanczos steps: 50 leave the quadrature far from converged
+            # here and bias the fit (the adaptive rule settles after 135-200);
+            # a fixed count, reorthogonalised, gives both precisions the same
+            # truncation
+            opts = K.kry_opts_default(lanczos_steps=256, num_probes=20, precision=prec, reorth=1, cg_rtol=1e-8,
                                       seed=303)
             print("fit, precision", prec, flush=True)
             est, at = K.kry_fit(P.h, init, 3, opts, xtol=1e-3, maxiter=200)
             fits[prec] = (np.log(est.range), np.log(est.tau2 / est.sigma2), at, est)
         lr32, le32, a32, est = fits[K.KRY_FP32]
         lr64, le64, a64, _ = fits[K.KRY_FP64]
-        assert abs(lr32 - lr64) < 5e-3 and abs(le32 - le64) < 5e-3, (lr32, lr64, le32, le64)
+        # The profile likelihood is flat along a range-nugget ridge here, so
+        # FP32's 1e-7 relative change of l_p moves the maximiser by ~5e-3 in
+        # log space.  The FP32 estimate must be as good as the FP64 one for
+        # the FP64 objective (within 0.5 in l_p, well inside the statistical
+        # uncertainty), and close in log space.
+        assert abs(lr32 - lr64) < 2e-2 and abs(le32 - le64) < 2e-2, (lr32, lr64, le32, le64)
         assert abs(a32["loglik_profiled"] - a64["loglik_profiled"]) <= 1e-3 * abs(a64["loglik_profiled"])
+        o64 = K.kry_opts_default(lanczos_steps=256, num_probes=20, precision=K.KRY_FP64, reorth=1, cg_rtol=1e-8,
+                                 seed=303)
+        at32 = K.kry_loglik(P.h, K.theta(sigma2=1.0, tau2=float(np.exp(le32)), range=float(np.exp(lr32)), nu=1.0,
+                                         aniso_ratio=2.0, aniso_angle=ang), o64)
+        at64 = K.kry_loglik(P.h, K.theta(sigma2=1.0, tau2=float(np.exp(le64)), range=float(np.exp(lr64)), nu=1.0,
+                                         aniso_ratio=2.0, aniso_angle=ang), o64)
+        assert at64["loglik_profiled"] - at32["loglik_profiled"] < 0.5, (at64["loglik_profiled"],
+                                                                         at32["loglik_profiled"])
         # the fit is a maximum of the likelihood it evaluates: at least as high
         # as at the true parameters, with the same probes
-        tru = K.kry_loglik(P.h, truth, K.kry_opts_default(lanczos_steps=50, num_probes=20, precision=K.KRY_FP64,
+        tru = K.kry_loglik(P.h, truth, K.kry_opts_default(lanczos_steps=256, num_probes=20, precision=K.KRY_FP64,
                                                             reorth=1, cg_rtol=1e-8, seed=303))
         assert a64["loglik_profiled"] >= tru["loglik_profiled"] - 1e-6 * abs(tru["loglik_profiled"])
+        # with converged quadrature the estimates land near the truth (about
+        # 157k observations)
+        assert abs(lr64 - np.log(0.05)) < 0.15 and abs(le64 - np.log(0.1)) < 0.3, (np.exp(lr64), np.exp(le64))
         # every missing cell: means and bootstrap variances (B = 20)
         miss = np.flatnonzero(mask.ravel() == 0)
         kopts = K.kry_opts_default(precision=K.KRY_FP32, cg_rtol=1e-8, seed=404)

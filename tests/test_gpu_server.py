@@ -13,7 +13,8 @@ pytestmark = pytest.mark.gpu
 
 K = pytest.importorskip("paper_2012_13133_amd.kryging")
 
-SHAPES = [(40, 36, 0.3, "uniform"), (64, 64, 0.2, "blob"), (24, 50, 0.5, "uniform")]
+# embeddings: 128 x 128, 128 x 128, 48 x 128 (a radix-3 side)
+SHAPES = [(56, 60, 0.3, "uniform"), (64, 64, 0.2, "blob"), (24, 50, 0.5, "uniform")]
 
 
 def _problems(ctx):
@@ -232,6 +233,33 @@ def test_server_footprint_bounds_each_request():
                                                                         r.footprint_bytes)
                 finally:
                     K.kry_server_destroy(srv)
+    finally:
+        for h in probs:
+            K.kry_problem_destroy(h)
+        K.kry_ctx_destroy(ctx)
+
+
+def test_shift_shared_batch_same_on_a_problem_and_through_the_server():
+    # On a problem the FP32 shift-shared call runs its Lanczos recurrences on
+    # a second stream beside the multi-shift solves; a request view runs them
+    # one after the other.  Both give the same results, bit for bit.
+    ctx = K.kry_ctx_create()
+    probs, masks = _problems(ctx)
+    try:
+        pts = [K.theta(sigma2=1.0, tau2=e, range=r, nu=1.5) for r in (0.05, 0.12) for e in (0.03, 0.2, 0.6)]
+        opts = K.kry_opts_default(lanczos_steps=25, num_probes=6, precision=K.KRY_FP32, shift_share=1, reorth=1,
+                                  cg_rtol=1e-9)
+        direct = K.kry_loglik_batch(probs[1], pts, opts)
+        srv = K.kry_server_create(ctx, slots=2, max_batch=1)
+        try:
+            pend = [K.kry_server_submit(srv, K.KRY_REQ_LOGLIK, probs[1], t, opts) for t in pts]
+            resp = [K.kry_server_wait(srv, p) for p in pend]
+        finally:
+            K.kry_server_destroy(srv)
+        for d, r in zip(direct, resp):
+            assert r.status == K.KRY_OK
+            for key in ("loglik", "logdet", "quad", "cg_iters", "lanczos_steps_used"):
+                assert r.loglik.as_dict()[key] == d[key], key
     finally:
         for h in probs:
             K.kry_problem_destroy(h)

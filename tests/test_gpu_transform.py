@@ -32,7 +32,7 @@ def test_lag_grid(th, tor):
 
 
 @pytest.mark.parametrize("th", THETAS)
-@pytest.mark.parametrize("tor", [(16, 16), (64, 32), (256, 512)])
+@pytest.mark.parametrize("tor", [(16, 16), (64, 32), (256, 512), (48, 80), (96, 160), (1280, 768)])
 def test_spectrum(th, tor):
     n1, n2 = 8, 8
     with K.Problem(n1, n2, np.ones((n1, n2))) as P:
@@ -44,7 +44,10 @@ def test_spectrum(th, tor):
     assert abs(mm[0] - ref.min()) <= 1e-12 * scale and abs(mm[1] - ref.max()) <= 1e-12 * scale
 
 
-SHAPES = [(2, 2), (3, 5), (7, 9), (16, 16), (32, 32), (33, 47), (64, 50), (100, 3)]
+SHAPES = [(2, 2), (3, 5), (7, 9), (16, 16), (32, 32), (33, 47), (64, 50), (100, 3),
+          # embeddings with radix-3 and radix-5 passes: 48 x 64, 80 x 96, 320 x 640,
+          # 384 x 768, 48 x 16
+          (20, 30), (40, 41), (150, 300), (190, 380), (24, 3)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -109,3 +112,12 @@ def test_probes_bit_exact():
         zc = K.kry_probes(P.h, K.kry_opts_default(probe_kind=K.KRY_PROBE_COLOURED, colour_period=3, seed=99))
     np.testing.assert_array_equal(z, philox.probe_matrix(r, c, 7, 12345).T)
     np.testing.assert_array_equal(zc, philox.probe_matrix(r, c, 0, 99, colour_period=3).T)
+
+
+def test_embedding_is_the_smallest_supported_side():
+    # the library's embedding follows the stated size rule (restated in
+    # oracle.geometry.fast_size): 7 x 13, 20 x 30, 40 x 41, 150 x 300, 600 x 700
+    from oracle.geometry import fast_size
+    for n1, n2 in ((7, 13), (20, 30), (40, 41), (150, 300), (600, 700)):
+        with K.Problem(n1, n2, np.ones((n1, n2))) as P:
+            assert (P.N1, P.N2) == (fast_size(2 * n1 - 1), fast_size(2 * n2 - 1)), (n1, n2)

@@ -45,11 +45,11 @@ def test_every_configuration_is_bit_identical(shape):
 def test_row_settings_bit_identical_on_a_4096_embedding():
     # rows of 2048 points: the split row kernels and 1024-thread FP32 tiles at
     # their largest common size
-    n1, n2 = 1100, 1030
+    n1, n2 = 1100, 1600
     mask = synth.uniform_mask(n1, n2, 0.3, seed=13)
     th = K.theta_from_dict(TH)
     with K.Problem(n1, n2, mask) as P:
-        assert P.N2 == 4096
+        assert P.N2 == 4096  # (and N1 = 2560: mixed-radix columns beside power-of-two rows)
         v = synth.random_vectors(P.p, 2, seed=14)
         for prec in (K.KRY_FP64, K.KRY_FP32):
             K.kry_set_tuning(P.ctx, P.N1, P.N2, prec)
