@@ -69,7 +69,7 @@ def parse():
     ap.add_argument("--c4-probes", type=int, default=8)
     ap.add_argument("--c4-steps", type=int, default=50)
     ap.add_argument("--c4-lanczos-rtol", type=float, default=1e-5)
-    ap.add_argument("--c4-lanczos-max", type=int, default=512)
+    ap.add_argument("--c4-lanczos-max", type=int, default=1024)
     ap.add_argument("--c4-cg-rtol", type=float, default=1e-7)
     ap.add_argument("--c4-maxiter", type=int, default=20)
     ap.add_argument("--c4-xtol", type=float, default=1e-2)

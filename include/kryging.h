@@ -83,7 +83,7 @@ typedef enum { KRY_SOLVER_CG = 0, KRY_SOLVER_GENGK = 1 } kry_solver;
  * vectors in FP32; dot products, Lanczos coefficients, quadrature, CG
  * scalars and the likelihood in FP64, with FP64 residual refinement in CG. */
 typedef struct {
-    int32_t lanczos_steps;   /* m, Lanczos steps per probe (>= 1)           */
+    int32_t lanczos_steps;   /* m, Lanczos steps per probe (1..1024)        */
     int32_t num_probes;      /* N, Rademacher probes (ignored if coloured)  */
     int32_t probe_kind;      /* kry_probe_kind                              */
     int32_t colour_period;   /* c for coloured probes (c*c probes)          */
@@ -96,7 +96,7 @@ typedef struct {
     int32_t gk_steps;        /* k for genGK                                 */
     int32_t shift_share;     /* 1 = points of one call that differ only in
                                 the nugget ratio share Krylov spaces (below) */
-    int32_t lanczos_max_steps; /* adaptive mode: cap on the steps (10..512)  */
+    int32_t lanczos_max_steps; /* adaptive mode: cap on the steps (10..1024) */
     double lanczos_rtol;     /* > 0: adaptive mode for the log-determinants:
                                 after every 5th step from step 10 on, stop once
                                 every probe's quadrature value moved by at most

@@ -111,7 +111,7 @@ void check_theta(const kry_matern* t) {
 
 void check_opts(const kry_opts* o) {
     KRY_REQUIRE(o != nullptr, "opts is NULL");
-    KRY_REQUIRE(o->lanczos_steps >= 1 && o->lanczos_steps <= KRY_MAX_LANCZOS, "lanczos_steps must be in [1, 512]");
+    KRY_REQUIRE(o->lanczos_steps >= 1 && o->lanczos_steps <= KRY_MAX_LANCZOS, "lanczos_steps must be in [1, 1024]");
     KRY_REQUIRE(o->probe_kind == KRY_PROBE_RADEMACHER || o->probe_kind == KRY_PROBE_COLOURED, "bad probe_kind");
     if (o->probe_kind == KRY_PROBE_RADEMACHER) KRY_REQUIRE(o->num_probes >= 1 && o->num_probes <= 4096, "num_probes must be in [1, 4096]");
     else KRY_REQUIRE(o->colour_period >= 1 && o->colour_period <= 64, "colour_period must be in [1, 64]");
@@ -124,7 +124,7 @@ void check_opts(const kry_opts* o) {
     KRY_REQUIRE(std::isfinite(o->lanczos_rtol) && o->lanczos_rtol >= 0, "lanczos_rtol must be >= 0");
     if (o->lanczos_rtol > 0)
         KRY_REQUIRE(o->lanczos_max_steps >= 10 && o->lanczos_max_steps <= KRY_MAX_LANCZOS,
-                    "lanczos_max_steps must be in [10, 512] in the adaptive mode");
+                    "lanczos_max_steps must be in [10, 1024] in the adaptive mode");
     KRY_REQUIRE(o->reml == 0 || o->reml == 1, "reml must be 0 or 1");
 }
 
@@ -1051,7 +1051,6 @@ void loglik_points_shared(Problem& P, const kry_matern* thetas, int count, const
             B.rhs = a.take<int>(Gm);
             B.partial = a.take<double>((size_t)(1 + nd) * Gm * nblk);
             B.partial_pw = a.take<double>((size_t)Gm * nblk);
-            B.counter = a.take<unsigned>(1);
         };
         with_arena(P, lay);
         auto A = masked_op<double>(P, P.spec_multi64.ptr, nspec, 1, d_zero);

@@ -516,8 +516,12 @@ __global__ void k_quadrature(const double* __restrict__ alpha, const double* __r
                              const int* __restrict__ steps, const double* __restrict__ znorm2, int nvec,
                              int64_t coef_stride /* distance between steps j and j+1 */, double* __restrict__ gamma,
                              const int* __restrict__ src, const double* __restrict__ shift) {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= nvec) return;
+    // One output per workgroup; its first lane runs the (serial) QL sweeps
+    // on the tridiagonal held in LDS: 24 KB at the step cap, where arrays in
+    // private memory would ask the runtime for 24 KB of scratch per lane.
+    __shared__ double d[KRY_MAX_LANCZOS], e[KRY_MAX_LANCZOS], z[KRY_MAX_LANCZOS];
+    const int v = blockIdx.x;
+    if (v >= nvec || threadIdx.x != 0) return;
     const int u = src ? src[v] : v;
     const double sh = shift ? shift[v] : 0.0;
     const int n = steps[u];
@@ -525,7 +529,6 @@ __global__ void k_quadrature(const double* __restrict__ alpha, const double* __r
         gamma[v] = 0.0;
         return;
     }
-    double d[KRY_MAX_LANCZOS], e[KRY_MAX_LANCZOS], z[KRY_MAX_LANCZOS];
     for (int i = 0; i < n; ++i) {
         d[i] = alpha[i * coef_stride + u] + sh;
         e[i] = (i + 1 < n) ? beta[i * coef_stride + u] : 0.0;
@@ -580,8 +583,9 @@ __global__ void k_quadrature(const double* __restrict__ alpha, const double* __r
 
 void quadrature(const double* alpha, const double* beta, const int* steps, const double* znorm2, int nvec,
                 int64_t coef_stride, double* gamma, hipStream_t st, const int* src, const double* shift) {
-    hipLaunchKernelGGL(k_quadrature, dim3((nvec + 63) / 64), dim3(64), 0, st, alpha, beta, steps, znorm2, nvec,
-                       coef_stride, gamma, src, shift);
+    if (nvec <= 0) return;
+    hipLaunchKernelGGL(k_quadrature, dim3(nvec), dim3(64), 0, st, alpha, beta, steps, znorm2, nvec, coef_stride,
+                       gamma, src, shift);
     KRY_HIP(hipGetLastError());
 }
 
@@ -916,22 +920,22 @@ __device__ void ms_scalar_step(const MsScalarArgs& a) {
     }
 }
 
-// The residual update of k_ms_r, then the iteration's scalar step in the
-// block that finishes last (counted on the device: each block publishes its
-// partials with a device-scope release before it counts itself; the last
-// one acquires them all and resets the counter for the next launch).  No
-// block waits for another.
+// r_q -= alpha_q w_q, with alpha_q formed in every block from the p . w
+// partials; partials of ||r_q||^2 and D_j . r_q.  The scalar step is a
+// one-block launch of its own: publishing the partials to a last block
+// within this launch would take a device-scope release per block, which
+// writes back the XCD's L2 and cost more than the launch it saves.
 template <int ND>
-__global__ void __launch_bounds__(RB) k_ms_r_last(double* __restrict__ r, const double* __restrict__ w,
-                                                  const double* __restrict__ D, int64_t n, MsScalarArgs a,
-                                                  unsigned* __restrict__ counter) {
+__global__ void __launch_bounds__(RB) k_ms_r(double* __restrict__ r, const double* __restrict__ w,
+                                             const double* __restrict__ D, const double* __restrict__ partial_pw,
+                                             const double* __restrict__ rr, int Gact, int64_t n,
+                                             double* __restrict__ partial) {
     __shared__ double sh[RB];
-    __shared__ int last;
     const int nblk = gridDim.x, q = blockIdx.y;
     double x = 0.0;
-    if ((int)threadIdx.x < nblk) x += a.partial_pw[q * nblk + threadIdx.x];
+    if ((int)threadIdx.x < nblk) x += partial_pw[q * nblk + threadIdx.x];
     const double pwq = block_sum(x, sh);
-    const double al = pwq > 0.0 ? a.rr[q] / pwq : 0.0;
+    const double al = pwq > 0.0 ? rr[q] / pwq : 0.0;
     double acc = 0.0, accb[ND];
 #pragma unroll
     for (int j = 0; j < ND; ++j) accb[j] = 0.0;
@@ -947,46 +951,38 @@ __global__ void __launch_bounds__(RB) k_ms_r_last(double* __restrict__ r, const 
 #pragma unroll
     for (int j = 0; j < ND; ++j) accb[j] = block_sum(accb[j], sh);
     if (threadIdx.x == 0) {
-        a.partial[q * nblk + blockIdx.x] = acc;
+        partial[q * nblk + blockIdx.x] = acc;
 #pragma unroll
-        for (int j = 0; j < ND; ++j) a.partial[(a.Gact + q * ND + j) * nblk + blockIdx.x] = accb[j];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const unsigned total = (unsigned)nblk * gridDim.y;
-        const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        last = prev + 1u == total;
+        for (int j = 0; j < ND; ++j) partial[(Gact + q * ND + j) * nblk + blockIdx.x] = accb[j];
     }
-    __syncthreads();
-    if (!last) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    ms_scalar_step(a);
-    if (threadIdx.x == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+__global__ void __launch_bounds__(RB) k_ms_scalar(MsScalarArgs a) { ms_scalar_step(a); }
 
 template <int ND>
-void launch_ms_r_last(int nblk, int Gact, hipStream_t st, double* r, const double* w, const double* D, int64_t n,
-                      const MsScalarArgs& a, unsigned* counter) {
-    hipLaunchKernelGGL(k_ms_r_last<ND>, dim3(nblk, Gact), dim3(RB), 0, st, r, w, D, n, a, counter);
+void launch_ms_r(int nblk, int Gact, hipStream_t st, double* r, const double* w, const double* D, int64_t n,
+                 const MsScalarArgs& a) {
+    hipLaunchKernelGGL(k_ms_r<ND>, dim3(nblk, Gact), dim3(RB), 0, st, r, w, D, a.partial_pw, a.rr, Gact, n,
+                       a.partial);
 }
 
-void ms_r_last(int nd, int nblk, int Gact, hipStream_t st, double* r, const double* w, const double* D, int64_t n,
-               const MsScalarArgs& a, unsigned* counter) {
+void ms_residual_and_scalars(int nd, int nblk, int Gact, hipStream_t st, double* r, const double* w, const double* D,
+                             int64_t n, const MsScalarArgs& a) {
     switch (nd) {
-        case 1: launch_ms_r_last<1>(nblk, Gact, st, r, w, D, n, a, counter); break;
-        case 2: launch_ms_r_last<2>(nblk, Gact, st, r, w, D, n, a, counter); break;
-        case 3: launch_ms_r_last<3>(nblk, Gact, st, r, w, D, n, a, counter); break;
-        case 4: launch_ms_r_last<4>(nblk, Gact, st, r, w, D, n, a, counter); break;
-        case 5: launch_ms_r_last<5>(nblk, Gact, st, r, w, D, n, a, counter); break;
-        case 6: launch_ms_r_last<6>(nblk, Gact, st, r, w, D, n, a, counter); break;
-        case 7: launch_ms_r_last<7>(nblk, Gact, st, r, w, D, n, a, counter); break;
-        case 8: launch_ms_r_last<8>(nblk, Gact, st, r, w, D, n, a, counter); break;
-        case 9: launch_ms_r_last<9>(nblk, Gact, st, r, w, D, n, a, counter); break;
+        case 1: launch_ms_r<1>(nblk, Gact, st, r, w, D, n, a); break;
+        case 2: launch_ms_r<2>(nblk, Gact, st, r, w, D, n, a); break;
+        case 3: launch_ms_r<3>(nblk, Gact, st, r, w, D, n, a); break;
+        case 4: launch_ms_r<4>(nblk, Gact, st, r, w, D, n, a); break;
+        case 5: launch_ms_r<5>(nblk, Gact, st, r, w, D, n, a); break;
+        case 6: launch_ms_r<6>(nblk, Gact, st, r, w, D, n, a); break;
+        case 7: launch_ms_r<7>(nblk, Gact, st, r, w, D, n, a); break;
+        case 8: launch_ms_r<8>(nblk, Gact, st, r, w, D, n, a); break;
+        case 9: launch_ms_r<9>(nblk, Gact, st, r, w, D, n, a); break;
         default: KRY_REQUIRE(false, "multi-shift CG takes 1..9 dot vectors");
     }
     KRY_HIP(hipGetLastError());
-}
-
-__global__ void k_zero_u32(unsigned* __restrict__ c) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) __hip_atomic_store(c, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    hipLaunchKernelGGL(k_ms_scalar, dim3(1), dim3(RB), 0, st, a);
+    KRY_HIP(hipGetLastError());
 }
 
 // p_q = r_q + beta_q p_q
@@ -1066,8 +1062,6 @@ void mscg_run(const MatvecFn<double>& A, const MsFusedFn* fused, const std::func
                        B.alpha_old, B.beta_old, B.beta, B.zeta, B.zeta_old, B.d, B.Q, B.relres, B.active, B.iters,
                        B.limit);
     KRY_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, B.counter);
-    KRY_HIP(hipGetLastError());
     MsScalarArgs sa;
     sa.nd = nd;
     sa.nblk = nblk;
@@ -1100,9 +1094,9 @@ void mscg_run(const MatvecFn<double>& A, const MsFusedFn* fused, const std::func
     if (ublocks > 1024) ublocks = 1024;
     const int check = 16;
     // An iteration: the product (with the previous iteration's direction
-    // update folded in when `fused` is given), the p . w partials, and the
-    // residual update, whose last block takes the scalar step; without
-    // `fused`, the direction update is a pass of its own at the end.
+    // update folded in when `fused` is given), the p . w partials, the
+    // residual update and the one-block scalar step; without `fused`, the
+    // direction update is a pass of its own at the end.
     for (int it = 0; it < maxit && Gact > 0; ++it) {
         if (fused) (*fused)(B.r, B.p, B.beta, B.w, Gact, st);
         else A(B.p, B.w, Gact, st, nullptr);
@@ -1111,7 +1105,7 @@ void mscg_run(const MatvecFn<double>& A, const MsFusedFn* fused, const std::func
         KRY_HIP(hipGetLastError());
         sa.Gact = Gact;
         sa.nlist = nlist;
-        ms_r_last(nd, nblk, Gact, st, B.r, B.w, D, n, sa, B.counter);
+        ms_residual_and_scalars(nd, nblk, Gact, st, B.r, B.w, D, n, sa);
         if (!fused) {
             hipLaunchKernelGGL(k_ms_p, dim3((unsigned)ublocks, Gact), dim3(256), 0, st, B.p, B.r, B.beta, n);
             KRY_HIP(hipGetLastError());

@@ -7,7 +7,7 @@
 
 namespace kry {
 
-constexpr int KRY_MAX_LANCZOS = 512;
+constexpr int KRY_MAX_LANCZOS = 1024;
 
 // y_v = K x_v for nvec vectors of length n (contiguous, stride n).  With
 // active (device, nvec flags) given, vectors whose flag is 0 may be skipped:
@@ -58,7 +58,6 @@ struct MsCgBuffers {
     int* rhs;               // G
     double* partial;        // (1 + nd) G x nblk (at least nd x nd x nblk)
     double* partial_pw;     // G x nblk: p . w partials, read while the residual kernel writes `partial`
-    unsigned* counter;      // blocks of the residual kernel that have finished (reset by the last)
 };
 // Arguments of an iteration's scalar step (see ms_scalar_step).
 struct MsScalarArgs {

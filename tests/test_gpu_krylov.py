@@ -77,6 +77,23 @@ def test_gauss_quadrature_matches_oracle():
         assert abs(got[k] - ref) <= 1e-12 * max(abs(ref), 1.0)
 
 
+def test_gauss_quadrature_at_the_step_cap():
+    # tridiagonals of up to the 1024-step cap (the adaptive rule's ceiling),
+    # with a ragged mix of lengths across 70 probes (more than one wavefront)
+    rng = np.random.default_rng(4)
+    nprobe, m = 70, 1024
+    steps = rng.integers(1, m + 1, size=nprobe).astype(np.int32)
+    steps[:3] = [m, m - 1, 1]
+    alpha = rng.uniform(2.0, 5.0, size=(nprobe, m))  # diagonally dominant: positive definite
+    beta = rng.uniform(0.05, 0.9, size=(nprobe, m))
+    zn = rng.uniform(10, 100, size=nprobe)
+    got = K.kry_gauss_quadrature(alpha, beta, steps, zn)
+    for k in range(nprobe):
+        s = steps[k]
+        ref = lanczos.quadrature(alpha[k, :s], beta[k, : s - 1], zn[k])
+        assert abs(got[k] - ref) <= 1e-11 * max(abs(ref), 1.0), (k, s, got[k], ref)
+
+
 def test_slq_logdet_matches_oracle_and_exact_hutchinson():
     g, mask, y, yo = _problem(32, 32, CONFIG1, 0.0)
     Kd = dense.covariance(g, mask, CONFIG1)
