@@ -98,11 +98,14 @@ typedef struct {
                                 the nugget ratio share Krylov spaces (below) */
     int32_t lanczos_max_steps; /* adaptive mode: cap on the steps (10..1024) */
     double lanczos_rtol;     /* > 0: adaptive mode for the log-determinants:
-                                after every 5th step from step 10 on, stop once
-                                every probe's quadrature value moved by at most
-                                lanczos_rtol times its size over the last 5
-                                steps (or at lanczos_max_steps); lanczos_steps
-                                is then unused.  0 = exactly lanczos_steps.  */
+                                checks after steps 5, 10, ..., each
+                                5 max(1, floor(j / 50)) steps after the last
+                                (every 5 to step 100, every 10 to 150, ...);
+                                from step 10 on, stop once every probe's
+                                quadrature value moved by at most lanczos_rtol
+                                times its size since the previous check (or
+                                at lanczos_max_steps); lanczos_steps is then
+                                unused.  0 = exactly lanczos_steps.        */
     int32_t reml;            /* with covariates: 0 = likelihood with beta at its
                                 GLS estimate, 1 = restricted likelihood (of
                                 the error contrasts; see kry_loglik)        */
@@ -383,7 +386,9 @@ kry_status kry_loglik_multi(kry_problem* const* probs, const kry_matern* thetas,
 /* Maximise l_p over (log range, log eta) -- bit 0 of free_mask frees the
  * range, bit 1 the nugget ratio -- by Nelder-Mead from `init`, with the same
  * probes at every point.  est receives the estimate with sigma2 = sigma2_hat
- * and tau2 = eta * sigma2_hat; at_est the likelihood there. */
+ * and tau2 = eta * sigma2_hat; at_est the likelihood there.  With the
+ * environment variable KRY_VERBOSE set to 1 or more, every evaluation writes
+ * one progress line to stderr. */
 kry_status kry_fit(kry_problem* prob, const kry_matern* init, uint32_t free_mask,
                    const kry_opts* opts, double xtol, int32_t maxiter,
                    kry_matern* est, kry_loglik_result* at_est);

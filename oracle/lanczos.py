@@ -95,13 +95,25 @@ def slq_logdet(matvec, probes, m, reorth=True, coloured=False):
     return est, se, np.array(vals), np.array(steps)
 
 
+def check_steps(longest, every=5):
+    """Step counts at which the adaptive mode checks: every, 2 every, ...,
+    then each check `every` * max(1, floor(j / 50)) steps after the last
+    (every 5 steps up to 100, every 10 up to 150, every 15 up to 200, ...)."""
+    out, j = [], every
+    while j <= longest:
+        out.append(j)
+        j += every * max(1, j // 50)
+    return out
+
+
 def adaptive_steps(alphas, betas, znorm2s, rtol, every=5, first=10):
-    """Step count at which the adaptive mode stops: after each multiple of
-    `every` steps from `first` on, every probe's quadrature value with the
-    steps so far must have moved by at most rtol times its size since
-    `every` steps earlier; otherwise (including when every recurrence ended
-    before the first check) all the steps that were run.  A probe whose
-    recurrence ended earlier keeps its final value (it no longer moves).
+    """Step count at which the adaptive mode stops: at each check of
+    `check_steps` from `first` on, every probe's quadrature value with the
+    steps so far must have moved by at most rtol times its size since the
+    previous check; otherwise (including when every recurrence ended before
+    the first check) all the steps that were run.  A probe whose recurrence
+    ended earlier keeps its final value (it no longer moves).  This stopping
+    rule is the library's own (the paper fixes the step count).
     alphas / betas: per-probe coefficient arrays of the full run."""
     longest = max((len(a) for a in alphas), default=0)
 
@@ -116,7 +128,7 @@ def adaptive_steps(alphas, betas, znorm2s, rtol, every=5, first=10):
         return np.array(out)
 
     prev = None
-    for j in range(every, longest + 1, every):
+    for j in check_steps(longest, every):
         cur = gammas(j)
         if j >= first and prev is not None and np.all(np.abs(cur - prev) <= rtol * np.abs(cur)):
             return j

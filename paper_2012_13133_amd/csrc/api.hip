@@ -5,6 +5,8 @@
 // profile-likelihood fit (Sec. 3.4).
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -968,58 +970,9 @@ void loglik_points_shared(Problem& P, const kry_matern* thetas, int count, const
         if (fp32) slq_device<float>(Qp, o, P.spec_multi32.ptr, nspec, d_zero, G, W, nullptr, nullptr, s, &sq);
         else slq_device<double>(Qp, o, P.spec_multi64.ptr, gstride, d_zero, G, W, nullptr, nullptr, s, &sq);
     };
-    // The log-determinants and the multi-shift solves are independent: on a
-    // problem (not a request view of the server) the Lanczos recurrences run
-    // on a second stream with a workspace of their own while the solves run
-    // here, so the solves' small products no longer leave the device idle.
-    // Every kernel sees the same inputs as in sequence: the results are the same.
-    // (FP32 form only: the FP64 recurrences read the FP64 spectra, whose
-    // positions the solves permute as groups finish.)
-    const bool overlap = fp32 && need_ms && !P.is_view && !C.prof.on;
-    std::thread lz;
-    hipStream_t st2 = nullptr;
-    Problem lv;
-    std::string lz_err;
-    kry_status lz_status = KRY_OK;
-    if (overlap) {
-        if (!P.side) {
-            P.side = std::make_shared<Problem>();
-            P.side->ctx = &C;
-        }
-        lv = P.view();
-        lv.no_graphs = true;
-        lv.swap_work(*P.side);
-        KRY_HIP(hipStreamCreateWithFlags(&st2, hipStreamNonBlocking));
-        KRY_HIP(hipStreamSynchronize(st));  // spectra, shifts and nugget ratios are in place
-        lz = std::thread([&] {
-            try {
-                KRY_HIP(hipSetDevice(C.device));
-                run_slq(lv, st2);
-            } catch (const Error& e) {
-                lz_status = e.status;
-                lz_err = e.what();
-            } catch (const std::exception& e) {
-                lz_status = KRY_EDEVICE;
-                lz_err = e.what();
-            }
-        });
-    } else {
-        run_slq(P, st);
-    }
-    struct Join {
-        std::thread& t;
-        hipStream_t& s;
-        Problem& v;
-        Problem& P;
-        ~Join() {
-            if (t.joinable()) t.join();
-            if (s) {
-                (void)hipStreamSynchronize(s);
-                (void)hipStreamDestroy(s);
-                v.swap_work(*P.side);
-            }
-        }
-    } join{lz, st2, lv, P};
+    // log-determinants first, then the multi-shift solves (running the two
+    // on separate streams was measured to gain nothing: each fills the device)
+    run_slq(P, st);
     std::vector<double> Q(count, 0.0), relres(count, 0.0), M;
     std::vector<int> iters(count, 0);
     std::vector<Gls> gls(P.q > 0 ? count : 0);
@@ -1080,8 +1033,6 @@ void loglik_points_shared(Problem& P, const kry_matern* thetas, int count, const
             Q[t] = P.q > 0 ? gls[t].Q : Mt[0];
         }
     }
-    if (lz.joinable()) lz.join();
-    if (lz_status != KRY_OK) throw Error(lz_status, lz_err);
     if (o->solver != KRY_SOLVER_CG) {
         double* resid = nullptr;
         if (P.q > 0) {
@@ -2905,10 +2856,18 @@ static void fit_impl(Problem& P, const kry_matern* init, uint32_t free_mask, con
             t.tau2 = std::exp(le);
             return t;
         };
+        // KRY_VERBOSE >= 1 in the environment: one line per evaluation on
+        // stderr, so that a long fit reports its progress
+        const char* vb = std::getenv("KRY_VERBOSE");
+        const bool verbose = vb && std::atoi(vb) >= 1;
+        int nev = 0;
         auto f = [&](const std::vector<double>& x) {
             kry_matern t = point(x);
             kry_loglik_result r;
             loglik_points(P, &t, 1, opts, &r, st);
+            if (verbose)
+                std::fprintf(stderr, "[kry] fit evaluation %d: range %.6g nugget ratio %.6g l_p %.6f (%d Lanczos steps, %d CG iterations)\n",
+                             ++nev, t.range, t.tau2, r.loglik_profiled, r.lanczos_steps_used, r.cg_iters);
             return -r.loglik_profiled;
         };
         // Nelder-Mead (reflection 1, expansion 2, contraction 1/2, shrink 1/2)

@@ -185,7 +185,6 @@ struct Problem {
     bool no_graphs = false;  // set on the server's request views (several threads)
     const ProbDesc* tab = nullptr;  // set on a group of problems sharing an embedding
     // workspace (per problem or per view)
-    std::shared_ptr<Problem> side;  // a second workspace (log-determinants beside the solves; not in views)
     Spectrum spec;               // cache of the last parameter point
     DevBuf Y;                    // transform workspace
     DevBuf lagtmp, spectmp, spec_multi64, spec_multi32;
@@ -249,7 +248,6 @@ struct Problem {
         std::swap(spec.lam_max, o.spec.lam_max);
     }
     void release_work() {
-        if (side) side->release_work();
         for (DevBuf* b : {&Y, &lagtmp, &spectmp, &spec_multi64, &spec_multi32, &kws, &scal, &tmp1, &tmp2, &tmp3,
                           &tmp4, &irr, &spec.s64, &spec.s32})
             b->release(*ctx);

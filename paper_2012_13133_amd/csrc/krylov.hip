@@ -428,6 +428,10 @@ void lanczos_run(const MatvecFn<R>& A, int64_t n, int nvec, int m, bool reorth, 
     KRY_HIP(hipGetLastError());
     (void)nslots;
     double *g_prev = nullptr, *g_cur = nullptr;
+    // checks after steps 5, 10, ..., 100, 110, ..., 150, 165, ...: every
+    // 5 max(1, floor(j / 50)) steps, so that the quadratures, each O(j^2),
+    // cost O(m^2) in all rather than O(m^3)
+    int next_check = 5;
     if (ad) {
         KRY_HIP(hipMemsetAsync(ad->stop, 0, (ad->nout / ad->per_point) * sizeof(int), st));
         g_prev = ad->g_prev;
@@ -479,7 +483,8 @@ void lanczos_run(const MatvecFn<R>& A, int64_t n, int nvec, int m, bool reorth, 
         hipLaunchKernelGGL(k_lanczos_beta, dim3(nvec), dim3(RB), 0, st, B.partial, nblk, j, aj, bprev, bj, B.scale,
                            B.active, B.steps, tol);
         KRY_HIP(hipGetLastError());
-        if (ad && (j + 1) % 5 == 0) {
+        if (ad && j + 1 == next_check) {
+            next_check += 5 * std::max(1, (j + 1) / 50);
             quadrature(B.alpha, B.beta, B.steps, B.znorm2, ad->nout, nvec, g_cur, st, ad->src, ad->shift);
             if (j + 1 >= 10) {
                 hipLaunchKernelGGL(k_lanczos_settle, dim3(1), dim3(256), 0, st, g_cur, g_prev, ad->g_final, ad->stop,

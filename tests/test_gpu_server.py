@@ -240,9 +240,9 @@ def test_server_footprint_bounds_each_request():
 
 
 def test_shift_shared_batch_same_on_a_problem_and_through_the_server():
-    # On a problem the FP32 shift-shared call runs its Lanczos recurrences on
-    # a second stream beside the multi-shift solves; a request view runs them
-    # one after the other.  Both give the same results, bit for bit.
+    # The FP32 shift-shared call on a problem and the same points as requests
+    # on views with the server's slot workspaces give the same results, bit
+    # for bit.
     ctx = K.kry_ctx_create()
     probs, masks = _problems(ctx)
     try:

@@ -131,3 +131,13 @@ def test_adaptive_slq_stopping_rule():
     _, _, _, Kn = _problem(8, 8, th=theta(1e-6, 0.5, tau2=eta))
     estn, _, _, mn = lanczos.slq_logdet_adaptive(lambda v: Kn @ v, Z, max_steps=40, rtol=1e-12)
     assert mn == 1 and estn == pytest.approx(p * np.log1p(eta), rel=1e-14)
+
+
+def test_adaptive_check_schedule():
+    # every 5 steps to 100, then 10, 15, 20, ... apart (5 floor(j / 50))
+    got = lanczos.check_steps(260)
+    want = list(range(5, 101, 5)) + [110, 120, 130, 140, 150, 165, 180, 195, 210, 230, 250]
+    assert got == want
+    assert lanczos.check_steps(4) == []
+    # at the 1024-step cap: 46 checks instead of 204
+    assert len(lanczos.check_steps(1024)) == 46
