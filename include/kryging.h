@@ -206,6 +206,17 @@ kry_status kry_set_graphs(kry_ctx* ctx, int32_t enable);
  * device.  Creates the library's stream (default priority). */
 kry_status kry_ctx_create(int32_t device, uint64_t hbm_budget_bytes, kry_ctx** out);
 void kry_ctx_destroy(kry_ctx* ctx);
+/* How problems created on the context choose their embedding sides (each
+ * side independently; any side >= 2 n - 1 gives the exact product, Sec. 3.3):
+ * KRY_EMBED_FAST (the default) takes the supported side >= max(16, 2 n - 1)
+ * with the least N w(N), where w = 1 for powers of two, 1.2 for a side with
+ * one factor 3, 5 or 7 and 1.75 for a side with more (their transforms cost
+ * more per point);
+ * KRY_EMBED_SMALLEST takes the smallest supported side (least memory).
+ * Supported sides: powers of two and multiples of 16 with no prime factor
+ * above 7, in [16, 8192].  KRY_EINVAL for another rule. */
+enum { KRY_EMBED_FAST = 0, KRY_EMBED_SMALLEST = 1 };
+kry_status kry_ctx_set_embedding(kry_ctx* ctx, int32_t rule);
 /* Device bytes the context holds now (problems, workspaces, tables, server
  * slots) and the most it has held since creation or the last reset
  * (reset_peak != 0 sets the peak to the current value after reading it).
@@ -216,8 +227,8 @@ kry_status kry_ctx_memory(kry_ctx* ctx, uint64_t* allocated, uint64_t* peak, int
 /* A problem: grid, observation mask (n1*n2 bytes, nonzero = observed; at
  * least one observed cell) and data y (n1*n2 doubles read only where
  * observed, must be finite; NULL = zeros).  Uploads the mask in packed form
- * and y to the device.  The embedding used by the masked product is the
- * smallest power of two >= max(16, 2 n - 1) per axis. */
+ * and y to the device.  The embedding used by the masked product (Sec. 3.3)
+ * follows the context's embedding rule (kry_ctx_set_embedding). */
 kry_status kry_problem_create(kry_ctx* ctx, const kry_grid* grid, const uint8_t* mask,
                               const double* y, kry_problem** out);
 /* A problem with irregularly spaced observations (Sec. 2): the latent field
@@ -257,7 +268,8 @@ void kry_problem_destroy(kry_problem* prob);
 /* Lag grid c of the N1 x N2 block-circulant embedding (row-major):
  * c[l1][l2] = C(h2 dx2, h1 dx1) at the wrapped lag (h1, h2); on a Nyquist
  * line (l = N/2) the mean over both aliases.  N1, N2 = 0 selects the
- * problem's own embedding; otherwise powers of two in [16, 8192]. */
+ * problem's own embedding; otherwise supported sides in [16, 8192] (powers
+ * of two, or multiples of 16 with no prime factor above 7). */
 kry_status kry_lag_grid(kry_problem* prob, const kry_matern* theta, int32_t N1, int32_t N2,
                         double* c_out /* N1*N2 */);
 /* Eigenvalues lam = DFT2(c) on the half spectrum, layout [k2][k1] with
@@ -482,8 +494,8 @@ kry_status kry_posterior_variance(kry_problem* prob, const kry_matern* theta, co
 kry_status kry_tridiag_eigen(int32_t k, const double* d, const double* e, double* theta, double* W);
 
 /* ---- sampling (Sec. 3.5 fields; Sec. 3.6 embedding caveat) -------------- */
-/* Smallest torus N1 x N2 (powers of two, from the product's embedding,
- * doubling) whose spectrum satisfies min >= -1e-10 max, up to 8192.
+/* Smallest torus N1 x N2 (from the product's embedding, doubling both
+ * sides) whose spectrum satisfies min >= -1e-10 max, up to 8192.
  * KRY_ENOTPSD if none. */
 kry_status kry_psd_torus(kry_problem* prob, const kry_matern* theta, int32_t* N1, int32_t* N2);
 /* `count` fields x = sigma * (C^{1/2} xi)[corner] on the N1 x N2 torus, xi

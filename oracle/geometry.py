@@ -86,16 +86,45 @@ def spectrum(c):
     return np.real(np.fft.fft2(c))
 
 
-def fast_size(m):
-    """Smallest side >= max(16, m) of the form 2^a 3^b 5^c with 16 | side whose
-    half has at most one factor 3 or 5 beyond 2^3, within 8192 (the sides the
-    library's transforms take: powers of two, 3 * 2^a, 5 * 2^a; any side
-    >= 2n - 1 gives the exact product, so this only sets the cost)."""
+def _odd_factors(N):
+    """(the part of N without factors 2, 3, 5, 7; how many factors 3, 5, 7)."""
+    k = 0
+    while N % 2 == 0:
+        N //= 2
+    for q in (3, 5, 7):
+        while N % q == 0:
+            N //= q
+            k += 1
+    return N, k
+
+
+def supported_side(N):
+    """The sides the library's transforms take: powers of two, and multiples
+    of 16 with no prime factor above 7, in [16, 8192]."""
+    if N < 16 or N > 8192:
+        return False
+    if N & (N - 1) == 0:
+        return True
+    return N % 16 == 0 and _odd_factors(N)[0] == 1
+
+
+def fast_size(m, rule="fast"):
+    """Embedding side for a need of m >= 2n - 1 (any such side gives the
+    exact product; this only sets cost and memory).  rule "smallest": the
+    smallest supported side >= max(16, m).  rule "fast": the supported side
+    >= max(16, m) with the least N w(N), w = 1 for powers of two, 1.2 for a
+    side with one factor 3, 5 or 7 and 1.75 for a side with more (ties to the
+    smaller side).  None beyond 8192."""
+    best = None
     N = max(16, int(m))
     while N <= 8192:
-        k = N // 16
-        if N % 16 == 0 and (k & (k - 1) == 0 or (k % 3 == 0 and (k // 3) & (k // 3 - 1) == 0)
-                            or (k % 5 == 0 and (k // 5) & (k // 5 - 1) == 0)):
-            return N
+        if supported_side(N):
+            if rule == "smallest":
+                return N
+            w = 1.0 if N & (N - 1) == 0 else (1.2 if _odd_factors(N)[1] == 1 else 1.75)
+            if best is None or N * w < best[0]:
+                best = (N * w, N)
+            if N & (N - 1) == 0:
+                break
         N += 1
-    return None
+    return None if best is None else best[1]

@@ -1427,6 +1427,14 @@ kry_status kry_ctx_create(int32_t device, uint64_t hbm_budget_bytes, kry_ctx** o
     });
 }
 
+kry_status kry_ctx_set_embedding(kry_ctx* ctx, int32_t rule) {
+    return run_guarded([&] {
+        KRY_REQUIRE(ctx, "NULL context");
+        KRY_REQUIRE(rule == KRY_EMBED_FAST || rule == KRY_EMBED_SMALLEST, "unknown embedding rule");
+        ctx->c.embed_rule = rule;
+    });
+}
+
 kry_status kry_ctx_memory(kry_ctx* ctx, uint64_t* allocated, uint64_t* peak, int32_t reset_peak) {
     return guard([&] {
         KRY_REQUIRE(ctx && allocated && peak, "NULL argument");
@@ -1588,8 +1596,9 @@ kry_status kry_problem_create(kry_ctx* ctx, const kry_grid* grid, const uint8_t*
             P.n2 = n2;
             P.dx1 = grid->dx1;
             P.dx2 = grid->dx2;
-            P.N1 = embedding_side(2 * n1 - 1);
-            P.N2 = embedding_side(2 * n2 - 1);
+            P.N1 = embedding_side(2 * n1 - 1, P.ctx->embed_rule);
+            P.N2 = embedding_side(2 * n2 - 1, P.ctx->embed_rule);
+            build_embedding_tables(*P.ctx, P.N1, P.N2);
             P.p = p;
             P.words_per_row = (n2 + 31) / 32;
             const int64_t nw = (int64_t)n1 * P.words_per_row;
@@ -1729,8 +1738,9 @@ kry_status kry_problem_create_irregular(kry_ctx* ctx, const kry_grid* grid, int6
             P.n2 = n2;
             P.dx1 = grid->dx1;
             P.dx2 = grid->dx2;
-            P.N1 = embedding_side(2 * n1 - 1);
-            P.N2 = embedding_side(2 * n2 - 1);
+            P.N1 = embedding_side(2 * n1 - 1, P.ctx->embed_rule);
+            P.N2 = embedding_side(2 * n2 - 1, P.ctx->embed_rule);
+            build_embedding_tables(*P.ctx, P.N1, P.N2);
             P.p = p;
             P.irregular = true;
             P.h_cell = hc;

@@ -19,6 +19,7 @@
 //                    N2/2, gather observed cells (+ eta v) or write the grid
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <mutex>
 #include <unordered_map>
 
@@ -135,6 +136,9 @@ __global__ void k_lag_grid(double* __restrict__ c, int N1, int N2, MaternDev m) 
 // runs of the transposed intermediate) in 1024 threads, FP64 ones 512.
 template <typename R>
 constexpr int row_threads_max(int vt) { return vt > 1 && sizeof(R) == 8 ? 512 : 1024; }
+// (mixed-radix rows: FP64 passes hold more values per thread than radix 8)
+template <typename R>
+constexpr int row_threads_mixed() { return sizeof(R) == 8 ? 512 : 1024; }
 struct StageAArgs {
     const void* in;
     int64_t in_vstride;
@@ -837,14 +841,15 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
 }
 
 // ---------------------------------------------------------------------------
-// Mixed-radix stage kernels (embeddings 2^a 3^b 5^c that are not powers of
-// two; fftm.hpp).  The data flow and layouts are those of the kernels above,
-// with one value set per thread, complex exchanges, and every pass through
-// LDS.  The last forward pass of a column leaves the spectrum in natural
-// order in LDS, where the first inverse pass reads it multiplied by lam.
+// Mixed-radix stage kernels with compile-time plans (3 2^a, 5 2^a and 7 2^a
+// lengths; fftm.hpp).  The data flow and layouts are those of the kernels
+// above, with one value set per thread, complex exchanges, and every pass
+// through LDS.  The last forward pass of a column leaves the spectrum in
+// natural order in LDS, where the first inverse pass reads it multiplied by
+// lam.
 // ---------------------------------------------------------------------------
 template <typename R, int M, int IN>
-__global__ void __launch_bounds__(1024) k_row_fwd_m(StageAArgs a, const cpx<R>* __restrict__ twp) {
+__global__ void __launch_bounds__(row_threads_mixed<R>()) k_row_fwd_c(StageAArgs a, const cpx<R>* __restrict__ twp) {
     using S = MSched<M>;
     constexpr int T = M / 8, PM = lpadded<cpx<R>>(M) + 1;
     constexpr bool LOW = (IN == IN_COMPACT);
@@ -897,7 +902,7 @@ __global__ void __launch_bounds__(1024) k_row_fwd_m(StageAArgs a, const cpx<R>* 
 }
 
 template <typename R, int L, int MODE, int V>
-__global__ void __launch_bounds__((L / 8 > 256 ? L / 8 : 256)) k_col_m(StageBArgs a, const cpx<R>* __restrict__ twp) {
+__global__ void __launch_bounds__((L / 8 > 256 ? L / 8 : 256)) k_col_c(StageBArgs a, const cpx<R>* __restrict__ twp) {
     using S = MSched<L>;
     constexpr int T = L / 8, PL = lpadded<cpx<R>>(L);
     constexpr bool LOW = (MODE == B_LOW);
@@ -1026,7 +1031,7 @@ __global__ void __launch_bounds__((L / 8 > 256 ? L / 8 : 256)) k_col_m(StageBArg
 }
 
 template <typename R, int M, int OUT>
-__global__ void __launch_bounds__(1024) k_row_inv_m(StageCArgs a, const cpx<R>* __restrict__ twp) {
+__global__ void __launch_bounds__(row_threads_mixed<R>()) k_row_inv_c(StageCArgs a, const cpx<R>* __restrict__ twp) {
     using S = MSched<M>;
     constexpr int T = M / 8, PM = lpadded<cpx<R>>(M) + 1;
     constexpr int NV = 8;
@@ -1120,6 +1125,299 @@ __global__ void __launch_bounds__(1024) k_row_inv_m(StageCArgs a, const cpx<R>* 
 }
 
 // ---------------------------------------------------------------------------
+// Mixed-radix stage kernels with run-time plans (the other embeddings
+// 2^a 3^b 5^c 7^d that are not powers of two; fftm.hpp).  The data
+// flow and layouts are those of the kernels above, with one value set per
+// thread, complex exchanges, and every pass through LDS.  The last forward
+// pass of a column leaves the spectrum in natural order in LDS, where the
+// first inverse pass (radix RI, the plan's last forward radix, a template
+// argument so that its per-thread layout is fixed) reads it multiplied by
+// lam.
+// ---------------------------------------------------------------------------
+template <typename R, int IN>
+__global__ void __launch_bounds__(row_threads_mixed<R>()) k_row_fwd_m(StageAArgs a, const cpx<R>* __restrict__ twp,
+                                                    const MPlan* __restrict__ pl) {
+    const int M = pl->L, T = pl->T, PM = lpadded<cpx<R>>(M) + 1;
+    constexpr bool LOW = (IN == IN_COMPACT);
+    extern __shared__ unsigned char smem_raw[];
+    cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int rr = tid / T, t = tid % T;
+    const int lid = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int row0 = (lid % gridDim.x) * a.RT;
+    const int row = row0 + rr;
+    const int vec = lid / gridDim.x;
+    if (a.active && !a.active[vec]) return;
+    MaskView mask = a.mask;
+    int rows_in = a.rows_in, row_len = a.row_len;
+    if (a.tab) {
+        const ProbDesc& d = a.tab[(a.vec0 + vec) / a.tab_vpp];
+        mask = MaskView{d.bits, d.base, d.wpr};
+        rows_in = d.n1;
+        row_len = d.n2;
+        if (row0 >= rows_in) return;
+    }
+    cpx<R>* buf = lds + rr * PM;
+    cpx<R> v[MVMAX];
+#pragma unroll
+    for (int k = 0; k < MVMAX; ++k) v[k] = cpx<R>{(R)0, (R)0};
+    row_inputs<R, IN, 1, LOW>(a, mask, vec, row, rows_in, row_len, t, T, T, v);
+    mr_butterflies<R, 8, false, LOW>(v);
+    mr_write<R, 8>(v, buf, t, T, M, 1);
+    __syncthreads();
+    mr_lds_passes<R, false>(pl, 1, pl->npass, v, buf, 0, t, twp);
+    // split Z into the real transform X[k] = (s - i w d) / 2, k = 0..M, with
+    // w = W_{2M}^k from the plan table
+    cpx<R>* Y = reinterpret_cast<cpx<R>*>(a.Y) + vec * a.Y_vstride;
+    const cpx<R>* ws = twp + pl->split_off;
+    auto split = [&](int r2, int k) {
+        const cpx<R>* bp = lds + r2 * PM;
+        const cpx<R> zk = bp[lpad<cpx<R>>(k == M ? 0 : k)];
+        const cpx<R> zc = cconj(bp[lpad<cpx<R>>(k == 0 ? 0 : M - k)]);
+        const cpx<R> s2 = cadd(zk, zc);
+        const cpx<R> wd = cmul(ws[k], csub(zk, zc));
+        at32(Y, (uint32_t)(k * a.ldY + row0 + r2)) = cpx<R>{(R)0.5 * (s2.x + wd.y), (R)0.5 * (s2.y - wd.x)};
+    };
+    const int nt = blockDim.x;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int o = tid + i * nt;
+        split(o & (a.RT - 1), o >> a.log2RT);
+    }
+    if (tid < a.RT) split(tid, M);
+}
+
+// TMAX: the largest workgroup the launch may use (256, 512, 768 or 1024
+// threads: one column of up to 2048, 4096, 6144 or 8192 points, or several
+// shorter ones).
+template <typename R, int MODE, int V, int RI, int TMAX>
+__global__ void __launch_bounds__(TMAX) k_col_m(StageBArgs a, const cpx<R>* __restrict__ twp,
+                                                const MPlan* __restrict__ pl) {
+    const int L = pl->L, T = pl->T, PL = lpadded<cpx<R>>(L), npass = pl->npass;
+    constexpr bool LOW = (MODE == B_LOW);
+    constexpr int BI = mbpt<RI>();
+    const int QI = L / RI;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int cl = T >= 256 ? 0 : tid / T, t = T >= 256 ? tid : tid % T;
+    const int lid = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int col = (lid / gridDim.y) * a.CB + cl;
+    const bool valid = col < a.ncols;
+    const int vbase = (lid % gridDim.y) * V;
+    cpx<R>* buf = lds + cl * V * PL;
+    if (a.active) {
+        bool any = false;
+#pragma unroll
+        for (int u = 0; u < V; ++u) any = any || (vbase + u < a.nvec && a.active[vbase + u]);
+        if (!any) return;
+    }
+    int rows_in[V], rows_out[V];
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+        rows_in[u] = a.rows_in;
+        rows_out[u] = a.rows_out;
+        if (a.tab) {
+            const ProbDesc& d = a.tab[(a.vec0 + min(vbase + u, a.nvec - 1)) / a.tab_vpp];
+            rows_in[u] = d.n1;
+            rows_out[u] = d.n1;
+        }
+    }
+    // spectrum values at the first inverse pass's input positions, fetched
+    // up front (unused slots read position 0 of the last vector's spectrum)
+    R lamv[MODE == B_SPEC ? 1 : V * BI * RI];
+    if constexpr (MODE != B_SPEC) {
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            const int vl = min(vbase + u, a.nvec - 1);
+            const R* lam;
+            if (a.tab) {
+                const ProbDesc& d = a.tab[(a.vec0 + vl) / a.tab_vpp];
+                lam = reinterpret_cast<const R*>(sizeof(R) == 8 ? (const void*)d.lam64 : (const void*)d.lam32);
+            } else {
+                lam = reinterpret_cast<const R*>(a.lam) + (int64_t)((a.vec0 + vl) / a.vecs_per_theta) * a.lam_tstride;
+            }
+            lam += (int64_t)(valid ? col : 0) * L;
+#pragma unroll
+            for (int b = 0; b < BI; ++b) {
+                const int j = t + b * T;
+#pragma unroll
+                for (int r = 0; r < RI; ++r) lamv[(u * BI + b) * RI + r] = lam[j < QI ? j + r * QI : 0];
+            }
+        }
+    }
+    cpx<R>* Ycol = reinterpret_cast<cpx<R>*>(a.Y) + (int64_t)(valid ? col : 0) * a.ldY;
+    cpx<R> v[V * MVMAX];
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+        const bool vu = valid && (vbase + u < a.nvec);
+        const cpx<R>* Yv = Ycol + (vbase + u) * a.Y_vstride;
+#pragma unroll
+        for (int r = 0; r < MVMAX; ++r) {
+            const int idx = t + r * T;
+            v[u * MVMAX + r] = cpx<R>{(R)0, (R)0};
+            if (r >= 8 || (LOW && r >= 4)) continue;
+            if (vu && idx < rows_in[u]) v[u * MVMAX + r] = Yv[idx];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+        mr_butterflies<R, 8, false, LOW>(v + u * MVMAX);
+        mr_write<R, 8>(v + u * MVMAX, buf + u * PL, t, T, L, 1);
+    }
+    __syncthreads();
+    mr_lds_passes<R, false, V>(pl, 1, npass, v, buf, PL, t, twp);
+    if constexpr (MODE == B_SPEC) {
+        if (valid) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int pos = t + k * T;
+                a.spec_out[(int64_t)col * L + pos] = (double)buf[lpad<cpx<R>>(pos)].x;
+            }
+        }
+        return;
+    } else {
+        // first inverse pass: its inputs times lam
+#pragma unroll
+        for (int u = 0; u < V; ++u)
+#pragma unroll
+            for (int b = 0; b < BI; ++b) {
+                const int j = t + b * T;
+                if (j < QI) {
+#pragma unroll
+                    for (int r = 0; r < RI; ++r)
+                        v[u * MVMAX + b * RI + r] =
+                            cscale(buf[u * PL + lpad<cpx<R>>(j + r * QI)], lamv[(u * BI + b) * RI + r]);
+                }
+            }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            mr_butterflies<R, RI, true>(v + u * MVMAX);
+            mr_write<R, RI>(v + u * MVMAX, buf + u * PL, t, T, L, 1);
+        }
+        __syncthreads();
+        mr_lds_passes<R, true, V>(pl, 1, npass - 1, v, buf, PL, t, twp);
+        {
+            // the last inverse pass is radix 8: outputs at t + k T
+            const int PLAST = npass - 1;
+            const auto w = mr_twiddles<R, 8>(t, T, L, pl->ns_i[PLAST], pl->magic_i[PLAST], twp + pl->tw_i[PLAST]);
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+                mr_read<R, 8>(v + u * MVMAX, buf + u * PL, t, T, L);
+                mr_compute<R, 8, true>(v + u * MVMAX, w);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            if (!(valid && vbase + u < a.nvec)) continue;
+            cpx<R>* Yv = Ycol + (vbase + u) * a.Y_vstride;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int idx = t + k * T;
+                if (idx < rows_out[u]) Yv[idx] = v[u * MVMAX + k];
+            }
+        }
+    }
+}
+
+// R0: radix of the first inverse pass (the plan's last forward radix).
+template <typename R, int OUT, int R0>
+__global__ void __launch_bounds__(row_threads_mixed<R>()) k_row_inv_m(StageCArgs a, const cpx<R>* __restrict__ twp,
+                                                    const MPlan* __restrict__ pl) {
+    const int M = pl->L, T = pl->T, PM = lpadded<cpx<R>>(M) + 1, npass = pl->npass;
+    constexpr int NV = 8;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<R>* lds = reinterpret_cast<cpx<R>*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int lid = xcd_remap(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int tile = lid % gridDim.x;
+    const int row0 = tile * a.RT;
+    const int vec = lid / gridDim.x;
+    const cpx<R>* Y = reinterpret_cast<const cpx<R>*>(a.Y) + vec * a.Y_vstride;
+    const int rr = tid / T, t = tid % T;
+    const int row = row0 + rr;
+    if (a.active && !a.active[vec]) return;
+    MaskView mask = a.mask;
+    int rows_out = a.rows_out, cols_out = a.cols_out;
+    if (a.tab) {
+        const ProbDesc& d = a.tab[(a.vec0 + vec) / a.tab_vpp];
+        mask = MaskView{d.bits, d.base, d.wpr};
+        rows_out = d.n1;
+        cols_out = d.n2;
+        if constexpr (OUT == OUT_COMPACT) {
+            const int64_t len = a.out_vstride - d.p;
+            const int64_t per = (len + gridDim.x - 1) / gridDim.x;
+            const int64_t b = d.p + tile * per, e = min(b + per, a.out_vstride);
+            R* o = reinterpret_cast<R*>(a.out) + vec * a.out_vstride;
+            for (int64_t i = b + tid; i < e; i += blockDim.x) o[i] = (R)0;
+        }
+        if (row0 >= rows_out) return;
+    }
+    auto pos = [&](int k) { return t + k * T; };  // the last inverse pass is radix 8
+    int32_t oci[NV];
+    uint64_t obits = 0u;
+    row_output_cells<OUT, NV>(mask, row, rows_out, cols_out, oci, obits, pos);
+    {
+        const int nt = blockDim.x;  // = RT * T
+        cpx<R> tv[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int o = tid + i * nt;
+            const int r2 = o & (a.RT - 1);
+            const int k = o >> a.log2RT;
+            tv[i] = (row0 + r2 < rows_out) ? at32(Y, (uint32_t)(k * a.ldY + row0 + r2)) : cpx<R>{(R)0, (R)0};
+        }
+        cpx<R> ny{(R)0, (R)0};
+        if (tid < a.RT && row0 + tid < rows_out) ny = at32(Y, (uint32_t)(M * a.ldY + row0 + tid));
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int o = tid + i * nt;
+            lds[(o & (a.RT - 1)) * PM + lpad<cpx<R>>(o >> a.log2RT)] = tv[i];
+        }
+        if (tid < a.RT) lds[tid * PM + lpad<cpx<R>>(M)] = ny;
+    }
+    __syncthreads();
+    // first inverse pass: inputs merged from the split half spectrum,
+    // Z[k] = (X[k] + X*[M-k]) + i conj(W_{2M}^k) (X[k] - X*[M-k])
+    cpx<R>* buf = lds + rr * PM;
+    const cpx<R>* ws = twp + pl->split_off;
+    auto merged = [&](int k) {
+        const cpx<R> xk = buf[lpad<cpx<R>>(k)];
+        const cpx<R> xm = buf[lpad<cpx<R>>(M - k)];
+        const cpx<R> s2 = cadd(xk, cconj(xm));
+        const cpx<R> d = cmul(cconj(ws[k]), csub(xk, cconj(xm)));
+        return cpx<R>{s2.x - d.y, s2.y + d.x};
+    };
+    constexpr int B0 = mbpt<R0>();
+    const int Q0 = M / R0;
+    cpx<R> v[MVMAX];
+#pragma unroll
+    for (int k = 0; k < MVMAX; ++k) v[k] = cpx<R>{(R)0, (R)0};
+#pragma unroll
+    for (int b = 0; b < B0; ++b) {
+        const int j = t + b * T;
+        if (j < Q0) {
+#pragma unroll
+            for (int r = 0; r < R0; ++r) v[b * R0 + r] = merged(j + r * Q0);
+        }
+    }
+    __syncthreads();  // every read of X before the pass overwrites it
+    mr_butterflies<R, R0, true>(v);
+    mr_write<R, R0>(v, buf, t, T, M, 1);
+    __syncthreads();
+    mr_lds_passes<R, true>(pl, 1, npass - 1, v, buf, 0, t, twp);
+    {
+        const int PLAST = npass - 1;
+        const auto w = mr_twiddles<R, 8>(t, T, M, pl->ns_i[PLAST], pl->magic_i[PLAST], twp + pl->tw_i[PLAST]);
+        mr_read<R, 8>(v, buf, t, T, M);
+        mr_compute<R, 8, true>(v, w);
+    }
+    if (row >= rows_out) return;
+    row_outputs<R, OUT, NV>(a, row, cols_out, vec, oci, obits, v, pos);
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
 static int ilog2(int v) {
@@ -1194,81 +1492,122 @@ static const cpx<R>* plan_table(Ctx& c, int log2L) {
     return static_cast<const cpx<R>*>(slot);
 }
 
-// Mixed-radix lengths (fftm.hpp): row lengths M (half a torus side) and
-// column lengths (torus sides) that are not powers of two.
-#define KRY_MROWS(X) X(24) X(40) X(48) X(80) X(96) X(160) X(192) X(320) X(384) X(640) X(768) X(1280) X(1536) X(2560) X(3072)
-#define KRY_MCOLS(X) X(48) X(80) X(96) X(160) X(192) X(320) X(384) X(640) X(768) X(1280) X(1536) X(2560) X(3072) X(5120) X(6144)
-
-static bool is_mixed_row(int M) {
-#define KRY_T(L) if (M == L) return true;
-    KRY_MROWS(KRY_T)
-#undef KRY_T
-    return false;
-}
-static bool is_mixed_col(int L) {
-#define KRY_T(X) if (L == X) return true;
-    KRY_MCOLS(KRY_T)
-#undef KRY_T
-    return false;
-}
 static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Lengths with compile-time mixed-radix kernels (3 2^a, 5 2^a, 7 2^a):
+// row lengths M (half a torus side) and column lengths (torus sides).
+#define KRY_CROWS(X) X(24) X(40) X(48) X(56) X(80) X(96) X(112) X(160) X(192) X(224) X(320) X(384) X(448) \
+    X(640) X(768) X(896) X(1280) X(1536) X(1792) X(2560) X(3072) X(3584)
+#define KRY_CCOLS(X) X(48) X(80) X(96) X(112) X(160) X(192) X(224) X(320) X(384) X(448) X(640) X(768) X(896) \
+    X(1280) X(1536) X(1792) X(2560) X(3072) X(3584) X(5120) X(6144) X(7168)
+
+static bool is_ct_row(int M) {
+#define KRY_T(X) if (M == X) return true;
+    KRY_CROWS(KRY_T)
+#undef KRY_T
+    return false;
+}
+static bool is_ct_col(int L) {
+#define KRY_T(X) if (L == X) return true;
+    KRY_CCOLS(KRY_T)
+#undef KRY_T
+    return false;
+}
+
+// Mixed-radix lengths (fftm.hpp): 2^a 3^b 5^c 7^d, a >= 3, not powers of two.
+static bool mixed_len_ok(int L) {
+    MPlan p;
+    return !is_pow2(L) && mplan_make(L, &p);
+}
+
+static MPlan mixed_plan(int L) {
+    MPlan p;
+    if (!mplan_make(L, &p)) throw Error(KRY_EINVAL, "mixed-radix transform length not supported");
+    return p;
+}
 
 bool torus_side_ok(int N) {
     if (N < 16 || N > 8192) return false;
-    return is_pow2(N) || (is_mixed_col(N) && is_mixed_row(N / 2));
+    return is_pow2(N) || (N % 16 == 0 && mixed_len_ok(N) && mixed_len_ok(N / 2));
 }
 
-int embedding_side(int m) {
-    for (int N = std::max(16, m); N <= 8192; ++N)
-        if (torus_side_ok(N)) return N;
-    return 0;
+// Relative cost per point of a torus side: 1 for a power of two, 1.2 for a
+// side with compile-time kernels (one factor 3, 5 or 7; measured 1.2-1.5
+// times the power-of-two cost per point over both axes of a product), 1.75
+// for the other sides (run-time plans: 2.2-3.5 times).
+static double side_weight(int N) {
+    if (is_pow2(N)) return 1.0;
+    return is_ct_col(N) && is_ct_row(N / 2) ? 1.2 : 1.75;
+}
+
+int embedding_side(int m, int rule) {
+    int best = 0;
+    double best_cost = 0.0;
+    for (int N = std::max(16, m); N <= 8192; ++N) {
+        if (!torus_side_ok(N)) continue;
+        if (rule == KRY_EMBED_SMALLEST) return N;
+        const double cost = N * side_weight(N);
+        if (!best || cost < best_cost) {
+            best = N;
+            best_cost = cost;
+        }
+        if (is_pow2(N)) break;  // every larger side costs more
+    }
+    return best;
 }
 
 // Pass twiddles of a mixed-radix length, [r][j mod Ns] per pass and
 // direction, then W_{2L}^k for k = 0..L (the real-to-complex split).
-template <typename Real, int L>
-static void fill_mplan(std::vector<std::array<long double, 2>>& out) {
-    using S = MSched<L>;
-    out.assign(S::tw_total, {1.0L, 0.0L});
+static void fill_mplan(const MPlan& pl, std::vector<std::array<long double, 2>>& out) {
+    out.assign(pl.tw_total, {1.0L, 0.0L});
     const long double pi = 3.141592653589793238462643383279502884L;
     for (int inv = 0; inv < 2; ++inv)
-        for (int p = 1; p < S::npass; ++p) {
-            const int R = S::radix(inv, p), NS = S::ns(inv, p);
-            const int off = S::tw_off(inv, p);
+        for (int p = 1; p < pl.npass; ++p) {
+            const int R = pl.radix_at(inv, p), NS = inv ? pl.ns_i[p] : pl.ns_f[p];
+            const int off = inv ? pl.tw_i[p] : pl.tw_f[p];
             for (int jn = 0; jn < NS; ++jn)
                 for (int r = 0; r < R; ++r) {
                     const long double ang = (inv ? 2.0L : -2.0L) * pi * (long double)(r * jn) / (long double)(NS * R);
                     out[off + r * NS + jn] = {cosl(ang), sinl(ang)};
                 }
         }
-    for (int k = 0; k <= L; ++k) {
-        const long double ang = -2.0L * pi * (long double)k / (long double)(2 * L);
-        out[S::split_off + k] = {cosl(ang), sinl(ang)};
+    for (int k = 0; k <= pl.L; ++k) {
+        const long double ang = -2.0L * pi * (long double)k / (long double)(2 * pl.L);
+        out[pl.split_off + k] = {cosl(ang), sinl(ang)};
     }
 }
 
+// A mixed-radix length's plan and twiddle table in one device allocation:
+// the plan (read by the kernels pass by pass), then the twiddles.
 template <typename R>
-static const cpx<R>* mplan_table(Ctx& c, int L) {
+struct MTable {
+    const MPlan* plan;
+    const cpx<R>* tw;
+};
+constexpr size_t kPlanBytes = (sizeof(MPlan) + 255) & ~size_t(255);
+
+// Built on first use (problems build theirs when they are created, so
+// products allocate nothing).
+template <typename R>
+static MTable<R> mplan_table(Ctx& c, int L) {
     static std::mutex mu;
     std::lock_guard<std::mutex> g(mu);
     auto& m = sizeof(R) == 8 ? c.mplan64 : c.mplan32;
     auto it = m.find(L);
-    if (it != m.end()) return static_cast<const cpx<R>*>(it->second);
-    std::vector<std::array<long double, 2>> tab;
-    switch (L) {
-#define KRY_F(X) case X: fill_mplan<R, X>(tab); break;
-        KRY_MROWS(KRY_F)
-        case 5120: fill_mplan<R, 5120>(tab); break;
-        case 6144: fill_mplan<R, 6144>(tab); break;
-#undef KRY_F
-        default: throw Error(KRY_EINVAL, "mixed-radix transform length not supported");
+    if (it == m.end()) {
+        const MPlan pl = mixed_plan(L);
+        std::vector<std::array<long double, 2>> tab;
+        fill_mplan(pl, tab);
+        std::vector<unsigned char> h(kPlanBytes + tab.size() * sizeof(cpx<R>), 0);
+        std::memcpy(h.data(), &pl, sizeof(MPlan));
+        cpx<R>* hw = reinterpret_cast<cpx<R>*>(h.data() + kPlanBytes);
+        for (size_t i = 0; i < tab.size(); ++i) hw[i] = cpx<R>{(R)tab[i][0], (R)tab[i][1]};
+        void* slot = dev_alloc(c, h.size());
+        KRY_HIP(hipMemcpy(slot, h.data(), h.size(), hipMemcpyHostToDevice));
+        it = m.emplace(L, slot).first;
     }
-    std::vector<cpx<R>> h(tab.size());
-    for (size_t i = 0; i < tab.size(); ++i) h[i] = cpx<R>{(R)tab[i][0], (R)tab[i][1]};
-    void* slot = dev_alloc(c, h.size() * sizeof(cpx<R>));
-    KRY_HIP(hipMemcpy(slot, h.data(), h.size() * sizeof(cpx<R>), hipMemcpyHostToDevice));
-    m[L] = slot;
-    return static_cast<const cpx<R>*>(slot);
+    const unsigned char* base = static_cast<const unsigned char*>(it->second);
+    return MTable<R>{reinterpret_cast<const MPlan*>(base), reinterpret_cast<const cpx<R>*>(base + kPlanBytes)};
 }
 
 void build_plan_tables(Ctx& c) {
@@ -1276,13 +1615,14 @@ void build_plan_tables(Ctx& c) {
         plan_table<double>(c, lg);
         plan_table<float>(c, lg);
     }
-#define KRY_P(X) mplan_table<double>(c, X); mplan_table<float>(c, X);
-    KRY_MROWS(KRY_P)
-    mplan_table<double>(c, 5120);
-    mplan_table<float>(c, 5120);
-    mplan_table<double>(c, 6144);
-    mplan_table<float>(c, 6144);
-#undef KRY_P
+}
+
+void build_embedding_tables(Ctx& c, int N1, int N2) {
+    for (int L : {N1, N2 / 2})
+        if (!is_pow2(L)) {
+            mplan_table<double>(c, L);
+            mplan_table<float>(c, L);
+        }
 }
 
 struct RowTiling {
@@ -1297,7 +1637,7 @@ template <typename R>
 static RowTiling row_tiling(int M, int rt_scale = 1, int vt = 1, bool split = false) {
     const size_t cs = sizeof(cpx<R>);
     const int T = M / 8 / vt;  // threads per row
-    const int tmax = row_threads_max<R>(vt);
+    const int tmax = is_pow2(M) ? row_threads_max<R>(vt) : row_threads_mixed<R>();
     const size_t PM = (size_t)M + M / 16 + 1;  // lpadded<cpx<R>>(M) + 1, as the kernels
     int RT = (int)(64 * rt_scale / cs);
     while (RT > 1 && RT * T > tmax) RT /= 2;
@@ -1376,25 +1716,25 @@ static void launch_col(const StageBArgs& b, int nvec, int V, bool split, Ctx& c,
 }
 
 template <typename R, int M, int IN>
-static void launch_row_fwd_m(const StageAArgs& a, dim3 grid, const RowTiling& t, Ctx& c, hipStream_t st) {
-    auto k = k_row_fwd_m<R, M, IN>;
+static void launch_row_fwd_c(const StageAArgs& a, dim3 grid, const RowTiling& t, Ctx& c, hipStream_t st) {
+    auto k = k_row_fwd_c<R, M, IN>;
     set_lds(k, t.lds);
-    hipLaunchKernelGGL(k, grid, dim3(t.threads), t.lds, st, a, mplan_table<R>(c, M));
+    hipLaunchKernelGGL(k, grid, dim3(t.threads), t.lds, st, a, mplan_table<R>(c, M).tw);
     KRY_HIP(hipGetLastError());
 }
 
 template <typename R, int M, int OUT>
-static void launch_row_inv_m(const StageCArgs& a, dim3 grid, const RowTiling& t, Ctx& c, hipStream_t st) {
-    auto k = k_row_inv_m<R, M, OUT>;
+static void launch_row_inv_c(const StageCArgs& a, dim3 grid, const RowTiling& t, Ctx& c, hipStream_t st) {
+    auto k = k_row_inv_c<R, M, OUT>;
     set_lds(k, t.lds);
-    hipLaunchKernelGGL(k, grid, dim3(t.threads), t.lds, st, a, mplan_table<R>(c, M));
+    hipLaunchKernelGGL(k, grid, dim3(t.threads), t.lds, st, a, mplan_table<R>(c, M).tw);
     KRY_HIP(hipGetLastError());
 }
 
-// Columns of a mixed-radix length: V = 2 vectors per workgroup where their
-// LDS fits, else one.
+// Columns of a compile-time mixed-radix length: V = 2 vectors per workgroup
+// where their LDS fits, else one.
 template <typename R, int L, int MODE>
-static void launch_col_m(const StageBArgs& b, int nvec, int V, Ctx& c, hipStream_t st) {
+static void launch_col_c(const StageBArgs& b, int nvec, int V, Ctx& c, hipStream_t st) {
     constexpr int T = L / 8;
     const size_t per = (size_t)b.CB * lpadded<cpx<R>>(L) * sizeof(cpx<R>);
     if (MODE == B_SPEC || 2 * per > 160 * 1024) V = 1;
@@ -1403,15 +1743,106 @@ static void launch_col_m(const StageBArgs& b, int nvec, int V, Ctx& c, hipStream
     StageBArgs bb = b;
     bb.nvec = nvec;
     if (V == 2) {
-        auto k = k_col_m<R, L, MODE, 2>;
+        auto k = k_col_c<R, L, MODE, 2>;
         set_lds(k, lds);
-        hipLaunchKernelGGL(k, grid, dim3(b.CB * T), lds, st, bb, mplan_table<R>(c, L));
+        hipLaunchKernelGGL(k, grid, dim3(b.CB * T), lds, st, bb, mplan_table<R>(c, L).tw);
     } else {
-        auto k = k_col_m<R, L, MODE, 1>;
+        auto k = k_col_c<R, L, MODE, 1>;
         set_lds(k, lds);
-        hipLaunchKernelGGL(k, grid, dim3(b.CB * T), lds, st, bb, mplan_table<R>(c, L));
+        hipLaunchKernelGGL(k, grid, dim3(b.CB * T), lds, st, bb, mplan_table<R>(c, L).tw);
     }
     KRY_HIP(hipGetLastError());
+}
+
+template <typename R, int IN>
+static void launch_row_fwd_m(const StageAArgs& a, dim3 grid, const RowTiling& t, const MPlan& pl, Ctx& c,
+                             hipStream_t st) {
+    auto k = k_row_fwd_m<R, IN>;
+    set_lds(k, t.lds);
+    const MTable<R> tb = mplan_table<R>(c, pl.L);
+    hipLaunchKernelGGL(k, grid, dim3(t.threads), t.lds, st, a, tb.tw, tb.plan);
+    KRY_HIP(hipGetLastError());
+}
+
+template <typename R, int OUT, int R0>
+static void launch_row_inv_mr(const StageCArgs& a, dim3 grid, const RowTiling& t, const MPlan& pl, Ctx& c,
+                              hipStream_t st) {
+    auto k = k_row_inv_m<R, OUT, R0>;
+    set_lds(k, t.lds);
+    const MTable<R> tb = mplan_table<R>(c, pl.L);
+    hipLaunchKernelGGL(k, grid, dim3(t.threads), t.lds, st, a, tb.tw, tb.plan);
+    KRY_HIP(hipGetLastError());
+}
+
+// (the first inverse pass's radix is the plan's last forward radix: 2, 3, 4,
+// 5 or 7 for a length that is not a power of two)
+template <typename R, int OUT>
+static void launch_row_inv_m(const StageCArgs& a, dim3 grid, const RowTiling& t, const MPlan& pl, Ctx& c,
+                             hipStream_t st) {
+    switch (pl.radix[pl.npass - 1]) {
+        case 2: launch_row_inv_mr<R, OUT, 2>(a, grid, t, pl, c, st); break;
+        case 3: launch_row_inv_mr<R, OUT, 3>(a, grid, t, pl, c, st); break;
+        case 4: launch_row_inv_mr<R, OUT, 4>(a, grid, t, pl, c, st); break;
+        case 5: launch_row_inv_mr<R, OUT, 5>(a, grid, t, pl, c, st); break;
+        case 7: launch_row_inv_mr<R, OUT, 7>(a, grid, t, pl, c, st); break;
+        default: throw Error(KRY_EINVAL, "mixed-radix plan without a non-8 last pass");
+    }
+}
+
+template <typename R, int MODE, int V, int RI, int TMAX>
+static void launch_col_mk(const StageBArgs& bb, dim3 grid, int threads, size_t lds, const MPlan& pl, Ctx& c,
+                          hipStream_t st) {
+    auto k = k_col_m<R, MODE, V, RI, TMAX>;
+    set_lds(k, lds);
+    const MTable<R> tb = mplan_table<R>(c, pl.L);
+    hipLaunchKernelGGL(k, grid, dim3(threads), lds, st, bb, tb.tw, tb.plan);
+    KRY_HIP(hipGetLastError());
+}
+
+template <typename R, int MODE, int V, int RI>
+static void launch_col_mt(const StageBArgs& bb, dim3 grid, int threads, size_t lds, const MPlan& pl, Ctx& c,
+                          hipStream_t st) {
+    if (threads <= 256) launch_col_mk<R, MODE, V, RI, 256>(bb, grid, threads, lds, pl, c, st);
+    else if constexpr (V == 1) {
+        if (threads <= 512) launch_col_mk<R, MODE, 1, RI, 512>(bb, grid, threads, lds, pl, c, st);
+        else if (threads <= 768) launch_col_mk<R, MODE, 1, RI, 768>(bb, grid, threads, lds, pl, c, st);
+        else launch_col_mk<R, MODE, 1, RI, 1024>(bb, grid, threads, lds, pl, c, st);
+    } else {
+        throw Error(KRY_EINVAL, "two column vectors per workgroup take columns of at most 2048 points");
+    }
+}
+
+template <typename R, int MODE, int V>
+static void launch_col_mv(const StageBArgs& bb, dim3 grid, int threads, size_t lds, const MPlan& pl, Ctx& c,
+                          hipStream_t st) {
+    switch (pl.radix[pl.npass - 1]) {
+        case 2: launch_col_mt<R, MODE, V, 2>(bb, grid, threads, lds, pl, c, st); break;
+        case 3: launch_col_mt<R, MODE, V, 3>(bb, grid, threads, lds, pl, c, st); break;
+        case 4: launch_col_mt<R, MODE, V, 4>(bb, grid, threads, lds, pl, c, st); break;
+        case 5: launch_col_mt<R, MODE, V, 5>(bb, grid, threads, lds, pl, c, st); break;
+        case 7: launch_col_mt<R, MODE, V, 7>(bb, grid, threads, lds, pl, c, st); break;
+        default: throw Error(KRY_EINVAL, "mixed-radix plan without a non-8 last pass");
+    }
+}
+
+// Columns of a mixed-radix length: V = 2 vectors per workgroup where their
+// LDS fits and the column has at most 2048 points, else one.
+template <typename R, int MODE>
+static void launch_col_m(const StageBArgs& b, int nvec, int V, const MPlan& pl, Ctx& c, hipStream_t st) {
+    const int threads = b.CB * pl.T;
+    const size_t per = (size_t)b.CB * lpadded<cpx<R>>(pl.L) * sizeof(cpx<R>);
+    if (MODE == B_SPEC || 2 * per > 160 * 1024 || threads > 256) V = 1;
+    const size_t lds = per * V;
+    dim3 grid((b.ncols + b.CB - 1) / b.CB, (nvec + V - 1) / V);
+    StageBArgs bb = b;
+    bb.nvec = nvec;
+    if constexpr (MODE != B_SPEC) {
+        if (V == 2) {
+            launch_col_mv<R, MODE, 2>(bb, grid, threads, lds, pl, c, st);
+            return;
+        }
+    }
+    launch_col_mv<R, MODE, 1>(bb, grid, threads, lds, pl, c, st);
 }
 
 #define KRY_SIZES(X) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
@@ -1446,18 +1877,24 @@ static void run_stage_a(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R
     dim3 grid((s.rows_in + t.RT - 1) / t.RT, nvec);
     const int lg = ilog2(M);
     Ctx& c = *P.ctx;
-    if (!is_pow2(M)) {
+    if (is_ct_row(M)) {
         switch (M) {
-#define KRY_AM(X)                                                                                   \
+#define KRY_AC(X)                                                                                   \
     case X:                                                                                         \
-        if (s.in_mode == IN_COMPACT) launch_row_fwd_m<R, X, IN_COMPACT>(a, grid, t, c, st);           \
-        else if (s.in_mode == IN_DENSE) launch_row_fwd_m<R, X, IN_DENSE>(a, grid, t, c, st);          \
-        else launch_row_fwd_m<R, X, IN_NOISE>(a, grid, t, c, st);                                    \
+        if (s.in_mode == IN_COMPACT) launch_row_fwd_c<R, X, IN_COMPACT>(a, grid, t, c, st);           \
+        else if (s.in_mode == IN_DENSE) launch_row_fwd_c<R, X, IN_DENSE>(a, grid, t, c, st);          \
+        else launch_row_fwd_c<R, X, IN_NOISE>(a, grid, t, c, st);                                    \
         break;
-            KRY_MROWS(KRY_AM)
-#undef KRY_AM
-            default: throw Error(KRY_EINVAL, "row transform length not supported");
+            KRY_CROWS(KRY_AC)
+#undef KRY_AC
         }
+        return;
+    }
+    if (!is_pow2(M)) {
+        const MPlan pl = mixed_plan(M);
+        if (s.in_mode == IN_COMPACT) launch_row_fwd_m<R, IN_COMPACT>(a, grid, t, pl, c, st);
+        else if (s.in_mode == IN_DENSE) launch_row_fwd_m<R, IN_DENSE>(a, grid, t, pl, c, st);
+        else launch_row_fwd_m<R, IN_NOISE>(a, grid, t, pl, c, st);
         return;
     }
 #define KRY_A(LG)                                                                             \
@@ -1498,18 +1935,24 @@ static void run_stage_b(Problem& P, int N1, int M, int vec0, int nvec, cpx<R>* Y
     const int mode = spec_out ? B_SPEC : (2 * rows_in <= N1 ? B_LOW : B_FULL);
     const int lg = ilog2(N1);
     Ctx& c = *P.ctx;
-    if (!is_pow2(N1)) {
+    if (is_ct_col(N1)) {
         switch (N1) {
-#define KRY_BM(X)                                                                 \
+#define KRY_BC(X)                                                                 \
     case X:                                                                       \
-        if (mode == B_LOW) launch_col_m<R, X, B_LOW>(b, nvec, V, c, st);          \
-        else if (mode == B_FULL) launch_col_m<R, X, B_FULL>(b, nvec, V, c, st);   \
-        else launch_col_m<R, X, B_SPEC>(b, nvec, 1, c, st);                       \
+        if (mode == B_LOW) launch_col_c<R, X, B_LOW>(b, nvec, V, c, st);          \
+        else if (mode == B_FULL) launch_col_c<R, X, B_FULL>(b, nvec, V, c, st);   \
+        else launch_col_c<R, X, B_SPEC>(b, nvec, 1, c, st);                       \
         break;
-            KRY_MCOLS(KRY_BM)
-#undef KRY_BM
-            default: throw Error(KRY_EINVAL, "column transform length not supported");
+            KRY_CCOLS(KRY_BC)
+#undef KRY_BC
         }
+        return;
+    }
+    if (!is_pow2(N1)) {
+        const MPlan pl = mixed_plan(N1);
+        if (mode == B_LOW) launch_col_m<R, B_LOW>(b, nvec, V, pl, c, st);
+        else if (mode == B_FULL) launch_col_m<R, B_FULL>(b, nvec, V, pl, c, st);
+        else launch_col_m<R, B_SPEC>(b, nvec, 1, pl, c, st);
         return;
     }
 #define KRY_B(LG)                                                                          \
@@ -1552,17 +1995,22 @@ static void run_stage_c(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R
     dim3 grid((s.rows_out + t.RT - 1) / t.RT, nvec);
     const int lg = ilog2(M);
     Ctx& cx = *P.ctx;
-    if (!is_pow2(M)) {
+    if (is_ct_row(M)) {
         switch (M) {
-#define KRY_CM(X)                                                                              \
+#define KRY_CC(X)                                                                              \
     case X:                                                                                    \
-        if (s.out_mode == OUT_COMPACT) launch_row_inv_m<R, X, OUT_COMPACT>(c, grid, t, cx, st); \
-        else launch_row_inv_m<R, X, OUT_GRID>(c, grid, t, cx, st);                             \
+        if (s.out_mode == OUT_COMPACT) launch_row_inv_c<R, X, OUT_COMPACT>(c, grid, t, cx, st); \
+        else launch_row_inv_c<R, X, OUT_GRID>(c, grid, t, cx, st);                             \
         break;
-            KRY_MROWS(KRY_CM)
-#undef KRY_CM
-            default: throw Error(KRY_EINVAL, "row transform length not supported");
+            KRY_CROWS(KRY_CC)
+#undef KRY_CC
         }
+        return;
+    }
+    if (!is_pow2(M)) {
+        const MPlan pl = mixed_plan(M);
+        if (s.out_mode == OUT_COMPACT) launch_row_inv_m<R, OUT_COMPACT>(c, grid, t, pl, cx, st);
+        else launch_row_inv_m<R, OUT_GRID>(c, grid, t, pl, cx, st);
         return;
     }
 #define KRY_C(LG)                                                                             \
@@ -1580,7 +2028,7 @@ static void run_stage_c(Problem& P, const ConvSpec& s, int vec0, int nvec, cpx<R
 template <typename R>
 void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st) {
     KRY_REQUIRE(torus_side_ok(s.N1) && torus_side_ok(s.N2),
-                "torus sides must be supported transform lengths (16..8192: powers of two or 2^a 3^b 5^c)");
+                "torus sides must be supported transform lengths (16..8192: powers of two or multiples of 16 of the form 2^a 3^b 5^c 7^d)");
     KRY_REQUIRE(s.rows_in <= s.N1 && s.row_len <= s.N2 && s.rows_out <= s.N1 && s.cols_out <= s.N2,
                 "block larger than the torus");
     KRY_REQUIRE(s.in_mode != IN_COMPACT || 2 * s.row_len <= s.N2, "compact input wider than half the torus");

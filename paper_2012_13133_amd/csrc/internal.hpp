@@ -77,6 +77,7 @@ struct Ctx {
     static constexpr int kSmallBatch = 8;
     static int batch_class(int nvec) { return nvec <= kSmallBatch ? 0 : 1; }
     void* scratch = nullptr;  // device address of the no-allocation product's scratch array
+    int embed_rule = KRY_EMBED_FAST;  // how new problems choose their embedding sides
     // The setting for products of nvec vectors: that batch class's, else the
     // other class's, else the built-in default.
     Tuning tuning_for(int N1, int N2, int real_bytes, int nvec = 1 << 30) {
@@ -327,11 +328,15 @@ size_t spectrum_ws_bytes(int N1, int N2);
 // Every per-length twiddle table of the transforms, both precisions (so
 // later products allocate none).
 void build_plan_tables(Ctx& c);
-// Torus sides the transforms support: 16..8192, powers of two or 2^a 3^b 5^c
-// from the mixed-radix set (multiples of 16 whose half is a supported row
-// length); and the smallest supported side >= max(16, m) (0 if none).
+// Torus sides the transforms support: 16..8192, powers of two or multiples
+// of 16 of the form 2^a 3^b 5^c 7^d (mixed-radix plans); and the embedding
+// side for a need of m by the rule (kry_ctx_set_embedding; 0 if none).
 bool torus_side_ok(int N);
-int embedding_side(int m);
+int embedding_side(int m, int rule = KRY_EMBED_SMALLEST);
+// Twiddle tables of the mixed-radix lengths of an embedding N1 x N2 (column
+// length N1, row length N2 / 2), built when a problem is created so that its
+// products allocate nothing.
+void build_embedding_tables(Ctx& c, int N1, int N2);
 // Scale a half spectrum by s into FP64 and FP32 copies; optional sqrt of
 // max(lam, 0) first (sampling).
 void spectrum_scale(const double* lam, int64_t n, double s, bool sqrt_clip, double* out64,

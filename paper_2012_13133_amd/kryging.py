@@ -108,6 +108,7 @@ _SIGS = {
     "kry_ctx_create": (C.c_int, [C.c_int32, C.c_uint64, C.POINTER(_P)]),
     "kry_ctx_destroy": (None, [_P]),
     "kry_ctx_memory": (C.c_int, [_P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.c_int32]),
+    "kry_ctx_set_embedding": (C.c_int, [_P, C.c_int32]),
     "kry_profile_begin": (C.c_int, [_P]),
     "kry_profile_end": (C.c_int, [_P, _DP, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "kry_problem_create": (C.c_int, [_P, C.POINTER(kry_grid), C.POINTER(C.c_uint8), _DP, C.POINTER(_P)]),
@@ -218,6 +219,13 @@ def kry_ctx_create(device=0, hbm_budget_bytes=0):
 
 def kry_ctx_destroy(ctx):
     lib.kry_ctx_destroy(ctx)
+
+
+KRY_EMBED_FAST, KRY_EMBED_SMALLEST = 0, 1
+
+
+def kry_ctx_set_embedding(ctx, rule):
+    _check(lib.kry_ctx_set_embedding(ctx, rule))
 
 
 def kry_ctx_memory(ctx, reset_peak=False):
@@ -597,10 +605,12 @@ def kry_server_destroy(srv):
 class Problem:
     """Owns a context and a problem handle (closes both)."""
 
-    def __init__(self, n1, n2, mask, y=None, device=0, dx1=None, dx2=None, hbm_budget_bytes=0):
+    def __init__(self, n1, n2, mask, y=None, device=0, dx1=None, dx2=None, hbm_budget_bytes=0, embedding=None):
         self.n1, self.n2 = n1, n2
         self.ctx = kry_ctx_create(device, hbm_budget_bytes)
         try:
+            if embedding is not None:
+                kry_ctx_set_embedding(self.ctx, embedding)
             self.h = kry_problem_create(self.ctx, n1, n2, mask, y, dx1, dx2)
         except Exception:
             kry_ctx_destroy(self.ctx)
@@ -631,10 +641,12 @@ class Problem:
 class IrregularProblem(Problem):
     """Owns a context and an irregular problem handle (closes both)."""
 
-    def __init__(self, n1, n2, locs, y=None, device=0, dx1=None, dx2=None, hbm_budget_bytes=0):
+    def __init__(self, n1, n2, locs, y=None, device=0, dx1=None, dx2=None, hbm_budget_bytes=0, embedding=None):
         self.n1, self.n2 = n1, n2
         self.ctx = kry_ctx_create(device, hbm_budget_bytes)
         try:
+            if embedding is not None:
+                kry_ctx_set_embedding(self.ctx, embedding)
             self.h = kry_problem_create_irregular(self.ctx, n1, n2, locs, y, dx1, dx2)
         except Exception:
             kry_ctx_destroy(self.ctx)

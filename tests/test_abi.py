@@ -54,6 +54,8 @@ def test_host_side_paths_without_gpu():
     m = (ctypes.c_uint8 * 64)(*([1] * 64))
     st = K.lib.kry_problem_create(None, ctypes.byref(g), m, None, ctypes.byref(h))
     assert st == K.KRY_EINVAL
+    # the embedding rule setting rejects a NULL context
+    assert K.lib.kry_ctx_set_embedding(None, K.KRY_EMBED_SMALLEST) == K.KRY_EINVAL
     # gauss quadrature validates its sizes before touching the device
     one = (ctypes.c_double * 1)(1.0)
     steps = (ctypes.c_int32 * 1)(5)

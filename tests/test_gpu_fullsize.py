@@ -19,16 +19,18 @@ CASES = {
     # large anisotropic shape: 2048^2, 40 % blob missing, nu 1, ratio 2 at 30 degrees, nugget ratio 0.1
     "2048": (2048, theta(0.05, 1.0, sigma2=1.0, tau2=0.1, ratio=2.0, angle=np.pi / 6),
              lambda n: synth.blob_mask(n, n, 0.4, seed=102)),
-    # grids whose smallest embedding takes a radix-5 pass (600^2: 1280 =
-    # 2^8 5) or a radix-3 pass (700^2: 1536 = 2^9 3)
+    # grids whose smallest embedding (the smallest-side rule) takes mixed
+    # radices (600^2: 1200 = 2^4 3 5^2; 700^2: 1440 = 2^5 3^2 5; 880^2:
+    # 1792 = 2^8 7)
     "600": (600, theta(0.04, 2.5, sigma2=1.0, tau2=0.2), lambda n: synth.uniform_mask(n, n, 0.3, seed=103)),
     "700": (700, theta(0.06, 0.5, sigma2=1.0, tau2=0.2, ratio=1.5, angle=0.3),
             lambda n: synth.blob_mask(n, n, 0.25, seed=104, rmin=5, rmax=40)),
+    "880": (880, theta(0.03, 1.5, sigma2=1.0, tau2=0.1), lambda n: synth.uniform_mask(n, n, 0.2, seed=105)),
 }
-EMBEDDING = {"1024": 2048, "2048": 4096, "600": 1280, "700": 1536}
+EMBEDDING = {"1024": 2048, "2048": 4096, "600": 1200, "700": 1440, "880": 1792}
 
 
-@pytest.mark.parametrize("case", ["1024", "2048", "600", "700"])
+@pytest.mark.parametrize("case", ["1024", "2048", "600", "700", "880"])
 def test_masked_product_sampled_rows(case):
     n, th, mk = CASES[case]
     mask = mk(n)
@@ -40,11 +42,11 @@ def test_masked_product_sampled_rows(case):
     T = lag_table(n, n, 1.0 / n, 1.0 / n, th)
     pick = [0, 13, 31]
     ref = direct.masked_matvec(g, mask, th, v[pick].T, rows=rows, table=T)  # (24, 3)
-    with K.Problem(n, n, mask) as P:
+    with K.Problem(n, n, mask, embedding=K.KRY_EMBED_SMALLEST) as P:
         assert (P.N1, P.N2) == (EMBEDDING[case],) * 2
         got64 = K.kry_matvec(P.h, K.theta_from_dict(th), v, K.KRY_FP64)
         got32 = K.kry_matvec(P.h, K.theta_from_dict(th), v, K.KRY_FP32)
-        if case in ("600", "700"):
+        if case in ("600", "700", "880"):
             # one and two vectors per column workgroup, both tile heights: bit for bit
             for cv in (1, 2):
                 for rs in (1, 2):

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 K = pytest.importorskip("paper_2012_13133_amd.kryging")
 
 # embeddings: 128 x 128, 128 x 128, 48 x 128 (a radix-3 side)
-SHAPES = [(56, 60, 0.3, "uniform"), (64, 64, 0.2, "blob"), (24, 50, 0.5, "uniform")]
+SHAPES = [(60, 62, 0.3, "uniform"), (64, 64, 0.2, "blob"), (24, 50, 0.5, "uniform")]
 
 
 def _problems(ctx):

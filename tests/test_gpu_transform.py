@@ -45,14 +45,17 @@ def test_spectrum(th, tor):
 
 
 SHAPES = [(2, 2), (3, 5), (7, 9), (16, 16), (32, 32), (33, 47), (64, 50), (100, 3),
-          # embeddings with radix-3 and radix-5 passes: 48 x 64, 80 x 96, 320 x 640,
-          # 384 x 768, 48 x 16
-          (20, 30), (40, 41), (150, 300), (190, 380), (24, 3)]
+          # mixed-radix embeddings by the smallest-side rule: 48 x 64, 80 x 96,
+          # 320 x 640, 384 x 768, 48 x 16 (radix 3 or 5), 128 x 112 and 224 x 16
+          # above (radix 7), 96 x 144 (3 and 3^2), 240 x 400 (3 5 and 5^2),
+          # 784 x 48 (7^2); the fast rule keeps some of them (80 x 96, 320 x 640, ...)
+          (20, 30), (40, 41), (150, 300), (190, 380), (24, 3), (45, 68), (113, 200), (392, 20)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("ti", range(len(THETAS)))
-def test_masked_product_fp64_and_fp32(shape, ti):
+@pytest.mark.parametrize("rule", ["fast", "smallest"])
+def test_masked_product_fp64_and_fp32(shape, ti, rule):
     th = THETAS[ti]
     n1, n2 = shape
     g = grid(n1, n2)
@@ -60,7 +63,8 @@ def test_masked_product_fp64_and_fp32(shape, ti):
     p = int(mask.sum())
     v = synth.random_vectors(p, 3, seed=5)
     ref = direct.masked_matvec(g, mask, th, v.T).T
-    with K.Problem(n1, n2, mask) as P:
+    emb = K.KRY_EMBED_FAST if rule == "fast" else K.KRY_EMBED_SMALLEST
+    with K.Problem(n1, n2, mask, embedding=emb) as P:
         t = K.theta_from_dict(th)
         got64 = K.kry_matvec(P.h, t, v, K.KRY_FP64)
         got32 = K.kry_matvec(P.h, t, v, K.KRY_FP32)
@@ -114,10 +118,13 @@ def test_probes_bit_exact():
     np.testing.assert_array_equal(zc, philox.probe_matrix(r, c, 0, 99, colour_period=3).T)
 
 
-def test_embedding_is_the_smallest_supported_side():
-    # the library's embedding follows the stated size rule (restated in
-    # oracle.geometry.fast_size): 7 x 13, 20 x 30, 40 x 41, 150 x 300, 600 x 700
+@pytest.mark.parametrize("rule", ["fast", "smallest"])
+def test_embedding_follows_the_rule(rule):
+    # the library's embedding follows the stated rules (restated in
+    # oracle.geometry.fast_size): 7 x 13, 20 x 30, 40 x 41, 150 x 300,
+    # 600 x 700, 513 x 880, 1100 x 2040
     from oracle.geometry import fast_size
-    for n1, n2 in ((7, 13), (20, 30), (40, 41), (150, 300), (600, 700)):
-        with K.Problem(n1, n2, np.ones((n1, n2))) as P:
-            assert (P.N1, P.N2) == (fast_size(2 * n1 - 1), fast_size(2 * n2 - 1)), (n1, n2)
+    emb = K.KRY_EMBED_FAST if rule == "fast" else K.KRY_EMBED_SMALLEST
+    for n1, n2 in ((7, 13), (20, 30), (40, 41), (150, 300), (600, 700), (513, 880), (1100, 2040)):
+        with K.Problem(n1, n2, np.ones((n1, n2)), embedding=emb) as P:
+            assert (P.N1, P.N2) == (fast_size(2 * n1 - 1, rule), fast_size(2 * n2 - 1, rule)), (n1, n2)

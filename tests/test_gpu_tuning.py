@@ -15,11 +15,14 @@ K = pytest.importorskip("paper_2012_13133_amd.kryging")
 TH = theta(0.1, 1.5, tau2=0.2, ratio=1.5, angle=0.4)
 
 
-@pytest.mark.parametrize("shape", [(40, 36), (600, 530)])  # 128 x 128 and 2048 x 2048 embeddings
+# embeddings 128 x 128, 2048 x 2048 and 80 x 80 (mixed radix: the settings
+# that apply to power-of-two transforms only must leave it unchanged); on the
+# 2048 x 2048 embedding a shorter range keeps the sampler's torus PSD
+@pytest.mark.parametrize("shape", [(60, 62, 0.1), (1010, 1020, 0.03), (40, 36, 0.1)])
 def test_every_configuration_is_bit_identical(shape):
-    n1, n2 = shape
+    n1, n2, rng = shape
     mask = synth.uniform_mask(n1, n2, 0.3, seed=3)
-    th = K.theta_from_dict(TH)
+    th = K.theta_from_dict(dict(TH, range=rng))
     with K.Problem(n1, n2, mask) as P:
         v = synth.random_vectors(P.p, 3, seed=4)
         w = synth.random_vectors(P.p, 2, seed=6)
@@ -45,11 +48,11 @@ def test_every_configuration_is_bit_identical(shape):
 def test_row_settings_bit_identical_on_a_4096_embedding():
     # rows of 2048 points: the split row kernels and 1024-thread FP32 tiles at
     # their largest common size
-    n1, n2 = 1100, 1600
+    n1, n2 = 1100, 2040
     mask = synth.uniform_mask(n1, n2, 0.3, seed=13)
     th = K.theta_from_dict(TH)
     with K.Problem(n1, n2, mask) as P:
-        assert P.N2 == 4096  # (and N1 = 2560: mixed-radix columns beside power-of-two rows)
+        assert P.N2 == 4096  # (and N1 = 2560 = 2^9 5: mixed-radix columns beside power-of-two rows)
         v = synth.random_vectors(P.p, 2, seed=14)
         for prec in (K.KRY_FP64, K.KRY_FP32):
             K.kry_set_tuning(P.ctx, P.N1, P.N2, prec)

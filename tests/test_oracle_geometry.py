@@ -36,3 +36,21 @@ def test_lag_table_symmetry():
     T = lag_table(6, 5, 1 / 6, 1 / 5, th)
     np.testing.assert_array_equal(T, T[::-1, ::-1])
     assert T[5, 4] == 1.0
+
+
+def test_fast_size_rule():
+    # supported sides: powers of two, or multiples of 16 with prime factors
+    # 2, 3, 5, 7 only; "smallest" takes the first, "fast" weighs mixed sides
+    from oracle.geometry import fast_size, supported_side
+    smallest = {5: 16, 17: 32, 47: 48, 99: 112, 111: 112, 119: 128, 199: 224, 783: 784, 1199: 1200,
+                1399: 1440, 1759: 1792, 2047: 2048, 3199: 3200, 4079: 4096, 8192: 8192}
+    for m, want in smallest.items():
+        assert fast_size(m, "smallest") == want, (m, fast_size(m, "smallest"), want)
+    # fast: w = 1.2 for one odd factor (1280 = 1536 < 2048; 1536 = 1843 <
+    # 2048; 1792 = 2150 > 2048), 1.75 for more (1200, 1440, 2240 lose)
+    fast = {79: 80, 1199: 1280, 1399: 1536, 1759: 2048, 1025: 1280, 2199: 2560, 4079: 4096, 47: 48, 2047: 2048,
+            3199: 4096, 99: 128}
+    for m, want in fast.items():
+        assert fast_size(m) == want, (m, fast_size(m), want)
+    assert fast_size(8193) is None and fast_size(8193, "smallest") is None
+    assert supported_side(1400) is False and supported_side(1440) and not supported_side(1408)
