@@ -137,3 +137,28 @@ def test_range_nugget_grid_fp32_shared_matches_plain_fp64(nu):
             for key in ("loglik", "loglik_profiled"):
                 assert abs(batch[k][key] - plain[key]) <= 1e-3 * abs(plain[key]), (k, key)
             assert abs(batch[k]["quad"] - plain["quad"]) <= 1e-7 * plain["quad"]
+
+
+@pytest.mark.parametrize("shape", [(2520, 20), (20, 2520)])
+def test_masked_product_long_run_time_plan_sides(shape):
+    # the smallest-side rule puts 2 2520 - 1 on 5040 = 2^4 3^2 5 7: a column
+    # (630 threads) or a row (2520 points) of a run-time plan at its largest
+    # workgroup classes; sampled rows against the direct sum
+    n1, n2 = shape
+    th = theta(0.05, 1.5, sigma2=1.0, tau2=0.2, ratio=1.5, angle=0.3)
+    mask = synth.uniform_mask(n1, n2, 0.3, seed=106)
+    g = (n1, n2, 1.0 / n1, 1.0 / n2)
+    p = int(mask.sum())
+    rng = np.random.default_rng(8)
+    v = rng.standard_normal((4, p))
+    rows = np.sort(rng.choice(p, size=24, replace=False))
+    T = lag_table(n1, n2, 1.0 / n1, 1.0 / n2, th)
+    ref = direct.masked_matvec(g, mask, th, v.T, rows=rows, table=T)  # (24, 4)
+    with K.Problem(n1, n2, mask, embedding=K.KRY_EMBED_SMALLEST) as P:
+        assert sorted((P.N1, P.N2)) == [48, 5040]
+        got64 = K.kry_matvec(P.h, K.theta_from_dict(th), v, K.KRY_FP64)
+        got32 = K.kry_matvec(P.h, K.theta_from_dict(th), v, K.KRY_FP32)
+    for got, tol in ((got64, 1e-12), (got32, 1e-5)):
+        for j in range(4):
+            scale = np.sqrt(np.mean(got[j] ** 2))
+            assert np.abs(got[j][rows] - ref[:, j]).max() <= tol * scale, (shape, tol)
