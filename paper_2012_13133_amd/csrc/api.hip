@@ -153,10 +153,12 @@ void bind(Ctx& c) { KRY_HIP(hipSetDevice(c.device)); }
 
 // ---- product operators ----------------------------------------------------------------
 template <typename R>
-MatvecFn<R> masked_op(Problem& P, const void* lam, int64_t lam_tstride, int vpt, const double* d_eta) {
+MatvecFn<R> masked_op(Problem& P, const void* lam, int64_t lam_tstride, int vpt, const double* d_eta,
+                      bool lam_even = false) {
     if (P.irregular) return irregular_op<R>(P, lam, lam_tstride, vpt, d_eta);
     Problem* pp = &P;
-    return [pp, lam, lam_tstride, vpt, d_eta](const R* x, R* y, int nvec, hipStream_t st, const int* active) {
+    return [pp, lam, lam_tstride, vpt, d_eta, lam_even](const R* x, R* y, int nvec, hipStream_t st,
+                                                        const int* active) {
         Problem& Q = *pp;
         ConvSpec s;
         s.N1 = Q.N1;
@@ -178,6 +180,7 @@ MatvecFn<R> masked_op(Problem& P, const void* lam, int64_t lam_tstride, int vpt,
         s.lam = lam;
         s.lam_tstride = lam_tstride;
         s.vecs_per_theta = vpt;
+        s.lam_even = lam_even && !Q.tab;
         s.tab = Q.tab;
         s.tab_vpp = vpt;
         s.active = active;
@@ -187,10 +190,11 @@ MatvecFn<R> masked_op(Problem& P, const void* lam, int64_t lam_tstride, int vpt,
 
 // The FP64 masked product of the multi-shift CG with its direction update
 // p = r + beta p folded into the first stage (masked grid problems).
-MsFusedFn masked_op_update(Problem& P, const void* lam, int64_t lam_tstride, const double* d_eta) {
+MsFusedFn masked_op_update(Problem& P, const void* lam, int64_t lam_tstride, const double* d_eta,
+                           bool lam_even = false) {
     Problem* pp = &P;
-    return [pp, lam, lam_tstride, d_eta](const double* r, double* p, const double* beta, double* w, int nvec,
-                                         hipStream_t st) {
+    return [pp, lam, lam_tstride, d_eta, lam_even](const double* r, double* p, const double* beta, double* w,
+                                                   int nvec, double* pw, hipStream_t st) {
         Problem& Q = *pp;
         ConvSpec s;
         s.N1 = Q.N1;
@@ -212,6 +216,8 @@ MsFusedFn masked_op_update(Problem& P, const void* lam, int64_t lam_tstride, con
         s.lam = lam;
         s.lam_tstride = lam_tstride;
         s.vecs_per_theta = 1;
+        s.lam_even = lam_even;
+        s.pw_out = pw;
         s.upd_r = r;
         s.upd_beta = beta;
         conv_apply<double>(Q, s, st);
@@ -987,6 +993,8 @@ void loglik_points_shared(Problem& P, const kry_matern* thetas, int count, const
         }
         const int S = count * nd;
         const int nblk = dot_blocks(p);
+        // power-of-two columns form p . w in the product, from the spectrum of p
+        const int fused_pw = P.irregular ? 0 : spectral_qf_count(P.N1, P.N2);
         MsCgBuffers B{};
         auto lay = [&](Arena& a) {
             B.r = a.take<double>((size_t)Gm * p);
@@ -1003,11 +1011,16 @@ void loglik_points_shared(Problem& P, const kry_matern* thetas, int count, const
             B.gram = a.take<double>((size_t)nd * nd);
             B.rhs = a.take<int>(Gm);
             B.partial = a.take<double>((size_t)(1 + nd) * Gm * nblk);
-            B.partial_pw = a.take<double>((size_t)Gm * nblk);
+            B.partial_pw = a.take<double>((size_t)Gm * std::max(nblk, fused_pw));
         };
         with_arena(P, lay);
-        auto A = masked_op<double>(P, P.spec_multi64.ptr, nspec, 1, d_zero);
-        const MsFusedFn fused = P.irregular ? MsFusedFn() : masked_op_update(P, P.spec_multi64.ptr, nspec, d_zero);
+        // one spectrum per vector here, so the column stage's spectrum reads
+        // are a third of its bytes; even spectra halve them
+        bool even = true;
+        for (int g = 0; g < G; ++g) even = even && matern_even(to_matern(&thetas[rep[g]]));
+        auto A = masked_op<double>(P, P.spec_multi64.ptr, nspec, 1, d_zero, even);
+        const MsFusedFn fused =
+            P.irregular ? MsFusedFn() : masked_op_update(P, P.spec_multi64.ptr, nspec, d_zero, even);
         double* lam64 = P.spec_multi64.as<double>();
         auto swp = [&](int a, int b) { swap_vectors<double>(lam64, nspec, a, b, nspec, st); };
         // shift entry t nd + a: point t's system with right-hand side D_a
@@ -1021,7 +1034,7 @@ void loglik_points_shared(Problem& P, const kry_matern* thetas, int count, const
         for (int g = 0; g < Gm; ++g) rhs[g] = g % nd;
         std::vector<int> it;
         std::vector<double> rr;
-        mscg_run(A, P.irregular ? nullptr : &fused, swp, p, Gm, gos, sig, D, nd, rhs, o->cg_rtol, o->cg_maxit, B, it,
+        mscg_run(A, P.irregular ? nullptr : &fused, fused_pw, swp, p, Gm, gos, sig, D, nd, rhs, o->cg_rtol, o->cg_maxit, B, it,
                  rr, M, st);
         for (int t = 0; t < count; ++t) {
             for (int a = 0; a < nd; ++a) {
@@ -1834,7 +1847,7 @@ static void torus_args(Problem& P, int32_t& N1, int32_t& N2) {
         N2 = P.N2;
     }
     KRY_REQUIRE(torus_side_ok(N1) && torus_side_ok(N2),
-                "torus sides must be in [16, 8192], powers of two or 2^a 3^b 5^c transform lengths");
+                "torus sides must be in [16, 8192]: powers of two or multiples of 16 of the form 2^a 3^b 5^c 7^d");
 }
 
 kry_status kry_lag_grid(kry_problem* prob, const kry_matern* theta, int32_t N1, int32_t N2, double* c_out) {

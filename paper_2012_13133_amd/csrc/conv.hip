@@ -419,12 +419,60 @@ struct StageBArgs {
     const void* lam;
     int64_t lam_tstride;
     int vecs_per_theta;
+    int lam_even;         // lam even in k1 (power-of-two columns read the lower half)
     int vec0;
     double* spec_out;
+    double* pw_out;       // FP64 power-of-two columns (nullable): per (vector, column) partials of p . lam p
     const ProbDesc* tab;  // several problems: per-vector rows and spectrum
     int tab_vpp;
     const int* active;    // per-vector skip flags (nullable)
 };
+
+// The quadratic form of the product, read off the spectrum: for a real x
+// zero outside the observed cells, with X its forward transform on the torus
+// and lam the spectrum scaled by 1 / (N1 N2), x . (Sigma_oo x) = sum over the
+// whole torus of lam |X|^2; over the half spectrum, columns 0 and M once and
+// the others twice (Hermitian symmetry).  All terms are non-negative (a PSD
+// spectrum), so the sum has no cancellation.  A thread sums its eight values
+// before the multiplication (col_qf_thread) and, once its column is written,
+// the column's lanes of each wavefront are summed by a butterfly
+// (col_qf_write): one partial per (column, wavefront), written to
+// pw_out[vector][column][wavefront].  The order depends on the column length
+// only -- not on the batch, the vectors per workgroup or the exchange form --
+// and no barrier is needed.
+__host__ __device__ constexpr int col_qf_waves(int log2l) { return (1 << log2l) / 8 > 64 ? (1 << log2l) / 512 : 1; }
+
+template <int V>
+__device__ __forceinline__ void col_qf_thread(const cpx<double>* v, const double* lamv, double* acc) {
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+        acc[u] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {  // explicit fused multiply-adds: one rounding each, the same everywhere
+            const cpx<double> z = v[u * 8 + k];
+            acc[u] = fma(lamv[u * 8 + k], fma(z.x, z.x, z.y * z.y), acc[u]);
+        }
+    }
+}
+
+template <int LOG2L, int V>
+__device__ __forceinline__ void col_qf_write(const StageBArgs& a, double* acc, int t, int col, bool valid,
+                                             int vbase) {
+    constexpr int T = (1 << LOG2L) / 8;
+    constexpr int SEG = T < 64 ? T : 64;  // lanes of one column in a wavefront
+    constexpr int NW = col_qf_waves(LOG2L);
+#pragma unroll
+    for (int u = 0; u < V; ++u)
+#pragma unroll
+        for (int off = SEG / 2; off > 0; off >>= 1) acc[u] += __shfl_xor(acc[u], off, 64);
+    if (t % SEG == 0 && valid) {
+        const double wt = (col == 0 || col == a.ncols - 1) ? 1.0 : 2.0;
+#pragma unroll
+        for (int u = 0; u < V; ++u)
+            if (vbase + u < a.nvec)
+                a.pw_out[((int64_t)(a.vec0 + vbase + u) * a.ncols + col) * NW + t / SEG] = wt * acc[u];
+    }
+}
 
 // Stage B: per column of the half spectrum, forward FFT of length L (rows
 // beyond rows_in are zero), multiply by lam in registers, inverse FFT, keep
@@ -487,7 +535,12 @@ __global__ void __launch_bounds__(((1 << LOG2L) / 8 > 256 ? (1 << LOG2L) / 8 : 2
             }
             lam += (int64_t)(valid ? col : 0) * L;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) lamv[u * 8 + k] = lam[edge_pos<LOG2L, LRF>(t, k)];
+            for (int k = 0; k < 8; ++k) {
+                // an even table is read at min(k1, N1 - k1): half the bytes
+                // from memory, the mirrored reads served by the caches
+                const int e = edge_pos<LOG2L, LRF>(t, k);
+                lamv[u * 8 + k] = lam[a.lam_even && e > L / 2 ? L - e : e];
+            }
         }
     }
 #pragma unroll
@@ -521,6 +574,10 @@ __global__ void __launch_bounds__(((1 << LOG2L) / 8 > 256 ? (1 << LOG2L) / 8 : 2
         }
         return;
     } else {
+        double qf[V];  // quadratic-form partials of this thread (FP64 with pw_out)
+        if constexpr (sizeof(R) == 8) {
+            if (a.pw_out) col_qf_thread<V>(v, lamv, qf);
+        }
 #pragma unroll
         for (int k = 0; k < V * 8; ++k) v[k] = cscale(v[k], lamv[k]);
         if constexpr (SPLIT) {
@@ -546,6 +603,9 @@ __global__ void __launch_bounds__(((1 << LOG2L) / 8 > 256 ? (1 << LOG2L) / 8 : 2
                 const int idx = t + k * T;
                 if (idx < rows_out[u]) Yv[idx] = v[u * 8 + k];
             }
+        }
+        if constexpr (sizeof(R) == 8) {
+            if (a.pw_out) col_qf_write<LOG2L, V>(a, qf, t, col, valid, vbase);
         }
     }
 }
@@ -1531,6 +1591,10 @@ bool torus_side_ok(int N) {
     return is_pow2(N) || (N % 16 == 0 && mixed_len_ok(N) && mixed_len_ok(N / 2));
 }
 
+int spectral_qf_count(int N1, int N2) {
+    return is_pow2(N1) ? (N2 / 2 + 1) * col_qf_waves(ilog2(N1)) : 0;
+}
+
 // Relative cost per point of a torus side: 1 for a power of two, 1.2 for a
 // side with compile-time kernels (one factor 3, 5 or 7; measured 1.2-1.5
 // times the power-of-two cost per point over both axes of a product), 1.75
@@ -1914,7 +1978,8 @@ template <typename R>
 static void run_stage_b(Problem& P, int N1, int M, int vec0, int nvec, cpx<R>* Y, int ldY, int64_t Yvs, int rows_in,
                         int rows_out, const void* lam, int64_t lam_tstride, int vpt, double* spec_out,
                         hipStream_t st, const ProbDesc* tab = nullptr, int tab_vpp = 1,
-                        const int* active = nullptr, int V = 1, bool split = false) {
+                        const int* active = nullptr, int V = 1, bool split = false, bool lam_even = false,
+                        double* pw_out = nullptr) {
     const int T = N1 / 8;
     StageBArgs b;
     b.Y = Y;
@@ -1927,8 +1992,15 @@ static void run_stage_b(Problem& P, int N1, int M, int vec0, int nvec, cpx<R>* Y
     b.lam = lam;
     b.lam_tstride = lam_tstride;
     b.vecs_per_theta = vpt;
+    b.lam_even = lam_even && !tab && !spec_out ? 1 : 0;
     b.vec0 = vec0;
     b.spec_out = spec_out;
+    b.pw_out = nullptr;
+    if (pw_out) {
+        KRY_REQUIRE(sizeof(R) == 8 && is_pow2(N1) && !tab && !spec_out,
+                    "spectral quadratic forms need FP64 power-of-two columns");
+        b.pw_out = pw_out;
+    }
     b.tab = tab;
     b.tab_vpp = tab_vpp;
     b.active = active ? active + vec0 : nullptr;
@@ -2087,7 +2159,7 @@ void conv_apply(Problem& P, const ConvSpec& s, hipStream_t st) {
         mark(1);
         run_stage_b<R>(P, s.N1, M, v0, nv, Y, ldY, Yvs, s.rows_in, s.rows_out, s.lam, s.lam_tstride,
                        s.vecs_per_theta, nullptr, st, s.tab, s.tab_vpp, s.active, V,
-                       tu.col_split != 0 && is_pow2(s.N1));
+                       tu.col_split != 0 && is_pow2(s.N1), s.lam_even, s.pw_out);
         mark(2);
         run_stage_c<R>(P, s, v0, nv, Y, ldY, Yvs, tc, vt, csplit, st);
         mark(3);
@@ -2173,6 +2245,23 @@ __global__ void k_minmax_final(const double* __restrict__ part, int nb, double* 
     out[1] = hi;
 }
 
+// lam[k2][k1] = lam[k2][N1 - k1] for N1 / 2 < k1 < N1 (N1 even): the
+// spectrum of a covariance even in the row lag is even in k1; the transform
+// leaves the two halves equal only to rounding, and the fold makes them equal
+// bit for bit.
+__global__ void k_fold_even(double* __restrict__ lam, int N1, int ncols) {
+    const int h = N1 / 2 - 1;  // mirrored entries per column
+    const int64_t n = (int64_t)ncols * h;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int col = (int)(i / h), k1 = N1 / 2 + 1 + (int)(i - (int64_t)col * h);
+        lam[(int64_t)col * N1 + k1] = lam[(int64_t)col * N1 + (N1 - k1)];
+    }
+}
+
+// The covariance is even in each lag separately (c(h1, h2) = c(-h1, h2)) when
+// it is isotropic or its anisotropy axes are the grid's.
+bool matern_even(const Matern& th) { return th.ratio == 1.0 || th.angle == 0.0; }
+
 size_t spectrum_ws_bytes(int N1, int N2) {
     const int M = N2 / 2;
     const RowTiling ta = row_tiling<double>(M);
@@ -2214,6 +2303,15 @@ void spectrum_device(Problem& P, int N1, int N2, const Matern& th, double* d_lam
     s.row_len = N2;
     run_stage_a<double>(P, s, 0, 1, Y, ldY, Yvs, ta, 1, false, st);
     run_stage_b<double>(P, N1, M, 0, 1, Y, ldY, Yvs, N1, N1, nullptr, 0, 1, d_lam, st);
+    if (matern_even(th)) {
+        const int64_t n = (int64_t)(M + 1) * (N1 / 2 - 1);
+        int64_t blocks = (n + 255) / 256;
+        if (blocks > 4096) blocks = 4096;
+        if (n > 0) {
+            hipLaunchKernelGGL(k_fold_even, dim3((unsigned)blocks), dim3(256), 0, st, d_lam, N1, M + 1);
+            KRY_HIP(hipGetLastError());
+        }
+    }
     if (!lam_min) return;
     // min / max
     double* part = reinterpret_cast<double*>(reinterpret_cast<char*>(Y) + (size_t)Yvs * sizeof(cpx<double>));

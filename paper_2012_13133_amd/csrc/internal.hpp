@@ -285,6 +285,15 @@ struct ConvSpec {
     const void* lam = nullptr;  // [theta][k2][k1], element type R, scaled
     int64_t lam_tstride = 0;
     int vecs_per_theta = 1;
+    // every lam table is even in k1 bit for bit (lam[k2][k1] == lam[k2][N1 - k1],
+    // as spectrum_device leaves it for an even covariance): the column stage
+    // may then read the lower half only
+    bool lam_even = false;
+    // FP64, power-of-two N1, one table per vector or shared, no nugget term
+    // (eta = 0): partials of the quadratic form x . (K x), formed in the
+    // column stage from the spectrum of x, spectral_qf_count(N1, N2) per
+    // vector, vector-major; summed in index order they give the form; nullable
+    double* pw_out = nullptr;
     // several problems (device table): vector v belongs to tab[(v) / tab_vpp],
     // whose mask, block and spectrum replace the ones above; compact outputs
     // are zero from the problem's count up to out_vstride
@@ -332,6 +341,12 @@ void build_plan_tables(Ctx& c);
 // of 16 of the form 2^a 3^b 5^c 7^d (mixed-radix plans); and the embedding
 // side for a need of m by the rule (kry_ctx_set_embedding; 0 if none).
 bool torus_side_ok(int N);
+// Quadratic-form partials per vector that the column stage writes with
+// ConvSpec::pw_out on an N1 x N2 torus (0: not available for this N1).
+int spectral_qf_count(int N1, int N2);
+// the covariance is even in each lag separately (its spectrum, as
+// spectrum_device leaves it, even in k1 bit for bit)
+bool matern_even(const Matern& th);
 int embedding_side(int m, int rule = KRY_EMBED_SMALLEST);
 // Twiddle tables of the mixed-radix lengths of an embedding N1 x N2 (column
 // length N1, row length N2 / 2), built when a problem is created so that its

@@ -849,17 +849,16 @@ __device__ __forceinline__ void reduce_rows_block(const double* __restrict__ par
     }
 }
 
-// p_q . w_q from the dot partials; base alpha per active position, then
-// zeta_{k+1} and alpha^s of the listed shifts.  One block of RB threads.
-__device__ __forceinline__ void ms_alpha_step(int Gact, const double* __restrict__ partial_pw, int nblk,
-                                              const double* __restrict__ rr, double* __restrict__ pw,
+// Base alpha per active position from p_q . w_q (published by the residual
+// kernel), then zeta_{k+1} and alpha^s of the listed shifts.  One block of RB
+// threads.
+__device__ __forceinline__ void ms_alpha_step(int Gact, const double* __restrict__ rr, const double* __restrict__ pw,
                                               double* __restrict__ alpha, const double* __restrict__ alpha_old,
                                               const double* __restrict__ beta_old, const int* __restrict__ list,
                                               int nlist, const int* __restrict__ pos,
                                               const double* __restrict__ sigma, const double* __restrict__ zeta,
                                               const double* __restrict__ zeta_old, double* __restrict__ zeta_new,
                                               double* __restrict__ alpha_s, int* __restrict__ active) {
-    reduce_rows_block(partial_pw, nblk, Gact, pw);
     for (int q = threadIdx.x; q < Gact; q += blockDim.x) alpha[q] = pw[q] > 0.0 ? rr[q] / pw[q] : 0.0;
     __syncthreads();
     for (int i = threadIdx.x; i < nlist; i += blockDim.x) {
@@ -880,14 +879,14 @@ __device__ __forceinline__ void ms_alpha_step(int Gact, const double* __restrict
 }
 
 // The scalars of an iteration, after the residual update: first the alpha
-// step (from the p . w partials; the residual kernel reads none of what it
-// writes), then base beta and roll of the position scalars; Q^s and d^s,
+// step (from the p . w the residual kernel published), then base beta and
+// roll of the position scalars; Q^s and d^s,
 // beta^s, the stopping test and the zeta roll of the listed shifts.  rc gets,
 // from the residual kernel's partials, ||r_{k+1}||^2 (rows 0..Gact-1) and
 // D_j . r_{k+1} (row Gact + q nd + j).  One block of RB threads.
 __device__ void ms_scalar_step(const MsScalarArgs& a) {
-    ms_alpha_step(a.Gact, a.partial_pw, a.nblk, a.rr, a.pw, a.alpha, a.alpha_old, a.beta_old, a.list, a.nlist, a.pos,
-                  a.sigma, a.zeta, a.zeta_old, a.zeta_new, a.alpha_s, a.active);
+    ms_alpha_step(a.Gact, a.rr, a.pw, a.alpha, a.alpha_old, a.beta_old, a.list, a.nlist, a.pos, a.sigma, a.zeta,
+                  a.zeta_old, a.zeta_new, a.alpha_s, a.active);
     __syncthreads();
     const int Gact = a.Gact, nd = a.nd;
     reduce_rows_block(a.partial, a.nblk, (1 + nd) * Gact, a.rc);
@@ -925,21 +924,36 @@ __device__ void ms_scalar_step(const MsScalarArgs& a) {
     }
 }
 
-// r_q -= alpha_q w_q, with alpha_q formed in every block from the p . w
-// partials; partials of ||r_q||^2 and D_j . r_q.  The scalar step is a
-// one-block launch of its own: publishing the partials to a last block
-// within this launch would take a device-scope release per block, which
-// writes back the XCD's L2 and cost more than the launch it saves.
+// r_q -= alpha_q w_q, with alpha_q formed in every block from the npw
+// partials of p_q . w_q (thread t adding partials t, t + RB, ... in order,
+// then block_sum: the same value in every block, which block 0 publishes to
+// pw for the scalar step); partials of ||r_q||^2 and D_j . r_q.  The scalar
+// step is a one-block launch of its own: publishing the partials to a last
+// block within this launch would take a device-scope release per block,
+// which writes back the XCD's L2 and cost more than the launch it saves.
 template <int ND>
 __global__ void __launch_bounds__(RB) k_ms_r(double* __restrict__ r, const double* __restrict__ w,
                                              const double* __restrict__ D, const double* __restrict__ partial_pw,
-                                             const double* __restrict__ rr, int Gact, int64_t n,
-                                             double* __restrict__ partial) {
+                                             int npw, const double* __restrict__ rr, double* __restrict__ pw,
+                                             int Gact, int64_t n, double* __restrict__ partial) {
     __shared__ double sh[RB];
     const int nblk = gridDim.x, q = blockIdx.y;
     double x = 0.0;
-    if ((int)threadIdx.x < nblk) x += partial_pw[q * nblk + threadIdx.x];
+    {
+        // in index order; eight loads in flight at a time
+        const double* pp = partial_pw + (int64_t)q * npw;
+        int i = threadIdx.x;
+        for (; i + 7 * RB < npw; i += 8 * RB) {
+            double a[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) a[k] = pp[i + k * RB];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) x += a[k];
+        }
+        for (; i < npw; i += RB) x += pp[i];
+    }
     const double pwq = block_sum(x, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0) pw[q] = pwq;
     const double al = pwq > 0.0 ? rr[q] / pwq : 0.0;
     double acc = 0.0, accb[ND];
 #pragma unroll
@@ -964,11 +978,126 @@ __global__ void __launch_bounds__(RB) k_ms_r(double* __restrict__ r, const doubl
 
 __global__ void __launch_bounds__(RB) k_ms_scalar(MsScalarArgs a) { ms_scalar_step(a); }
 
+// Rows of the two reductions that the one-pass scalar step keeps in LDS.
+constexpr int MS_ONE_ROWS = 1024;
+
+// ms_scalar_step when every shift and every position has a thread of its own
+// (S <= RB, Gact <= RB) and the (1 + nd) Gact reduction rows fit LDS.  The
+// step is a chain of dependent reads, each costing a trip to memory from
+// whichever XCD the block lands on; here every load is issued at the start
+// (the shift and position state beside the partials), the position values
+// reach the shift threads through LDS, and the step waits on memory about
+// once.  Same sums, in the same order, and the same arithmetic as
+// ms_scalar_step; every shift is visited (a shift missing from the list has
+// stopped, and stays stopped).
+__global__ void __launch_bounds__(RB) k_ms_scalar_one(MsScalarArgs a) {
+    constexpr int RK = 32;  // reduction rows in flight together
+    __shared__ double red[MS_ONE_ROWS];  // ||r||^2 rows, then D_j . r rows
+    __shared__ double wsum[RK][RB / 64];
+    __shared__ double s_pw[RB], s_alpha[RB], s_ao[RB], s_bo[RB], s_rr[RB], s_bn[RB];
+    const int t = threadIdx.x, Gact = a.Gact, nd = a.nd, nblk = a.nblk;
+    const int nrows = (1 + nd) * Gact;
+    // shift t's state
+    const int s = t < a.nS ? t : 0;
+    const int act = t < a.nS ? a.active[s] : 0;
+    const int q = a.pos[s], it0 = a.iters[s], lim = a.limit[s];
+    const double z = a.zeta[s], zo = a.zeta_old[s], sg = a.sigma[s];
+    double dj[KRY_MS_MAX_ND], Qj[KRY_MS_MAX_ND];
+#pragma unroll
+    for (int j = 0; j < KRY_MS_MAX_ND; ++j) {
+        dj[j] = j < nd ? a.d[s * nd + j] : 0.0;
+        Qj[j] = j < nd ? a.Q[s * nd + j] : 0.0;
+    }
+    // position t's state
+    const int qt = t < Gact ? t : 0;
+    const double rr_t = a.rr[qt], ao_t = a.alpha_old[qt], bo_t = a.beta_old[qt], bn_t = a.bnorm2[qt];
+    const double pw_t = a.pw[qt];
+    // the reductions, as reduce_rows_block forms them: thread t adds partial
+    // t, wavefront sums, then the RB / 64 of them in wavefront order
+    const int tc = min(t, nblk - 1);
+    for (int r0 = 0; r0 < nrows; r0 += RK) {
+        const int nr = min(RK, nrows - r0);
+        double x[RK];
+#pragma unroll
+        for (int k = 0; k < RK; ++k) x[k] = a.partial[(int64_t)(r0 + min(k, nr - 1)) * nblk + tc];
+#pragma unroll
+        for (int k = 0; k < RK; ++k) {
+            if (k < nr) {  // uniform over the block
+                double acc = 0.0;
+                if (t < nblk) acc += x[k];
+                acc = wave_sum(acc);
+                if ((t & 63) == 0) wsum[k][t >> 6] = acc;
+            }
+        }
+        __syncthreads();
+        if (t < nr) {
+            double r = wsum[t][0];
+#pragma unroll
+            for (int w = 1; w < RB / 64; ++w) r += wsum[t][w];
+            red[r0 + t] = r;
+        }
+        __syncthreads();
+    }
+    if (t < Gact) {
+        s_pw[t] = pw_t;
+        s_alpha[t] = pw_t > 0.0 ? rr_t / pw_t : 0.0;
+        s_ao[t] = ao_t;
+        s_bo[t] = bo_t;
+        s_rr[t] = rr_t;
+        s_bn[t] = bn_t;
+    }
+    __syncthreads();
+    if (act) {
+        if (!(s_pw[q] > 0.0) || !(fabs(z) > 0.0)) {  // breakdown of the base, or a vanished shifted residual
+            a.active[s] = 0;
+        } else {
+            const double al = s_alpha[q], ao = s_ao[q], bo = s_bo[q];
+            const double den = al * bo * (zo - z) + zo * ao * (1.0 + sg * al);
+            const double zn = z * zo * ao / den;
+            a.zeta_new[s] = zn;
+            const double as = al * zn / z;
+            a.alpha_s[s] = as;
+            const double rn = red[q];
+            const double rrq = s_rr[q];
+            const double b = rrq > 0.0 ? rn / rrq : 0.0;
+            const double ratio = zn / z;
+            const double bs = b * ratio * ratio;
+#pragma unroll
+            for (int j = 0; j < KRY_MS_MAX_ND; ++j) {
+                if (j < nd) {
+                    Qj[j] += as * dj[j];
+                    dj[j] = zn * red[Gact + q * nd + j] + bs * dj[j];
+                    a.Q[s * nd + j] = Qj[j];
+                    a.d[s * nd + j] = dj[j];
+                }
+            }
+            const int it = it0 + 1;
+            a.iters[s] = it;
+            const double res = fabs(zn) * sqrt(rn);
+            const double bn = sqrt(s_bn[q]);
+            a.relres[s] = res / bn;
+            if (!(res > a.rtol * bn) || it >= lim) a.active[s] = 0;
+            a.zeta_old[s] = z;
+            a.zeta[s] = zn;
+        }
+    }
+    if (t < Gact) {
+        const double rcq = red[t];
+        const double b = rr_t > 0.0 ? rcq / rr_t : 0.0;
+        a.alpha[t] = s_alpha[t];
+        a.beta[t] = b;
+        a.alpha_old[t] = s_alpha[t];
+        a.beta_old[t] = b;
+        a.rr[t] = rcq;
+    }
+    for (int i = t; i < nrows; i += RB) a.rc[i] = red[i];
+}
+
 template <int ND>
 void launch_ms_r(int nblk, int Gact, hipStream_t st, double* r, const double* w, const double* D, int64_t n,
                  const MsScalarArgs& a) {
-    hipLaunchKernelGGL(k_ms_r<ND>, dim3(nblk, Gact), dim3(RB), 0, st, r, w, D, a.partial_pw, a.rr, Gact, n,
-                       a.partial);
+    hipLaunchKernelGGL(k_ms_r<ND>, dim3(nblk, Gact), dim3(RB), 0, st, r, w, D, a.partial_pw, a.npw, a.rr, a.pw,
+                       Gact, n, a.partial);
 }
 
 void ms_residual_and_scalars(int nd, int nblk, int Gact, hipStream_t st, double* r, const double* w, const double* D,
@@ -986,7 +1115,10 @@ void ms_residual_and_scalars(int nd, int nblk, int Gact, hipStream_t st, double*
         default: KRY_REQUIRE(false, "multi-shift CG takes 1..9 dot vectors");
     }
     KRY_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_ms_scalar, dim3(1), dim3(RB), 0, st, a);
+    if (a.nS <= RB && Gact <= RB && (1 + nd) * Gact <= MS_ONE_ROWS)
+        hipLaunchKernelGGL(k_ms_scalar_one, dim3(1), dim3(RB), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_ms_scalar, dim3(1), dim3(RB), 0, st, a);
     KRY_HIP(hipGetLastError());
 }
 
@@ -1033,7 +1165,8 @@ __global__ void k_ms_swap_scalars(double* rr, double* bnorm2, double* alpha_old,
     }
 }
 
-void mscg_run(const MatvecFn<double>& A, const MsFusedFn* fused, const std::function<void(int, int)>& swap,
+void mscg_run(const MatvecFn<double>& A, const MsFusedFn* fused, int fused_pw,
+              const std::function<void(int, int)>& swap,
               int64_t n, int G,
               const std::vector<int>& group_of_shift, const std::vector<double>& sigma, const double* D, int nd,
               const std::vector<int>& rhs_of_group, double rtol, int maxit, MsCgBuffers& B, std::vector<int>& iters,
@@ -1094,20 +1227,26 @@ void mscg_run(const MatvecFn<double>& A, const MsFusedFn* fused, const std::func
     sa.iters = B.iters;
     sa.limit = B.limit;
     sa.rtol = rtol;
+    sa.nS = S;
+    const bool spectral_pw = fused && fused_pw > 0;
+    sa.npw = spectral_pw ? fused_pw : nblk;
     int Gact = G, nlist = S;
     int64_t ublocks = (n + 255) / 256;
     if (ublocks > 1024) ublocks = 1024;
     const int check = 16;
     // An iteration: the product (with the previous iteration's direction
-    // update folded in when `fused` is given), the p . w partials, the
-    // residual update and the one-block scalar step; without `fused`, the
+    // update folded in when `fused` is given, and the p . w partials formed
+    // inside it when it can), else the p . w partials as a pass of their own,
+    // the residual update and the one-block scalar step; without `fused`, the
     // direction update is a pass of its own at the end.
     for (int it = 0; it < maxit && Gact > 0; ++it) {
-        if (fused) (*fused)(B.r, B.p, B.beta, B.w, Gact, st);
+        if (fused) (*fused)(B.r, B.p, B.beta, B.w, Gact, spectral_pw ? B.partial_pw : nullptr, st);
         else A(B.p, B.w, Gact, st, nullptr);
-        hipLaunchKernelGGL(k_dot_partial<double>, dim3(nblk, Gact), dim3(RB), 0, st, B.p, n, B.w, n, n,
-                           B.partial_pw);
-        KRY_HIP(hipGetLastError());
+        if (!spectral_pw) {
+            hipLaunchKernelGGL(k_dot_partial<double>, dim3(nblk, Gact), dim3(RB), 0, st, B.p, n, B.w, n, n,
+                               B.partial_pw);
+            KRY_HIP(hipGetLastError());
+        }
         sa.Gact = Gact;
         sa.nlist = nlist;
         ms_residual_and_scalars(nd, nblk, Gact, st, B.r, B.w, D, n, sa);

@@ -57,11 +57,13 @@ struct MsCgBuffers {
     double* gram;           // nd x nd
     int* rhs;               // G
     double* partial;        // (1 + nd) G x nblk (at least nd x nd x nblk)
-    double* partial_pw;     // G x nblk: p . w partials, read while the residual kernel writes `partial`
+    double* partial_pw;     // G x npw: p . w partials (npw: nblk, or what the fused product writes),
+                            // read while the residual kernel writes `partial`
 };
 // Arguments of an iteration's scalar step (see ms_scalar_step).
 struct MsScalarArgs {
-    int Gact, nd, nblk, nlist;
+    int Gact, nd, nblk, nlist, nS;  // nS: every shift, listed or not
+    int npw;                         // p . w partials per position
     const double* partial_pw;
     double* partial;
     double *rr, *rc, *pw, *beta, *alpha, *alpha_old, *beta_old;
@@ -75,16 +77,21 @@ struct MsScalarArgs {
 };
 // The base product with the direction update folded into it: applies the
 // operators of positions 0..k-1 to p after replacing p by r + beta p (per
-// position), as the update would have done.
-using MsFusedFn = std::function<void(const double* r, double* p, const double* beta, double* w, int k,
+// position), as the update would have done.  With pw non-null it also
+// writes, per position, the partials of p . w (the count mscg_run is told),
+// whose sum in order is the quadratic form of the updated p.
+using MsFusedFn = std::function<void(const double* r, double* p, const double* beta, double* w, int k, double* pw,
                                      hipStream_t st)>;
 // A(x, y, k, st) applies the base operators of positions 0..k-1;
 // swap(a, b) exchanges whatever the caller keeps per position (spectra).
 // D: nd (<= KRY_MS_MAX_ND) vectors of n, contiguous; rhs_of_group: index of
 // each group's right-hand side in D.
 // With `fused` (nullable) the products go through it and the direction
-// update has no pass of its own.
-void mscg_run(const MatvecFn<double>& A, const MsFusedFn* fused, const std::function<void(int, int)>& swap,
+// update has no pass of its own; with fused_pw > 0 as well, the fused product
+// writes fused_pw partials of p . w per position and the dot pass is skipped
+// (B.partial_pw then holds G x max(nblk, fused_pw)).
+void mscg_run(const MatvecFn<double>& A, const MsFusedFn* fused, int fused_pw,
+              const std::function<void(int, int)>& swap,
               int64_t n, int G,
               const std::vector<int>& group_of_shift, const std::vector<double>& sigma, const double* D, int nd,
               const std::vector<int>& rhs_of_group, double rtol, int maxit, MsCgBuffers& B, std::vector<int>& iters,

@@ -379,6 +379,55 @@ def test_shift_share_same_alone_and_in_mix(precision):
             assert a[k] == s[k] and b[k] == s[k], k
 
 
+def test_shift_share_even_spectra_on_a_power_of_two_embedding():
+    # 32 x 32 grid, 64 x 64 embedding (power-of-two column kernels): the
+    # multi-shift CG reads half of each spectrum when every group's covariance
+    # is even (isotropic or grid-aligned), the whole of it otherwise, and takes
+    # p . w from the spectrum of p inside the product; a point's result does
+    # not depend on the other points of the call
+    n1, n2 = 32, 32
+    g, mask, y, yo = _problem(n1, n2, CONFIG1, 0.3)
+    sets = [[theta(r, 1.5, tau2=e) for r in (0.05, 0.15) for e in (0.02, 0.3)],
+            [theta(0.1, 0.5, tau2=e, ratio=2.0, angle=0.0) for e in (0.05, 0.5)],
+            [theta(0.1, 0.5, tau2=0.1), theta(0.1, 0.5, tau2=0.1, ratio=2.0, angle=0.7)]]
+    opts = K.kry_opts_default(lanczos_steps=10, num_probes=2, cg_rtol=1e-10, shift_share=1)
+    with K.Problem(n1, n2, mask, y) as P:
+        assert K.kry_problem_info(P.h)[1] == 64
+        for thetas in sets:
+            ths = [K.theta_from_dict(t) for t in thetas]
+            res = K.kry_loglik_batch(P.h, ths, opts)
+            rev = K.kry_loglik_batch(P.h, ths[::-1], opts)[::-1]
+            for got, back, th, t in zip(res, rev, ths, thetas):
+                ref = dense.loglik(g, mask, t, yo)
+                assert abs(got["quad"] - ref["quad"]) <= 1e-8 * ref["quad"], t
+                assert got["cg_relres"] <= 1e-10
+                alone = K.kry_loglik(P.h, th, opts)
+                for k in ("quad", "cg_iters", "cg_relres"):
+                    assert got[k] == alone[k] and back[k] == alone[k], (k, t)
+
+
+def test_shift_share_with_more_shifts_than_a_block():
+    # 300 shifts (30 ranges x 10 nuggets): more than one thread each in a
+    # reduction block, so the scalar step takes its looped form; the same
+    # points in batches of 150 take the one-pass form
+    n1, n2 = 20, 16
+    g, mask, y, yo = _problem(n1, n2, CONFIG1, 0.3)
+    thetas = [theta(float(r), 1.5, tau2=float(e)) for r in np.geomspace(0.03, 0.2, 30)
+              for e in np.geomspace(0.01, 1.0, 10)]
+    opts = K.kry_opts_default(lanczos_steps=8, num_probes=2, cg_rtol=1e-10, shift_share=1)
+    with K.Problem(n1, n2, mask, y) as P:
+        ths = [K.theta_from_dict(t) for t in thetas]
+        whole = K.kry_loglik_batch(P.h, ths, opts)
+        parts = K.kry_loglik_batch(P.h, ths[:150], opts) + K.kry_loglik_batch(P.h, ths[150:], opts)
+    for k in range(0, 300, 7):
+        ref = dense.loglik(g, mask, thetas[k], yo)
+        assert abs(whole[k]["quad"] - ref["quad"]) <= 1e-8 * ref["quad"], thetas[k]
+    for a, b in zip(whole, parts):
+        assert a["cg_relres"] <= 1e-10 and b["cg_relres"] <= 1e-10
+        assert abs(a["cg_iters"] - b["cg_iters"]) <= 1
+        assert abs(a["quad"] - b["quad"]) <= 1e-11 * abs(b["quad"])
+
+
 def test_shift_share_zero_nugget_and_unshared_agreement():
     # a zero nugget makes the point its group's base system; the shared and
     # unshared forms agree to rounding of the two recurrences

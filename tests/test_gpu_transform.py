@@ -44,6 +44,30 @@ def test_spectrum(th, tor):
     assert abs(mm[0] - ref.min()) <= 1e-12 * scale and abs(mm[1] - ref.max()) <= 1e-12 * scale
 
 
+@pytest.mark.parametrize("tor", [(64, 32), (256, 512), (48, 80), (1280, 768), (112, 48)])
+def test_spectrum_even_in_k1_for_even_covariances(tor):
+    # an isotropic or grid-aligned covariance is even in the row lag, so its
+    # spectrum is even in k1: the library's comes out even bit for bit (the
+    # products of the multi-shift CG then read half of it); a rotated
+    # anisotropy is not even and its spectrum is left as the transform gives it
+    n1, n2 = 8, 8
+    N1 = tor[0]
+    cases = [(THETAS[0], True), (THETAS[2], True), (theta(0.08, 1.0, tau2=0.1, ratio=2.0, angle=0.0), True),
+             (THETAS[3], False)]
+    with K.Problem(n1, n2, np.ones((n1, n2))) as P:
+        for th, even in cases:
+            lam, _ = K.kry_spectrum(P.h, K.theta_from_dict(th), *tor)
+            c = embedding_lags(tor[0], tor[1], 1.0 / n1, 1.0 / n2, th)
+            ref = np.real(np.fft.fft2(c))[:, : tor[1] // 2 + 1].T
+            scale = np.abs(ref).max()
+            assert np.abs(lam - ref).max() <= 1e-12 * scale
+            mirrored = lam[:, (-np.arange(N1)) % N1]
+            if even:
+                assert np.array_equal(lam, mirrored), th
+            else:
+                assert np.abs(lam - mirrored).max() > 1e-6 * scale, th
+
+
 SHAPES = [(2, 2), (3, 5), (7, 9), (16, 16), (32, 32), (33, 47), (64, 50), (100, 3),
           # mixed-radix embeddings by the smallest-side rule: 48 x 64, 80 x 96,
           # 320 x 640, 384 x 768, 48 x 16 (radix 3 or 5), 128 x 112 and 224 x 16
