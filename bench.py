@@ -85,10 +85,11 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def measured_traffic():
-    """HBM bytes per launch of the FP32 column stage (batch 32, 1024 x 1024
-    workload) from the committed rocprofv3 counter summary, or None when the
-    kernel sources have changed since those counters were taken."""
+def measured_traffic(stage):
+    """HBM bytes per launch of an FP32 stage kernel ("a", "b" or "c"; batch
+    32, 1024 x 1024 workload) from the committed rocprofv3 counter summary, or
+    None when the kernel sources have changed since those counters were
+    taken."""
     import hashlib
     import re
 
@@ -97,14 +98,15 @@ def measured_traffic():
             txt = f.read()
     except OSError:
         return None
-    vals = dict(re.findall(r"^(traffic_stage_b_fp32_bytes|kernel_sources_sha256): (\S+)$", txt, re.M))
+    vals = dict(re.findall(r"^(traffic_stage_[abc]_fp32_bytes|kernel_sources_sha256): (\S+)$", txt, re.M))
     h = hashlib.sha256()
     for name in ("conv.hip", "fftk.hpp", "fftm.hpp", "fft.hpp", "common.hpp"):
         with open(os.path.join(ROOT, "paper_2012_13133_amd", "csrc", name), "rb") as f:
             h.update(f.read())
-    if vals.get("kernel_sources_sha256") != h.hexdigest() or "traffic_stage_b_fp32_bytes" not in vals:
+    key = "traffic_stage_%s_fp32_bytes" % stage
+    if vals.get("kernel_sources_sha256") != h.hexdigest() or key not in vals:
         return None
-    return int(vals["traffic_stage_b_fp32_bytes"])
+    return int(vals[key])
 
 
 def main():
@@ -226,7 +228,7 @@ def main():
         P.close()
         return
 
-    # ---- algorithmic bytes of the dominant kernel (stage B, FP32) ----
+    # ---- algorithmic bytes of the dominant kernel (the slowest FP32 stage: B or C, about equal) ----
     p = P.p
     M = P.N2 // 2
     cs = 8  # complex FP32
@@ -365,7 +367,7 @@ def main():
         "products_per_step": per_step,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if (dom == 1 and Bv == 32 and n == 1024) else None,
+                     "traffic": measured_traffic("abc"[dom]) if (Bv == 32 and n == 1024) else None,
                      "kernel": ["stage A (row transform)", "stage B (column transform x spectrum)",
                                 "stage C (inverse row transform, gather)"][dom],
                      "bytes_per_launch": stage_bytes[dom], "launch_ms": stage_ms[dom], "batch": Bv},

@@ -781,8 +781,8 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
 #pragma unroll
         for (int i = 0; i < NV; ++i)
             tv[i] = rin ? at32(Y, (uint32_t)((k0 + i * TR) * a.ldY + row0 + r2)) : cpx<R>{(R)0, (R)0};
-        cpx<R> ny{(R)0, (R)0};
-        if (tid < a.RT && row0 + tid < rows_out) ny = at32(Y, (uint32_t)(M * a.ldY + row0 + tid));
+        const cpx<R> ny = (tid < a.RT && row0 + tid < rows_out) ? at32(Y, (uint32_t)(M * a.ldY + row0 + tid))
+                                                                 : cpx<R>{(R)0, (R)0};
 #pragma unroll
         for (int i = 0; i < NV; ++i) tl[i * PTR] = tv[i].x;
         if (tid < a.RT) rl[tid * PM + lpad<R>(M)] = ny.x;
@@ -844,14 +844,17 @@ __global__ void __launch_bounds__(row_threads_max<R>(VT), (VT > 1 ? 2 : (sizeof(
                 const int row = row0 + r2;
                 tv[i] = (row < rows_out) ? at32(Y, (uint32_t)(k * a.ldY + row)) : cpx<R>{(R)0, (R)0};
             }
-            cpx<R> ny{(R)0, (R)0};
-            if (tid < a.RT && row0 + tid < rows_out) ny = at32(Y, (uint32_t)(M * a.ldY + row0 + tid));
+            // the Nyquist column, taken as the tile values are (a value
+            // assigned under a branch was kept in scratch memory)
+            const cpx<R> ny = (tid < a.RT && row0 + tid < rows_out)
+                                  ? at32(Y, (uint32_t)(M * a.ldY + row0 + tid))
+                                  : cpx<R>{(R)0, (R)0};
+            if (tid < a.RT) lds[tid * PM + lpad<cpx<R>>(M)] = ny;
 #pragma unroll
             for (int i = 0; i < NV; ++i) {
                 const int o = tid + i * nt;
                 lds[(o & (a.RT - 1)) * PM + lpad<cpx<R>>(o >> a.log2RT)] = tv[i];
             }
-            if (tid < a.RT) lds[tid * PM + lpad<cpx<R>>(M)] = ny;
         }
         __syncthreads();
         // The first inverse pass reads its inputs merged from the split half
@@ -1136,14 +1139,16 @@ __global__ void __launch_bounds__(row_threads_mixed<R>()) k_row_inv_c(StageCArgs
             const int k = o >> a.log2RT;
             tv[i] = (row0 + r2 < rows_out) ? at32(Y, (uint32_t)(k * a.ldY + row0 + r2)) : cpx<R>{(R)0, (R)0};
         }
-        cpx<R> ny{(R)0, (R)0};
-        if (tid < a.RT && row0 + tid < rows_out) ny = at32(Y, (uint32_t)(M * a.ldY + row0 + tid));
+        // (the Nyquist value taken by a select, not assigned under a branch,
+        // which kept it in scratch memory)
+        const cpx<R> ny = (tid < a.RT && row0 + tid < rows_out) ? at32(Y, (uint32_t)(M * a.ldY + row0 + tid))
+                                                                 : cpx<R>{(R)0, (R)0};
+        if (tid < a.RT) lds[tid * PM + lpad<cpx<R>>(M)] = ny;
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
             const int o = tid + i * nt;
             lds[(o & (a.RT - 1)) * PM + lpad<cpx<R>>(o >> a.log2RT)] = tv[i];
         }
-        if (tid < a.RT) lds[tid * PM + lpad<cpx<R>>(M)] = ny;
     }
     __syncthreads();
     // first inverse pass: inputs merged from the split half spectrum,
@@ -1428,14 +1433,16 @@ __global__ void __launch_bounds__(row_threads_mixed<R>()) k_row_inv_m(StageCArgs
             const int k = o >> a.log2RT;
             tv[i] = (row0 + r2 < rows_out) ? at32(Y, (uint32_t)(k * a.ldY + row0 + r2)) : cpx<R>{(R)0, (R)0};
         }
-        cpx<R> ny{(R)0, (R)0};
-        if (tid < a.RT && row0 + tid < rows_out) ny = at32(Y, (uint32_t)(M * a.ldY + row0 + tid));
+        // (the Nyquist value taken by a select, not assigned under a branch,
+        // which kept it in scratch memory)
+        const cpx<R> ny = (tid < a.RT && row0 + tid < rows_out) ? at32(Y, (uint32_t)(M * a.ldY + row0 + tid))
+                                                                 : cpx<R>{(R)0, (R)0};
+        if (tid < a.RT) lds[tid * PM + lpad<cpx<R>>(M)] = ny;
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
             const int o = tid + i * nt;
             lds[(o & (a.RT - 1)) * PM + lpad<cpx<R>>(o >> a.log2RT)] = tv[i];
         }
-        if (tid < a.RT) lds[tid * PM + lpad<cpx<R>>(M)] = ny;
     }
     __syncthreads();
     // first inverse pass: inputs merged from the split half spectrum,
