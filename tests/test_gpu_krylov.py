@@ -406,6 +406,25 @@ def test_shift_share_even_spectra_on_a_power_of_two_embedding():
                     assert got[k] == alone[k] and back[k] == alone[k], (k, t)
 
 
+@pytest.mark.parametrize("shape, N1", [((2048, 48), 4096), ((4096, 12), 8192)])
+def test_shift_share_long_power_of_two_columns(shape, N1):
+    # 4096- and 8192-point columns: eight and sixteen wavefronts per column
+    # write the spectral p . Ap partials; the shared form's quadratic forms
+    # against the unshared FP64 CG's (a dot of p with the product)
+    n1, n2 = shape
+    mask = synth.uniform_mask(n1, n2, 0.3, seed=21)
+    y = synth.random_vectors(n1 * n2, 1, seed=22)[0].reshape(n1, n2)
+    ths = [K.theta_from_dict(theta(0.05, 1.5, tau2=e)) for e in (0.05, 0.5)]
+    base = dict(lanczos_steps=5, num_probes=2, cg_rtol=1e-11)
+    with K.Problem(n1, n2, mask, y) as P:
+        assert K.kry_problem_info(P.h)[1] == N1
+        sh = K.kry_loglik_batch(P.h, ths, K.kry_opts_default(shift_share=1, **base))
+        un = K.kry_loglik_batch(P.h, ths, K.kry_opts_default(**base))
+    for a, b in zip(sh, un):
+        assert a["cg_relres"] <= 1e-11 and b["cg_relres"] <= 1e-11
+        assert abs(a["quad"] - b["quad"]) <= 1e-8 * abs(b["quad"])
+
+
 def test_shift_share_with_more_shifts_than_a_block():
     # 300 shifts (30 ranges x 10 nuggets): more than one thread each in a
     # reduction block, so the scalar step takes its looped form; the same
