@@ -108,7 +108,10 @@ uint64_t footprint(const Problem& P, const kry_request& r) {
         const uint64_t nblk = 256;
         const uint64_t kws = np * p * el * (slots + 2) + np * (m + 1) * nblk * 8 + np * (3 * m + 8) * 8 + 65536;
         const uint64_t spec = nd * nspec * 12;
-        const uint64_t rhs = nd * p * 16 + 4096 + nd * 257 * 8;
+        // the multi-shift CG's p . w partials: one block's worth, or the
+        // column stage's spectral partials on a power-of-two embedding
+        const uint64_t pwp = nd * (uint64_t)std::max(256, spectral_qf_count(P.N1, P.N2)) * 8;
+        const uint64_t rhs = nd * p * 16 + 4096 + nd * 257 * 8 + pwp;
         const uint64_t gk = r.opts.solver == KRY_SOLVER_GENGK
                                 ? (uint64_t)(r.opts.gk_steps + 2) * 2 * n * el + 4 * n * 8 + p * 8 * 4
                                 : 0;
