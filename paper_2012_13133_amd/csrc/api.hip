@@ -189,7 +189,10 @@ MatvecFn<R> masked_op(Problem& P, const void* lam, int64_t lam_tstride, int vpt,
 }
 
 // The FP64 masked product of the multi-shift CG with its direction update
-// p = r + beta p folded into the first stage (masked grid problems).
+// p = r + beta p folded into the first stage (masked grid problems).  The
+// multi-shift CG's base operators have no nugget (d_eta points at zeros):
+// the p . w partials the column stage forms from the spectrum (pw non-null)
+// hold the quadratic form of Sigma_oo alone.
 MsFusedFn masked_op_update(Problem& P, const void* lam, int64_t lam_tstride, const double* d_eta,
                            bool lam_even = false) {
     Problem* pp = &P;
