@@ -137,9 +137,9 @@ struct kry_server {
     std::unordered_map<uint64_t, kry_response> done;
     std::unordered_map<uint64_t, bool> known;
     uint64_t next_ticket = 1;
-    // Device memory of the slots: a running slot may use up to the larger of
-    // its retained workspace and its batch's estimated footprint; an idle one
-    // holds its retained workspace, which can be released to admit a request.
+    // Device memory of the slots: a running slot may use up to its retained
+    // workspace plus its batch's estimated footprint; an idle one holds its
+    // retained workspace, which can be released to admit a request.
     std::vector<uint64_t> retained, running;
     bool stop = false;
     std::vector<std::thread> workers;
@@ -171,11 +171,16 @@ struct kry_server {
                !h.prob->P.irregular;
     }
 
-    // Memory held by the running slots (requires mu).
+    // Memory held by the running slots (requires mu).  A running slot may
+    // hold its retained workspace plus its batch's footprint: its buffers
+    // grow one by one to what the batch needs, so a buffer the batch leaves
+    // small keeps its retained size while others grow (the larger of the two
+    // totals is not a bound when the retained workspace and the batch differ
+    // in which buffers are large).
     uint64_t busy_bytes() const {
         uint64_t b = 0;
         for (size_t s = 0; s < running.size(); ++s)
-            if (running[s]) b += std::max(retained[s], running[s]);
+            if (running[s]) b += retained[s] + running[s];
         return b;
     }
     bool any_running() const {
@@ -187,14 +192,14 @@ struct kry_server {
     uint64_t other_bytes(int slot) const {
         uint64_t b = 0;
         for (size_t s = 0; s < running.size(); ++s)
-            if ((int)s != slot) b += running[s] ? std::max(retained[s], running[s]) : retained[s];
+            if ((int)s != slot) b += retained[s] + running[s];
         return b;
     }
     // Make room for a batch of footprint fp on `slot` by releasing idle
     // slots' workspaces, its own first (requires mu; the idle slots' threads
     // are waiting for work, so their buffers are not in use).
     void make_room(int slot, uint64_t fp) {
-        auto need = [&] { return other_bytes(slot) + std::max(retained[slot], fp); };
+        auto need = [&] { return other_bytes(slot) + retained[slot] + fp; };
         if (need() <= budget) return;
         if (retained[slot]) {
             work[slot].release(*ctx);
